@@ -1,0 +1,506 @@
+"""Pins for the FP64 CPU oracle, each against something other than the oracle
+itself: closed forms, an independent ray-plane derivation, scipy's rotation
+conventions, invariants of front-to-back compositing (Eq. 1), finite
+differences, symmetries and exact brute force on tiny inputs."""
+import math
+
+import numpy as np
+import pytest
+from scipy.spatial.transform import Rotation
+
+from paper_2604_03092_amd import scenes
+
+A_MIN = float(np.float32(1.0 / 255.0))
+
+
+def one_surfel(mu, quat, scale, sigma, color):
+    f = lambda a: np.asarray(a, np.float32).reshape(-1, 1)
+    return dict(mean=f(mu), quat=f(quat), scale=f(scale), opacity=np.asarray([sigma], np.float32),
+                color=f(color))
+
+
+def stack(*sms):
+    return {k: np.concatenate([s[k] for s in sms], axis=-1) for k in sms[0]}
+
+
+IDENT = np.array([1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0], np.float32)
+
+
+def _pix(w, h):
+    yy, xx = np.meshgrid(np.arange(h) + 0.5, np.arange(w) + 0.5, indexing="ij")
+    return xx.reshape(-1), yy.reshape(-1)
+
+
+def _expected_from_uv(u, v, sigma, rho=3.0, a_max=0.99, a_min=A_MIN):
+    r2 = u * u + v * v
+    at = sigma * np.exp(-0.5 * r2)
+    a = np.minimum(a_max, at)
+    a[(r2 > rho * rho) | (at < a_min)] = 0.0
+    return a
+
+
+# ---------------------------------------------------------------- P1
+@pytest.mark.parametrize("qscale", [1.0, 2.5, -1.0])
+def test_p1_frontoparallel_closed_form(orc, qscale):
+    """Fronto-parallel surfel at the identity pose: u = (x-cx-fx X/Z) Z/(fx s_u),
+    v likewise; I = c A, D = Z A, N = (0,0,-1) A."""
+    w, h = 40, 32
+    intr = np.array([50, 55, 20.5, 15.0], np.float32)
+    X, Y, Z = 0.1, -0.05, 3.0
+    su, sv, sig = 0.2, 0.12, 0.8
+    c = [0.3, 0.6, 0.9]
+    sm = one_surfel([X, Y, Z], [qscale, 0, 0, 0], [su, sv], sig, c)
+    o = orc.render_view(sm, w, h, intr, IDENT)
+    x, y = _pix(w, h)
+    fx, fy, cx, cy = [float(v) for v in intr]
+    X, Y, Z, su, sv, sig = [float(np.float32(v)) for v in (X, Y, Z, su, sv, sig)]
+    u = (x - cx - fx * X / Z) * Z / (fx * su)
+    v = (y - cy - fy * Y / Z) * Z / (fy * sv)
+    a = _expected_from_uv(u, v, sig)
+    assert a.max() > 0.5
+    np.testing.assert_allclose(o["alpha"], a, atol=1e-12)
+    for k in range(3):
+        np.testing.assert_allclose(o["rgb"][k], float(np.float32(c[k])) * a, atol=1e-12)
+    np.testing.assert_allclose(o["depth"], Z * a, atol=1e-12)
+    np.testing.assert_allclose(o["normal"][2], -a, atol=1e-12)
+    np.testing.assert_allclose(o["normal"][:2], 0.0, atol=1e-12)
+
+
+# ---------------------------------------------------------------- P2
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_p2_tilted_surfel_ray_plane(orc, seed):
+    """A tilted surfel under a general pose, against an independent
+    derivation: intersect the pixel ray d = K^-1 (x,y,1) with the plane through
+    p with normal t_u x t_v, then u = (X-p).t_u / s_u, v = (X-p).t_v / s_v.
+    The surfel frame is built by scipy from the quaternion (scalar-last)."""
+    rng = np.random.default_rng(seed)
+    w, h = 48, 40
+    intr = np.array([45, 50, 23.0, 21.0], np.float32)
+    rot = Rotation.from_rotvec(rng.normal(size=3) * 0.6)
+    cam = Rotation.from_rotvec(rng.normal(size=3) * 0.1)
+    Rv = cam.as_matrix().astype(np.float32)
+    tv = np.array([0.05, -0.02, 0.1], np.float32)
+    vm = np.concatenate([Rv, tv[:, None]], 1).reshape(12)
+    q_xyzw = rot.as_quat()
+    q = np.array([q_xyzw[3], q_xyzw[0], q_xyzw[1], q_xyzw[2]], np.float32)
+    mu = np.array([0.05, 0.1, 3.0], np.float32)
+    su, sv, sig = 0.25, 0.15, 0.9
+    sm = one_surfel(mu, q, [su, sv], sig, [1, 1, 1])
+    o = orc.render_view(sm, w, h, intr, vm)
+
+    Rs = Rotation.from_quat([q[1], q[2], q[3], q[0]]).as_matrix()
+    R = vm.reshape(3, 4)[:, :3].astype(np.float64)
+    t = vm.reshape(3, 4)[:, 3].astype(np.float64)
+    p = R @ mu.astype(np.float64) + t
+    t_u, t_v = R @ Rs[:, 0], R @ Rs[:, 1]
+    nrm = np.cross(t_u, t_v)
+    x, y = _pix(w, h)
+    fx, fy, cx, cy = [float(v) for v in intr]
+    d = np.stack([(x - cx) / fx, (y - cy) / fy, np.ones_like(x)], -1)
+    lam = (p @ nrm) / (d @ nrm)
+    Xp = lam[:, None] * d - p
+    # coordinates of X - p in the (s_u t_u, s_v t_v) basis (the float32 view
+    # rotation is orthonormal only to ~1e-7, so solve rather than project)
+    A = np.stack([t_u * float(np.float32(su)), t_v * float(np.float32(sv))], 1)
+    uv = np.linalg.solve(A.T @ A, A.T @ Xp.T)
+    u, v = uv[0], uv[1]
+    a = _expected_from_uv(u, v, float(np.float32(sig)))
+    assert a.max() > 0.1
+    np.testing.assert_allclose(o["alpha"], a, atol=1e-11)
+    # depth accumulates the centre depth, normal faces the camera
+    np.testing.assert_allclose(o["depth"], p[2] * a, atol=1e-10)
+    n0 = R @ Rs[:, 2]                  # surfel normal in camera space
+    n_face = n0 if n0 @ p < 0 else -n0
+    for k in range(3):
+        np.testing.assert_allclose(o["normal"][k], n_face[k] * a, atol=1e-11)
+
+
+# ---------------------------------------------------------------- P3
+@pytest.mark.parametrize("name", ["config0"])
+def test_p3_partition_of_unity(orc, name):
+    """sum_k alpha_k T_k + T_final = 1 at every pixel (Eq. 1 weights)."""
+    sc = scenes.make(name)
+    o = orc.render_scene(sc)
+    np.testing.assert_allclose(o["alpha"] + o["t_final"], 1.0, atol=1e-12)
+    assert (o["t_final"] >= 1e-4 * (1 - 1e-6)).all()
+
+
+def test_p3_partition_of_unity_dense(orc):
+    sc = scenes.random_scene(7, 3000, 48, 40, scale_lo=0.05, scale_hi=0.3)
+    o = orc.render_scene(sc)
+    np.testing.assert_allclose(o["alpha"] + o["t_final"], 1.0, atol=1e-12)
+    assert (o["n_contrib"] > 5).mean() > 0.5
+
+
+# ---------------------------------------------------------------- P4
+def test_p4_opaque_occluder_hides_everything_behind(orc):
+    """alpha_max = 1 and sigma = 1: at the pixel whose centre sits on the
+    occluder's centre, alpha = 1 would take the transmittance to 0 < T_min,
+    so compositing stops there and nothing behind shows through.  Off the
+    occluder the surfel behind is seen unattenuated."""
+    w, h = 16, 16
+    intr = np.array([20, 20, 8.5, 8.5], np.float32)
+    front = one_surfel([0, 0, 2], [1, 0, 0, 0], [0.1, 0.1], 1.0, [1, 0, 0])
+    back = one_surfel([0, 0, 4], [1, 0, 0, 0], [2.0, 2.0], 0.9, [0, 1, 0])
+    o = orc.render_view(stack(front, back), w, h, intr, IDENT, alpha_max=1.0)
+    q = 8 * w + 8
+    assert o["rgb"][1, q] == 0.0 and o["n_contrib"][q] == 0 and o["t_final"][q] == 1.0
+    q2 = 8 * w + 15          # 7 px right: front r^2 = (7*2/(20*0.1))^2 = 49 > 9
+    xb = 7.0 * 4 / (20 * 2.0)
+    np.testing.assert_allclose(o["rgb"][1, q2], float(np.float32(0.9)) * math.exp(-0.5 * xb * xb),
+                               rtol=1e-6)
+
+
+def test_p4_stack_closed_form(orc):
+    """alpha_max = 0.99: three fronto-parallel surfels centred on one pixel
+    with opacities 1, 0.95, 0.9.  Front: alpha 0.99 (clamped), T = 0.01;
+    second: alpha 0.95, T = 5e-4; third would take T to 5e-5 < T_min and
+    is excluded, as is everything behind it."""
+    w, h = 16, 16
+    intr = np.array([20, 20, 8.5, 8.5], np.float32)
+    s1 = one_surfel([0, 0, 2], [1, 0, 0, 0], [0.5, 0.5], 1.0, [1, 0, 0])
+    s2 = one_surfel([0, 0, 3], [1, 0, 0, 0], [0.5, 0.5], 0.95, [0, 1, 0])
+    s3 = one_surfel([0, 0, 4], [1, 0, 0, 0], [0.5, 0.5], 0.9, [0, 0, 1])
+    s4 = one_surfel([0, 0, 5], [1, 0, 0, 0], [0.5, 0.5], 0.5, [1, 1, 1])
+    o = orc.render_view(stack(s4, s2, s1, s3), w, h, intr, IDENT)
+    q = 8 * w + 8
+    a1 = float(np.float32(0.99))
+    a2 = float(np.float32(0.95))
+    np.testing.assert_allclose(o["rgb"][:, q], [a1, (1 - a1) * a2, 0.0], atol=1e-12)
+    np.testing.assert_allclose(o["alpha"][q], a1 + (1 - a1) * a2, atol=1e-12)
+    np.testing.assert_allclose(o["depth"][q], 2 * a1 + 3 * (1 - a1) * a2, atol=1e-12)
+    np.testing.assert_allclose(o["t_final"][q], (1 - a1) * (1 - a2), rtol=1e-12)
+    assert o["n_contrib"][q] == 2
+
+
+# ---------------------------------------------------------------- P5
+def _fd_scene(seed):
+    rng = np.random.default_rng(seed)
+    n = 4
+    mu = np.stack([rng.uniform(-0.3, 0.3, n), rng.uniform(-0.3, 0.3, n), rng.uniform(2.5, 4.0, n)])
+    q = rng.normal(size=(4, n))
+    q /= np.linalg.norm(q, axis=0)
+    q[0] = np.abs(q[0]) + 0.8          # mostly facing the camera
+    sm = dict(mean=mu.astype(np.float32), quat=q.astype(np.float32),
+              scale=rng.uniform(0.15, 0.35, (2, n)).astype(np.float32),
+              opacity=rng.uniform(0.3, 0.8, n).astype(np.float32),
+              color=rng.uniform(0, 1, (3, n)).astype(np.float32))
+    Rv = Rotation.from_rotvec(rng.normal(size=3) * 0.05).as_matrix()
+    vm = np.concatenate([Rv, rng.uniform(-0.05, 0.05, (3, 1))], 1).reshape(12).astype(np.float32)
+    return sm, vm
+
+
+def _loss(orc, sm, w, h, intr, vm, g, bg):
+    o = orc.render_view(sm, w, h, intr, vm, bg=bg)
+    return (np.sum(g["rgb"] * o["rgb"]) + np.sum(g["depth"] * o["depth"]) +
+            np.sum(g["normal"] * o["normal"]) + np.sum(g["alpha"] * o["alpha"]))
+
+
+@pytest.mark.parametrize("seed", [11, 12, 13])
+def test_p5_finite_differences(orc, seed):
+    """Analytic backward vs central differences of the FP64 forward, for
+    every surfel parameter and every view-matrix entry.  Inputs are float32,
+    so each perturbation is the exact float32 step and the quotient uses it;
+    a Richardson step (h, h/2) removes the O(h^2) term."""
+    w, h = 24, 20
+    intr = np.array([30, 32, 12.0, 10.0], np.float32)
+    sm, vm = _fd_scene(seed)
+    bg = (0.2, 0.1, 0.3)
+    o = orc.render_view(sm, w, h, intr, vm, bg=bg, margin=5e-3, margin_t=5e-3)
+    assert o["flags"].mean() < 0.05
+    rng = np.random.default_rng(seed + 100)
+    keep = ~o["flags"]          # pixels near a threshold carry no upstream gradient
+    g = dict(rgb=rng.normal(size=(3, w * h)) * keep, depth=rng.normal(size=w * h) * keep,
+             normal=rng.normal(size=(3, w * h)) * keep, alpha=rng.normal(size=w * h) * keep)
+    an = orc.backward_view(sm, w, h, intr, vm, g, bg=bg)
+
+    def fd(get, put, base):
+        vals = []
+        for hh in (2e-5, 1e-5):
+            step = max(abs(base), 1.0) * hh
+            xp = np.float32(base + step)
+            xm = np.float32(base - step)
+            put(xp); lp = _loss(orc, sm2, w, h, intr, vm2, g, bg)
+            put(xm); lm = _loss(orc, sm2, w, h, intr, vm2, g, bg)
+            put(np.float32(base))
+            vals.append((lp - lm) / (float(xp) - float(xm)))
+        return (4 * vals[1] - vals[0]) / 3
+
+    sm2 = {k: v.copy() for k, v in sm.items()}
+    vm2 = vm.copy()
+    errs = []
+    scale_ref = {}
+    for key in ("mean", "quat", "scale", "opacity", "color"):
+        arr = sm2[key]
+        flat = arr.reshape(-1)
+        ref = an[key].reshape(-1)
+        num = np.zeros_like(ref)
+        for j in range(flat.size):
+            base = float(flat[j])
+
+            def put(v, j=j, flat=flat):
+                flat[j] = v
+            num[j] = fd(None, put, base)
+        scale_ref[key] = np.sqrt(np.mean(ref ** 2)) + 1e-30
+        errs.append((key, np.max(np.abs(num - ref)) / scale_ref[key]))
+        np.testing.assert_allclose(num, ref, rtol=2e-5, atol=2e-5 * scale_ref[key], err_msg=key)
+    ref = an["viewmat"]
+    num = np.zeros(12)
+    for j in range(12):
+        base = float(vm2[j])
+
+        def put(v, j=j):
+            vm2[j] = v
+        num[j] = fd(None, put, base)
+    np.testing.assert_allclose(num, ref, rtol=2e-5, atol=2e-5 * (np.sqrt(np.mean(ref ** 2))),
+                               err_msg="viewmat")
+
+
+# ---------------------------------------------------------------- P6
+def test_p6_quaternion_sign_and_scale(orc):
+    sc = scenes.config0()
+    base = orc.render_scene(sc)
+    for f in (-1.0, 2.0, 3.0):
+        sm = dict(sc.submaps[0])
+        sm["quat"] = (sm["quat"] * f).astype(np.float32)
+        sc2 = scenes.Scene("q", [sm], sc.views, sc.intr, sc.viewmat)
+        o = orc.render_scene(sc2)
+        ok = ~(o["flags"] | base["flags"])
+        for k in ("rgb", "depth", "normal", "alpha"):
+            if f in (-1.0, 2.0):     # exact scalings: bit-identical
+                np.testing.assert_array_equal(o[k], base[k], err_msg=k)
+            else:                    # 3q rounds in float32
+                np.testing.assert_allclose(o[k][..., ok], base[k][..., ok], atol=1e-5, err_msg=k)
+
+
+def test_p6_quarter_turn_with_swapped_scales(orc):
+    """Rotating the surfel frame by 90 deg about its normal and swapping
+    (s_u, s_v) describes the same disk."""
+    sc = scenes.config0()
+    sm = sc.submaps[0]
+    q = sm["quat"].astype(np.float64)
+    rz = np.array([math.cos(math.pi / 4), 0, 0, math.sin(math.pi / 4)])  # 90 deg about local z
+
+    def qmul(a, b):
+        aw, av = a[0], a[1:]
+        bw, bv = b[0], b[1:]
+        return np.concatenate([[aw * bw - av @ bv], aw * bv + bw * av + np.cross(av, bv)])
+    q2 = np.stack([qmul(q[:, i], rz) for i in range(q.shape[1])], 1)
+    sm2 = dict(sm)
+    sm2["quat"] = q2.astype(np.float32)
+    sm2["scale"] = sm["scale"][::-1].copy()
+    a = orc.render_view(sm, 64, 48, sc.intr[0], sc.viewmat[0])
+    b = orc.render_view(sm2, 64, 48, sc.intr[0], sc.viewmat[0])
+    ok = ~(a["flags"] | b["flags"])
+    for k in ("rgb", "depth", "normal", "alpha"):
+        np.testing.assert_allclose(b[k][..., ok], a[k][..., ok], atol=1e-5, err_msg=k)
+
+
+def test_p6_rigid_motion_of_world_and_camera(orc):
+    sc = scenes.config0()
+    sm = sc.submaps[0]
+    W = Rotation.from_rotvec([0.3, -0.2, 0.5])
+    b = np.array([0.5, -1.0, 2.0])
+    Wm = W.as_matrix()
+    mu = Wm @ sm["mean"].astype(np.float64) + b[:, None]
+    qs = Rotation.from_quat(np.stack([sm["quat"][1], sm["quat"][2], sm["quat"][3], sm["quat"][0]], 1))
+    q2 = (W * qs).as_quat()
+    sm2 = dict(sm)
+    sm2["mean"] = mu.astype(np.float32)
+    sm2["quat"] = np.stack([q2[:, 3], q2[:, 0], q2[:, 1], q2[:, 2]]).astype(np.float32)
+    R = np.eye(3) @ Wm.T
+    t = -R @ b
+    vm2 = np.concatenate([R, t[:, None]], 1).reshape(12).astype(np.float32)
+    a = orc.render_view(sm, 64, 48, sc.intr[0], sc.viewmat[0])
+    c = orc.render_view(sm2, 64, 48, sc.intr[0], vm2)
+    ok = ~(a["flags"] | c["flags"])
+    assert ok.mean() > 0.95
+    for k in ("rgb", "depth", "normal", "alpha"):
+        # the moved inputs are re-rounded to float32 (~4e-7 absolute at |mu|~6),
+        # which moves sub-pixel surfels measurably: O(1e-4) in depth
+        tol = 4e-4 if k == "depth" else 1e-4
+        np.testing.assert_allclose(c[k][..., ok], a[k][..., ok], atol=tol, err_msg=k)
+
+
+# ---------------------------------------------------------------- P7
+def _qmul(a, b):
+    aw, av = a[0], a[1:]
+    bw, bv = b[0], b[1:]
+    return np.concatenate([[aw * bw - av @ bv], aw * bv + bw * av + np.cross(av, bv)])
+
+
+@pytest.mark.parametrize("seed", [21, 22])
+def test_p7_pose_identities(orc, seed):
+    """Translation: sum_i dL/dmu_i = R^T dL/dt.  Rotation: rotating world
+    points, surfel frames and the camera together leaves the image fixed, so
+    sum_i [dmu_i . (w x mu_i) + dq_i . ((0, w/2) (x) q_i)] = <dL/dR, R [w]_x>."""
+    sc = scenes.random_scene(seed, 400, 40, 32, scale_lo=0.03, scale_hi=0.2)
+    sm = sc.submaps[0]
+    vm = sc.viewmat[0].copy()
+    Rv = Rotation.from_rotvec([0.05, -0.08, 0.02]).as_matrix()
+    vm = np.concatenate([Rv, np.array([[0.1], [-0.05], [0.2]])], 1).reshape(12).astype(np.float32)
+    rng = np.random.default_rng(seed)
+    g = dict(rgb=rng.normal(size=(3, 1280)), depth=rng.normal(size=1280),
+             normal=rng.normal(size=(3, 1280)), alpha=rng.normal(size=1280))
+    gr = orc.backward_view(sm, 40, 32, sc.intr[0], vm, g)
+    R = vm.reshape(3, 4)[:, :3].astype(np.float64)
+    dR = gr["viewmat"].reshape(3, 4)[:, :3]
+    dt = gr["viewmat"].reshape(3, 4)[:, 3]
+    np.testing.assert_allclose(gr["mean"].sum(1), R.T @ dt, rtol=1e-9, atol=1e-12)
+    mu = sm["mean"].astype(np.float64)
+    q = sm["quat"].astype(np.float64)
+    for axis in np.eye(3):
+        Om = np.array([[0, -axis[2], axis[1]], [axis[2], 0, -axis[0]], [-axis[1], axis[0], 0]])
+        lhs = np.sum(gr["mean"] * (Om @ mu))
+        dq_pert = np.stack([_qmul(np.concatenate([[0.0], axis / 2]), q[:, i]) for i in range(q.shape[1])], 1)
+        lhs += np.sum(gr["quat"] * dq_pert)
+        rhs = np.sum(dR * (R @ Om))
+        assert abs(lhs - rhs) <= 1e-9 * (abs(lhs) + abs(rhs) + np.abs(dR).sum())
+
+
+# ---------------------------------------------------------------- P8
+def test_p8_alpha_integral(orc):
+    """sum over pixels of A = 2 pi sigma s_u s_v fx fy (1 - e^{-rho^2/2}) / Z^2
+    for a fronto-parallel surfel many pixels wide (no clamp, no alpha_min cut)."""
+    w, h = 96, 96
+    intr = np.array([60, 70, 48.0, 48.0], np.float32)
+    Z, su, sv, sig = 5.0, 0.5, 0.35, 0.5
+    sm = one_surfel([0.02, -0.03, Z], [1, 0, 0, 0], [su, sv], sig, [1, 1, 1])
+    rho = 5.0
+    o = orc.render_view(sm, w, h, intr, IDENT, rho_max=rho, alpha_min=1e-9)
+    Z, su, sv, sig = [float(np.float32(v)) for v in (Z, su, sv, sig)]
+    expect = 2 * math.pi * sig * su * sv * 60 * 70 * (1 - math.exp(-rho * rho / 2)) / Z ** 2
+    assert abs(o["alpha"].sum() - expect) <= 1e-6 * expect
+
+
+# ---------------------------------------------------------------- brute force / culls
+def test_prefilter_is_exact(orc):
+    """The loose candidate box changes nothing: identical to evaluating every
+    surfel at every pixel."""
+    sc = scenes.config0()
+    a = orc.render_scene(sc, prefilter=1)
+    b = orc.render_scene(sc, prefilter=0)
+    for k in ("rgb", "depth", "normal", "alpha", "t_final", "n_contrib", "flags"):
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_culls(orc):
+    """Non-finite inputs, zero quaternions, near-plane and low-opacity
+    surfels contribute nothing and get zero gradient."""
+    good = one_surfel([0, 0, 3], [1, 0, 0, 0], [0.3, 0.3], 0.8, [1, 1, 1])
+    bad = [one_surfel([0, 0, 3], [0, 0, 0, 0], [0.3, 0.3], 0.8, [1, 1, 1]),
+           one_surfel([0, 0, 0.1], [1, 0, 0, 0], [0.3, 0.3], 0.8, [1, 1, 1]),
+           one_surfel([0, 0, 3], [1, 0, 0, 0], [0.3, 0.3], 0.001, [1, 1, 1]),
+           one_surfel([np.nan, 0, 3], [1, 0, 0, 0], [0.3, 0.3], 0.8, [1, 1, 1]),
+           one_surfel([0, 0, 3], [1, 0, 0, 0], [np.inf, 0.3], 0.8, [1, 1, 1]),
+           one_surfel([0, 0, 2.5], [1, 0, 0, 0], [0.3, 0.0], 0.8, [1, 1, 1])]
+    intr = np.array([20, 20, 8, 8], np.float32)
+    ref = orc.render_view(good, 16, 16, intr, IDENT)
+    for b in bad:
+        o = orc.render_view(stack(good, b), 16, 16, intr, IDENT)
+        for k in ("rgb", "alpha"):
+            np.testing.assert_array_equal(o[k], ref[k])
+        g = dict(rgb=np.ones((3, 256)), depth=np.ones(256), normal=np.ones((3, 256)), alpha=np.ones(256))
+        gr = orc.backward_view(stack(good, b), 16, 16, intr, IDENT, g)
+        for k in ("mean", "quat", "scale", "opacity", "color"):
+            assert np.all(gr[k][..., 1] == 0.0)
+
+
+# ---------------------------------------------------------------- binning
+def test_bbox_matches_sampled_ellipse(orc):
+    """The pixel-centre bbox of each surfel equals the one obtained by densely
+    sampling the projected support ellipse boundary (independent of the
+    dual-conic roots), except where a sampled extreme falls within 1e-4 px of
+    a pixel-centre boundary."""
+    sc = scenes.config0()
+    sm = sc.submaps[0]
+    w, h = 64, 48
+    pr = orc.project(sm, w, h, sc.intr[0], sc.viewmat[0])
+    fx, fy, cx, cy = [float(v) for v in sc.intr[0]]
+    th = np.linspace(0, 2 * math.pi, 20001)
+    checked = 0
+    for i in np.nonzero(pr["valid"])[0][:400]:
+        q = sm["quat"][:, i].astype(np.float64)
+        Rs = Rotation.from_quat([q[1], q[2], q[3], q[0]]).as_matrix()
+        p = sm["mean"][:, i].astype(np.float64)
+        su, sv = sm["scale"][:, i].astype(np.float64)
+        pts = p[:, None] + 3.0 * (np.cos(th) * su * Rs[:, 0:1] + np.sin(th) * sv * Rs[:, 1:2])
+        x = fx * pts[0] / pts[2] + cx
+        y = fy * pts[1] / pts[2] + cy
+        lo, hi = x.min(), x.max()
+        ylo, yhi = y.min(), y.max()
+        c0, c1 = max(math.ceil(lo - 0.5), 0), min(math.floor(hi - 0.5), w - 1)
+        r0, r1 = max(math.ceil(ylo - 0.5), 0), min(math.floor(yhi - 0.5), h - 1)
+        near = lambda v: abs((v - 0.5) - round(v - 0.5)) < 1e-4
+        if any(near(v) for v in (lo, hi, ylo, yhi)):
+            continue
+        bb = pr["pix_bbox"][i]
+        if c0 > c1 or r0 > r1:
+            assert bb[0] > bb[2] or bb[1] > bb[3]
+            continue
+        assert tuple(bb) == (c0, r0, c1, r1), (i, bb, (c0, r0, c1, r1))
+        checked += 1
+    assert checked > 100
+
+
+def test_binning_order_and_ranges(orc):
+    """Pairs are the tiles of each surfel's rect, ordered by (tile, fp32
+    depth, index); tile ranges partition the list."""
+    sc = scenes.config0()
+    sm = sc.submaps[0]
+    for tw, th in ((16, 16), (8, 8), (32, 8)):
+        b = orc.bin_view(sm, 64, 48, sc.intr[0], sc.viewmat[0], tile_w=tw, tile_h=th)
+        tx, ty = b["tiles"]
+        tiles, kap, idx = [], [], []
+        for i, (a0, b0, a1, b1) in enumerate(b["rect"]):
+            if a0 < 0:
+                continue
+            for yy in range(b0, b1 + 1):
+                for xx in range(a0, a1 + 1):
+                    tiles.append(yy * tx + xx)
+                    kap.append(np.uint32(b["kappa"][i]).view(np.float32))
+                    idx.append(i)
+        tiles, kap, idx = map(np.asarray, (tiles, kap, idx))
+        o = np.lexsort((idx, kap, tiles))
+        assert np.array_equal(b["pair_tile"], tiles[o])
+        assert np.array_equal(b["pair_surf"], idx[o])
+        cnt = np.bincount(tiles, minlength=tx * ty)
+        assert np.array_equal((b["tile_end"] - b["tile_start"]).astype(np.int64), cnt)
+
+
+def test_pixels_with_support_lie_in_rect(orc):
+    """Every pixel a surfel contributes to (evaluated independently) lies in
+    one of its listed tiles."""
+    sc = scenes.config0()
+    sm = sc.submaps[0]
+    w, h = 64, 48
+    b = orc.bin_view(sm, w, h, sc.intr[0], sc.viewmat[0], tile_w=8, tile_h=8)
+    pr = orc.project(sm, w, h, sc.intr[0], sc.viewmat[0])
+    fx, fy, cx, cy = [float(v) for v in sc.intr[0]]
+    x, y = _pix(w, h)
+    d = np.stack([(x - cx) / fx, (y - cy) / fy, np.ones_like(x)], -1)
+    for i in np.nonzero(pr["valid"])[0][:300]:
+        q = sm["quat"][:, i].astype(np.float64)
+        Rs = Rotation.from_quat([q[1], q[2], q[3], q[0]]).as_matrix()
+        p = sm["mean"][:, i].astype(np.float64)
+        su, sv = sm["scale"][:, i].astype(np.float64)
+        nrm = Rs[:, 2]
+        lam = (p @ nrm) / (d @ nrm)
+        X = lam[:, None] * d - p
+        r2 = (X @ Rs[:, 0] / su) ** 2 + (X @ Rs[:, 1] / sv) ** 2
+        inside = (r2 < 9.0 * (1 - 1e-6)) & (lam > 0)
+        if not inside.any():
+            continue
+        a0, b0, a1, b1 = b["rect"][i]
+        cols = (x[inside] - 0.5).astype(int) // 8
+        rows = (y[inside] - 0.5).astype(int) // 8
+        assert a0 >= 0 and cols.min() >= a0 and cols.max() <= a1 and rows.min() >= b0 and rows.max() <= b1
+
+
+def test_l1_loss_definition(orc):
+    sc = scenes.config0()
+    out = dict(rgb=np.full((3, 3072), 0.5), depth=np.zeros(3072), normal=np.zeros((3, 3072)),
+               alpha=np.zeros(3072))
+    L, g = orc.l1_loss(sc, out)
+    assert abs(L - np.mean(np.abs(0.5 - sc.target_rgb.astype(np.float64)))) < 1e-12
+    assert np.allclose(np.abs(g["rgb"]), 1.0 / (3 * 3072))
