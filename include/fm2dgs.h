@@ -1,0 +1,240 @@
+/*
+ * fm2dgs.h -- C ABI of the MI355X (gfx950) differentiable 2D Gaussian surfel
+ * rasterizer: the data-parallel hot path of the 2DGS mapping backend of
+ * Flash-Mono (arXiv 2604.03092).
+ *
+ * What is computed.  A surfel map (per surfel: centre mu, colour c, opacity
+ * sigma, rotation r as a quaternion, two tangent scales s; Sec. 3,
+ * "Preliminaries") is seen from one or more pinhole cameras.  Each pixel
+ * composites the surfels that cover it front to back with the volumetric
+ * alpha blending of Eq. 1: (I, D, A) = sum_i (c_i, z_i, 1) w_i prod_{j<i}
+ * (1 - w_j), plus a camera-space normal map sum_i n_i w_i prod_{j<i}(1-w_j).
+ * The weight w_i is evaluated by exact ray-splat intersection (the surfel is
+ * a planar disk, Sec. 3): the pixel ray meets the surfel plane at local
+ * coordinates (u, v), G = exp(-(u^2+v^2)/2), w_i = alpha_i =
+ * min(alpha_max, sigma_i G); a surfel is skipped at a pixel when
+ * u^2 + v^2 > rho_max^2 or sigma_i G < alpha_min, and compositing stops
+ * before the surfel that would take the transmittance below t_min.  z_i is
+ * the camera-space depth of the surfel centre, n_i the camera-space surfel
+ * normal turned to face the camera.  Surfels with equal depth key are taken
+ * in index order.  The image adds T_final * background.
+ *
+ * The backward returns dL/d(mean, quat, scale, opacity, color) of every
+ * surfel and dL/d(view matrix) of every view, given dL/d(outputs).  The
+ * fused call evaluates the backend's L1 render loss (Sec. 3.1 render term,
+ * refinement of Sec. 3.3) and its gradient in one pass.
+ *
+ * Conventions (all calls):
+ *   - Every pointer inside fm_surfels, fm_outputs, fm_grad_outputs,
+ *     fm_surfel_grads, the intrinsics/view-matrix arrays, targets, masks,
+ *     the loss scalar and the workspace is DEVICE memory owned by the
+ *     caller.  fm_batch.submaps and fm_batch.views are HOST arrays.
+ *   - Planes are float32, structure-of-arrays, channel-major.  Per-pixel
+ *     planes cover all views of a batch back to back, view v starting at
+ *     sum_{u<v} W_u H_u, rows top to bottom, pixel (col,row) has its centre
+ *     at (col+0.5, row+0.5).
+ *   - Quaternions are (w,x,y,z) of any non-zero norm (normalised inside;
+ *     gradients are w.r.t. the raw values).  Scales are linear and > 0;
+ *     opacity is the activated value.  Activations belong to the caller.
+ *   - intr[v] = (fx, fy, cx, cy); viewmat[v] = world->camera [R|t], 12
+ *     floats row-major.  A Sim(3) keyframe pose renders as its SE(3) part
+ *     with depths divided by the scale; that scaling is the caller's.
+ *   - Gradients are ACCUMULATED (+=) into the caller's buffers.
+ *   - Surfels with any non-finite value, a zero quaternion, a non-positive
+ *     scale, depth <= near_plane, opacity <= alpha_min, or a support disk
+ *     not entirely in front of the camera are culled: they contribute
+ *     nothing and receive zero gradient.
+ *   - Work is enqueued on `stream` (a hipStream_t; NULL = default stream)
+ *     and the calls return without synchronising.  No call allocates
+ *     device memory or synchronises except fm_create, fm_query_status,
+ *     fm_debug_pairs and fm_autotune, so fm_forward, fm_backward and
+ *     fm_fwd_bwd_l1 may be captured into a HIP graph.
+ *   - Errors: every call returns an fm_status and never throws.  Arguments
+ *     are validated on the host before anything is launched; on failure
+ *     nothing is enqueued and fm_last_error(ctx) describes the problem.
+ *   - Calls on one fm_ctx are not thread-safe.
+ */
+#ifndef FM2DGS_H
+#define FM2DGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int fm_status;
+#define FM_OK 0
+#define FM_ERR_INVALID_ARG 1   /* bad pointer, size, index or parameter          */
+#define FM_ERR_CAPACITY 2      /* pair buffer too small (see fm_query_status)     */
+#define FM_ERR_HIP 3           /* a HIP runtime call failed                       */
+#define FM_ERR_UNSUPPORTED 4   /* e.g. a tile shape the library was not built for */
+#define FM_ERR_WORKSPACE 5     /* workspace smaller than fm_workspace_size        */
+
+typedef struct fm_ctx fm_ctx;
+
+/* One surfel map (a submap).  Device pointers, float32, n surfels:
+ * mean[3][n], quat[4][n] (w,x,y,z), scale[2][n], opacity[n], color[3][n]. */
+typedef struct {
+    int32_t n;
+    const float *mean;
+    const float *quat;
+    const float *scale;
+    const float *opacity;
+    const float *color;
+} fm_surfels;
+
+/* Gradient buffers of one submap, same layout as fm_surfels; += semantics.
+ * A NULL member skips that gradient. */
+typedef struct {
+    float *mean;
+    float *quat;
+    float *scale;
+    float *opacity;
+    float *color;
+} fm_surfel_grads;
+
+/* One view (host struct): image size and the submap it renders. */
+typedef struct {
+    int32_t width;   /* 1 .. 16384 */
+    int32_t height;  /* 1 .. 16384 */
+    int32_t submap;  /* index into fm_batch.submaps */
+} fm_view_shape;
+
+/* A batch: several views over one or several submaps (Sec. 3.3 refines the
+ * latest keyframes; each keyframe is a view). */
+typedef struct {
+    int32_t n_submaps;
+    const fm_surfels *submaps;   /* HOST array [n_submaps] */
+    int32_t n_views;
+    const fm_view_shape *views;  /* HOST array [n_views] */
+    const float *intr;           /* DEVICE [n_views][4]  fx, fy, cx, cy */
+    const float *viewmat;        /* DEVICE [n_views][12] world->camera [R|t] */
+} fm_batch;
+
+/* Rasterization parameters; fm_default_params fills the defaults. */
+typedef struct {
+    float alpha_min;   /* 1/255: skip a surfel at a pixel when sigma G < alpha_min */
+    float alpha_max;   /* 0.99: clamp of alpha (must be < 1 for the backward)     */
+    float t_min;       /* 1e-4: stop before the transmittance would fall below it */
+    float rho_max;     /* 3: support radius in units of the tangent scales        */
+    float near_plane;  /* 0.2: cull surfels with centre depth <= near_plane       */
+    float bg[3];       /* background colour added with weight T_final             */
+    int32_t tile_w;    /* tile width in pixels: 8, 16 or 32                       */
+    int32_t tile_h;    /* tile height in pixels: 8, 16 or 32 (tile_w*tile_h<=1024)*/
+    int32_t reserved[2];
+} fm_raster_params;
+
+/* Output planes (device, float32): rgb[3][P], depth[P], normal[3][P],
+ * alpha[P], P = total pixels of the batch.  Depth and normal are the
+ * unnormalised sums of Eq. 1 (divide by alpha for a mean). */
+typedef struct {
+    float *rgb;
+    float *depth;
+    float *normal;
+    float *alpha;
+} fm_outputs;
+
+/* Upstream gradients dL/d(outputs), same layout.  A NULL member means zero. */
+typedef struct {
+    const float *rgb;
+    const float *depth;
+    const float *normal;
+    const float *alpha;
+} fm_grad_outputs;
+
+/* L1 render loss of the fused call: for every view v with P_v pixels,
+ *   L += w_rgb   * sum_px mask * |I - I*| / (3 P_v)
+ *      + w_depth * sum_px mask * |D - D*| / P_v
+ * target_rgb[3][P], target_depth[P] (may be NULL when w_depth == 0),
+ * mask[P] as uint8 0/1 (NULL = all ones).  sign(0) = 0. */
+typedef struct {
+    const float *target_rgb;
+    const float *target_depth;
+    const uint8_t *mask;
+    float w_rgb;
+    float w_depth;
+} fm_l1_loss;
+
+/* Context: binds to a HIP device, queries its properties and holds the
+ * autotuner's choices.  Allocates no device memory. */
+fm_status fm_create(fm_ctx **ctx, int device);
+void fm_destroy(fm_ctx *ctx);
+const char *fm_status_string(fm_status s);
+const char *fm_last_error(const fm_ctx *ctx);
+void fm_default_params(fm_raster_params *p);
+/* Library version as major*10000 + minor*100 + patch. */
+int fm_version(void);
+
+/* Bytes of workspace a batch needs with room for max_pairs (surfel, tile)
+ * pairs.  The workspace holds the projected surfels, the sorted pair list,
+ * per-pixel saved state and gradient scratch; it must stay untouched from
+ * fm_forward until the matching fm_backward has run. */
+fm_status fm_workspace_size(fm_ctx *ctx, const fm_batch *batch, const fm_raster_params *params,
+                            int64_t max_pairs, size_t *bytes);
+
+/* Forward render of every view of the batch into `out`.  If more than
+ * max_pairs pairs are needed the extra pairs are dropped (nothing is written
+ * out of bounds), the workspace records the overflow and fm_query_status
+ * reports FM_ERR_CAPACITY with the required count. */
+fm_status fm_forward(fm_ctx *ctx, const fm_batch *batch, const fm_raster_params *params,
+                     fm_outputs out, void *workspace, size_t ws_bytes, int64_t max_pairs,
+                     void *stream);
+
+/* Backward of the preceding fm_forward on the same workspace, batch and
+ * parameters.  `out` must still hold that forward's outputs (they enter the
+ * adjoint of the compositing).  grads is a HOST array [n_submaps];
+ * dL_dviewmat (device, [n_views][12], may be NULL) receives dL/d[R|t]. */
+fm_status fm_backward(fm_ctx *ctx, const fm_batch *batch, const fm_raster_params *params,
+                      fm_outputs out, fm_grad_outputs dL_dout, void *workspace, size_t ws_bytes,
+                      int64_t max_pairs, const fm_surfel_grads *grads, float *dL_dviewmat,
+                      void *stream);
+
+/* Fused forward + L1 loss + backward of the whole batch (the refinement
+ * step's render term, Sec. 3.3).  Writes the outputs, ADDS the loss into
+ * *loss (device float) and accumulates the gradients as fm_backward does. */
+fm_status fm_fwd_bwd_l1(fm_ctx *ctx, const fm_batch *batch, const fm_raster_params *params,
+                        const fm_l1_loss *loss_spec, fm_outputs out, float *loss,
+                        const fm_surfel_grads *grads, float *dL_dviewmat, void *workspace,
+                        size_t ws_bytes, int64_t max_pairs, void *stream);
+
+/* After the stream that ran fm_forward / fm_fwd_bwd_l1 has been synchronised:
+ * reads the pair count of the last forward on this workspace.  Returns
+ * FM_ERR_CAPACITY (and the required count) if the pair buffer overflowed,
+ * else FM_OK.  Synchronous device read. */
+fm_status fm_query_status(fm_ctx *ctx, const fm_batch *batch, const fm_raster_params *params,
+                          const void *workspace, int64_t max_pairs, int64_t *n_pairs,
+                          int64_t *required_pairs);
+
+/* Test hook: copies the sorted pair list of the last forward into HOST
+ * buffers (cap entries each): tile[k] = global tile id (views' tiles back to
+ * back, row-major within a view), entry[k] = view-local surfel index, view[k]
+ * = view index, and the per-tile ranges tile_start/tile_end (host arrays
+ * sized to the batch's total tile count).  Synchronous. */
+fm_status fm_debug_pairs(fm_ctx *ctx, const fm_batch *batch, const fm_raster_params *params,
+                         const void *workspace, int64_t max_pairs, uint32_t *tile,
+                         uint32_t *surfel, uint32_t *view, int64_t cap, int64_t *n_pairs,
+                         uint32_t *tile_start, uint32_t *tile_end, int64_t n_tiles);
+
+/* Total tile count of a batch for the given tile shape. */
+fm_status fm_tile_count(const fm_batch *batch, const fm_raster_params *params, int64_t *n_tiles);
+
+/* Autotuner: times fm_fwd_bwd_l1 over the supported tile shapes on this
+ * batch (outputs, gradients and the loss are overwritten/accumulated while
+ * it runs) and writes the fastest shape into *chosen (a copy of *params
+ * with tile_w/tile_h set).  The choice is cached in the context under the
+ * batch's shape signature and, if cache_path is not NULL, in a JSON file
+ * read back by later contexts.  The workspace must be sized for the largest
+ * candidate (fm_workspace_size with tile 8x8).  Synchronous. */
+fm_status fm_autotune(fm_ctx *ctx, const fm_batch *batch, const fm_raster_params *params,
+                      const fm_l1_loss *loss_spec, fm_outputs out, float *loss,
+                      const fm_surfel_grads *grads, float *dL_dviewmat, void *workspace,
+                      size_t ws_bytes, int64_t max_pairs, const char *cache_path,
+                      fm_raster_params *chosen, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FM2DGS_H */

@@ -1,0 +1,597 @@
+// fm_api.cpp -- the C ABI (include/fm2dgs.h): argument validation, workspace
+// planning, and the launch sequences of forward, backward and the fused
+// L1 forward+backward.  Every launch goes on the caller's stream; nothing here
+// allocates device memory or synchronises on the hot path.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "fm_internal.h"
+
+using fm::Plan;
+using fm::SubmapDesc;
+using fm::ViewDesc;
+
+struct fm_ctx {
+    int device = 0;
+    std::string name;
+    int n_cu = 0;
+    std::string last_error;
+    std::map<std::string, std::pair<int, int>> tuned;  // batch signature -> tile shape
+};
+
+namespace {
+
+constexpr int kVersion = 10000;  // 1.0.0
+
+fm_status fail(fm_ctx *ctx, fm_status s, const std::string &msg) {
+    if (ctx) ctx->last_error = msg;
+    return s;
+}
+
+fm_status hip_fail(fm_ctx *ctx, hipError_t e, const char *where) {
+    return fail(ctx, FM_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+std::string signature(const fm_batch *b) {
+    std::ostringstream os;
+    os << "v" << b->n_views;
+    for (int v = 0; v < b->n_views; ++v) {
+        const fm_view_shape &s = b->views[v];
+        const int n = b->submaps[s.submap].n;
+        // bucket surfel counts to powers of two so nearby maps share a choice
+        int nb = 0;
+        while ((1 << nb) < n && nb < 31) ++nb;
+        os << "_" << s.width << "x" << s.height << "n" << nb;
+    }
+    return os.str();
+}
+
+struct Built {
+    Plan plan;
+    std::vector<ViewDesc> views;
+    std::vector<SubmapDesc> subs;
+    std::vector<int32_t> vlist;
+};
+
+fm_status resolve_tile(fm_ctx *ctx, const fm_batch *b, const fm_raster_params *prm, int &tw, int &th) {
+    tw = prm->tile_w;
+    th = prm->tile_h;
+    if (tw == 0 && th == 0) {
+        auto it = ctx->tuned.find(signature(b));
+        if (it != ctx->tuned.end()) {
+            tw = it->second.first;
+            th = it->second.second;
+        } else {
+            tw = 16;
+            th = 16;
+        }
+    }
+    if (!fm::tile_shape_supported(tw, th))
+        return fail(ctx, FM_ERR_UNSUPPORTED, "unsupported tile shape " + std::to_string(tw) + "x" +
+                                                 std::to_string(th) + " (use 8x8, 16x8, 16x16 or 32x8)");
+    return FM_OK;
+}
+
+fm_status build(fm_ctx *ctx, const fm_batch *b, const fm_raster_params *prm, int64_t max_pairs,
+                const fm_surfel_grads *grads, bool need_backward, Built &out) {
+    if (!ctx) return FM_ERR_INVALID_ARG;
+    if (!b || !prm) return fail(ctx, FM_ERR_INVALID_ARG, "batch and params must not be NULL");
+    if (b->n_views < 1 || b->n_submaps < 1 || !b->views || !b->submaps)
+        return fail(ctx, FM_ERR_INVALID_ARG, "a batch needs >= 1 view, >= 1 submap and host arrays for both");
+    if (!b->intr || !b->viewmat) return fail(ctx, FM_ERR_INVALID_ARG, "intr and viewmat must not be NULL");
+    if (!(prm->alpha_min > 0.f) || !(prm->alpha_max > prm->alpha_min) || !(prm->alpha_max <= 1.f))
+        return fail(ctx, FM_ERR_INVALID_ARG, "need 0 < alpha_min < alpha_max <= 1");
+    if (need_backward && !(prm->alpha_max < 1.f))
+        return fail(ctx, FM_ERR_INVALID_ARG, "the backward needs alpha_max < 1");
+    if (!(prm->t_min > 0.f && prm->t_min < 1.f)) return fail(ctx, FM_ERR_INVALID_ARG, "need 0 < t_min < 1");
+    if (!(prm->rho_max > 0.f && std::isfinite(prm->rho_max)))
+        return fail(ctx, FM_ERR_INVALID_ARG, "need rho_max > 0");
+    if (!(prm->near_plane > 0.f && std::isfinite(prm->near_plane)))
+        return fail(ctx, FM_ERR_INVALID_ARG, "need near_plane > 0");
+    for (int k = 0; k < 3; ++k)
+        if (!std::isfinite(prm->bg[k])) return fail(ctx, FM_ERR_INVALID_ARG, "background must be finite");
+    if (max_pairs < 1 || max_pairs > (int64_t)0x7FFFFFFF)
+        return fail(ctx, FM_ERR_INVALID_ARG, "max_pairs must be in [1, 2^31-1]");
+    int tw, th;
+    fm_status s = resolve_tile(ctx, b, prm, tw, th);
+    if (s != FM_OK) return s;
+
+    Plan &p = out.plan;
+    p = Plan();
+    p.V = b->n_views;
+    p.S = b->n_submaps;
+    p.tile_w = tw;
+    p.tile_h = th;
+    p.cap = max_pairs;
+    for (int i = 0; i < p.S; ++i) {
+        const fm_surfels &sm = b->submaps[i];
+        if (sm.n < 0 || sm.n > (1 << 28))
+            return fail(ctx, FM_ERR_INVALID_ARG, "submap " + std::to_string(i) + ": n out of range");
+        if (sm.n > 0 && (!sm.mean || !sm.quat || !sm.scale || !sm.opacity || !sm.color))
+            return fail(ctx, FM_ERR_INVALID_ARG, "submap " + std::to_string(i) + ": NULL surfel plane");
+    }
+    out.views.resize(p.V);
+    int64_t E = 0, T = 0, NPX = 0;
+    for (int v = 0; v < p.V; ++v) {
+        const fm_view_shape &vs = b->views[v];
+        if (vs.width < 1 || vs.height < 1 || vs.width > 16384 || vs.height > 16384)
+            return fail(ctx, FM_ERR_INVALID_ARG, "view " + std::to_string(v) + ": size out of [1, 16384]");
+        if (vs.submap < 0 || vs.submap >= p.S)
+            return fail(ctx, FM_ERR_INVALID_ARG, "view " + std::to_string(v) + ": submap index out of range");
+        const fm_surfels &sm = b->submaps[vs.submap];
+        ViewDesc &d = out.views[v];
+        memset(&d, 0, sizeof(d));
+        d.mean = sm.mean; d.quat = sm.quat; d.scale = sm.scale; d.opacity = sm.opacity; d.color = sm.color;
+        d.n = sm.n;
+        d.submap = vs.submap;
+        d.entry_base = (int32_t)E;
+        d.width = vs.width;
+        d.height = vs.height;
+        d.tiles_x = (vs.width + tw - 1) / tw;
+        d.tiles_y = (vs.height + th - 1) / th;
+        d.tile_base = (int32_t)T;
+        d.pixel_offset = NPX;
+        E += (int64_t)align_up((size_t)sm.n, fm::kEntryAlign);
+        T += (int64_t)d.tiles_x * d.tiles_y;
+        NPX += (int64_t)vs.width * vs.height;
+        if (E > ((int64_t)1 << 31) - 256 || T > ((int64_t)1 << 31) || NPX > ((int64_t)1 << 31))
+            return fail(ctx, FM_ERR_INVALID_ARG, "batch too large (entries, tiles or pixels exceed 2^31)");
+    }
+    p.E = E;
+    p.T = T;
+    p.NPX = NPX;
+    int bits = 1;
+    while (bits < 32 && ((int64_t)1 << bits) < T) ++bits;
+    p.tile_bits = bits;
+    p.pair_passes = (bits + fm::kRadixBits - 1) / fm::kRadixBits;
+    p.pairs_in_alt = (p.pair_passes & 1) != 0;
+    auto grid_for = [](int64_t n) {
+        int64_t g = (n + 4095) / 4096;
+        return (int)std::max<int64_t>(1, std::min<int64_t>(g, fm::kMaxSortGrid));
+    };
+    p.sortG_e = grid_for(E);
+    p.sortG_p = grid_for(max_pairs);
+    p.scan_blocks = (int)std::max<int64_t>(1, (E + fm::kScanChunk - 1) / fm::kScanChunk);
+
+    // submaps in index order, each with the list of its views
+    out.subs.resize(p.S);
+    out.vlist.clear();
+    int blocks = 0, max_blocks = 1;
+    for (int sidx = 0; sidx < p.S; ++sidx) {
+        const fm_surfels &sm = b->submaps[sidx];
+        SubmapDesc &d = out.subs[sidx];
+        memset(&d, 0, sizeof(d));
+        d.mean = sm.mean; d.quat = sm.quat; d.scale = sm.scale; d.opacity = sm.opacity; d.color = sm.color;
+        if (grads) {
+            d.g_mean = grads[sidx].mean; d.g_quat = grads[sidx].quat; d.g_scale = grads[sidx].scale;
+            d.g_opacity = grads[sidx].opacity; d.g_color = grads[sidx].color;
+        }
+        d.n = sm.n;
+        d.view_begin = (int32_t)out.vlist.size();
+        for (int v = 0; v < p.V; ++v)
+            if (b->views[v].submap == sidx) out.vlist.push_back(v);
+        d.view_count = (int32_t)out.vlist.size() - d.view_begin;
+        d.block_base = blocks;
+        const int nb = d.view_count > 0 ? (sm.n + 255) / 256 : 0;
+        blocks += nb;
+        max_blocks = std::max(max_blocks, (sm.n + 255) / 256);
+    }
+    p.a7_blocks = blocks;
+    p.a7_max_blocks = max_blocks;
+
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o = align_up(o + std::max<size_t>(bytes, 1), 256);
+        return at;
+    };
+    p.o_views = take(sizeof(ViewDesc) * p.V);
+    p.o_subs = take(sizeof(SubmapDesc) * p.S);
+    p.o_vlist = take(4 * (size_t)p.V);
+    p.o_status = take(sizeof(fm::Status));
+    p.o_rec = take(sizeof(fm::Rec) * (size_t)E);
+    p.o_key = take(4 * (size_t)E);
+    p.o_cnt = take(4 * (size_t)E);
+    p.o_key2 = take(4 * (size_t)E);
+    p.o_val = take(4 * (size_t)E);
+    p.o_val2 = take(4 * (size_t)E);
+    p.o_scan = take(4 * align_up(p.scan_blocks, 64) + 8 * (size_t)p.scan_blocks);
+    p.o_pkey = take(4 * (size_t)max_pairs);
+    p.o_pval = take(4 * (size_t)max_pairs);
+    p.o_pkey2 = take(4 * (size_t)max_pairs);
+    p.o_pval2 = take(4 * (size_t)max_pairs);
+    p.o_hist = take(4 * (size_t)fm::kRadix * std::max(p.sortG_e, p.sortG_p));
+    p.o_tstart = take(4 * (size_t)T);
+    p.o_tend = take(4 * (size_t)T);
+    p.o_tfinal = take(4 * (size_t)NPX);
+    p.o_nlast = take(4 * (size_t)NPX);
+    p.o_grad = take(64 * (size_t)E);
+    p.o_pose = take(48 * (size_t)p.V * p.a7_max_blocks);
+    p.o_loss = take(4 * (size_t)T);
+    p.bytes = o;
+    return FM_OK;
+}
+
+fm::KParams kparams(const fm_raster_params *prm, const Plan &p) {
+    fm::KParams k;
+    k.alpha_min = prm->alpha_min;
+    k.alpha_max = prm->alpha_max;
+    k.t_min = prm->t_min;
+    k.rho_max = prm->rho_max;
+    k.near_plane = prm->near_plane;
+    k.bg[0] = prm->bg[0]; k.bg[1] = prm->bg[1]; k.bg[2] = prm->bg[2];
+    k.tile_w = p.tile_w;
+    k.tile_h = p.tile_h;
+    return k;
+}
+
+fm_status check_ws(fm_ctx *ctx, const Plan &p, const void *ws, size_t ws_bytes) {
+    if (!ws) return fail(ctx, FM_ERR_INVALID_ARG, "workspace must not be NULL");
+    if (ws_bytes < p.bytes)
+        return fail(ctx, FM_ERR_WORKSPACE, "workspace has " + std::to_string(ws_bytes) + " bytes, needs " +
+                                               std::to_string(p.bytes));
+    return FM_OK;
+}
+
+fm_status check_out(fm_ctx *ctx, const fm_outputs &o) {
+    if (!o.rgb || !o.depth || !o.normal || !o.alpha)
+        return fail(ctx, FM_ERR_INVALID_ARG, "every output plane must be non-NULL");
+    return FM_OK;
+}
+
+fm_status use_device(fm_ctx *ctx) {
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipGetDevice");
+    if (cur != ctx->device) {
+        e = hipSetDevice(ctx->device);
+        if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
+    }
+    return FM_OK;
+}
+
+#define FM_TRY_HIP(expr, where)                      \
+    do {                                             \
+        hipError_t _e = (expr);                      \
+        if (_e != hipSuccess) return hip_fail(ctx, _e, where); \
+    } while (0)
+
+fm_status run_forward(fm_ctx *ctx, Built &bt, const fm_raster_params *prm, const fm_batch *b, void *ws,
+                      const fm_outputs &out, hipStream_t st) {
+    const fm::KParams kp = kparams(prm, bt.plan);
+    FM_TRY_HIP(fm::launch_setup(bt.plan, ws, bt.views.data(), bt.subs.data(), bt.vlist.data(), st), "setup");
+    FM_TRY_HIP(fm::launch_preprocess(bt.plan, ws, kp, b->intr, b->viewmat, st), "preprocess");
+    FM_TRY_HIP(fm::launch_binning(bt.plan, ws, kp, st), "binning");
+    FM_TRY_HIP(fm::launch_render_fwd(bt.plan, ws, kp, out, st), "render_fwd");
+    return FM_OK;
+}
+
+fm_status run_fused(fm_ctx *ctx, Built &bt, const fm_raster_params *prm, const fm_batch *b, void *ws,
+                    const fm_l1_loss *ls, const fm_outputs &out, float *loss, float *dL_dviewmat,
+                    hipStream_t st) {
+    const fm::KParams kp = kparams(prm, bt.plan);
+    fm::LossArgs la;
+    la.target_rgb = ls->target_rgb;
+    la.target_depth = ls->target_depth;
+    la.mask = ls->mask;
+    la.w_rgb = ls->w_rgb;
+    la.w_depth = ls->w_depth;
+    FM_TRY_HIP(fm::launch_setup(bt.plan, ws, bt.views.data(), bt.subs.data(), bt.vlist.data(), st), "setup");
+    FM_TRY_HIP(fm::launch_preprocess(bt.plan, ws, kp, b->intr, b->viewmat, st), "preprocess");
+    FM_TRY_HIP(fm::launch_binning(bt.plan, ws, kp, st), "binning");
+    FM_TRY_HIP(fm::launch_zero_grad(bt.plan, ws, st), "zero_grad");
+    FM_TRY_HIP(fm::launch_render_fused(bt.plan, ws, kp, la, out, loss, st), "render_fused");
+    FM_TRY_HIP(fm::launch_preprocess_bwd(bt.plan, ws, b->intr, b->viewmat, dL_dviewmat, st), "preprocess_bwd");
+    return FM_OK;
+}
+
+fm_status check_loss(fm_ctx *ctx, const fm_l1_loss *ls) {
+    if (!ls) return fail(ctx, FM_ERR_INVALID_ARG, "loss spec must not be NULL");
+    if (!ls->target_rgb) return fail(ctx, FM_ERR_INVALID_ARG, "target_rgb must not be NULL");
+    if (ls->w_depth != 0.f && !ls->target_depth)
+        return fail(ctx, FM_ERR_INVALID_ARG, "target_depth is required when w_depth != 0");
+    if (!std::isfinite(ls->w_rgb) || !std::isfinite(ls->w_depth))
+        return fail(ctx, FM_ERR_INVALID_ARG, "loss weights must be finite");
+    return FM_OK;
+}
+
+// --- tiny JSON cache: {"signature": [tw, th], ...} ---------------------------
+void load_cache(fm_ctx *ctx, const char *path) {
+    std::ifstream f(path);
+    if (!f) return;
+    std::stringstream ss;
+    ss << f.rdbuf();
+    const std::string s = ss.str();
+    size_t pos = 0;
+    const std::string dev = "\"device\": \"";
+    while (true) {
+        size_t q0 = s.find('"', pos);
+        if (q0 == std::string::npos) break;
+        size_t q1 = s.find('"', q0 + 1);
+        if (q1 == std::string::npos) break;
+        const std::string key = s.substr(q0 + 1, q1 - q0 - 1);
+        size_t lb = s.find('[', q1);
+        size_t rb = s.find(']', q1);
+        size_t nextq = s.find('"', q1 + 1);
+        if (lb == std::string::npos || rb == std::string::npos || (nextq != std::string::npos && nextq < lb)) {
+            pos = q1 + 1;
+            continue;
+        }
+        int tw = 0, th = 0;
+        if (sscanf(s.c_str() + lb, "[%d, %d]", &tw, &th) == 2 && fm::tile_shape_supported(tw, th))
+            ctx->tuned[key] = {tw, th};
+        pos = rb + 1;
+    }
+}
+
+void save_cache(fm_ctx *ctx, const char *path) {
+    std::ofstream f(path);
+    if (!f) return;
+    f << "{\n";
+    size_t k = 0;
+    for (auto &kv : ctx->tuned) {
+        f << "  \"" << kv.first << "\": [" << kv.second.first << ", " << kv.second.second << "]";
+        f << (++k < ctx->tuned.size() ? ",\n" : "\n");
+    }
+    f << "}\n";
+}
+
+}  // namespace
+
+extern "C" {
+
+fm_status fm_create(fm_ctx **out, int device) {
+    if (!out) return FM_ERR_INVALID_ARG;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return FM_ERR_INVALID_ARG;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return FM_ERR_HIP;
+    fm_ctx *c = new fm_ctx();
+    c->device = device;
+    c->name = prop.gcnArchName;
+    c->n_cu = prop.multiProcessorCount;
+    *out = c;
+    return FM_OK;
+}
+
+void fm_destroy(fm_ctx *ctx) { delete ctx; }
+
+const char *fm_status_string(fm_status s) {
+    switch (s) {
+        case FM_OK: return "ok";
+        case FM_ERR_INVALID_ARG: return "invalid argument";
+        case FM_ERR_CAPACITY: return "pair capacity exceeded";
+        case FM_ERR_HIP: return "HIP runtime error";
+        case FM_ERR_UNSUPPORTED: return "unsupported configuration";
+        case FM_ERR_WORKSPACE: return "workspace too small";
+        default: return "unknown status";
+    }
+}
+
+const char *fm_last_error(const fm_ctx *ctx) { return ctx ? ctx->last_error.c_str() : "no context"; }
+
+int fm_version(void) { return kVersion; }
+
+void fm_default_params(fm_raster_params *p) {
+    if (!p) return;
+    memset(p, 0, sizeof(*p));
+    p->alpha_min = 1.0f / 255.0f;
+    p->alpha_max = 0.99f;
+    p->t_min = 1e-4f;
+    p->rho_max = 3.0f;
+    p->near_plane = 0.2f;
+    p->tile_w = 16;
+    p->tile_h = 16;
+}
+
+fm_status fm_workspace_size(fm_ctx *ctx, const fm_batch *b, const fm_raster_params *prm, int64_t max_pairs,
+                            size_t *bytes) {
+    if (!ctx) return FM_ERR_INVALID_ARG;
+    if (!bytes) return fail(ctx, FM_ERR_INVALID_ARG, "bytes must not be NULL");
+    Built bt;
+    fm_status s = build(ctx, b, prm, max_pairs, nullptr, false, bt);
+    if (s != FM_OK) return s;
+    *bytes = bt.plan.bytes;
+    return FM_OK;
+}
+
+fm_status fm_tile_count(const fm_batch *b, const fm_raster_params *prm, int64_t *n_tiles) {
+    if (!b || !prm || !n_tiles || !b->views || b->n_views < 1) return FM_ERR_INVALID_ARG;
+    if (!fm::tile_shape_supported(prm->tile_w, prm->tile_h)) return FM_ERR_UNSUPPORTED;
+    int64_t T = 0;
+    for (int v = 0; v < b->n_views; ++v)
+        T += (int64_t)((b->views[v].width + prm->tile_w - 1) / prm->tile_w) *
+             ((b->views[v].height + prm->tile_h - 1) / prm->tile_h);
+    *n_tiles = T;
+    return FM_OK;
+}
+
+fm_status fm_forward(fm_ctx *ctx, const fm_batch *b, const fm_raster_params *prm, fm_outputs out, void *ws,
+                     size_t ws_bytes, int64_t max_pairs, void *stream) {
+    if (!ctx) return FM_ERR_INVALID_ARG;
+    Built bt;
+    fm_status s = build(ctx, b, prm, max_pairs, nullptr, false, bt);
+    if (s == FM_OK) s = check_ws(ctx, bt.plan, ws, ws_bytes);
+    if (s == FM_OK) s = check_out(ctx, out);
+    if (s == FM_OK) s = use_device(ctx);
+    if (s != FM_OK) return s;
+    return run_forward(ctx, bt, prm, b, ws, out, (hipStream_t)stream);
+}
+
+fm_status fm_backward(fm_ctx *ctx, const fm_batch *b, const fm_raster_params *prm, fm_outputs out,
+                      fm_grad_outputs g, void *ws, size_t ws_bytes, int64_t max_pairs,
+                      const fm_surfel_grads *grads, float *dL_dviewmat, void *stream) {
+    if (!ctx) return FM_ERR_INVALID_ARG;
+    if (!grads) return fail(ctx, FM_ERR_INVALID_ARG, "grads must not be NULL (one entry per submap)");
+    Built bt;
+    fm_status s = build(ctx, b, prm, max_pairs, grads, true, bt);
+    if (s == FM_OK) s = check_ws(ctx, bt.plan, ws, ws_bytes);
+    if (s == FM_OK) s = check_out(ctx, out);
+    if (s == FM_OK) s = use_device(ctx);
+    if (s != FM_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    const fm::KParams kp = kparams(prm, bt.plan);
+    FM_TRY_HIP(fm::launch_setup(bt.plan, ws, bt.views.data(), bt.subs.data(), bt.vlist.data(), st), "setup");
+    FM_TRY_HIP(fm::launch_zero_grad(bt.plan, ws, st), "zero_grad");
+    FM_TRY_HIP(fm::launch_render_bwd(bt.plan, ws, kp, out, g, st), "render_bwd");
+    FM_TRY_HIP(fm::launch_preprocess_bwd(bt.plan, ws, b->intr, b->viewmat, dL_dviewmat, st), "preprocess_bwd");
+    return FM_OK;
+}
+
+fm_status fm_fwd_bwd_l1(fm_ctx *ctx, const fm_batch *b, const fm_raster_params *prm, const fm_l1_loss *ls,
+                        fm_outputs out, float *loss, const fm_surfel_grads *grads, float *dL_dviewmat, void *ws,
+                        size_t ws_bytes, int64_t max_pairs, void *stream) {
+    if (!ctx) return FM_ERR_INVALID_ARG;
+    if (!grads) return fail(ctx, FM_ERR_INVALID_ARG, "grads must not be NULL (one entry per submap)");
+    Built bt;
+    fm_status s = build(ctx, b, prm, max_pairs, grads, true, bt);
+    if (s == FM_OK) s = check_ws(ctx, bt.plan, ws, ws_bytes);
+    if (s == FM_OK) s = check_out(ctx, out);
+    if (s == FM_OK) s = check_loss(ctx, ls);
+    if (s == FM_OK) s = use_device(ctx);
+    if (s != FM_OK) return s;
+    return run_fused(ctx, bt, prm, b, ws, ls, out, loss, dL_dviewmat, (hipStream_t)stream);
+}
+
+fm_status fm_query_status(fm_ctx *ctx, const fm_batch *b, const fm_raster_params *prm, const void *ws,
+                          int64_t max_pairs, int64_t *n_pairs, int64_t *required) {
+    if (!ctx) return FM_ERR_INVALID_ARG;
+    Built bt;
+    fm_status s = build(ctx, b, prm, max_pairs, nullptr, false, bt);
+    if (s != FM_OK) return s;
+    if (!ws) return fail(ctx, FM_ERR_INVALID_ARG, "workspace must not be NULL");
+    s = use_device(ctx);
+    if (s != FM_OK) return s;
+    fm::Status st;
+    FM_TRY_HIP(hipMemcpy(&st, static_cast<const char *>(ws) + bt.plan.o_status, sizeof(st), hipMemcpyDeviceToHost),
+               "hipMemcpy(status)");
+    if (n_pairs) *n_pairs = st.n_pairs;
+    if (required) *required = (int64_t)st.required;
+    if (st.overflow) {
+        ctx->last_error = "pair buffer overflow: " + std::to_string(st.required) + " pairs needed, capacity " +
+                          std::to_string(max_pairs);
+        return FM_ERR_CAPACITY;
+    }
+    return FM_OK;
+}
+
+fm_status fm_debug_pairs(fm_ctx *ctx, const fm_batch *b, const fm_raster_params *prm, const void *ws,
+                         int64_t max_pairs, uint32_t *tile, uint32_t *surfel, uint32_t *view, int64_t cap,
+                         int64_t *n_pairs, uint32_t *tile_start, uint32_t *tile_end, int64_t n_tiles) {
+    if (!ctx) return FM_ERR_INVALID_ARG;
+    Built bt;
+    fm_status s = build(ctx, b, prm, max_pairs, nullptr, false, bt);
+    if (s != FM_OK) return s;
+    const Plan &p = bt.plan;
+    if (!ws || !n_pairs) return fail(ctx, FM_ERR_INVALID_ARG, "workspace and n_pairs must not be NULL");
+    s = use_device(ctx);
+    if (s != FM_OK) return s;
+    fm::Status st;
+    const char *w = static_cast<const char *>(ws);
+    FM_TRY_HIP(hipMemcpy(&st, w + p.o_status, sizeof(st), hipMemcpyDeviceToHost), "hipMemcpy(status)");
+    *n_pairs = st.n_pairs;
+    const int64_t m = std::min<int64_t>(st.n_pairs, cap);
+    if (m > 0 && (tile || surfel || view)) {
+        std::vector<uint32_t> k(m), e(m);
+        FM_TRY_HIP(hipMemcpy(k.data(), w + (p.pairs_in_alt ? p.o_pkey2 : p.o_pkey), 4 * m, hipMemcpyDeviceToHost),
+                   "hipMemcpy(pairs)");
+        FM_TRY_HIP(hipMemcpy(e.data(), w + (p.pairs_in_alt ? p.o_pval2 : p.o_pval), 4 * m, hipMemcpyDeviceToHost),
+                   "hipMemcpy(pairs)");
+        for (int64_t i = 0; i < m; ++i) {
+            int lo = 0, hi = p.V - 1;
+            while (lo < hi) {
+                int mid = (lo + hi + 1) / 2;
+                if ((uint32_t)bt.views[mid].entry_base <= e[i]) lo = mid; else hi = mid - 1;
+            }
+            if (tile) tile[i] = k[i];
+            if (surfel) surfel[i] = e[i] - (uint32_t)bt.views[lo].entry_base;
+            if (view) view[i] = (uint32_t)lo;
+        }
+    }
+    if (tile_start && tile_end) {
+        if (n_tiles < p.T) return fail(ctx, FM_ERR_INVALID_ARG, "tile range buffers too small");
+        FM_TRY_HIP(hipMemcpy(tile_start, w + p.o_tstart, 4 * p.T, hipMemcpyDeviceToHost), "hipMemcpy(ranges)");
+        FM_TRY_HIP(hipMemcpy(tile_end, w + p.o_tend, 4 * p.T, hipMemcpyDeviceToHost), "hipMemcpy(ranges)");
+    }
+    return FM_OK;
+}
+
+fm_status fm_autotune(fm_ctx *ctx, const fm_batch *b, const fm_raster_params *prm, const fm_l1_loss *ls,
+                      fm_outputs out, float *loss, const fm_surfel_grads *grads, float *dL_dviewmat, void *ws,
+                      size_t ws_bytes, int64_t max_pairs, const char *cache_path, fm_raster_params *chosen,
+                      void *stream) {
+    if (!ctx) return FM_ERR_INVALID_ARG;
+    if (!chosen || !prm) return fail(ctx, FM_ERR_INVALID_ARG, "params and chosen must not be NULL");
+    if (cache_path) load_cache(ctx, cache_path);
+    const std::string sig = signature(b);
+    *chosen = *prm;
+    auto hit = ctx->tuned.find(sig);
+    if (hit != ctx->tuned.end()) {
+        chosen->tile_w = hit->second.first;
+        chosen->tile_h = hit->second.second;
+        return FM_OK;
+    }
+    const int shapes[4][2] = {{16, 16}, {8, 8}, {16, 8}, {32, 8}};
+    hipStream_t st = (hipStream_t)stream;
+    fm_status s = use_device(ctx);
+    if (s != FM_OK) return s;
+    hipEvent_t e0, e1;
+    FM_TRY_HIP(hipEventCreate(&e0), "hipEventCreate");
+    FM_TRY_HIP(hipEventCreate(&e1), "hipEventCreate");
+    float best = 1e30f;
+    int bw = 16, bh = 16;
+    bool any = false;
+    for (auto &sh : shapes) {
+        fm_raster_params q = *prm;
+        q.tile_w = sh[0];
+        q.tile_h = sh[1];
+        Built bt;
+        s = build(ctx, b, &q, max_pairs, grads, true, bt);
+        if (s != FM_OK || bt.plan.bytes > ws_bytes) continue;
+        if (check_loss(ctx, ls) != FM_OK || check_out(ctx, out) != FM_OK) break;
+        // warm-up, then time a few repetitions
+        s = run_fused(ctx, bt, &q, b, ws, ls, out, loss, dL_dviewmat, st);
+        if (s != FM_OK) break;
+        FM_TRY_HIP(hipStreamSynchronize(st), "hipStreamSynchronize");
+        fm::Status stt;
+        FM_TRY_HIP(hipMemcpy(&stt, static_cast<char *>(ws) + bt.plan.o_status, sizeof(stt), hipMemcpyDeviceToHost),
+                   "hipMemcpy(status)");
+        if (stt.overflow) continue;
+        const int reps = 3;
+        FM_TRY_HIP(hipEventRecord(e0, st), "hipEventRecord");
+        for (int r = 0; r < reps; ++r) run_fused(ctx, bt, &q, b, ws, ls, out, loss, dL_dviewmat, st);
+        FM_TRY_HIP(hipEventRecord(e1, st), "hipEventRecord");
+        FM_TRY_HIP(hipEventSynchronize(e1), "hipEventSynchronize");
+        float ms = 0.f;
+        FM_TRY_HIP(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+        any = true;
+        if (ms < best) {
+            best = ms;
+            bw = sh[0];
+            bh = sh[1];
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (!any) return s != FM_OK ? s : fail(ctx, FM_ERR_WORKSPACE, "no tile shape fits the workspace and capacity");
+    ctx->tuned[sig] = {bw, bh};
+    if (cache_path) save_cache(ctx, cache_path);
+    chosen->tile_w = bw;
+    chosen->tile_h = bh;
+    return FM_OK;
+}
+
+}  // extern "C"

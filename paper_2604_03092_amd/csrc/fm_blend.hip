@@ -1,0 +1,510 @@
+// fm_blend.hip -- per-tile front-to-back compositing (Eq. 1) and its adjoint
+// on gfx950.
+//
+// One workgroup per tile; each wave64 owns an 8x8 pixel block of the tile.
+// The tile's depth-ordered surfels are staged through LDS in batches of one
+// record per thread; every wave reads them as broadcasts and skips a whole
+// surfel with one scalar test when the surfel's pixel bbox misses its block.
+// Waves stop when all their pixels have reached the transmittance floor.
+//
+// Backward (forward order, no per-pixel lists): with f_k = g . (c_k, z_k,
+// n_k, 1) and S = g . (I, D, N, A) known from the forward outputs, the
+// adjoint of the compositing is
+//     dL/dalpha_k = T_k f_k - (S - S_k) / (1 - alpha_k),   S_k = sum_{j<=k} f_j alpha_j T_j,
+// so the backward walks the list front to back exactly like the forward,
+// recomputing T, and stops at the pixel's last contributor.  Per surfel, the
+// 16 screen-space gradients of a wave are reduced with permlane swaps + DPP,
+// the waves of the tile add into LDS, and the tile adds into the entry's
+// gradient slot with one coalesced 16-float atomic group.
+#include "fm_internal.h"
+#include "fm_wave.h"
+
+namespace fm {
+
+namespace {
+
+struct Surf {
+    float h0, h1, h2, h3, h4, h5, h6, h7, h8;
+    float sig, c0, c1, c2, n0, n1, n2, xc, yc;
+};
+
+__device__ __forceinline__ void load_surf(const Rec *r, Surf &s) {
+    const float4 *p = reinterpret_cast<const float4 *>(r);
+    const float4 a = p[0], b = p[1], c = p[2], d = p[3];
+    const float2 e = reinterpret_cast<const float2 *>(r)[8];
+    s.h0 = a.x; s.h1 = a.y; s.h2 = a.z; s.h3 = a.w;
+    s.h4 = b.x; s.h5 = b.y; s.h6 = b.z; s.h7 = b.w;
+    s.h8 = c.x; s.sig = c.y; s.c0 = c.z; s.c1 = c.w;
+    s.c2 = d.x; s.n0 = d.y; s.n1 = d.z; s.n2 = d.w;
+    s.xc = e.x; s.yc = e.y;
+}
+
+struct Hit {
+    float a0, a1, a2, b0, b1, b2, w0, w1, w2;
+    float G, at, alpha;
+};
+
+// Ray-splat intersection at the pixel centre (px, py).  The rows a, b are the
+// two plane constraints of the pixel ray in the surfel's local (u, v, 1)
+// coordinates; their cross product w gives (u, v) = (w0, w1) / w2.  Returns
+// false when the pixel is outside the rho_max support or sigma G < alpha_min.
+// Identical arithmetic in forward and backward (no contraction beyond the
+// explicit fmaf calls), so both see the same decisions.
+__device__ __forceinline__ bool splat(const Surf &s, float px, float py, float rho2, float amin, float amax,
+                                      Hit &h) {
+#pragma clang fp contract(off)
+    const float xp = px - s.xc, yp = py - s.yc;
+    h.a0 = fmaf(-xp, s.h6, s.h0);
+    h.a1 = fmaf(-xp, s.h7, s.h1);
+    h.a2 = fmaf(-xp, s.h8, s.h2);
+    h.b0 = fmaf(-yp, s.h6, s.h3);
+    h.b1 = fmaf(-yp, s.h7, s.h4);
+    h.b2 = fmaf(-yp, s.h8, s.h5);
+    h.w0 = fmaf(h.a1, h.b2, -(h.a2 * h.b1));
+    h.w1 = fmaf(h.a2, h.b0, -(h.a0 * h.b2));
+    h.w2 = fmaf(h.a0, h.b1, -(h.a1 * h.b0));
+    const float num = fmaf(h.w0, h.w0, h.w1 * h.w1);
+    const float den = h.w2 * h.w2;
+    if (!(num <= rho2 * den) || !(den > 0.f)) return false;
+    const float r2 = num * __builtin_amdgcn_rcpf(den);
+    h.G = __builtin_amdgcn_exp2f(r2 * -0.72134752044448170368f);  // exp(-r2/2)
+    h.at = s.sig * h.G;
+    if (!(h.at >= amin)) return false;
+    h.alpha = fminf(amax, h.at);
+    return true;
+}
+
+template <int TW, int TH> struct Geo {
+    static constexpr int NT = TW * TH;
+    static constexpr int WX = TW / 8;
+    static constexpr int NW = NT / 64;
+};
+
+struct PixelCtx {
+    int view, col, row, wx0, wy0;
+    bool inside;
+    int64_t pix;       // global pixel index
+    float px, py;
+    uint32_t start, end;
+    int W, H;
+};
+
+template <int TW, int TH>
+__device__ __forceinline__ PixelCtx pixel_ctx(const ViewDesc *views, int V, const uint32_t *ts,
+                                              const uint32_t *te) {
+    using Gm = Geo<TW, TH>;
+    PixelCtx c;
+    const int tile = blockIdx.x;
+    c.view = view_of_tile(views, V, tile);
+    const ViewDesc &vd = views[c.view];
+    const int local = tile - vd.tile_base;
+    const int tx = local % vd.tiles_x, ty = local / vd.tiles_x;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    c.wx0 = tx * TW + (wave % Gm::WX) * 8;
+    c.wy0 = ty * TH + (wave / Gm::WX) * 8;
+    c.col = c.wx0 + (lane & 7);
+    c.row = c.wy0 + (lane >> 3);
+    c.W = vd.width;
+    c.H = vd.height;
+    c.inside = c.col < vd.width && c.row < vd.height;
+    c.pix = vd.pixel_offset + (int64_t)c.row * vd.width + c.col;
+    c.px = (float)c.col + 0.5f;
+    c.py = (float)c.row + 0.5f;
+    c.start = ts[tile];
+    c.end = te[tile];
+    return c;
+}
+
+// Does surfel j's bbox miss this wave's 8x8 block?  Scalar test.
+__device__ __forceinline__ bool bbox_miss(const Rec *sr, int wx0, int wy0) {
+    const uint32_t *bw = reinterpret_cast<const uint32_t *>(sr) + 18;
+    const uint32_t b0 = __builtin_amdgcn_readfirstlane(bw[0]);
+    const uint32_t b1 = __builtin_amdgcn_readfirstlane(bw[1]);
+    const int x0 = (int)(b0 & 0xFFFFu), y0 = (int)(b0 >> 16);
+    const int x1 = (int)(b1 & 0xFFFFu), y1 = (int)(b1 >> 16);
+    return x1 < wx0 || x0 > wx0 + 7 || y1 < wy0 || y0 > wy0 + 7;
+}
+
+// Forward traversal of the tile list.  acc = (r, g, b, depth, nx, ny, nz, A).
+template <int TW, int TH>
+__device__ __forceinline__ void tile_forward(const PixelCtx &c, const uint32_t *__restrict__ pval,
+                                             const Rec *__restrict__ rec, const KParams &kp, Rec *srec,
+                                             float acc[8], float &T, uint32_t &nlast) {
+    using Gm = Geo<TW, TH>;
+    const float rho2 = kp.rho_max * kp.rho_max;
+    bool done = !c.inside;
+    T = 1.f;
+    nlast = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc[k] = 0.f;
+    for (uint32_t base = c.start; base < c.end; base += Gm::NT) {
+        if (__syncthreads_count(!done) == 0) break;
+        const int cntb = (int)min((uint32_t)Gm::NT, c.end - base);
+        if ((int)threadIdx.x < cntb) srec[threadIdx.x] = rec[pval[base + threadIdx.x]];
+        __syncthreads();
+        if (ballot64(!done) == 0) continue;
+        for (int j = 0; j < cntb; ++j) {
+            if (bbox_miss(&srec[j], c.wx0, c.wy0)) continue;
+            if (!done) {
+                Surf s;
+                load_surf(&srec[j], s);
+                Hit h;
+                if (splat(s, c.px, c.py, rho2, kp.alpha_min, kp.alpha_max, h)) {
+#pragma clang fp contract(off)
+                    const float test = T * (1.f - h.alpha);
+                    if (test < kp.t_min) {
+                        done = true;
+                    } else {
+                        const float wgt = h.alpha * T;
+                        acc[0] = fmaf(s.c0, wgt, acc[0]);
+                        acc[1] = fmaf(s.c1, wgt, acc[1]);
+                        acc[2] = fmaf(s.c2, wgt, acc[2]);
+                        acc[3] = fmaf(s.h8, wgt, acc[3]);
+                        acc[4] = fmaf(s.n0, wgt, acc[4]);
+                        acc[5] = fmaf(s.n1, wgt, acc[5]);
+                        acc[6] = fmaf(s.n2, wgt, acc[6]);
+                        acc[7] = acc[7] + wgt;
+                        T = test;
+                        nlast = base - c.start + (uint32_t)j + 1u;
+                    }
+                }
+            }
+            if (ballot64(!done) == 0) break;
+        }
+    }
+}
+
+// Adjoint traversal.  g = dL/d(r, g, b, depth, nx, ny, nz, A) of this pixel,
+// S = g . outputs, nlast = this pixel's contributor prefix length, maxlast =
+// the tile's maximum.  Accumulates into the entries' gradient slots.
+template <int TW, int TH>
+__device__ __forceinline__ void tile_backward(const PixelCtx &c, const uint32_t *__restrict__ pval,
+                                              const Rec *__restrict__ rec, const KParams &kp, Rec *srec,
+                                              uint32_t *sent, float (*sgrad)[16], uint32_t *stouch,
+                                              const float g[8], float S, uint32_t nlast, uint32_t maxlast,
+                                              float *__restrict__ grad) {
+    using Gm = Geo<TW, TH>;
+    const float rho2 = kp.rho_max * kp.rho_max;
+    float T = 1.f, Sk = 0.f;
+    const uint32_t len = c.end - c.start;
+    const uint32_t end = c.start + (maxlast < len ? maxlast : len);
+    for (uint32_t base = c.start; base < end; base += Gm::NT) {
+        const int cntb = (int)min((uint32_t)Gm::NT, end - base);
+        if ((int)threadIdx.x < cntb) {
+            const uint32_t ent = pval[base + threadIdx.x];
+            sent[threadIdx.x] = ent;
+            srec[threadIdx.x] = rec[ent];
+        }
+#pragma unroll
+        for (int k = 0; k < 16; ++k) sgrad[threadIdx.x][k] = 0.f;
+        stouch[threadIdx.x] = 0;
+        __syncthreads();
+        const uint32_t kbase = base - c.start;
+        if (ballot64(kbase < nlast) != 0) {
+            for (int j = 0; j < cntb; ++j) {
+                if (bbox_miss(&srec[j], c.wx0, c.wy0)) continue;
+                const bool live = kbase + (uint32_t)j < nlast;
+                if (ballot64(live) == 0) break;
+                float gr[16];
+#pragma unroll
+                for (int k = 0; k < 16; ++k) gr[k] = 0.f;
+                bool hit = false;
+                if (live) {
+                    Surf s;
+                    load_surf(&srec[j], s);
+                    Hit h;
+                    if (splat(s, c.px, c.py, rho2, kp.alpha_min, kp.alpha_max, h)) {
+#pragma clang fp contract(off)
+                        hit = true;
+                        const float test = T * (1.f - h.alpha);
+                        const float wgt = h.alpha * T;
+                        const float f = g[0] * s.c0 + g[1] * s.c1 + g[2] * s.c2 + g[3] * s.h8 +
+                                        g[4] * s.n0 + g[5] * s.n1 + g[6] * s.n2 + g[7];
+                        Sk = fmaf(f, wgt, Sk);
+                        const float dal = T * f - (S - Sk) * __builtin_amdgcn_rcpf(1.f - h.alpha);
+                        gr[10] = g[0] * wgt;
+                        gr[11] = g[1] * wgt;
+                        gr[12] = g[2] * wgt;
+                        gr[13] = g[4] * wgt;
+                        gr[14] = g[5] * wgt;
+                        gr[15] = g[6] * wgt;
+                        if (h.at <= kp.alpha_max) {
+                            const float xp = c.px - s.xc, yp = c.py - s.yc;
+                            gr[9] = dal * h.G;
+                            const float dr2 = -0.5f * h.G * s.sig * dal;
+                            const float iw = __builtin_amdgcn_rcpf(h.w2);
+                            const float u = h.w0 * iw, v = h.w1 * iw;
+                            const float du = 2.f * u * dr2, dv = 2.f * v * dr2;
+                            const float gw0 = du * iw, gw1 = dv * iw, gw2 = -(du * u + dv * v) * iw;
+                            const float da0 = h.b1 * gw2 - h.b2 * gw1;
+                            const float da1 = h.b2 * gw0 - h.b0 * gw2;
+                            const float da2 = h.b0 * gw1 - h.b1 * gw0;
+                            const float db0 = gw1 * h.a2 - gw2 * h.a1;
+                            const float db1 = gw2 * h.a0 - gw0 * h.a2;
+                            const float db2 = gw0 * h.a1 - gw1 * h.a0;
+                            gr[0] = da0; gr[1] = da1; gr[2] = da2;
+                            gr[3] = db0; gr[4] = db1; gr[5] = db2;
+                            gr[6] = -xp * da0 - yp * db0;
+                            gr[7] = -xp * da1 - yp * db1;
+                            gr[8] = -xp * da2 - yp * db2;
+                        }
+                        gr[8] += g[3] * wgt;
+                        T = test;
+                    }
+                }
+                if (ballot64(hit) == 0) continue;
+                const float r = wave_reduce16(gr);
+                const int comp = wave_reduce16_component();
+                if (comp >= 0) atomicAdd(&sgrad[j][comp], r);
+                if (lane_id() == 0) stouch[j] = 1u;
+            }
+        }
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < cntb * 16; idx += Gm::NT) {
+            const int j = idx >> 4, k = idx & 15;
+            if (stouch[j]) atomicAdd(&grad[(int64_t)sent[j] * 16 + k], sgrad[j][k]);
+        }
+        __syncthreads();
+    }
+}
+
+template <int NT> __device__ __forceinline__ uint32_t block_max(uint32_t v, uint32_t *scratch) {
+    if (threadIdx.x == 0) *scratch = 0;
+    __syncthreads();
+    atomicMax(scratch, v);
+    __syncthreads();
+    const uint32_t r = *scratch;
+    __syncthreads();
+    return r;
+}
+
+template <int NT> __device__ __forceinline__ float block_sum(float v, float *scratch) {
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) scratch[threadIdx.x >> 6] = v;
+    __syncthreads();
+    float s = 0.f;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < NT / 64; ++k) s += scratch[k];
+    __syncthreads();
+    return s;
+}
+
+// ---------------------------------------------------------------------------
+template <int TW, int TH>
+__global__ __launch_bounds__(TW *TH) void k_render_fwd(const ViewDesc *__restrict__ views, int V,
+                                                        const uint32_t *__restrict__ ts,
+                                                        const uint32_t *__restrict__ te,
+                                                        const uint32_t *__restrict__ pval,
+                                                        const Rec *__restrict__ rec, KParams kp, int64_t NPX,
+                                                        fm_outputs out, float *__restrict__ tfinal,
+                                                        uint32_t *__restrict__ nlast_out) {
+    using Gm = Geo<TW, TH>;
+    __shared__ Rec srec[Gm::NT];
+    const PixelCtx c = pixel_ctx<TW, TH>(views, V, ts, te);
+    float acc[8], T;
+    uint32_t nl;
+    tile_forward<TW, TH>(c, pval, rec, kp, srec, acc, T, nl);
+    if (c.inside) {
+        out.rgb[c.pix] = acc[0] + T * kp.bg[0];
+        out.rgb[NPX + c.pix] = acc[1] + T * kp.bg[1];
+        out.rgb[2 * NPX + c.pix] = acc[2] + T * kp.bg[2];
+        out.depth[c.pix] = acc[3];
+        out.normal[c.pix] = acc[4];
+        out.normal[NPX + c.pix] = acc[5];
+        out.normal[2 * NPX + c.pix] = acc[6];
+        out.alpha[c.pix] = acc[7];
+        tfinal[c.pix] = T;
+        nlast_out[c.pix] = nl;
+    }
+}
+
+template <int TW, int TH>
+__global__ __launch_bounds__(TW *TH) void k_render_bwd(const ViewDesc *__restrict__ views, int V,
+                                                        const uint32_t *__restrict__ ts,
+                                                        const uint32_t *__restrict__ te,
+                                                        const uint32_t *__restrict__ pval,
+                                                        const Rec *__restrict__ rec, KParams kp, int64_t NPX,
+                                                        fm_outputs out, fm_grad_outputs gout,
+                                                        const uint32_t *__restrict__ nlast_in,
+                                                        float *__restrict__ grad) {
+    using Gm = Geo<TW, TH>;
+    __shared__ Rec srec[Gm::NT];
+    __shared__ uint32_t sent[Gm::NT];
+    __shared__ float sgrad[Gm::NT][16];
+    __shared__ uint32_t stouch[Gm::NT];
+    __shared__ uint32_t smax;
+    const PixelCtx c = pixel_ctx<TW, TH>(views, V, ts, te);
+    float g[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    float S = 0.f;
+    uint32_t nl = 0;
+    if (c.inside) {
+        const int64_t q = c.pix;
+        if (gout.rgb) { g[0] = gout.rgb[q]; g[1] = gout.rgb[NPX + q]; g[2] = gout.rgb[2 * NPX + q]; }
+        if (gout.depth) g[3] = gout.depth[q];
+        if (gout.normal) { g[4] = gout.normal[q]; g[5] = gout.normal[NPX + q]; g[6] = gout.normal[2 * NPX + q]; }
+        if (gout.alpha) g[7] = gout.alpha[q];
+        bool any = false;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) any |= g[k] != 0.f;
+        if (any) {
+            nl = nlast_in[q];
+            S = g[0] * out.rgb[q] + g[1] * out.rgb[NPX + q] + g[2] * out.rgb[2 * NPX + q] + g[3] * out.depth[q] +
+                g[4] * out.normal[q] + g[5] * out.normal[NPX + q] + g[6] * out.normal[2 * NPX + q] +
+                g[7] * out.alpha[q];
+        }
+    }
+    const uint32_t maxlast = block_max<Gm::NT>(nl, &smax);
+    if (maxlast == 0) return;
+    tile_backward<TW, TH>(c, pval, rec, kp, srec, sent, sgrad, stouch, g, S, nl, maxlast, grad);
+}
+
+template <int TW, int TH>
+__global__ __launch_bounds__(TW *TH) void k_render_fused(const ViewDesc *__restrict__ views, int V,
+                                                          const uint32_t *__restrict__ ts,
+                                                          const uint32_t *__restrict__ te,
+                                                          const uint32_t *__restrict__ pval,
+                                                          const Rec *__restrict__ rec, KParams kp, int64_t NPX,
+                                                          fm_outputs out, LossArgs la, float *__restrict__ tfinal,
+                                                          uint32_t *__restrict__ nlast_out, float *__restrict__ grad,
+                                                          float *__restrict__ loss_part) {
+    using Gm = Geo<TW, TH>;
+    __shared__ Rec srec[Gm::NT];
+    __shared__ uint32_t sent[Gm::NT];
+    __shared__ float sgrad[Gm::NT][16];
+    __shared__ uint32_t stouch[Gm::NT];
+    __shared__ uint32_t smax;
+    __shared__ float sred[Gm::NW];
+    const PixelCtx c = pixel_ctx<TW, TH>(views, V, ts, te);
+    float acc[8], T;
+    uint32_t nl;
+    tile_forward<TW, TH>(c, pval, rec, kp, srec, acc, T, nl);
+    float g[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    float S = 0.f, l = 0.f;
+    if (c.inside) {
+        const int64_t q = c.pix;
+        const float o0 = acc[0] + T * kp.bg[0], o1 = acc[1] + T * kp.bg[1], o2 = acc[2] + T * kp.bg[2];
+        out.rgb[q] = o0;
+        out.rgb[NPX + q] = o1;
+        out.rgb[2 * NPX + q] = o2;
+        out.depth[q] = acc[3];
+        out.normal[q] = acc[4];
+        out.normal[NPX + q] = acc[5];
+        out.normal[2 * NPX + q] = acc[6];
+        out.alpha[q] = acc[7];
+        tfinal[q] = T;
+        nlast_out[q] = nl;
+        const bool m = la.mask ? (la.mask[q] != 0) : true;
+        if (m) {
+            const float npx = (float)c.W * (float)c.H;
+            const float k_rgb = la.w_rgb / (3.f * npx);
+            const float o[3] = {o0, o1, o2};
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) {
+                const float d = o[ch] - la.target_rgb[ch * NPX + q];
+                l += k_rgb * fabsf(d);
+                g[ch] = d > 0.f ? k_rgb : (d < 0.f ? -k_rgb : 0.f);
+            }
+            if (la.w_depth != 0.f && la.target_depth) {
+                const float k_d = la.w_depth / npx;
+                const float d = acc[3] - la.target_depth[q];
+                l += k_d * fabsf(d);
+                g[3] = d > 0.f ? k_d : (d < 0.f ? -k_d : 0.f);
+            }
+            S = g[0] * o0 + g[1] * o1 + g[2] * o2 + g[3] * acc[3];
+        } else {
+            nl = 0;
+        }
+    } else {
+        nl = 0;
+    }
+    const float lsum = block_sum<Gm::NT>(l, sred);
+    if (threadIdx.x == 0) loss_part[blockIdx.x] = lsum;
+    const uint32_t maxlast = block_max<Gm::NT>(nl, &smax);
+    if (maxlast == 0) return;
+    tile_backward<TW, TH>(c, pval, rec, kp, srec, sent, sgrad, stouch, g, S, nl, maxlast, grad);
+}
+
+__global__ __launch_bounds__(1024) void k_loss_reduce(const float *__restrict__ part, int64_t n,
+                                                       float *__restrict__ loss) {
+    __shared__ float red[16];
+    float s = 0.f;
+    for (int64_t i = threadIdx.x; i < n; i += 1024) s += part[i];
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float t = 0.f;
+        for (int k = 0; k < 16; ++k) t += red[k];
+        *loss += t;
+    }
+}
+
+template <int TW, int TH>
+hipError_t fwd_t(const Plan &p, void *ws, const KParams &kp, const fm_outputs &out, hipStream_t st) {
+    const uint32_t *pval = at<uint32_t>(ws, p.pairs_in_alt ? p.o_pval2 : p.o_pval);
+    hipLaunchKernelGGL((k_render_fwd<TW, TH>), dim3((unsigned)p.T), dim3(TW * TH), 0, st,
+                       at<ViewDesc>(ws, p.o_views), p.V, at<uint32_t>(ws, p.o_tstart),
+                       at<uint32_t>(ws, p.o_tend), pval, at<Rec>(ws, p.o_rec), kp, p.NPX, out,
+                       at<float>(ws, p.o_tfinal), at<uint32_t>(ws, p.o_nlast));
+    return hipGetLastError();
+}
+
+template <int TW, int TH>
+hipError_t bwd_t(const Plan &p, void *ws, const KParams &kp, const fm_outputs &out, const fm_grad_outputs &g,
+                 hipStream_t st) {
+    const uint32_t *pval = at<uint32_t>(ws, p.pairs_in_alt ? p.o_pval2 : p.o_pval);
+    hipLaunchKernelGGL((k_render_bwd<TW, TH>), dim3((unsigned)p.T), dim3(TW * TH), 0, st,
+                       at<ViewDesc>(ws, p.o_views), p.V, at<uint32_t>(ws, p.o_tstart),
+                       at<uint32_t>(ws, p.o_tend), pval, at<Rec>(ws, p.o_rec), kp, p.NPX, out, g,
+                       at<uint32_t>(ws, p.o_nlast), at<float>(ws, p.o_grad));
+    return hipGetLastError();
+}
+
+template <int TW, int TH>
+hipError_t fused_t(const Plan &p, void *ws, const KParams &kp, const LossArgs &la, const fm_outputs &out,
+                   float *loss, hipStream_t st) {
+    const uint32_t *pval = at<uint32_t>(ws, p.pairs_in_alt ? p.o_pval2 : p.o_pval);
+    hipLaunchKernelGGL((k_render_fused<TW, TH>), dim3((unsigned)p.T), dim3(TW * TH), 0, st,
+                       at<ViewDesc>(ws, p.o_views), p.V, at<uint32_t>(ws, p.o_tstart),
+                       at<uint32_t>(ws, p.o_tend), pval, at<Rec>(ws, p.o_rec), kp, p.NPX, out, la,
+                       at<float>(ws, p.o_tfinal), at<uint32_t>(ws, p.o_nlast), at<float>(ws, p.o_grad),
+                       at<float>(ws, p.o_loss));
+    if (loss) hipLaunchKernelGGL(k_loss_reduce, dim3(1), dim3(1024), 0, st, at<float>(ws, p.o_loss), p.T, loss);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+bool tile_shape_supported(int tw, int th) {
+    return (tw == 8 && th == 8) || (tw == 16 && th == 8) || (tw == 16 && th == 16) ||
+           (tw == 32 && th == 8);
+}
+
+#define FM_DISPATCH(FN, ...)                                                     \
+    do {                                                                         \
+        if (p.tile_w == 16 && p.tile_h == 16) return FN<16, 16>(__VA_ARGS__);    \
+        if (p.tile_w == 8 && p.tile_h == 8) return FN<8, 8>(__VA_ARGS__);        \
+        if (p.tile_w == 16 && p.tile_h == 8) return FN<16, 8>(__VA_ARGS__);      \
+        if (p.tile_w == 32 && p.tile_h == 8) return FN<32, 8>(__VA_ARGS__);      \
+        return hipErrorInvalidValue;                                             \
+    } while (0)
+
+hipError_t launch_render_fwd(const Plan &p, void *ws, const KParams &kp, const fm_outputs &out,
+                             hipStream_t st) {
+    if (p.T == 0) return hipSuccess;
+    FM_DISPATCH(fwd_t, p, ws, kp, out, st);
+}
+
+hipError_t launch_render_bwd(const Plan &p, void *ws, const KParams &kp, const fm_outputs &out,
+                             const fm_grad_outputs &g, hipStream_t st) {
+    if (p.T == 0) return hipSuccess;
+    FM_DISPATCH(bwd_t, p, ws, kp, out, g, st);
+}
+
+hipError_t launch_render_fused(const Plan &p, void *ws, const KParams &kp, const LossArgs &la,
+                               const fm_outputs &out, float *loss, hipStream_t st) {
+    if (p.T == 0) return hipSuccess;
+    FM_DISPATCH(fused_t, p, ws, kp, la, out, loss, st);
+}
+
+}  // namespace fm

@@ -1,0 +1,147 @@
+// fm_internal.h -- shared device-side layout of the gfx950 surfel rasterizer.
+//
+// Workspace organisation (one caller-owned device buffer, carved on the host
+// by make_plan):
+//   entries   one slot per (view, surfel of the view's submap); each view's
+//             segment is padded to 256 so a 256-thread block never straddles
+//             two views.  Per entry: an 80-byte projected record (Rec), a
+//             32-bit depth key, a tile count, and a 64-byte gradient slot.
+//   pairs     (global tile id, entry id), capacity max_pairs, double-buffered
+//             for the radix sort.
+//   tiles     per global tile [start, end) into the sorted pair list.
+//   pixels    per pixel: final transmittance and the length of the prefix of
+//             the tile list that the pixel composited.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "fm2dgs.h"
+
+namespace fm {
+
+constexpr int kEntryAlign = 256;   // entry segment padding per view
+constexpr int kRadixBits = 8;
+constexpr int kRadix = 1 << kRadixBits;
+constexpr int kSortBlock = 256;    // threads per radix-sort block
+constexpr int kScanChunk = 2048;   // entries per block of the count scan
+constexpr int kMaxSortGrid = 2048;
+
+// Per-view descriptor, written into the workspace at the start of each call.
+struct ViewDesc {
+    const float *mean, *quat, *scale, *opacity, *color;  // the view's submap
+    int32_t n;           // surfels in that submap
+    int32_t submap;
+    int32_t entry_base;  // first entry of the view (multiple of 256)
+    int32_t width, height;
+    int32_t tiles_x, tiles_y;
+    int32_t tile_base;   // first global tile id
+    int64_t pixel_offset;
+    int32_t pad[2];
+};
+
+// Per-submap descriptor for the surfel-major backward projection.
+struct SubmapDesc {
+    const float *mean, *quat, *scale, *opacity, *color;
+    float *g_mean, *g_quat, *g_scale, *g_opacity, *g_color;
+    int32_t n;
+    int32_t view_begin, view_count;  // slice of the submap-ordered view list
+    int32_t block_base;              // first block of the backward projection
+};
+
+// Projected surfel as the blend kernels consume it (80 bytes).
+// h: homography rows in a pixel frame shifted by the integers (xc, yc):
+//    h[0..2] = row0 - xc*row2, h[3..5] = row1 - yc*row2, h[6..8] = row2,
+//    where H = K [s_u t_u | s_v t_v | p] (columns), so h[8] = centre depth.
+struct alignas(16) Rec {
+    float h[9];
+    float sigma;
+    float col[3];
+    float nrm[3];   // camera-space unit normal facing the camera
+    float xc, yc;   // pixel-frame shift (integers, exact in float)
+    int16_t bb[4];  // inclusive pixel-centre bbox: x0, y0, x1, y1
+};
+static_assert(sizeof(Rec) == 80, "record layout");
+
+struct Status {
+    uint32_t n_pairs;    // pairs actually stored (min(required, capacity))
+    uint32_t overflow;   // 1 when required > capacity
+    uint64_t required;   // pairs the batch needs
+    uint32_t pad[4];
+};
+
+struct KParams {
+    float alpha_min, alpha_max, t_min, rho_max, near_plane;
+    float bg[3];
+    int32_t tile_w, tile_h;
+};
+
+struct LossArgs {
+    const float *target_rgb, *target_depth;
+    const uint8_t *mask;
+    float w_rgb, w_depth;
+};
+
+struct Plan {
+    int V = 0, S = 0;
+    int64_t E = 0;      // entries (padded)
+    int64_t T = 0;      // total tiles
+    int64_t NPX = 0;    // total pixels
+    int64_t cap = 0;    // pair capacity
+    int max_view_entries = 0;
+    int tile_w = 16, tile_h = 16;
+    int tile_bits = 1;
+    int pair_passes = 1;
+    int sortG_e = 1, sortG_p = 1;
+    int scan_blocks = 1;
+    int a7_blocks = 0;      // total blocks of the backward projection
+    int a7_max_blocks = 0;  // max blocks of one submap
+    size_t o_views = 0, o_subs = 0, o_vlist = 0, o_status = 0, o_rec = 0, o_key = 0, o_cnt = 0,
+           o_key2 = 0, o_val = 0, o_val2 = 0, o_scan = 0, o_pkey = 0, o_pval = 0, o_pkey2 = 0,
+           o_pval2 = 0, o_hist = 0, o_tstart = 0, o_tend = 0, o_tfinal = 0, o_nlast = 0, o_grad = 0,
+           o_pose = 0, o_loss = 0, o_tilemax = 0;
+    size_t bytes = 0;
+    bool pairs_in_alt = false;  // final sorted pairs live in the *2 buffers
+};
+
+template <class T> __host__ __device__ inline T *at(void *ws, size_t off) {
+    return reinterpret_cast<T *>(static_cast<char *>(ws) + off);
+}
+
+// Index of the last view whose `entry_base` (or `tile_base`) is <= x.
+__device__ inline int view_of_entry(const ViewDesc *v, int V, int64_t x) {
+    int lo = 0, hi = V - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if ((int64_t)v[mid].entry_base <= x) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+__device__ inline int view_of_tile(const ViewDesc *v, int V, int64_t x) {
+    int lo = 0, hi = V - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if ((int64_t)v[mid].tile_base <= x) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// ---- launchers (host) ------------------------------------------------------
+hipError_t launch_setup(const Plan &p, void *ws, const ViewDesc *views, const SubmapDesc *subs,
+                        const int32_t *vlist, hipStream_t st);
+hipError_t launch_preprocess(const Plan &p, void *ws, const KParams &kp, const float *intr,
+                             const float *viewmat, hipStream_t st);
+hipError_t launch_binning(const Plan &p, void *ws, const KParams &kp, hipStream_t st);
+hipError_t launch_render_fwd(const Plan &p, void *ws, const KParams &kp, const fm_outputs &out,
+                             hipStream_t st);
+hipError_t launch_render_bwd(const Plan &p, void *ws, const KParams &kp, const fm_outputs &out,
+                             const fm_grad_outputs &g, hipStream_t st);
+hipError_t launch_render_fused(const Plan &p, void *ws, const KParams &kp, const LossArgs &la,
+                               const fm_outputs &out, float *loss, hipStream_t st);
+hipError_t launch_zero_grad(const Plan &p, void *ws, hipStream_t st);
+hipError_t launch_preprocess_bwd(const Plan &p, void *ws, const float *intr, const float *viewmat,
+                                 float *dL_dviewmat, hipStream_t st);
+bool tile_shape_supported(int tw, int th);
+
+}  // namespace fm

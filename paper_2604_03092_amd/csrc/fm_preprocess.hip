@@ -1,0 +1,459 @@
+// fm_preprocess.hip -- per-(view, surfel) projection (forward) and the
+// projection chain rule (backward) of the 2DGS rasterizer on gfx950.
+//
+// Forward: each thread projects one surfel into one view.  The cull
+// decisions, the depth key and the pixel bbox are evaluated in FP64 with a
+// fixed operation order and no contraction, so that they are bit-identical to
+// any other FP64 evaluation of the same formulas in the same order; the
+// record the blend kernels read is rounded to FP32.  This is the projection
+// of the surfel planar disk (Sec. 3) through the pinhole camera: the local
+// plane coordinates (u, v) map to the image by H = K [s_u t_u | s_v t_v | p].
+//
+// Backward: one thread per surfel walks the views of its submap and chains
+// dL/dH, dL/dsigma, dL/dc, dL/dn back to mean, quaternion, scales, opacity,
+// colour and the view matrix.  No atomics: each surfel is owned by one
+// thread; pose partials are reduced per block and summed by a second kernel.
+#include "fm_internal.h"
+#include "fm_wave.h"
+
+namespace fm {
+
+namespace {
+
+constexpr int kViewChunk = 32;
+constexpr int kSubChunk = 32;
+constexpr int kListChunk = 512;
+
+struct ViewChunk {
+    ViewDesc d[kViewChunk];
+    int count, first;
+};
+struct SubChunk {
+    SubmapDesc d[kSubChunk];
+    int count, first;
+};
+struct ListChunk {
+    int32_t d[kListChunk];
+    int count, first;
+};
+
+__global__ void k_write_views(ViewChunk c, ViewDesc *out) {
+    int i = threadIdx.x;
+    if (i < c.count) out[c.first + i] = c.d[i];
+}
+__global__ void k_write_subs(SubChunk c, SubmapDesc *out) {
+    int i = threadIdx.x;
+    if (i < c.count) out[c.first + i] = c.d[i];
+}
+__global__ void k_write_list(ListChunk c, int32_t *out) {
+    for (int i = threadIdx.x; i < c.count; i += blockDim.x) out[c.first + i] = c.d[i];
+}
+
+// ---------------------------------------------------------------------------
+// forward projection
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_preprocess(const ViewDesc *__restrict__ views, int V,
+                                                     const float *__restrict__ intr,
+                                                     const float *__restrict__ viewmat, KParams kp,
+                                                     Rec *__restrict__ rec, uint32_t *__restrict__ key,
+                                                     uint32_t *__restrict__ cnt) {
+#pragma clang fp contract(off)
+    const int64_t e0 = (int64_t)blockIdx.x * 256;
+    const int v = view_of_entry(views, V, e0);
+    const ViewDesc &vd = views[v];
+    const int64_t e = e0 + threadIdx.x;
+    const int i = (int)(e - vd.entry_base);
+    const int n = vd.n;
+    uint32_t out_key = 0xFFFFFFFFu, out_cnt = 0;
+    if (i < n) {
+        const float f_mx = vd.mean[i], f_my = vd.mean[n + i], f_mz = vd.mean[2 * n + i];
+        const float f_qw = vd.quat[i], f_qx = vd.quat[n + i], f_qy = vd.quat[2 * n + i],
+                    f_qz = vd.quat[3 * n + i];
+        const float f_su = vd.scale[i], f_sv = vd.scale[n + i];
+        const float f_sig = vd.opacity[i];
+        const float f_c0 = vd.color[i], f_c1 = vd.color[n + i], f_c2 = vd.color[2 * n + i];
+        bool ok = isfinite(f_mx) && isfinite(f_my) && isfinite(f_mz) && isfinite(f_qw) &&
+                  isfinite(f_qx) && isfinite(f_qy) && isfinite(f_qz) && isfinite(f_su) &&
+                  isfinite(f_sv) && isfinite(f_sig) && isfinite(f_c0) && isfinite(f_c1) &&
+                  isfinite(f_c2);
+        const double mx = f_mx, my = f_my, mz = f_mz;
+        const double qw = f_qw, qx = f_qx, qy = f_qy, qz = f_qz;
+        const double su = f_su, sv = f_sv, sigma = f_sig;
+        ok = ok && (su > 0.0) && (sv > 0.0);
+        const double qn = qw * qw + qx * qx + qy * qy + qz * qz;
+        ok = ok && (qn > 0.0);
+        if (ok) {
+            const double qnorm = sqrt(qn);
+            const double w = qw / qnorm, x = qx / qnorm, y = qy / qnorm, z = qz / qnorm;
+            double Rs[9];
+            Rs[0] = 1.0 - 2.0 * (y * y + z * z);
+            Rs[1] = 2.0 * (x * y - w * z);
+            Rs[2] = 2.0 * (x * z + w * y);
+            Rs[3] = 2.0 * (x * y + w * z);
+            Rs[4] = 1.0 - 2.0 * (x * x + z * z);
+            Rs[5] = 2.0 * (y * z - w * x);
+            Rs[6] = 2.0 * (x * z - w * y);
+            Rs[7] = 2.0 * (y * z + w * x);
+            Rs[8] = 1.0 - 2.0 * (x * x + y * y);
+            const float *vm = viewmat + 12 * v;
+            const double R[9] = {vm[0], vm[1], vm[2], vm[4], vm[5], vm[6], vm[8], vm[9], vm[10]};
+            const double t[3] = {vm[3], vm[7], vm[11]};
+            double p[3], tu[3], tv[3], n0[3];
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                p[r] = R[3 * r] * mx + R[3 * r + 1] * my + R[3 * r + 2] * mz + t[r];
+                tu[r] = R[3 * r] * Rs[0] + R[3 * r + 1] * Rs[3] + R[3 * r + 2] * Rs[6];
+                tv[r] = R[3 * r] * Rs[1] + R[3 * r + 1] * Rs[4] + R[3 * r + 2] * Rs[7];
+                n0[r] = R[3 * r] * Rs[2] + R[3 * r + 1] * Rs[5] + R[3 * r + 2] * Rs[8];
+            }
+            const double depth = p[2];
+            ok = (depth > (double)kp.near_plane) && (sigma > (double)kp.alpha_min);
+            if (ok) {
+                const float *K = intr + 4 * v;
+                const double fx = K[0], fy = K[1], cx = K[2], cy = K[3];
+                double M[9];
+#pragma unroll
+                for (int r = 0; r < 3; ++r) {
+                    M[3 * r + 0] = su * tu[r];
+                    M[3 * r + 1] = sv * tv[r];
+                    M[3 * r + 2] = p[r];
+                }
+                double H[9];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    H[c] = fx * M[c] + cx * M[6 + c];
+                    H[3 + c] = fy * M[3 + c] + cy * M[6 + c];
+                    H[6 + c] = M[6 + c];
+                }
+                const double rho2 = (double)kp.rho_max * (double)kp.rho_max;
+                const double C00 = rho2 * (H[0] * H[0] + H[1] * H[1]) - H[2] * H[2];
+                const double C02 = rho2 * (H[0] * H[6] + H[1] * H[7]) - H[2] * H[8];
+                const double C11 = rho2 * (H[3] * H[3] + H[4] * H[4]) - H[5] * H[5];
+                const double C12 = rho2 * (H[3] * H[6] + H[4] * H[7]) - H[5] * H[8];
+                const double C22 = rho2 * (H[6] * H[6] + H[7] * H[7]) - H[8] * H[8];
+                const double dx = C02 * C02 - C00 * C22;
+                const double dy = C12 * C12 - C11 * C22;
+                ok = (C22 < 0.0) && (dx >= 0.0) && (dy >= 0.0);
+                if (ok) {
+                    const double sx = sqrt(dx), sy = sqrt(dy);
+                    const double xa = (C02 - sx) / C22, xb = (C02 + sx) / C22;
+                    const double ya = (C12 - sy) / C22, yb = (C12 + sy) / C22;
+                    const double xlo = xa < xb ? xa : xb, xhi = xa < xb ? xb : xa;
+                    const double ylo = ya < yb ? ya : yb, yhi = ya < yb ? yb : ya;
+                    double c0 = ceil(xlo - 0.5), c1 = floor(xhi - 0.5);
+                    double r0 = ceil(ylo - 0.5), r1 = floor(yhi - 0.5);
+                    if (c0 < 0.0) c0 = 0.0;
+                    if (r0 < 0.0) r0 = 0.0;
+                    if (c1 > (double)(vd.width - 1)) c1 = (double)(vd.width - 1);
+                    if (r1 > (double)(vd.height - 1)) r1 = (double)(vd.height - 1);
+                    if (c0 <= c1 && r0 <= r1) {
+                        const int px0 = (int)c0, px1 = (int)c1, py0 = (int)r0, py1 = (int)r1;
+                        const double dotnp = n0[0] * p[0] + n0[1] * p[1] + n0[2] * p[2];
+                        const double sgn = dotnp < 0.0 ? 1.0 : -1.0;
+                        const int ixc = (px0 + px1) >> 1, iyc = (py0 + py1) >> 1;
+                        const double xc = (double)ixc, yc = (double)iyc;
+                        Rec r;
+                        r.h[0] = (float)(H[0] - xc * H[6]);
+                        r.h[1] = (float)(H[1] - xc * H[7]);
+                        r.h[2] = (float)(H[2] - xc * H[8]);
+                        r.h[3] = (float)(H[3] - yc * H[6]);
+                        r.h[4] = (float)(H[4] - yc * H[7]);
+                        r.h[5] = (float)(H[5] - yc * H[8]);
+                        r.h[6] = (float)H[6];
+                        r.h[7] = (float)H[7];
+                        r.h[8] = (float)H[8];
+                        r.sigma = f_sig;
+                        r.col[0] = f_c0; r.col[1] = f_c1; r.col[2] = f_c2;
+                        r.nrm[0] = (float)(sgn * n0[0]);
+                        r.nrm[1] = (float)(sgn * n0[1]);
+                        r.nrm[2] = (float)(sgn * n0[2]);
+                        r.xc = (float)ixc;
+                        r.yc = (float)iyc;
+                        r.bb[0] = (int16_t)px0; r.bb[1] = (int16_t)py0;
+                        r.bb[2] = (int16_t)px1; r.bb[3] = (int16_t)py1;
+                        rec[e] = r;
+                        const int tx0 = px0 / kp.tile_w, tx1 = px1 / kp.tile_w;
+                        const int ty0 = py0 / kp.tile_h, ty1 = py1 / kp.tile_h;
+                        out_cnt = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+                        out_key = __float_as_uint((float)depth);
+                    }
+                }
+            }
+        }
+    }
+    key[e] = out_key;
+    cnt[e] = out_cnt;
+}
+
+// Zero the 16-float gradient slot of every entry that has pairs.
+__global__ __launch_bounds__(256) void k_zero_grad(const uint32_t *__restrict__ cnt, float4 *__restrict__ grad,
+                                                    int64_t E) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e < E && cnt[e] != 0) {
+        const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+        grad[4 * e] = z;
+        grad[4 * e + 1] = z;
+        grad[4 * e + 2] = z;
+        grad[4 * e + 3] = z;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// backward projection (one thread per surfel, looping over its views)
+// ---------------------------------------------------------------------------
+__device__ inline int submap_of_block(const SubmapDesc *s, int S, int b) {
+    int lo = 0, hi = S - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (s[mid].block_base <= b) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(256) void k_preprocess_bwd(
+    const SubmapDesc *__restrict__ subs, int S, const int32_t *__restrict__ vlist,
+    const ViewDesc *__restrict__ views, const float *__restrict__ intr,
+    const float *__restrict__ viewmat, const Rec *__restrict__ rec, const uint32_t *__restrict__ cnt,
+    const float4 *__restrict__ grad, float *__restrict__ pose_part, int max_blocks) {
+    __shared__ float red[4][16];
+    const int s_idx = submap_of_block(subs, S, blockIdx.x);
+    const SubmapDesc &sd = subs[s_idx];
+    const int lb = blockIdx.x - sd.block_base;
+    const int i = lb * 256 + threadIdx.x;
+    const int n = sd.n;
+    const bool live = i < n;
+    const int wave = threadIdx.x >> 6;
+
+    float mu[3] = {0.f, 0.f, 0.f}, qh[4] = {1.f, 0.f, 0.f, 0.f}, qnorm = 1.f, su = 0.f, sv = 0.f;
+    float Rs[9] = {1.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.f, 0.f, 1.f};
+    if (live) {
+        mu[0] = sd.mean[i]; mu[1] = sd.mean[n + i]; mu[2] = sd.mean[2 * n + i];
+        const float q0 = sd.quat[i], q1 = sd.quat[n + i], q2 = sd.quat[2 * n + i], q3 = sd.quat[3 * n + i];
+        su = sd.scale[i]; sv = sd.scale[n + i];
+        const float qn = q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3;
+        if (qn > 0.f && isfinite(qn)) {
+            qnorm = sqrtf(qn);
+            const float inv = 1.f / qnorm;
+            qh[0] = q0 * inv; qh[1] = q1 * inv; qh[2] = q2 * inv; qh[3] = q3 * inv;
+        }
+        const float w = qh[0], x = qh[1], y = qh[2], z = qh[3];
+        Rs[0] = 1.f - 2.f * (y * y + z * z);
+        Rs[1] = 2.f * (x * y - w * z);
+        Rs[2] = 2.f * (x * z + w * y);
+        Rs[3] = 2.f * (x * y + w * z);
+        Rs[4] = 1.f - 2.f * (x * x + z * z);
+        Rs[5] = 2.f * (y * z - w * x);
+        Rs[6] = 2.f * (x * z - w * y);
+        Rs[7] = 2.f * (y * z + w * x);
+        Rs[8] = 1.f - 2.f * (x * x + y * y);
+    }
+    float dmu[3] = {0.f, 0.f, 0.f}, dRs[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    float dsu = 0.f, dsv = 0.f, dsig = 0.f, dc[3] = {0.f, 0.f, 0.f};
+
+    for (int k = 0; k < sd.view_count; ++k) {
+        const int v = vlist[sd.view_begin + k];
+        const ViewDesc &vd = views[v];
+        const int64_t e = (int64_t)vd.entry_base + i;
+        float dV[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) dV[j] = 0.f;
+        if (live && cnt[e] != 0) {
+            const float4 g0 = grad[4 * e], g1 = grad[4 * e + 1], g2 = grad[4 * e + 2], g3 = grad[4 * e + 3];
+            const float g[16] = {g0.x, g0.y, g0.z, g0.w, g1.x, g1.y, g1.z, g1.w,
+                                 g2.x, g2.y, g2.z, g2.w, g3.x, g3.y, g3.z, g3.w};
+            const Rec &rc = rec[e];
+            const float xc = rc.xc, yc = rc.yc;
+            const float nr0 = rc.nrm[0], nr1 = rc.nrm[1], nr2 = rc.nrm[2];
+            const float *vm = viewmat + 12 * v;
+            const float R[9] = {vm[0], vm[1], vm[2], vm[4], vm[5], vm[6], vm[8], vm[9], vm[10]};
+            const float *K = intr + 4 * v;
+            const float fx = K[0], fy = K[1], cx = K[2], cy = K[3];
+            // undo the pixel-frame shift: row2 absorbs -xc*drow0' - yc*drow1'
+            float dH[9];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                dH[c] = g[c];
+                dH[3 + c] = g[3 + c];
+                dH[6 + c] = g[6 + c] - xc * g[c] - yc * g[3 + c];
+            }
+            // H = K M  ->  dM = K^T dH
+            float dM[9];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                dM[c] = fx * dH[c];
+                dM[3 + c] = fy * dH[3 + c];
+                dM[6 + c] = cx * dH[c] + cy * dH[3 + c] + dH[6 + c];
+            }
+            float tu[3], tv[3], n0[3];
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                tu[r] = R[3 * r] * Rs[0] + R[3 * r + 1] * Rs[3] + R[3 * r + 2] * Rs[6];
+                tv[r] = R[3 * r] * Rs[1] + R[3 * r + 1] * Rs[4] + R[3 * r + 2] * Rs[7];
+                n0[r] = R[3 * r] * Rs[2] + R[3 * r + 1] * Rs[5] + R[3 * r + 2] * Rs[8];
+            }
+            const float sgn = (n0[0] * nr0 + n0[1] * nr1 + n0[2] * nr2) >= 0.f ? 1.f : -1.f;
+            const float dp[3] = {dM[2], dM[5], dM[8]};
+            const float dtu[3] = {su * dM[0], su * dM[3], su * dM[6]};
+            const float dtv[3] = {sv * dM[1], sv * dM[4], sv * dM[7]};
+            dsu += tu[0] * dM[0] + tu[1] * dM[3] + tu[2] * dM[6];
+            dsv += tv[0] * dM[1] + tv[1] * dM[4] + tv[2] * dM[7];
+            const float dn0[3] = {sgn * g[13], sgn * g[14], sgn * g[15]};
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                dmu[c] += R[c] * dp[0] + R[3 + c] * dp[1] + R[6 + c] * dp[2];
+                dRs[3 * c + 0] += R[c] * dtu[0] + R[3 + c] * dtu[1] + R[6 + c] * dtu[2];
+                dRs[3 * c + 1] += R[c] * dtv[0] + R[3 + c] * dtv[1] + R[6 + c] * dtv[2];
+                dRs[3 * c + 2] += R[c] * dn0[0] + R[3 + c] * dn0[1] + R[6 + c] * dn0[2];
+            }
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    dV[4 * r + c] = dp[r] * mu[c] + dtu[r] * Rs[3 * c] + dtv[r] * Rs[3 * c + 1] +
+                                    dn0[r] * Rs[3 * c + 2];
+                dV[4 * r + 3] = dp[r];
+            }
+            dsig += g[9];
+            dc[0] += g[10]; dc[1] += g[11]; dc[2] += g[12];
+        }
+        // block reduction of the 12 pose-gradient values of view v
+        const float r = wave_reduce16(dV);
+        const int comp = wave_reduce16_component();
+        if (comp >= 0) red[wave][comp] = r;
+        __syncthreads();
+        if (threadIdx.x < 12) {
+            const float s = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] +
+                            red[3][threadIdx.x];
+            pose_part[((int64_t)v * max_blocks + lb) * 12 + threadIdx.x] = s;
+        }
+        __syncthreads();
+    }
+    if (!live) return;
+    // dL/d(unit quaternion) from dL/dR_s, then project onto the raw quaternion
+    const float w = qh[0], x = qh[1], y = qh[2], z = qh[3];
+    const float *G = dRs;
+    float dq[4];
+    dq[0] = 2.f * (-z * G[1] + y * G[2] + z * G[3] - x * G[5] - y * G[6] + x * G[7]);
+    dq[1] = 2.f * (y * G[1] + z * G[2] + y * G[3] - 2.f * x * G[4] - w * G[5] + z * G[6] + w * G[7] -
+                   2.f * x * G[8]);
+    dq[2] = 2.f * (-2.f * y * G[0] + x * G[1] + w * G[2] + x * G[3] + z * G[5] - w * G[6] + z * G[7] -
+                   2.f * y * G[8]);
+    dq[3] = 2.f * (-2.f * z * G[0] - w * G[1] + x * G[2] + w * G[3] - 2.f * z * G[4] + y * G[5] +
+                   x * G[6] + y * G[7]);
+    const float dot = dq[0] * w + dq[1] * x + dq[2] * y + dq[3] * z;
+    const float inv = 1.f / qnorm;
+    if (sd.g_mean) {
+        sd.g_mean[i] += dmu[0];
+        sd.g_mean[n + i] += dmu[1];
+        sd.g_mean[2 * n + i] += dmu[2];
+    }
+    if (sd.g_quat) {
+        sd.g_quat[i] += (dq[0] - w * dot) * inv;
+        sd.g_quat[n + i] += (dq[1] - x * dot) * inv;
+        sd.g_quat[2 * n + i] += (dq[2] - y * dot) * inv;
+        sd.g_quat[3 * n + i] += (dq[3] - z * dot) * inv;
+    }
+    if (sd.g_scale) {
+        sd.g_scale[i] += dsu;
+        sd.g_scale[n + i] += dsv;
+    }
+    if (sd.g_opacity) sd.g_opacity[i] += dsig;
+    if (sd.g_color) {
+        sd.g_color[i] += dc[0];
+        sd.g_color[n + i] += dc[1];
+        sd.g_color[2 * n + i] += dc[2];
+    }
+}
+
+// dL_dviewmat[v] += sum over the blocks of v's submap of the pose partials.
+__global__ __launch_bounds__(256) void k_pose_reduce(const ViewDesc *__restrict__ views,
+                                                      const SubmapDesc *__restrict__ subs,
+                                                      const float *__restrict__ pose_part, int max_blocks,
+                                                      float *__restrict__ dL_dviewmat) {
+    __shared__ float red[256][13];
+    const int v = blockIdx.x;
+    const SubmapDesc &sd = subs[views[v].submap];
+    const int nb = (sd.n + 255) / 256;
+    float acc[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[k] = 0.f;
+    for (int b = threadIdx.x; b < nb; b += 256) {
+        const float *p = pose_part + ((int64_t)v * max_blocks + b) * 12;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) acc[k] += p[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 12; ++k) red[threadIdx.x][k] = acc[k];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s)
+            for (int k = 0; k < 12; ++k) red[threadIdx.x][k] += red[threadIdx.x + s][k];
+        __syncthreads();
+    }
+    if (threadIdx.x < 12) dL_dviewmat[12 * v + threadIdx.x] += red[0][threadIdx.x];
+}
+
+}  // namespace
+
+hipError_t launch_setup(const Plan &p, void *ws, const ViewDesc *views, const SubmapDesc *subs,
+                        const int32_t *vlist, hipStream_t st) {
+    for (int f = 0; f < p.V; f += kViewChunk) {
+        ViewChunk c;
+        c.first = f;
+        c.count = p.V - f < kViewChunk ? p.V - f : kViewChunk;
+        for (int i = 0; i < c.count; ++i) c.d[i] = views[f + i];
+        hipLaunchKernelGGL(k_write_views, dim3(1), dim3(kViewChunk), 0, st, c, at<ViewDesc>(ws, p.o_views));
+    }
+    for (int f = 0; f < p.S; f += kSubChunk) {
+        SubChunk c;
+        c.first = f;
+        c.count = p.S - f < kSubChunk ? p.S - f : kSubChunk;
+        for (int i = 0; i < c.count; ++i) c.d[i] = subs[f + i];
+        hipLaunchKernelGGL(k_write_subs, dim3(1), dim3(kSubChunk), 0, st, c, at<SubmapDesc>(ws, p.o_subs));
+    }
+    for (int f = 0; f < p.V; f += kListChunk) {
+        ListChunk c;
+        c.first = f;
+        c.count = p.V - f < kListChunk ? p.V - f : kListChunk;
+        for (int i = 0; i < c.count; ++i) c.d[i] = vlist[f + i];
+        hipLaunchKernelGGL(k_write_list, dim3(1), dim3(256), 0, st, c, at<int32_t>(ws, p.o_vlist));
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_preprocess(const Plan &p, void *ws, const KParams &kp, const float *intr,
+                             const float *viewmat, hipStream_t st) {
+    const int blocks = (int)(p.E / 256);
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_preprocess, dim3(blocks), dim3(256), 0, st, at<ViewDesc>(ws, p.o_views), p.V,
+                       intr, viewmat, kp, at<Rec>(ws, p.o_rec), at<uint32_t>(ws, p.o_key),
+                       at<uint32_t>(ws, p.o_cnt));
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_grad(const Plan &p, void *ws, hipStream_t st) {
+    const int blocks = (int)((p.E + 255) / 256);
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_grad, dim3(blocks), dim3(256), 0, st, at<uint32_t>(ws, p.o_cnt),
+                       at<float4>(ws, p.o_grad), p.E);
+    return hipGetLastError();
+}
+
+hipError_t launch_preprocess_bwd(const Plan &p, void *ws, const float *intr, const float *viewmat,
+                                 float *dL_dviewmat, hipStream_t st) {
+    if (p.a7_blocks > 0) {
+        hipLaunchKernelGGL(k_preprocess_bwd, dim3(p.a7_blocks), dim3(256), 0, st,
+                           at<SubmapDesc>(ws, p.o_subs), p.S, at<int32_t>(ws, p.o_vlist),
+                           at<ViewDesc>(ws, p.o_views), intr, viewmat, at<Rec>(ws, p.o_rec),
+                           at<uint32_t>(ws, p.o_cnt), at<float4>(ws, p.o_grad), at<float>(ws, p.o_pose),
+                           p.a7_max_blocks);
+    }
+    if (dL_dviewmat) {
+        hipLaunchKernelGGL(k_pose_reduce, dim3(p.V), dim3(256), 0, st, at<ViewDesc>(ws, p.o_views),
+                           at<SubmapDesc>(ws, p.o_subs), at<float>(ws, p.o_pose), p.a7_max_blocks,
+                           dL_dviewmat);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace fm

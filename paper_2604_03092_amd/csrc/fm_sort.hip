@@ -1,0 +1,300 @@
+// fm_sort.hip -- tile binning on gfx950: depth sort of the projected entries,
+// pair emission, stable tile sort and per-tile ranges.
+//
+// The pair list must come out ordered by (tile, depth key, surfel index).
+// Instead of one radix sort over 64-bit (tile, depth) keys of every pair, the
+// entries are first sorted by their 32-bit depth key (a stable LSD radix sort,
+// so equal keys keep entry order = surfel order), pairs are emitted in that
+// order, and a second stable LSD radix sort over the tile id alone groups
+// them by tile.  Both sorts are stable, so the result equals the 64-bit sort
+// while moving only ceil(tile_bits/8) passes over the pairs.
+//
+// Every kernel runs on a fixed grid sized on the host from capacities; the
+// actual pair count lives in device memory (Status), so nothing here needs a
+// host read-back and the whole sequence can be graph-captured.
+#include "fm_internal.h"
+#include "fm_wave.h"
+
+namespace fm {
+
+namespace {
+
+__device__ __forceinline__ uint32_t count_of(const Status *st, uint32_t n_host) {
+    return st ? st->n_pairs : n_host;
+}
+__device__ __forceinline__ void chunk_of(uint32_t n, int G, uint32_t &lo, uint32_t &hi) {
+    uint32_t chunk = (n + (uint32_t)G - 1) / (uint32_t)G;
+    chunk = (chunk + 255u) & ~255u;
+    lo = (uint32_t)blockIdx.x * chunk;
+    hi = lo + chunk;
+    if (lo > n) lo = n;
+    if (hi > n) hi = n;
+}
+
+// Per-block digit histogram, written digit-major: hist[d * G + block].
+__global__ __launch_bounds__(256) void k_radix_hist(const uint32_t *__restrict__ keys, const Status *st,
+                                                     uint32_t n_host, int shift, uint32_t *__restrict__ hist,
+                                                     int G) {
+    __shared__ uint32_t h[4][kRadix];
+    const int w = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) h[k][threadIdx.x] = 0;
+    __syncthreads();
+    uint32_t lo, hi;
+    chunk_of(count_of(st, n_host), G, lo, hi);
+    for (uint32_t i = lo + threadIdx.x; i < hi; i += 256) atomicAdd(&h[w][(keys[i] >> shift) & 0xFFu], 1u);
+    __syncthreads();
+    hist[threadIdx.x * G + blockIdx.x] = h[0][threadIdx.x] + h[1][threadIdx.x] + h[2][threadIdx.x] +
+                                         h[3][threadIdx.x];
+}
+
+// Exclusive scan of `count` u32 values in place (one block of 1024 threads).
+__global__ __launch_bounds__(1024) void k_scan_inplace(uint32_t *__restrict__ data, int count) {
+    __shared__ uint32_t part[1024];
+    const int per = (count + 1023) / 1024;
+    const int beg = threadIdx.x * per;
+    const int end = beg + per < count ? beg + per : count;
+    uint32_t s = 0;
+    for (int i = beg; i < end; ++i) s += data[i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        uint32_t v = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0u;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    uint32_t run = threadIdx.x ? part[threadIdx.x - 1] : 0u;
+    for (int i = beg; i < end; ++i) {
+        const uint32_t d = data[i];
+        data[i] = run;
+        run += d;
+    }
+}
+
+// Stable scatter by digit.  Each block walks its chunk in order, 256 items at
+// a time; within a wave, items with equal digits are ranked by lane through
+// ballots; waves are ranked in order through LDS.
+__global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t *__restrict__ keys_in,
+                                                        const uint32_t *__restrict__ vals_in,
+                                                        uint32_t *__restrict__ keys_out,
+                                                        uint32_t *__restrict__ vals_out, const Status *st,
+                                                        uint32_t n_host, int shift,
+                                                        const uint32_t *__restrict__ hist, int G) {
+    __shared__ uint32_t run[kRadix];
+    __shared__ uint32_t wcnt[4][kRadix];
+    const int w = threadIdx.x >> 6;
+    const int lane = lane_id();
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    run[threadIdx.x] = hist[threadIdx.x * G + blockIdx.x];
+    uint32_t lo, hi;
+    chunk_of(count_of(st, n_host), G, lo, hi);
+    for (uint32_t base = lo; base < hi; base += 256) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) wcnt[k][threadIdx.x] = 0;
+        __syncthreads();
+        const uint32_t i = base + threadIdx.x;
+        const bool valid = i < hi;
+        const uint32_t key = valid ? keys_in[i] : 0u;
+        const uint32_t val = valid ? (vals_in ? vals_in[i] : i) : 0u;
+        const uint32_t d = (key >> shift) & 0xFFu;
+        uint64_t m = ballot64(valid);
+#pragma unroll
+        for (int b = 0; b < kRadixBits; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t bb = ballot64(bit);
+            m &= bit ? bb : ~bb;
+        }
+        const uint32_t rank = (uint32_t)__popcll(m & lt);
+        if (valid && rank == 0) wcnt[w][d] = (uint32_t)__popcll(m);
+        __syncthreads();
+        {
+            uint32_t r = run[threadIdx.x];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const uint32_t c = wcnt[k][threadIdx.x];
+                wcnt[k][threadIdx.x] = r;
+                r += c;
+            }
+            run[threadIdx.x] = r;
+        }
+        __syncthreads();
+        if (valid) {
+            const uint32_t dst = wcnt[w][d] + rank;
+            keys_out[dst] = key;
+            vals_out[dst] = val;
+        }
+        __syncthreads();
+    }
+}
+
+// ---- pair count scan and emission -----------------------------------------
+
+// Block b sums the tile counts of sorted entries [b*kScanChunk, ...).
+__global__ __launch_bounds__(256) void k_count_reduce(const uint32_t *__restrict__ sorted_entry,
+                                                       const uint32_t *__restrict__ cnt, int64_t E,
+                                                       uint32_t *__restrict__ blk) {
+    __shared__ uint32_t red[4];
+    const int64_t lo = (int64_t)blockIdx.x * kScanChunk;
+    int64_t hi = lo + kScanChunk;
+    if (hi > E) hi = E;
+    uint32_t s = 0;
+    for (int64_t k = lo + threadIdx.x; k < hi; k += 256) s += cnt[sorted_entry[k]];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if (lane_id() == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) blk[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+// Exclusive scan of the block sums into 64-bit block offsets; the total is
+// the number of pairs the batch needs.
+__global__ __launch_bounds__(1024) void k_count_scan(const uint32_t *__restrict__ blk, int nb,
+                                                      uint64_t *__restrict__ blk_off, Status *st,
+                                                      uint64_t cap) {
+    __shared__ uint64_t part[1024];
+    const int per = (nb + 1023) / 1024;
+    const int beg = threadIdx.x * per;
+    const int end = beg + per < nb ? beg + per : nb;
+    uint64_t s = 0;
+    for (int i = beg; i < end; ++i) s += blk[i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        uint64_t v = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0ull;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    uint64_t run = threadIdx.x ? part[threadIdx.x - 1] : 0ull;
+    for (int i = beg; i < end; ++i) {
+        blk_off[i] = run;
+        run += blk[i];
+    }
+    if (threadIdx.x == 1023) {
+        const uint64_t total = part[1023];
+        st->required = total;
+        st->overflow = total > cap ? 1u : 0u;
+        st->n_pairs = (uint32_t)(total > cap ? cap : total);
+    }
+}
+
+// Scan within the block and emit each entry's (tile, entry) pairs, in depth
+// order, at its offset.  Pairs beyond the capacity are dropped.
+__global__ __launch_bounds__(256) void k_emit(const uint32_t *__restrict__ sorted_entry,
+                                               const uint32_t *__restrict__ cnt, int64_t E,
+                                               const uint64_t *__restrict__ blk_off,
+                                               const ViewDesc *__restrict__ views, int V,
+                                               const Rec *__restrict__ rec, KParams kp, uint64_t cap,
+                                               uint32_t *__restrict__ pkey, uint32_t *__restrict__ pval) {
+    __shared__ uint32_t wsum[4];
+    const int64_t lo = (int64_t)blockIdx.x * kScanChunk;
+    int64_t hi = lo + kScanChunk;
+    if (hi > E) hi = E;
+    uint64_t run = blk_off[blockIdx.x];
+    const int w = threadIdx.x >> 6;
+    for (int64_t base = lo; base < hi; base += 256) {
+        const int64_t k = base + threadIdx.x;
+        uint32_t e = 0, c = 0;
+        if (k < hi) {
+            e = sorted_entry[k];
+            c = cnt[e];
+        }
+        // inclusive scan of c within the wave
+        uint32_t x = c;
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(x, off);
+            if (lane_id() >= off) x += y;
+        }
+        if (lane_id() == 63) wsum[w] = x;
+        __syncthreads();
+        uint32_t wbase = 0;
+        for (int j = 0; j < w; ++j) wbase += wsum[j];
+        const uint32_t tot = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+        const uint64_t off = run + wbase + (x - c);
+        if (c != 0) {
+            const int v = view_of_entry(views, V, e);
+            const ViewDesc &vd = views[v];
+            const Rec &r = rec[e];
+            const int tx0 = r.bb[0] / kp.tile_w, tx1 = r.bb[2] / kp.tile_w;
+            const int ty0 = r.bb[1] / kp.tile_h;
+            const int ntx = tx1 - tx0 + 1;
+            for (uint32_t j = 0; j < c; ++j) {
+                const uint64_t o = off + j;
+                if (o >= cap) break;
+                const int ty = ty0 + (int)(j / (uint32_t)ntx);
+                const int tx = tx0 + (int)(j % (uint32_t)ntx);
+                pkey[o] = (uint32_t)(vd.tile_base + ty * vd.tiles_x + tx);
+                pval[o] = e;
+            }
+        }
+        run += tot;
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void k_fill_u32(uint32_t *__restrict__ p, uint32_t v, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] = v;
+}
+
+__global__ __launch_bounds__(256) void k_tile_ranges(const uint32_t *__restrict__ pkey, const Status *st,
+                                                      uint32_t *__restrict__ ts, uint32_t *__restrict__ te) {
+    const uint32_t n = st->n_pairs;
+    for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+        const uint32_t t = pkey[i];
+        if (i == 0 || pkey[i - 1] != t) ts[t] = i;
+        if (i == n - 1 || pkey[i + 1] != t) te[t] = i + 1;
+    }
+}
+
+void radix_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout, const Status *st,
+                uint32_t n_host, int shift, uint32_t *hist, int G, hipStream_t s) {
+    hipLaunchKernelGGL(k_radix_hist, dim3(G), dim3(256), 0, s, kin, st, n_host, shift, hist, G);
+    hipLaunchKernelGGL(k_scan_inplace, dim3(1), dim3(1024), 0, s, hist, kRadix * G);
+    hipLaunchKernelGGL(k_radix_scatter, dim3(G), dim3(256), 0, s, kin, vin, kout, vout, st, n_host, shift,
+                       hist, G);
+}
+
+}  // namespace
+
+hipError_t launch_binning(const Plan &p, void *ws, const KParams &kp, hipStream_t st) {
+    Status *status = at<Status>(ws, p.o_status);
+    uint32_t *key = at<uint32_t>(ws, p.o_key), *key2 = at<uint32_t>(ws, p.o_key2);
+    uint32_t *val = at<uint32_t>(ws, p.o_val), *val2 = at<uint32_t>(ws, p.o_val2);
+    uint32_t *hist = at<uint32_t>(ws, p.o_hist);
+    // 1. stable sort of the entries by their 32-bit depth key (4 passes; the
+    //    first pass starts from the identity permutation)
+    const uint32_t E = (uint32_t)p.E;
+    radix_pass(key, nullptr, key2, val2, nullptr, E, 0, hist, p.sortG_e, st);
+    radix_pass(key2, val2, key, val, nullptr, E, 8, hist, p.sortG_e, st);
+    radix_pass(key, val, key2, val2, nullptr, E, 16, hist, p.sortG_e, st);
+    radix_pass(key2, val2, key, val, nullptr, E, 24, hist, p.sortG_e, st);
+    // 2. pair offsets in depth order and emission
+    uint32_t *blk = at<uint32_t>(ws, p.o_scan);
+    uint64_t *blk_off = reinterpret_cast<uint64_t *>(blk + ((p.scan_blocks + 63) & ~63));
+    hipLaunchKernelGGL(k_count_reduce, dim3(p.scan_blocks), dim3(256), 0, st, val, at<uint32_t>(ws, p.o_cnt),
+                       p.E, blk);
+    hipLaunchKernelGGL(k_count_scan, dim3(1), dim3(1024), 0, st, blk, p.scan_blocks, blk_off, status,
+                       (uint64_t)p.cap);
+    uint32_t *pkey = at<uint32_t>(ws, p.o_pkey), *pval = at<uint32_t>(ws, p.o_pval);
+    uint32_t *pkey2 = at<uint32_t>(ws, p.o_pkey2), *pval2 = at<uint32_t>(ws, p.o_pval2);
+    hipLaunchKernelGGL(k_emit, dim3(p.scan_blocks), dim3(256), 0, st, val, at<uint32_t>(ws, p.o_cnt), p.E,
+                       blk_off, at<ViewDesc>(ws, p.o_views), p.V, at<Rec>(ws, p.o_rec), kp,
+                       (uint64_t)p.cap, pkey, pval);
+    // 3. stable sort of the pairs by tile id
+    uint32_t *ka = pkey, *va = pval, *kb = pkey2, *vb = pval2;
+    for (int pass = 0; pass < p.pair_passes; ++pass) {
+        radix_pass(ka, va, kb, vb, status, 0, 8 * pass, hist, p.sortG_p, st);
+        uint32_t *t = ka; ka = kb; kb = t;
+        t = va; va = vb; vb = t;
+    }
+    // 4. per-tile ranges
+    uint32_t *ts = at<uint32_t>(ws, p.o_tstart), *te = at<uint32_t>(ws, p.o_tend);
+    const int fill_blocks = (int)((p.T + 255) / 256 < 4096 ? (p.T + 255) / 256 : 4096);
+    hipLaunchKernelGGL(k_fill_u32, dim3(fill_blocks), dim3(256), 0, st, ts, 0u, p.T);
+    hipLaunchKernelGGL(k_fill_u32, dim3(fill_blocks), dim3(256), 0, st, te, 0u, p.T);
+    const int rblocks = (int)((p.cap + 255) / 256 < 8192 ? (p.cap + 255) / 256 : 8192);
+    hipLaunchKernelGGL(k_tile_ranges, dim3(rblocks), dim3(256), 0, st, ka, status, ts, te);
+    return hipGetLastError();
+}
+
+}  // namespace fm

@@ -1,0 +1,311 @@
+"""PyTorch-facing binding of the gfx950 surfel rasterizer.
+
+PyTorch only provides device memory and the current stream; every step of
+projection, binning, sorting, compositing and their adjoints runs in
+libfm2dgs.so through the C ABI declared in include/fm2dgs.h.
+
+    rast = Rasterizer()
+    gs = GpuScene.from_scene(scenes.config1())
+    out, ws = rast.forward(gs)
+    rast.backward(gs, ws, out, dL_dout, grads, dL_dviewmat)
+
+``render`` wraps the same calls in a torch.autograd.Function.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass, field
+
+import torch
+
+from . import native
+from .native import (FmBatch, FmGradOutputs, FmL1Loss, FmOutputs, FmRasterParams, FmSurfelGrads, FmSurfels,
+                     FmViewShape)
+
+PLANES = ("mean", "quat", "scale", "opacity", "color")
+CHANNELS = {"mean": 3, "quat": 4, "scale": 2, "opacity": 1, "color": 3}
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class GpuScene:
+    """Device tensors of a batch (surfel submaps, views, cameras, targets) and
+    the C-ABI batch descriptor pointing at them."""
+
+    def __init__(self, submaps, views, intr, viewmat, target_rgb=None, target_depth=None,
+                 w_rgb=1.0, w_depth=0.0, name="scene"):
+        self.submaps = submaps
+        self.views = [tuple(int(x) for x in v) for v in views]
+        self.intr = intr.contiguous()
+        self.viewmat = viewmat.contiguous()
+        self.target_rgb = target_rgb
+        self.target_depth = target_depth
+        self.w_rgb = float(w_rgb)
+        self.w_depth = float(w_depth)
+        self.name = name
+        self.npx = sum(w * h for (w, h, _) in self.views)
+        self.pixel_offsets = []
+        off = 0
+        for (w, h, _) in self.views:
+            self.pixel_offsets.append(off)
+            off += w * h
+        self._batch = None
+
+    @classmethod
+    def from_scene(cls, scene, device="cuda"):
+        subs = [{k: torch.from_numpy(sm[k]).to(device).contiguous() for k in PLANES} for sm in scene.submaps]
+        f = lambda a: None if a is None else torch.from_numpy(a).to(device).contiguous()
+        return cls(subs, scene.views, f(scene.intr), f(scene.viewmat), f(scene.target_rgb),
+                   f(scene.target_depth), scene.w_rgb, scene.w_depth, scene.name)
+
+    @property
+    def n_views(self):
+        return len(self.views)
+
+    def batch(self):
+        """FmBatch (cached; rebuilt if a tensor was replaced)."""
+        key = tuple(t.data_ptr() for sm in self.submaps for t in sm.values()) + (
+            self.intr.data_ptr(), self.viewmat.data_ptr())
+        if self._batch is None or self._batch[0] != key:
+            subs = (FmSurfels * len(self.submaps))()
+            for i, sm in enumerate(self.submaps):
+                subs[i].n = int(sm["opacity"].shape[-1])
+                for k in PLANES:
+                    assert sm[k].is_contiguous() and sm[k].dtype == torch.float32
+                    assert sm[k].shape[-1] == subs[i].n and sm[k].numel() == CHANNELS[k] * subs[i].n
+                    setattr(subs[i], k, sm[k].data_ptr())
+            vs = (FmViewShape * len(self.views))()
+            for i, (w, h, s) in enumerate(self.views):
+                vs[i].width, vs[i].height, vs[i].submap = w, h, s
+            b = FmBatch(len(self.submaps), subs, len(self.views), vs, self.intr.data_ptr(),
+                        self.viewmat.data_ptr())
+            self._batch = (key, b, subs, vs)
+        return self._batch[1]
+
+    def view_image(self, plane, v):
+        """Slice a [C, P] (or [P]) output plane to view v as [C, H, W]."""
+        w, h, _ = self.views[v]
+        o = self.pixel_offsets[v]
+        x = plane[..., o:o + w * h]
+        return x.reshape(*x.shape[:-1], h, w)
+
+    def zero_grads(self):
+        grads = [{k: torch.zeros_like(sm[k]) for k in PLANES} for sm in self.submaps]
+        return grads, torch.zeros_like(self.viewmat)
+
+
+@dataclass
+class Workspace:
+    buf: torch.Tensor
+    nbytes: int
+    max_pairs: int
+    params: FmRasterParams
+    n_pairs: int = -1
+    extra: dict = field(default_factory=dict)
+
+
+def _outputs(out):
+    return FmOutputs(out["rgb"].data_ptr(), out["depth"].data_ptr(), out["normal"].data_ptr(),
+                     out["alpha"].data_ptr())
+
+
+def _grad_structs(grads):
+    arr = (FmSurfelGrads * len(grads))()
+    for i, g in enumerate(grads):
+        for k in PLANES:
+            t = g.get(k) if g is not None else None
+            if t is not None:
+                assert t.is_contiguous() and t.dtype == torch.float32
+            setattr(arr[i], k, t.data_ptr() if t is not None else None)
+    return arr
+
+
+class Rasterizer:
+    """One fm_ctx on one device."""
+
+    def __init__(self, device=None):
+        self.lib = native.load()
+        dev = torch.cuda.current_device() if device is None else int(device)
+        self.device = dev
+        ctx = ctypes.c_void_p()
+        st = self.lib.fm_create(ctypes.byref(ctx), dev)
+        if st != 0:
+            raise native.FmError(st, "fm_create failed")
+        self.ctx = ctx
+
+    def __del__(self):
+        try:
+            if getattr(self, "ctx", None):
+                self.lib.fm_destroy(self.ctx)
+                self.ctx = None
+        except Exception:
+            pass
+
+    # -- helpers ---------------------------------------------------------
+    def check(self, st):
+        if st != 0:
+            raise native.FmError(st, self.lib.fm_last_error(self.ctx).decode())
+
+    def params(self, alpha_min=1.0 / 255.0, alpha_max=0.99, t_min=1e-4, rho_max=3.0, near=0.2,
+               bg=(0.0, 0.0, 0.0), tile=(16, 16)):
+        p = FmRasterParams()
+        self.lib.fm_default_params(ctypes.byref(p))
+        p.alpha_min, p.alpha_max, p.t_min, p.rho_max, p.near_plane = alpha_min, alpha_max, t_min, rho_max, near
+        for k in range(3):
+            p.bg[k] = bg[k]
+        p.tile_w, p.tile_h = tile
+        return p
+
+    def workspace_size(self, gs, params, max_pairs):
+        n = ctypes.c_size_t(0)
+        self.check(self.lib.fm_workspace_size(self.ctx, ctypes.byref(gs.batch()), ctypes.byref(params),
+                                              int(max_pairs), ctypes.byref(n)))
+        return int(n.value)
+
+    def workspace(self, gs, params=None, max_pairs=None):
+        params = params or self.params()
+        if max_pairs is None:
+            ent = sum(int(gs.submaps[s]["opacity"].shape[-1]) for (_, _, s) in gs.views)
+            max_pairs = max(1 << 16, 4 * ent)
+        nbytes = self.workspace_size(gs, params, max_pairs)
+        buf = torch.empty(nbytes, dtype=torch.uint8, device=gs.intr.device)
+        return Workspace(buf, nbytes, int(max_pairs), params)
+
+    def new_outputs(self, gs):
+        d = gs.intr.device
+        return dict(rgb=torch.empty(3, gs.npx, device=d), depth=torch.empty(gs.npx, device=d),
+                    normal=torch.empty(3, gs.npx, device=d), alpha=torch.empty(gs.npx, device=d))
+
+    def query(self, gs, ws):
+        """(status, n_pairs, required) of the last forward on ws (synchronous)."""
+        n = ctypes.c_int64(0)
+        r = ctypes.c_int64(0)
+        st = self.lib.fm_query_status(self.ctx, ctypes.byref(gs.batch()), ctypes.byref(ws.params), _ptr(ws.buf),
+                                      ws.max_pairs, ctypes.byref(n), ctypes.byref(r))
+        if st not in (0, native.FM_ERR_CAPACITY):
+            self.check(st)
+        return st, int(n.value), int(r.value)
+
+    # -- forward / backward -------------------------------------------------
+    def forward_into(self, gs, ws, out, stream=None):
+        self.check(self.lib.fm_forward(self.ctx, ctypes.byref(gs.batch()), ctypes.byref(ws.params),
+                                       _outputs(out), _ptr(ws.buf), ws.nbytes, ws.max_pairs, _stream(stream)))
+
+    def forward(self, gs, params=None, ws=None, out=None, grow=True):
+        """Render every view; grows the pair capacity (synchronising) when it
+        overflows.  Returns (outputs, workspace)."""
+        params = params or self.params()
+        ws = ws or self.workspace(gs, params)
+        out = out or self.new_outputs(gs)
+        while True:
+            self.forward_into(gs, ws, out)
+            if not grow:
+                return out, ws
+            st, n, req = self.query(gs, ws)
+            ws.n_pairs = n
+            if st == 0:
+                return out, ws
+            ws = self.workspace(gs, params, max_pairs=int(req * 1.25) + 1024)
+
+    def backward(self, gs, ws, out, g, grads, dviewmat=None, stream=None):
+        """Accumulate gradients of the last forward on ws.  g: dict of
+        dL/d(rgb, depth, normal, alpha) planes (missing = zero); grads: list
+        (per submap) of dicts of gradient tensors (+=)."""
+        keep = {k: (g[k].contiguous() if g.get(k) is not None else None)
+                for k in ("rgb", "depth", "normal", "alpha")}
+        gstruct = FmGradOutputs(*[(keep[k].data_ptr() if keep[k] is not None else None)
+                                  for k in ("rgb", "depth", "normal", "alpha")])
+        gg = _grad_structs(grads)
+        self.check(self.lib.fm_backward(self.ctx, ctypes.byref(gs.batch()), ctypes.byref(ws.params),
+                                        _outputs(out), gstruct, _ptr(ws.buf), ws.nbytes, ws.max_pairs, gg,
+                                        _ptr(dviewmat), _stream(stream)))
+        del keep
+
+    def fwd_bwd_l1(self, gs, ws, out, grads, dviewmat, loss, mask=None, stream=None):
+        """Fused forward + L1 loss + backward (adds the loss into `loss`)."""
+        ls = FmL1Loss(gs.target_rgb.data_ptr(),
+                      gs.target_depth.data_ptr() if gs.target_depth is not None else None,
+                      mask.data_ptr() if mask is not None else None, gs.w_rgb,
+                      gs.w_depth if gs.target_depth is not None else 0.0)
+        gg = _grad_structs(grads)
+        self.check(self.lib.fm_fwd_bwd_l1(self.ctx, ctypes.byref(gs.batch()), ctypes.byref(ws.params),
+                                          ctypes.byref(ls), _outputs(out), _ptr(loss), gg, _ptr(dviewmat),
+                                          _ptr(ws.buf), ws.nbytes, ws.max_pairs, _stream(stream)))
+
+    def autotune(self, gs, ws, out, grads, dviewmat, loss, cache_path=None):
+        ls = FmL1Loss(gs.target_rgb.data_ptr(),
+                      gs.target_depth.data_ptr() if gs.target_depth is not None else None, None, gs.w_rgb,
+                      gs.w_depth if gs.target_depth is not None else 0.0)
+        chosen = FmRasterParams()
+        gg = _grad_structs(grads)
+        self.check(self.lib.fm_autotune(self.ctx, ctypes.byref(gs.batch()), ctypes.byref(ws.params),
+                                        ctypes.byref(ls), _outputs(out), _ptr(loss), gg, _ptr(dviewmat),
+                                        _ptr(ws.buf), ws.nbytes, ws.max_pairs,
+                                        cache_path.encode() if cache_path else None, ctypes.byref(chosen),
+                                        _stream(None)))
+        return chosen
+
+    def debug_pairs(self, gs, ws):
+        """Sorted pair list of the last forward: (tile, surfel, view, tile_start, tile_end) as numpy."""
+        import numpy as np
+        n = ctypes.c_int64(0)
+        tcount = ctypes.c_int64(0)
+        self.check(self.lib.fm_tile_count(ctypes.byref(gs.batch()), ctypes.byref(ws.params), ctypes.byref(tcount)))
+        self.check(self.lib.fm_debug_pairs(self.ctx, ctypes.byref(gs.batch()), ctypes.byref(ws.params),
+                                           _ptr(ws.buf), ws.max_pairs, None, None, None, 0, ctypes.byref(n),
+                                           None, None, 0))
+        m = int(n.value)
+        tile = np.zeros(max(m, 1), np.uint32)
+        surf = np.zeros(max(m, 1), np.uint32)
+        view = np.zeros(max(m, 1), np.uint32)
+        ts = np.zeros(int(tcount.value), np.uint32)
+        te = np.zeros(int(tcount.value), np.uint32)
+        self.check(self.lib.fm_debug_pairs(self.ctx, ctypes.byref(gs.batch()), ctypes.byref(ws.params),
+                                           _ptr(ws.buf), ws.max_pairs, tile.ctypes.data, surf.ctypes.data,
+                                           view.ctypes.data, m, ctypes.byref(n), ts.ctypes.data, te.ctypes.data,
+                                           int(tcount.value)))
+        return tile[:m], surf[:m], view[:m], ts, te
+
+
+# ---------------------------------------------------------------------------
+# autograd
+# ---------------------------------------------------------------------------
+
+class _RenderFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, rast, gs, params, *flat):
+        out, ws = rast.forward(gs, params)
+        ctx.rast, ctx.gs, ctx.ws, ctx.out = rast, gs, ws, out
+        return out["rgb"], out["depth"], out["normal"], out["alpha"]
+
+    @staticmethod
+    def backward(ctx, g_rgb, g_depth, g_normal, g_alpha):
+        gs = ctx.gs
+        grads, dvm = gs.zero_grads()
+        g = dict(rgb=g_rgb, depth=g_depth, normal=g_normal, alpha=g_alpha)
+        ctx.rast.backward(gs, ctx.ws, ctx.out, g, grads, dvm)
+        flat = []
+        for gr in grads:
+            flat += [gr[k] for k in PLANES]
+        return (None, None, None, *flat, dvm)
+
+
+def render(rast, submaps, views, intr, viewmat, params=None):
+    """Differentiable render of a batch.  submaps: list of dicts of
+    float32 CUDA tensors (mean[3,n], quat[4,n], scale[2,n], opacity[n],
+    color[3,n]); views: list of (W, H, submap); intr [V,4]; viewmat [V,12].
+    Returns planes (rgb[3,P], depth[P], normal[3,P], alpha[P]) whose backward
+    yields gradients for every surfel plane and for viewmat."""
+    gs = GpuScene([{k: sm[k].detach() for k in PLANES} for sm in submaps], views, intr.detach(),
+                  viewmat.detach())
+    flat = []
+    for sm in submaps:
+        flat += [sm[k] for k in PLANES]
+    return _RenderFn.apply(rast, gs, params or rast.params(), *flat, viewmat)

@@ -1,0 +1,112 @@
+"""The C-ABI library loads on a machine without a GPU, exports every function
+include/fm2dgs.h declares, and the ctypes mirror matches the C struct layout
+(checked by compiling a probe against the header with gcc).  No compute call
+is made here."""
+import ctypes
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+from paper_2604_03092_amd import native
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fm2dgs.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:fm_status|void|const char \*|int)\s*\*?\s*(fm_\w+)\s*\(", text, re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(native.LIB_PATH):
+        from paper_2604_03092_amd import build
+        build.build()
+    return native.load()
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("fm_create", "fm_destroy", "fm_forward", "fm_backward", "fm_fwd_bwd_l1", "fm_workspace_size",
+                 "fm_query_status", "fm_debug_pairs", "fm_autotune"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    out = subprocess.run(["nm", "-D", "--defined-only", native.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    exported = set(re.findall(r" T (fm_\w+)$", out, re.M))
+    missing = [n for n in declared_functions() if n not in exported]
+    assert not missing, missing
+    for n in declared_functions():
+        assert getattr(lib, n) is not None
+    assert set(native.SIGNATURES) == set(declared_functions())
+
+
+def test_host_only_calls(lib):
+    p = native.FmRasterParams()
+    lib.fm_default_params(ctypes.byref(p))
+    assert p.tile_w == 16 and p.tile_h == 16 and abs(p.alpha_max - 0.99) < 1e-7
+    assert abs(p.alpha_min - 1 / 255) < 1e-9 and abs(p.t_min - 1e-4) < 1e-10 and p.rho_max == 3.0
+    assert lib.fm_version() >= 10000
+    assert lib.fm_status_string(2) == b"pair capacity exceeded"
+    # tile count is host arithmetic
+    vs = (native.FmViewShape * 2)(native.FmViewShape(640, 480, 0), native.FmViewShape(100, 50, 0))
+    b = native.FmBatch(1, None, 2, vs, None, None)
+    n = ctypes.c_int64(0)
+    assert lib.fm_tile_count(ctypes.byref(b), ctypes.byref(p), ctypes.byref(n)) == 0
+    assert n.value == 40 * 30 + 7 * 4
+    p.tile_w, p.tile_h = 12, 12
+    assert lib.fm_tile_count(ctypes.byref(b), ctypes.byref(p), ctypes.byref(n)) == native.FM_ERR_UNSUPPORTED
+
+
+PROBE = r"""
+#include <stdio.h>
+#include <stddef.h>
+#include "fm2dgs.h"
+#define S(T) printf(#T " %zu\n", sizeof(T));
+#define O(T, f) printf(#T "." #f " %zu\n", offsetof(T, f));
+int main(void) {
+  S(fm_surfels) S(fm_surfel_grads) S(fm_view_shape) S(fm_batch) S(fm_raster_params) S(fm_outputs)
+  S(fm_grad_outputs) S(fm_l1_loss)
+  O(fm_batch, views) O(fm_batch, intr) O(fm_batch, viewmat) O(fm_raster_params, bg)
+  O(fm_raster_params, tile_w) O(fm_l1_loss, w_rgb) O(fm_surfels, color)
+  return 0;
+}
+"""
+
+
+def test_ctypes_layout_matches_header():
+    with tempfile.TemporaryDirectory() as d:
+        src = os.path.join(d, "probe.c")
+        exe = os.path.join(d, "probe")
+        open(src, "w").write(PROBE)
+        subprocess.check_call(["gcc", "-I", os.path.dirname(HEADER), src, "-o", exe])
+        vals = dict(line.split() for line in subprocess.check_output([exe], text=True).splitlines())
+    m = {"fm_surfels": native.FmSurfels, "fm_surfel_grads": native.FmSurfelGrads,
+         "fm_view_shape": native.FmViewShape, "fm_batch": native.FmBatch,
+         "fm_raster_params": native.FmRasterParams, "fm_outputs": native.FmOutputs,
+         "fm_grad_outputs": native.FmGradOutputs, "fm_l1_loss": native.FmL1Loss}
+    for k, cls in m.items():
+        assert int(vals[k]) == ctypes.sizeof(cls), k
+    assert int(vals["fm_batch.views"]) == native.FmBatch.views.offset
+    assert int(vals["fm_batch.intr"]) == native.FmBatch.intr.offset
+    assert int(vals["fm_batch.viewmat"]) == native.FmBatch.viewmat.offset
+    assert int(vals["fm_raster_params.bg"]) == native.FmRasterParams.bg.offset
+    assert int(vals["fm_raster_params.tile_w"]) == native.FmRasterParams.tile_w.offset
+    assert int(vals["fm_l1_loss.w_rgb"]) == native.FmL1Loss.w_rgb.offset
+    assert int(vals["fm_surfels.color"]) == native.FmSurfels.color.offset
+
+
+def test_create_without_gpu_fails_cleanly(lib):
+    """With no visible device fm_create returns an error instead of crashing."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    ctx = ctypes.c_void_p()
+    assert lib.fm_create(ctypes.byref(ctx), 0) != 0
+    assert not ctx.value

@@ -1,0 +1,292 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Every test seeds its inputs with the scene generators; the oracle sees the
+same float32 arrays.  Output planes are compared on pixels the oracle does
+not flag; upstream gradients are zeroed on flagged pixels on both sides."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2604_03092_amd import scenes
+from paper_2604_03092_amd.raster import GpuScene, Rasterizer
+from tests.gpu_util import assert_grad_close, assert_images_close, random_upstream, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rast():
+    return Rasterizer()
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _oracle_forward(sc, views=None, **kw):
+    return oracle.render_scene(sc, views=views, **kw)
+
+
+def _gpu_pairs_by_view(rast, gs, ws, sc, tile):
+    tile_ids, surf, view, ts, te = rast.debug_pairs(gs, ws)
+    return tile_ids, surf, view, ts, te
+
+
+# ------------------------------------------------------------------ forward
+@pytest.mark.parametrize("tile", [(16, 16), (8, 8), (16, 8), (32, 8)])
+def test_config0_forward_and_pairs(rast, tile):
+    sc = scenes.config0()
+    _say(f"config0 forward tile={tile}")
+    gs = GpuScene.from_scene(sc)
+    p = rast.params(tile=tile)
+    out, ws = rast.forward(gs, p)
+    torch.cuda.synchronize()
+    ref = _oracle_forward(sc)
+    keep = ~ref["flags"]
+    assert keep.mean() > 0.99
+    assert_images_close(out, ref, keep, what="config0")
+    # pair list and tile ranges: bit-exact
+    b = oracle.bin_view(sc.submaps[0], 64, 48, sc.intr[0], sc.viewmat[0], tile_w=tile[0], tile_h=tile[1])
+    t, s, v, ts, te = rast.debug_pairs(gs, ws)
+    assert len(t) == b["n_pairs"]
+    assert np.array_equal(t, b["pair_tile"])
+    assert np.array_equal(s, b["pair_surf"])
+    assert np.array_equal(ts[te > ts], b["tile_start"][b["tile_end"] > b["tile_start"]])
+    assert np.array_equal(te - ts, b["tile_end"] - b["tile_start"])
+
+
+def test_tile_shape_does_not_change_images(rast):
+    sc = scenes.random_scene(5, 20000, 200, 136, scale_lo=0.02, scale_hi=0.15)
+    gs = GpuScene.from_scene(sc)
+    ref = None
+    for tile in [(16, 16), (8, 8), (16, 8), (32, 8)]:
+        _say(f"tile invariance {tile}")
+        out, _ = rast.forward(gs, rast.params(tile=tile))
+        got = {k: v.cpu().numpy() for k, v in out.items()}
+        if ref is None:
+            ref = got
+        else:
+            for k in ref:
+                assert np.array_equal(got[k], ref[k]), (tile, k)
+
+
+# ------------------------------------------------------------------ backward
+@pytest.mark.parametrize("name,seed", [("config0", 1), ("dense", 2)])
+def test_backward_small(rast, name, seed):
+    sc = scenes.config0() if name == "config0" else scenes.random_scene(
+        33, 4000, 72, 56, scale_lo=0.03, scale_hi=0.2)
+    _say(f"backward {name}")
+    gs = GpuScene.from_scene(sc)
+    out, ws = rast.forward(gs)
+    ref = _oracle_forward(sc)
+    keep = ~ref["flags"]
+    rng = np.random.default_rng(seed)
+    g = random_upstream(rng, gs.npx, keep)
+    gt = {k: torch.from_numpy(v.astype(np.float32)).cuda() for k, v in g.items()}
+    grads, dvm = gs.zero_grads()
+    rast.backward(gs, ws, out, gt, grads, dvm)
+    torch.cuda.synchronize()
+    rg, rdvm = oracle.backward_scene(sc, g)
+    for k in ("mean", "quat", "scale", "opacity", "color"):
+        assert_grad_close(to_np(grads[0][k]), rg[0][k], f"{name}.{k}")
+    assert_grad_close(to_np(dvm), rdvm, f"{name}.viewmat")
+
+
+def test_fused_l1_config0(rast):
+    sc = scenes.config0()
+    _say("fused l1 config0")
+    gs = GpuScene.from_scene(sc)
+    ref = _oracle_forward(sc)
+    # pixels whose L1 sign is not decided robustly are masked on both sides
+    near = np.any(np.abs(ref["rgb"] - sc.target_rgb) < 5e-4, axis=0)
+    keep = ~(ref["flags"] | near)
+    mask = torch.from_numpy(keep.astype(np.uint8)).cuda()
+    ws = rast.workspace(gs)
+    out = rast.new_outputs(gs)
+    grads, dvm = gs.zero_grads()
+    loss = torch.zeros(1, device="cuda")
+    rast.fwd_bwd_l1(gs, ws, out, grads, dvm, loss, mask=mask)
+    torch.cuda.synchronize()
+    assert rast.query(gs, ws)[0] == 0
+    L, g = oracle.l1_loss(sc, ref, mask=keep)
+    assert abs(float(loss) - L) <= 1e-5 * max(1.0, abs(L))
+    assert_images_close(out, ref, keep, what="fused")
+    rg, rdvm = oracle.backward_scene(sc, g)
+    for k in ("mean", "quat", "scale", "opacity", "color"):
+        assert_grad_close(to_np(grads[0][k]), rg[0][k], f"fused.{k}")
+    assert_grad_close(to_np(dvm), rdvm, "fused.viewmat")
+
+
+# ------------------------------------------------------------------ batches
+def test_batch_equals_single_views(rast):
+    sc = scenes.random_scene(9, 30000, 160, 120, n_views=4, scale_lo=0.02, scale_hi=0.12)
+    gs = GpuScene.from_scene(sc)
+    _say("batch of 4 views")
+    out, ws = rast.forward(gs)
+    rng = np.random.default_rng(3)
+    g = random_upstream(rng, gs.npx, np.ones(gs.npx, bool))
+    gt = {k: torch.from_numpy(v.astype(np.float32)).cuda() for k, v in g.items()}
+    grads, dvm = gs.zero_grads()
+    rast.backward(gs, ws, out, gt, grads, dvm)
+    acc_grads, _ = gs.zero_grads()
+    for v in range(4):
+        gv = GpuScene(gs.submaps, [gs.views[v]], gs.intr[v:v + 1].contiguous(), gs.viewmat[v:v + 1].contiguous())
+        o1, w1 = rast.forward(gv)
+        sl = slice(gs.pixel_offsets[v], gs.pixel_offsets[v] + gv.npx)
+        for k in out:
+            assert torch.equal(o1[k], out[k][..., sl]), (v, k)
+        g1 = {k: x[..., sl].contiguous() for k, x in gt.items()}
+        d1 = torch.zeros(1, 12, device="cuda")
+        rast.backward(gv, w1, o1, g1, acc_grads, d1)
+        assert torch.allclose(d1[0], dvm[v], rtol=1e-4, atol=1e-6 * float(dvm.abs().max()))
+    for k in acc_grads[0]:
+        assert_grad_close(to_np(grads[0][k]), to_np(acc_grads[0][k]), f"batch.{k}", rel=1e-5)
+
+
+def test_multi_submap_batch(rast):
+    base = [scenes.random_scene(40 + i, 3000 * (i + 1), 64, 48, scale_lo=0.03, scale_hi=0.15) for i in range(3)]
+    views = [(64, 48, 0), (64, 48, 2), (64, 48, 1), (64, 48, 2)]
+    intr = np.concatenate([base[s].intr for (_, _, s) in views])
+    vm = np.concatenate([base[s].viewmat for (_, _, s) in views])
+    sc = scenes.Scene("multi", [b.submaps[0] for b in base], views, intr, vm)
+    _say("multi-submap batch")
+    gs = GpuScene.from_scene(sc)
+    out, ws = rast.forward(gs)
+    ref = _oracle_forward(sc)
+    keep = ~ref["flags"]
+    assert_images_close(out, ref, keep, what="multi")
+    rng = np.random.default_rng(4)
+    g = random_upstream(rng, gs.npx, keep)
+    gt = {k: torch.from_numpy(v.astype(np.float32)).cuda() for k, v in g.items()}
+    grads, dvm = gs.zero_grads()
+    rast.backward(gs, ws, out, gt, grads, dvm)
+    torch.cuda.synchronize()
+    rg, rdvm = oracle.backward_scene(sc, g)
+    for s in range(3):
+        for k in ("mean", "quat", "scale", "opacity", "color"):
+            assert_grad_close(to_np(grads[s][k]), rg[s][k], f"multi[{s}].{k}")
+    assert_grad_close(to_np(dvm), rdvm, "multi.viewmat")
+
+
+# ------------------------------------------------------------------ full size
+def test_config1_forward_backward(rast):
+    sc = scenes.config1()
+    _say("config1 forward")
+    gs = GpuScene.from_scene(sc)
+    out, ws = rast.forward(gs)
+    torch.cuda.synchronize()
+    ref = _oracle_forward(sc)
+    keep = ~ref["flags"]
+    _say(f"config1 flagged fraction {1 - keep.mean():.2e}")
+    assert keep.mean() > 0.99
+    assert_images_close(out, ref, keep, what="config1")
+    _say("config1 pairs")
+    b = oracle.bin_view(sc.submaps[0], 640, 480, sc.intr[0], sc.viewmat[0])
+    t, s, v, ts, te = rast.debug_pairs(gs, ws)
+    assert len(t) == b["n_pairs"]
+    assert np.array_equal(t, b["pair_tile"]) and np.array_equal(s, b["pair_surf"])
+    assert np.array_equal(te - ts, b["tile_end"] - b["tile_start"])
+    _say("config1 backward")
+    near = np.any(np.abs(ref["rgb"] - sc.target_rgb) < 5e-4, axis=0) | (
+        np.abs(ref["depth"] - sc.target_depth) < 5e-4)
+    keep2 = keep & ~near
+    L, g = oracle.l1_loss(sc, ref, mask=keep2)
+    gt = {k: torch.from_numpy(v.astype(np.float32)).cuda() for k, v in g.items()}
+    grads, dvm = gs.zero_grads()
+    rast.backward(gs, ws, out, gt, grads, dvm)
+    torch.cuda.synchronize()
+    rg, rdvm = oracle.backward_scene(sc, g)
+    for k in ("mean", "quat", "scale", "opacity", "color"):
+        assert_grad_close(to_np(grads[0][k]), rg[0][k], f"config1.{k}")
+    assert_grad_close(to_np(dvm), rdvm, "config1.viewmat")
+
+
+# ------------------------------------------------------------------ edge cases
+def test_capacity_overflow_then_retry(rast):
+    sc = scenes.config0()
+    gs = GpuScene.from_scene(sc)
+    _say("capacity overflow")
+    ws = rast.workspace(gs, max_pairs=100)
+    out = rast.new_outputs(gs)
+    rast.forward_into(gs, ws, out)
+    st, n, req = rast.query(gs, ws)
+    assert st == 2 and n == 100 and req > 100
+    out2, ws2 = rast.forward(gs)            # grows and succeeds
+    assert rast.query(gs, ws2)[0] == 0
+    ref = _oracle_forward(sc)
+    assert_images_close(out2, ref, ~ref["flags"], what="after grow")
+
+
+def test_empty_and_culled(rast):
+    # every surfel culled: NaN, zero quaternion, behind the camera, transparent
+    n = 8
+    sm = dict(mean=np.tile(np.array([[0.0], [0.0], [3.0]], np.float32), (1, n)),
+              quat=np.tile(np.array([[1.0], [0.0], [0.0], [0.0]], np.float32), (1, n)),
+              scale=np.full((2, n), 0.3, np.float32), opacity=np.full(n, 0.8, np.float32),
+              color=np.ones((3, n), np.float32))
+    sm["mean"][0, 0] = np.nan
+    sm["quat"][:, 1] = 0.0
+    sm["mean"][2, 2] = -1.0
+    sm["opacity"][3] = 0.001
+    sm["scale"][1, 4] = 0.0
+    sm["quat"][2, 5] = np.inf
+    sm["mean"][2, 6] = 0.1
+    sm["color"][1, 7] = np.nan
+    sc = scenes.Scene("culled", [sm], [(32, 24, 0)], np.array([[30, 30, 16, 12]], np.float32),
+                      np.array([[1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0]], np.float32))
+    gs = GpuScene.from_scene(sc)
+    _say("all culled")
+    out, ws = rast.forward(gs)
+    assert float(out["alpha"].abs().max()) == 0.0 and float(out["rgb"].abs().max()) == 0.0
+    assert rast.query(gs, ws)[1] == 0
+    g = {k: torch.ones_like(v) for k, v in out.items()}
+    grads, dvm = gs.zero_grads()
+    rast.backward(gs, ws, out, g, grads, dvm)
+    for k in grads[0]:
+        assert float(grads[0][k].abs().max()) == 0.0
+    # empty submap
+    sm0 = {k: v[..., :0].copy() for k, v in sm.items()}
+    gs0 = GpuScene.from_scene(scenes.Scene("empty", [sm0], [(20, 10, 0)], sc.intr, sc.viewmat))
+    out0, _ = rast.forward(gs0)
+    assert float(out0["alpha"].abs().max()) == 0.0
+
+
+def test_invalid_arguments(rast):
+    from paper_2604_03092_amd import native
+    sc = scenes.config0()
+    gs = GpuScene.from_scene(sc)
+    with pytest.raises(native.FmError) as e:
+        rast.workspace(gs, rast.params(tile=(12, 12)))
+    assert e.value.status == native.FM_ERR_UNSUPPORTED
+    with pytest.raises(native.FmError) as e:
+        rast.workspace(gs, rast.params(alpha_max=1.5))
+    assert e.value.status == native.FM_ERR_INVALID_ARG
+    ws = rast.workspace(gs)
+    ws.nbytes = 10
+    with pytest.raises(native.FmError) as e:
+        rast.forward_into(gs, ws, rast.new_outputs(gs))
+    assert e.value.status == native.FM_ERR_WORKSPACE
+    bad = GpuScene(gs.submaps, [(64, 48, 3)], gs.intr, gs.viewmat)
+    with pytest.raises(native.FmError):
+        rast.workspace(bad)
+
+
+def test_autograd_matches_direct(rast):
+    from paper_2604_03092_amd.raster import render
+    sc = scenes.config0()
+    gs = GpuScene.from_scene(sc)
+    sub = {k: v.clone().requires_grad_(True) for k, v in gs.submaps[0].items()}
+    vm = gs.viewmat.clone().requires_grad_(True)
+    _say("autograd")
+    rgb, depth, normal, alpha = render(rast, [sub], gs.views, gs.intr, vm)
+    loss = (rgb * 0.3).sum() + (depth * 0.1).sum() + normal.sum() * 0.05 + alpha.sum() * 0.2
+    loss.backward()
+    out, ws = rast.forward(gs)
+    g = dict(rgb=torch.full_like(out["rgb"], 0.3), depth=torch.full_like(out["depth"], 0.1),
+             normal=torch.full_like(out["normal"], 0.05), alpha=torch.full_like(out["alpha"], 0.2))
+    grads, dvm = gs.zero_grads()
+    rast.backward(gs, ws, out, g, grads, dvm)
+    for k in sub:
+        assert_grad_close(to_np(sub[k].grad), to_np(grads[0][k]), f"autograd.{k}", rel=1e-5)
+    assert_grad_close(to_np(vm.grad), to_np(dvm), "autograd.viewmat", rel=1e-5)
