@@ -1,0 +1,250 @@
+#!/usr/bin/env python3
+"""Benchmark of the MI355X 2DGS surfel rasterizer: forward + L1 render loss +
+backward, in Mpixel/s and views/s, batched fused vs per-view plain.
+
+Workload (default): 16 keyframes at 640x480 of the 300k-surfel scene
+(config-1 laws: centres in [-3,3]^2 x [1,8], log-uniform tangent scales in
+[0.01, 0.1], random rotations, sigmoid(N(0,1)) opacity, uniform colour),
+poses along a smooth random trajectory, L1 RGB + 0.1 L1 depth against
+seeded random targets.  One step = one pass of the whole hot path over the
+batch: projection, depth sort, binning, tile sort, fused forward + loss +
+backward blend, backward projection, gradients accumulated into the shared
+surfel tensors and the 16 view matrices (zeroed at the start of each step).
+
+  batched fused : one hipGraph replay of fm_fwd_bwd_l1 over all 16 views
+  per-view plain: for each view fm_forward -> torch L1 gradient -> fm_backward
+
+Prints one JSON line (rank 0) as the last line of stdout.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+METRIC = "fwd+bwd Mpixel/s and views/s, batched fused vs per-view plain, 640x480"
+# VALU lane-operations per useful (pixel, surfel) evaluation of forward +
+# backward; transcendental and reciprocal instructions count 4 (quarter rate).
+OPS_PER_USEFUL = 143
+# gfx950: 256 CUs x 64 FP32 lanes x 2.4 GHz, one non-packed VALU op per lane per clock
+ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def make_workload(name):
+    from paper_2604_03092_amd import scenes
+    return scenes.make(name)
+
+
+def cpu_baseline(scene, threads):
+    """FP64 oracle (as it stands) on a bounded sample: view 0 of the batch,
+    forward + L1 loss + backward."""
+    import oracle
+    from paper_2604_03092_amd import scenes as S
+    v = 0
+    w, h, s = scene.views[v]
+    one = S.Scene("sample", scene.submaps, [scene.views[v]], scene.intr[v:v + 1], scene.viewmat[v:v + 1],
+                  scene.target_rgb[:, :w * h], scene.target_depth[:w * h] if scene.target_depth is not None
+                  else None, scene.w_rgb, scene.w_depth)
+    oracle.lib()
+    t0 = time.perf_counter()
+    out = oracle.render_scene(one, n_threads=threads)
+    _, g = oracle.l1_loss(one, out)
+    oracle.backward_scene(one, g, n_threads=threads)
+    dt = time.perf_counter() - t0
+    return dict(value=round(w * h / dt / 1e6, 6), unit="Mpixel/s", cores=threads, kind="oracle",
+                sample=f"view 0 of {scene.n_views} ({w}x{h}, {scene.submaps[s]['opacity'].shape[0]} surfels): "
+                       f"FP64 oracle forward + L1 loss + backward, {dt:.2f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="headline")
+    ap.add_argument("--tile", default="16x16")
+    ap.add_argument("--no-graph", action="store_true", help="time eager calls instead of a graph replay")
+    ap.add_argument("--no-plain", action="store_true", help="skip the per-view plain comparison")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-threads", type=int, default=0)
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (views or submaps would shard "
+              "across GPUs with one gradient all-reduce, see the design notes); run with --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2604_03092_amd.raster import GpuScene, Rasterizer
+
+    log(f"workload {args.workload}")
+    scene = make_workload(args.workload)
+    gs = GpuScene.from_scene(scene)
+    rast = Rasterizer()
+    tw, th = (int(x) for x in args.tile.split("x"))
+    params = rast.params(tile=(tw, th))
+
+    # size the pair buffer from one eager forward (not timed)
+    out, ws = rast.forward(gs, params)
+    torch.cuda.synchronize()
+    _, n_pairs, _ = rast.query(gs, ws)
+    ws = rast.workspace(gs, params, max_pairs=int(n_pairs * 1.1) + 4096)
+    out = rast.new_outputs(gs)
+    grads, dvm = gs.zero_grads()
+    loss = torch.zeros(1, device="cuda")
+    log(f"{gs.n_views} views, {gs.npx} px, {n_pairs} pairs, workspace {ws.nbytes / 2**20:.0f} MiB")
+
+    def step():
+        for g in grads:
+            for t in g.values():
+                t.zero_()
+        dvm.zero_()
+        loss.zero_()
+        rast.fwd_bwd_l1(gs, ws, out, grads, dvm, loss)
+
+    step()
+    torch.cuda.synchronize()
+    st, n_pairs, req = rast.query(gs, ws)
+    assert st == 0, "pair capacity overflow"
+
+    # per-phase timing of the eager fused path (HIP events between phases on
+    # the call's stream); the blend kernel is the dominant one
+    rast.set_timing(True)
+    acc = None
+    n_t = max(3, min(args.steps, 10))
+    for _ in range(n_t):
+        step()
+        ph = rast.phase_times()
+        acc = ph if acc is None else {k: acc[k] + ph[k] for k in acc}
+    rast.set_timing(False)
+    phases = {k: v / n_t for k, v in acc.items()}
+    tf, nc = rast.pixel_state(gs, ws)
+    useful = int(nc.astype(np.int64).sum())
+    log(f"phases (ms): " + ", ".join(f"{k}={v:.3f}" for k, v in phases.items()))
+
+    graph = None
+    if not args.no_graph:
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            for _ in range(2):
+                step()
+        torch.cuda.current_stream().wait_stream(s)
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            step()
+        torch.cuda.synchronize()
+
+    run = graph.replay if graph is not None else step
+    for _ in range(args.warmup):
+        run()
+    torch.cuda.synchronize()
+    log(f"timing {args.steps} fused steps ({'graph' if graph else 'eager'})")
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        run()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_step = dt / args.steps * 1e3
+    mpx = gs.npx * args.steps / dt / 1e6
+    views_s = gs.n_views * args.steps / dt
+    log(f"fused: {ms_step:.3f} ms/step, {mpx:.1f} Mpixel/s, {views_s:.1f} views/s")
+
+    plain = None
+    if not args.no_plain:
+        singles = []
+        for v in range(gs.n_views):
+            gv = GpuScene(gs.submaps, [gs.views[v]], gs.intr[v:v + 1].contiguous(), gs.viewmat[v:v + 1].contiguous())
+            o = gs.pixel_offsets[v]
+            npx = gv.npx
+            tr = gs.target_rgb[:, o:o + npx].contiguous()
+            td = gs.target_depth[o:o + npx].contiguous() if gs.target_depth is not None else None
+            o1, w1 = rast.forward(gv, params)
+            w1 = rast.workspace(gv, params, max_pairs=int(w1.n_pairs * 1.1) + 4096)
+            d1 = torch.zeros(1, 12, device="cuda")
+            singles.append((gv, w1, rast.new_outputs(gv), tr, td, npx, d1))
+
+        def plain_step():
+            for g in grads:
+                for t in g.values():
+                    t.zero_()
+            for (gv, w1, o1, tr, td, npx, d1) in singles:
+                rast.forward_into(gv, w1, o1)
+                k = gs.w_rgb / (3.0 * npx)
+                g = dict(rgb=torch.sign(o1["rgb"] - tr) * k)
+                if td is not None and gs.w_depth != 0.0:
+                    g["depth"] = torch.sign(o1["depth"] - td) * (gs.w_depth / npx)
+                d1.zero_()
+                rast.backward(gv, w1, o1, g, grads, d1)
+
+        for _ in range(max(1, args.warmup)):
+            plain_step()
+        torch.cuda.synchronize()
+        for (gv, w1, *_rest) in singles:
+            assert rast.query(gv, w1)[0] == 0
+        k_plain = max(3, args.steps // 4)
+        t0 = time.perf_counter()
+        for _ in range(k_plain):
+            plain_step()
+        torch.cuda.synchronize()
+        dtp = time.perf_counter() - t0
+        plain = dict(ms_per_step=round(dtp / k_plain * 1e3, 4), mpixel_s=round(gs.npx * k_plain / dtp / 1e6, 3),
+                     views_s=round(gs.n_views * k_plain / dtp, 3), steps=k_plain)
+        log(f"plain: {plain['ms_per_step']:.3f} ms/step, {plain['mpixel_s']:.1f} Mpixel/s")
+
+    blend_s = phases["blend"] * 1e-3
+    achieved = useful * OPS_PER_USEFUL / blend_s / 1e12 if blend_s > 0 else 0.0
+    roofline = dict(bound="alu", achieved=round(achieved, 3), peak=round(ALU_PEAK_TOPS, 3), unit="TOP/s",
+                    frac=round(achieved / ALU_PEAK_TOPS, 4), traffic=None,
+                    kernel="k_render_fused", kernel_ms=round(phases["blend"], 4),
+                    useful_evals=useful, ops_per_useful=OPS_PER_USEFUL)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        threads = args.cpu_threads or min(16, os.cpu_count() or 1)
+        log(f"cpu baseline on {threads} threads")
+        cpu = cpu_baseline(scene, threads)
+
+    res = {
+        "metric": METRIC,
+        "value": round(mpx, 3),
+        "unit": "Mpixel/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": scene.name, "views": gs.n_views, "pixels_per_step": gs.npx,
+                   "surfels": int(sum(sm["opacity"].shape[0] for sm in scene.submaps)),
+                   "tile": f"{tw}x{th}", "mode": "hipgraph" if graph is not None else "eager",
+                   "pairs": n_pairs},
+        "views_per_s": round(views_s, 3),
+        "plain": plain,
+        "speedup_vs_plain": round(plain["ms_per_step"] / ms_step, 3) if plain else None,
+        "phases_ms": {k: round(v, 4) for k, v in phases.items()},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -121,8 +121,8 @@ typedef struct {
     float rho_max;     /* 3: support radius in units of the tangent scales        */
     float near_plane;  /* 0.2: cull surfels with centre depth <= near_plane       */
     float bg[3];       /* background colour added with weight T_final             */
-    int32_t tile_w;    /* tile width in pixels: 8, 16 or 32                       */
-    int32_t tile_h;    /* tile height in pixels: 8, 16 or 32 (tile_w*tile_h<=1024)*/
+    int32_t tile_w;    /* tile shape in pixels: 8x8, 16x8, 16x16 or 32x8; 0x0 uses  */
+    int32_t tile_h;    /* the context's autotuned choice for the batch, else 16x16 */
     int32_t reserved[2];
 } fm_raster_params;
 
@@ -216,6 +216,23 @@ fm_status fm_debug_pairs(fm_ctx *ctx, const fm_batch *batch, const fm_raster_par
                          const void *workspace, int64_t max_pairs, uint32_t *tile,
                          uint32_t *surfel, uint32_t *view, int64_t cap, int64_t *n_pairs,
                          uint32_t *tile_start, uint32_t *tile_end, int64_t n_tiles);
+
+/* Test hook: copies the per-pixel final transmittance and number of
+ * composited surfels of the last forward into HOST buffers of npx entries
+ * (npx >= total pixels of the batch).  Synchronous. */
+fm_status fm_debug_pixel_state(fm_ctx *ctx, const fm_batch *batch, const fm_raster_params *params,
+                               const void *workspace, int64_t max_pairs, float *t_final,
+                               uint32_t *n_contrib, int64_t npx);
+
+/* Benchmark hook.  With timing enabled, fm_forward / fm_backward /
+ * fm_fwd_bwd_l1 record HIP events between their phases on the call's stream
+ * (skipped while the stream is being captured).  fm_phase_times waits for the
+ * last call's events and writes per-phase milliseconds into ms[0..5]:
+ * 0 projection, 1 binning (depth sort, emission, tile sort, ranges),
+ * 2 zeroing of gradient slots, 3 blend kernel (forward, backward or fused),
+ * 4 loss reduction, 5 backward projection and pose reduction.  n >= 6. */
+fm_status fm_set_timing(fm_ctx *ctx, int enable);
+fm_status fm_phase_times(fm_ctx *ctx, float *ms, int n);
 
 /* Total tile count of a batch for the given tile shape. */
 fm_status fm_tile_count(const fm_batch *batch, const fm_raster_params *params, int64_t *n_tiles);

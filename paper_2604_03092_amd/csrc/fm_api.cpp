@@ -27,6 +27,11 @@ struct fm_ctx {
     int n_cu = 0;
     std::string last_error;
     std::map<std::string, std::pair<int, int>> tuned;  // batch signature -> tile shape
+    // optional phase timing (benchmarks): events recorded between phases
+    bool timing = false;
+    hipEvent_t ev[8] = {};
+    int marks = 0;
+    int ev_phase[8] = {};
 };
 
 namespace {
@@ -217,6 +222,7 @@ fm_status build(fm_ctx *ctx, const fm_batch *b, const fm_raster_params *prm, int
     p.o_tend = take(4 * (size_t)T);
     p.o_tfinal = take(4 * (size_t)NPX);
     p.o_nlast = take(4 * (size_t)NPX);
+    p.o_ncount = take(4 * (size_t)NPX);
     p.o_grad = take(64 * (size_t)E);
     p.o_pose = take(48 * (size_t)p.V * p.a7_max_blocks);
     p.o_loss = take(4 * (size_t)T);
@@ -262,6 +268,21 @@ fm_status use_device(fm_ctx *ctx) {
     return FM_OK;
 }
 
+// Phase marks: phase ids as documented for fm_phase_times.
+enum { PH_PRE = 0, PH_BIN = 1, PH_ZERO = 2, PH_BLEND = 3, PH_LOSS = 4, PH_BWDPROJ = 5, PH_N = 6 };
+
+void mark_begin(fm_ctx *ctx, hipStream_t st) {
+    ctx->marks = 0;
+    if (!ctx->timing) return;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
+    if (hipEventRecord(ctx->ev[0], st) == hipSuccess) ctx->marks = 1;
+}
+void mark(fm_ctx *ctx, hipStream_t st, int phase) {
+    if (!ctx->timing || ctx->marks == 0 || ctx->marks >= 8) return;
+    if (hipEventRecord(ctx->ev[ctx->marks], st) == hipSuccess) ctx->ev_phase[ctx->marks++] = phase;
+}
+
 #define FM_TRY_HIP(expr, where)                      \
     do {                                             \
         hipError_t _e = (expr);                      \
@@ -271,10 +292,14 @@ fm_status use_device(fm_ctx *ctx) {
 fm_status run_forward(fm_ctx *ctx, Built &bt, const fm_raster_params *prm, const fm_batch *b, void *ws,
                       const fm_outputs &out, hipStream_t st) {
     const fm::KParams kp = kparams(prm, bt.plan);
+    mark_begin(ctx, st);
     FM_TRY_HIP(fm::launch_setup(bt.plan, ws, bt.views.data(), bt.subs.data(), bt.vlist.data(), st), "setup");
     FM_TRY_HIP(fm::launch_preprocess(bt.plan, ws, kp, b->intr, b->viewmat, st), "preprocess");
+    mark(ctx, st, PH_PRE);
     FM_TRY_HIP(fm::launch_binning(bt.plan, ws, kp, st), "binning");
+    mark(ctx, st, PH_BIN);
     FM_TRY_HIP(fm::launch_render_fwd(bt.plan, ws, kp, out, st), "render_fwd");
+    mark(ctx, st, PH_BLEND);
     return FM_OK;
 }
 
@@ -288,12 +313,20 @@ fm_status run_fused(fm_ctx *ctx, Built &bt, const fm_raster_params *prm, const f
     la.mask = ls->mask;
     la.w_rgb = ls->w_rgb;
     la.w_depth = ls->w_depth;
+    mark_begin(ctx, st);
     FM_TRY_HIP(fm::launch_setup(bt.plan, ws, bt.views.data(), bt.subs.data(), bt.vlist.data(), st), "setup");
     FM_TRY_HIP(fm::launch_preprocess(bt.plan, ws, kp, b->intr, b->viewmat, st), "preprocess");
+    mark(ctx, st, PH_PRE);
     FM_TRY_HIP(fm::launch_binning(bt.plan, ws, kp, st), "binning");
+    mark(ctx, st, PH_BIN);
     FM_TRY_HIP(fm::launch_zero_grad(bt.plan, ws, st), "zero_grad");
-    FM_TRY_HIP(fm::launch_render_fused(bt.plan, ws, kp, la, out, loss, st), "render_fused");
+    mark(ctx, st, PH_ZERO);
+    FM_TRY_HIP(fm::launch_render_fused(bt.plan, ws, kp, la, out, st), "render_fused");
+    mark(ctx, st, PH_BLEND);
+    FM_TRY_HIP(fm::launch_loss_reduce(bt.plan, ws, loss, st), "loss_reduce");
+    mark(ctx, st, PH_LOSS);
     FM_TRY_HIP(fm::launch_preprocess_bwd(bt.plan, ws, b->intr, b->viewmat, dL_dviewmat, st), "preprocess_bwd");
+    mark(ctx, st, PH_BWDPROJ);
     return FM_OK;
 }
 
@@ -367,7 +400,55 @@ fm_status fm_create(fm_ctx **out, int device) {
     return FM_OK;
 }
 
-void fm_destroy(fm_ctx *ctx) { delete ctx; }
+void fm_destroy(fm_ctx *ctx) {
+    if (!ctx) return;
+    for (auto &e : ctx->ev)
+        if (e) (void)hipEventDestroy(e);
+    delete ctx;
+}
+
+fm_status fm_set_timing(fm_ctx *ctx, int enable) {
+    if (!ctx) return FM_ERR_INVALID_ARG;
+    if (enable && !ctx->ev[0]) {
+        fm_status s = use_device(ctx);
+        if (s != FM_OK) return s;
+        for (auto &e : ctx->ev) FM_TRY_HIP(hipEventCreate(&e), "hipEventCreate");
+    }
+    ctx->timing = enable != 0;
+    ctx->marks = 0;
+    return FM_OK;
+}
+
+fm_status fm_phase_times(fm_ctx *ctx, float *ms, int n) {
+    if (!ctx || !ms || n < 6) return FM_ERR_INVALID_ARG;
+    for (int k = 0; k < n; ++k) ms[k] = 0.f;
+    if (ctx->marks < 2) return fail(ctx, FM_ERR_INVALID_ARG, "no timed call recorded (timing off or captured)");
+    FM_TRY_HIP(hipEventSynchronize(ctx->ev[ctx->marks - 1]), "hipEventSynchronize");
+    for (int k = 1; k < ctx->marks; ++k) {
+        float t = 0.f;
+        FM_TRY_HIP(hipEventElapsedTime(&t, ctx->ev[k - 1], ctx->ev[k]), "hipEventElapsedTime");
+        ms[ctx->ev_phase[k]] += t;
+    }
+    return FM_OK;
+}
+
+fm_status fm_debug_pixel_state(fm_ctx *ctx, const fm_batch *b, const fm_raster_params *prm, const void *ws,
+                               int64_t max_pairs, float *t_final, uint32_t *n_contrib, int64_t npx) {
+    if (!ctx) return FM_ERR_INVALID_ARG;
+    Built bt;
+    fm_status s = build(ctx, b, prm, max_pairs, nullptr, false, bt);
+    if (s != FM_OK) return s;
+    if (!ws) return fail(ctx, FM_ERR_INVALID_ARG, "workspace must not be NULL");
+    if (npx < bt.plan.NPX) return fail(ctx, FM_ERR_INVALID_ARG, "pixel buffers smaller than the batch");
+    s = use_device(ctx);
+    if (s != FM_OK) return s;
+    const char *w = static_cast<const char *>(ws);
+    if (t_final)
+        FM_TRY_HIP(hipMemcpy(t_final, w + bt.plan.o_tfinal, 4 * bt.plan.NPX, hipMemcpyDeviceToHost), "hipMemcpy");
+    if (n_contrib)
+        FM_TRY_HIP(hipMemcpy(n_contrib, w + bt.plan.o_ncount, 4 * bt.plan.NPX, hipMemcpyDeviceToHost), "hipMemcpy");
+    return FM_OK;
+}
 
 const char *fm_status_string(fm_status s) {
     switch (s) {
@@ -444,10 +525,14 @@ fm_status fm_backward(fm_ctx *ctx, const fm_batch *b, const fm_raster_params *pr
     if (s != FM_OK) return s;
     hipStream_t st = (hipStream_t)stream;
     const fm::KParams kp = kparams(prm, bt.plan);
+    mark_begin(ctx, st);
     FM_TRY_HIP(fm::launch_setup(bt.plan, ws, bt.views.data(), bt.subs.data(), bt.vlist.data(), st), "setup");
     FM_TRY_HIP(fm::launch_zero_grad(bt.plan, ws, st), "zero_grad");
+    mark(ctx, st, PH_ZERO);
     FM_TRY_HIP(fm::launch_render_bwd(bt.plan, ws, kp, out, g, st), "render_bwd");
+    mark(ctx, st, PH_BLEND);
     FM_TRY_HIP(fm::launch_preprocess_bwd(bt.plan, ws, b->intr, b->viewmat, dL_dviewmat, st), "preprocess_bwd");
+    mark(ctx, st, PH_BWDPROJ);
     return FM_OK;
 }
 

@@ -129,12 +129,13 @@ __device__ __forceinline__ bool bbox_miss(const Rec *sr, int wx0, int wy0) {
 template <int TW, int TH>
 __device__ __forceinline__ void tile_forward(const PixelCtx &c, const uint32_t *__restrict__ pval,
                                              const Rec *__restrict__ rec, const KParams &kp, Rec *srec,
-                                             float acc[8], float &T, uint32_t &nlast) {
+                                             float acc[8], float &T, uint32_t &nlast, uint32_t &ncount) {
     using Gm = Geo<TW, TH>;
     const float rho2 = kp.rho_max * kp.rho_max;
     bool done = !c.inside;
     T = 1.f;
     nlast = 0;
+    ncount = 0;
 #pragma unroll
     for (int k = 0; k < 8; ++k) acc[k] = 0.f;
     for (uint32_t base = c.start; base < c.end; base += Gm::NT) {
@@ -166,6 +167,7 @@ __device__ __forceinline__ void tile_forward(const PixelCtx &c, const uint32_t *
                         acc[7] = acc[7] + wgt;
                         T = test;
                         nlast = base - c.start + (uint32_t)j + 1u;
+                        ++ncount;
                     }
                 }
             }
@@ -297,13 +299,14 @@ __global__ __launch_bounds__(TW *TH) void k_render_fwd(const ViewDesc *__restric
                                                         const uint32_t *__restrict__ pval,
                                                         const Rec *__restrict__ rec, KParams kp, int64_t NPX,
                                                         fm_outputs out, float *__restrict__ tfinal,
-                                                        uint32_t *__restrict__ nlast_out) {
+                                                        uint32_t *__restrict__ nlast_out,
+                                                        uint32_t *__restrict__ ncount_out) {
     using Gm = Geo<TW, TH>;
     __shared__ Rec srec[Gm::NT];
     const PixelCtx c = pixel_ctx<TW, TH>(views, V, ts, te);
     float acc[8], T;
-    uint32_t nl;
-    tile_forward<TW, TH>(c, pval, rec, kp, srec, acc, T, nl);
+    uint32_t nl, nc;
+    tile_forward<TW, TH>(c, pval, rec, kp, srec, acc, T, nl, nc);
     if (c.inside) {
         out.rgb[c.pix] = acc[0] + T * kp.bg[0];
         out.rgb[NPX + c.pix] = acc[1] + T * kp.bg[1];
@@ -315,6 +318,7 @@ __global__ __launch_bounds__(TW *TH) void k_render_fwd(const ViewDesc *__restric
         out.alpha[c.pix] = acc[7];
         tfinal[c.pix] = T;
         nlast_out[c.pix] = nl;
+        ncount_out[c.pix] = nc;
     }
 }
 
@@ -365,7 +369,8 @@ __global__ __launch_bounds__(TW *TH) void k_render_fused(const ViewDesc *__restr
                                                           const uint32_t *__restrict__ pval,
                                                           const Rec *__restrict__ rec, KParams kp, int64_t NPX,
                                                           fm_outputs out, LossArgs la, float *__restrict__ tfinal,
-                                                          uint32_t *__restrict__ nlast_out, float *__restrict__ grad,
+                                                          uint32_t *__restrict__ nlast_out,
+                                                          uint32_t *__restrict__ ncount_out, float *__restrict__ grad,
                                                           float *__restrict__ loss_part) {
     using Gm = Geo<TW, TH>;
     __shared__ Rec srec[Gm::NT];
@@ -376,8 +381,8 @@ __global__ __launch_bounds__(TW *TH) void k_render_fused(const ViewDesc *__restr
     __shared__ float sred[Gm::NW];
     const PixelCtx c = pixel_ctx<TW, TH>(views, V, ts, te);
     float acc[8], T;
-    uint32_t nl;
-    tile_forward<TW, TH>(c, pval, rec, kp, srec, acc, T, nl);
+    uint32_t nl, nc;
+    tile_forward<TW, TH>(c, pval, rec, kp, srec, acc, T, nl, nc);
     float g[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     float S = 0.f, l = 0.f;
     if (c.inside) {
@@ -393,6 +398,7 @@ __global__ __launch_bounds__(TW *TH) void k_render_fused(const ViewDesc *__restr
         out.alpha[q] = acc[7];
         tfinal[q] = T;
         nlast_out[q] = nl;
+        ncount_out[q] = nc;
         const bool m = la.mask ? (la.mask[q] != 0) : true;
         if (m) {
             const float npx = (float)c.W * (float)c.H;
@@ -445,7 +451,7 @@ hipError_t fwd_t(const Plan &p, void *ws, const KParams &kp, const fm_outputs &o
     hipLaunchKernelGGL((k_render_fwd<TW, TH>), dim3((unsigned)p.T), dim3(TW * TH), 0, st,
                        at<ViewDesc>(ws, p.o_views), p.V, at<uint32_t>(ws, p.o_tstart),
                        at<uint32_t>(ws, p.o_tend), pval, at<Rec>(ws, p.o_rec), kp, p.NPX, out,
-                       at<float>(ws, p.o_tfinal), at<uint32_t>(ws, p.o_nlast));
+                       at<float>(ws, p.o_tfinal), at<uint32_t>(ws, p.o_nlast), at<uint32_t>(ws, p.o_ncount));
     return hipGetLastError();
 }
 
@@ -462,14 +468,13 @@ hipError_t bwd_t(const Plan &p, void *ws, const KParams &kp, const fm_outputs &o
 
 template <int TW, int TH>
 hipError_t fused_t(const Plan &p, void *ws, const KParams &kp, const LossArgs &la, const fm_outputs &out,
-                   float *loss, hipStream_t st) {
+                   hipStream_t st) {
     const uint32_t *pval = at<uint32_t>(ws, p.pairs_in_alt ? p.o_pval2 : p.o_pval);
     hipLaunchKernelGGL((k_render_fused<TW, TH>), dim3((unsigned)p.T), dim3(TW * TH), 0, st,
                        at<ViewDesc>(ws, p.o_views), p.V, at<uint32_t>(ws, p.o_tstart),
                        at<uint32_t>(ws, p.o_tend), pval, at<Rec>(ws, p.o_rec), kp, p.NPX, out, la,
-                       at<float>(ws, p.o_tfinal), at<uint32_t>(ws, p.o_nlast), at<float>(ws, p.o_grad),
-                       at<float>(ws, p.o_loss));
-    if (loss) hipLaunchKernelGGL(k_loss_reduce, dim3(1), dim3(1024), 0, st, at<float>(ws, p.o_loss), p.T, loss);
+                       at<float>(ws, p.o_tfinal), at<uint32_t>(ws, p.o_nlast), at<uint32_t>(ws, p.o_ncount),
+                       at<float>(ws, p.o_grad), at<float>(ws, p.o_loss));
     return hipGetLastError();
 }
 
@@ -502,9 +507,15 @@ hipError_t launch_render_bwd(const Plan &p, void *ws, const KParams &kp, const f
 }
 
 hipError_t launch_render_fused(const Plan &p, void *ws, const KParams &kp, const LossArgs &la,
-                               const fm_outputs &out, float *loss, hipStream_t st) {
+                               const fm_outputs &out, hipStream_t st) {
     if (p.T == 0) return hipSuccess;
-    FM_DISPATCH(fused_t, p, ws, kp, la, out, loss, st);
+    FM_DISPATCH(fused_t, p, ws, kp, la, out, st);
+}
+
+hipError_t launch_loss_reduce(const Plan &p, void *ws, float *loss, hipStream_t st) {
+    if (p.T == 0 || !loss) return hipSuccess;
+    hipLaunchKernelGGL(k_loss_reduce, dim3(1), dim3(1024), 0, st, at<float>(ws, p.o_loss), p.T, loss);
+    return hipGetLastError();
 }
 
 }  // namespace fm

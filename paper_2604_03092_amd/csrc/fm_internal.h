@@ -99,7 +99,7 @@ struct Plan {
     int a7_max_blocks = 0;  // max blocks of one submap
     size_t o_views = 0, o_subs = 0, o_vlist = 0, o_status = 0, o_rec = 0, o_key = 0, o_cnt = 0,
            o_key2 = 0, o_val = 0, o_val2 = 0, o_scan = 0, o_pkey = 0, o_pval = 0, o_pkey2 = 0,
-           o_pval2 = 0, o_hist = 0, o_tstart = 0, o_tend = 0, o_tfinal = 0, o_nlast = 0, o_grad = 0,
+           o_pval2 = 0, o_hist = 0, o_tstart = 0, o_tend = 0, o_tfinal = 0, o_nlast = 0, o_ncount = 0, o_grad = 0,
            o_pose = 0, o_loss = 0, o_tilemax = 0;
     size_t bytes = 0;
     bool pairs_in_alt = false;  // final sorted pairs live in the *2 buffers
@@ -138,7 +138,8 @@ hipError_t launch_render_fwd(const Plan &p, void *ws, const KParams &kp, const f
 hipError_t launch_render_bwd(const Plan &p, void *ws, const KParams &kp, const fm_outputs &out,
                              const fm_grad_outputs &g, hipStream_t st);
 hipError_t launch_render_fused(const Plan &p, void *ws, const KParams &kp, const LossArgs &la,
-                               const fm_outputs &out, float *loss, hipStream_t st);
+                               const fm_outputs &out, hipStream_t st);
+hipError_t launch_loss_reduce(const Plan &p, void *ws, float *loss, hipStream_t st);
 hipError_t launch_zero_grad(const Plan &p, void *ws, hipStream_t st);
 hipError_t launch_preprocess_bwd(const Plan &p, void *ws, const float *intr, const float *viewmat,
                                  float *dL_dviewmat, hipStream_t st);

@@ -81,6 +81,10 @@ SIGNATURES = {
     "fm_debug_pairs": (c_int32, [c_void_p, P(FmBatch), P(FmRasterParams), c_void_p, c_int64, c_void_p,
                                  c_void_p, c_void_p, c_int64, P(c_int64), c_void_p, c_void_p, c_int64]),
     "fm_tile_count": (c_int32, [P(FmBatch), P(FmRasterParams), P(c_int64)]),
+    "fm_debug_pixel_state": (c_int32, [c_void_p, P(FmBatch), P(FmRasterParams), c_void_p, c_int64, c_void_p,
+                                       c_void_p, c_int64]),
+    "fm_set_timing": (c_int32, [c_void_p, c_int32]),
+    "fm_phase_times": (c_int32, [c_void_p, P(c_float), c_int32]),
     "fm_autotune": (c_int32, [c_void_p, P(FmBatch), P(FmRasterParams), P(FmL1Loss), FmOutputs, c_void_p,
                               P(FmSurfelGrads), c_void_p, c_void_p, ctypes.c_size_t, c_int64, ctypes.c_char_p,
                               P(FmRasterParams), c_void_p]),

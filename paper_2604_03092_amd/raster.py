@@ -172,7 +172,8 @@ class Rasterizer:
     def workspace(self, gs, params=None, max_pairs=None):
         params = params or self.params()
         if max_pairs is None:
-            ent = sum(int(gs.submaps[s]["opacity"].shape[-1]) for (_, _, s) in gs.views)
+            ent = sum(int(gs.submaps[s]["opacity"].shape[-1]) for (_, _, s) in gs.views
+                      if 0 <= s < len(gs.submaps))
             max_pairs = max(1 << 16, 4 * ent)
         nbytes = self.workspace_size(gs, params, max_pairs)
         buf = torch.empty(nbytes, dtype=torch.uint8, device=gs.intr.device)
@@ -251,6 +252,28 @@ class Rasterizer:
                                         cache_path.encode() if cache_path else None, ctypes.byref(chosen),
                                         _stream(None)))
         return chosen
+
+    def pixel_state(self, gs, ws):
+        """Per-pixel final transmittance and number of composited surfels of
+        the last forward (numpy, synchronous)."""
+        import numpy as np
+        tf = np.zeros(gs.npx, np.float32)
+        nc = np.zeros(gs.npx, np.uint32)
+        self.check(self.lib.fm_debug_pixel_state(self.ctx, ctypes.byref(gs.batch()), ctypes.byref(ws.params),
+                                                 _ptr(ws.buf), ws.max_pairs, tf.ctypes.data, nc.ctypes.data,
+                                                 gs.npx))
+        return tf, nc
+
+    def set_timing(self, on=True):
+        self.check(self.lib.fm_set_timing(self.ctx, 1 if on else 0))
+
+    PHASES = ("projection", "binning", "zero_grad", "blend", "loss_reduce", "backward_projection")
+
+    def phase_times(self):
+        """Milliseconds per phase of the last timed call."""
+        ms = (ctypes.c_float * 6)()
+        self.check(self.lib.fm_phase_times(self.ctx, ms, 6))
+        return dict(zip(self.PHASES, [float(x) for x in ms]))
 
     def debug_pairs(self, gs, ws):
         """Sorted pair list of the last forward: (tile, surfel, view, tile_start, tile_end) as numpy."""
