@@ -225,7 +225,8 @@ fm_status build(fm_ctx *ctx, const fm_batch *b, const fm_raster_params *prm, int
     p.o_ncount = take(4 * (size_t)NPX);
     p.o_grad = take(64 * (size_t)E);
     p.o_pose = take(48 * (size_t)p.V * p.a7_max_blocks);
-    p.o_loss = take(4 * (size_t)T);
+    p.o_loss = take(4 * (size_t)T * 16);
+    p.o_tot = take(4 * (size_t)fm::kRadix * fm::kMaxPasses);
     p.bytes = o;
     return FM_OK;
 }
@@ -294,7 +295,7 @@ fm_status run_forward(fm_ctx *ctx, Built &bt, const fm_raster_params *prm, const
     const fm::KParams kp = kparams(prm, bt.plan);
     mark_begin(ctx, st);
     FM_TRY_HIP(fm::launch_setup(bt.plan, ws, bt.views.data(), bt.subs.data(), bt.vlist.data(), st), "setup");
-    FM_TRY_HIP(fm::launch_preprocess(bt.plan, ws, kp, b->intr, b->viewmat, st), "preprocess");
+    FM_TRY_HIP(fm::launch_preprocess(bt.plan, ws, kp, b->intr, b->viewmat, false, st), "preprocess");
     mark(ctx, st, PH_PRE);
     FM_TRY_HIP(fm::launch_binning(bt.plan, ws, kp, st), "binning");
     mark(ctx, st, PH_BIN);
@@ -315,12 +316,10 @@ fm_status run_fused(fm_ctx *ctx, Built &bt, const fm_raster_params *prm, const f
     la.w_depth = ls->w_depth;
     mark_begin(ctx, st);
     FM_TRY_HIP(fm::launch_setup(bt.plan, ws, bt.views.data(), bt.subs.data(), bt.vlist.data(), st), "setup");
-    FM_TRY_HIP(fm::launch_preprocess(bt.plan, ws, kp, b->intr, b->viewmat, st), "preprocess");
+    FM_TRY_HIP(fm::launch_preprocess(bt.plan, ws, kp, b->intr, b->viewmat, true, st), "preprocess");
     mark(ctx, st, PH_PRE);
     FM_TRY_HIP(fm::launch_binning(bt.plan, ws, kp, st), "binning");
     mark(ctx, st, PH_BIN);
-    FM_TRY_HIP(fm::launch_zero_grad(bt.plan, ws, st), "zero_grad");
-    mark(ctx, st, PH_ZERO);
     FM_TRY_HIP(fm::launch_render_fused(bt.plan, ws, kp, la, out, st), "render_fused");
     mark(ctx, st, PH_BLEND);
     FM_TRY_HIP(fm::launch_loss_reduce(bt.plan, ws, loss, st), "loss_reduce");

@@ -27,6 +27,7 @@ constexpr int kRadix = 1 << kRadixBits;
 constexpr int kSortBlock = 256;    // threads per radix-sort block
 constexpr int kScanChunk = 2048;   // entries per block of the count scan
 constexpr int kMaxSortGrid = 2048;
+constexpr int kMaxPasses = 8;      // radix passes per binning (4 depth + up to 4 tile)
 
 // Per-view descriptor, written into the workspace at the start of each call.
 struct ViewDesc {
@@ -100,7 +101,7 @@ struct Plan {
     size_t o_views = 0, o_subs = 0, o_vlist = 0, o_status = 0, o_rec = 0, o_key = 0, o_cnt = 0,
            o_key2 = 0, o_val = 0, o_val2 = 0, o_scan = 0, o_pkey = 0, o_pval = 0, o_pkey2 = 0,
            o_pval2 = 0, o_hist = 0, o_tstart = 0, o_tend = 0, o_tfinal = 0, o_nlast = 0, o_ncount = 0, o_grad = 0,
-           o_pose = 0, o_loss = 0, o_tilemax = 0;
+           o_pose = 0, o_loss = 0, o_tot = 0;
     size_t bytes = 0;
     bool pairs_in_alt = false;  // final sorted pairs live in the *2 buffers
 };
@@ -131,7 +132,7 @@ __device__ inline int view_of_tile(const ViewDesc *v, int V, int64_t x) {
 hipError_t launch_setup(const Plan &p, void *ws, const ViewDesc *views, const SubmapDesc *subs,
                         const int32_t *vlist, hipStream_t st);
 hipError_t launch_preprocess(const Plan &p, void *ws, const KParams &kp, const float *intr,
-                             const float *viewmat, hipStream_t st);
+                             const float *viewmat, bool zero_grad, hipStream_t st);
 hipError_t launch_binning(const Plan &p, void *ws, const KParams &kp, hipStream_t st);
 hipError_t launch_render_fwd(const Plan &p, void *ws, const KParams &kp, const fm_outputs &out,
                              hipStream_t st);

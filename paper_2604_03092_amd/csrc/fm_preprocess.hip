@@ -56,7 +56,7 @@ __global__ __launch_bounds__(256) void k_preprocess(const ViewDesc *__restrict__
                                                      const float *__restrict__ intr,
                                                      const float *__restrict__ viewmat, KParams kp,
                                                      Rec *__restrict__ rec, uint32_t *__restrict__ key,
-                                                     uint32_t *__restrict__ cnt) {
+                                                     uint32_t *__restrict__ cnt, float4 *__restrict__ grad) {
 #pragma clang fp contract(off)
     const int64_t e0 = (int64_t)blockIdx.x * 256;
     const int v = view_of_entry(views, V, e0);
@@ -183,6 +183,13 @@ __global__ __launch_bounds__(256) void k_preprocess(const ViewDesc *__restrict__
     }
     key[e] = out_key;
     cnt[e] = out_cnt;
+    if (grad && out_cnt != 0) {  // the fused path clears the entry's gradient slot here
+        const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+        grad[4 * e] = z;
+        grad[4 * e + 1] = z;
+        grad[4 * e + 2] = z;
+        grad[4 * e + 3] = z;
+    }
 }
 
 // Zero the 16-float gradient slot of every entry that has pairs.
@@ -422,12 +429,12 @@ hipError_t launch_setup(const Plan &p, void *ws, const ViewDesc *views, const Su
 }
 
 hipError_t launch_preprocess(const Plan &p, void *ws, const KParams &kp, const float *intr,
-                             const float *viewmat, hipStream_t st) {
+                             const float *viewmat, bool zero_grad, hipStream_t st) {
     const int blocks = (int)(p.E / 256);
     if (blocks == 0) return hipSuccess;
     hipLaunchKernelGGL(k_preprocess, dim3(blocks), dim3(256), 0, st, at<ViewDesc>(ws, p.o_views), p.V,
                        intr, viewmat, kp, at<Rec>(ws, p.o_rec), at<uint32_t>(ws, p.o_key),
-                       at<uint32_t>(ws, p.o_cnt));
+                       at<uint32_t>(ws, p.o_cnt), zero_grad ? at<float4>(ws, p.o_grad) : nullptr);
     return hipGetLastError();
 }
 

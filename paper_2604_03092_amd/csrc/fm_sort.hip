@@ -31,10 +31,11 @@ __device__ __forceinline__ void chunk_of(uint32_t n, int G, uint32_t &lo, uint32
     if (hi > n) hi = n;
 }
 
-// Per-block digit histogram, written digit-major: hist[d * G + block].
+// Per-block digit histogram, written digit-major: hist[d * G + block]; the
+// digit totals of the whole pass are added into tot[d].
 __global__ __launch_bounds__(256) void k_radix_hist(const uint32_t *__restrict__ keys, const Status *st,
                                                      uint32_t n_host, int shift, uint32_t *__restrict__ hist,
-                                                     int G) {
+                                                     int G, uint32_t *__restrict__ tot) {
     __shared__ uint32_t h[4][kRadix];
     const int w = threadIdx.x >> 6;
 #pragma unroll
@@ -44,31 +45,40 @@ __global__ __launch_bounds__(256) void k_radix_hist(const uint32_t *__restrict__
     chunk_of(count_of(st, n_host), G, lo, hi);
     for (uint32_t i = lo + threadIdx.x; i < hi; i += 256) atomicAdd(&h[w][(keys[i] >> shift) & 0xFFu], 1u);
     __syncthreads();
-    hist[threadIdx.x * G + blockIdx.x] = h[0][threadIdx.x] + h[1][threadIdx.x] + h[2][threadIdx.x] +
-                                         h[3][threadIdx.x];
+    const uint32_t c = h[0][threadIdx.x] + h[1][threadIdx.x] + h[2][threadIdx.x] + h[3][threadIdx.x];
+    hist[threadIdx.x * G + blockIdx.x] = c;
+    if (c) atomicAdd(&tot[threadIdx.x], c);
 }
 
-// Exclusive scan of `count` u32 values in place (one block of 1024 threads).
-__global__ __launch_bounds__(1024) void k_scan_inplace(uint32_t *__restrict__ data, int count) {
-    __shared__ uint32_t part[1024];
-    const int per = (count + 1023) / 1024;
-    const int beg = threadIdx.x * per;
-    const int end = beg + per < count ? beg + per : count;
-    uint32_t s = 0;
-    for (int i = beg; i < end; ++i) s += data[i];
-    part[threadIdx.x] = s;
+// Global scatter offsets: block d turns row d of the histogram into
+// sum_{d' < d} tot[d'] + exclusive prefix over the blocks.
+__global__ __launch_bounds__(256) void k_radix_rowscan(uint32_t *__restrict__ hist, const uint32_t *__restrict__ tot,
+                                                        int G) {
+    __shared__ uint32_t wsum[4];
+    const int d = blockIdx.x;
+    const int w = threadIdx.x >> 6, lane = lane_id();
+    uint32_t t = threadIdx.x < (unsigned)d ? tot[threadIdx.x] : 0u;
+    for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off);
+    if (lane == 0) wsum[w] = t;
     __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        uint32_t v = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0u;
+    uint32_t carry = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    __syncthreads();
+    uint32_t *row = hist + (size_t)d * G;
+    for (int base = 0; base < G; base += 256) {
+        const int b = base + threadIdx.x;
+        const uint32_t c = b < G ? row[b] : 0u;
+        uint32_t x = c;
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(x, off);
+            if (lane >= off) x += y;
+        }
+        if (lane == 63) wsum[w] = x;
         __syncthreads();
-        part[threadIdx.x] += v;
+        uint32_t wb = 0;
+        for (int j = 0; j < w; ++j) wb += wsum[j];
+        if (b < G) row[b] = carry + wb + x - c;
+        carry += wsum[0] + wsum[1] + wsum[2] + wsum[3];
         __syncthreads();
-    }
-    uint32_t run = threadIdx.x ? part[threadIdx.x - 1] : 0u;
-    for (int i = beg; i < end; ++i) {
-        const uint32_t d = data[i];
-        data[i] = run;
-        run += d;
     }
 }
 
@@ -178,57 +188,85 @@ __global__ __launch_bounds__(1024) void k_count_scan(const uint32_t *__restrict_
     }
 }
 
-// Scan within the block and emit each entry's (tile, entry) pairs, in depth
-// order, at its offset.  Pairs beyond the capacity are dropped.
+// Load-balanced emission.  The block scans the tile counts of its
+// kScanChunk depth-sorted entries in LDS, then its threads walk the block's
+// pair range with a unit stride, each finding its entry by binary search over
+// the local offsets, so that consecutive threads write consecutive pairs.
+// Pairs beyond the capacity are dropped.
 __global__ __launch_bounds__(256) void k_emit(const uint32_t *__restrict__ sorted_entry,
                                                const uint32_t *__restrict__ cnt, int64_t E,
                                                const uint64_t *__restrict__ blk_off,
                                                const ViewDesc *__restrict__ views, int V,
                                                const Rec *__restrict__ rec, KParams kp, uint64_t cap,
                                                uint32_t *__restrict__ pkey, uint32_t *__restrict__ pval) {
+    constexpr int PER = kScanChunk / 256;
+    __shared__ uint32_t s_off[kScanChunk];
+    __shared__ uint32_t s_ent[kScanChunk];
+    __shared__ uint32_t s_tb[kScanChunk];
+    __shared__ uint32_t s_nt[kScanChunk];
     __shared__ uint32_t wsum[4];
     const int64_t lo = (int64_t)blockIdx.x * kScanChunk;
-    int64_t hi = lo + kScanChunk;
-    if (hi > E) hi = E;
-    uint64_t run = blk_off[blockIdx.x];
-    const int w = threadIdx.x >> 6;
-    for (int64_t base = lo; base < hi; base += 256) {
-        const int64_t k = base + threadIdx.x;
-        uint32_t e = 0, c = 0;
-        if (k < hi) {
+    const int w = threadIdx.x >> 6, lane = lane_id();
+    for (int i = 0; i < PER; ++i) {
+        const int j = i * 256 + threadIdx.x;
+        const int64_t k = lo + j;
+        uint32_t e = 0, c = 0, tb = 0, nt = 1;
+        if (k < E) {
             e = sorted_entry[k];
             c = cnt[e];
-        }
-        // inclusive scan of c within the wave
-        uint32_t x = c;
-        for (int off = 1; off < 64; off <<= 1) {
-            const uint32_t y = __shfl_up(x, off);
-            if (lane_id() >= off) x += y;
-        }
-        if (lane_id() == 63) wsum[w] = x;
-        __syncthreads();
-        uint32_t wbase = 0;
-        for (int j = 0; j < w; ++j) wbase += wsum[j];
-        const uint32_t tot = wsum[0] + wsum[1] + wsum[2] + wsum[3];
-        const uint64_t off = run + wbase + (x - c);
-        if (c != 0) {
-            const int v = view_of_entry(views, V, e);
-            const ViewDesc &vd = views[v];
-            const Rec &r = rec[e];
-            const int tx0 = r.bb[0] / kp.tile_w, tx1 = r.bb[2] / kp.tile_w;
-            const int ty0 = r.bb[1] / kp.tile_h;
-            const int ntx = tx1 - tx0 + 1;
-            for (uint32_t j = 0; j < c; ++j) {
-                const uint64_t o = off + j;
-                if (o >= cap) break;
-                const int ty = ty0 + (int)(j / (uint32_t)ntx);
-                const int tx = tx0 + (int)(j % (uint32_t)ntx);
-                pkey[o] = (uint32_t)(vd.tile_base + ty * vd.tiles_x + tx);
-                pval[o] = e;
+            if (c != 0) {
+                const int v = view_of_entry(views, V, e);
+                const ViewDesc &vd = views[v];
+                const Rec &r = rec[e];
+                const int tx0 = r.bb[0] / kp.tile_w, tx1 = r.bb[2] / kp.tile_w;
+                const int ty0 = r.bb[1] / kp.tile_h;
+                tb = (uint32_t)(vd.tile_base + ty0 * vd.tiles_x + tx0);
+                nt = (uint32_t)(tx1 - tx0 + 1) | ((uint32_t)vd.tiles_x << 16);
             }
         }
-        run += tot;
-        __syncthreads();
+        s_off[j] = c;
+        s_ent[j] = e;
+        s_tb[j] = tb;
+        s_nt[j] = nt;
+    }
+    __syncthreads();
+    // exclusive scan of the PER consecutive counts owned by each thread
+    uint32_t loc[PER];
+    uint32_t run = 0;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        loc[i] = run;
+        run += s_off[threadIdx.x * PER + i];
+    }
+    uint32_t x = run;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) wsum[w] = x;
+    __syncthreads();
+    uint32_t base = x - run;
+    for (int j = 0; j < w; ++j) base += wsum[j];
+    const uint32_t total = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) s_off[threadIdx.x * PER + i] = base + loc[i];
+    __syncthreads();
+    const uint64_t gbase = blk_off[blockIdx.x];
+    for (uint32_t q = threadIdx.x; q < total; q += 256) {
+        const uint64_t o = gbase + q;
+        if (o >= cap) break;
+        // the entry owning pair q: last j with s_off[j] <= q
+        int a = 0, b = kScanChunk - 1;
+        while (a < b) {
+            const int m = (a + b + 1) >> 1;
+            if (s_off[m] <= q) a = m; else b = m - 1;
+        }
+        const uint32_t r = q - s_off[a];
+        const uint32_t nt = s_nt[a];
+        const uint32_t ntx = nt & 0xFFFFu, tiles_x = nt >> 16;
+        const uint32_t ry = r / ntx, rx = r - ry * ntx;
+        pkey[o] = s_tb[a] + ry * tiles_x + rx;
+        pval[o] = s_ent[a];
     }
 }
 
@@ -247,9 +285,9 @@ __global__ __launch_bounds__(256) void k_tile_ranges(const uint32_t *__restrict_
 }
 
 void radix_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout, const Status *st,
-                uint32_t n_host, int shift, uint32_t *hist, int G, hipStream_t s) {
-    hipLaunchKernelGGL(k_radix_hist, dim3(G), dim3(256), 0, s, kin, st, n_host, shift, hist, G);
-    hipLaunchKernelGGL(k_scan_inplace, dim3(1), dim3(1024), 0, s, hist, kRadix * G);
+                uint32_t n_host, int shift, uint32_t *hist, int G, uint32_t *tot, hipStream_t s) {
+    hipLaunchKernelGGL(k_radix_hist, dim3(G), dim3(256), 0, s, kin, st, n_host, shift, hist, G, tot);
+    hipLaunchKernelGGL(k_radix_rowscan, dim3(kRadix), dim3(256), 0, s, hist, tot, G);
     hipLaunchKernelGGL(k_radix_scatter, dim3(G), dim3(256), 0, s, kin, vin, kout, vout, st, n_host, shift,
                        hist, G);
 }
@@ -261,13 +299,15 @@ hipError_t launch_binning(const Plan &p, void *ws, const KParams &kp, hipStream_
     uint32_t *key = at<uint32_t>(ws, p.o_key), *key2 = at<uint32_t>(ws, p.o_key2);
     uint32_t *val = at<uint32_t>(ws, p.o_val), *val2 = at<uint32_t>(ws, p.o_val2);
     uint32_t *hist = at<uint32_t>(ws, p.o_hist);
+    uint32_t *tot = at<uint32_t>(ws, p.o_tot);
+    hipLaunchKernelGGL(k_fill_u32, dim3(8), dim3(256), 0, st, tot, 0u, (int64_t)kRadix * kMaxPasses);
     // 1. stable sort of the entries by their 32-bit depth key (4 passes; the
     //    first pass starts from the identity permutation)
     const uint32_t E = (uint32_t)p.E;
-    radix_pass(key, nullptr, key2, val2, nullptr, E, 0, hist, p.sortG_e, st);
-    radix_pass(key2, val2, key, val, nullptr, E, 8, hist, p.sortG_e, st);
-    radix_pass(key, val, key2, val2, nullptr, E, 16, hist, p.sortG_e, st);
-    radix_pass(key2, val2, key, val, nullptr, E, 24, hist, p.sortG_e, st);
+    radix_pass(key, nullptr, key2, val2, nullptr, E, 0, hist, p.sortG_e, tot + 0 * kRadix, st);
+    radix_pass(key2, val2, key, val, nullptr, E, 8, hist, p.sortG_e, tot + 1 * kRadix, st);
+    radix_pass(key, val, key2, val2, nullptr, E, 16, hist, p.sortG_e, tot + 2 * kRadix, st);
+    radix_pass(key2, val2, key, val, nullptr, E, 24, hist, p.sortG_e, tot + 3 * kRadix, st);
     // 2. pair offsets in depth order and emission
     uint32_t *blk = at<uint32_t>(ws, p.o_scan);
     uint64_t *blk_off = reinterpret_cast<uint64_t *>(blk + ((p.scan_blocks + 63) & ~63));
@@ -283,7 +323,7 @@ hipError_t launch_binning(const Plan &p, void *ws, const KParams &kp, hipStream_
     // 3. stable sort of the pairs by tile id
     uint32_t *ka = pkey, *va = pval, *kb = pkey2, *vb = pval2;
     for (int pass = 0; pass < p.pair_passes; ++pass) {
-        radix_pass(ka, va, kb, vb, status, 0, 8 * pass, hist, p.sortG_p, st);
+        radix_pass(ka, va, kb, vb, status, 0, 8 * pass, hist, p.sortG_p, tot + (4 + pass) * kRadix, st);
         uint32_t *t = ka; ka = kb; kb = t;
         t = va; va = vb; vb = t;
     }
