@@ -223,7 +223,7 @@ fm_status build(fm_ctx *ctx, const fm_batch *b, const fm_raster_params *prm, int
     p.o_tfinal = take(4 * (size_t)NPX);
     p.o_nlast = take(4 * (size_t)NPX);
     p.o_ncount = take(4 * (size_t)NPX);
-    p.o_grad = take(64 * (size_t)E);
+    p.o_grad = take(4 * fm::kGradStride * (size_t)E);
     p.o_pose = take(48 * (size_t)p.V * p.a7_max_blocks);
     p.o_loss = take(4 * (size_t)T * 16);
     p.o_tot = take(4 * (size_t)fm::kRadix * fm::kMaxPasses);

@@ -13,9 +13,10 @@
 //     dL/dalpha_k = T_k f_k - (S - S_k) / (1 - alpha_k),   S_k = sum_{j<=k} f_j alpha_j T_j,
 // so the backward walks the list front to back exactly like the forward,
 // recomputing T, and stops at the pixel's last contributor.  Per surfel, the
-// 16 screen-space gradients of a wave are reduced with permlane swaps + DPP,
-// the waves of the tile add into LDS, and the tile adds into the entry's
-// gradient slot with one coalesced 16-float atomic group.
+// screen-space gradients of a wave are reduced with permlane swaps + DPP and
+// added into the entry's gradient slot with one coalesced 16-float atomic
+// group (plus one for the last normal component when normals carry a
+// gradient).
 #include "fm_internal.h"
 #include "fm_wave.h"
 
@@ -24,50 +25,43 @@ namespace fm {
 namespace {
 
 struct Surf {
-    float h0, h1, h2, h3, h4, h5, h6, h7, h8;
-    float sig, c0, c1, c2, n0, n1, n2, xc, yc;
+    float c00, c01, c02, c10, c11, c12, c20, c21, c22;
+    float sig, r, g, b, n0, n1, n2, z, xs, ys;
 };
 
-__device__ __forceinline__ void load_surf(const Rec *r, Surf &s) {
-    const float4 *p = reinterpret_cast<const float4 *>(r);
-    const float4 a = p[0], b = p[1], c = p[2], d = p[3];
-    const float2 e = reinterpret_cast<const float2 *>(r)[8];
-    s.h0 = a.x; s.h1 = a.y; s.h2 = a.z; s.h3 = a.w;
-    s.h4 = b.x; s.h5 = b.y; s.h6 = b.z; s.h7 = b.w;
-    s.h8 = c.x; s.sig = c.y; s.c0 = c.z; s.c1 = c.w;
-    s.c2 = d.x; s.n0 = d.y; s.n1 = d.z; s.n2 = d.w;
-    s.xc = e.x; s.yc = e.y;
+__device__ __forceinline__ void load_surf(const Rec *rp, Surf &s) {
+    const float4 *p = reinterpret_cast<const float4 *>(rp);
+    const float4 a = p[0], b = p[1], c = p[2], d = p[3], e = p[4];
+    s.c00 = a.x; s.c01 = a.y; s.c02 = a.z; s.c10 = a.w;
+    s.c11 = b.x; s.c12 = b.y; s.c20 = b.z; s.c21 = b.w;
+    s.c22 = c.x; s.sig = c.y; s.r = c.z; s.g = c.w;
+    s.b = d.x; s.n0 = d.y; s.n1 = d.z; s.n2 = d.w;
+    s.z = e.x; s.xs = e.y; s.ys = e.z;
 }
 
 struct Hit {
-    float a0, a1, a2, b0, b1, b2, w0, w1, w2;
+    float xp, yp, w0, w1, w2, r2;
     float G, at, alpha;
 };
 
-// Ray-splat intersection at the pixel centre (px, py).  The rows a, b are the
-// two plane constraints of the pixel ray in the surfel's local (u, v, 1)
-// coordinates; their cross product w gives (u, v) = (w0, w1) / w2.  Returns
-// false when the pixel is outside the rho_max support or sigma G < alpha_min.
-// Identical arithmetic in forward and backward (no contraction beyond the
-// explicit fmaf calls), so both see the same decisions.
+// Ray-splat intersection at the pixel centre (px, py): in the surfel's
+// shifted pixel frame, w = c0 + x' c2 - y' c1 and (u, v) = (w0, w1) / w2.
+// Returns false when the pixel is outside the rho_max support or
+// sigma G < alpha_min.  Identical arithmetic in forward and backward (no
+// contraction beyond the explicit fmaf calls), so both see the same decisions.
 __device__ __forceinline__ bool splat(const Surf &s, float px, float py, float rho2, float amin, float amax,
                                       Hit &h) {
 #pragma clang fp contract(off)
-    const float xp = px - s.xc, yp = py - s.yc;
-    h.a0 = fmaf(-xp, s.h6, s.h0);
-    h.a1 = fmaf(-xp, s.h7, s.h1);
-    h.a2 = fmaf(-xp, s.h8, s.h2);
-    h.b0 = fmaf(-yp, s.h6, s.h3);
-    h.b1 = fmaf(-yp, s.h7, s.h4);
-    h.b2 = fmaf(-yp, s.h8, s.h5);
-    h.w0 = fmaf(h.a1, h.b2, -(h.a2 * h.b1));
-    h.w1 = fmaf(h.a2, h.b0, -(h.a0 * h.b2));
-    h.w2 = fmaf(h.a0, h.b1, -(h.a1 * h.b0));
+    h.xp = px - s.xs;
+    h.yp = py - s.ys;
+    h.w0 = fmaf(h.xp, s.c20, fmaf(-h.yp, s.c10, s.c00));
+    h.w1 = fmaf(h.xp, s.c21, fmaf(-h.yp, s.c11, s.c01));
+    h.w2 = fmaf(h.xp, s.c22, fmaf(-h.yp, s.c12, s.c02));
     const float num = fmaf(h.w0, h.w0, h.w1 * h.w1);
     const float den = h.w2 * h.w2;
     if (!(num <= rho2 * den) || !(den > 0.f)) return false;
-    const float r2 = num * __builtin_amdgcn_rcpf(den);
-    h.G = __builtin_amdgcn_exp2f(r2 * -0.72134752044448170368f);  // exp(-r2/2)
+    h.r2 = num * __builtin_amdgcn_rcpf(den);
+    h.G = __builtin_amdgcn_exp2f(h.r2 * -0.72134752044448170368f);  // exp(-r2/2)
     h.at = s.sig * h.G;
     if (!(h.at >= amin)) return false;
     h.alpha = fminf(amax, h.at);
@@ -117,7 +111,7 @@ __device__ __forceinline__ PixelCtx pixel_ctx(const ViewDesc *views, int V, cons
 
 // Does surfel j's bbox miss this wave's 8x8 block?  Scalar test.
 __device__ __forceinline__ bool bbox_miss(const Rec *sr, int wx0, int wy0) {
-    const uint32_t *bw = reinterpret_cast<const uint32_t *>(sr) + 18;
+    const uint32_t *bw = reinterpret_cast<const uint32_t *>(sr) + 19;
     const uint32_t b0 = __builtin_amdgcn_readfirstlane(bw[0]);
     const uint32_t b1 = __builtin_amdgcn_readfirstlane(bw[1]);
     const int x0 = (int)(b0 & 0xFFFFu), y0 = (int)(b0 >> 16);
@@ -157,10 +151,10 @@ __device__ __forceinline__ void tile_forward(const PixelCtx &c, const uint32_t *
                         done = true;
                     } else {
                         const float wgt = h.alpha * T;
-                        acc[0] = fmaf(s.c0, wgt, acc[0]);
-                        acc[1] = fmaf(s.c1, wgt, acc[1]);
-                        acc[2] = fmaf(s.c2, wgt, acc[2]);
-                        acc[3] = fmaf(s.h8, wgt, acc[3]);
+                        acc[0] = fmaf(s.r, wgt, acc[0]);
+                        acc[1] = fmaf(s.g, wgt, acc[1]);
+                        acc[2] = fmaf(s.b, wgt, acc[2]);
+                        acc[3] = fmaf(s.z, wgt, acc[3]);
                         acc[4] = fmaf(s.n0, wgt, acc[4]);
                         acc[5] = fmaf(s.n1, wgt, acc[5]);
                         acc[6] = fmaf(s.n2, wgt, acc[6]);
@@ -178,95 +172,85 @@ __device__ __forceinline__ void tile_forward(const PixelCtx &c, const uint32_t *
 
 // Adjoint traversal.  g = dL/d(r, g, b, depth, nx, ny, nz, A) of this pixel,
 // S = g . outputs, nlast = this pixel's contributor prefix length, maxlast =
-// the tile's maximum.  Accumulates into the entries' gradient slots.
-template <int TW, int TH>
+// the tile's maximum.  HAS_N: the normal map carries a gradient.
+// Accumulates into the entries' gradient slots (kGradStride floats each).
+template <int TW, int TH, bool HAS_N>
 __device__ __forceinline__ void tile_backward(const PixelCtx &c, const uint32_t *__restrict__ pval,
                                               const Rec *__restrict__ rec, const KParams &kp, Rec *srec,
-                                              uint32_t *sent, float (*sgrad)[16], uint32_t *stouch,
-                                              const float g[8], float S, uint32_t nlast, uint32_t maxlast,
-                                              float *__restrict__ grad) {
+                                              uint32_t *sent, const float g[8], float S, uint32_t nlast,
+                                              uint32_t maxlast, float *__restrict__ grad) {
     using Gm = Geo<TW, TH>;
     const float rho2 = kp.rho_max * kp.rho_max;
     float T = 1.f, Sk = 0.f;
     const uint32_t len = c.end - c.start;
     const uint32_t end = c.start + (maxlast < len ? maxlast : len);
+    const int comp = wave_reduce16_component();
     for (uint32_t base = c.start; base < end; base += Gm::NT) {
         const int cntb = (int)min((uint32_t)Gm::NT, end - base);
+        __syncthreads();
         if ((int)threadIdx.x < cntb) {
             const uint32_t ent = pval[base + threadIdx.x];
             sent[threadIdx.x] = ent;
             srec[threadIdx.x] = rec[ent];
         }
-#pragma unroll
-        for (int k = 0; k < 16; ++k) sgrad[threadIdx.x][k] = 0.f;
-        stouch[threadIdx.x] = 0;
         __syncthreads();
         const uint32_t kbase = base - c.start;
-        if (ballot64(kbase < nlast) != 0) {
-            for (int j = 0; j < cntb; ++j) {
-                if (bbox_miss(&srec[j], c.wx0, c.wy0)) continue;
-                const bool live = kbase + (uint32_t)j < nlast;
-                if (ballot64(live) == 0) break;
-                float gr[16];
+        if (ballot64(kbase < nlast) == 0) continue;
+        for (int j = 0; j < cntb; ++j) {
+            if (bbox_miss(&srec[j], c.wx0, c.wy0)) continue;
+            const bool live = kbase + (uint32_t)j < nlast;
+            if (ballot64(live) == 0) break;
+            float gr[16];
 #pragma unroll
-                for (int k = 0; k < 16; ++k) gr[k] = 0.f;
-                bool hit = false;
-                if (live) {
-                    Surf s;
-                    load_surf(&srec[j], s);
-                    Hit h;
-                    if (splat(s, c.px, c.py, rho2, kp.alpha_min, kp.alpha_max, h)) {
+            for (int k = 0; k < 16; ++k) gr[k] = 0.f;
+            float gn2 = 0.f;
+            bool hit = false;
+            if (live) {
+                Surf s;
+                load_surf(&srec[j], s);
+                Hit h;
+                if (splat(s, c.px, c.py, rho2, kp.alpha_min, kp.alpha_max, h)) {
 #pragma clang fp contract(off)
-                        hit = true;
-                        const float test = T * (1.f - h.alpha);
-                        const float wgt = h.alpha * T;
-                        const float f = g[0] * s.c0 + g[1] * s.c1 + g[2] * s.c2 + g[3] * s.h8 +
-                                        g[4] * s.n0 + g[5] * s.n1 + g[6] * s.n2 + g[7];
-                        Sk = fmaf(f, wgt, Sk);
-                        const float dal = T * f - (S - Sk) * __builtin_amdgcn_rcpf(1.f - h.alpha);
-                        gr[10] = g[0] * wgt;
-                        gr[11] = g[1] * wgt;
-                        gr[12] = g[2] * wgt;
-                        gr[13] = g[4] * wgt;
-                        gr[14] = g[5] * wgt;
-                        gr[15] = g[6] * wgt;
-                        if (h.at <= kp.alpha_max) {
-                            const float xp = c.px - s.xc, yp = c.py - s.yc;
-                            gr[9] = dal * h.G;
-                            const float dr2 = -0.5f * h.G * s.sig * dal;
-                            const float iw = __builtin_amdgcn_rcpf(h.w2);
-                            const float u = h.w0 * iw, v = h.w1 * iw;
-                            const float du = 2.f * u * dr2, dv = 2.f * v * dr2;
-                            const float gw0 = du * iw, gw1 = dv * iw, gw2 = -(du * u + dv * v) * iw;
-                            const float da0 = h.b1 * gw2 - h.b2 * gw1;
-                            const float da1 = h.b2 * gw0 - h.b0 * gw2;
-                            const float da2 = h.b0 * gw1 - h.b1 * gw0;
-                            const float db0 = gw1 * h.a2 - gw2 * h.a1;
-                            const float db1 = gw2 * h.a0 - gw0 * h.a2;
-                            const float db2 = gw0 * h.a1 - gw1 * h.a0;
-                            gr[0] = da0; gr[1] = da1; gr[2] = da2;
-                            gr[3] = db0; gr[4] = db1; gr[5] = db2;
-                            gr[6] = -xp * da0 - yp * db0;
-                            gr[7] = -xp * da1 - yp * db1;
-                            gr[8] = -xp * da2 - yp * db2;
-                        }
-                        gr[8] += g[3] * wgt;
-                        T = test;
+                    hit = true;
+                    const float test = T * (1.f - h.alpha);
+                    const float wgt = h.alpha * T;
+                    float f = g[0] * s.r + g[1] * s.g + g[2] * s.b + g[3] * s.z + g[7];
+                    if (HAS_N) f += g[4] * s.n0 + g[5] * s.n1 + g[6] * s.n2;
+                    Sk = fmaf(f, wgt, Sk);
+                    const float dal = T * f - (S - Sk) * __builtin_amdgcn_rcpf(1.f - h.alpha);
+                    gr[10] = g[0] * wgt;
+                    gr[11] = g[1] * wgt;
+                    gr[12] = g[2] * wgt;
+                    gr[13] = g[3] * wgt;
+                    if (HAS_N) {
+                        gr[14] = g[4] * wgt;
+                        gr[15] = g[5] * wgt;
+                        gn2 = g[6] * wgt;
                     }
+                    if (h.at <= kp.alpha_max) {
+                        // alpha = sigma G, G = exp(-r2/2), r2 = (w0^2 + w1^2) / w2^2
+                        gr[9] = dal * h.G;
+                        const float dr2 = -0.5f * h.G * s.sig * dal;
+                        const float iw = __builtin_amdgcn_rcpf(h.w2);
+                        const float q = 2.f * dr2 * iw;
+                        const float gw0 = q * h.w0 * iw, gw1 = q * h.w1 * iw, gw2 = -q * h.r2;
+                        // w = c0 + x' c2 - y' c1
+                        gr[0] = gw0; gr[1] = gw1; gr[2] = gw2;
+                        gr[3] = -h.yp * gw0; gr[4] = -h.yp * gw1; gr[5] = -h.yp * gw2;
+                        gr[6] = h.xp * gw0; gr[7] = h.xp * gw1; gr[8] = h.xp * gw2;
+                    }
+                    T = test;
                 }
-                if (ballot64(hit) == 0) continue;
-                const float r = wave_reduce16(gr);
-                const int comp = wave_reduce16_component();
-                if (comp >= 0) atomicAdd(&sgrad[j][comp], r);
-                if (lane_id() == 0) stouch[j] = 1u;
+            }
+            if (ballot64(hit) == 0) continue;
+            const float r = wave_reduce16(gr);
+            float *dst = grad + (int64_t)sent[j] * kGradStride;
+            if (comp >= 0) atomicAdd(dst + comp, r);
+            if (HAS_N) {
+                const float t2 = wave_sum(gn2);
+                if (lane_id() == 0) atomicAdd(dst + 16, t2);
             }
         }
-        __syncthreads();
-        for (int idx = threadIdx.x; idx < cntb * 16; idx += Gm::NT) {
-            const int j = idx >> 4, k = idx & 15;
-            if (stouch[j]) atomicAdd(&grad[(int64_t)sent[j] * 16 + k], sgrad[j][k]);
-        }
-        __syncthreads();
     }
 }
 
@@ -322,7 +306,7 @@ __global__ __launch_bounds__(TW *TH) void k_render_fwd(const ViewDesc *__restric
     }
 }
 
-template <int TW, int TH>
+template <int TW, int TH, bool HAS_N>
 __global__ __launch_bounds__(TW *TH) void k_render_bwd(const ViewDesc *__restrict__ views, int V,
                                                         const uint32_t *__restrict__ ts,
                                                         const uint32_t *__restrict__ te,
@@ -334,8 +318,6 @@ __global__ __launch_bounds__(TW *TH) void k_render_bwd(const ViewDesc *__restric
     using Gm = Geo<TW, TH>;
     __shared__ Rec srec[Gm::NT];
     __shared__ uint32_t sent[Gm::NT];
-    __shared__ float sgrad[Gm::NT][16];
-    __shared__ uint32_t stouch[Gm::NT];
     __shared__ uint32_t smax;
     const PixelCtx c = pixel_ctx<TW, TH>(views, V, ts, te);
     float g[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
@@ -345,7 +327,7 @@ __global__ __launch_bounds__(TW *TH) void k_render_bwd(const ViewDesc *__restric
         const int64_t q = c.pix;
         if (gout.rgb) { g[0] = gout.rgb[q]; g[1] = gout.rgb[NPX + q]; g[2] = gout.rgb[2 * NPX + q]; }
         if (gout.depth) g[3] = gout.depth[q];
-        if (gout.normal) { g[4] = gout.normal[q]; g[5] = gout.normal[NPX + q]; g[6] = gout.normal[2 * NPX + q]; }
+        if (HAS_N) { g[4] = gout.normal[q]; g[5] = gout.normal[NPX + q]; g[6] = gout.normal[2 * NPX + q]; }
         if (gout.alpha) g[7] = gout.alpha[q];
         bool any = false;
 #pragma unroll
@@ -353,13 +335,13 @@ __global__ __launch_bounds__(TW *TH) void k_render_bwd(const ViewDesc *__restric
         if (any) {
             nl = nlast_in[q];
             S = g[0] * out.rgb[q] + g[1] * out.rgb[NPX + q] + g[2] * out.rgb[2 * NPX + q] + g[3] * out.depth[q] +
-                g[4] * out.normal[q] + g[5] * out.normal[NPX + q] + g[6] * out.normal[2 * NPX + q] +
                 g[7] * out.alpha[q];
+            if (HAS_N) S += g[4] * out.normal[q] + g[5] * out.normal[NPX + q] + g[6] * out.normal[2 * NPX + q];
         }
     }
     const uint32_t maxlast = block_max<Gm::NT>(nl, &smax);
     if (maxlast == 0) return;
-    tile_backward<TW, TH>(c, pval, rec, kp, srec, sent, sgrad, stouch, g, S, nl, maxlast, grad);
+    tile_backward<TW, TH, HAS_N>(c, pval, rec, kp, srec, sent, g, S, nl, maxlast, grad);
 }
 
 template <int TW, int TH>
@@ -375,8 +357,6 @@ __global__ __launch_bounds__(TW *TH) void k_render_fused(const ViewDesc *__restr
     using Gm = Geo<TW, TH>;
     __shared__ Rec srec[Gm::NT];
     __shared__ uint32_t sent[Gm::NT];
-    __shared__ float sgrad[Gm::NT][16];
-    __shared__ uint32_t stouch[Gm::NT];
     __shared__ uint32_t smax;
     __shared__ float sred[Gm::NW];
     const PixelCtx c = pixel_ctx<TW, TH>(views, V, ts, te);
@@ -427,7 +407,7 @@ __global__ __launch_bounds__(TW *TH) void k_render_fused(const ViewDesc *__restr
     if (threadIdx.x == 0) loss_part[blockIdx.x] = lsum;
     const uint32_t maxlast = block_max<Gm::NT>(nl, &smax);
     if (maxlast == 0) return;
-    tile_backward<TW, TH>(c, pval, rec, kp, srec, sent, sgrad, stouch, g, S, nl, maxlast, grad);
+    tile_backward<TW, TH, false>(c, pval, rec, kp, srec, sent, g, S, nl, maxlast, grad);
 }
 
 __global__ __launch_bounds__(1024) void k_loss_reduce(const float *__restrict__ part, int64_t n,
@@ -459,10 +439,16 @@ template <int TW, int TH>
 hipError_t bwd_t(const Plan &p, void *ws, const KParams &kp, const fm_outputs &out, const fm_grad_outputs &g,
                  hipStream_t st) {
     const uint32_t *pval = at<uint32_t>(ws, p.pairs_in_alt ? p.o_pval2 : p.o_pval);
-    hipLaunchKernelGGL((k_render_bwd<TW, TH>), dim3((unsigned)p.T), dim3(TW * TH), 0, st,
-                       at<ViewDesc>(ws, p.o_views), p.V, at<uint32_t>(ws, p.o_tstart),
-                       at<uint32_t>(ws, p.o_tend), pval, at<Rec>(ws, p.o_rec), kp, p.NPX, out, g,
-                       at<uint32_t>(ws, p.o_nlast), at<float>(ws, p.o_grad));
+    if (g.normal)
+        hipLaunchKernelGGL((k_render_bwd<TW, TH, true>), dim3((unsigned)p.T), dim3(TW * TH), 0, st,
+                           at<ViewDesc>(ws, p.o_views), p.V, at<uint32_t>(ws, p.o_tstart),
+                           at<uint32_t>(ws, p.o_tend), pval, at<Rec>(ws, p.o_rec), kp, p.NPX, out, g,
+                           at<uint32_t>(ws, p.o_nlast), at<float>(ws, p.o_grad));
+    else
+        hipLaunchKernelGGL((k_render_bwd<TW, TH, false>), dim3((unsigned)p.T), dim3(TW * TH), 0, st,
+                           at<ViewDesc>(ws, p.o_views), p.V, at<uint32_t>(ws, p.o_tstart),
+                           at<uint32_t>(ws, p.o_tend), pval, at<Rec>(ws, p.o_rec), kp, p.NPX, out, g,
+                           at<uint32_t>(ws, p.o_nlast), at<float>(ws, p.o_grad));
     return hipGetLastError();
 }
 

@@ -51,19 +51,30 @@ struct SubmapDesc {
     int32_t block_base;              // first block of the backward projection
 };
 
-// Projected surfel as the blend kernels consume it (80 bytes).
-// h: homography rows in a pixel frame shifted by the integers (xc, yc):
-//    h[0..2] = row0 - xc*row2, h[3..5] = row1 - yc*row2, h[6..8] = row2,
-//    where H = K [s_u t_u | s_v t_v | p] (columns), so h[8] = centre depth.
+// Projected surfel as the blend kernels consume it (96 bytes).
+// With H = K [s_u t_u | s_v t_v | p] (columns) and its rows shifted to a
+// pixel frame centred on (xs, ys): row0' = row0 - xs row2, row1' = row1 -
+// ys row2, the pixel ray through (x, y) meets the surfel plane where
+// (u, v, 1) ~ w = (row0' - x' row2) x (row1' - y' row2), x' = x - xs,
+// y' = y - ys.  w is linear in the pixel coordinates:
+//     w(x', y') = c0 + x' c2 - y' c1,
+//     c0 = row0' x row1',  c1 = row0' x row2,  c2 = row1' x row2,
+// so the blend kernels store the three vectors instead of H.
 struct alignas(16) Rec {
-    float h[9];
+    float c0[3], c1[3], c2[3];
     float sigma;
     float col[3];
     float nrm[3];   // camera-space unit normal facing the camera
-    float xc, yc;   // pixel-frame shift (integers, exact in float)
+    float z;        // camera-space depth of the centre
+    float xs, ys;   // pixel-frame shift (integers, exact in float)
     int16_t bb[4];  // inclusive pixel-centre bbox: x0, y0, x1, y1
+    float pad[1];
 };
-static_assert(sizeof(Rec) == 80, "record layout");
+static_assert(sizeof(Rec) == 96, "record layout");
+
+// Gradient slot of one entry (20 floats): dL/dc0[3], dL/dc1[3], dL/dc2[3],
+// dL/dsigma, dL/dcol[3], dL/dz, dL/dn[3], unused.
+constexpr int kGradStride = 20;
 
 struct Status {
     uint32_t n_pairs;    // pairs actually stored (min(required, capacity))

@@ -151,26 +151,32 @@ __global__ __launch_bounds__(256) void k_preprocess(const ViewDesc *__restrict__
                         const double dotnp = n0[0] * p[0] + n0[1] * p[1] + n0[2] * p[2];
                         const double sgn = dotnp < 0.0 ? 1.0 : -1.0;
                         const int ixc = (px0 + px1) >> 1, iyc = (py0 + py1) >> 1;
-                        const double xc = (double)ixc, yc = (double)iyc;
+                        const double xs = (double)ixc, ys = (double)iyc;
+                        // rows in the shifted pixel frame and the linear ray-plane form
+                        const double r0[3] = {H[0] - xs * H[6], H[1] - xs * H[7], H[2] - xs * H[8]};
+                        const double r1[3] = {H[3] - ys * H[6], H[4] - ys * H[7], H[5] - ys * H[8]};
+                        const double r2[3] = {H[6], H[7], H[8]};
                         Rec r;
-                        r.h[0] = (float)(H[0] - xc * H[6]);
-                        r.h[1] = (float)(H[1] - xc * H[7]);
-                        r.h[2] = (float)(H[2] - xc * H[8]);
-                        r.h[3] = (float)(H[3] - yc * H[6]);
-                        r.h[4] = (float)(H[4] - yc * H[7]);
-                        r.h[5] = (float)(H[5] - yc * H[8]);
-                        r.h[6] = (float)H[6];
-                        r.h[7] = (float)H[7];
-                        r.h[8] = (float)H[8];
+                        r.c0[0] = (float)(r0[1] * r1[2] - r0[2] * r1[1]);
+                        r.c0[1] = (float)(r0[2] * r1[0] - r0[0] * r1[2]);
+                        r.c0[2] = (float)(r0[0] * r1[1] - r0[1] * r1[0]);
+                        r.c1[0] = (float)(r0[1] * r2[2] - r0[2] * r2[1]);
+                        r.c1[1] = (float)(r0[2] * r2[0] - r0[0] * r2[2]);
+                        r.c1[2] = (float)(r0[0] * r2[1] - r0[1] * r2[0]);
+                        r.c2[0] = (float)(r1[1] * r2[2] - r1[2] * r2[1]);
+                        r.c2[1] = (float)(r1[2] * r2[0] - r1[0] * r2[2]);
+                        r.c2[2] = (float)(r1[0] * r2[1] - r1[1] * r2[0]);
                         r.sigma = f_sig;
                         r.col[0] = f_c0; r.col[1] = f_c1; r.col[2] = f_c2;
                         r.nrm[0] = (float)(sgn * n0[0]);
                         r.nrm[1] = (float)(sgn * n0[1]);
                         r.nrm[2] = (float)(sgn * n0[2]);
-                        r.xc = (float)ixc;
-                        r.yc = (float)iyc;
+                        r.z = (float)depth;
+                        r.xs = (float)ixc;
+                        r.ys = (float)iyc;
                         r.bb[0] = (int16_t)px0; r.bb[1] = (int16_t)py0;
                         r.bb[2] = (int16_t)px1; r.bb[3] = (int16_t)py1;
+                        r.pad[0] = 0.f;
                         rec[e] = r;
                         const int tx0 = px0 / kp.tile_w, tx1 = px1 / kp.tile_w;
                         const int ty0 = py0 / kp.tile_h, ty1 = py1 / kp.tile_h;
@@ -185,10 +191,8 @@ __global__ __launch_bounds__(256) void k_preprocess(const ViewDesc *__restrict__
     cnt[e] = out_cnt;
     if (grad && out_cnt != 0) {  // the fused path clears the entry's gradient slot here
         const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
-        grad[4 * e] = z;
-        grad[4 * e + 1] = z;
-        grad[4 * e + 2] = z;
-        grad[4 * e + 3] = z;
+#pragma unroll
+        for (int k = 0; k < kGradStride / 4; ++k) grad[(kGradStride / 4) * e + k] = z;
     }
 }
 
@@ -198,10 +202,8 @@ __global__ __launch_bounds__(256) void k_zero_grad(const uint32_t *__restrict__ 
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (e < E && cnt[e] != 0) {
         const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
-        grad[4 * e] = z;
-        grad[4 * e + 1] = z;
-        grad[4 * e + 2] = z;
-        grad[4 * e + 3] = z;
+#pragma unroll
+        for (int k = 0; k < kGradStride / 4; ++k) grad[(kGradStride / 4) * e + k] = z;
     }
 }
 
@@ -265,46 +267,66 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
 #pragma unroll
         for (int j = 0; j < 16; ++j) dV[j] = 0.f;
         if (live && cnt[e] != 0) {
-            const float4 g0 = grad[4 * e], g1 = grad[4 * e + 1], g2 = grad[4 * e + 2], g3 = grad[4 * e + 3];
-            const float g[16] = {g0.x, g0.y, g0.z, g0.w, g1.x, g1.y, g1.z, g1.w,
-                                 g2.x, g2.y, g2.z, g2.w, g3.x, g3.y, g3.z, g3.w};
+            const float4 *gp = grad + (kGradStride / 4) * e;
+            const float4 g0 = gp[0], g1 = gp[1], g2 = gp[2], g3 = gp[3], g4 = gp[4];
+            const float g[20] = {g0.x, g0.y, g0.z, g0.w, g1.x, g1.y, g1.z, g1.w, g2.x, g2.y,
+                                 g2.z, g2.w, g3.x, g3.y, g3.z, g3.w, g4.x, g4.y, g4.z, g4.w};
             const Rec &rc = rec[e];
-            const float xc = rc.xc, yc = rc.yc;
+            const float xs = rc.xs, ys = rc.ys;
             const float nr0 = rc.nrm[0], nr1 = rc.nrm[1], nr2 = rc.nrm[2];
             const float *vm = viewmat + 12 * v;
             const float R[9] = {vm[0], vm[1], vm[2], vm[4], vm[5], vm[6], vm[8], vm[9], vm[10]};
+            const float t[3] = {vm[3], vm[7], vm[11]};
             const float *K = intr + 4 * v;
             const float fx = K[0], fy = K[1], cx = K[2], cy = K[3];
-            // undo the pixel-frame shift: row2 absorbs -xc*drow0' - yc*drow1'
-            float dH[9];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                dH[c] = g[c];
-                dH[3 + c] = g[3 + c];
-                dH[6 + c] = g[6 + c] - xc * g[c] - yc * g[3 + c];
-            }
-            // H = K M  ->  dM = K^T dH
-            float dM[9];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                dM[c] = fx * dH[c];
-                dM[3 + c] = fy * dH[3 + c];
-                dM[6 + c] = cx * dH[c] + cy * dH[3 + c] + dH[6 + c];
-            }
-            float tu[3], tv[3], n0[3];
+            float tu[3], tv[3], n0[3], p[3];
 #pragma unroll
             for (int r = 0; r < 3; ++r) {
                 tu[r] = R[3 * r] * Rs[0] + R[3 * r + 1] * Rs[3] + R[3 * r + 2] * Rs[6];
                 tv[r] = R[3 * r] * Rs[1] + R[3 * r + 1] * Rs[4] + R[3 * r + 2] * Rs[7];
                 n0[r] = R[3 * r] * Rs[2] + R[3 * r + 1] * Rs[5] + R[3 * r + 2] * Rs[8];
+                p[r] = R[3 * r] * mu[0] + R[3 * r + 1] * mu[1] + R[3 * r + 2] * mu[2] + t[r];
+            }
+            // M = [s_u t_u | s_v t_v | p]; shifted rows r0 = fx M0 + (cx - xs) M2,
+            // r1 = fy M1 + (cy - ys) M2, r2 = M2
+            const float M0[3] = {su * tu[0], sv * tv[0], p[0]};
+            const float M1[3] = {su * tu[1], sv * tv[1], p[1]};
+            const float M2[3] = {su * tu[2], sv * tv[2], p[2]};
+            const float ox = cx - xs, oy = cy - ys;
+            float r0[3], r1[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                r0[c] = fx * M0[c] + ox * M2[c];
+                r1[c] = fy * M1[c] + oy * M2[c];
+            }
+            const float *r2 = M2;
+            // c0 = r0 x r1, c1 = r0 x r2, c2 = r1 x r2  ->  d(r0, r1, r2)
+            const float dc0[3] = {g[0], g[1], g[2]}, dc1[3] = {g[3], g[4], g[5]}, dc2[3] = {g[6], g[7], g[8]};
+            float dr0[3], dr1[3], dr2[3];
+            dr0[0] = (r1[1] * dc0[2] - r1[2] * dc0[1]) + (r2[1] * dc1[2] - r2[2] * dc1[1]);
+            dr0[1] = (r1[2] * dc0[0] - r1[0] * dc0[2]) + (r2[2] * dc1[0] - r2[0] * dc1[2]);
+            dr0[2] = (r1[0] * dc0[1] - r1[1] * dc0[0]) + (r2[0] * dc1[1] - r2[1] * dc1[0]);
+            dr1[0] = (dc0[1] * r0[2] - dc0[2] * r0[1]) + (r2[1] * dc2[2] - r2[2] * dc2[1]);
+            dr1[1] = (dc0[2] * r0[0] - dc0[0] * r0[2]) + (r2[2] * dc2[0] - r2[0] * dc2[2]);
+            dr1[2] = (dc0[0] * r0[1] - dc0[1] * r0[0]) + (r2[0] * dc2[1] - r2[1] * dc2[0]);
+            dr2[0] = (dc1[1] * r0[2] - dc1[2] * r0[1]) + (dc2[1] * r1[2] - dc2[2] * r1[1]);
+            dr2[1] = (dc1[2] * r0[0] - dc1[0] * r0[2]) + (dc2[2] * r1[0] - dc2[0] * r1[2]);
+            dr2[2] = (dc1[0] * r0[1] - dc1[1] * r0[0]) + (dc2[0] * r1[1] - dc2[1] * r1[0]);
+            // r0 = fx M0 + (cx - xs) M2, r1 = fy M1 + (cy - ys) M2, r2 = M2  ->  dM
+            float dM[9];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                dM[c] = fx * dr0[c];
+                dM[3 + c] = fy * dr1[c];
+                dM[6 + c] = ox * dr0[c] + oy * dr1[c] + dr2[c];
             }
             const float sgn = (n0[0] * nr0 + n0[1] * nr1 + n0[2] * nr2) >= 0.f ? 1.f : -1.f;
-            const float dp[3] = {dM[2], dM[5], dM[8]};
+            const float dp[3] = {dM[2], dM[5], dM[8] + g[13]};
             const float dtu[3] = {su * dM[0], su * dM[3], su * dM[6]};
             const float dtv[3] = {sv * dM[1], sv * dM[4], sv * dM[7]};
             dsu += tu[0] * dM[0] + tu[1] * dM[3] + tu[2] * dM[6];
             dsv += tv[0] * dM[1] + tv[1] * dM[4] + tv[2] * dM[7];
-            const float dn0[3] = {sgn * g[13], sgn * g[14], sgn * g[15]};
+            const float dn0[3] = {sgn * g[14], sgn * g[15], sgn * g[16]};
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 dmu[c] += R[c] * dp[0] + R[3 + c] * dp[1] + R[6 + c] * dp[2];
