@@ -79,6 +79,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the per-view plain comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy a 1 GiB device buffer 5 times (reference for HBM counter scaling)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -90,6 +92,16 @@ def main():
 
     import torch
     from paper_2604_03092_amd.raster import GpuScene, Rasterizer
+
+    if args.copy_calibration:
+        n = 1 << 28   # 2^28 float32 = 1 GiB
+        src = torch.ones(n, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_per_copy": 4 * n, "copies": 5}), flush=True)
+        return
 
     log(f"workload {args.workload}")
     scene = make_workload(args.workload)

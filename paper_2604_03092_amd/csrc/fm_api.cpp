@@ -151,8 +151,9 @@ fm_status build(fm_ctx *ctx, const fm_batch *b, const fm_raster_params *prm, int
         E += (int64_t)align_up((size_t)sm.n, fm::kEntryAlign);
         T += (int64_t)d.tiles_x * d.tiles_y;
         NPX += (int64_t)vs.width * vs.height;
-        if (E > ((int64_t)1 << 31) - 256 || T > ((int64_t)1 << 31) || NPX > ((int64_t)1 << 31))
-            return fail(ctx, FM_ERR_INVALID_ARG, "batch too large (entries, tiles or pixels exceed 2^31)");
+        if (E > (int64_t)fm::kEntryMask || T > ((int64_t)1 << 31) || NPX > ((int64_t)1 << 31))
+            return fail(ctx, FM_ERR_INVALID_ARG,
+                        "batch too large (entries exceed 2^28, or tiles or pixels exceed 2^31)");
     }
     p.E = E;
     p.T = T;
@@ -224,6 +225,7 @@ fm_status build(fm_ctx *ctx, const fm_batch *b, const fm_raster_params *prm, int
     p.o_nlast = take(4 * (size_t)NPX);
     p.o_ncount = take(4 * (size_t)NPX);
     p.o_grad = take(4 * fm::kGradStride * (size_t)E);
+    p.o_ell = take(sizeof(fm::Ell) * (size_t)E);
     p.o_pose = take(48 * (size_t)p.V * p.a7_max_blocks);
     p.o_loss = take(4 * (size_t)T * 16);
     p.o_tot = take(4 * (size_t)fm::kRadix * fm::kMaxPasses);
@@ -598,10 +600,10 @@ fm_status fm_debug_pairs(fm_ctx *ctx, const fm_batch *b, const fm_raster_params 
             int lo = 0, hi = p.V - 1;
             while (lo < hi) {
                 int mid = (lo + hi + 1) / 2;
-                if ((uint32_t)bt.views[mid].entry_base <= e[i]) lo = mid; else hi = mid - 1;
+                if ((uint32_t)bt.views[mid].entry_base <= (e[i] & fm::kEntryMask)) lo = mid; else hi = mid - 1;
             }
             if (tile) tile[i] = k[i];
-            if (surfel) surfel[i] = e[i] - (uint32_t)bt.views[lo].entry_base;
+            if (surfel) surfel[i] = (e[i] & fm::kEntryMask) - (uint32_t)bt.views[lo].entry_base;
             if (view) view[i] = (uint32_t)lo;
         }
     }

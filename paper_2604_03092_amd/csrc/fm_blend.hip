@@ -109,21 +109,18 @@ __device__ __forceinline__ PixelCtx pixel_ctx(const ViewDesc *views, int V, cons
     return c;
 }
 
-// Does surfel j's bbox miss this wave's 8x8 block?  Scalar test.
-__device__ __forceinline__ bool bbox_miss(const Rec *sr, int wx0, int wy0) {
-    const uint32_t *bw = reinterpret_cast<const uint32_t *>(sr) + 19;
-    const uint32_t b0 = __builtin_amdgcn_readfirstlane(bw[0]);
-    const uint32_t b1 = __builtin_amdgcn_readfirstlane(bw[1]);
-    const int x0 = (int)(b0 & 0xFFFFu), y0 = (int)(b0 >> 16);
-    const int x1 = (int)(b1 & 0xFFFFu), y1 = (int)(b1 >> 16);
-    return x1 < wx0 || x0 > wx0 + 7 || y1 < wy0 || y0 > wy0 + 7;
+// Does the pair's 8x8-block mask exclude this wave's block?  Scalar test.
+__device__ __forceinline__ bool block_miss(const uint32_t *sval, int j, int wave) {
+    const uint32_t m = __builtin_amdgcn_readfirstlane(sval[j]);
+    return ((m >> (kMaskShift + wave)) & 1u) == 0u;
 }
 
 // Forward traversal of the tile list.  acc = (r, g, b, depth, nx, ny, nz, A).
 template <int TW, int TH>
 __device__ __forceinline__ void tile_forward(const PixelCtx &c, const uint32_t *__restrict__ pval,
                                              const Rec *__restrict__ rec, const KParams &kp, Rec *srec,
-                                             float acc[8], float &T, uint32_t &nlast, uint32_t &ncount) {
+                                             uint32_t *sval, float acc[8], float &T, uint32_t &nlast,
+                                             uint32_t &ncount) {
     using Gm = Geo<TW, TH>;
     const float rho2 = kp.rho_max * kp.rho_max;
     bool done = !c.inside;
@@ -135,11 +132,16 @@ __device__ __forceinline__ void tile_forward(const PixelCtx &c, const uint32_t *
     for (uint32_t base = c.start; base < c.end; base += Gm::NT) {
         if (__syncthreads_count(!done) == 0) break;
         const int cntb = (int)min((uint32_t)Gm::NT, c.end - base);
-        if ((int)threadIdx.x < cntb) srec[threadIdx.x] = rec[pval[base + threadIdx.x]];
+        if ((int)threadIdx.x < cntb) {
+            const uint32_t pv = pval[base + threadIdx.x];
+            sval[threadIdx.x] = pv;
+            srec[threadIdx.x] = rec[pv & kEntryMask];
+        }
         __syncthreads();
         if (ballot64(!done) == 0) continue;
+        const int wave = threadIdx.x >> 6;
         for (int j = 0; j < cntb; ++j) {
-            if (bbox_miss(&srec[j], c.wx0, c.wy0)) continue;
+            if (block_miss(sval, j, wave)) continue;
             if (!done) {
                 Surf s;
                 load_surf(&srec[j], s);
@@ -177,7 +179,7 @@ __device__ __forceinline__ void tile_forward(const PixelCtx &c, const uint32_t *
 template <int TW, int TH, bool HAS_N>
 __device__ __forceinline__ void tile_backward(const PixelCtx &c, const uint32_t *__restrict__ pval,
                                               const Rec *__restrict__ rec, const KParams &kp, Rec *srec,
-                                              uint32_t *sent, const float g[8], float S, uint32_t nlast,
+                                              uint32_t *sval, const float g[8], float S, uint32_t nlast,
                                               uint32_t maxlast, float *__restrict__ grad) {
     using Gm = Geo<TW, TH>;
     const float rho2 = kp.rho_max * kp.rho_max;
@@ -189,15 +191,16 @@ __device__ __forceinline__ void tile_backward(const PixelCtx &c, const uint32_t 
         const int cntb = (int)min((uint32_t)Gm::NT, end - base);
         __syncthreads();
         if ((int)threadIdx.x < cntb) {
-            const uint32_t ent = pval[base + threadIdx.x];
-            sent[threadIdx.x] = ent;
-            srec[threadIdx.x] = rec[ent];
+            const uint32_t pv = pval[base + threadIdx.x];
+            sval[threadIdx.x] = pv;
+            srec[threadIdx.x] = rec[pv & kEntryMask];
         }
         __syncthreads();
         const uint32_t kbase = base - c.start;
         if (ballot64(kbase < nlast) == 0) continue;
+        const int wave = threadIdx.x >> 6;
         for (int j = 0; j < cntb; ++j) {
-            if (bbox_miss(&srec[j], c.wx0, c.wy0)) continue;
+            if (block_miss(sval, j, wave)) continue;
             const bool live = kbase + (uint32_t)j < nlast;
             if (ballot64(live) == 0) break;
             float gr[16];
@@ -244,7 +247,7 @@ __device__ __forceinline__ void tile_backward(const PixelCtx &c, const uint32_t 
             }
             if (ballot64(hit) == 0) continue;
             const float r = wave_reduce16(gr);
-            float *dst = grad + (int64_t)sent[j] * kGradStride;
+            float *dst = grad + (int64_t)(sval[j] & kEntryMask) * kGradStride;
             if (comp >= 0) atomicAdd(dst + comp, r);
             if (HAS_N) {
                 const float t2 = wave_sum(gn2);
@@ -287,10 +290,11 @@ __global__ __launch_bounds__(TW *TH) void k_render_fwd(const ViewDesc *__restric
                                                         uint32_t *__restrict__ ncount_out) {
     using Gm = Geo<TW, TH>;
     __shared__ Rec srec[Gm::NT];
+    __shared__ uint32_t sval[Gm::NT];
     const PixelCtx c = pixel_ctx<TW, TH>(views, V, ts, te);
     float acc[8], T;
     uint32_t nl, nc;
-    tile_forward<TW, TH>(c, pval, rec, kp, srec, acc, T, nl, nc);
+    tile_forward<TW, TH>(c, pval, rec, kp, srec, sval, acc, T, nl, nc);
     if (c.inside) {
         out.rgb[c.pix] = acc[0] + T * kp.bg[0];
         out.rgb[NPX + c.pix] = acc[1] + T * kp.bg[1];
@@ -317,7 +321,7 @@ __global__ __launch_bounds__(TW *TH) void k_render_bwd(const ViewDesc *__restric
                                                         float *__restrict__ grad) {
     using Gm = Geo<TW, TH>;
     __shared__ Rec srec[Gm::NT];
-    __shared__ uint32_t sent[Gm::NT];
+    __shared__ uint32_t sval[Gm::NT];
     __shared__ uint32_t smax;
     const PixelCtx c = pixel_ctx<TW, TH>(views, V, ts, te);
     float g[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
@@ -341,7 +345,7 @@ __global__ __launch_bounds__(TW *TH) void k_render_bwd(const ViewDesc *__restric
     }
     const uint32_t maxlast = block_max<Gm::NT>(nl, &smax);
     if (maxlast == 0) return;
-    tile_backward<TW, TH, HAS_N>(c, pval, rec, kp, srec, sent, g, S, nl, maxlast, grad);
+    tile_backward<TW, TH, HAS_N>(c, pval, rec, kp, srec, sval, g, S, nl, maxlast, grad);
 }
 
 template <int TW, int TH>
@@ -356,13 +360,13 @@ __global__ __launch_bounds__(TW *TH) void k_render_fused(const ViewDesc *__restr
                                                           float *__restrict__ loss_part) {
     using Gm = Geo<TW, TH>;
     __shared__ Rec srec[Gm::NT];
-    __shared__ uint32_t sent[Gm::NT];
+    __shared__ uint32_t sval[Gm::NT];
     __shared__ uint32_t smax;
     __shared__ float sred[Gm::NW];
     const PixelCtx c = pixel_ctx<TW, TH>(views, V, ts, te);
     float acc[8], T;
     uint32_t nl, nc;
-    tile_forward<TW, TH>(c, pval, rec, kp, srec, acc, T, nl, nc);
+    tile_forward<TW, TH>(c, pval, rec, kp, srec, sval, acc, T, nl, nc);
     float g[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     float S = 0.f, l = 0.f;
     if (c.inside) {
@@ -407,7 +411,7 @@ __global__ __launch_bounds__(TW *TH) void k_render_fused(const ViewDesc *__restr
     if (threadIdx.x == 0) loss_part[blockIdx.x] = lsum;
     const uint32_t maxlast = block_max<Gm::NT>(nl, &smax);
     if (maxlast == 0) return;
-    tile_backward<TW, TH, false>(c, pval, rec, kp, srec, sent, g, S, nl, maxlast, grad);
+    tile_backward<TW, TH, false>(c, pval, rec, kp, srec, sval, g, S, nl, maxlast, grad);
 }
 
 __global__ __launch_bounds__(1024) void k_loss_reduce(const float *__restrict__ part, int64_t n,

@@ -72,6 +72,20 @@ struct alignas(16) Rec {
 };
 static_assert(sizeof(Rec) == 96, "record layout");
 
+// Image-space support ellipse of one entry, used only to cull 8x8 pixel
+// blocks: centre (ex, ey) and shape S, the ellipse being
+// {p : (p - e)^T S^-1 (p - e) <= 1}; the radius includes the opacity cut-off
+// and a small safety enlargement.
+struct alignas(16) Ell {
+    float ex, ey, s00, s01, s11, pad[3];
+};
+static_assert(sizeof(Ell) == 32, "ellipse layout");
+
+// Pair values: entry id in the low 28 bits, 8x8-block mask of the tile in the
+// high 4 bits (bit b set when block b of the tile may hold a covered pixel).
+constexpr uint32_t kEntryMask = 0x0FFFFFFFu;
+constexpr int kMaskShift = 28;
+
 // Gradient slot of one entry (20 floats): dL/dc0[3], dL/dc1[3], dL/dc2[3],
 // dL/dsigma, dL/dcol[3], dL/dz, dL/dn[3], unused.
 constexpr int kGradStride = 20;
@@ -112,7 +126,7 @@ struct Plan {
     size_t o_views = 0, o_subs = 0, o_vlist = 0, o_status = 0, o_rec = 0, o_key = 0, o_cnt = 0,
            o_key2 = 0, o_val = 0, o_val2 = 0, o_scan = 0, o_pkey = 0, o_pval = 0, o_pkey2 = 0,
            o_pval2 = 0, o_hist = 0, o_tstart = 0, o_tend = 0, o_tfinal = 0, o_nlast = 0, o_ncount = 0, o_grad = 0,
-           o_pose = 0, o_loss = 0, o_tot = 0;
+           o_pose = 0, o_loss = 0, o_tot = 0, o_ell = 0;
     size_t bytes = 0;
     bool pairs_in_alt = false;  // final sorted pairs live in the *2 buffers
 };

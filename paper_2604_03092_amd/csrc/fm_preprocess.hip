@@ -56,7 +56,8 @@ __global__ __launch_bounds__(256) void k_preprocess(const ViewDesc *__restrict__
                                                      const float *__restrict__ intr,
                                                      const float *__restrict__ viewmat, KParams kp,
                                                      Rec *__restrict__ rec, uint32_t *__restrict__ key,
-                                                     uint32_t *__restrict__ cnt, float4 *__restrict__ grad) {
+                                                     uint32_t *__restrict__ cnt, float4 *__restrict__ grad,
+                                                     Ell *__restrict__ ell) {
 #pragma clang fp contract(off)
     const int64_t e0 = (int64_t)blockIdx.x * 256;
     const int v = view_of_entry(views, V, e0);
@@ -177,6 +178,28 @@ __global__ __launch_bounds__(256) void k_preprocess(const ViewDesc *__restrict__
                         r.bb[0] = (int16_t)px0; r.bb[1] = (int16_t)py0;
                         r.bb[2] = (int16_t)px1; r.bb[3] = (int16_t)py1;
                         r.pad[0] = 0.f;
+                        // culling ellipse: support radius with the opacity cut-off,
+                        // rho_eff^2 = min(rho_max^2, 2 ln(sigma / alpha_min)), enlarged
+                        // by 0.2% so that it contains every pixel the FP32 blend accepts
+                        {
+                            double re2 = 2.0 * log(sigma / (double)kp.alpha_min);
+                            if (re2 > rho2) re2 = rho2;
+                            const double E00 = re2 * (H[0] * H[0] + H[1] * H[1]) - H[2] * H[2];
+                            const double E01 = re2 * (H[0] * H[3] + H[1] * H[4]) - H[2] * H[5];
+                            const double E02 = re2 * (H[0] * H[6] + H[1] * H[7]) - H[2] * H[8];
+                            const double E11 = re2 * (H[3] * H[3] + H[4] * H[4]) - H[5] * H[5];
+                            const double E12 = re2 * (H[3] * H[6] + H[4] * H[7]) - H[5] * H[8];
+                            const double E22 = re2 * (H[6] * H[6] + H[7] * H[7]) - H[8] * H[8];
+                            const double i22 = 1.0 / E22, k = 1.002 * i22 * i22;
+                            Ell el;
+                            el.ex = (float)(E02 * i22);
+                            el.ey = (float)(E12 * i22);
+                            el.s00 = (float)((E02 * E02 - E00 * E22) * k);
+                            el.s01 = (float)((E02 * E12 - E01 * E22) * k);
+                            el.s11 = (float)((E12 * E12 - E11 * E22) * k);
+                            el.pad[0] = el.pad[1] = el.pad[2] = 0.f;
+                            ell[e] = el;
+                        }
                         rec[e] = r;
                         const int tx0 = px0 / kp.tile_w, tx1 = px1 / kp.tile_w;
                         const int ty0 = py0 / kp.tile_h, ty1 = py1 / kp.tile_h;
@@ -456,7 +479,8 @@ hipError_t launch_preprocess(const Plan &p, void *ws, const KParams &kp, const f
     if (blocks == 0) return hipSuccess;
     hipLaunchKernelGGL(k_preprocess, dim3(blocks), dim3(256), 0, st, at<ViewDesc>(ws, p.o_views), p.V,
                        intr, viewmat, kp, at<Rec>(ws, p.o_rec), at<uint32_t>(ws, p.o_key),
-                       at<uint32_t>(ws, p.o_cnt), zero_grad ? at<float4>(ws, p.o_grad) : nullptr);
+                       at<uint32_t>(ws, p.o_cnt), zero_grad ? at<float4>(ws, p.o_grad) : nullptr,
+                       at<Ell>(ws, p.o_ell));
     return hipGetLastError();
 }
 

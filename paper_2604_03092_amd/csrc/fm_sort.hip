@@ -82,57 +82,82 @@ __global__ __launch_bounds__(256) void k_radix_rowscan(uint32_t *__restrict__ hi
     }
 }
 
-// Stable scatter by digit.  Each block walks its chunk in order, 256 items at
-// a time; within a wave, items with equal digits are ranked by lane through
-// ballots; waves are ranked in order through LDS.
+// Stable scatter by digit.  Each block walks its chunk in order in rounds
+// of 1024 items (item base + k*256 + thread, k = 0..3, so the round's order
+// is (k, wave, lane)).  Within a wave, items with equal digits are ranked by
+// lane through ballots; (k, wave) groups are ranked in order through LDS.
+// The next round's keys and values are loaded while the current one ranks.
 __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t *__restrict__ keys_in,
                                                         const uint32_t *__restrict__ vals_in,
                                                         uint32_t *__restrict__ keys_out,
                                                         uint32_t *__restrict__ vals_out, const Status *st,
                                                         uint32_t n_host, int shift,
                                                         const uint32_t *__restrict__ hist, int G) {
+    constexpr int KPT = 4;
     __shared__ uint32_t run[kRadix];
-    __shared__ uint32_t wcnt[4][kRadix];
+    __shared__ uint32_t gcnt[KPT * 4][kRadix];
     const int w = threadIdx.x >> 6;
     const int lane = lane_id();
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     run[threadIdx.x] = hist[threadIdx.x * G + blockIdx.x];
     uint32_t lo, hi;
     chunk_of(count_of(st, n_host), G, lo, hi);
-    for (uint32_t base = lo; base < hi; base += 256) {
+    uint32_t key[KPT], val[KPT];
+    auto load = [&](uint32_t base) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) wcnt[k][threadIdx.x] = 0;
-        __syncthreads();
-        const uint32_t i = base + threadIdx.x;
-        const bool valid = i < hi;
-        const uint32_t key = valid ? keys_in[i] : 0u;
-        const uint32_t val = valid ? (vals_in ? vals_in[i] : i) : 0u;
-        const uint32_t d = (key >> shift) & 0xFFu;
-        uint64_t m = ballot64(valid);
-#pragma unroll
-        for (int b = 0; b < kRadixBits; ++b) {
-            const bool bit = (d >> b) & 1u;
-            const uint64_t bb = ballot64(bit);
-            m &= bit ? bb : ~bb;
+        for (int k = 0; k < KPT; ++k) {
+            const uint32_t i = base + k * 256 + threadIdx.x;
+            const bool valid = i < hi;
+            key[k] = valid ? keys_in[i] : 0xFFFFFFFFu;
+            val[k] = valid ? (vals_in ? vals_in[i] : i) : 0u;
         }
-        const uint32_t rank = (uint32_t)__popcll(m & lt);
-        if (valid && rank == 0) wcnt[w][d] = (uint32_t)__popcll(m);
+    };
+    if (lo < hi) load(lo);
+    for (uint32_t base = lo; base < hi; base += KPT * 256) {
+        uint32_t ck[KPT], cv[KPT];
+#pragma unroll
+        for (int k = 0; k < KPT; ++k) { ck[k] = key[k]; cv[k] = val[k]; }
+        if (base + KPT * 256 < hi) load(base + KPT * 256);
+#pragma unroll
+        for (int k = 0; k < KPT; ++k) gcnt[k * 4 + w][threadIdx.x] = 0;
+        __syncthreads();
+        uint32_t rank[KPT], dig[KPT];
+        bool ok[KPT];
+#pragma unroll
+        for (int k = 0; k < KPT; ++k) {
+            const uint32_t i = base + k * 256 + threadIdx.x;
+            ok[k] = i < hi;
+            const uint32_t d = (ck[k] >> shift) & 0xFFu;
+            dig[k] = d;
+            uint64_t m = ballot64(ok[k]);
+#pragma unroll
+            for (int b = 0; b < kRadixBits; ++b) {
+                const bool bit = (d >> b) & 1u;
+                const uint64_t bb = ballot64(bit);
+                m &= bit ? bb : ~bb;
+            }
+            rank[k] = (uint32_t)__popcll(m & lt);
+            if (ok[k] && rank[k] == 0) gcnt[k * 4 + w][d] = (uint32_t)__popcll(m);
+        }
         __syncthreads();
         {
             uint32_t r = run[threadIdx.x];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const uint32_t c = wcnt[k][threadIdx.x];
-                wcnt[k][threadIdx.x] = r;
+            for (int g = 0; g < KPT * 4; ++g) {
+                const uint32_t c = gcnt[g][threadIdx.x];
+                gcnt[g][threadIdx.x] = r;
                 r += c;
             }
             run[threadIdx.x] = r;
         }
         __syncthreads();
-        if (valid) {
-            const uint32_t dst = wcnt[w][d] + rank;
-            keys_out[dst] = key;
-            vals_out[dst] = val;
+#pragma unroll
+        for (int k = 0; k < KPT; ++k) {
+            if (ok[k]) {
+                const uint32_t dst = gcnt[k * 4 + w][dig[k]] + rank[k];
+                keys_out[dst] = ck[k];
+                vals_out[dst] = cv[k];
+            }
         }
         __syncthreads();
     }
@@ -188,6 +213,41 @@ __global__ __launch_bounds__(1024) void k_count_scan(const uint32_t *__restrict_
     }
 }
 
+// Which 8x8 pixel blocks of the tile with origin (x0, y0) may hold a pixel
+// centre inside the entry's culling ellipse.  Per block row, the x-extent of
+// the ellipse over that row band is the hull of the slice at the clamped band
+// edges and of the leftmost/rightmost points when they fall inside the band;
+// it is widened by 0.01 px against FP32 rounding.
+__device__ inline uint32_t block_mask(const Ell &el, int x0, int y0, int tw, int th) {
+    const float hy = sqrtf(fmaxf(el.s11, 0.f));
+    const float hx = sqrtf(fmaxf(el.s00, 0.f));
+    const float ds = fmaxf(el.s00 * el.s11 - el.s01 * el.s01, 0.f);
+    const float is11 = el.s11 > 0.f ? 1.f / el.s11 : 0.f;
+    const float dy_r = hx > 0.f ? el.s01 / hx : 0.f;  // height of the rightmost point
+    const int bw = tw >> 3, bh = th >> 3;
+    uint32_t mask = 0;
+    for (int br = 0; br < bh; ++br) {
+        float dy0 = (float)(y0 + 8 * br) + 0.5f - el.ey - 0.01f;
+        float dy1 = (float)(y0 + 8 * br) + 7.5f - el.ey + 0.01f;
+        dy0 = fmaxf(dy0, -hy);
+        dy1 = fminf(dy1, hy);
+        if (!(dy0 <= dy1)) continue;
+        const float q0 = sqrtf(fmaxf(ds * (el.s11 - dy0 * dy0), 0.f));
+        const float q1 = sqrtf(fmaxf(ds * (el.s11 - dy1 * dy1), 0.f));
+        float xmax = fmaxf(el.s01 * dy0 + q0, el.s01 * dy1 + q1) * is11;
+        float xmin = fminf(el.s01 * dy0 - q0, el.s01 * dy1 - q1) * is11;
+        if (dy_r >= dy0 && dy_r <= dy1) xmax = hx;
+        if (-dy_r >= dy0 && -dy_r <= dy1) xmin = -hx;
+        xmax += el.ex + 0.01f;
+        xmin += el.ex - 0.01f;
+        for (int bc = 0; bc < bw; ++bc) {
+            const float bx0 = (float)(x0 + 8 * bc) + 0.5f, bx1 = bx0 + 7.0f;
+            if (xmax >= bx0 && xmin <= bx1) mask |= 1u << (br * bw + bc);
+        }
+    }
+    return mask;
+}
+
 // Load-balanced emission.  The block scans the tile counts of its
 // kScanChunk depth-sorted entries in LDS, then its threads walk the block's
 // pair range with a unit stride, each finding its entry by binary search over
@@ -197,20 +257,22 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t *__restrict__ sorte
                                                const uint32_t *__restrict__ cnt, int64_t E,
                                                const uint64_t *__restrict__ blk_off,
                                                const ViewDesc *__restrict__ views, int V,
-                                               const Rec *__restrict__ rec, KParams kp, uint64_t cap,
+                                               const Rec *__restrict__ rec, const Ell *__restrict__ ell,
+                                               KParams kp, uint64_t cap,
                                                uint32_t *__restrict__ pkey, uint32_t *__restrict__ pval) {
     constexpr int PER = kScanChunk / 256;
     __shared__ uint32_t s_off[kScanChunk];
     __shared__ uint32_t s_ent[kScanChunk];
     __shared__ uint32_t s_tb[kScanChunk];
     __shared__ uint32_t s_nt[kScanChunk];
+    __shared__ uint32_t s_t0[kScanChunk];
     __shared__ uint32_t wsum[4];
     const int64_t lo = (int64_t)blockIdx.x * kScanChunk;
     const int w = threadIdx.x >> 6, lane = lane_id();
     for (int i = 0; i < PER; ++i) {
         const int j = i * 256 + threadIdx.x;
         const int64_t k = lo + j;
-        uint32_t e = 0, c = 0, tb = 0, nt = 1;
+        uint32_t e = 0, c = 0, tb = 0, nt = 1, t0 = 0;
         if (k < E) {
             e = sorted_entry[k];
             c = cnt[e];
@@ -222,12 +284,14 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t *__restrict__ sorte
                 const int ty0 = r.bb[1] / kp.tile_h;
                 tb = (uint32_t)(vd.tile_base + ty0 * vd.tiles_x + tx0);
                 nt = (uint32_t)(tx1 - tx0 + 1) | ((uint32_t)vd.tiles_x << 16);
+                t0 = (uint32_t)tx0 | ((uint32_t)ty0 << 16);
             }
         }
         s_off[j] = c;
         s_ent[j] = e;
         s_tb[j] = tb;
         s_nt[j] = nt;
+        s_t0[j] = t0;
     }
     __syncthreads();
     // exclusive scan of the PER consecutive counts owned by each thread
@@ -265,8 +329,14 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t *__restrict__ sorte
         const uint32_t nt = s_nt[a];
         const uint32_t ntx = nt & 0xFFFFu, tiles_x = nt >> 16;
         const uint32_t ry = r / ntx, rx = r - ry * ntx;
-        pkey[o] = s_tb[a] + ry * tiles_x + rx;
-        pval[o] = s_ent[a];
+        const uint32_t tile = s_tb[a] + ry * tiles_x + rx;
+        const uint32_t ent = s_ent[a];
+        // tile position inside its view -> 8x8 block mask
+        const uint32_t t0 = s_t0[a];
+        const int tx = (int)(t0 & 0xFFFFu) + (int)rx, ty = (int)(t0 >> 16) + (int)ry;
+        const uint32_t mask = block_mask(ell[ent], tx * kp.tile_w, ty * kp.tile_h, kp.tile_w, kp.tile_h);
+        pkey[o] = tile;
+        pval[o] = ent | (mask << kMaskShift);
     }
 }
 
@@ -318,8 +388,8 @@ hipError_t launch_binning(const Plan &p, void *ws, const KParams &kp, hipStream_
     uint32_t *pkey = at<uint32_t>(ws, p.o_pkey), *pval = at<uint32_t>(ws, p.o_pval);
     uint32_t *pkey2 = at<uint32_t>(ws, p.o_pkey2), *pval2 = at<uint32_t>(ws, p.o_pval2);
     hipLaunchKernelGGL(k_emit, dim3(p.scan_blocks), dim3(256), 0, st, val, at<uint32_t>(ws, p.o_cnt), p.E,
-                       blk_off, at<ViewDesc>(ws, p.o_views), p.V, at<Rec>(ws, p.o_rec), kp,
-                       (uint64_t)p.cap, pkey, pval);
+                       blk_off, at<ViewDesc>(ws, p.o_views), p.V, at<Rec>(ws, p.o_rec), at<Ell>(ws, p.o_ell),
+                       kp, (uint64_t)p.cap, pkey, pval);
     // 3. stable sort of the pairs by tile id
     uint32_t *ka = pkey, *va = pval, *kb = pkey2, *vb = pval2;
     for (int pass = 0; pass < p.pair_passes; ++pass) {
