@@ -81,6 +81,7 @@ struct PixelCtx {
     float px, py;
     uint32_t start, end;
     int W, H;
+    uint32_t n_entries;
 };
 
 template <int TW, int TH>
@@ -106,6 +107,8 @@ __device__ __forceinline__ PixelCtx pixel_ctx(const ViewDesc *views, int V, cons
     c.py = (float)c.row + 0.5f;
     c.start = ts[tile];
     c.end = te[tile];
+    // total entries: the last view's segment end
+    c.n_entries = (uint32_t)views[V - 1].entry_base + (((uint32_t)views[V - 1].n + 255u) & ~255u);
     return c;
 }
 
@@ -134,8 +137,9 @@ __device__ __forceinline__ void tile_forward(const PixelCtx &c, const uint32_t *
         const int cntb = (int)min((uint32_t)Gm::NT, c.end - base);
         if ((int)threadIdx.x < cntb) {
             const uint32_t pv = pval[base + threadIdx.x];
-            sval[threadIdx.x] = pv;
-            srec[threadIdx.x] = rec[pv & kEntryMask];
+            const bool ok = (pv & kEntryMask) < c.n_entries;  // guards the record load
+            sval[threadIdx.x] = ok ? pv : 0u;
+            if (ok) srec[threadIdx.x] = rec[pv & kEntryMask];
         }
         __syncthreads();
         if (ballot64(!done) == 0) continue;
@@ -192,8 +196,9 @@ __device__ __forceinline__ void tile_backward(const PixelCtx &c, const uint32_t 
         __syncthreads();
         if ((int)threadIdx.x < cntb) {
             const uint32_t pv = pval[base + threadIdx.x];
-            sval[threadIdx.x] = pv;
-            srec[threadIdx.x] = rec[pv & kEntryMask];
+            const bool ok = (pv & kEntryMask) < c.n_entries;  // guards the record load
+            sval[threadIdx.x] = ok ? pv : 0u;
+            if (ok) srec[threadIdx.x] = rec[pv & kEntryMask];
         }
         __syncthreads();
         const uint32_t kbase = base - c.start;

@@ -101,7 +101,8 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t *__restric
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     run[threadIdx.x] = hist[threadIdx.x * G + blockIdx.x];
     uint32_t lo, hi;
-    chunk_of(count_of(st, n_host), G, lo, hi);
+    const uint32_t n = count_of(st, n_host);
+    chunk_of(n, G, lo, hi);
     uint32_t key[KPT], val[KPT];
     auto load = [&](uint32_t base) {
 #pragma unroll
@@ -119,7 +120,7 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t *__restric
         for (int k = 0; k < KPT; ++k) { ck[k] = key[k]; cv[k] = val[k]; }
         if (base + KPT * 256 < hi) load(base + KPT * 256);
 #pragma unroll
-        for (int k = 0; k < KPT; ++k) gcnt[k * 4 + w][threadIdx.x] = 0;
+        for (int g = 0; g < KPT * 4; ++g) gcnt[g][threadIdx.x] = 0;
         __syncthreads();
         uint32_t rank[KPT], dig[KPT];
         bool ok[KPT];
@@ -153,8 +154,8 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t *__restric
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < KPT; ++k) {
-            if (ok[k]) {
-                const uint32_t dst = gcnt[k * 4 + w][dig[k]] + rank[k];
+            const uint32_t dst = gcnt[k * 4 + w][dig[k]] + rank[k];
+            if (ok[k] && dst < n) {  // dst < n always holds; the test only guards the store
                 keys_out[dst] = ck[k];
                 vals_out[dst] = cv[k];
             }
@@ -345,10 +346,12 @@ __global__ __launch_bounds__(256) void k_fill_u32(uint32_t *__restrict__ p, uint
 }
 
 __global__ __launch_bounds__(256) void k_tile_ranges(const uint32_t *__restrict__ pkey, const Status *st,
-                                                      uint32_t *__restrict__ ts, uint32_t *__restrict__ te) {
+                                                      uint32_t *__restrict__ ts, uint32_t *__restrict__ te,
+                                                      uint32_t n_tiles) {
     const uint32_t n = st->n_pairs;
     for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
         const uint32_t t = pkey[i];
+        if (t >= n_tiles) continue;  // cannot happen for emitted ids; guards the stores
         if (i == 0 || pkey[i - 1] != t) ts[t] = i;
         if (i == n - 1 || pkey[i + 1] != t) te[t] = i + 1;
     }
@@ -403,7 +406,7 @@ hipError_t launch_binning(const Plan &p, void *ws, const KParams &kp, hipStream_
     hipLaunchKernelGGL(k_fill_u32, dim3(fill_blocks), dim3(256), 0, st, ts, 0u, p.T);
     hipLaunchKernelGGL(k_fill_u32, dim3(fill_blocks), dim3(256), 0, st, te, 0u, p.T);
     const int rblocks = (int)((p.cap + 255) / 256 < 8192 ? (p.cap + 255) / 256 : 8192);
-    hipLaunchKernelGGL(k_tile_ranges, dim3(rblocks), dim3(256), 0, st, ka, status, ts, te);
+    hipLaunchKernelGGL(k_tile_ranges, dim3(rblocks), dim3(256), 0, st, ka, status, ts, te, (uint32_t)p.T);
     return hipGetLastError();
 }
 
