@@ -94,7 +94,8 @@ struct Status {
     uint32_t n_pairs;    // pairs actually stored (min(required, capacity))
     uint32_t overflow;   // 1 when required > capacity
     uint64_t required;   // pairs the batch needs
-    uint32_t pad[4];
+    uint32_t n_vis;      // entries that cover at least one tile
+    uint32_t pad[3];
 };
 
 struct KParams {

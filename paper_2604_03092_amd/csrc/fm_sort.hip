@@ -19,9 +19,12 @@ namespace fm {
 
 namespace {
 
-__device__ __forceinline__ uint32_t count_of(const Status *st, uint32_t n_host) {
-    return st ? st->n_pairs : n_host;
+// Item count of a pass: from device memory when n_dev is set, else n_host.
+__device__ __forceinline__ uint32_t count_of(const uint32_t *n_dev, uint32_t n_host) {
+    return n_dev ? *n_dev : n_host;
 }
+// Entries culled or off-screen carry this key; the first depth pass drops them.
+constexpr uint32_t kNoKey = 0xFFFFFFFFu;
 __device__ __forceinline__ void chunk_of(uint32_t n, int G, uint32_t &lo, uint32_t &hi) {
     uint32_t chunk = (n + (uint32_t)G - 1) / (uint32_t)G;
     chunk = (chunk + 255u) & ~255u;
@@ -32,22 +35,31 @@ __device__ __forceinline__ void chunk_of(uint32_t n, int G, uint32_t &lo, uint32
 }
 
 // Per-block digit histogram, written digit-major: hist[d * G + block]; the
-// digit totals of the whole pass are added into tot[d].
-__global__ __launch_bounds__(256) void k_radix_hist(const uint32_t *__restrict__ keys, const Status *st,
+// digit totals of the whole pass are added into tot[d].  With `drop`, items
+// whose key is kNoKey are left out (and the kept count is added to *n_kept).
+__global__ __launch_bounds__(256) void k_radix_hist(const uint32_t *__restrict__ keys, const uint32_t *n_dev,
                                                      uint32_t n_host, int shift, uint32_t *__restrict__ hist,
-                                                     int G, uint32_t *__restrict__ tot) {
+                                                     int G, uint32_t *__restrict__ tot, int drop,
+                                                     uint32_t *__restrict__ n_kept) {
     __shared__ uint32_t h[4][kRadix];
     const int w = threadIdx.x >> 6;
 #pragma unroll
     for (int k = 0; k < 4; ++k) h[k][threadIdx.x] = 0;
     __syncthreads();
     uint32_t lo, hi;
-    chunk_of(count_of(st, n_host), G, lo, hi);
-    for (uint32_t i = lo + threadIdx.x; i < hi; i += 256) atomicAdd(&h[w][(keys[i] >> shift) & 0xFFu], 1u);
+    chunk_of(count_of(n_dev, n_host), G, lo, hi);
+    for (uint32_t i = lo + threadIdx.x; i < hi; i += 256) {
+        const uint32_t key = keys[i];
+        if (drop && key == kNoKey) continue;
+        atomicAdd(&h[w][(key >> shift) & 0xFFu], 1u);
+    }
     __syncthreads();
     const uint32_t c = h[0][threadIdx.x] + h[1][threadIdx.x] + h[2][threadIdx.x] + h[3][threadIdx.x];
     hist[threadIdx.x * G + blockIdx.x] = c;
-    if (c) atomicAdd(&tot[threadIdx.x], c);
+    if (c) {
+        atomicAdd(&tot[threadIdx.x], c);
+        if (drop) atomicAdd(n_kept, c);
+    }
 }
 
 // Global scatter offsets: block d turns row d of the histogram into
@@ -90,9 +102,9 @@ __global__ __launch_bounds__(256) void k_radix_rowscan(uint32_t *__restrict__ hi
 __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t *__restrict__ keys_in,
                                                         const uint32_t *__restrict__ vals_in,
                                                         uint32_t *__restrict__ keys_out,
-                                                        uint32_t *__restrict__ vals_out, const Status *st,
+                                                        uint32_t *__restrict__ vals_out, const uint32_t *n_dev,
                                                         uint32_t n_host, int shift,
-                                                        const uint32_t *__restrict__ hist, int G) {
+                                                        const uint32_t *__restrict__ hist, int G, int drop) {
     constexpr int KPT = 4;
     __shared__ uint32_t run[kRadix];
     __shared__ uint32_t gcnt[KPT * 4][kRadix];
@@ -101,7 +113,7 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t *__restric
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     run[threadIdx.x] = hist[threadIdx.x * G + blockIdx.x];
     uint32_t lo, hi;
-    const uint32_t n = count_of(st, n_host);
+    const uint32_t n = count_of(n_dev, n_host);
     chunk_of(n, G, lo, hi);
     uint32_t key[KPT], val[KPT];
     auto load = [&](uint32_t base) {
@@ -127,7 +139,7 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t *__restric
 #pragma unroll
         for (int k = 0; k < KPT; ++k) {
             const uint32_t i = base + k * 256 + threadIdx.x;
-            ok[k] = i < hi;
+            ok[k] = i < hi && !(drop && ck[k] == kNoKey);
             const uint32_t d = (ck[k] >> shift) & 0xFFu;
             dig[k] = d;
             uint64_t m = ballot64(ok[k]);
@@ -168,9 +180,10 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t *__restric
 
 // Block b sums the tile counts of sorted entries [b*kScanChunk, ...).
 __global__ __launch_bounds__(256) void k_count_reduce(const uint32_t *__restrict__ sorted_entry,
-                                                       const uint32_t *__restrict__ cnt, int64_t E,
+                                                       const uint32_t *__restrict__ cnt, const uint32_t *n_vis,
                                                        uint32_t *__restrict__ blk) {
     __shared__ uint32_t red[4];
+    const int64_t E = *n_vis;
     const int64_t lo = (int64_t)blockIdx.x * kScanChunk;
     int64_t hi = lo + kScanChunk;
     if (hi > E) hi = E;
@@ -255,13 +268,14 @@ __device__ inline uint32_t block_mask(const Ell &el, int x0, int y0, int tw, int
 // the local offsets, so that consecutive threads write consecutive pairs.
 // Pairs beyond the capacity are dropped.
 __global__ __launch_bounds__(256) void k_emit(const uint32_t *__restrict__ sorted_entry,
-                                               const uint32_t *__restrict__ cnt, int64_t E,
+                                               const uint32_t *__restrict__ cnt, const uint32_t *n_vis,
                                                const uint64_t *__restrict__ blk_off,
                                                const ViewDesc *__restrict__ views, int V,
                                                const Rec *__restrict__ rec, const Ell *__restrict__ ell,
                                                KParams kp, uint64_t cap,
                                                uint32_t *__restrict__ pkey, uint32_t *__restrict__ pval) {
     constexpr int PER = kScanChunk / 256;
+    const int64_t E = *n_vis;
     __shared__ uint32_t s_off[kScanChunk];
     __shared__ uint32_t s_ent[kScanChunk];
     __shared__ uint32_t s_tb[kScanChunk];
@@ -357,12 +371,14 @@ __global__ __launch_bounds__(256) void k_tile_ranges(const uint32_t *__restrict_
     }
 }
 
-void radix_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout, const Status *st,
-                uint32_t n_host, int shift, uint32_t *hist, int G, uint32_t *tot, hipStream_t s) {
-    hipLaunchKernelGGL(k_radix_hist, dim3(G), dim3(256), 0, s, kin, st, n_host, shift, hist, G, tot);
+void radix_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout, const uint32_t *n_dev,
+                uint32_t n_host, int shift, uint32_t *hist, int G, uint32_t *tot, int drop, uint32_t *n_kept,
+                hipStream_t s) {
+    hipLaunchKernelGGL(k_radix_hist, dim3(G), dim3(256), 0, s, kin, n_dev, n_host, shift, hist, G, tot, drop,
+                       n_kept);
     hipLaunchKernelGGL(k_radix_rowscan, dim3(kRadix), dim3(256), 0, s, hist, tot, G);
-    hipLaunchKernelGGL(k_radix_scatter, dim3(G), dim3(256), 0, s, kin, vin, kout, vout, st, n_host, shift,
-                       hist, G);
+    hipLaunchKernelGGL(k_radix_scatter, dim3(G), dim3(256), 0, s, kin, vin, kout, vout, n_dev, n_host, shift,
+                       hist, G, drop);
 }
 
 }  // namespace
@@ -374,29 +390,35 @@ hipError_t launch_binning(const Plan &p, void *ws, const KParams &kp, hipStream_
     uint32_t *hist = at<uint32_t>(ws, p.o_hist);
     uint32_t *tot = at<uint32_t>(ws, p.o_tot);
     hipLaunchKernelGGL(k_fill_u32, dim3(8), dim3(256), 0, st, tot, 0u, (int64_t)kRadix * kMaxPasses);
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, st, reinterpret_cast<uint32_t *>(status), 0u,
+                       (int64_t)(sizeof(Status) / 4));
     // 1. stable sort of the entries by their 32-bit depth key (4 passes; the
-    //    first pass starts from the identity permutation)
+    //    first pass starts from the identity permutation and drops the
+    //    entries that cover no tile, so the later passes see only the
+    //    visible ones)
     const uint32_t E = (uint32_t)p.E;
-    radix_pass(key, nullptr, key2, val2, nullptr, E, 0, hist, p.sortG_e, tot + 0 * kRadix, st);
-    radix_pass(key2, val2, key, val, nullptr, E, 8, hist, p.sortG_e, tot + 1 * kRadix, st);
-    radix_pass(key, val, key2, val2, nullptr, E, 16, hist, p.sortG_e, tot + 2 * kRadix, st);
-    radix_pass(key2, val2, key, val, nullptr, E, 24, hist, p.sortG_e, tot + 3 * kRadix, st);
+    uint32_t *n_vis = &status->n_vis;
+    radix_pass(key, nullptr, key2, val2, nullptr, E, 0, hist, p.sortG_e, tot + 0 * kRadix, 1, n_vis, st);
+    radix_pass(key2, val2, key, val, n_vis, 0, 8, hist, p.sortG_e, tot + 1 * kRadix, 0, nullptr, st);
+    radix_pass(key, val, key2, val2, n_vis, 0, 16, hist, p.sortG_e, tot + 2 * kRadix, 0, nullptr, st);
+    radix_pass(key2, val2, key, val, n_vis, 0, 24, hist, p.sortG_e, tot + 3 * kRadix, 0, nullptr, st);
     // 2. pair offsets in depth order and emission
     uint32_t *blk = at<uint32_t>(ws, p.o_scan);
     uint64_t *blk_off = reinterpret_cast<uint64_t *>(blk + ((p.scan_blocks + 63) & ~63));
     hipLaunchKernelGGL(k_count_reduce, dim3(p.scan_blocks), dim3(256), 0, st, val, at<uint32_t>(ws, p.o_cnt),
-                       p.E, blk);
+                       n_vis, blk);
     hipLaunchKernelGGL(k_count_scan, dim3(1), dim3(1024), 0, st, blk, p.scan_blocks, blk_off, status,
                        (uint64_t)p.cap);
     uint32_t *pkey = at<uint32_t>(ws, p.o_pkey), *pval = at<uint32_t>(ws, p.o_pval);
     uint32_t *pkey2 = at<uint32_t>(ws, p.o_pkey2), *pval2 = at<uint32_t>(ws, p.o_pval2);
-    hipLaunchKernelGGL(k_emit, dim3(p.scan_blocks), dim3(256), 0, st, val, at<uint32_t>(ws, p.o_cnt), p.E,
+    hipLaunchKernelGGL(k_emit, dim3(p.scan_blocks), dim3(256), 0, st, val, at<uint32_t>(ws, p.o_cnt), n_vis,
                        blk_off, at<ViewDesc>(ws, p.o_views), p.V, at<Rec>(ws, p.o_rec), at<Ell>(ws, p.o_ell),
                        kp, (uint64_t)p.cap, pkey, pval);
     // 3. stable sort of the pairs by tile id
     uint32_t *ka = pkey, *va = pval, *kb = pkey2, *vb = pval2;
     for (int pass = 0; pass < p.pair_passes; ++pass) {
-        radix_pass(ka, va, kb, vb, status, 0, 8 * pass, hist, p.sortG_p, tot + (4 + pass) * kRadix, st);
+        radix_pass(ka, va, kb, vb, &status->n_pairs, 0, 8 * pass, hist, p.sortG_p, tot + (4 + pass) * kRadix, 0,
+                   nullptr, st);
         uint32_t *t = ka; ka = kb; kb = t;
         t = va; va = vb; vb = t;
     }
