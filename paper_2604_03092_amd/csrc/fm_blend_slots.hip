@@ -1,0 +1,540 @@
+// fm_blend.hip -- per-tile front-to-back compositing (Eq. 1) and its adjoint
+// on gfx950.
+//
+// One wave64 per tile.  The tile is a grid of 8x8 pixel blocks; lane l owns
+// pixel (l mod 8, l / 8) of every block, so each lane carries one pixel
+// "slot" per block (1, 2 or 4 slots).  The tile's depth-ordered surfels are
+// staged through LDS 64 at a time and read as broadcasts; per surfel, the
+// pair's block mask (exact support-ellipse culling) and the set of slots
+// still compositing select the slots to evaluate with scalar tests.  The
+// surfel's record is read once per tile, and in the adjoint the slots'
+// gradients are summed in registers before one cross-lane reduction.
+//
+// Backward (forward order, no per-pixel lists): with f_k = g . (c_k, z_k,
+// n_k, 1) and S = g . (I, D, N, A) known from the forward outputs, the
+// adjoint of the compositing is
+//     dL/dalpha_k = T_k f_k - (S - S_k) / (1 - alpha_k),   S_k = sum_{j<=k} f_j alpha_j T_j,
+// so the backward walks the list front to back exactly like the forward,
+// recomputing T, and stops at the pixel's last contributor.  Per surfel, the
+// screen-space gradients of the tile are reduced with permlane swaps + DPP and
+// added into the entry's gradient slot with one coalesced 16-float atomic
+// group (plus one for the last normal component when normals carry a
+// gradient).
+#include "fm_internal.h"
+#include "fm_wave.h"
+
+namespace fm {
+
+namespace slots {
+
+struct Surf {
+    float c00, c01, c02, c10, c11, c12, c20, c21, c22;
+    float sig, r, g, b, n0, n1, n2, z, xs, ys;
+};
+
+__device__ __forceinline__ void load_surf(const Rec *rp, Surf &s) {
+    const float4 *p = reinterpret_cast<const float4 *>(rp);
+    const float4 a = p[0], b = p[1], c = p[2], d = p[3], e = p[4];
+    s.c00 = a.x; s.c01 = a.y; s.c02 = a.z; s.c10 = a.w;
+    s.c11 = b.x; s.c12 = b.y; s.c20 = b.z; s.c21 = b.w;
+    s.c22 = c.x; s.sig = c.y; s.r = c.z; s.g = c.w;
+    s.b = d.x; s.n0 = d.y; s.n1 = d.z; s.n2 = d.w;
+    s.z = e.x; s.xs = e.y; s.ys = e.z;
+}
+
+struct Hit {
+    float xp, yp, w0, w1, w2, r2;
+    float G, at, alpha;
+};
+
+// Ray-splat intersection at the pixel centre (px, py): in the surfel's
+// shifted pixel frame, w = c0 + x' c2 - y' c1 and (u, v) = (w0, w1) / w2.
+// Returns false when the pixel is outside the rho_max support or
+// sigma G < alpha_min.  Identical arithmetic in forward and backward (no
+// contraction beyond the explicit fmaf calls), so both see the same decisions.
+__device__ __forceinline__ bool splat(const Surf &s, float px, float py, float rho2, float amin, float amax,
+                                      Hit &h) {
+#pragma clang fp contract(off)
+    h.xp = px - s.xs;
+    h.yp = py - s.ys;
+    h.w0 = fmaf(h.xp, s.c20, fmaf(-h.yp, s.c10, s.c00));
+    h.w1 = fmaf(h.xp, s.c21, fmaf(-h.yp, s.c11, s.c01));
+    h.w2 = fmaf(h.xp, s.c22, fmaf(-h.yp, s.c12, s.c02));
+    const float num = fmaf(h.w0, h.w0, h.w1 * h.w1);
+    const float den = h.w2 * h.w2;
+    if (!(num <= rho2 * den) || !(den > 0.f)) return false;
+    h.r2 = num * __builtin_amdgcn_rcpf(den);
+    h.G = __builtin_amdgcn_exp2f(h.r2 * -0.72134752044448170368f);  // exp(-r2/2)
+    h.at = s.sig * h.G;
+    if (!(h.at >= amin)) return false;
+    h.alpha = fminf(amax, h.at);
+    return true;
+}
+
+template <int TW, int TH> struct Geo {
+    static constexpr int BW = TW / 8;
+    static constexpr int BH = TH / 8;
+    static constexpr int NB = BW * BH;  // pixel slots per lane
+};
+
+struct TileCtx {
+    int view, W, H;
+    int64_t pix_base;      // first pixel of the view in the output planes
+    uint32_t start, end;   // the tile's range in the sorted pair list
+    uint32_t n_entries;
+};
+
+template <int TW, int TH> struct Slots {
+    float px[Geo<TW, TH>::NB], py[Geo<TW, TH>::NB];
+    int64_t pix[Geo<TW, TH>::NB];
+    bool inside[Geo<TW, TH>::NB];
+};
+
+template <int TW, int TH>
+__device__ __forceinline__ TileCtx tile_ctx(const ViewDesc *views, int V, const uint32_t *ts,
+                                            const uint32_t *te, Slots<TW, TH> &sl) {
+    using Gm = Geo<TW, TH>;
+    TileCtx c;
+    const int tile = blockIdx.x;
+    c.view = view_of_tile(views, V, tile);
+    const ViewDesc &vd = views[c.view];
+    const int local = tile - vd.tile_base;
+    const int tx = local % vd.tiles_x, ty = local / vd.tiles_x;
+    c.W = vd.width;
+    c.H = vd.height;
+    c.pix_base = vd.pixel_offset;
+    c.start = ts[tile];
+    c.end = te[tile];
+    c.n_entries = (uint32_t)views[V - 1].entry_base + (((uint32_t)views[V - 1].n + 255u) & ~255u);
+    const int lane = threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < Gm::NB; ++q) {
+        const int col = tx * TW + 8 * (q % Gm::BW) + (lane & 7);
+        const int row = ty * TH + 8 * (q / Gm::BW) + (lane >> 3);
+        sl.inside[q] = col < c.W && row < c.H;
+        sl.pix[q] = c.pix_base + (int64_t)row * c.W + col;
+        sl.px[q] = (float)col + 0.5f;
+        sl.py[q] = (float)row + 0.5f;
+    }
+    return c;
+}
+
+// Stage up to 64 pairs of the tile list into LDS (one per lane).  Entries out
+// of range (impossible for emitted pairs) get an empty block mask.
+__device__ __forceinline__ int stage(const TileCtx &c, uint32_t base, uint32_t end,
+                                     const uint32_t *__restrict__ pval, const Rec *__restrict__ rec,
+                                     Rec *srec, uint32_t *sval) {
+    const int cntb = (int)min(64u, end - base);
+    __syncthreads();
+    if ((int)threadIdx.x < cntb) {
+        const uint32_t pv = pval[base + threadIdx.x];
+        const bool ok = (pv & kEntryMask) < c.n_entries;
+        sval[threadIdx.x] = ok ? pv : 0u;
+        if (ok) srec[threadIdx.x] = rec[pv & kEntryMask];
+    }
+    __syncthreads();
+    return cntb;
+}
+
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const uint32_t o = (uint32_t)__shfl_xor((int)v, off);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+// Forward traversal of the tile list for every slot of the lane.
+// acc = (r, g, b, depth, nx, ny, nz, A) per slot.
+template <int TW, int TH>
+__device__ __forceinline__ void tile_forward(const TileCtx &c, const Slots<TW, TH> &sl,
+                                             const uint32_t *__restrict__ pval, const Rec *__restrict__ rec,
+                                             const KParams &kp, Rec *srec, uint32_t *sval,
+                                             float (&acc)[Geo<TW, TH>::NB][8], float (&T)[Geo<TW, TH>::NB],
+                                             uint32_t (&nlast)[Geo<TW, TH>::NB],
+                                             uint32_t (&ncount)[Geo<TW, TH>::NB]) {
+    using Gm = Geo<TW, TH>;
+    const float rho2 = kp.rho_max * kp.rho_max;
+    bool done[Gm::NB];
+    uint32_t live = 0;
+#pragma unroll
+    for (int q = 0; q < Gm::NB; ++q) {
+        done[q] = !sl.inside[q];
+        T[q] = 1.f;
+        nlast[q] = 0;
+        ncount[q] = 0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc[q][k] = 0.f;
+        if (ballot64(!done[q]) != 0) live |= 1u << q;
+    }
+    for (uint32_t base = c.start; base < c.end && live != 0; base += 64) {
+        const int cntb = stage(c, base, c.end, pval, rec, srec, sval);
+        for (int j = 0; j < cntb; ++j) {
+            const uint32_t m = (__builtin_amdgcn_readfirstlane(sval[j]) >> kMaskShift) & live;
+            if (m == 0) continue;
+            Surf s;
+            load_surf(&srec[j], s);
+#pragma unroll
+            for (int q = 0; q < Gm::NB; ++q) {
+                if (((m >> q) & 1u) == 0) continue;
+                if (!done[q]) {
+                    Hit h;
+                    if (splat(s, sl.px[q], sl.py[q], rho2, kp.alpha_min, kp.alpha_max, h)) {
+#pragma clang fp contract(off)
+                        const float test = T[q] * (1.f - h.alpha);
+                        if (test < kp.t_min) {
+                            done[q] = true;
+                        } else {
+                            const float wgt = h.alpha * T[q];
+                            acc[q][0] = fmaf(s.r, wgt, acc[q][0]);
+                            acc[q][1] = fmaf(s.g, wgt, acc[q][1]);
+                            acc[q][2] = fmaf(s.b, wgt, acc[q][2]);
+                            acc[q][3] = fmaf(s.z, wgt, acc[q][3]);
+                            acc[q][4] = fmaf(s.n0, wgt, acc[q][4]);
+                            acc[q][5] = fmaf(s.n1, wgt, acc[q][5]);
+                            acc[q][6] = fmaf(s.n2, wgt, acc[q][6]);
+                            acc[q][7] = acc[q][7] + wgt;
+                            T[q] = test;
+                            nlast[q] = base - c.start + (uint32_t)j + 1u;
+                            ++ncount[q];
+                        }
+                    }
+                }
+                if (ballot64(!done[q]) == 0) live &= ~(1u << q);
+            }
+            if (live == 0) break;
+        }
+    }
+}
+
+// Adjoint traversal.  g[q] = dL/d(r, g, b, depth, nx, ny, nz, A) of slot q's
+// pixel, S[q] = g[q] . outputs, nl[q] = its contributor prefix length.
+// HAS_N: the normal map carries a gradient.
+template <int TW, int TH, bool HAS_N>
+__device__ __forceinline__ void tile_backward(const TileCtx &c, const Slots<TW, TH> &sl,
+                                              const uint32_t *__restrict__ pval, const Rec *__restrict__ rec,
+                                              const KParams &kp, Rec *srec, uint32_t *sval,
+                                              const float (&g)[Geo<TW, TH>::NB][8], const float (&S)[Geo<TW, TH>::NB],
+                                              const uint32_t (&nl)[Geo<TW, TH>::NB], float *__restrict__ grad) {
+    using Gm = Geo<TW, TH>;
+    const float rho2 = kp.rho_max * kp.rho_max;
+    float T[Gm::NB], Sk[Gm::NB];
+    uint32_t smax[Gm::NB];
+    uint32_t maxlast = 0;
+#pragma unroll
+    for (int q = 0; q < Gm::NB; ++q) {
+        T[q] = 1.f;
+        Sk[q] = 0.f;
+        smax[q] = __builtin_amdgcn_readfirstlane(wave_max_u32(nl[q]));
+        maxlast = smax[q] > maxlast ? smax[q] : maxlast;
+    }
+    const uint32_t len = c.end - c.start;
+    const uint32_t end = c.start + (maxlast < len ? maxlast : len);
+    const int comp = wave_reduce16_component();
+    for (uint32_t base = c.start; base < end; base += 64) {
+        const int cntb = stage(c, base, end, pval, rec, srec, sval);
+        const uint32_t kbase = base - c.start;
+        for (int j = 0; j < cntb; ++j) {
+            const uint32_t k = kbase + (uint32_t)j;
+            uint32_t m = __builtin_amdgcn_readfirstlane(sval[j]) >> kMaskShift;
+#pragma unroll
+            for (int q = 0; q < Gm::NB; ++q)
+                if (k >= smax[q]) m &= ~(1u << q);
+            if (m == 0) continue;
+            Surf s;
+            load_surf(&srec[j], s);
+            float gr[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) gr[i] = 0.f;
+            float gn2 = 0.f;
+            bool hit = false;
+#pragma unroll
+            for (int q = 0; q < Gm::NB; ++q) {
+                if (((m >> q) & 1u) == 0) continue;
+                if (k < nl[q]) {
+                    Hit h;
+                    if (splat(s, sl.px[q], sl.py[q], rho2, kp.alpha_min, kp.alpha_max, h)) {
+#pragma clang fp contract(off)
+                        hit = true;
+                        const float test = T[q] * (1.f - h.alpha);
+                        const float wgt = h.alpha * T[q];
+                        float f = g[q][0] * s.r + g[q][1] * s.g + g[q][2] * s.b + g[q][3] * s.z + g[q][7];
+                        if (HAS_N) f += g[q][4] * s.n0 + g[q][5] * s.n1 + g[q][6] * s.n2;
+                        Sk[q] = fmaf(f, wgt, Sk[q]);
+                        const float dal = T[q] * f - (S[q] - Sk[q]) * __builtin_amdgcn_rcpf(1.f - h.alpha);
+                        gr[10] = fmaf(g[q][0], wgt, gr[10]);
+                        gr[11] = fmaf(g[q][1], wgt, gr[11]);
+                        gr[12] = fmaf(g[q][2], wgt, gr[12]);
+                        gr[13] = fmaf(g[q][3], wgt, gr[13]);
+                        if (HAS_N) {
+                            gr[14] = fmaf(g[q][4], wgt, gr[14]);
+                            gr[15] = fmaf(g[q][5], wgt, gr[15]);
+                            gn2 = fmaf(g[q][6], wgt, gn2);
+                        }
+                        if (h.at <= kp.alpha_max) {
+                            // alpha = sigma G, G = exp(-r2/2), r2 = (w0^2 + w1^2) / w2^2
+                            gr[9] = fmaf(dal, h.G, gr[9]);
+                            const float dr2 = -0.5f * h.G * s.sig * dal;
+                            const float iw = __builtin_amdgcn_rcpf(h.w2);
+                            const float qq = 2.f * dr2 * iw;
+                            const float gw0 = qq * h.w0 * iw, gw1 = qq * h.w1 * iw, gw2 = -qq * h.r2;
+                            // w = c0 + x' c2 - y' c1
+                            gr[0] += gw0;
+                            gr[1] += gw1;
+                            gr[2] += gw2;
+                            gr[3] = fmaf(-h.yp, gw0, gr[3]);
+                            gr[4] = fmaf(-h.yp, gw1, gr[4]);
+                            gr[5] = fmaf(-h.yp, gw2, gr[5]);
+                            gr[6] = fmaf(h.xp, gw0, gr[6]);
+                            gr[7] = fmaf(h.xp, gw1, gr[7]);
+                            gr[8] = fmaf(h.xp, gw2, gr[8]);
+                        }
+                        T[q] = test;
+                    }
+                }
+            }
+            if (ballot64(hit) == 0) continue;
+            const float r = wave_reduce16(gr);
+            float *dst = grad + (int64_t)(sval[j] & kEntryMask) * kGradStride;
+            if (comp >= 0) atomicAdd(dst + comp, r);
+            if (HAS_N) {
+                const float t2 = wave_sum(gn2);
+                if (lane_id() == 0) atomicAdd(dst + 16, t2);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+template <int TW, int TH>
+__global__ __launch_bounds__(64) void k_render_fwd(const ViewDesc *__restrict__ views, int V,
+                                                    const uint32_t *__restrict__ ts, const uint32_t *__restrict__ te,
+                                                    const uint32_t *__restrict__ pval, const Rec *__restrict__ rec,
+                                                    KParams kp, int64_t NPX, fm_outputs out,
+                                                    float *__restrict__ tfinal, uint32_t *__restrict__ nlast_out,
+                                                    uint32_t *__restrict__ ncount_out) {
+    using Gm = Geo<TW, TH>;
+    __shared__ Rec srec[64];
+    __shared__ uint32_t sval[64];
+    Slots<TW, TH> sl;
+    const TileCtx c = tile_ctx<TW, TH>(views, V, ts, te, sl);
+    float acc[Gm::NB][8], T[Gm::NB];
+    uint32_t nl[Gm::NB], nc[Gm::NB];
+    tile_forward<TW, TH>(c, sl, pval, rec, kp, srec, sval, acc, T, nl, nc);
+#pragma unroll
+    for (int q = 0; q < Gm::NB; ++q) {
+        if (!sl.inside[q]) continue;
+        const int64_t p = sl.pix[q];
+        out.rgb[p] = acc[q][0] + T[q] * kp.bg[0];
+        out.rgb[NPX + p] = acc[q][1] + T[q] * kp.bg[1];
+        out.rgb[2 * NPX + p] = acc[q][2] + T[q] * kp.bg[2];
+        out.depth[p] = acc[q][3];
+        out.normal[p] = acc[q][4];
+        out.normal[NPX + p] = acc[q][5];
+        out.normal[2 * NPX + p] = acc[q][6];
+        out.alpha[p] = acc[q][7];
+        tfinal[p] = T[q];
+        nlast_out[p] = nl[q];
+        ncount_out[p] = nc[q];
+    }
+}
+
+template <int TW, int TH, bool HAS_N>
+__global__ __launch_bounds__(64) void k_render_bwd(const ViewDesc *__restrict__ views, int V,
+                                                    const uint32_t *__restrict__ ts, const uint32_t *__restrict__ te,
+                                                    const uint32_t *__restrict__ pval, const Rec *__restrict__ rec,
+                                                    KParams kp, int64_t NPX, fm_outputs out, fm_grad_outputs gout,
+                                                    const uint32_t *__restrict__ nlast_in, float *__restrict__ grad) {
+    using Gm = Geo<TW, TH>;
+    __shared__ Rec srec[64];
+    __shared__ uint32_t sval[64];
+    Slots<TW, TH> sl;
+    const TileCtx c = tile_ctx<TW, TH>(views, V, ts, te, sl);
+    float g[Gm::NB][8], S[Gm::NB];
+    uint32_t nl[Gm::NB];
+#pragma unroll
+    for (int q = 0; q < Gm::NB; ++q) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) g[q][k] = 0.f;
+        S[q] = 0.f;
+        nl[q] = 0;
+        if (!sl.inside[q]) continue;
+        const int64_t p = sl.pix[q];
+        if (gout.rgb) { g[q][0] = gout.rgb[p]; g[q][1] = gout.rgb[NPX + p]; g[q][2] = gout.rgb[2 * NPX + p]; }
+        if (gout.depth) g[q][3] = gout.depth[p];
+        if (HAS_N) { g[q][4] = gout.normal[p]; g[q][5] = gout.normal[NPX + p]; g[q][6] = gout.normal[2 * NPX + p]; }
+        if (gout.alpha) g[q][7] = gout.alpha[p];
+        bool any = false;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) any |= g[q][k] != 0.f;
+        if (any) {
+            nl[q] = nlast_in[p];
+            S[q] = g[q][0] * out.rgb[p] + g[q][1] * out.rgb[NPX + p] + g[q][2] * out.rgb[2 * NPX + p] +
+                   g[q][3] * out.depth[p] + g[q][7] * out.alpha[p];
+            if (HAS_N)
+                S[q] += g[q][4] * out.normal[p] + g[q][5] * out.normal[NPX + p] + g[q][6] * out.normal[2 * NPX + p];
+        }
+    }
+    tile_backward<TW, TH, HAS_N>(c, sl, pval, rec, kp, srec, sval, g, S, nl, grad);
+}
+
+template <int TW, int TH>
+__global__ __launch_bounds__(64) void k_render_fused(const ViewDesc *__restrict__ views, int V,
+                                                      const uint32_t *__restrict__ ts, const uint32_t *__restrict__ te,
+                                                      const uint32_t *__restrict__ pval, const Rec *__restrict__ rec,
+                                                      KParams kp, int64_t NPX, fm_outputs out, LossArgs la,
+                                                      float *__restrict__ tfinal, uint32_t *__restrict__ nlast_out,
+                                                      uint32_t *__restrict__ ncount_out, float *__restrict__ grad,
+                                                      float *__restrict__ loss_part) {
+    using Gm = Geo<TW, TH>;
+    __shared__ Rec srec[64];
+    __shared__ uint32_t sval[64];
+    Slots<TW, TH> sl;
+    const TileCtx c = tile_ctx<TW, TH>(views, V, ts, te, sl);
+    float acc[Gm::NB][8], T[Gm::NB];
+    uint32_t nl[Gm::NB], nc[Gm::NB];
+    tile_forward<TW, TH>(c, sl, pval, rec, kp, srec, sval, acc, T, nl, nc);
+    float g[Gm::NB][8], S[Gm::NB];
+    float l = 0.f;
+    const float npx = (float)c.W * (float)c.H;
+    const float k_rgb = la.w_rgb / (3.f * npx);
+    const float k_d = la.w_depth / npx;
+#pragma unroll
+    for (int q = 0; q < Gm::NB; ++q) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) g[q][k] = 0.f;
+        S[q] = 0.f;
+        if (!sl.inside[q]) {
+            nl[q] = 0;
+            continue;
+        }
+        const int64_t p = sl.pix[q];
+        const float o0 = acc[q][0] + T[q] * kp.bg[0], o1 = acc[q][1] + T[q] * kp.bg[1],
+                    o2 = acc[q][2] + T[q] * kp.bg[2];
+        out.rgb[p] = o0;
+        out.rgb[NPX + p] = o1;
+        out.rgb[2 * NPX + p] = o2;
+        out.depth[p] = acc[q][3];
+        out.normal[p] = acc[q][4];
+        out.normal[NPX + p] = acc[q][5];
+        out.normal[2 * NPX + p] = acc[q][6];
+        out.alpha[p] = acc[q][7];
+        tfinal[p] = T[q];
+        nlast_out[p] = nl[q];
+        ncount_out[p] = nc[q];
+        const bool m = la.mask ? (la.mask[p] != 0) : true;
+        if (!m) {
+            nl[q] = 0;
+            continue;
+        }
+        const float o[3] = {o0, o1, o2};
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            const float d = o[ch] - la.target_rgb[ch * NPX + p];
+            l += k_rgb * fabsf(d);
+            g[q][ch] = d > 0.f ? k_rgb : (d < 0.f ? -k_rgb : 0.f);
+        }
+        if (la.w_depth != 0.f && la.target_depth) {
+            const float d = acc[q][3] - la.target_depth[p];
+            l += k_d * fabsf(d);
+            g[q][3] = d > 0.f ? k_d : (d < 0.f ? -k_d : 0.f);
+        }
+        S[q] = g[q][0] * o0 + g[q][1] * o1 + g[q][2] * o2 + g[q][3] * acc[q][3];
+    }
+    const float lsum = wave_sum(l);
+    if (threadIdx.x == 0) loss_part[blockIdx.x] = lsum;
+    tile_backward<TW, TH, false>(c, sl, pval, rec, kp, srec, sval, g, S, nl, grad);
+}
+
+__global__ __launch_bounds__(1024) void k_loss_reduce(const float *__restrict__ part, int64_t n,
+                                                       float *__restrict__ loss) {
+    __shared__ float red[16];
+    float s = 0.f;
+    for (int64_t i = threadIdx.x; i < n; i += 1024) s += part[i];
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float t = 0.f;
+        for (int k = 0; k < 16; ++k) t += red[k];
+        *loss += t;
+    }
+}
+
+template <int TW, int TH>
+hipError_t fwd_t(const Plan &p, void *ws, const KParams &kp, const fm_outputs &out, hipStream_t st) {
+    const uint32_t *pval = at<uint32_t>(ws, p.pairs_in_alt ? p.o_pval2 : p.o_pval);
+    hipLaunchKernelGGL((k_render_fwd<TW, TH>), dim3((unsigned)p.T), dim3(64), 0, st,
+                       at<ViewDesc>(ws, p.o_views), p.V, at<uint32_t>(ws, p.o_tstart),
+                       at<uint32_t>(ws, p.o_tend), pval, at<Rec>(ws, p.o_rec), kp, p.NPX, out,
+                       at<float>(ws, p.o_tfinal), at<uint32_t>(ws, p.o_nlast), at<uint32_t>(ws, p.o_ncount));
+    return hipGetLastError();
+}
+
+template <int TW, int TH>
+hipError_t bwd_t(const Plan &p, void *ws, const KParams &kp, const fm_outputs &out, const fm_grad_outputs &g,
+                 hipStream_t st) {
+    const uint32_t *pval = at<uint32_t>(ws, p.pairs_in_alt ? p.o_pval2 : p.o_pval);
+    if (g.normal)
+        hipLaunchKernelGGL((k_render_bwd<TW, TH, true>), dim3((unsigned)p.T), dim3(64), 0, st,
+                           at<ViewDesc>(ws, p.o_views), p.V, at<uint32_t>(ws, p.o_tstart),
+                           at<uint32_t>(ws, p.o_tend), pval, at<Rec>(ws, p.o_rec), kp, p.NPX, out, g,
+                           at<uint32_t>(ws, p.o_nlast), at<float>(ws, p.o_grad));
+    else
+        hipLaunchKernelGGL((k_render_bwd<TW, TH, false>), dim3((unsigned)p.T), dim3(64), 0, st,
+                           at<ViewDesc>(ws, p.o_views), p.V, at<uint32_t>(ws, p.o_tstart),
+                           at<uint32_t>(ws, p.o_tend), pval, at<Rec>(ws, p.o_rec), kp, p.NPX, out, g,
+                           at<uint32_t>(ws, p.o_nlast), at<float>(ws, p.o_grad));
+    return hipGetLastError();
+}
+
+template <int TW, int TH>
+hipError_t fused_t(const Plan &p, void *ws, const KParams &kp, const LossArgs &la, const fm_outputs &out,
+                   hipStream_t st) {
+    const uint32_t *pval = at<uint32_t>(ws, p.pairs_in_alt ? p.o_pval2 : p.o_pval);
+    hipLaunchKernelGGL((k_render_fused<TW, TH>), dim3((unsigned)p.T), dim3(64), 0, st,
+                       at<ViewDesc>(ws, p.o_views), p.V, at<uint32_t>(ws, p.o_tstart),
+                       at<uint32_t>(ws, p.o_tend), pval, at<Rec>(ws, p.o_rec), kp, p.NPX, out, la,
+                       at<float>(ws, p.o_tfinal), at<uint32_t>(ws, p.o_nlast), at<uint32_t>(ws, p.o_ncount),
+                       at<float>(ws, p.o_grad), at<float>(ws, p.o_loss));
+    return hipGetLastError();
+}
+
+}  // namespace slots
+using namespace slots;
+
+static bool tile_shape_supported_slots(int tw, int th) {
+    return (tw == 8 && th == 8) || (tw == 16 && th == 8) || (tw == 16 && th == 16) ||
+           (tw == 32 && th == 8);
+}
+
+#define FM_DISPATCH(FN, ...)                                                     \
+    do {                                                                         \
+        if (p.tile_w == 16 && p.tile_h == 16) return FN<16, 16>(__VA_ARGS__);    \
+        if (p.tile_w == 8 && p.tile_h == 8) return FN<8, 8>(__VA_ARGS__);        \
+        if (p.tile_w == 16 && p.tile_h == 8) return FN<16, 8>(__VA_ARGS__);      \
+        if (p.tile_w == 32 && p.tile_h == 8) return FN<32, 8>(__VA_ARGS__);      \
+        return hipErrorInvalidValue;                                             \
+    } while (0)
+
+hipError_t launch_render_fwd_slots(const Plan &p, void *ws, const KParams &kp, const fm_outputs &out,
+                             hipStream_t st) {
+    if (p.T == 0) return hipSuccess;
+    FM_DISPATCH(fwd_t, p, ws, kp, out, st);
+}
+
+hipError_t launch_render_bwd_slots(const Plan &p, void *ws, const KParams &kp, const fm_outputs &out,
+                             const fm_grad_outputs &g, hipStream_t st) {
+    if (p.T == 0) return hipSuccess;
+    FM_DISPATCH(bwd_t, p, ws, kp, out, g, st);
+}
+
+hipError_t launch_render_fused_slots(const Plan &p, void *ws, const KParams &kp, const LossArgs &la,
+                               const fm_outputs &out, hipStream_t st) {
+    if (p.T == 0) return hipSuccess;
+    FM_DISPATCH(fused_t, p, ws, kp, la, out, st);
+}
+
+
+}  // namespace fm
