@@ -51,7 +51,7 @@ struct SubmapDesc {
     int32_t block_base;              // first block of the backward projection
 };
 
-// Projected surfel as the blend kernels consume it (96 bytes).
+// Projected surfel as the blend kernels consume it (80 bytes).
 // With H = K [s_u t_u | s_v t_v | p] (columns) and its rows shifted to a
 // pixel frame centred on (xs, ys): row0' = row0 - xs row2, row1' = row1 -
 // ys row2, the pixel ray through (x, y) meets the surfel plane where
@@ -67,17 +67,19 @@ struct alignas(16) Rec {
     float nrm[3];   // camera-space unit normal facing the camera
     float z;        // camera-space depth of the centre
     float xs, ys;   // pixel-frame shift (integers, exact in float)
-    int16_t bb[4];  // inclusive pixel-centre bbox: x0, y0, x1, y1
     float pad[1];
 };
-static_assert(sizeof(Rec) == 96, "record layout");
+static_assert(sizeof(Rec) == 80, "record layout");
 
-// Image-space support ellipse of one entry, used only to cull 8x8 pixel
-// blocks: centre (ex, ey) and shape S, the ellipse being
-// {p : (p - e)^T S^-1 (p - e) <= 1}; the radius includes the opacity cut-off
-// and a small safety enlargement.
+// Image-space support ellipse of one entry, used to cull 8x8 pixel blocks:
+// centre (ex, ey) and shape S, the ellipse being
+// {p : (p - e)^T S^-1 (p - e) <= 1}; its radius includes the opacity cut-off
+// and a small safety enlargement.  bb is the canonical inclusive pixel-centre
+// bbox (x0, y0, x1, y1) from which the entry's tile rect is derived.
 struct alignas(16) Ell {
-    float ex, ey, s00, s01, s11, pad[3];
+    float ex, ey, s00, s01, s11;
+    int16_t bb[4];
+    float pad[1];
 };
 static_assert(sizeof(Ell) == 32, "ellipse layout");
 

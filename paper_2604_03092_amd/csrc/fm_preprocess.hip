@@ -175,8 +175,6 @@ __global__ __launch_bounds__(256) void k_preprocess(const ViewDesc *__restrict__
                         r.z = (float)depth;
                         r.xs = (float)ixc;
                         r.ys = (float)iyc;
-                        r.bb[0] = (int16_t)px0; r.bb[1] = (int16_t)py0;
-                        r.bb[2] = (int16_t)px1; r.bb[3] = (int16_t)py1;
                         r.pad[0] = 0.f;
                         // culling ellipse: support radius with the opacity cut-off,
                         // rho_eff^2 = min(rho_max^2, 2 ln(sigma / alpha_min)), enlarged
@@ -197,7 +195,9 @@ __global__ __launch_bounds__(256) void k_preprocess(const ViewDesc *__restrict__
                             el.s00 = (float)((E02 * E02 - E00 * E22) * k);
                             el.s01 = (float)((E02 * E12 - E01 * E22) * k);
                             el.s11 = (float)((E12 * E12 - E11 * E22) * k);
-                            el.pad[0] = el.pad[1] = el.pad[2] = 0.f;
+                            el.bb[0] = (int16_t)px0; el.bb[1] = (int16_t)py0;
+                            el.bb[2] = (int16_t)px1; el.bb[3] = (int16_t)py1;
+                            el.pad[0] = 0.f;
                             ell[e] = el;
                         }
                         rec[e] = r;

@@ -294,7 +294,7 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t *__restrict__ sorte
             if (c != 0) {
                 const int v = view_of_entry(views, V, e);
                 const ViewDesc &vd = views[v];
-                const Rec &r = rec[e];
+                const Ell &r = ell[e];
                 const int tx0 = r.bb[0] / kp.tile_w, tx1 = r.bb[2] / kp.tile_w;
                 const int ty0 = r.bb[1] / kp.tile_h;
                 tb = (uint32_t)(vd.tile_base + ty0 * vd.tiles_x + tx0);
