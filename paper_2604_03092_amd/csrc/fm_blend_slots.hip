@@ -42,33 +42,47 @@ __device__ __forceinline__ void load_surf(const Rec *rp, Surf &s) {
     s.z = e.x; s.xs = e.y; s.ys = e.z;
 }
 
+// Ray-splat intersection at the pixel centre (px, py), evaluated for every
+// lane without branches.  In the surfel's shifted pixel frame the ray meets
+// the plane at (u, v) = (w0, w1) / w2 with w = c0 + x' c2 - y' c1.
+// Stage 1 decides `in`: the lane is live and u^2 + v^2 <= rho_max^2.
+// Stage 2 evaluates G = exp(-r^2/2) and alpha = min(alpha_max, sigma G),
+// with `hit` = in and sigma G >= alpha_min; lanes that miss get alpha = 0,
+// G = 0, r2 = 0 and w2 = 1, so every downstream value stays finite and their
+// contributions vanish.  Forward and backward run the same instructions on
+// the same inputs and so take the same decisions.
 struct Hit {
-    float xp, yp, w0, w1, w2, r2;
+    float xp, yp, w0, w1, w2, num, den, r2;
     float G, at, alpha;
+    bool in, hit;
 };
 
-// Ray-splat intersection at the pixel centre (px, py): in the surfel's
-// shifted pixel frame, w = c0 + x' c2 - y' c1 and (u, v) = (w0, w1) / w2.
-// Returns false when the pixel is outside the rho_max support or
-// sigma G < alpha_min.  Identical arithmetic in forward and backward (no
-// contraction beyond the explicit fmaf calls), so both see the same decisions.
-__device__ __forceinline__ bool splat(const Surf &s, float px, float py, float rho2, float amin, float amax,
-                                      Hit &h) {
+__device__ __forceinline__ void splat_geom(const Surf &s, float px, float py, float rho2, bool live, Hit &h) {
 #pragma clang fp contract(off)
     h.xp = px - s.xs;
     h.yp = py - s.ys;
     h.w0 = fmaf(h.xp, s.c20, fmaf(-h.yp, s.c10, s.c00));
     h.w1 = fmaf(h.xp, s.c21, fmaf(-h.yp, s.c11, s.c01));
     h.w2 = fmaf(h.xp, s.c22, fmaf(-h.yp, s.c12, s.c02));
-    const float num = fmaf(h.w0, h.w0, h.w1 * h.w1);
-    const float den = h.w2 * h.w2;
-    if (!(num <= rho2 * den) || !(den > 0.f)) return false;
-    h.r2 = num * __builtin_amdgcn_rcpf(den);
-    h.G = __builtin_amdgcn_exp2f(h.r2 * -0.72134752044448170368f);  // exp(-r2/2)
-    h.at = s.sig * h.G;
-    if (!(h.at >= amin)) return false;
-    h.alpha = fminf(amax, h.at);
-    return true;
+    h.num = fmaf(h.w0, h.w0, h.w1 * h.w1);
+    h.den = h.w2 * h.w2;
+    h.in = live && (h.num <= rho2 * h.den) && (h.den > 0.f);
+}
+
+__device__ __forceinline__ void splat_alpha(const Surf &s, float amin, float amax, Hit &h) {
+#pragma clang fp contract(off)
+    const float den = h.in ? h.den : 1.f;
+    const float r2 = h.num * __builtin_amdgcn_rcpf(den);
+    h.r2 = h.in ? r2 : 0.f;
+    const float G = __builtin_amdgcn_exp2f(h.r2 * -0.72134752044448170368f);  // exp(-r2/2)
+    const float at = s.sig * G;
+    h.hit = h.in && (at >= amin);
+    h.G = h.hit ? G : 0.f;
+    h.at = h.hit ? at : 0.f;
+    h.alpha = h.hit ? (at > amax ? amax : at) : 0.f;
+    h.w2 = h.hit ? h.w2 : 1.f;
+    h.w0 = h.hit ? h.w0 : 0.f;
+    h.w1 = h.hit ? h.w1 : 0.f;
 }
 
 template <int TW, int TH> struct Geo {
@@ -178,28 +192,28 @@ __device__ __forceinline__ void tile_forward(const TileCtx &c, const Slots<TW, T
 #pragma unroll
             for (int q = 0; q < Gm::NB; ++q) {
                 if (((m >> q) & 1u) == 0) continue;
-                if (!done[q]) {
-                    Hit h;
-                    if (splat(s, sl.px[q], sl.py[q], rho2, kp.alpha_min, kp.alpha_max, h)) {
+                Hit h;
+                splat_geom(s, sl.px[q], sl.py[q], rho2, !done[q], h);
+                if (ballot64(h.in) == 0) continue;
+                splat_alpha(s, kp.alpha_min, kp.alpha_max, h);
+                {
 #pragma clang fp contract(off)
-                        const float test = T[q] * (1.f - h.alpha);
-                        if (test < kp.t_min) {
-                            done[q] = true;
-                        } else {
-                            const float wgt = h.alpha * T[q];
-                            acc[q][0] = fmaf(s.r, wgt, acc[q][0]);
-                            acc[q][1] = fmaf(s.g, wgt, acc[q][1]);
-                            acc[q][2] = fmaf(s.b, wgt, acc[q][2]);
-                            acc[q][3] = fmaf(s.z, wgt, acc[q][3]);
-                            acc[q][4] = fmaf(s.n0, wgt, acc[q][4]);
-                            acc[q][5] = fmaf(s.n1, wgt, acc[q][5]);
-                            acc[q][6] = fmaf(s.n2, wgt, acc[q][6]);
-                            acc[q][7] = acc[q][7] + wgt;
-                            T[q] = test;
-                            nlast[q] = base - c.start + (uint32_t)j + 1u;
-                            ++ncount[q];
-                        }
-                    }
+                    const float test = T[q] * (1.f - h.alpha);
+                    const bool stop = h.hit && test < kp.t_min;
+                    const bool con = h.hit && !stop;
+                    const float wgt = (con ? h.alpha : 0.f) * T[q];
+                    acc[q][0] = fmaf(s.r, wgt, acc[q][0]);
+                    acc[q][1] = fmaf(s.g, wgt, acc[q][1]);
+                    acc[q][2] = fmaf(s.b, wgt, acc[q][2]);
+                    acc[q][3] = fmaf(s.z, wgt, acc[q][3]);
+                    acc[q][4] = fmaf(s.n0, wgt, acc[q][4]);
+                    acc[q][5] = fmaf(s.n1, wgt, acc[q][5]);
+                    acc[q][6] = fmaf(s.n2, wgt, acc[q][6]);
+                    acc[q][7] = acc[q][7] + wgt;
+                    T[q] = stop ? T[q] : test;
+                    nlast[q] = con ? base - c.start + (uint32_t)j + 1u : nlast[q];
+                    ncount[q] += con ? 1u : 0u;
+                    done[q] = done[q] || stop;
                 }
                 if (ballot64(!done[q]) == 0) live &= ~(1u << q);
             }
@@ -252,46 +266,48 @@ __device__ __forceinline__ void tile_backward(const TileCtx &c, const Slots<TW, 
 #pragma unroll
             for (int q = 0; q < Gm::NB; ++q) {
                 if (((m >> q) & 1u) == 0) continue;
-                if (k < nl[q]) {
-                    Hit h;
-                    if (splat(s, sl.px[q], sl.py[q], rho2, kp.alpha_min, kp.alpha_max, h)) {
+                Hit h;
+                splat_geom(s, sl.px[q], sl.py[q], rho2, k < nl[q], h);
+                if (ballot64(h.in) == 0) continue;
+                splat_alpha(s, kp.alpha_min, kp.alpha_max, h);
+                if (ballot64(h.hit) == 0) continue;
+                {
 #pragma clang fp contract(off)
-                        hit = true;
-                        const float test = T[q] * (1.f - h.alpha);
-                        const float wgt = h.alpha * T[q];
-                        float f = g[q][0] * s.r + g[q][1] * s.g + g[q][2] * s.b + g[q][3] * s.z + g[q][7];
-                        if (HAS_N) f += g[q][4] * s.n0 + g[q][5] * s.n1 + g[q][6] * s.n2;
-                        Sk[q] = fmaf(f, wgt, Sk[q]);
-                        const float dal = T[q] * f - (S[q] - Sk[q]) * __builtin_amdgcn_rcpf(1.f - h.alpha);
-                        gr[10] = fmaf(g[q][0], wgt, gr[10]);
-                        gr[11] = fmaf(g[q][1], wgt, gr[11]);
-                        gr[12] = fmaf(g[q][2], wgt, gr[12]);
-                        gr[13] = fmaf(g[q][3], wgt, gr[13]);
-                        if (HAS_N) {
-                            gr[14] = fmaf(g[q][4], wgt, gr[14]);
-                            gr[15] = fmaf(g[q][5], wgt, gr[15]);
-                            gn2 = fmaf(g[q][6], wgt, gn2);
-                        }
-                        if (h.at <= kp.alpha_max) {
-                            // alpha = sigma G, G = exp(-r2/2), r2 = (w0^2 + w1^2) / w2^2
-                            gr[9] = fmaf(dal, h.G, gr[9]);
-                            const float dr2 = -0.5f * h.G * s.sig * dal;
-                            const float iw = __builtin_amdgcn_rcpf(h.w2);
-                            const float qq = 2.f * dr2 * iw;
-                            const float gw0 = qq * h.w0 * iw, gw1 = qq * h.w1 * iw, gw2 = -qq * h.r2;
-                            // w = c0 + x' c2 - y' c1
-                            gr[0] += gw0;
-                            gr[1] += gw1;
-                            gr[2] += gw2;
-                            gr[3] = fmaf(-h.yp, gw0, gr[3]);
-                            gr[4] = fmaf(-h.yp, gw1, gr[4]);
-                            gr[5] = fmaf(-h.yp, gw2, gr[5]);
-                            gr[6] = fmaf(h.xp, gw0, gr[6]);
-                            gr[7] = fmaf(h.xp, gw1, gr[7]);
-                            gr[8] = fmaf(h.xp, gw2, gr[8]);
-                        }
-                        T[q] = test;
+                    hit = hit || h.hit;
+                    // lanes that miss have alpha = 0: wgt = 0 and T is unchanged
+                    const float test = T[q] * (1.f - h.alpha);
+                    const float wgt = h.alpha * T[q];
+                    float f = g[q][0] * s.r + g[q][1] * s.g + g[q][2] * s.b + g[q][3] * s.z + g[q][7];
+                    if (HAS_N) f += g[q][4] * s.n0 + g[q][5] * s.n1 + g[q][6] * s.n2;
+                    Sk[q] = fmaf(f, wgt, Sk[q]);
+                    const float dal = T[q] * f - (S[q] - Sk[q]) * __builtin_amdgcn_rcpf(1.f - h.alpha);
+                    // alpha = sigma G below the clamp; above it alpha carries no gradient
+                    const float du = (h.hit && h.at <= kp.alpha_max) ? dal : 0.f;
+                    gr[10] = fmaf(g[q][0], wgt, gr[10]);
+                    gr[11] = fmaf(g[q][1], wgt, gr[11]);
+                    gr[12] = fmaf(g[q][2], wgt, gr[12]);
+                    gr[13] = fmaf(g[q][3], wgt, gr[13]);
+                    if (HAS_N) {
+                        gr[14] = fmaf(g[q][4], wgt, gr[14]);
+                        gr[15] = fmaf(g[q][5], wgt, gr[15]);
+                        gn2 = fmaf(g[q][6], wgt, gn2);
                     }
+                    // G = exp(-r2/2), r2 = (w0^2 + w1^2) / w2^2, w = c0 + x' c2 - y' c1
+                    gr[9] = fmaf(du, h.G, gr[9]);
+                    const float dr2 = -0.5f * h.G * s.sig * du;
+                    const float iw = __builtin_amdgcn_rcpf(h.w2);
+                    const float qq = 2.f * dr2 * iw;
+                    const float gw0 = qq * h.w0 * iw, gw1 = qq * h.w1 * iw, gw2 = -qq * h.r2;
+                    gr[0] += gw0;
+                    gr[1] += gw1;
+                    gr[2] += gw2;
+                    gr[3] = fmaf(-h.yp, gw0, gr[3]);
+                    gr[4] = fmaf(-h.yp, gw1, gr[4]);
+                    gr[5] = fmaf(-h.yp, gw2, gr[5]);
+                    gr[6] = fmaf(h.xp, gw0, gr[6]);
+                    gr[7] = fmaf(h.xp, gw1, gr[7]);
+                    gr[8] = fmaf(h.xp, gw2, gr[8]);
+                    T[q] = test;
                 }
             }
             if (ballot64(hit) == 0) continue;
