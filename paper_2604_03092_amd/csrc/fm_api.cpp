@@ -172,6 +172,8 @@ fm_status build(fm_ctx *ctx, const fm_batch *b, const fm_raster_params *prm, int
     p.sortG_e = grid_for(E);
     p.sortG_p = grid_for(max_pairs);
     p.scan_blocks = (int)std::max<int64_t>(1, (E + fm::kScanChunk - 1) / fm::kScanChunk);
+    p.emit_blocks = (int)std::max<int64_t>(1, std::min<int64_t>((max_pairs + fm::kEmitChunk - 1) / fm::kEmitChunk,
+                                                                 fm::kMaxEmitGrid));
 
     // submaps in index order, each with the list of its views
     out.subs.resize(p.S);
@@ -231,6 +233,7 @@ fm_status build(fm_ctx *ctx, const fm_batch *b, const fm_raster_params *prm, int
     p.o_pose = take(48 * (size_t)p.V * p.a7_max_blocks);
     p.o_loss = take(4 * (size_t)T * 16);
     p.o_tot = take(4 * (size_t)fm::kRadix * fm::kMaxPasses);
+    p.o_chunk = take(4 * (size_t)((max_pairs + fm::kEmitChunk - 1) / fm::kEmitChunk + 1));
     p.bytes = o;
     return FM_OK;
 }

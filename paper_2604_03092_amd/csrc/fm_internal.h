@@ -27,6 +27,8 @@ constexpr int kRadix = 1 << kRadixBits;
 constexpr int kSortBlock = 256;    // threads per radix-sort block
 constexpr int kScanChunk = 2048;   // entries per block of the count scan
 constexpr int kMaxSortGrid = 2048;
+constexpr int kEmitChunk = 2048;   // pairs per iteration of the emission blocks
+constexpr int kMaxEmitGrid = 4096;
 constexpr int kMaxPasses = 8;      // radix passes per binning (4 depth + up to 4 tile)
 
 // Per-view descriptor, written into the workspace at the start of each call.
@@ -74,12 +76,13 @@ static_assert(sizeof(Rec) == 80, "record layout");
 // Image-space support ellipse of one entry, used to cull 8x8 pixel blocks:
 // centre (ex, ey) and shape S, the ellipse being
 // {p : (p - e)^T S^-1 (p - e) <= 1}; its radius includes the opacity cut-off
-// and a small safety enlargement.  bb is the canonical inclusive pixel-centre
-// bbox (x0, y0, x1, y1) from which the entry's tile rect is derived.
+// and a small safety enlargement.  The entry's tile rect (from the canonical
+// inclusive pixel-centre bbox) rides along for the pair emission: tb is the
+// batch-global id of its top-left tile, t0 = tx0 | ty0 << 16 that tile's
+// position in the view, nt = (tiles per rect row) | (tiles_x of the view) << 16.
 struct alignas(16) Ell {
     float ex, ey, s00, s01, s11;
-    int16_t bb[4];
-    float pad[1];
+    uint32_t tb, t0, nt;
 };
 static_assert(sizeof(Ell) == 32, "ellipse layout");
 
@@ -124,12 +127,13 @@ struct Plan {
     int pair_passes = 1;
     int sortG_e = 1, sortG_p = 1;
     int scan_blocks = 1;
+    int emit_blocks = 1;
     int a7_blocks = 0;      // total blocks of the backward projection
     int a7_max_blocks = 0;  // max blocks of one submap
     size_t o_views = 0, o_subs = 0, o_vlist = 0, o_status = 0, o_rec = 0, o_key = 0, o_cnt = 0,
            o_key2 = 0, o_val = 0, o_val2 = 0, o_scan = 0, o_pkey = 0, o_pval = 0, o_pkey2 = 0,
            o_pval2 = 0, o_hist = 0, o_tstart = 0, o_tend = 0, o_tfinal = 0, o_nlast = 0, o_ncount = 0, o_grad = 0,
-           o_pose = 0, o_loss = 0, o_tot = 0, o_ell = 0;
+           o_pose = 0, o_loss = 0, o_tot = 0, o_ell = 0, o_chunk = 0;
     size_t bytes = 0;
     bool pairs_in_alt = false;  // final sorted pairs live in the *2 buffers
 };

@@ -195,9 +195,11 @@ __global__ __launch_bounds__(256) void k_preprocess(const ViewDesc *__restrict__
                             el.s00 = (float)((E02 * E02 - E00 * E22) * k);
                             el.s01 = (float)((E02 * E12 - E01 * E22) * k);
                             el.s11 = (float)((E12 * E12 - E11 * E22) * k);
-                            el.bb[0] = (int16_t)px0; el.bb[1] = (int16_t)py0;
-                            el.bb[2] = (int16_t)px1; el.bb[3] = (int16_t)py1;
-                            el.pad[0] = 0.f;
+                            const int tx0 = px0 / kp.tile_w, tx1 = px1 / kp.tile_w;
+                            const int ty0 = py0 / kp.tile_h;
+                            el.tb = (uint32_t)(vd.tile_base + ty0 * vd.tiles_x + tx0);
+                            el.t0 = (uint32_t)tx0 | ((uint32_t)ty0 << 16);
+                            el.nt = (uint32_t)(tx1 - tx0 + 1) | ((uint32_t)vd.tiles_x << 16);
                             ell[e] = el;
                         }
                         rec[e] = r;

@@ -262,61 +262,31 @@ __device__ inline uint32_t block_mask(const Ell &el, int x0, int y0, int tw, int
     return mask;
 }
 
-// Load-balanced emission.  The block scans the tile counts of its
-// kScanChunk depth-sorted entries in LDS, then its threads walk the block's
-// pair range with a unit stride, each finding its entry by binary search over
-// the local offsets, so that consecutive threads write consecutive pairs.
-// Pairs beyond the capacity are dropped.
-__global__ __launch_bounds__(256) void k_emit(const uint32_t *__restrict__ sorted_entry,
-                                               const uint32_t *__restrict__ cnt, const uint32_t *n_vis,
-                                               const uint64_t *__restrict__ blk_off,
-                                               const ViewDesc *__restrict__ views, int V,
-                                               const Rec *__restrict__ rec, const Ell *__restrict__ ell,
-                                               KParams kp, uint64_t cap,
-                                               uint32_t *__restrict__ pkey, uint32_t *__restrict__ pval) {
-    constexpr int PER = kScanChunk / 256;
-    const int64_t E = *n_vis;
-    __shared__ uint32_t s_off[kScanChunk];
-    __shared__ uint32_t s_ent[kScanChunk];
-    __shared__ uint32_t s_tb[kScanChunk];
-    __shared__ uint32_t s_nt[kScanChunk];
-    __shared__ uint32_t s_t0[kScanChunk];
+// Pair offsets of the depth-sorted entries and the first entry of every
+// emission chunk.  Block b owns sorted entries [b*kScanChunk, ...), thread t
+// the kPer consecutive ones from b*kScanChunk + t*kPer; the exclusive scan of
+// their tile counts, plus the block's offset, gives each entry's first pair.
+// Offsets are clamped to the capacity (pairs beyond it are never emitted).
+// Every entry that holds the first pair of a chunk of kEmitChunk pairs writes
+// its sorted index into chunk_first.  Visible entries cover at least one
+// tile, so chunk c's pairs belong to entries chunk_first[c] .. chunk_first[c+1].
+constexpr int kPer = kScanChunk / 256;
+__global__ __launch_bounds__(256) void k_offsets(const uint32_t *__restrict__ sorted_entry,
+                                                  const uint32_t *__restrict__ cnt, const uint32_t *n_vis,
+                                                  const uint64_t *__restrict__ blk_off, uint64_t cap,
+                                                  uint32_t *__restrict__ off32, uint32_t *__restrict__ chunk_first) {
     __shared__ uint32_t wsum[4];
+    const int64_t E = *n_vis;
     const int64_t lo = (int64_t)blockIdx.x * kScanChunk;
+    if (lo >= E) return;
     const int w = threadIdx.x >> 6, lane = lane_id();
-    for (int i = 0; i < PER; ++i) {
-        const int j = i * 256 + threadIdx.x;
-        const int64_t k = lo + j;
-        uint32_t e = 0, c = 0, tb = 0, nt = 1, t0 = 0;
-        if (k < E) {
-            e = sorted_entry[k];
-            c = cnt[e];
-            if (c != 0) {
-                const int v = view_of_entry(views, V, e);
-                const ViewDesc &vd = views[v];
-                const Ell &r = ell[e];
-                const int tx0 = r.bb[0] / kp.tile_w, tx1 = r.bb[2] / kp.tile_w;
-                const int ty0 = r.bb[1] / kp.tile_h;
-                tb = (uint32_t)(vd.tile_base + ty0 * vd.tiles_x + tx0);
-                nt = (uint32_t)(tx1 - tx0 + 1) | ((uint32_t)vd.tiles_x << 16);
-                t0 = (uint32_t)tx0 | ((uint32_t)ty0 << 16);
-            }
-        }
-        s_off[j] = c;
-        s_ent[j] = e;
-        s_tb[j] = tb;
-        s_nt[j] = nt;
-        s_t0[j] = t0;
-    }
-    __syncthreads();
-    // exclusive scan of the PER consecutive counts owned by each thread
-    uint32_t loc[PER];
+    const int64_t k0 = lo + (int64_t)threadIdx.x * kPer;
+    uint32_t c[kPer];
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) c[i] = k0 + i < E ? cnt[sorted_entry[k0 + i]] : 0u;
     uint32_t run = 0;
 #pragma unroll
-    for (int i = 0; i < PER; ++i) {
-        loc[i] = run;
-        run += s_off[threadIdx.x * PER + i];
-    }
+    for (int i = 0; i < kPer; ++i) run += c[i];
     uint32_t x = run;
     for (int off = 1; off < 64; off <<= 1) {
         const uint32_t y = __shfl_up(x, off);
@@ -324,34 +294,101 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t *__restrict__ sorte
     }
     if (lane == 63) wsum[w] = x;
     __syncthreads();
-    uint32_t base = x - run;
-    for (int j = 0; j < w; ++j) base += wsum[j];
-    const uint32_t total = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    uint64_t o = blk_off[blockIdx.x] + (x - run);
+    for (int j = 0; j < w; ++j) o += wsum[j];
 #pragma unroll
-    for (int i = 0; i < PER; ++i) s_off[threadIdx.x * PER + i] = base + loc[i];
-    __syncthreads();
-    const uint64_t gbase = blk_off[blockIdx.x];
-    for (uint32_t q = threadIdx.x; q < total; q += 256) {
-        const uint64_t o = gbase + q;
-        if (o >= cap) break;
-        // the entry owning pair q: last j with s_off[j] <= q
-        int a = 0, b = kScanChunk - 1;
-        while (a < b) {
-            const int m = (a + b + 1) >> 1;
-            if (s_off[m] <= q) a = m; else b = m - 1;
+    for (int i = 0; i < kPer; ++i) {
+        const int64_t k = k0 + i;
+        if (k < E) {
+            off32[k] = (uint32_t)(o < cap ? o : cap);
+            // chunk boundaries inside [o, o + c): the first multiple of kEmitChunk >= o, then every kEmitChunk
+            for (uint64_t bnd = (o + kEmitChunk - 1) / kEmitChunk * kEmitChunk; bnd < o + c[i] && bnd < cap;
+                 bnd += kEmitChunk)
+                chunk_first[bnd / kEmitChunk] = (uint32_t)k;
         }
-        const uint32_t r = q - s_off[a];
-        const uint32_t nt = s_nt[a];
-        const uint32_t ntx = nt & 0xFFFFu, tiles_x = nt >> 16;
-        const uint32_t ry = r / ntx, rx = r - ry * ntx;
-        const uint32_t tile = s_tb[a] + ry * tiles_x + rx;
-        const uint32_t ent = s_ent[a];
-        // tile position inside its view -> 8x8 block mask
-        const uint32_t t0 = s_t0[a];
-        const int tx = (int)(t0 & 0xFFFFu) + (int)rx, ty = (int)(t0 >> 16) + (int)ry;
-        const uint32_t mask = block_mask(ell[ent], tx * kp.tile_w, ty * kp.tile_h, kp.tile_w, kp.tile_h);
-        pkey[o] = tile;
-        pval[o] = ent | (mask << kMaskShift);
+        o += c[i];
+    }
+}
+
+// Pair emission balanced over pairs: each iteration of a block emits one
+// chunk of kEmitChunk consecutive pairs.  The chunk's entries (at most
+// kEmitChunk, each covering >= 1 tile) are staged in LDS; every entry marks
+// the chunk position of its first pair with its local index and an inclusive
+// max-scan over the chunk gives every pair its entry.  Consecutive threads
+// write consecutive pairs.
+__device__ __forceinline__ uint32_t wave_incl_max_u32(uint32_t x, int lane) {
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off);
+        if (lane >= off) x = y > x ? y : x;
+    }
+    return x;
+}
+
+__global__ __launch_bounds__(256) void k_emit(const uint32_t *__restrict__ sorted_entry,
+                                               const uint32_t *__restrict__ off32, const uint32_t *n_vis,
+                                               const uint32_t *__restrict__ chunk_first, const Status *st,
+                                               const Ell *__restrict__ ell, KParams kp,
+                                               uint32_t *__restrict__ pkey, uint32_t *__restrict__ pval) {
+    constexpr int PER = kEmitChunk / 256;
+    __shared__ uint32_t s_own[kEmitChunk];
+    __shared__ uint32_t s_ent[kEmitChunk];
+    __shared__ uint32_t s_off[kEmitChunk];
+    __shared__ uint32_t wmax[4];
+    const uint32_t total = st->n_pairs;
+    const uint32_t nv = *n_vis;
+    const uint32_t nchunks = (total + kEmitChunk - 1) / kEmitChunk;
+    const int w = threadIdx.x >> 6, lane = lane_id();
+    for (uint32_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        const uint32_t p0 = c * kEmitChunk;
+        const uint32_t np = total - p0 < (uint32_t)kEmitChunk ? total - p0 : (uint32_t)kEmitChunk;
+        const uint32_t first = chunk_first[c];
+        const uint32_t lastx = c + 1 < nchunks ? chunk_first[c + 1] + 1 : nv;
+        uint32_t n_ent = lastx > first ? lastx - first : 0u;
+        if (n_ent > (uint32_t)kEmitChunk) n_ent = kEmitChunk;
+        if (first >= nv || first + n_ent > nv) n_ent = 0;  // cannot happen; guards the loads
+        __syncthreads();  // the previous chunk's readers are done with the LDS arrays
+#pragma unroll
+        for (int i = 0; i < PER; ++i) s_own[i * 256 + threadIdx.x] = 0u;
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < n_ent; i += 256) {
+            const uint32_t o = off32[first + i];
+            s_ent[i] = sorted_entry[first + i];
+            s_off[i] = o;
+            const uint32_t ls = o > p0 ? o - p0 : 0u;
+            if (ls < np && i > 0) s_own[ls] = i;
+        }
+        __syncthreads();
+        // inclusive max-scan of s_own: thread t owns positions [t*PER, t*PER + PER)
+        uint32_t v[PER];
+        uint32_t m = 0;
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const uint32_t y = s_own[threadIdx.x * PER + i];
+            m = y > m ? y : m;
+            v[i] = m;
+        }
+        const uint32_t incl = wave_incl_max_u32(m, lane);
+        if (lane == 63) wmax[w] = incl;
+        __syncthreads();
+        uint32_t pre = __shfl_up(incl, 1);
+        if (lane == 0) pre = 0;
+        for (int j = 0; j < w; ++j) pre = wmax[j] > pre ? wmax[j] : pre;
+#pragma unroll
+        for (int i = 0; i < PER; ++i) s_own[threadIdx.x * PER + i] = v[i] > pre ? v[i] : pre;
+        __syncthreads();
+        for (uint32_t q = threadIdx.x; q < np; q += 256) {
+            uint32_t i = s_own[q];
+            if (i >= n_ent) i = 0;  // cannot happen; keeps the LDS read in range
+            const uint32_t ent = s_ent[i];
+            const uint32_t r = p0 + q - s_off[i];
+            const Ell el = ell[ent];
+            const uint32_t ntx = el.nt & 0xFFFFu, tiles_x = el.nt >> 16;
+            const uint32_t ry = r / ntx, rx = r - ry * ntx;
+            const int tx = (int)(el.t0 & 0xFFFFu) + (int)rx, ty = (int)(el.t0 >> 16) + (int)ry;
+            const uint32_t mask = block_mask(el, tx * kp.tile_w, ty * kp.tile_h, kp.tile_w, kp.tile_h);
+            pkey[p0 + q] = el.tb + ry * tiles_x + rx;
+            pval[p0 + q] = ent | (mask << kMaskShift);
+        }
     }
 }
 
@@ -411,9 +448,13 @@ hipError_t launch_binning(const Plan &p, void *ws, const KParams &kp, hipStream_
                        (uint64_t)p.cap);
     uint32_t *pkey = at<uint32_t>(ws, p.o_pkey), *pval = at<uint32_t>(ws, p.o_pval);
     uint32_t *pkey2 = at<uint32_t>(ws, p.o_pkey2), *pval2 = at<uint32_t>(ws, p.o_pval2);
-    hipLaunchKernelGGL(k_emit, dim3(p.scan_blocks), dim3(256), 0, st, val, at<uint32_t>(ws, p.o_cnt), n_vis,
-                       blk_off, at<ViewDesc>(ws, p.o_views), p.V, at<Rec>(ws, p.o_rec), at<Ell>(ws, p.o_ell),
-                       kp, (uint64_t)p.cap, pkey, pval);
+    // the sorted depth keys are dead after the last pass: their buffer holds the offsets
+    uint32_t *off32 = key;
+    uint32_t *chunk_first = at<uint32_t>(ws, p.o_chunk);
+    hipLaunchKernelGGL(k_offsets, dim3(p.scan_blocks), dim3(256), 0, st, val, at<uint32_t>(ws, p.o_cnt), n_vis,
+                       blk_off, (uint64_t)p.cap, off32, chunk_first);
+    hipLaunchKernelGGL(k_emit, dim3(p.emit_blocks), dim3(256), 0, st, val, off32, n_vis, chunk_first, status,
+                       at<Ell>(ws, p.o_ell), kp, pkey, pval);
     // 3. stable sort of the pairs by tile id
     uint32_t *ka = pkey, *va = pval, *kb = pkey2, *vb = pval2;
     for (int pass = 0; pass < p.pair_passes; ++pass) {
