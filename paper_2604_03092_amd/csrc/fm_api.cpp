@@ -29,7 +29,6 @@ struct fm_ctx {
     std::string last_error;
     std::map<std::string, std::pair<int, int>> tuned;  // batch signature -> tile shape
     // optional phase timing (benchmarks): events recorded between phases
-    bool slots = false;  // one-wave-per-tile blend kernels (FM_BLEND=slots)
     bool timing = false;
     hipEvent_t ev[8] = {};
     int marks = 0;
@@ -306,8 +305,7 @@ fm_status run_forward(fm_ctx *ctx, Built &bt, const fm_raster_params *prm, const
     mark(ctx, st, PH_PRE);
     FM_TRY_HIP(fm::launch_binning(bt.plan, ws, kp, st), "binning");
     mark(ctx, st, PH_BIN);
-    FM_TRY_HIP(ctx->slots ? fm::launch_render_fwd_slots(bt.plan, ws, kp, out, st)
-                          : fm::launch_render_fwd(bt.plan, ws, kp, out, st), "render_fwd");
+    FM_TRY_HIP(fm::launch_render_fwd(bt.plan, ws, kp, out, st), "render_fwd");
     mark(ctx, st, PH_BLEND);
     return FM_OK;
 }
@@ -328,8 +326,7 @@ fm_status run_fused(fm_ctx *ctx, Built &bt, const fm_raster_params *prm, const f
     mark(ctx, st, PH_PRE);
     FM_TRY_HIP(fm::launch_binning(bt.plan, ws, kp, st), "binning");
     mark(ctx, st, PH_BIN);
-    FM_TRY_HIP(ctx->slots ? fm::launch_render_fused_slots(bt.plan, ws, kp, la, out, st)
-                          : fm::launch_render_fused(bt.plan, ws, kp, la, out, st), "render_fused");
+    FM_TRY_HIP(fm::launch_render_fused(bt.plan, ws, kp, la, out, st), "render_fused");
     mark(ctx, st, PH_BLEND);
     FM_TRY_HIP(fm::launch_loss_reduce(bt.plan, ws, loss, st), "loss_reduce");
     mark(ctx, st, PH_LOSS);
@@ -404,8 +401,6 @@ fm_status fm_create(fm_ctx **out, int device) {
     c->device = device;
     c->name = prop.gcnArchName;
     c->n_cu = prop.multiProcessorCount;
-    const char *blend = getenv("FM_BLEND");
-    c->slots = blend && strcmp(blend, "slots") == 0;
     *out = c;
     return FM_OK;
 }
@@ -539,8 +534,7 @@ fm_status fm_backward(fm_ctx *ctx, const fm_batch *b, const fm_raster_params *pr
     FM_TRY_HIP(fm::launch_setup(bt.plan, ws, bt.views.data(), bt.subs.data(), bt.vlist.data(), st), "setup");
     FM_TRY_HIP(fm::launch_zero_grad(bt.plan, ws, st), "zero_grad");
     mark(ctx, st, PH_ZERO);
-    FM_TRY_HIP(ctx->slots ? fm::launch_render_bwd_slots(bt.plan, ws, kp, out, g, st)
-                          : fm::launch_render_bwd(bt.plan, ws, kp, out, g, st), "render_bwd");
+    FM_TRY_HIP(fm::launch_render_bwd(bt.plan, ws, kp, out, g, st), "render_bwd");
     mark(ctx, st, PH_BLEND);
     FM_TRY_HIP(fm::launch_preprocess_bwd(bt.plan, ws, b->intr, b->viewmat, dL_dviewmat, st), "preprocess_bwd");
     mark(ctx, st, PH_BWDPROJ);

@@ -173,13 +173,6 @@ hipError_t launch_render_bwd(const Plan &p, void *ws, const KParams &kp, const f
 hipError_t launch_render_fused(const Plan &p, void *ws, const KParams &kp, const LossArgs &la,
                                const fm_outputs &out, hipStream_t st);
 hipError_t launch_loss_reduce(const Plan &p, void *ws, float *loss, hipStream_t st);
-// one-wave-per-tile variants of the blend kernels (same contracts)
-hipError_t launch_render_fwd_slots(const Plan &p, void *ws, const KParams &kp, const fm_outputs &out,
-                                   hipStream_t st);
-hipError_t launch_render_bwd_slots(const Plan &p, void *ws, const KParams &kp, const fm_outputs &out,
-                                   const fm_grad_outputs &g, hipStream_t st);
-hipError_t launch_render_fused_slots(const Plan &p, void *ws, const KParams &kp, const LossArgs &la,
-                                     const fm_outputs &out, hipStream_t st);
 hipError_t launch_zero_grad(const Plan &p, void *ws, hipStream_t st);
 hipError_t launch_preprocess_bwd(const Plan &p, void *ws, const float *intr, const float *viewmat,
                                  float *dL_dviewmat, hipStream_t st);
