@@ -47,12 +47,13 @@ __device__ __forceinline__ void load_surf(const Rec *rp, Surf &s) {
 // the plane at (u, v) = (w0, w1) / w2 with w = c0 + x' c2 - y' c1.
 // Stage 1 decides `in`: the lane is live and u^2 + v^2 <= rho_max^2.
 // Stage 2 evaluates G = exp(-r^2/2) and alpha = min(alpha_max, sigma G),
-// with `hit` = in and sigma G >= alpha_min; lanes that miss get alpha = 0,
-// G = 0, r2 = 0 and w2 = 1, so every downstream value stays finite and their
-// contributions vanish.  Forward and backward run the same instructions on
-// the same inputs and so take the same decisions.
+// with `hit` = in and sigma G >= alpha_min.  Lanes that miss get alpha = 0
+// (so T and the weights do not move) and r2 = w0 = w1 = 0, w2 = rden = 1, so
+// that every gradient term they form is an exact zero.  Forward and backward
+// run the same instructions on the same inputs and so take the same
+// decisions.
 struct Hit {
-    float xp, yp, w0, w1, w2, num, den, r2;
+    float xp, yp, w0, w1, w2, num, den, r2, rden;
     float G, at, alpha;
     bool in, hit;
 };
@@ -71,15 +72,14 @@ __device__ __forceinline__ void splat_geom(const Surf &s, float px, float py, fl
 
 __device__ __forceinline__ void splat_alpha(const Surf &s, float amin, float amax, Hit &h) {
 #pragma clang fp contract(off)
-    const float den = h.in ? h.den : 1.f;
-    const float r2 = h.num * __builtin_amdgcn_rcpf(den);
-    h.r2 = h.in ? r2 : 0.f;
-    const float G = __builtin_amdgcn_exp2f(h.r2 * -0.72134752044448170368f);  // exp(-r2/2)
-    const float at = s.sig * G;
-    h.hit = h.in && (at >= amin);
-    h.G = h.hit ? G : 0.f;
-    h.at = h.hit ? at : 0.f;
-    h.alpha = h.hit ? (at > amax ? amax : at) : 0.f;
+    h.rden = __builtin_amdgcn_rcpf(h.in ? h.den : 1.f);
+    h.r2 = h.in ? h.num * h.rden : 0.f;
+    h.G = __builtin_amdgcn_exp2f(h.r2 * -0.72134752044448170368f);  // exp(-r2/2)
+    h.at = s.sig * h.G;
+    h.hit = h.in && (h.at >= amin);
+    h.alpha = h.hit ? (h.at > amax ? amax : h.at) : 0.f;
+    h.rden = h.hit ? h.rden : 1.f;
+    h.r2 = h.hit ? h.r2 : 0.f;
     h.w2 = h.hit ? h.w2 : 1.f;
     h.w0 = h.hit ? h.w0 : 0.f;
     h.w1 = h.hit ? h.w1 : 0.f;
@@ -294,10 +294,10 @@ __device__ __forceinline__ void tile_backward(const TileCtx &c, const Slots<TW, 
                     }
                     // G = exp(-r2/2), r2 = (w0^2 + w1^2) / w2^2, w = c0 + x' c2 - y' c1
                     gr[9] = fmaf(du, h.G, gr[9]);
+                    // dr2/dw0 = 2 w0 / w2^2, dr2/dw1 = 2 w1 / w2^2, dr2/dw2 = -2 r2 w2 / w2^2
                     const float dr2 = -0.5f * h.G * s.sig * du;
-                    const float iw = __builtin_amdgcn_rcpf(h.w2);
-                    const float qq = 2.f * dr2 * iw;
-                    const float gw0 = qq * h.w0 * iw, gw1 = qq * h.w1 * iw, gw2 = -qq * h.r2;
+                    const float kk = 2.f * dr2 * h.rden;
+                    const float gw0 = kk * h.w0, gw1 = kk * h.w1, gw2 = -kk * h.r2 * h.w2;
                     gr[0] += gw0;
                     gr[1] += gw1;
                     gr[2] += gw2;

@@ -48,10 +48,23 @@ __global__ __launch_bounds__(256) void k_radix_hist(const uint32_t *__restrict__
     __syncthreads();
     uint32_t lo, hi;
     chunk_of(count_of(n_dev, n_host), G, lo, hi);
-    for (uint32_t i = lo + threadIdx.x; i < hi; i += 256) {
-        const uint32_t key = keys[i];
-        if (drop && key == kNoKey) continue;
-        atomicAdd(&h[w][(key >> shift) & 0xFFu], 1u);
+    const int lane = lane_id();
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    // lanes of a wave with equal digits are matched through ballots and their
+    // lowest lane adds the group's size: one LDS atomic per distinct digit
+    for (uint32_t base = lo; base < hi; base += 256) {
+        const uint32_t i = base + threadIdx.x;
+        const uint32_t key = i < hi ? keys[i] : kNoKey;
+        const bool ok = i < hi && !(drop && key == kNoKey);
+        const uint32_t d = (key >> shift) & 0xFFu;
+        uint64_t m = ballot64(ok);
+#pragma unroll
+        for (int b = 0; b < kRadixBits; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t bb = ballot64(bit);
+            m &= bit ? bb : ~bb;
+        }
+        if (ok && (m & lt) == 0) atomicAdd(&h[w][d], (uint32_t)__popcll(m));
     }
     __syncthreads();
     const uint32_t c = h[0][threadIdx.x] + h[1][threadIdx.x] + h[2][threadIdx.x] + h[3][threadIdx.x];
