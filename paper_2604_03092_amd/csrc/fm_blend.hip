@@ -45,15 +45,17 @@ __device__ __forceinline__ void load_surf(const Rec *rp, Surf &s) {
 // Ray-splat intersection at the pixel centre (px, py), evaluated for every
 // lane without branches.  In the surfel's shifted pixel frame the ray meets
 // the plane at (u, v) = (w0, w1) / w2 with w = c0 + x' c2 - y' c1.
-// Stage 1 decides `in`: the lane is live and u^2 + v^2 <= rho_max^2.
+// Stage 1 decides `in`: the lane is live and u^2 + v^2 <= rho_max^2 (a ray
+// with w2^2 below 1e-30, parallel to the plane to FP32 precision, is out).
 // Stage 2 evaluates G = exp(-r^2/2) and alpha = min(alpha_max, sigma G),
-// with `hit` = in and sigma G >= alpha_min.  Lanes that miss get alpha = 0
-// (so T and the weights do not move) and r2 = w0 = w1 = 0, w2 = rden = 1, so
-// that every gradient term they form is an exact zero.  Forward and backward
-// run the same instructions on the same inputs and so take the same
-// decisions.
+// with `hit` = in and sigma G >= alpha_min.  Lanes that miss get alpha = 0,
+// so T and the weights do not move, and finite r2, rden, G; the adjoint
+// zeroes their gradient terms.  Forward and backward run the same
+// instructions on the same inputs and so take the same decisions.
+constexpr float kMinDen = 1e-30f;
+
 struct Hit {
-    float xp, yp, w0, w1, w2, num, den, r2, rden;
+    float xp, yp, w0, w1, w2, num, den, rden, r2;
     float G, at, alpha;
     bool in, hit;
 };
@@ -67,7 +69,7 @@ __device__ __forceinline__ void splat_geom(const Surf &s, float px, float py, fl
     h.w2 = fmaf(h.xp, s.c22, fmaf(-h.yp, s.c12, s.c02));
     h.num = fmaf(h.w0, h.w0, h.w1 * h.w1);
     h.den = h.w2 * h.w2;
-    h.in = live && (h.num <= rho2 * h.den) && (h.den > 0.f);
+    h.in = live && (h.num <= rho2 * h.den) && (h.den > kMinDen);
 }
 
 __device__ __forceinline__ void splat_alpha(const Surf &s, float amin, float amax, Hit &h) {
@@ -77,12 +79,7 @@ __device__ __forceinline__ void splat_alpha(const Surf &s, float amin, float ama
     h.G = __builtin_amdgcn_exp2f(h.r2 * -0.72134752044448170368f);  // exp(-r2/2)
     h.at = s.sig * h.G;
     h.hit = h.in && (h.at >= amin);
-    h.alpha = h.hit ? (h.at > amax ? amax : h.at) : 0.f;
-    h.rden = h.hit ? h.rden : 1.f;
-    h.r2 = h.hit ? h.r2 : 0.f;
-    h.w2 = h.hit ? h.w2 : 1.f;
-    h.w0 = h.hit ? h.w0 : 0.f;
-    h.w1 = h.hit ? h.w1 : 0.f;
+    h.alpha = h.hit ? __builtin_fminf(h.at, amax) : 0.f;
 }
 
 template <int TW, int TH> struct Geo {
@@ -222,6 +219,53 @@ __device__ __forceinline__ void tile_forward(const TileCtx &c, const Slots<TW, T
     }
 }
 
+// Adjoint terms of one hit slot, added into the lane's per-surfel gradient
+// registers (gr: dL/dc0[3], dL/dc1[3], dL/dc2[3], dL/dsigma, dL/d(r, g, b),
+// dL/dz, dL/dn[0..1]; gn2: dL/dn[2]).  FIRST: the first slot of the surfel,
+// which assigns instead of adding.  Also steps S_k and T of the slot.
+template <bool FIRST, bool HAS_N>
+__device__ __forceinline__ void adjoint_terms(const Hit &h, const Surf &s, const float (&gq)[8], float Sq,
+                                              float &Skq, float &Tq, float amax, float (&gr)[16], float &gn2) {
+#pragma clang fp contract(off)
+    auto mac = [](float &d, float a, float b) { d = FIRST ? a * b : fmaf(a, b, d); };
+    auto add = [](float &d, float v) { d = FIRST ? v : d + v; };
+    // lanes that miss have alpha = 0: wgt = 0 and T is unchanged
+    const float test = Tq * (1.f - h.alpha);
+    const float wgt = h.alpha * Tq;
+    float f = fmaf(gq[0], s.r, fmaf(gq[1], s.g, fmaf(gq[2], s.b, fmaf(gq[3], s.z, gq[7]))));
+    if (HAS_N) f = fmaf(gq[4], s.n0, fmaf(gq[5], s.n1, fmaf(gq[6], s.n2, f)));
+    Skq = fmaf(f, wgt, Skq);
+    const float dal = fmaf(-(Sq - Skq), __builtin_amdgcn_rcpf(1.f - h.alpha), Tq * f);
+    // alpha = sigma G below the clamp; above it alpha carries no gradient
+    const float du = (h.hit && h.at <= amax) ? dal : 0.f;
+    mac(gr[10], gq[0], wgt);
+    mac(gr[11], gq[1], wgt);
+    mac(gr[12], gq[2], wgt);
+    mac(gr[13], gq[3], wgt);
+    if (HAS_N) {
+        mac(gr[14], gq[4], wgt);
+        mac(gr[15], gq[5], wgt);
+        mac(gn2, gq[6], wgt);
+    }
+    // G = exp(-r2/2), r2 = (w0^2 + w1^2) / w2^2, w = c0 + x' c2 - y' c1:
+    // dL/dsigma = du G, dL/dr2 = -du sigma G / 2, and
+    // dr2/dw = (2 w0, 2 w1, -2 r2 w2) / w2^2
+    mac(gr[9], du, h.G);
+    const float kk = -(du * h.at) * h.rden;
+    const float w0 = h.hit ? h.w0 : 0.f, w1 = h.hit ? h.w1 : 0.f, w2 = h.hit ? h.w2 : 0.f;
+    const float gw0 = kk * w0, gw1 = kk * w1, gw2 = -(kk * h.r2) * w2;
+    add(gr[0], gw0);
+    add(gr[1], gw1);
+    add(gr[2], gw2);
+    mac(gr[3], -h.yp, gw0);
+    mac(gr[4], -h.yp, gw1);
+    mac(gr[5], -h.yp, gw2);
+    mac(gr[6], h.xp, gw0);
+    mac(gr[7], h.xp, gw1);
+    mac(gr[8], h.xp, gw2);
+    Tq = test;
+}
+
 // Adjoint traversal.  g[q] = dL/d(r, g, b, depth, nx, ny, nz, A) of slot q's
 // pixel, S[q] = g[q] . outputs, nl[q] = its contributor prefix length.
 // HAS_N: the normal map carries a gradient.
@@ -258,11 +302,12 @@ __device__ __forceinline__ void tile_backward(const TileCtx &c, const Slots<TW, 
             if (m == 0) continue;
             Surf s;
             load_surf(&srec[j], s);
-            float gr[16];
-#pragma unroll
-            for (int i = 0; i < 16; ++i) gr[i] = 0.f;
-            float gn2 = 0.f;
-            bool hit = false;
+            // per-surfel gradient registers, written (not added) by the first hit
+            // slot, so nothing is carried from the previous surfel; without
+            // normal gradients gr[14], gr[15] are zero
+            float gr[16], gn2;
+            if (!HAS_N) gr[14] = gr[15] = 0.f;
+            bool first = true;
 #pragma unroll
             for (int q = 0; q < Gm::NB; ++q) {
                 if (((m >> q) & 1u) == 0) continue;
@@ -271,49 +316,16 @@ __device__ __forceinline__ void tile_backward(const TileCtx &c, const Slots<TW, 
                 if (ballot64(h.in) == 0) continue;
                 splat_alpha(s, kp.alpha_min, kp.alpha_max, h);
                 if (ballot64(h.hit) == 0) continue;
-                {
-#pragma clang fp contract(off)
-                    hit = hit || h.hit;
-                    // lanes that miss have alpha = 0: wgt = 0 and T is unchanged
-                    const float test = T[q] * (1.f - h.alpha);
-                    const float wgt = h.alpha * T[q];
-                    float f = g[q][0] * s.r + g[q][1] * s.g + g[q][2] * s.b + g[q][3] * s.z + g[q][7];
-                    if (HAS_N) f += g[q][4] * s.n0 + g[q][5] * s.n1 + g[q][6] * s.n2;
-                    Sk[q] = fmaf(f, wgt, Sk[q]);
-                    const float dal = T[q] * f - (S[q] - Sk[q]) * __builtin_amdgcn_rcpf(1.f - h.alpha);
-                    // alpha = sigma G below the clamp; above it alpha carries no gradient
-                    const float du = (h.hit && h.at <= kp.alpha_max) ? dal : 0.f;
-                    gr[10] = fmaf(g[q][0], wgt, gr[10]);
-                    gr[11] = fmaf(g[q][1], wgt, gr[11]);
-                    gr[12] = fmaf(g[q][2], wgt, gr[12]);
-                    gr[13] = fmaf(g[q][3], wgt, gr[13]);
-                    if (HAS_N) {
-                        gr[14] = fmaf(g[q][4], wgt, gr[14]);
-                        gr[15] = fmaf(g[q][5], wgt, gr[15]);
-                        gn2 = fmaf(g[q][6], wgt, gn2);
-                    }
-                    // G = exp(-r2/2), r2 = (w0^2 + w1^2) / w2^2, w = c0 + x' c2 - y' c1
-                    gr[9] = fmaf(du, h.G, gr[9]);
-                    // dr2/dw0 = 2 w0 / w2^2, dr2/dw1 = 2 w1 / w2^2, dr2/dw2 = -2 r2 w2 / w2^2
-                    const float dr2 = -0.5f * h.G * s.sig * du;
-                    const float kk = 2.f * dr2 * h.rden;
-                    const float gw0 = kk * h.w0, gw1 = kk * h.w1, gw2 = -kk * h.r2 * h.w2;
-                    gr[0] += gw0;
-                    gr[1] += gw1;
-                    gr[2] += gw2;
-                    gr[3] = fmaf(-h.yp, gw0, gr[3]);
-                    gr[4] = fmaf(-h.yp, gw1, gr[4]);
-                    gr[5] = fmaf(-h.yp, gw2, gr[5]);
-                    gr[6] = fmaf(h.xp, gw0, gr[6]);
-                    gr[7] = fmaf(h.xp, gw1, gr[7]);
-                    gr[8] = fmaf(h.xp, gw2, gr[8]);
-                    T[q] = test;
-                }
+                if (first)
+                    adjoint_terms<true, HAS_N>(h, s, g[q], S[q], Sk[q], T[q], kp.alpha_max, gr, gn2);
+                else
+                    adjoint_terms<false, HAS_N>(h, s, g[q], S[q], Sk[q], T[q], kp.alpha_max, gr, gn2);
+                first = false;
             }
-            if (ballot64(hit) == 0) continue;
+            if (first) continue;  // no lane of the tile is hit by this surfel
             const float r = wave_reduce16(gr);
             float *dst = grad + (int64_t)(sval[j] & kEntryMask) * kGradStride;
-            if (comp >= 0) atomicAdd(dst + comp, r);
+            if (comp >= 0 && (HAS_N || comp < 14)) atomicAdd(dst + comp, r);  // 14, 15: normal terms
             if (HAS_N) {
                 const float t2 = wave_sum(gn2);
                 if (lane_id() == 0) atomicAdd(dst + 16, t2);
@@ -372,7 +384,7 @@ __global__ __launch_bounds__(64) void k_render_bwd(const ViewDesc *__restrict__ 
 #pragma unroll
     for (int q = 0; q < Gm::NB; ++q) {
 #pragma unroll
-        for (int k = 0; k < 8; ++k) g[q][k] = 0.f;
+        for (int k = 0; k < 8; ++k) g[q][k] = -0.f;
         S[q] = 0.f;
         nl[q] = 0;
         if (!sl.inside[q]) continue;
@@ -419,7 +431,7 @@ __global__ __launch_bounds__(64) void k_render_fused(const ViewDesc *__restrict_
 #pragma unroll
     for (int q = 0; q < Gm::NB; ++q) {
 #pragma unroll
-        for (int k = 0; k < 8; ++k) g[q][k] = 0.f;
+        for (int k = 0; k < 8; ++k) g[q][k] = -0.f;
         S[q] = 0.f;
         if (!sl.inside[q]) {
             nl[q] = 0;

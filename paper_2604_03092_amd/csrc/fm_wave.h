@@ -25,12 +25,22 @@ __device__ __forceinline__ float row_sum(float x) {
     return x;
 }
 
+// DPP move within 16-lane rows (all lanes active).  CTRL: 0x120 + N rotates
+// right by N, 0x141 mirrors each 8-lane half (lane j <- lane j ^ 7),
+// 0xB1 / 0x4E swap lanes j ^ 1 / j ^ 2 inside each quad.
+template <int CTRL> __device__ __forceinline__ float dpp(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+
 // Transposing reduction of 16 values over the wave.  Every lane holds
-// v[0..15]; on return, the lane with (lane & 15) < 4 holds the wave sum of
-// component 4 * (lane >> 4) + (lane & 15); other lanes hold junk.
-// Steps: v_permlane32_swap pairs component c with c+8 across wave halves,
-// v_permlane16_swap pairs c with c+4 across rows, then a DPP row sum of the
-// remaining four components.  Must run with all 64 lanes active.
+// v[0..15]; on return, every lane holds the wave sum of component
+// 4 * (lane >> 4) + ((lane >> 2) & 3) (the four lanes of a quad agree).
+// Each step halves the values a lane carries and doubles the lanes a value
+// spans: v_permlane32_swap pairs component c with c+8 across wave halves,
+// v_permlane16_swap pairs c with c+4 across rows, then inside each row a
+// rotation by 8 pairs c with c+2, a half mirror pairs c with c+1, and two
+// quad swaps finish the sums.  v is overwritten.  Must run with all 64
+// lanes active.
 __device__ __forceinline__ float wave_reduce16(float v[16]) {
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
@@ -44,17 +54,25 @@ __device__ __forceinline__ float wave_reduce16(float v[16]) {
                                                   false, false);
         v[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
     }
-    const float r0 = row_sum(v[0]), r1 = row_sum(v[1]), r2 = row_sum(v[2]), r3 = row_sum(v[3]);
+    // row r now holds components 4r + 0..3 in v[0..3], each partial over its 16 lanes
     const int j = lane_id();
-    const float lo = (j & 1) ? r1 : r0;
-    const float hi = (j & 1) ? r3 : r2;
-    return (j & 2) ? hi : lo;
+    const bool b3 = (j & 8) != 0, b2 = (j & 4) != 0;
+    const float t0 = b3 ? v[2] : v[0], u0 = b3 ? v[0] : v[2];
+    const float t1 = b3 ? v[3] : v[1], u1 = b3 ? v[1] : v[3];
+    const float a0 = t0 + dpp<0x128>(u0);  // component 2 b3,     over lanes j, j ^ 8
+    const float a1 = t1 + dpp<0x128>(u1);  // component 2 b3 + 1
+    const float keep = b2 ? a1 : a0, give = b2 ? a0 : a1;
+    float x = keep + dpp<0x141>(give);     // component 2 b3 + b2, over 4 lanes
+    x += dpp<0xB1>(x);
+    x += dpp<0x4E>(x);
+    return x;
 }
 
-// Component index held by this lane after wave_reduce16 (or -1).
+// Component index held by this lane after wave_reduce16, for one lane per
+// quad (the others get -1).
 __device__ __forceinline__ int wave_reduce16_component() {
     const int l = lane_id();
-    return ((l & 15) < 4) ? (4 * (l >> 4) + (l & 15)) : -1;
+    return ((l & 3) == 0) ? (4 * (l >> 4) + ((l >> 2) & 3)) : -1;
 }
 
 // Plain wave sum broadcast to all lanes (all lanes active).
