@@ -26,7 +26,7 @@ constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 constexpr int kSortBlock = 256;    // threads per radix-sort block
 constexpr int kScanChunk = 2048;   // entries per block of the count scan
-constexpr int kMaxSortGrid = 2048;
+constexpr int kMaxSortGrid = 1024;
 constexpr int kEmitChunk = 2048;   // pairs per iteration of the emission blocks
 constexpr int kMaxEmitGrid = 4096;
 constexpr int kMaxPasses = 8;      // radix passes per binning (4 depth + up to 4 tile)
@@ -73,18 +73,24 @@ struct alignas(16) Rec {
 };
 static_assert(sizeof(Rec) == 80, "record layout");
 
-// Image-space support ellipse of one entry, used to cull 8x8 pixel blocks:
-// centre (ex, ey) and shape S, the ellipse being
-// {p : (p - e)^T S^-1 (p - e) <= 1}; its radius includes the opacity cut-off
-// and a small safety enlargement.  The entry's tile rect (from the canonical
-// inclusive pixel-centre bbox) rides along for the pair emission: tb is the
-// batch-global id of its top-left tile, t0 = tx0 | ty0 << 16 that tile's
-// position in the view, nt = (tiles per rect row) | (tiles_x of the view) << 16.
+// Image-space support ellipse of one entry, used to cull 8x8 pixel blocks.
+// The ellipse {p : (p - e)^T S^-1 (p - e) <= 1} (radius including the
+// opacity cut-off and a small safety enlargement) is kept in the form the
+// emission evaluates: centre (ex, ey), half-extents hx = sqrt(S00),
+// hy = sqrt(S11), the slice at height dy spanning
+// k1 dy +- sqrt(k2 (hy^2 - dy^2)) with k1 = S01 / S11, k2 = det S / S11^2,
+// and dyr = S01 / hx, the height of its rightmost point (S in FP64, the
+// derived values in FP32).  The entry's tile rect (from the canonical inclusive
+// pixel-centre bbox) rides along: tb is the batch-global id of its top-left
+// tile, t0 = tx0 | ty0 << 16 that tile's position in the view,
+// nt = (tiles per rect row) | (tiles_x of the view) << 16.
 struct alignas(16) Ell {
-    float ex, ey, s00, s01, s11;
-    uint32_t tb, t0, nt;
+    float ex, ey, hx, hy;
+    float k1, k2, dyr;
+    uint32_t tb;
+    uint32_t t0, nt, pad[2];
 };
-static_assert(sizeof(Ell) == 32, "ellipse layout");
+static_assert(sizeof(Ell) == 48, "ellipse layout");
 
 // Pair values: entry id in the low 28 bits, 8x8-block mask of the tile in the
 // high 4 bits (bit b set when block b of the tile may hold a covered pixel).

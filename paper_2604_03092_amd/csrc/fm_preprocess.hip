@@ -189,12 +189,22 @@ __global__ __launch_bounds__(256) void k_preprocess(const ViewDesc *__restrict__
                             const double E12 = re2 * (H[3] * H[6] + H[4] * H[7]) - H[5] * H[8];
                             const double E22 = re2 * (H[6] * H[6] + H[7] * H[7]) - H[8] * H[8];
                             const double i22 = 1.0 / E22, k = 1.002 * i22 * i22;
+                            // shape in FP64, the derived slice form in FP32 (the
+                            // enlargement above dwarfs its rounding)
+                            const double s00 = (E02 * E02 - E00 * E22) * k;
+                            const double s01 = (E02 * E12 - E01 * E22) * k;
+                            const double s11 = (E12 * E12 - E11 * E22) * k;
+                            const float f00 = (float)s00, f01 = (float)s01, f11 = (float)s11;
+                            const float fdet = (float)(s00 * s11 - s01 * s01);
                             Ell el;
                             el.ex = (float)(E02 * i22);
                             el.ey = (float)(E12 * i22);
-                            el.s00 = (float)((E02 * E02 - E00 * E22) * k);
-                            el.s01 = (float)((E02 * E12 - E01 * E22) * k);
-                            el.s11 = (float)((E12 * E12 - E11 * E22) * k);
+                            el.hx = f00 > 0.f ? sqrtf(f00) : 0.f;
+                            el.hy = f11 > 0.f ? sqrtf(f11) : 0.f;
+                            el.k1 = f11 > 0.f ? f01 / f11 : 0.f;
+                            el.k2 = f11 > 0.f && fdet > 0.f ? (fdet / f11) / f11 : 0.f;
+                            el.dyr = el.hx > 0.f ? f01 / el.hx : 0.f;
+                            el.pad[0] = el.pad[1] = 0u;
                             const int tx0 = px0 / kp.tile_w, tx1 = px1 / kp.tile_w;
                             const int ty0 = py0 / kp.tile_h;
                             el.tb = (uint32_t)(vd.tile_base + ty0 * vd.tiles_x + tx0);

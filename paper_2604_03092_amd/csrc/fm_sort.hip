@@ -191,17 +191,22 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t *__restric
 
 // ---- pair count scan and emission -----------------------------------------
 
-// Block b sums the tile counts of sorted entries [b*kScanChunk, ...).
+// Block b sums the tile counts of sorted entries [b*kScanChunk, ...) and
+// stores them in sorted order (cnt_sorted) for the offset pass.
 __global__ __launch_bounds__(256) void k_count_reduce(const uint32_t *__restrict__ sorted_entry,
                                                        const uint32_t *__restrict__ cnt, const uint32_t *n_vis,
-                                                       uint32_t *__restrict__ blk) {
+                                                       uint32_t *__restrict__ blk, uint32_t *__restrict__ cnt_sorted) {
     __shared__ uint32_t red[4];
     const int64_t E = *n_vis;
     const int64_t lo = (int64_t)blockIdx.x * kScanChunk;
     int64_t hi = lo + kScanChunk;
     if (hi > E) hi = E;
     uint32_t s = 0;
-    for (int64_t k = lo + threadIdx.x; k < hi; k += 256) s += cnt[sorted_entry[k]];
+    for (int64_t k = lo + threadIdx.x; k < hi; k += 256) {
+        const uint32_t c = cnt[sorted_entry[k]];
+        cnt_sorted[k] = c;
+        s += c;
+    }
     for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
     if (lane_id() == 0) red[threadIdx.x >> 6] = s;
     __syncthreads();
@@ -242,29 +247,26 @@ __global__ __launch_bounds__(1024) void k_count_scan(const uint32_t *__restrict_
 
 // Which 8x8 pixel blocks of the tile with origin (x0, y0) may hold a pixel
 // centre inside the entry's culling ellipse.  Per block row, the x-extent of
-// the ellipse over that row band is the hull of the slice at the clamped band
-// edges and of the leftmost/rightmost points when they fall inside the band;
-// it is widened by 0.01 px against FP32 rounding.
+// the ellipse over that row band is the hull of the slices at the clamped
+// band edges and of the leftmost/rightmost points when they fall inside the
+// band; it is widened by 0.01 px, which covers the FP32 rounding here
+// (hardware square root and reciprocal, 1 ulp).
 __device__ inline uint32_t block_mask(const Ell &el, int x0, int y0, int tw, int th) {
-    const float hy = sqrtf(fmaxf(el.s11, 0.f));
-    const float hx = sqrtf(fmaxf(el.s00, 0.f));
-    const float ds = fmaxf(el.s00 * el.s11 - el.s01 * el.s01, 0.f);
-    const float is11 = el.s11 > 0.f ? 1.f / el.s11 : 0.f;
-    const float dy_r = hx > 0.f ? el.s01 / hx : 0.f;  // height of the rightmost point
+    const float hy2 = el.hy * el.hy;
     const int bw = tw >> 3, bh = th >> 3;
     uint32_t mask = 0;
     for (int br = 0; br < bh; ++br) {
         float dy0 = (float)(y0 + 8 * br) + 0.5f - el.ey - 0.01f;
         float dy1 = (float)(y0 + 8 * br) + 7.5f - el.ey + 0.01f;
-        dy0 = fmaxf(dy0, -hy);
-        dy1 = fminf(dy1, hy);
+        dy0 = fmaxf(dy0, -el.hy);
+        dy1 = fminf(dy1, el.hy);
         if (!(dy0 <= dy1)) continue;
-        const float q0 = sqrtf(fmaxf(ds * (el.s11 - dy0 * dy0), 0.f));
-        const float q1 = sqrtf(fmaxf(ds * (el.s11 - dy1 * dy1), 0.f));
-        float xmax = fmaxf(el.s01 * dy0 + q0, el.s01 * dy1 + q1) * is11;
-        float xmin = fminf(el.s01 * dy0 - q0, el.s01 * dy1 - q1) * is11;
-        if (dy_r >= dy0 && dy_r <= dy1) xmax = hx;
-        if (-dy_r >= dy0 && -dy_r <= dy1) xmin = -hx;
+        const float q0 = __builtin_amdgcn_sqrtf(fmaxf(el.k2 * (hy2 - dy0 * dy0), 0.f));
+        const float q1 = __builtin_amdgcn_sqrtf(fmaxf(el.k2 * (hy2 - dy1 * dy1), 0.f));
+        float xmax = fmaxf(el.k1 * dy0 + q0, el.k1 * dy1 + q1);
+        float xmin = fminf(el.k1 * dy0 - q0, el.k1 * dy1 - q1);
+        if (el.dyr >= dy0 && el.dyr <= dy1) xmax = el.hx;
+        if (-el.dyr >= dy0 && -el.dyr <= dy1) xmin = -el.hx;
         xmax += el.ex + 0.01f;
         xmin += el.ex - 0.01f;
         for (int bc = 0; bc < bw; ++bc) {
@@ -284,8 +286,7 @@ __device__ inline uint32_t block_mask(const Ell &el, int x0, int y0, int tw, int
 // its sorted index into chunk_first.  Visible entries cover at least one
 // tile, so chunk c's pairs belong to entries chunk_first[c] .. chunk_first[c+1].
 constexpr int kPer = kScanChunk / 256;
-__global__ __launch_bounds__(256) void k_offsets(const uint32_t *__restrict__ sorted_entry,
-                                                  const uint32_t *__restrict__ cnt, const uint32_t *n_vis,
+__global__ __launch_bounds__(256) void k_offsets(const uint32_t *__restrict__ cnt_sorted, const uint32_t *n_vis,
                                                   const uint64_t *__restrict__ blk_off, uint64_t cap,
                                                   uint32_t *__restrict__ off32, uint32_t *__restrict__ chunk_first) {
     __shared__ uint32_t wsum[4];
@@ -296,7 +297,7 @@ __global__ __launch_bounds__(256) void k_offsets(const uint32_t *__restrict__ so
     const int64_t k0 = lo + (int64_t)threadIdx.x * kPer;
     uint32_t c[kPer];
 #pragma unroll
-    for (int i = 0; i < kPer; ++i) c[i] = k0 + i < E ? cnt[sorted_entry[k0 + i]] : 0u;
+    for (int i = 0; i < kPer; ++i) c[i] = k0 + i < E ? cnt_sorted[k0 + i] : 0u;
     uint32_t run = 0;
 #pragma unroll
     for (int i = 0; i < kPer; ++i) run += c[i];
@@ -396,7 +397,11 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t *__restrict__ sorte
             const uint32_t r = p0 + q - s_off[i];
             const Ell el = ell[ent];
             const uint32_t ntx = el.nt & 0xFFFFu, tiles_x = el.nt >> 16;
-            const uint32_t ry = r / ntx, rx = r - ry * ntx;
+            // r / ntx: r < 2^24, so the float estimate is off by at most one
+            uint32_t ry = (uint32_t)((float)r * __builtin_amdgcn_rcpf((float)ntx));
+            if (ry * ntx > r) --ry;
+            else if ((ry + 1u) * ntx <= r) ++ry;
+            const uint32_t rx = r - ry * ntx;
             const int tx = (int)(el.t0 & 0xFFFFu) + (int)rx, ty = (int)(el.t0 >> 16) + (int)ry;
             const uint32_t mask = block_mask(el, tx * kp.tile_w, ty * kp.tile_h, kp.tile_w, kp.tile_h);
             pkey[p0 + q] = el.tb + ry * tiles_x + rx;
@@ -455,8 +460,10 @@ hipError_t launch_binning(const Plan &p, void *ws, const KParams &kp, hipStream_
     // 2. pair offsets in depth order and emission
     uint32_t *blk = at<uint32_t>(ws, p.o_scan);
     uint64_t *blk_off = reinterpret_cast<uint64_t *>(blk + ((p.scan_blocks + 63) & ~63));
+    // the ping-pong key buffer is free after the last pass: it holds the counts in depth order
+    uint32_t *cnt_sorted = key2;
     hipLaunchKernelGGL(k_count_reduce, dim3(p.scan_blocks), dim3(256), 0, st, val, at<uint32_t>(ws, p.o_cnt),
-                       n_vis, blk);
+                       n_vis, blk, cnt_sorted);
     hipLaunchKernelGGL(k_count_scan, dim3(1), dim3(1024), 0, st, blk, p.scan_blocks, blk_off, status,
                        (uint64_t)p.cap);
     uint32_t *pkey = at<uint32_t>(ws, p.o_pkey), *pval = at<uint32_t>(ws, p.o_pval);
@@ -464,8 +471,8 @@ hipError_t launch_binning(const Plan &p, void *ws, const KParams &kp, hipStream_
     // the sorted depth keys are dead after the last pass: their buffer holds the offsets
     uint32_t *off32 = key;
     uint32_t *chunk_first = at<uint32_t>(ws, p.o_chunk);
-    hipLaunchKernelGGL(k_offsets, dim3(p.scan_blocks), dim3(256), 0, st, val, at<uint32_t>(ws, p.o_cnt), n_vis,
-                       blk_off, (uint64_t)p.cap, off32, chunk_first);
+    hipLaunchKernelGGL(k_offsets, dim3(p.scan_blocks), dim3(256), 0, st, cnt_sorted, n_vis, blk_off,
+                       (uint64_t)p.cap, off32, chunk_first);
     hipLaunchKernelGGL(k_emit, dim3(p.emit_blocks), dim3(256), 0, st, val, off32, n_vis, chunk_first, status,
                        at<Ell>(ws, p.o_ell), kp, pkey, pval);
     // 3. stable sort of the pairs by tile id
