@@ -115,9 +115,11 @@ typedef struct {
 
 /* Rasterization parameters; fm_default_params fills the defaults. */
 typedef struct {
-    float alpha_min;   /* 1/255: skip a surfel at a pixel when sigma G < alpha_min */
+    float alpha_min;   /* 1/255: skip a surfel at a pixel when sigma G < alpha_min
+                          (>= 1e-6, so every composited surfel lowers T)         */
     float alpha_max;   /* 0.99: clamp of alpha (must be < 1 for the backward)     */
-    float t_min;       /* 1e-4: stop before the transmittance would fall below it */
+    float t_min;       /* 1e-4: stop before the transmittance would fall below it
+                          (>= 1e-30)                                             */
     float rho_max;     /* 3: support radius in units of the tangent scales        */
     float near_plane;  /* 0.2: cull surfels with centre depth <= near_plane       */
     float bg[3];       /* background colour added with weight T_final             */

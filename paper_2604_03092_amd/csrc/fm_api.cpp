@@ -97,11 +97,11 @@ fm_status build(fm_ctx *ctx, const fm_batch *b, const fm_raster_params *prm, int
     if (b->n_views < 1 || b->n_submaps < 1 || !b->views || !b->submaps)
         return fail(ctx, FM_ERR_INVALID_ARG, "a batch needs >= 1 view, >= 1 submap and host arrays for both");
     if (!b->intr || !b->viewmat) return fail(ctx, FM_ERR_INVALID_ARG, "intr and viewmat must not be NULL");
-    if (!(prm->alpha_min > 0.f) || !(prm->alpha_max > prm->alpha_min) || !(prm->alpha_max <= 1.f))
-        return fail(ctx, FM_ERR_INVALID_ARG, "need 0 < alpha_min < alpha_max <= 1");
+    if (!(prm->alpha_min >= 1e-6f) || !(prm->alpha_max > prm->alpha_min) || !(prm->alpha_max <= 1.f))
+        return fail(ctx, FM_ERR_INVALID_ARG, "need 1e-6 <= alpha_min < alpha_max <= 1");
     if (need_backward && !(prm->alpha_max < 1.f))
         return fail(ctx, FM_ERR_INVALID_ARG, "the backward needs alpha_max < 1");
-    if (!(prm->t_min > 0.f && prm->t_min < 1.f)) return fail(ctx, FM_ERR_INVALID_ARG, "need 0 < t_min < 1");
+    if (!(prm->t_min >= 1e-30f && prm->t_min < 1.f)) return fail(ctx, FM_ERR_INVALID_ARG, "need 1e-30 <= t_min < 1");
     if (!(prm->rho_max > 0.f && std::isfinite(prm->rho_max)))
         return fail(ctx, FM_ERR_INVALID_ARG, "need rho_max > 0");
     if (!(prm->near_plane > 0.f && std::isfinite(prm->near_plane)))

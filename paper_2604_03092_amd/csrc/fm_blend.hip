@@ -49,8 +49,7 @@ __device__ __forceinline__ void load_surf(const Rec *rp, Surf &s) {
 // with w2^2 below 1e-30, parallel to the plane to FP32 precision, is out).
 // Stage 2 evaluates G = exp(-r^2/2) and alpha = min(alpha_max, sigma G),
 // with `hit` = in and sigma G >= alpha_min.  Lanes that miss get alpha = 0,
-// so T and the weights do not move, and finite r2, rden, G; the adjoint
-// zeroes their gradient terms.  Forward and backward run the same
+// so T and the weights do not move; the adjoint zeroes their gradient terms.  Forward and backward run the same
 // instructions on the same inputs and so take the same decisions.
 constexpr float kMinDen = 1e-30f;
 
@@ -72,10 +71,13 @@ __device__ __forceinline__ void splat_geom(const Surf &s, float px, float py, fl
     h.in = live && (h.num <= rho2 * h.den) && (h.den > kMinDen);
 }
 
+// SAFE (adjoint): lanes that are not `in` get rden = 1 and r2 = 0, so their
+// G, sigma G and 1/w2^2 stay finite; the forward needs only alpha and skips it.
+template <bool SAFE>
 __device__ __forceinline__ void splat_alpha(const Surf &s, float amin, float amax, Hit &h) {
 #pragma clang fp contract(off)
-    h.rden = __builtin_amdgcn_rcpf(h.in ? h.den : 1.f);
-    h.r2 = h.in ? h.num * h.rden : 0.f;
+    h.rden = __builtin_amdgcn_rcpf(SAFE ? (h.in ? h.den : 1.f) : h.den);
+    h.r2 = SAFE ? (h.in ? h.num * h.rden : 0.f) : h.num * h.rden;
     h.G = __builtin_amdgcn_exp2f(h.r2 * -0.72134752044448170368f);  // exp(-r2/2)
     h.at = s.sig * h.G;
     h.hit = h.in && (h.at >= amin);
@@ -106,7 +108,7 @@ __device__ __forceinline__ TileCtx tile_ctx(const ViewDesc *views, int V, const 
                                             const uint32_t *te, Slots<TW, TH> &sl) {
     using Gm = Geo<TW, TH>;
     TileCtx c;
-    const int tile = blockIdx.x;
+    const int tile = (int)xcd_chunked<16>(blockIdx.x, gridDim.x);  // runs of 16 tiles share an L2
     c.view = view_of_tile(views, V, tile);
     const ViewDesc &vd = views[c.view];
     const int local = tile - vd.tile_base;
@@ -157,23 +159,26 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
 }
 
 // Forward traversal of the tile list for every slot of the lane.
-// acc = (r, g, b, depth, nx, ny, nz, A) per slot.
+// acc = (r, g, b, depth, nx, ny, nz, A) per slot; slast[q] (wave-uniform) is
+// one past the list position of the slot's last contributor, the bound of
+// the adjoint traversal.
 template <int TW, int TH>
 __device__ __forceinline__ void tile_forward(const TileCtx &c, const Slots<TW, TH> &sl,
                                              const uint32_t *__restrict__ pval, const Rec *__restrict__ rec,
                                              const KParams &kp, Rec *srec, uint32_t *sval,
                                              float (&acc)[Geo<TW, TH>::NB][8], float (&T)[Geo<TW, TH>::NB],
-                                             uint32_t (&nlast)[Geo<TW, TH>::NB],
+                                             uint32_t (&slast)[Geo<TW, TH>::NB],
                                              uint32_t (&ncount)[Geo<TW, TH>::NB]) {
     using Gm = Geo<TW, TH>;
     const float rho2 = kp.rho_max * kp.rho_max;
+    const float amax = __builtin_canonicalizef(kp.alpha_max);
     bool done[Gm::NB];
     uint32_t live = 0;
 #pragma unroll
     for (int q = 0; q < Gm::NB; ++q) {
         done[q] = !sl.inside[q];
         T[q] = 1.f;
-        nlast[q] = 0;
+        slast[q] = 0;
         ncount[q] = 0;
 #pragma unroll
         for (int k = 0; k < 8; ++k) acc[q][k] = 0.f;
@@ -192,12 +197,13 @@ __device__ __forceinline__ void tile_forward(const TileCtx &c, const Slots<TW, T
                 Hit h;
                 splat_geom(s, sl.px[q], sl.py[q], rho2, !done[q], h);
                 if (ballot64(h.in) == 0) continue;
-                splat_alpha(s, kp.alpha_min, kp.alpha_max, h);
+                splat_alpha<false>(s, kp.alpha_min, amax, h);
+                bool con;
                 {
 #pragma clang fp contract(off)
                     const float test = T[q] * (1.f - h.alpha);
                     const bool stop = h.hit && test < kp.t_min;
-                    const bool con = h.hit && !stop;
+                    con = h.hit && !stop;
                     const float wgt = (con ? h.alpha : 0.f) * T[q];
                     acc[q][0] = fmaf(s.r, wgt, acc[q][0]);
                     acc[q][1] = fmaf(s.g, wgt, acc[q][1]);
@@ -207,11 +213,11 @@ __device__ __forceinline__ void tile_forward(const TileCtx &c, const Slots<TW, T
                     acc[q][5] = fmaf(s.n1, wgt, acc[q][5]);
                     acc[q][6] = fmaf(s.n2, wgt, acc[q][6]);
                     acc[q][7] = acc[q][7] + wgt;
-                    T[q] = stop ? T[q] : test;
-                    nlast[q] = con ? base - c.start + (uint32_t)j + 1u : nlast[q];
+                    T[q] = con ? test : T[q];
                     ncount[q] += con ? 1u : 0u;
                     done[q] = done[q] || stop;
                 }
+                if (ballot64(con) != 0) slast[q] = base - c.start + (uint32_t)j + 1u;
                 if (ballot64(!done[q]) == 0) live &= ~(1u << q);
             }
             if (live == 0) break;
@@ -267,16 +273,23 @@ __device__ __forceinline__ void adjoint_terms(const Hit &h, const Surf &s, const
 }
 
 // Adjoint traversal.  g[q] = dL/d(r, g, b, depth, nx, ny, nz, A) of slot q's
-// pixel, S[q] = g[q] . outputs, nl[q] = its contributor prefix length.
-// HAS_N: the normal map carries a gradient.
+// pixel, S[q] = g[q] . outputs, Tf[q] = its final transmittance (1 for a
+// pixel without gradient), bound[q] = the slot's traversal bound (any value
+// >= one past its last contributor).  Every contribution lowers T strictly
+// (alpha >= alpha_min >= 1e-6 and T >= t_min stays normal), and the
+// recomputed T repeats the forward's exactly, so a pixel still has
+// contributions ahead exactly while T > Tf.  HAS_N: the normal map carries a
+// gradient.
 template <int TW, int TH, bool HAS_N>
 __device__ __forceinline__ void tile_backward(const TileCtx &c, const Slots<TW, TH> &sl,
                                               const uint32_t *__restrict__ pval, const Rec *__restrict__ rec,
                                               const KParams &kp, Rec *srec, uint32_t *sval,
                                               const float (&g)[Geo<TW, TH>::NB][8], const float (&S)[Geo<TW, TH>::NB],
-                                              const uint32_t (&nl)[Geo<TW, TH>::NB], float *__restrict__ grad) {
+                                              const float (&Tf)[Geo<TW, TH>::NB],
+                                              const uint32_t (&bound)[Geo<TW, TH>::NB], float *__restrict__ grad) {
     using Gm = Geo<TW, TH>;
     const float rho2 = kp.rho_max * kp.rho_max;
+    const float amax = __builtin_canonicalizef(kp.alpha_max);
     float T[Gm::NB], Sk[Gm::NB];
     uint32_t smax[Gm::NB];
     uint32_t maxlast = 0;
@@ -284,7 +297,7 @@ __device__ __forceinline__ void tile_backward(const TileCtx &c, const Slots<TW, 
     for (int q = 0; q < Gm::NB; ++q) {
         T[q] = 1.f;
         Sk[q] = 0.f;
-        smax[q] = __builtin_amdgcn_readfirstlane(wave_max_u32(nl[q]));
+        smax[q] = bound[q];
         maxlast = smax[q] > maxlast ? smax[q] : maxlast;
     }
     const uint32_t len = c.end - c.start;
@@ -312,14 +325,14 @@ __device__ __forceinline__ void tile_backward(const TileCtx &c, const Slots<TW, 
             for (int q = 0; q < Gm::NB; ++q) {
                 if (((m >> q) & 1u) == 0) continue;
                 Hit h;
-                splat_geom(s, sl.px[q], sl.py[q], rho2, k < nl[q], h);
+                splat_geom(s, sl.px[q], sl.py[q], rho2, T[q] > Tf[q], h);
                 if (ballot64(h.in) == 0) continue;
-                splat_alpha(s, kp.alpha_min, kp.alpha_max, h);
+                splat_alpha<true>(s, kp.alpha_min, amax, h);
                 if (ballot64(h.hit) == 0) continue;
                 if (first)
-                    adjoint_terms<true, HAS_N>(h, s, g[q], S[q], Sk[q], T[q], kp.alpha_max, gr, gn2);
+                    adjoint_terms<true, HAS_N>(h, s, g[q], S[q], Sk[q], T[q], amax, gr, gn2);
                 else
-                    adjoint_terms<false, HAS_N>(h, s, g[q], S[q], Sk[q], T[q], kp.alpha_max, gr, gn2);
+                    adjoint_terms<false, HAS_N>(h, s, g[q], S[q], Sk[q], T[q], amax, gr, gn2);
                 first = false;
             }
             if (first) continue;  // no lane of the tile is hit by this surfel
@@ -348,8 +361,8 @@ __global__ __launch_bounds__(64) void k_render_fwd(const ViewDesc *__restrict__ 
     Slots<TW, TH> sl;
     const TileCtx c = tile_ctx<TW, TH>(views, V, ts, te, sl);
     float acc[Gm::NB][8], T[Gm::NB];
-    uint32_t nl[Gm::NB], nc[Gm::NB];
-    tile_forward<TW, TH>(c, sl, pval, rec, kp, srec, sval, acc, T, nl, nc);
+    uint32_t slast[Gm::NB], nc[Gm::NB];
+    tile_forward<TW, TH>(c, sl, pval, rec, kp, srec, sval, acc, T, slast, nc);
 #pragma unroll
     for (int q = 0; q < Gm::NB; ++q) {
         if (!sl.inside[q]) continue;
@@ -363,7 +376,7 @@ __global__ __launch_bounds__(64) void k_render_fwd(const ViewDesc *__restrict__ 
         out.normal[2 * NPX + p] = acc[q][6];
         out.alpha[p] = acc[q][7];
         tfinal[p] = T[q];
-        nlast_out[p] = nl[q];
+        nlast_out[p] = slast[q];
         ncount_out[p] = nc[q];
     }
 }
@@ -373,20 +386,23 @@ __global__ __launch_bounds__(64) void k_render_bwd(const ViewDesc *__restrict__ 
                                                     const uint32_t *__restrict__ ts, const uint32_t *__restrict__ te,
                                                     const uint32_t *__restrict__ pval, const Rec *__restrict__ rec,
                                                     KParams kp, int64_t NPX, fm_outputs out, fm_grad_outputs gout,
+                                                    const float *__restrict__ tfinal,
                                                     const uint32_t *__restrict__ nlast_in, float *__restrict__ grad) {
     using Gm = Geo<TW, TH>;
     __shared__ Rec srec[64];
     __shared__ uint32_t sval[64];
     Slots<TW, TH> sl;
     const TileCtx c = tile_ctx<TW, TH>(views, V, ts, te, sl);
-    float g[Gm::NB][8], S[Gm::NB];
-    uint32_t nl[Gm::NB];
+    float g[Gm::NB][8], S[Gm::NB], Tf[Gm::NB];
+    uint32_t bound[Gm::NB];
 #pragma unroll
     for (int q = 0; q < Gm::NB; ++q) {
 #pragma unroll
         for (int k = 0; k < 8; ++k) g[q][k] = -0.f;
         S[q] = 0.f;
-        nl[q] = 0;
+        Tf[q] = 1.f;
+        const uint32_t nl = sl.inside[q] ? nlast_in[sl.pix[q]] : 0u;
+        bound[q] = __builtin_amdgcn_readfirstlane(wave_max_u32(nl));
         if (!sl.inside[q]) continue;
         const int64_t p = sl.pix[q];
         if (gout.rgb) { g[q][0] = gout.rgb[p]; g[q][1] = gout.rgb[NPX + p]; g[q][2] = gout.rgb[2 * NPX + p]; }
@@ -397,14 +413,14 @@ __global__ __launch_bounds__(64) void k_render_bwd(const ViewDesc *__restrict__ 
 #pragma unroll
         for (int k = 0; k < 8; ++k) any |= g[q][k] != 0.f;
         if (any) {
-            nl[q] = nlast_in[p];
+            Tf[q] = tfinal[p];
             S[q] = g[q][0] * out.rgb[p] + g[q][1] * out.rgb[NPX + p] + g[q][2] * out.rgb[2 * NPX + p] +
                    g[q][3] * out.depth[p] + g[q][7] * out.alpha[p];
             if (HAS_N)
                 S[q] += g[q][4] * out.normal[p] + g[q][5] * out.normal[NPX + p] + g[q][6] * out.normal[2 * NPX + p];
         }
     }
-    tile_backward<TW, TH, HAS_N>(c, sl, pval, rec, kp, srec, sval, g, S, nl, grad);
+    tile_backward<TW, TH, HAS_N>(c, sl, pval, rec, kp, srec, sval, g, S, Tf, bound, grad);
 }
 
 template <int TW, int TH>
@@ -421,9 +437,9 @@ __global__ __launch_bounds__(64) void k_render_fused(const ViewDesc *__restrict_
     Slots<TW, TH> sl;
     const TileCtx c = tile_ctx<TW, TH>(views, V, ts, te, sl);
     float acc[Gm::NB][8], T[Gm::NB];
-    uint32_t nl[Gm::NB], nc[Gm::NB];
-    tile_forward<TW, TH>(c, sl, pval, rec, kp, srec, sval, acc, T, nl, nc);
-    float g[Gm::NB][8], S[Gm::NB];
+    uint32_t slast[Gm::NB], nc[Gm::NB];
+    tile_forward<TW, TH>(c, sl, pval, rec, kp, srec, sval, acc, T, slast, nc);
+    float g[Gm::NB][8], S[Gm::NB], Tf[Gm::NB];
     float l = 0.f;
     const float npx = (float)c.W * (float)c.H;
     const float k_rgb = la.w_rgb / (3.f * npx);
@@ -433,10 +449,8 @@ __global__ __launch_bounds__(64) void k_render_fused(const ViewDesc *__restrict_
 #pragma unroll
         for (int k = 0; k < 8; ++k) g[q][k] = -0.f;
         S[q] = 0.f;
-        if (!sl.inside[q]) {
-            nl[q] = 0;
-            continue;
-        }
+        Tf[q] = 1.f;
+        if (!sl.inside[q]) continue;
         const int64_t p = sl.pix[q];
         const float o0 = acc[q][0] + T[q] * kp.bg[0], o1 = acc[q][1] + T[q] * kp.bg[1],
                     o2 = acc[q][2] + T[q] * kp.bg[2];
@@ -449,13 +463,11 @@ __global__ __launch_bounds__(64) void k_render_fused(const ViewDesc *__restrict_
         out.normal[2 * NPX + p] = acc[q][6];
         out.alpha[p] = acc[q][7];
         tfinal[p] = T[q];
-        nlast_out[p] = nl[q];
+        nlast_out[p] = slast[q];
         ncount_out[p] = nc[q];
         const bool m = la.mask ? (la.mask[p] != 0) : true;
-        if (!m) {
-            nl[q] = 0;
-            continue;
-        }
+        if (!m) continue;
+        Tf[q] = T[q];
         const float o[3] = {o0, o1, o2};
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) {
@@ -472,7 +484,7 @@ __global__ __launch_bounds__(64) void k_render_fused(const ViewDesc *__restrict_
     }
     const float lsum = wave_sum(l);
     if (threadIdx.x == 0) loss_part[blockIdx.x] = lsum;
-    tile_backward<TW, TH, false>(c, sl, pval, rec, kp, srec, sval, g, S, nl, grad);
+    tile_backward<TW, TH, false>(c, sl, pval, rec, kp, srec, sval, g, S, Tf, slast, grad);
 }
 
 __global__ __launch_bounds__(1024) void k_loss_reduce(const float *__restrict__ part, int64_t n,
@@ -508,12 +520,12 @@ hipError_t bwd_t(const Plan &p, void *ws, const KParams &kp, const fm_outputs &o
         hipLaunchKernelGGL((k_render_bwd<TW, TH, true>), dim3((unsigned)p.T), dim3(64), 0, st,
                            at<ViewDesc>(ws, p.o_views), p.V, at<uint32_t>(ws, p.o_tstart),
                            at<uint32_t>(ws, p.o_tend), pval, at<Rec>(ws, p.o_rec), kp, p.NPX, out, g,
-                           at<uint32_t>(ws, p.o_nlast), at<float>(ws, p.o_grad));
+                           at<float>(ws, p.o_tfinal), at<uint32_t>(ws, p.o_nlast), at<float>(ws, p.o_grad));
     else
         hipLaunchKernelGGL((k_render_bwd<TW, TH, false>), dim3((unsigned)p.T), dim3(64), 0, st,
                            at<ViewDesc>(ws, p.o_views), p.V, at<uint32_t>(ws, p.o_tstart),
                            at<uint32_t>(ws, p.o_tend), pval, at<Rec>(ws, p.o_rec), kp, p.NPX, out, g,
-                           at<uint32_t>(ws, p.o_nlast), at<float>(ws, p.o_grad));
+                           at<float>(ws, p.o_tfinal), at<uint32_t>(ws, p.o_nlast), at<float>(ws, p.o_grad));
     return hipGetLastError();
 }
 

@@ -166,6 +166,24 @@ __device__ inline int view_of_tile(const ViewDesc *v, int V, int64_t x) {
     return lo;
 }
 
+// Workgroups are dealt to the 8 XCDs of the chip round-robin.  Remapping
+// workgroup b of n to logical index (b mod 8) * (n / 8) + b / 8 gives every
+// XCD a contiguous run of logical indices (the tail beyond a multiple of 8
+// maps to itself), so neighbouring tiles or chunks share one L2.
+__device__ __forceinline__ uint32_t xcd_contiguous(uint32_t b, uint32_t n) {
+    const uint32_t per = n >> 3;
+    return b < per * 8u ? (b & 7u) * per + (b >> 3) : b;
+}
+
+// The same at a finer grain: within every group of 8 C consecutive
+// workgroups, each XCD gets C consecutive logical indices (tail unchanged).
+// Neighbouring tiles still meet in one L2, while every XCD keeps sampling
+// the whole batch (a contiguous 1/8 of it can cost more than another).
+template <uint32_t C> __device__ __forceinline__ uint32_t xcd_chunked(uint32_t b, uint32_t n) {
+    constexpr uint32_t grp = 8u * C;
+    return b < (n / grp) * grp ? (b / grp) * grp + (b & 7u) * C + (b >> 3) % C : b;
+}
+
 // ---- launchers (host) ------------------------------------------------------
 hipError_t launch_setup(const Plan &p, void *ws, const ViewDesc *views, const SubmapDesc *subs,
                         const int32_t *vlist, hipStream_t st);

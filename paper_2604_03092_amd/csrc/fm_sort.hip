@@ -25,10 +25,15 @@ __device__ __forceinline__ uint32_t count_of(const uint32_t *n_dev, uint32_t n_h
 }
 // Entries culled or off-screen carry this key; the first depth pass drops them.
 constexpr uint32_t kNoKey = 0xFFFFFFFFu;
+// Chunk (logical block) handled by this workgroup: each XCD gets a
+// contiguous run of chunks, so the neighbouring output segments of one digit
+// stay in one L2, which merges their partial cache-line writes before they
+// reach HBM.
+__device__ __forceinline__ uint32_t logical_block(int G) { return xcd_contiguous(blockIdx.x, (uint32_t)G); }
 __device__ __forceinline__ void chunk_of(uint32_t n, int G, uint32_t &lo, uint32_t &hi) {
     uint32_t chunk = (n + (uint32_t)G - 1) / (uint32_t)G;
     chunk = (chunk + 255u) & ~255u;
-    lo = (uint32_t)blockIdx.x * chunk;
+    lo = logical_block(G) * chunk;
     hi = lo + chunk;
     if (lo > n) lo = n;
     if (hi > n) hi = n;
@@ -68,7 +73,7 @@ __global__ __launch_bounds__(256) void k_radix_hist(const uint32_t *__restrict__
     }
     __syncthreads();
     const uint32_t c = h[0][threadIdx.x] + h[1][threadIdx.x] + h[2][threadIdx.x] + h[3][threadIdx.x];
-    hist[threadIdx.x * G + blockIdx.x] = c;
+    hist[threadIdx.x * G + logical_block(G)] = c;
     if (c) {
         atomicAdd(&tot[threadIdx.x], c);
         if (drop) atomicAdd(n_kept, c);
@@ -124,7 +129,7 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t *__restric
     const int w = threadIdx.x >> 6;
     const int lane = lane_id();
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    run[threadIdx.x] = hist[threadIdx.x * G + blockIdx.x];
+    run[threadIdx.x] = hist[threadIdx.x * G + logical_block(G)];
     uint32_t lo, hi;
     const uint32_t n = count_of(n_dev, n_host);
     chunk_of(n, G, lo, hi);

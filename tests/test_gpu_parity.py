@@ -259,9 +259,10 @@ def test_invalid_arguments(rast):
     with pytest.raises(native.FmError) as e:
         rast.workspace(gs, rast.params(tile=(12, 12)))
     assert e.value.status == native.FM_ERR_UNSUPPORTED
-    with pytest.raises(native.FmError) as e:
-        rast.workspace(gs, rast.params(alpha_max=1.5))
-    assert e.value.status == native.FM_ERR_INVALID_ARG
+    for bad_params in (dict(alpha_max=1.5), dict(alpha_min=1e-7), dict(t_min=0.0), dict(t_min=1e-31)):
+        with pytest.raises(native.FmError) as e:
+            rast.workspace(gs, rast.params(**bad_params))
+        assert e.value.status == native.FM_ERR_INVALID_ARG, bad_params
     ws = rast.workspace(gs)
     ws.nbytes = 10
     with pytest.raises(native.FmError) as e:
