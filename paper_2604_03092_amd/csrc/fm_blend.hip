@@ -160,8 +160,11 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
 
 // Forward traversal of the tile list for every slot of the lane.
 // acc = (r, g, b, depth, nx, ny, nz, A) per slot; slast[q] (wave-uniform) is
-// one past the list position of the slot's last contributor, the bound of
-// the adjoint traversal.
+// one past the last list position where a pixel of the slot was inside a
+// surfel's support, a bound on its last contributor for the adjoint.  A
+// pixel that is outside the image or has stopped compositing carries x =
+// NaN, which fails every support test; slots whose pixels have all stopped
+// are dropped from the live set every 8 list positions.
 template <int TW, int TH>
 __device__ __forceinline__ void tile_forward(const TileCtx &c, const Slots<TW, TH> &sl,
                                              const uint32_t *__restrict__ pval, const Rec *__restrict__ rec,
@@ -169,41 +172,41 @@ __device__ __forceinline__ void tile_forward(const TileCtx &c, const Slots<TW, T
                                              float (&acc)[Geo<TW, TH>::NB][8], float (&T)[Geo<TW, TH>::NB],
                                              uint32_t (&slast)[Geo<TW, TH>::NB],
                                              uint32_t (&ncount)[Geo<TW, TH>::NB]) {
+#pragma clang fp contract(off)
     using Gm = Geo<TW, TH>;
     const float rho2 = kp.rho_max * kp.rho_max;
     const float amax = __builtin_canonicalizef(kp.alpha_max);
-    bool done[Gm::NB];
+    const float nan = __builtin_nanf("");
+    float px[Gm::NB];
     uint32_t live = 0;
 #pragma unroll
     for (int q = 0; q < Gm::NB; ++q) {
-        done[q] = !sl.inside[q];
+        px[q] = sl.inside[q] ? sl.px[q] : nan;
         T[q] = 1.f;
         slast[q] = 0;
         ncount[q] = 0;
 #pragma unroll
         for (int k = 0; k < 8; ++k) acc[q][k] = 0.f;
-        if (ballot64(!done[q]) != 0) live |= 1u << q;
+        if (ballot64(sl.inside[q]) != 0) live |= 1u << q;
     }
     for (uint32_t base = c.start; base < c.end && live != 0; base += 64) {
         const int cntb = stage(c, base, c.end, pval, rec, srec, sval);
         for (int j = 0; j < cntb; ++j) {
             const uint32_t m = (__builtin_amdgcn_readfirstlane(sval[j]) >> kMaskShift) & live;
-            if (m == 0) continue;
-            Surf s;
-            load_surf(&srec[j], s);
+            if (m != 0) {
+                Surf s;
+                load_surf(&srec[j], s);
 #pragma unroll
-            for (int q = 0; q < Gm::NB; ++q) {
-                if (((m >> q) & 1u) == 0) continue;
-                Hit h;
-                splat_geom(s, sl.px[q], sl.py[q], rho2, !done[q], h);
-                if (ballot64(h.in) == 0) continue;
-                splat_alpha<false>(s, kp.alpha_min, amax, h);
-                bool con;
-                {
-#pragma clang fp contract(off)
+                for (int q = 0; q < Gm::NB; ++q) {
+                    if (((m >> q) & 1u) == 0) continue;
+                    Hit h;
+                    splat_geom(s, px[q], sl.py[q], rho2, true, h);
+                    if (ballot64(h.in) == 0) continue;
+                    slast[q] = base - c.start + (uint32_t)j + 1u;
+                    splat_alpha<false>(s, kp.alpha_min, amax, h);
                     const float test = T[q] * (1.f - h.alpha);
                     const bool stop = h.hit && test < kp.t_min;
-                    con = h.hit && !stop;
+                    const bool con = h.hit && !stop;
                     const float wgt = (con ? h.alpha : 0.f) * T[q];
                     acc[q][0] = fmaf(s.r, wgt, acc[q][0]);
                     acc[q][1] = fmaf(s.g, wgt, acc[q][1]);
@@ -215,12 +218,15 @@ __device__ __forceinline__ void tile_forward(const TileCtx &c, const Slots<TW, T
                     acc[q][7] = acc[q][7] + wgt;
                     T[q] = con ? test : T[q];
                     ncount[q] += con ? 1u : 0u;
-                    done[q] = done[q] || stop;
+                    px[q] = stop ? nan : px[q];
                 }
-                if (ballot64(con) != 0) slast[q] = base - c.start + (uint32_t)j + 1u;
-                if (ballot64(!done[q]) == 0) live &= ~(1u << q);
             }
-            if (live == 0) break;
+            if ((j & 7) == 7) {
+#pragma unroll
+                for (int q = 0; q < Gm::NB; ++q)
+                    if (ballot64(px[q] == px[q]) == 0) live &= ~(1u << q);
+                if (live == 0) break;
+            }
         }
     }
 }

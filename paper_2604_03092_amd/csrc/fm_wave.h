@@ -8,7 +8,7 @@ namespace fm {
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
-__device__ __forceinline__ uint64_t ballot64(bool p) { return __ballot(p); }
+__device__ __forceinline__ uint64_t ballot64(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
 // Row rotate (16-lane rows) by N through DPP: lane j of a row receives lane
 // (j - N) mod 16 of the same row.  All lanes must be active.
