@@ -164,10 +164,7 @@ fm_status build(fm_ctx *ctx, const fm_batch *b, const fm_raster_params *prm, int
     p.tile_bits = bits;
     p.pair_passes = (bits + fm::kRadixBits - 1) / fm::kRadixBits;
     p.pairs_in_alt = (p.pair_passes & 1) != 0;
-    auto grid_for = [](int64_t n) {
-        int64_t g = (n + 4095) / 4096;
-        return (int)std::max<int64_t>(1, std::min<int64_t>(g, fm::kMaxSortGrid));
-    };
+    auto grid_for = [](int64_t n) { return (int)std::max<int64_t>(1, (n + fm::kSortTile - 1) / fm::kSortTile); };
     p.sortG_e = grid_for(E);
     p.sortG_p = grid_for(max_pairs);
     p.scan_blocks = (int)std::max<int64_t>(1, (E + fm::kScanChunk - 1) / fm::kScanChunk);

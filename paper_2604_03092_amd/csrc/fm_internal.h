@@ -26,7 +26,7 @@ constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 constexpr int kSortBlock = 256;    // threads per radix-sort block
 constexpr int kScanChunk = 2048;   // entries per block of the count scan
-constexpr int kMaxSortGrid = 1024;
+constexpr int kSortTile = 4096;     // items per block of a radix pass
 constexpr int kEmitChunk = 2048;   // pairs per iteration of the emission blocks
 constexpr int kMaxEmitGrid = 4096;
 constexpr int kMaxPasses = 8;      // radix passes per binning (4 depth + up to 4 tile)

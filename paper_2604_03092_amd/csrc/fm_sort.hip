@@ -25,18 +25,15 @@ __device__ __forceinline__ uint32_t count_of(const uint32_t *n_dev, uint32_t n_h
 }
 // Entries culled or off-screen carry this key; the first depth pass drops them.
 constexpr uint32_t kNoKey = 0xFFFFFFFFu;
-// Chunk (logical block) handled by this workgroup: each XCD gets a
-// contiguous run of chunks, so the neighbouring output segments of one digit
-// stay in one L2, which merges their partial cache-line writes before they
-// reach HBM.
+// Items of the logical block handled by this workgroup: a fixed tile of
+// kSortTile consecutive items.  Each XCD gets a contiguous run of tiles, so
+// the neighbouring output runs of one digit stay in one L2, which merges
+// their partial cache-line writes before they reach HBM.
 __device__ __forceinline__ uint32_t logical_block(int G) { return xcd_contiguous(blockIdx.x, (uint32_t)G); }
-__device__ __forceinline__ void chunk_of(uint32_t n, int G, uint32_t &lo, uint32_t &hi) {
-    uint32_t chunk = (n + (uint32_t)G - 1) / (uint32_t)G;
-    chunk = (chunk + 255u) & ~255u;
-    lo = logical_block(G) * chunk;
-    hi = lo + chunk;
-    if (lo > n) lo = n;
-    if (hi > n) hi = n;
+__device__ __forceinline__ void tile_of(uint32_t n, int G, uint32_t &lo, uint32_t &hi) {
+    const uint64_t l = (uint64_t)logical_block(G) * kSortTile;
+    lo = l < n ? (uint32_t)l : n;
+    hi = l + kSortTile < n ? (uint32_t)(l + kSortTile) : n;
 }
 
 // Per-block digit histogram, written digit-major: hist[d * G + block]; the
@@ -52,7 +49,7 @@ __global__ __launch_bounds__(256) void k_radix_hist(const uint32_t *__restrict__
     for (int k = 0; k < 4; ++k) h[k][threadIdx.x] = 0;
     __syncthreads();
     uint32_t lo, hi;
-    chunk_of(count_of(n_dev, n_host), G, lo, hi);
+    tile_of(count_of(n_dev, n_host), G, lo, hi);
     const int lane = lane_id();
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     // lanes of a wave with equal digits are matched through ballots and their
@@ -112,85 +109,108 @@ __global__ __launch_bounds__(256) void k_radix_rowscan(uint32_t *__restrict__ hi
     }
 }
 
-// Stable scatter by digit.  Each block walks its chunk in order in rounds
-// of 1024 items (item base + k*256 + thread, k = 0..3, so the round's order
-// is (k, wave, lane)).  Within a wave, items with equal digits are ranked by
-// lane through ballots; (k, wave) groups are ranked in order through LDS.
-// The next round's keys and values are loaded while the current one ranks.
+// Stable scatter by digit through a local sort.  The block's tile of
+// kSortTile items is split into one run of 1024 per wave; a wave ranks its
+// items in order (16 steps of 64 lanes; lanes with equal digits are matched
+// through ballots) against per-wave digit counters in LDS.  Per digit, the
+// waves' counts give the wave offsets and a scan over the digits the
+// block-local start of each digit's run.  The items are placed in LDS in
+// (digit, original order) order and written out by consecutive threads, so
+// each digit's run leaves the block as one contiguous, coalesced stream.
 __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t *__restrict__ keys_in,
                                                         const uint32_t *__restrict__ vals_in,
                                                         uint32_t *__restrict__ keys_out,
                                                         uint32_t *__restrict__ vals_out, const uint32_t *n_dev,
                                                         uint32_t n_host, int shift,
                                                         const uint32_t *__restrict__ hist, int G, int drop) {
-    constexpr int KPT = 4;
-    __shared__ uint32_t run[kRadix];
-    __shared__ uint32_t gcnt[KPT * 4][kRadix];
-    const int w = threadIdx.x >> 6;
-    const int lane = lane_id();
+    constexpr int IPT = kSortTile / 256;   // items per lane
+    constexpr int PER_WAVE = kSortTile / 4;
+    __shared__ uint32_t s_key[kSortTile];
+    __shared__ uint32_t s_val[kSortTile];
+    __shared__ uint32_t s_wcnt[4][kRadix];  // per-wave digit counts, then per-wave offsets
+    __shared__ uint32_t s_start[kRadix];    // block-local start of each digit's run
+    __shared__ uint32_t s_glob[kRadix];     // global start of this block's run of each digit
+    __shared__ uint32_t s_wsum[4];
+    const int w = threadIdx.x >> 6, lane = lane_id();
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    run[threadIdx.x] = hist[threadIdx.x * G + logical_block(G)];
-    uint32_t lo, hi;
     const uint32_t n = count_of(n_dev, n_host);
-    chunk_of(n, G, lo, hi);
-    uint32_t key[KPT], val[KPT];
-    auto load = [&](uint32_t base) {
+    uint32_t lo, hi;
+    tile_of(n, G, lo, hi);
+    if (lo >= hi) return;  // uniform over the block
 #pragma unroll
-        for (int k = 0; k < KPT; ++k) {
-            const uint32_t i = base + k * 256 + threadIdx.x;
-            const bool valid = i < hi;
-            key[k] = valid ? keys_in[i] : 0xFFFFFFFFu;
-            val[k] = valid ? (vals_in ? vals_in[i] : i) : 0u;
+    for (int k = 0; k < 4; ++k) s_wcnt[k][threadIdx.x] = 0u;
+    s_glob[threadIdx.x] = hist[threadIdx.x * G + logical_block(G)];
+    uint32_t key[IPT], val[IPT];
+    const uint32_t wbase = lo + (uint32_t)w * PER_WAVE;
+#pragma unroll
+    for (int k = 0; k < IPT; ++k) {
+        const uint32_t i = wbase + (uint32_t)k * 64u + (uint32_t)lane;
+        const bool valid = i < hi;
+        key[k] = valid ? keys_in[i] : kNoKey;
+        val[k] = valid ? (vals_in ? vals_in[i] : i) : 0u;
+    }
+    __syncthreads();
+    uint32_t rank[IPT];
+#pragma unroll
+    for (int k = 0; k < IPT; ++k) {
+        const uint32_t i = wbase + (uint32_t)k * 64u + (uint32_t)lane;
+        const bool ok = i < hi && !(drop && key[k] == kNoKey);
+        const uint32_t d = (key[k] >> shift) & 0xFFu;
+        uint64_t m = ballot64(ok);
+#pragma unroll
+        for (int b = 0; b < kRadixBits; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t bb = ballot64(bit);
+            m &= bit ? bb : ~bb;
         }
-    };
-    if (lo < hi) load(lo);
-    for (uint32_t base = lo; base < hi; base += KPT * 256) {
-        uint32_t ck[KPT], cv[KPT];
-#pragma unroll
-        for (int k = 0; k < KPT; ++k) { ck[k] = key[k]; cv[k] = val[k]; }
-        if (base + KPT * 256 < hi) load(base + KPT * 256);
-#pragma unroll
-        for (int g = 0; g < KPT * 4; ++g) gcnt[g][threadIdx.x] = 0;
-        __syncthreads();
-        uint32_t rank[KPT], dig[KPT];
-        bool ok[KPT];
-#pragma unroll
-        for (int k = 0; k < KPT; ++k) {
-            const uint32_t i = base + k * 256 + threadIdx.x;
-            ok[k] = i < hi && !(drop && ck[k] == kNoKey);
-            const uint32_t d = (ck[k] >> shift) & 0xFFu;
-            dig[k] = d;
-            uint64_t m = ballot64(ok[k]);
-#pragma unroll
-            for (int b = 0; b < kRadixBits; ++b) {
-                const bool bit = (d >> b) & 1u;
-                const uint64_t bb = ballot64(bit);
-                m &= bit ? bb : ~bb;
-            }
-            rank[k] = (uint32_t)__popcll(m & lt);
-            if (ok[k] && rank[k] == 0) gcnt[k * 4 + w][d] = (uint32_t)__popcll(m);
+        // the wave's LDS accesses complete in order: every lane reads the
+        // counter before its group's lowest lane advances it
+        const uint32_t before = ok ? s_wcnt[w][d] : 0u;
+        rank[k] = ok ? before + (uint32_t)__popcll(m & lt) : 0xFFFFFFFFu;
+        if (ok && (m & lt) == 0) s_wcnt[w][d] = before + (uint32_t)__popcll(m);
+    }
+    __syncthreads();
+    {
+        // thread = digit: wave offsets, then the block-wide exclusive scan of the totals
+        const int d = threadIdx.x;
+        const uint32_t c0 = s_wcnt[0][d], c1 = s_wcnt[1][d], c2 = s_wcnt[2][d], c3 = s_wcnt[3][d];
+        s_wcnt[0][d] = 0u;
+        s_wcnt[1][d] = c0;
+        s_wcnt[2][d] = c0 + c1;
+        s_wcnt[3][d] = c0 + c1 + c2;
+        const uint32_t tot = c0 + c1 + c2 + c3;
+        uint32_t x = tot;
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(x, off);
+            if (lane >= off) x += y;
         }
+        if (lane == 63) s_wsum[w] = x;
         __syncthreads();
-        {
-            uint32_t r = run[threadIdx.x];
+        uint32_t pre = x - tot;
+        for (int j = 0; j < w; ++j) pre += s_wsum[j];
+        s_start[d] = pre;
+    }
+    __syncthreads();
 #pragma unroll
-            for (int g = 0; g < KPT * 4; ++g) {
-                const uint32_t c = gcnt[g][threadIdx.x];
-                gcnt[g][threadIdx.x] = r;
-                r += c;
-            }
-            run[threadIdx.x] = r;
+    for (int k = 0; k < IPT; ++k) {
+        if (rank[k] == 0xFFFFFFFFu) continue;
+        const uint32_t d = (key[k] >> shift) & 0xFFu;
+        const uint32_t lp = s_start[d] + s_wcnt[w][d] + rank[k];
+        if (lp < (uint32_t)kSortTile) {  // always holds; guards the LDS store
+            s_key[lp] = key[k];
+            s_val[lp] = val[k];
         }
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < KPT; ++k) {
-            const uint32_t dst = gcnt[k * 4 + w][dig[k]] + rank[k];
-            if (ok[k] && dst < n) {  // dst < n always holds; the test only guards the store
-                keys_out[dst] = ck[k];
-                vals_out[dst] = cv[k];
-            }
+    }
+    __syncthreads();
+    const uint32_t total = s_wsum[0] + s_wsum[1] + s_wsum[2] + s_wsum[3];
+    for (uint32_t i = threadIdx.x; i < total; i += 256) {
+        const uint32_t k = s_key[i];
+        const uint32_t d = (k >> shift) & 0xFFu;
+        const uint32_t g = s_glob[d] + (i - s_start[d]);
+        if (g < n) {  // always holds; guards the store
+            keys_out[g] = k;
+            vals_out[g] = s_val[i];
         }
-        __syncthreads();
     }
 }
 
