@@ -36,29 +36,36 @@ __device__ __forceinline__ void tile_of(uint32_t n, int G, uint32_t &lo, uint32_
     hi = l + kSortTile < n ? (uint32_t)(l + kSortTile) : n;
 }
 
-// Per-block digit histogram, written digit-major: hist[d * G + block]; the
-// digit totals of the whole pass are added into tot[d].  With `drop`, items
-// whose key is kNoKey are left out (and the kept count is added to *n_kept).
+// Per-block digit histogram, written digit-major: hist[d * G + block].  With
+// `drop`, items whose key is kNoKey are left out.  Each wave counts its run of
+// 1024 items (all loads issued first); lanes with equal digits are matched
+// through ballots and their lowest lane adds the group's size to the wave's
+// LDS counters.
 __global__ __launch_bounds__(256) void k_radix_hist(const uint32_t *__restrict__ keys, const uint32_t *n_dev,
                                                      uint32_t n_host, int shift, uint32_t *__restrict__ hist,
-                                                     int G, uint32_t *__restrict__ tot, int drop,
-                                                     uint32_t *__restrict__ n_kept) {
+                                                     int G, int drop) {
+    constexpr int IPT = kSortTile / 256;
     __shared__ uint32_t h[4][kRadix];
-    const int w = threadIdx.x >> 6;
+    const int w = threadIdx.x >> 6, lane = lane_id();
 #pragma unroll
     for (int k = 0; k < 4; ++k) h[k][threadIdx.x] = 0;
-    __syncthreads();
     uint32_t lo, hi;
     tile_of(count_of(n_dev, n_host), G, lo, hi);
-    const int lane = lane_id();
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    // lanes of a wave with equal digits are matched through ballots and their
-    // lowest lane adds the group's size: one LDS atomic per distinct digit
-    for (uint32_t base = lo; base < hi; base += 256) {
-        const uint32_t i = base + threadIdx.x;
-        const uint32_t key = i < hi ? keys[i] : kNoKey;
-        const bool ok = i < hi && !(drop && key == kNoKey);
-        const uint32_t d = (key >> shift) & 0xFFu;
+    const uint32_t wbase = lo + (uint32_t)w * (kSortTile / 4);
+    uint32_t key[IPT];
+#pragma unroll
+    for (int k = 0; k < IPT; ++k) {
+        const uint32_t i = wbase + (uint32_t)k * 64u + (uint32_t)lane;
+        key[k] = i < hi ? keys[i] : kNoKey;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < IPT; ++k) {
+        const uint32_t i = wbase + (uint32_t)k * 64u + (uint32_t)lane;
+        const bool ok = i < hi && !(drop && key[k] == kNoKey);
+        if (ballot64(ok) == 0) continue;
+        const uint32_t d = (key[k] >> shift) & 0xFFu;
         uint64_t m = ballot64(ok);
 #pragma unroll
         for (int b = 0; b < kRadixBits; ++b) {
@@ -69,18 +76,29 @@ __global__ __launch_bounds__(256) void k_radix_hist(const uint32_t *__restrict__
         if (ok && (m & lt) == 0) atomicAdd(&h[w][d], (uint32_t)__popcll(m));
     }
     __syncthreads();
-    const uint32_t c = h[0][threadIdx.x] + h[1][threadIdx.x] + h[2][threadIdx.x] + h[3][threadIdx.x];
-    hist[threadIdx.x * G + logical_block(G)] = c;
-    if (c) {
-        atomicAdd(&tot[threadIdx.x], c);
-        if (drop) atomicAdd(n_kept, c);
-    }
+    hist[threadIdx.x * G + logical_block(G)] = h[0][threadIdx.x] + h[1][threadIdx.x] + h[2][threadIdx.x] +
+                                               h[3][threadIdx.x];
+}
+
+// Digit totals of the pass: block d sums row d of the histogram.
+__global__ __launch_bounds__(256) void k_radix_rowsum(const uint32_t *__restrict__ hist, int G,
+                                                       uint32_t *__restrict__ tot) {
+    __shared__ uint32_t wsum[4];
+    const int d = blockIdx.x;
+    const uint32_t *row = hist + (size_t)d * G;
+    uint32_t t = 0;
+    for (int b = threadIdx.x; b < G; b += 256) t += row[b];
+    for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off);
+    if (lane_id() == 0) wsum[threadIdx.x >> 6] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) tot[d] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
 }
 
 // Global scatter offsets: block d turns row d of the histogram into
-// sum_{d' < d} tot[d'] + exclusive prefix over the blocks.
+// sum_{d' < d} tot[d'] + exclusive prefix over the blocks.  The last block
+// also stores the number of items kept by the pass when n_kept is set.
 __global__ __launch_bounds__(256) void k_radix_rowscan(uint32_t *__restrict__ hist, const uint32_t *__restrict__ tot,
-                                                        int G) {
+                                                        int G, uint32_t *__restrict__ n_kept) {
     __shared__ uint32_t wsum[4];
     const int d = blockIdx.x;
     const int w = threadIdx.x >> 6, lane = lane_id();
@@ -107,6 +125,7 @@ __global__ __launch_bounds__(256) void k_radix_rowscan(uint32_t *__restrict__ hi
         carry += wsum[0] + wsum[1] + wsum[2] + wsum[3];
         __syncthreads();
     }
+    if (n_kept && d == kRadix - 1 && threadIdx.x == 0) *n_kept = carry;
 }
 
 // Stable scatter by digit through a local sort.  The block's tile of
@@ -454,9 +473,9 @@ __global__ __launch_bounds__(256) void k_tile_ranges(const uint32_t *__restrict_
 void radix_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout, const uint32_t *n_dev,
                 uint32_t n_host, int shift, uint32_t *hist, int G, uint32_t *tot, int drop, uint32_t *n_kept,
                 hipStream_t s) {
-    hipLaunchKernelGGL(k_radix_hist, dim3(G), dim3(256), 0, s, kin, n_dev, n_host, shift, hist, G, tot, drop,
-                       n_kept);
-    hipLaunchKernelGGL(k_radix_rowscan, dim3(kRadix), dim3(256), 0, s, hist, tot, G);
+    hipLaunchKernelGGL(k_radix_hist, dim3(G), dim3(256), 0, s, kin, n_dev, n_host, shift, hist, G, drop);
+    hipLaunchKernelGGL(k_radix_rowsum, dim3(kRadix), dim3(256), 0, s, hist, G, tot);
+    hipLaunchKernelGGL(k_radix_rowscan, dim3(kRadix), dim3(256), 0, s, hist, tot, G, n_kept);
     hipLaunchKernelGGL(k_radix_scatter, dim3(G), dim3(256), 0, s, kin, vin, kout, vout, n_dev, n_host, shift,
                        hist, G, drop);
 }
