@@ -30,12 +30,37 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, HERE)
 
 METRIC = "fwd+bwd Mpixel/s and views/s, batched fused vs per-view plain, 640x480"
-# VALU lane-operations per useful (pixel, surfel) evaluation of forward +
-# backward; transcendental and reciprocal instructions count 4 (quarter rate).
-OPS_PER_USEFUL = 143
+# Algorithmic VALU lane-operations per useful (pixel, surfel) evaluation --
+# inside the support and before termination: forward 32 + 2 transcendentals,
+# backward 90 + 3 transcendentals, a transcendental counting 4 (quarter
+# rate).  Tile over-evaluation and cross-lane reductions are not counted.
+OPS_PER_USEFUL = 32 + 2 * 4 + 90 + 3 * 4
 # gfx950: 256 CUs x 64 FP32 lanes x 2.4 GHz, one non-packed VALU op per lane per clock
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
+# HBM traffic of the blend kernel measured with rocprofv3 FETCH_SIZE / WRITE_SIZE
+# (scaled by a 1 GiB copy), valid while the kernel source is the one measured
+TRAFFIC_FILE = os.path.join(HERE, "profiles", "blend_traffic_headline.json")
+BLEND_SOURCE = os.path.join(HERE, "paper_2604_03092_amd", "csrc", "fm_blend.hip")
+
+
+def git_blob_sha1(path):
+    """git's object id of a file (sha1 of 'blob <size>\\0' + bytes)."""
+    import hashlib
+    data = open(path, "rb").read()
+    return hashlib.sha1(b"blob %d\0" % len(data) + data).hexdigest()
+
+
+def measured_traffic():
+    """Per-launch HBM bytes of the blend kernel, or None when the measurement
+    is missing or was taken on a different kernel source."""
+    try:
+        t = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if t.get("blend_source_sha1") != git_blob_sha1(BLEND_SOURCE):
+        return None
+    return t.get("bytes_per_launch")
 
 
 def log(msg):
@@ -68,17 +93,59 @@ def cpu_baseline(scene, threads):
                        f"FP64 oracle forward + L1 loss + backward, {dt:.2f} s")
 
 
+def time_config(rast, name, steps):
+    """Fused forward + L1 + backward of one config's whole batch, eager calls,
+    in Mpixel/s (setup and pair-buffer sizing untimed)."""
+    import torch
+    from paper_2604_03092_amd.raster import GpuScene
+    scene = make_workload(name)
+    gs = GpuScene.from_scene(scene)
+    params = rast.params()
+    out, ws = rast.forward(gs, params)
+    torch.cuda.synchronize()
+    _, n_pairs, _ = rast.query(gs, ws)
+    ws = rast.workspace(gs, params, max_pairs=int(n_pairs * 1.1) + 4096)
+    out = rast.new_outputs(gs)
+    grads, dvm = gs.zero_grads()
+    loss = torch.zeros(1, device="cuda")
+
+    def step():
+        for g in grads:
+            for t in g.values():
+                t.zero_()
+        dvm.zero_()
+        loss.zero_()
+        rast.fwd_bwd_l1(gs, ws, out, grads, dvm, loss)
+
+    for _ in range(2):
+        step()
+    torch.cuda.synchronize()
+    assert rast.query(gs, ws)[0] == 0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    res = dict(views=gs.n_views, pixels=gs.npx, pairs=n_pairs, ms_per_step=round(dt * 1e3, 4),
+               mpixel_s=round(gs.npx / dt / 1e6, 3), views_s=round(gs.n_views / dt, 3))
+    del ws, out, grads, dvm
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="headline")
     ap.add_argument("--tile", default="16x16")
     ap.add_argument("--no-graph", action="store_true", help="time eager calls instead of a graph replay")
     ap.add_argument("--no-plain", action="store_true", help="skip the per-view plain comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--all-configs", action="store_true",
+                    help="also time the fused step on configs 0-4 (reported under per_config)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 1 GiB device buffer 5 times (reference for HBM counter scaling)")
     args = ap.parse_args()
@@ -221,9 +288,30 @@ def main():
     blend_s = phases["blend"] * 1e-3
     achieved = useful * OPS_PER_USEFUL / blend_s / 1e12 if blend_s > 0 else 0.0
     roofline = dict(bound="alu", achieved=round(achieved, 3), peak=round(ALU_PEAK_TOPS, 3), unit="TOP/s",
-                    frac=round(achieved / ALU_PEAK_TOPS, 4), traffic=None,
+                    frac=round(achieved / ALU_PEAK_TOPS, 4), traffic=measured_traffic(),
                     kernel="k_render_fused", kernel_ms=round(phases["blend"], 4),
                     useful_evals=useful, ops_per_useful=OPS_PER_USEFUL)
+
+    # HBM-bound phases against their algorithmic bytes: projection 52 B of
+    # parameters per surfel + a 68 B record per visible (view, surfel);
+    # binning 12 B emitted + 24 B of one sort pass per pair; backward
+    # projection a 68 B screen-space gradient per visible entry + 52 B of
+    # parameters read and 52 B of gradients written per surfel
+    _, surf_ids, view_ids, _, _ = rast.debug_pairs(gs, ws)
+    n_vis = int(np.unique(view_ids.astype(np.int64) << 32 | surf_ids.astype(np.int64)).size)
+    n_surf = int(sum(sm["opacity"].shape[0] for sm in scene.submaps))
+    alg = {"projection": 52 * n_surf + 68 * n_vis, "binning": 36 * n_pairs,
+           "backward_projection": 68 * n_vis + 104 * n_surf}
+    phase_hbm = {k: dict(bytes=b, gbs=round(b / (phases[k] * 1e-3) / 1e9, 1),
+                         frac=round(b / (phases[k] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4))
+                 for k, b in alg.items() if phases.get(k, 0) > 0}
+
+    per_config = None
+    if args.all_configs:
+        per_config = {}
+        for name in ("config0", "config1", "config2", "config3", "config4"):
+            log(f"config {name}")
+            per_config[name] = time_config(rast, name, max(3, args.steps // 10))
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -252,9 +340,13 @@ def main():
         "plain": plain,
         "speedup_vs_plain": round(plain["ms_per_step"] / ms_step, 3) if plain else None,
         "phases_ms": {k: round(v, 4) for k, v in phases.items()},
+        "visible_entries": n_vis,
+        "phase_hbm": phase_hbm,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
+    if per_config is not None:
+        res["per_config"] = per_config
     print(json.dumps(res), flush=True)
 
 
