@@ -72,25 +72,28 @@ def make_workload(name):
     return scenes.make(name)
 
 
-def cpu_baseline(scene, threads):
-    """FP64 oracle (as it stands) on a bounded sample: view 0 of the batch,
-    forward + L1 loss + backward."""
+def cpu_baseline(scene, threads, n_sample):
+    """FP64 oracle (as it stands) on a bounded sample: the first n_sample views
+    of the batch, forward + L1 loss + backward."""
     import oracle
     from paper_2604_03092_amd import scenes as S
-    v = 0
-    w, h, s = scene.views[v]
-    one = S.Scene("sample", scene.submaps, [scene.views[v]], scene.intr[v:v + 1], scene.viewmat[v:v + 1],
-                  scene.target_rgb[:, :w * h], scene.target_depth[:w * h] if scene.target_depth is not None
-                  else None, scene.w_rgb, scene.w_depth)
+    n_sample = min(n_sample, scene.n_views)
+    npx = sum(w * h for (w, h, _) in scene.views[:n_sample])
+    sub = S.Scene("sample", scene.submaps, list(scene.views[:n_sample]), scene.intr[:n_sample],
+                  scene.viewmat[:n_sample], scene.target_rgb[:, :npx],
+                  scene.target_depth[:npx] if scene.target_depth is not None else None, scene.w_rgb,
+                  scene.w_depth)
     oracle.lib()
     t0 = time.perf_counter()
-    out = oracle.render_scene(one, n_threads=threads)
-    _, g = oracle.l1_loss(one, out)
-    oracle.backward_scene(one, g, n_threads=threads)
+    out = oracle.render_scene(sub, n_threads=threads)
+    _, g = oracle.l1_loss(sub, out)
+    oracle.backward_scene(sub, g, n_threads=threads)
     dt = time.perf_counter() - t0
-    return dict(value=round(w * h / dt / 1e6, 6), unit="Mpixel/s", cores=threads, kind="oracle",
-                sample=f"view 0 of {scene.n_views} ({w}x{h}, {scene.submaps[s]['opacity'].shape[0]} surfels): "
-                       f"FP64 oracle forward + L1 loss + backward, {dt:.2f} s")
+    w, h, s = scene.views[0]
+    return dict(value=round(npx / dt / 1e6, 6), unit="Mpixel/s", cores=threads, kind="oracle",
+                sample=f"views 0-{n_sample - 1} of {scene.n_views} ({w}x{h}, "
+                       f"{scene.submaps[s]['opacity'].shape[0]} surfels): FP64 oracle forward + L1 loss + "
+                       f"backward, {dt:.2f} s")
 
 
 def time_config(rast, name, steps):
@@ -144,6 +147,7 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the per-view plain comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--cpu-views", type=int, default=8, help="views in the CPU-baseline sample")
     ap.add_argument("--all-configs", action="store_true",
                     help="also time the fused step on configs 0-4 (reported under per_config)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -317,7 +321,7 @@ def main():
     if not args.no_cpu_baseline:
         threads = args.cpu_threads or min(16, os.cpu_count() or 1)
         log(f"cpu baseline on {threads} threads")
-        cpu = cpu_baseline(scene, threads)
+        cpu = cpu_baseline(scene, threads, args.cpu_views)
 
     res = {
         "metric": METRIC,
