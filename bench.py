@@ -96,6 +96,57 @@ def cpu_baseline(scene, threads, n_sample):
                        f"backward, {dt:.2f} s")
 
 
+def time_refine(rast, scene, params, iters, replays=3):
+    """The map-refinement loop over the batch's keyframes: `iters` iterations
+    of (zero gradients, fused forward + L1 + backward, Adam step on every
+    surfel tensor) captured in one hipGraph and replayed; a fresh copy of the
+    scene is refined."""
+    import torch
+    from paper_2604_03092_amd.raster import Adam, GpuScene
+    gs = GpuScene.from_scene(scene)
+    out, ws = rast.forward(gs, params)
+    torch.cuda.synchronize()
+    _, n_pairs, _ = rast.query(gs, ws)
+    ws = rast.workspace(gs, params, max_pairs=int(n_pairs * 1.5) + 4096)
+    out = rast.new_outputs(gs)
+    grads, dvm = gs.zero_grads()
+    adam = Adam(rast, gs, grads)
+    losses = torch.zeros(iters, device="cuda")
+
+    def iteration(i):
+        for g in grads:
+            for t in g.values():
+                t.zero_()
+        dvm.zero_()
+        rast.fwd_bwd_l1(gs, ws, out, grads, dvm, losses[i:i + 1])
+        adam.step()
+
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        iteration(0)
+    torch.cuda.current_stream().wait_stream(s)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        for i in range(iters):
+            iteration(i)
+    losses.zero_()
+    graph.replay()  # warm-up replay
+    torch.cuda.synchronize()
+    first = float(losses[0])
+    t0 = time.perf_counter()
+    for _ in range(replays):
+        losses.zero_()
+        graph.replay()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / (replays * iters)
+    st, _, req = rast.query(gs, ws)
+    return dict(iterations=iters, views=gs.n_views, ms_per_iteration=round(dt * 1e3, 4),
+                ms_per_graph=round(dt * iters * 1e3, 3), mpixel_s=round(gs.npx / dt / 1e6, 3),
+                loss_first=round(first, 6), loss_last=round(float(losses[-1]), 6),
+                pair_capacity_ok=bool(st == 0))
+
+
 def time_config(rast, name, steps):
     """Fused forward + L1 + backward of one config's whole batch, eager calls,
     in Mpixel/s (setup and pair-buffer sizing untimed)."""
@@ -148,6 +199,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--cpu-views", type=int, default=8, help="views in the CPU-baseline sample")
+    ap.add_argument("--refine-iters", type=int, default=20,
+                    help="iterations of the captured refine loop (render loss + Adam), 0 to skip")
     ap.add_argument("--all-configs", action="store_true",
                     help="also time the fused step on configs 0-4 (reported under per_config)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -310,6 +363,11 @@ def main():
                          frac=round(b / (phases[k] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4))
                  for k, b in alg.items() if phases.get(k, 0) > 0}
 
+    refine = None
+    if args.refine_iters > 0:
+        refine = time_refine(rast, scene, params, args.refine_iters)
+        log(f"refine: {refine['ms_per_iteration']:.3f} ms/iteration, {refine['mpixel_s']:.1f} Mpixel/s")
+
     per_config = None
     if args.all_configs:
         per_config = {}
@@ -348,6 +406,7 @@ def main():
         "phase_hbm": phase_hbm,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "refine": refine,
     }
     if per_config is not None:
         res["per_config"] = per_config

@@ -252,6 +252,50 @@ fm_status fm_autotune(fm_ctx *ctx, const fm_batch *batch, const fm_raster_params
                       size_t ws_bytes, int64_t max_pairs, const char *cache_path,
                       fm_raster_params *chosen, void *stream);
 
+/* ---- map refinement: optimizer step -------------------------------------
+ *
+ * The backend refines the map by gradient steps on the render loss
+ * (Sec. 3.3).  The paper names no optimizer; fm_adam_step is Adam as defined
+ * by Kingma & Ba (2015, Algorithm 1): with g the gradient of the tensor's
+ * free variable theta, m <- b1 m + (1 - b1) g, v <- b2 v + (1 - b2) g^2,
+ * theta <- theta - lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
+ * The rasterizer takes activated values p (opacity in (0, 1], linear scales),
+ * so each tensor names the parameterisation theta(p) its step is taken in;
+ * the kernel maps p and dL/dp to theta and dL/dtheta and maps the result
+ * back into p. */
+#define FM_PARAM_LINEAR 0  /* theta = p                                           */
+#define FM_PARAM_LOG 1     /* theta = log p; p is first raised to >= 1e-30       */
+#define FM_PARAM_LOGIT 2   /* theta = log(p / (1 - p)); p is first clamped into
+                              [1e-6, 1 - 1e-6]                                    */
+
+typedef struct {
+    float *param;        /* DEVICE [n] activated values p, updated in place      */
+    const float *grad;   /* DEVICE [n] dL/dp (e.g. the fm_surfel_grads planes)    */
+    float *m;            /* DEVICE [n] first moment of theta (zero before step 1) */
+    float *v;            /* DEVICE [n] second moment of theta (zero before step 1) */
+    int64_t n;           /* elements (0: the tensor is skipped)                   */
+    float lr;            /* learning rate of this tensor (> 0)                    */
+    int32_t kind;        /* FM_PARAM_*                                            */
+} fm_adam_tensor;
+
+typedef struct {
+    float beta1;   /* 0.9, in [0, 1)   */
+    float beta2;   /* 0.999, in [0, 1) */
+    float eps;     /* 1e-8, > 0        */
+} fm_adam_config;
+
+/* One Adam step over count tensors (HOST array of descriptors).  step is a
+ * DEVICE int32 step counter: the call first advances it by one and every
+ * update uses the advanced value t in its bias corrections, so a captured
+ * graph replays consecutive steps.  The caller owns every buffer; tensors
+ * must not overlap.  Enqueued on stream; no allocation, no synchronisation;
+ * graph-capturable.  Errors: FM_ERR_INVALID_ARG for a NULL context, step or
+ * descriptor array (count > 0), a negative count or n, NULL buffers with
+ * n > 0, lr <= 0 or non-finite, an unknown kind, or betas outside [0, 1) or
+ * eps <= 0; nothing is launched then.  FM_ERR_HIP if a launch fails. */
+fm_status fm_adam_step(fm_ctx *ctx, const fm_adam_tensor *tensors, int32_t count, const fm_adam_config *config,
+                       int32_t *step, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

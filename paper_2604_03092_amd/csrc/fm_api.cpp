@@ -681,4 +681,28 @@ fm_status fm_autotune(fm_ctx *ctx, const fm_batch *b, const fm_raster_params *pr
     return FM_OK;
 }
 
+fm_status fm_adam_step(fm_ctx *ctx, const fm_adam_tensor *tensors, int32_t count, const fm_adam_config *config,
+                       int32_t *step, void *stream) {
+    if (!ctx) return FM_ERR_INVALID_ARG;
+    if (!config || !step || count < 0 || (count > 0 && !tensors))
+        return fail(ctx, FM_ERR_INVALID_ARG, "fm_adam_step: NULL config/step/tensors or negative count");
+    if (!(config->beta1 >= 0.f && config->beta1 < 1.f) || !(config->beta2 >= 0.f && config->beta2 < 1.f) ||
+        !(config->eps > 0.f))
+        return fail(ctx, FM_ERR_INVALID_ARG, "fm_adam_step: need 0 <= beta1, beta2 < 1 and eps > 0");
+    for (int32_t k = 0; k < count; ++k) {
+        const fm_adam_tensor &t = tensors[k];
+        if (t.n < 0 || (t.n > 0 && (!t.param || !t.grad || !t.m || !t.v)))
+            return fail(ctx, FM_ERR_INVALID_ARG, "fm_adam_step: tensor " + std::to_string(k) +
+                                                     " has a negative size or a NULL buffer");
+        if (!(t.lr > 0.f) || !std::isfinite(t.lr))
+            return fail(ctx, FM_ERR_INVALID_ARG, "fm_adam_step: tensor " + std::to_string(k) + " needs lr > 0");
+        if (t.kind != FM_PARAM_LINEAR && t.kind != FM_PARAM_LOG && t.kind != FM_PARAM_LOGIT)
+            return fail(ctx, FM_ERR_INVALID_ARG, "fm_adam_step: tensor " + std::to_string(k) + " has an unknown kind");
+    }
+    fm_status s = use_device(ctx);
+    if (s != FM_OK) return s;
+    FM_TRY_HIP(fm::launch_adam(tensors, count, *config, step, (hipStream_t)stream), "adam");
+    return FM_OK;
+}
+
 }  // extern "C"

@@ -201,5 +201,7 @@ hipError_t launch_zero_grad(const Plan &p, void *ws, hipStream_t st);
 hipError_t launch_preprocess_bwd(const Plan &p, void *ws, const float *intr, const float *viewmat,
                                  float *dL_dviewmat, hipStream_t st);
 bool tile_shape_supported(int tw, int th);
+hipError_t launch_adam(const fm_adam_tensor *ts, int count, const fm_adam_config &cfg, int32_t *step,
+                       hipStream_t st);
 
 }  // namespace fm

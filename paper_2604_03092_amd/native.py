@@ -61,6 +61,20 @@ class FmL1Loss(ctypes.Structure):
                 ("w_rgb", c_float), ("w_depth", c_float)]
 
 
+FM_PARAM_LINEAR = 0
+FM_PARAM_LOG = 1
+FM_PARAM_LOGIT = 2
+
+
+class FmAdamTensor(ctypes.Structure):
+    _fields_ = [("param", c_void_p), ("grad", c_void_p), ("m", c_void_p), ("v", c_void_p), ("n", c_int64),
+                ("lr", c_float), ("kind", c_int32)]
+
+
+class FmAdamConfig(ctypes.Structure):
+    _fields_ = [("beta1", c_float), ("beta2", c_float), ("eps", c_float)]
+
+
 P = ctypes.POINTER
 SIGNATURES = {
     "fm_create": (c_int32, [P(c_void_p), c_int32]),
@@ -88,6 +102,7 @@ SIGNATURES = {
     "fm_autotune": (c_int32, [c_void_p, P(FmBatch), P(FmRasterParams), P(FmL1Loss), FmOutputs, c_void_p,
                               P(FmSurfelGrads), c_void_p, c_void_p, ctypes.c_size_t, c_int64, ctypes.c_char_p,
                               P(FmRasterParams), c_void_p]),
+    "fm_adam_step": (c_int32, [c_void_p, P(FmAdamTensor), c_int32, P(FmAdamConfig), c_void_p, c_void_p]),
 }
 
 _lib = None

@@ -301,6 +301,43 @@ class Rasterizer:
 # autograd
 # ---------------------------------------------------------------------------
 
+# parameterisation each surfel tensor is stepped in (the rasterizer takes
+# activated opacity and linear scales)
+ADAM_KINDS = {"mean": native.FM_PARAM_LINEAR, "quat": native.FM_PARAM_LINEAR, "scale": native.FM_PARAM_LOG,
+              "opacity": native.FM_PARAM_LOGIT, "color": native.FM_PARAM_LINEAR}
+ADAM_LR = {"mean": 1e-3, "quat": 1e-3, "scale": 5e-3, "opacity": 5e-2, "color": 2.5e-3}
+
+
+class Adam:
+    """Fused Adam over the surfel tensors of a GpuScene (fm_adam_step): one
+    moment pair per tensor and a device step counter, so a captured graph
+    replays consecutive steps.  grads: the per-submap gradient dicts the
+    rasterizer accumulates into (their buffers must stay the same)."""
+
+    def __init__(self, rast, gs, grads, lr=None, betas=(0.9, 0.999), eps=1e-8):
+        self.rast = rast
+        self.lr = dict(ADAM_LR, **(lr or {}))
+        self.m = [{k: torch.zeros_like(sm[k]) for k in PLANES} for sm in gs.submaps]
+        self.v = [{k: torch.zeros_like(sm[k]) for k in PLANES} for sm in gs.submaps]
+        self.step_count = torch.zeros(1, dtype=torch.int32, device=gs.intr.device)
+        self.config = native.FmAdamConfig(betas[0], betas[1], eps)
+        n = len(gs.submaps) * len(PLANES)
+        self.tensors = (native.FmAdamTensor * n)()
+        i = 0
+        for sm, g, m, v in zip(gs.submaps, grads, self.m, self.v):
+            for k in PLANES:
+                for t in (sm[k], g[k]):
+                    assert t.is_contiguous() and t.dtype == torch.float32
+                self.tensors[i] = native.FmAdamTensor(sm[k].data_ptr(), g[k].data_ptr(), m[k].data_ptr(),
+                                                      v[k].data_ptr(), sm[k].numel(), self.lr[k], ADAM_KINDS[k])
+                i += 1
+        self.n = n
+
+    def step(self, stream=None):
+        self.rast.check(self.rast.lib.fm_adam_step(self.rast.ctx, self.tensors, self.n, ctypes.byref(self.config),
+                                                   _ptr(self.step_count), _stream(stream)))
+
+
 class _RenderFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, rast, gs, params, *flat):

@@ -72,9 +72,10 @@ PROBE = r"""
 #define O(T, f) printf(#T "." #f " %zu\n", offsetof(T, f));
 int main(void) {
   S(fm_surfels) S(fm_surfel_grads) S(fm_view_shape) S(fm_batch) S(fm_raster_params) S(fm_outputs)
-  S(fm_grad_outputs) S(fm_l1_loss)
+  S(fm_grad_outputs) S(fm_l1_loss) S(fm_adam_tensor) S(fm_adam_config)
   O(fm_batch, views) O(fm_batch, intr) O(fm_batch, viewmat) O(fm_raster_params, bg)
-  O(fm_raster_params, tile_w) O(fm_l1_loss, w_rgb) O(fm_surfels, color)
+  O(fm_raster_params, tile_w) O(fm_l1_loss, w_rgb) O(fm_surfels, color) O(fm_adam_tensor, n)
+  O(fm_adam_tensor, lr) O(fm_adam_tensor, kind)
   return 0;
 }
 """
@@ -90,7 +91,8 @@ def test_ctypes_layout_matches_header():
     m = {"fm_surfels": native.FmSurfels, "fm_surfel_grads": native.FmSurfelGrads,
          "fm_view_shape": native.FmViewShape, "fm_batch": native.FmBatch,
          "fm_raster_params": native.FmRasterParams, "fm_outputs": native.FmOutputs,
-         "fm_grad_outputs": native.FmGradOutputs, "fm_l1_loss": native.FmL1Loss}
+         "fm_grad_outputs": native.FmGradOutputs, "fm_l1_loss": native.FmL1Loss,
+         "fm_adam_tensor": native.FmAdamTensor, "fm_adam_config": native.FmAdamConfig}
     for k, cls in m.items():
         assert int(vals[k]) == ctypes.sizeof(cls), k
     assert int(vals["fm_batch.views"]) == native.FmBatch.views.offset
@@ -100,6 +102,8 @@ def test_ctypes_layout_matches_header():
     assert int(vals["fm_raster_params.tile_w"]) == native.FmRasterParams.tile_w.offset
     assert int(vals["fm_l1_loss.w_rgb"]) == native.FmL1Loss.w_rgb.offset
     assert int(vals["fm_surfels.color"]) == native.FmSurfels.color.offset
+    for f in ("n", "lr", "kind"):
+        assert int(vals["fm_adam_tensor." + f]) == getattr(native.FmAdamTensor, f).offset
 
 
 def test_create_without_gpu_fails_cleanly(lib):
