@@ -49,7 +49,10 @@ def test_adam_matches_oracle(rast, kind):
             g = (rng.normal(0, 1, n) * 10.0 ** rng.uniform(-3, 1, n)).astype(np.float32)
             dev[i][1][:n] = torch.from_numpy(g).cuda()
             p, m, v = host[i]
-            host[i] = list(optim.adam_step(p, g.astype(np.float64), m, v, t, lrs[i], kind))
+            # the oracle sees the float32 values the API carries
+            f32 = lambda x: float(np.float32(x))
+            host[i] = list(optim.adam_step(p, g.astype(np.float64), m, v, t, f32(lrs[i]), kind, beta1=f32(0.9),
+                                           beta2=f32(0.999), eps=f32(1e-8)))
             d = dev[i]
             arr[i] = native.FmAdamTensor(d[0].data_ptr(), d[1].data_ptr(), d[2].data_ptr(), d[3].data_ptr(),
                                          n, lrs[i], kind)
