@@ -29,47 +29,48 @@ def _descriptor(p, g, m, v, lr, kind):
 
 @pytest.mark.parametrize("kind", [optim.LINEAR, optim.LOG, optim.LOGIT])
 def test_adam_matches_oracle(rast, kind):
+    """Three consecutive calls (device step counter 1, 2, 3) on tensors of
+    ragged sizes; each call is compared with the oracle's step from the
+    GPU's state before the call, so every comparison sees one step's
+    rounding."""
     rng = np.random.default_rng(100 + kind)
     sizes = [0, 1, 257, 65539]
-    host = []
+    lrs = [0.01, 0.02, 0.005, 0.03]
     dev = []
     for n in sizes:
         p = (rng.uniform(0.02, 0.98, n) if kind != optim.LINEAR else rng.normal(0, 1, n)).astype(np.float32)
-        host.append([p.astype(np.float64), np.zeros(n), np.zeros(n)])
-        t = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
-        dev.append([t(p), torch.zeros(max(n, 1), device="cuda"), torch.zeros(max(n, 1), device="cuda"),
-                    torch.zeros(max(n, 1), device="cuda")])
+        z = lambda: torch.zeros(max(n, 1), device="cuda")
+        d = [z(), z(), z(), z()]
+        d[0][:n] = torch.from_numpy(p).cuda()
+        dev.append(d)
     step = torch.zeros(1, dtype=torch.int32, device="cuda")
     cfg = native.FmAdamConfig(0.9, 0.999, 1e-8)
-    lrs = [0.01, 0.02, 0.005, 0.03]
-    scale = [None] * len(sizes)
+    f32 = lambda x: float(np.float32(x))  # the oracle sees the float32 values the API carries
     for t in range(1, 4):
         _say(f"adam kind={kind} step {t}")
         arr = (native.FmAdamTensor * len(sizes))()
+        expect = []
         for i, n in enumerate(sizes):
             g = (rng.normal(0, 1, n) * 10.0 ** rng.uniform(-3, 1, n)).astype(np.float32)
             dev[i][1][:n] = torch.from_numpy(g).cuda()
-            p, m, v = host[i]
-            # the oracle sees the float32 values the API carries
-            f32 = lambda x: float(np.float32(x))
-            host[i] = list(optim.adam_step(p, g.astype(np.float64), m, v, t, f32(lrs[i]), kind, beta1=f32(0.9),
-                                           beta2=f32(0.999), eps=f32(1e-8)))
-            # FP32 rounding bounds: a few ulps of the terms each moment sums
-            _, gt = optim.to_theta(p, g, kind)
-            scale[i] = (0.9 * np.abs(m) + 0.1 * np.abs(gt), 0.999 * v + 0.001 * gt * gt)
+            p0, m0, v0 = (dev[i][k][:n].cpu().numpy().astype(np.float64) for k in (0, 2, 3))
+            p1, m1, v1 = optim.adam_step(p0, g.astype(np.float64), m0, v0, t, f32(lrs[i]), kind, beta1=f32(0.9),
+                                         beta2=f32(0.999), eps=f32(1e-8))
+            _, gt = optim.to_theta(p0, g, kind)
+            # FP32 rounding bounds: a few ulps of the terms each moment sums;
+            # the step lr * m_hat / (sqrt(v_hat) + eps) is O(lr)
+            expect.append((p1, m1, v1, 0.9 * np.abs(m0) + 0.1 * np.abs(gt), 0.999 * v0 + 0.001 * gt * gt))
             d = dev[i]
             arr[i] = native.FmAdamTensor(d[0].data_ptr(), d[1].data_ptr(), d[2].data_ptr(), d[3].data_ptr(),
                                          n, lrs[i], kind)
         rast.check(rast.lib.fm_adam_step(rast.ctx, arr, len(sizes), ctypes.byref(cfg), _ptr(step), None))
         torch.cuda.synchronize()
         for i, n in enumerate(sizes):
-            p, m, v = host[i]
-            sm, sv = scale[i]
-            assert np.all(np.abs(dev[i][2][:n].cpu().numpy() - m) <= 1e-6 * sm + 1e-30), (kind, n, t)
-            assert np.all(np.abs(dev[i][3][:n].cpu().numpy() - v) <= 1e-6 * sv + 1e-30), (kind, n, t)
-            # the step is lr * m_hat / (sqrt(v_hat) + eps) = O(lr): its error is a few ulps of lr
-            assert np.all(np.abs(dev[i][0][:n].cpu().numpy() - p) <= 2e-6 * np.abs(p) + 1e-5 * lrs[i]), \
-                (kind, n, t)
+            p1, m1, v1, sm, sv = expect[i]
+            gp, gm, gv = (dev[i][k][:n].cpu().numpy() for k in (0, 2, 3))
+            assert np.all(np.abs(gm - m1) <= 1e-6 * sm + 1e-30), (kind, n, t)
+            assert np.all(np.abs(gv - v1) <= 1e-6 * sv + 1e-30), (kind, n, t)
+            assert np.all(np.abs(gp - p1) <= 2e-6 * np.abs(p1) + 1e-5 * lrs[i]), (kind, n, t)
     assert int(step.item()) == 3
 
 
