@@ -250,12 +250,14 @@ def _depth_field(rng, w, h, n_waves=6, lo=1.0, hi=6.0):
     return lo + (hi - lo) * d
 
 
-def per_pixel_frame(rng, w, h, fx, fy, cx, cy, r_wc, c):
-    """One frame of a pixel-aligned surfel map in world coordinates: a smooth
-    random depth field in [1,6], centres unprojected through the pixel centres,
-    normals from central-difference tangents (facing the camera), tangent
-    frame t_u = normalise(e_x - (e_x.n)n), t_v = n x t_u, scales
-    depth/fx * U(0.5,1.5), opacity U(0.3,1), colour U[0,1]."""
+def per_pixel_camera(rng, w, h, fx, fy, cx, cy):
+    """One frame of a pixel-aligned surfel map in camera coordinates, as
+    (centres [h,w,3], tangent frames [h,w,3,3] with columns t_u, t_v, n,
+    scales [2,h*w], opacity [h*w], colour [3,h*w]): a smooth random depth
+    field in [1,6], centres unprojected through the pixel centres, normals
+    from central-difference tangents (facing the camera), tangent frame
+    t_u = normalise(e_x - (e_x.n)n), t_v = n x t_u, scales depth/fx *
+    U(0.5,1.5), opacity U(0.3,1), colour U[0,1]."""
     d = _depth_field(rng, w, h)
     yy, xx = np.meshgrid(np.arange(h) + 0.5, np.arange(w) + 0.5, indexing="ij")
     mu = np.stack([(xx - cx) / fx * d, (yy - cy) / fy * d, d], -1)          # [h,w,3] camera
@@ -270,16 +272,62 @@ def per_pixel_frame(rng, w, h, fx, fy, cx, cy, r_wc, c):
     tu /= np.maximum(np.linalg.norm(tu, axis=-1, keepdims=True), 1e-12)
     tv = np.cross(n, tu)
     rs = np.stack([tu, tv, n], -1)                                         # columns
-    rs_w = np.einsum("ij,hwjk->hwik", r_wc, rs)
-    mu_w = mu @ r_wc.T + c
-    q = quat_from_matrix(rs_w.reshape(-1, 3, 3))
     npx = w * h
     scale = (d.reshape(1, -1) / fx) * rng.uniform(0.5, 1.5, (2, npx))
-    return dict(mean=np.ascontiguousarray(mu_w.reshape(-1, 3).T.astype(np.float32)),
+    opacity = rng.uniform(0.3, 1.0, npx)
+    color = rng.random((3, npx))
+    return mu, rs, scale, opacity, color
+
+
+def _planes(mu, rs, scale, opacity, color):
+    q = quat_from_matrix(rs.reshape(-1, 3, 3))
+    return dict(mean=np.ascontiguousarray(mu.reshape(-1, 3).T.astype(np.float32)),
                 quat=np.ascontiguousarray(q.T.astype(np.float32)),
                 scale=np.ascontiguousarray(scale.astype(np.float32)),
-                opacity=rng.uniform(0.3, 1.0, npx).astype(np.float32),
-                color=rng.random((3, npx)).astype(np.float32))
+                opacity=opacity.astype(np.float32),
+                color=color.astype(np.float32))
+
+
+def per_pixel_frame(rng, w, h, fx, fy, cx, cy, r_wc, c):
+    """per_pixel_camera's map moved into world coordinates by the camera
+    rotation r_wc and centre c."""
+    mu, rs, scale, opacity, color = per_pixel_camera(rng, w, h, fx, fy, cx, cy)
+    return _planes(mu @ r_wc.T + c, np.einsum("ij,hwjk->hwik", r_wc, rs), scale, opacity, color)
+
+
+@dataclass
+class FusionFrame:
+    """A frame for map fusion: its per-pixel map in camera coordinates, its
+    camera-to-world similarity x_w = s R(q) x_c + t and an accumulated-alpha
+    map of the global map rendered from it."""
+    width: int
+    height: int
+    planes: dict
+    s: float
+    q: np.ndarray
+    t: np.ndarray
+    accum: np.ndarray
+
+
+def fusion_frames(n_frames=32, w=518, h=392, seed_offset=0):
+    """Frames of the map-fusion workload: config-4 per-pixel maps in camera
+    coordinates, poses along config 4's small-step trajectory with a scale in
+    U(0.9, 1.1), and accumulation maps from a smooth random field in [0, 1]."""
+    rng = np.random.Generator(np.random.PCG64(SEED_BASE + 40 + seed_offset))
+    fx = fy = 400.0
+    cx, cy = w / 2.0, h / 2.0
+    out = []
+    pos = np.zeros(3)
+    yaw = 0.0
+    for _ in range(n_frames):
+        yaw += math.radians(rng.uniform(-1.0, 1.0))
+        pos = pos + rng.uniform(-0.02, 0.02, 3)
+        planes = _planes(*per_pixel_camera(rng, w, h, fx, fy, cx, cy))
+        q = quat_from_matrix(_rot_y(yaw).reshape(1, 3, 3))[0]
+        acc = (_depth_field(rng, w, h, lo=0.0, hi=1.0)).reshape(-1)
+        out.append(FusionFrame(w, h, planes, float(rng.uniform(0.9, 1.1)), q.astype(np.float32),
+                               pos.astype(np.float32), acc.astype(np.float32)))
+    return out
 
 
 def config4(n_frames=32, stress=False, w=518, h=392):
