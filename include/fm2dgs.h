@@ -296,6 +296,67 @@ typedef struct {
 fm_status fm_adam_step(fm_ctx *ctx, const fm_adam_tensor *tensors, int32_t count, const fm_adam_config *config,
                        int32_t *step, void *stream);
 
+/* ---- map fusion: an incoming per-pixel map -------------------------------
+ *
+ * The frontend predicts one surfel per pixel of a keyframe.  Before it joins
+ * the global map (Sec. 3.3), the map is thinned by adaptive voxelization:
+ * the pixel grid is cut into 2x2 blocks (blocks cut by the image border hold
+ * 2 or 1 pixels); a block whose camera-space depth range max z - min z is at
+ * most tau_depth becomes one primitive with the mean centre, scales, opacity
+ * and colour of its pixels and the normalised sum of their quaternions, each
+ * first sign-aligned with the block's first (Eq. for r_merged).  Blocks with
+ * a larger depth range, and 1-pixel blocks, keep their primitives.  The
+ * survivors move to world coordinates by the keyframe's similarity:
+ * mu_w = s R(q) mu + t, r_w = q r (Hamilton product), scales times s.  With
+ * an accumulation map (the accumulated alpha of the global map rendered from
+ * the keyframe), primitives are only added where the map is not yet well
+ * reconstructed: a merged block when the mean of its pixels' values is below
+ * tau_accum, a kept pixel when its own value is.  The float comparisons are
+ * made in float32 in the order: depth range as (max - min); accumulation
+ * sum as (a0 + a1) + (a2 + a3) or a0 + a1, compared with tau_accum * n. */
+typedef struct {
+    int32_t width, height;  /* pixel grid (>= 1 each, width * height < 2^31)      */
+    const float *mean;      /* DEVICE [3][W*H] camera-space centres, pixels row-major */
+    const float *quat;      /* DEVICE [4][W*H] (w, x, y, z) rotations              */
+    const float *scale;     /* DEVICE [2][W*H]                                      */
+    const float *opacity;   /* DEVICE [W*H]                                         */
+    const float *color;     /* DEVICE [3][W*H]                                      */
+} fm_pixel_map;
+
+typedef struct {
+    float s;      /* scale (> 0)                                  */
+    float q[4];   /* rotation (w, x, y, z), any non-zero norm     */
+    float t[3];   /* translation                                  */
+} fm_sim3;        /* camera -> world: x_w = s R(q) x_c + t         */
+
+typedef struct {
+    float tau_depth;  /* merge a block when its depth range is <= tau_depth (< 0: never)  */
+    float tau_accum;  /* with an accumulation map: add only below this accumulated alpha */
+} fm_fusion_params;
+
+typedef struct {
+    float *mean, *quat, *scale, *opacity, *color;  /* DEVICE [C][capacity] output planes */
+    int64_t capacity;                              /* primitives the planes hold (>= 0)  */
+} fm_surfel_buffer;
+
+/* Workspace bytes fm_voxelize_fuse needs for a width x height map. */
+size_t fm_fusion_workspace_size(int32_t width, int32_t height);
+
+/* Voxelize, transform and gate one per-pixel map; the survivors are written
+ * to out in block order (blocks row-major over the block grid, a kept
+ * block's pixels row-major) and their number to *count (DEVICE int32).
+ * Primitives beyond out.capacity are not written; *count still reports how
+ * many there are, so a caller compares it with the capacity (width * height
+ * always suffices).  accum: DEVICE [W*H] or NULL (no gate).  pose: HOST.
+ * Enqueued on stream; no allocation, no synchronisation; graph-capturable.
+ * Errors: FM_ERR_INVALID_ARG for NULL pointers, a grid outside the limits,
+ * s <= 0, a zero or non-finite quaternion, a negative capacity or NULL output
+ * planes with capacity > 0; FM_ERR_WORKSPACE when ws_bytes is below
+ * fm_fusion_workspace_size; FM_ERR_HIP if a launch fails. */
+fm_status fm_voxelize_fuse(fm_ctx *ctx, const fm_pixel_map *in, const fm_sim3 *pose,
+                           const fm_fusion_params *params, const float *accum, fm_surfel_buffer out,
+                           int32_t *count, void *workspace, size_t ws_bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -705,4 +705,35 @@ fm_status fm_adam_step(fm_ctx *ctx, const fm_adam_tensor *tensors, int32_t count
     return FM_OK;
 }
 
+size_t fm_fusion_workspace_size(int32_t width, int32_t height) {
+    if (width < 1 || height < 1) return 0;
+    return fm::fusion_workspace_bytes(width, height);
+}
+
+fm_status fm_voxelize_fuse(fm_ctx *ctx, const fm_pixel_map *in, const fm_sim3 *pose,
+                           const fm_fusion_params *params, const float *accum, fm_surfel_buffer out,
+                           int32_t *count, void *workspace, size_t ws_bytes, void *stream) {
+    if (!ctx) return FM_ERR_INVALID_ARG;
+    if (!in || !pose || !params || !count || !workspace)
+        return fail(ctx, FM_ERR_INVALID_ARG, "fm_voxelize_fuse: NULL map, pose, params, count or workspace");
+    if (in->width < 1 || in->height < 1 || (int64_t)in->width * in->height >= ((int64_t)1 << 31))
+        return fail(ctx, FM_ERR_INVALID_ARG, "fm_voxelize_fuse: need width, height >= 1 and width*height < 2^31");
+    if (!in->mean || !in->quat || !in->scale || !in->opacity || !in->color)
+        return fail(ctx, FM_ERR_INVALID_ARG, "fm_voxelize_fuse: NULL input plane");
+    const double qq = (double)pose->q[0] * pose->q[0] + (double)pose->q[1] * pose->q[1] +
+                      (double)pose->q[2] * pose->q[2] + (double)pose->q[3] * pose->q[3];
+    if (!(pose->s > 0.f) || !std::isfinite(pose->s) || !(qq > 0.0) || !std::isfinite(qq) ||
+        !std::isfinite(pose->t[0]) || !std::isfinite(pose->t[1]) || !std::isfinite(pose->t[2]))
+        return fail(ctx, FM_ERR_INVALID_ARG, "fm_voxelize_fuse: need s > 0 and a finite, non-zero pose");
+    if (out.capacity < 0 ||
+        (out.capacity > 0 && (!out.mean || !out.quat || !out.scale || !out.opacity || !out.color)))
+        return fail(ctx, FM_ERR_INVALID_ARG, "fm_voxelize_fuse: bad output buffer");
+    if (ws_bytes < fm::fusion_workspace_bytes(in->width, in->height))
+        return fail(ctx, FM_ERR_WORKSPACE, "fm_voxelize_fuse: workspace too small");
+    fm_status s = use_device(ctx);
+    if (s != FM_OK) return s;
+    FM_TRY_HIP(fm::launch_fusion(*in, *pose, *params, accum, out, count, workspace, (hipStream_t)stream), "fusion");
+    return FM_OK;
+}
+
 }  // extern "C"

@@ -1,0 +1,264 @@
+// fm_fusion.hip -- map fusion of an incoming per-pixel surfel map (Sec. 3.3):
+// adaptive 2x2 voxelization, the camera-to-world similarity and the
+// accumulation gate, written out as compacted SoA planes.
+//
+// The pixel grid is cut into 2x2 blocks (border blocks hold 2 or 1 pixels).
+// A block whose camera-space depth range is at most tau_depth becomes one
+// primitive: means of centre, scales, opacity and colour, and the normalised
+// sum of the quaternions after aligning each with the block's first.  Other
+// blocks keep their primitives.  With an accumulation map, a merged block is
+// kept when its mean value is below tau_accum, a kept pixel when its own
+// value is.  Survivors are mapped to world coordinates: mu_w = s R mu + t,
+// r_w = q r, scales times s.
+//
+// Three kernels: per chunk of 1024 blocks the survivor counts (reads depth
+// and accumulation only), one exclusive scan of the chunk sums, and the
+// write pass (block-wide scan of the recomputed counts, then the merge and
+// the transform).  Output order: blocks in row-major order, a kept block's
+// pixels in row-major order.
+#include "fm_internal.h"
+#include "fm_wave.h"
+
+namespace fm {
+
+namespace {
+
+constexpr int kFuseChunk = 1024;  // blocks per workgroup
+
+struct BlockPix {
+    int n;       // pixels in the block (1, 2 or 4)
+    int64_t p[4];
+};
+
+__device__ __forceinline__ BlockPix block_pixels(int64_t b, int W, int H) {
+    const int BX = (W + 1) >> 1;
+    const int bx = (int)(b % BX), by = (int)(b / BX);
+    BlockPix bp;
+    bp.n = 0;
+#pragma unroll
+    for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < 2; ++dx) {
+            const int x = 2 * bx + dx, y = 2 * by + dy;
+            if (x < W && y < H) bp.p[bp.n++] = (int64_t)y * W + x;
+        }
+    return bp;
+}
+
+// merge decision and survivor count of a block; keep_mask bit i: pixel i is
+// kept on its own (unmerged blocks)
+__device__ __forceinline__ int block_count(const BlockPix &bp, const float *__restrict__ z,
+                                           const float *__restrict__ accum, float tau_d, float tau_a,
+                                           bool &merge, uint32_t &keep_mask) {
+#pragma clang fp contract(off)
+    float zmin = z[bp.p[0]], zmax = zmin;
+    for (int i = 1; i < bp.n; ++i) {
+        const float v = z[bp.p[i]];
+        zmin = fminf(zmin, v);
+        zmax = fmaxf(zmax, v);
+    }
+    merge = bp.n > 1 && (zmax - zmin) <= tau_d;
+    keep_mask = 0;
+    if (merge) {
+        if (!accum) return 1;
+        float tot;
+        if (bp.n == 4)
+            tot = (accum[bp.p[0]] + accum[bp.p[1]]) + (accum[bp.p[2]] + accum[bp.p[3]]);
+        else
+            tot = accum[bp.p[0]] + accum[bp.p[1]];
+        return tot < tau_a * (float)bp.n ? 1 : 0;
+    }
+    int c = 0;
+    for (int i = 0; i < bp.n; ++i)
+        if (!accum || accum[bp.p[i]] < tau_a) {
+            keep_mask |= 1u << i;
+            ++c;
+        }
+    return c;
+}
+
+__device__ __forceinline__ float block_sum(float v, float *red) {
+    v = wave_sum(v);
+    __syncthreads();
+    if (lane_id() == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    float s = 0.f;
+    for (int w = 0; w < kFuseChunk / 64; ++w) s += red[w];
+    return s;
+}
+
+__global__ __launch_bounds__(kFuseChunk) void k_fuse_count(fm_pixel_map in, fm_fusion_params fp,
+                                                            const float *__restrict__ accum,
+                                                            uint32_t *__restrict__ chunk_sum) {
+    __shared__ float red[kFuseChunk / 64];
+    const int64_t NB = (int64_t)((in.width + 1) >> 1) * ((in.height + 1) >> 1);
+    const int64_t b = (int64_t)blockIdx.x * kFuseChunk + threadIdx.x;
+    const float *z = in.mean + 2 * (int64_t)in.width * in.height;
+    int c = 0;
+    if (b < NB) {
+        bool merge;
+        uint32_t km;
+        c = block_count(block_pixels(b, in.width, in.height), z, accum, fp.tau_depth, fp.tau_accum, merge, km);
+    }
+    // counts <= 4 * 1024 are exact in float
+    const float s = block_sum((float)c, red);
+    if (threadIdx.x == 0) chunk_sum[blockIdx.x] = (uint32_t)s;
+}
+
+__global__ __launch_bounds__(1024) void k_fuse_scan(uint32_t *__restrict__ chunk, int n, int32_t *__restrict__ count) {
+    __shared__ uint32_t part[1024];
+    const int per = (n + 1023) / 1024;
+    const int beg = threadIdx.x * per, end = beg + per < n ? beg + per : n;
+    uint32_t s = 0;
+    for (int i = beg; i < end; ++i) s += chunk[i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const uint32_t v = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0u;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    uint32_t run = threadIdx.x ? part[threadIdx.x - 1] : 0u;
+    for (int i = beg; i < end; ++i) {
+        const uint32_t c = chunk[i];
+        chunk[i] = run;
+        run += c;
+    }
+    if (threadIdx.x == 1023) *count = (int32_t)part[1023];
+}
+
+__device__ __forceinline__ void put(const fm_surfel_buffer &o, int64_t k, const float *mu, const float *q,
+                                    const float *sc, float op, const float *col) {
+    const int64_t C = o.capacity;
+    o.mean[k] = mu[0]; o.mean[C + k] = mu[1]; o.mean[2 * C + k] = mu[2];
+    o.quat[k] = q[0]; o.quat[C + k] = q[1]; o.quat[2 * C + k] = q[2]; o.quat[3 * C + k] = q[3];
+    o.scale[k] = sc[0]; o.scale[C + k] = sc[1];
+    o.opacity[k] = op;
+    o.color[k] = col[0]; o.color[C + k] = col[1]; o.color[2 * C + k] = col[2];
+}
+
+struct Sim3f {
+    float s, R[9], q[4], t[3];
+};
+
+__device__ __forceinline__ void to_world(const Sim3f &T, float *mu, float *q, float *sc) {
+#pragma clang fp contract(off)
+    const float x = mu[0], y = mu[1], z = mu[2];
+    mu[0] = T.s * (T.R[0] * x + T.R[1] * y + T.R[2] * z) + T.t[0];
+    mu[1] = T.s * (T.R[3] * x + T.R[4] * y + T.R[5] * z) + T.t[1];
+    mu[2] = T.s * (T.R[6] * x + T.R[7] * y + T.R[8] * z) + T.t[2];
+    const float aw = T.q[0], ax = T.q[1], ay = T.q[2], az = T.q[3];
+    const float bw = q[0], bx = q[1], by = q[2], bz = q[3];
+    q[0] = aw * bw - ax * bx - ay * by - az * bz;
+    q[1] = aw * bx + ax * bw + ay * bz - az * by;
+    q[2] = aw * by - ax * bz + ay * bw + az * bx;
+    q[3] = aw * bz + ax * by - ay * bx + az * bw;
+    sc[0] *= T.s;
+    sc[1] *= T.s;
+}
+
+__global__ __launch_bounds__(kFuseChunk) void k_fuse_write(fm_pixel_map in, fm_fusion_params fp, Sim3f T,
+                                                            const float *__restrict__ accum,
+                                                            const uint32_t *__restrict__ chunk_off,
+                                                            fm_surfel_buffer out) {
+#pragma clang fp contract(off)
+    __shared__ uint32_t wsum[kFuseChunk / 64];
+    const int W = in.width, H = in.height;
+    const int64_t P = (int64_t)W * H;
+    const int64_t NB = (int64_t)((W + 1) >> 1) * ((H + 1) >> 1);
+    const int64_t b = (int64_t)blockIdx.x * kFuseChunk + threadIdx.x;
+    const float *z = in.mean + 2 * P;
+    BlockPix bp;
+    bp.n = 0;
+    bool merge = false;
+    uint32_t km = 0;
+    int c = 0;
+    if (b < NB) {
+        bp = block_pixels(b, W, H);
+        c = block_count(bp, z, accum, fp.tau_depth, fp.tau_accum, merge, km);
+    }
+    // block-wide exclusive scan of the counts
+    const int lane = lane_id(), w = threadIdx.x >> 6;
+    uint32_t x = (uint32_t)c;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) wsum[w] = x;
+    __syncthreads();
+    uint32_t base = chunk_off[blockIdx.x] + x - (uint32_t)c;
+    for (int j = 0; j < w; ++j) base += wsum[j];
+    if (c == 0) return;
+    if (merge) {
+        float mu[3] = {0.f, 0.f, 0.f}, sc[2] = {0.f, 0.f}, col[3] = {0.f, 0.f, 0.f}, op = 0.f;
+        float q[4] = {0.f, 0.f, 0.f, 0.f};
+        const float q0w = in.quat[bp.p[0]], q0x = in.quat[P + bp.p[0]], q0y = in.quat[2 * P + bp.p[0]],
+                    q0z = in.quat[3 * P + bp.p[0]];
+        for (int i = 0; i < bp.n; ++i) {
+            const int64_t p = bp.p[i];
+            for (int k = 0; k < 3; ++k) mu[k] += in.mean[k * P + p];
+            for (int k = 0; k < 2; ++k) sc[k] += in.scale[k * P + p];
+            for (int k = 0; k < 3; ++k) col[k] += in.color[k * P + p];
+            op += in.opacity[p];
+            const float qw = in.quat[p], qx = in.quat[P + p], qy = in.quat[2 * P + p], qz = in.quat[3 * P + p];
+            const float d = (qw * q0w + qx * q0x) + (qy * q0y + qz * q0z);
+            const float sg = d < 0.f ? -1.f : 1.f;
+            q[0] += sg * qw; q[1] += sg * qx; q[2] += sg * qy; q[3] += sg * qz;
+        }
+        const float inv = 1.f / (float)bp.n;
+        for (int k = 0; k < 3; ++k) { mu[k] *= inv; col[k] *= inv; }
+        sc[0] *= inv; sc[1] *= inv;
+        op *= inv;
+        const float qn = 1.f / sqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+        for (int k = 0; k < 4; ++k) q[k] *= qn;
+        to_world(T, mu, q, sc);
+        if ((int64_t)base < out.capacity) put(out, base, mu, q, sc, op, col);
+        return;
+    }
+    uint32_t o = base;
+    for (int i = 0; i < bp.n; ++i) {
+        if (!((km >> i) & 1u)) continue;
+        const int64_t p = bp.p[i];
+        float mu[3] = {in.mean[p], in.mean[P + p], in.mean[2 * P + p]};
+        float q[4] = {in.quat[p], in.quat[P + p], in.quat[2 * P + p], in.quat[3 * P + p]};
+        float sc[2] = {in.scale[p], in.scale[P + p]};
+        const float col[3] = {in.color[p], in.color[P + p], in.color[2 * P + p]};
+        to_world(T, mu, q, sc);
+        if ((int64_t)o < out.capacity) put(out, o, mu, q, sc, in.opacity[p], col);
+        ++o;
+    }
+}
+
+}  // namespace
+
+size_t fusion_workspace_bytes(int32_t width, int32_t height) {
+    const int64_t NB = (int64_t)((width + 1) / 2) * ((height + 1) / 2);
+    return 4 * (size_t)((NB + kFuseChunk - 1) / kFuseChunk + 1);
+}
+
+hipError_t launch_fusion(const fm_pixel_map &in, const fm_sim3 &pose, const fm_fusion_params &fp,
+                         const float *accum, const fm_surfel_buffer &out, int32_t *count, void *ws,
+                         hipStream_t st) {
+    const int64_t NB = (int64_t)((in.width + 1) / 2) * ((in.height + 1) / 2);
+    const int chunks = (int)((NB + kFuseChunk - 1) / kFuseChunk);
+    uint32_t *chunk = static_cast<uint32_t *>(ws);
+    // the similarity on the host: unit quaternion and its rotation matrix
+    Sim3f T;
+    const double qn = std::sqrt((double)pose.q[0] * pose.q[0] + (double)pose.q[1] * pose.q[1] +
+                                (double)pose.q[2] * pose.q[2] + (double)pose.q[3] * pose.q[3]);
+    const double w = pose.q[0] / qn, x = pose.q[1] / qn, y = pose.q[2] / qn, z = pose.q[3] / qn;
+    const double R[9] = {1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y),
+                         2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
+                         2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)};
+    T.s = pose.s;
+    for (int k = 0; k < 9; ++k) T.R[k] = (float)R[k];
+    T.q[0] = (float)w; T.q[1] = (float)x; T.q[2] = (float)y; T.q[3] = (float)z;
+    for (int k = 0; k < 3; ++k) T.t[k] = pose.t[k];
+    hipLaunchKernelGGL(k_fuse_count, dim3(chunks), dim3(kFuseChunk), 0, st, in, fp, accum, chunk);
+    hipLaunchKernelGGL(k_fuse_scan, dim3(1), dim3(1024), 0, st, chunk, chunks, count);
+    hipLaunchKernelGGL(k_fuse_write, dim3(chunks), dim3(kFuseChunk), 0, st, in, fp, T, accum, chunk, out);
+    return hipGetLastError();
+}
+
+}  // namespace fm

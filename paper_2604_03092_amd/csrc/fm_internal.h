@@ -201,6 +201,10 @@ hipError_t launch_zero_grad(const Plan &p, void *ws, hipStream_t st);
 hipError_t launch_preprocess_bwd(const Plan &p, void *ws, const float *intr, const float *viewmat,
                                  float *dL_dviewmat, hipStream_t st);
 bool tile_shape_supported(int tw, int th);
+size_t fusion_workspace_bytes(int32_t width, int32_t height);
+hipError_t launch_fusion(const fm_pixel_map &in, const fm_sim3 &pose, const fm_fusion_params &fp,
+                         const float *accum, const fm_surfel_buffer &out, int32_t *count, void *ws,
+                         hipStream_t st);
 hipError_t launch_adam(const fm_adam_tensor *ts, int count, const fm_adam_config &cfg, int32_t *step,
                        hipStream_t st);
 

@@ -75,6 +75,24 @@ class FmAdamConfig(ctypes.Structure):
     _fields_ = [("beta1", c_float), ("beta2", c_float), ("eps", c_float)]
 
 
+class FmPixelMap(ctypes.Structure):
+    _fields_ = [("width", c_int32), ("height", c_int32), ("mean", c_void_p), ("quat", c_void_p),
+                ("scale", c_void_p), ("opacity", c_void_p), ("color", c_void_p)]
+
+
+class FmSim3(ctypes.Structure):
+    _fields_ = [("s", c_float), ("q", c_float * 4), ("t", c_float * 3)]
+
+
+class FmFusionParams(ctypes.Structure):
+    _fields_ = [("tau_depth", c_float), ("tau_accum", c_float)]
+
+
+class FmSurfelBuffer(ctypes.Structure):
+    _fields_ = [("mean", c_void_p), ("quat", c_void_p), ("scale", c_void_p), ("opacity", c_void_p),
+                ("color", c_void_p), ("capacity", c_int64)]
+
+
 P = ctypes.POINTER
 SIGNATURES = {
     "fm_create": (c_int32, [P(c_void_p), c_int32]),
@@ -103,6 +121,9 @@ SIGNATURES = {
                               P(FmSurfelGrads), c_void_p, c_void_p, ctypes.c_size_t, c_int64, ctypes.c_char_p,
                               P(FmRasterParams), c_void_p]),
     "fm_adam_step": (c_int32, [c_void_p, P(FmAdamTensor), c_int32, P(FmAdamConfig), c_void_p, c_void_p]),
+    "fm_fusion_workspace_size": (ctypes.c_size_t, [c_int32, c_int32]),
+    "fm_voxelize_fuse": (c_int32, [c_void_p, P(FmPixelMap), P(FmSim3), P(FmFusionParams), c_void_p,
+                                   FmSurfelBuffer, c_void_p, c_void_p, ctypes.c_size_t, c_void_p]),
 }
 
 _lib = None

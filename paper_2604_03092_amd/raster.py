@@ -338,6 +338,32 @@ class Adam:
                                                    _ptr(self.step_count), _stream(stream)))
 
 
+class Fusion:
+    """Map fusion of per-pixel maps (fm_voxelize_fuse) with an owned
+    workspace and output planes sized for the largest frame."""
+
+    def __init__(self, rast, width, height, device="cuda"):
+        self.rast = rast
+        self.cap = width * height
+        n = rast.lib.fm_fusion_workspace_size(width, height)
+        self.ws = torch.empty(max(int(n), 4), dtype=torch.uint8, device=device)
+        self.out = {k: torch.empty(CHANNELS[k], self.cap, device=device) for k in PLANES}
+        self.count = torch.zeros(1, dtype=torch.int32, device=device)
+
+    def run(self, planes, width, height, s, q, t, tau_depth, accum=None, tau_accum=1.0, stream=None):
+        """Fuse one map (dict of device planes [C, W*H]); returns the count
+        tensor (device) -- the first count entries of self.out are valid."""
+        pm = native.FmPixelMap(width, height, *(planes[k].data_ptr() for k in PLANES))
+        pose = native.FmSim3(float(s), (ctypes.c_float * 4)(*[float(x) for x in q]),
+                             (ctypes.c_float * 3)(*[float(x) for x in t]))
+        fp = native.FmFusionParams(float(tau_depth), float(tau_accum))
+        buf = native.FmSurfelBuffer(*(self.out[k].data_ptr() for k in PLANES), self.cap)
+        self.rast.check(self.rast.lib.fm_voxelize_fuse(self.rast.ctx, ctypes.byref(pm), ctypes.byref(pose),
+                                                       ctypes.byref(fp), _ptr(accum), buf, _ptr(self.count),
+                                                       _ptr(self.ws), self.ws.numel(), _stream(stream)))
+        return self.count
+
+
 class _RenderFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, rast, gs, params, *flat):

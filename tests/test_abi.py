@@ -18,7 +18,7 @@ HEADER = os.path.join(ROOT, "include", "fm2dgs.h")
 
 def declared_functions():
     text = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:fm_status|void|const char \*|int)\s*\*?\s*(fm_\w+)\s*\(", text, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:fm_status|void|const char \*|int|size_t)\s*\*?\s*(fm_\w+)\s*\(", text, re.M)))
 
 
 @pytest.fixture(scope="module")
@@ -72,7 +72,8 @@ PROBE = r"""
 #define O(T, f) printf(#T "." #f " %zu\n", offsetof(T, f));
 int main(void) {
   S(fm_surfels) S(fm_surfel_grads) S(fm_view_shape) S(fm_batch) S(fm_raster_params) S(fm_outputs)
-  S(fm_grad_outputs) S(fm_l1_loss) S(fm_adam_tensor) S(fm_adam_config)
+  S(fm_grad_outputs) S(fm_l1_loss) S(fm_adam_tensor) S(fm_adam_config) S(fm_pixel_map) S(fm_sim3)
+  S(fm_fusion_params) S(fm_surfel_buffer) O(fm_surfel_buffer, capacity) O(fm_sim3, t)
   O(fm_batch, views) O(fm_batch, intr) O(fm_batch, viewmat) O(fm_raster_params, bg)
   O(fm_raster_params, tile_w) O(fm_l1_loss, w_rgb) O(fm_surfels, color) O(fm_adam_tensor, n)
   O(fm_adam_tensor, lr) O(fm_adam_tensor, kind)
@@ -92,7 +93,9 @@ def test_ctypes_layout_matches_header():
          "fm_view_shape": native.FmViewShape, "fm_batch": native.FmBatch,
          "fm_raster_params": native.FmRasterParams, "fm_outputs": native.FmOutputs,
          "fm_grad_outputs": native.FmGradOutputs, "fm_l1_loss": native.FmL1Loss,
-         "fm_adam_tensor": native.FmAdamTensor, "fm_adam_config": native.FmAdamConfig}
+         "fm_adam_tensor": native.FmAdamTensor, "fm_adam_config": native.FmAdamConfig,
+         "fm_pixel_map": native.FmPixelMap, "fm_sim3": native.FmSim3, "fm_fusion_params": native.FmFusionParams,
+         "fm_surfel_buffer": native.FmSurfelBuffer}
     for k, cls in m.items():
         assert int(vals[k]) == ctypes.sizeof(cls), k
     assert int(vals["fm_batch.views"]) == native.FmBatch.views.offset
@@ -102,6 +105,8 @@ def test_ctypes_layout_matches_header():
     assert int(vals["fm_raster_params.tile_w"]) == native.FmRasterParams.tile_w.offset
     assert int(vals["fm_l1_loss.w_rgb"]) == native.FmL1Loss.w_rgb.offset
     assert int(vals["fm_surfels.color"]) == native.FmSurfels.color.offset
+    assert int(vals["fm_surfel_buffer.capacity"]) == native.FmSurfelBuffer.capacity.offset
+    assert int(vals["fm_sim3.t"]) == native.FmSim3.t.offset
     for f in ("n", "lr", "kind"):
         assert int(vals["fm_adam_tensor." + f]) == getattr(native.FmAdamTensor, f).offset
 

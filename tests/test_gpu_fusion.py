@@ -1,0 +1,87 @@
+"""GPU parity of map fusion (fm_voxelize_fuse through the C ABI) against the
+FP64 fusion oracle: counts and order exact, values to float32 rounding."""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import fusion
+from paper_2604_03092_amd import native, scenes
+from paper_2604_03092_amd.raster import PLANES, Fusion, Rasterizer, _ptr
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rast():
+    return Rasterizer()
+
+
+def _dev(planes):
+    return {k: torch.from_numpy(np.ascontiguousarray(planes[k])).cuda() for k in PLANES}
+
+
+def _check(fu, ref, n):
+    for k in PLANES:
+        want = ref[k].reshape(-1, n)
+        got = fu.out[k].reshape(-1, fu.cap)[:, :n].cpu().numpy().astype(np.float64)
+        tol = 2e-6 * (np.abs(want) + (1.0 if k == "mean" else 0.0) * 6.0) + 1e-7
+        assert np.all(np.abs(got - want) <= tol), (k, np.max(np.abs(got - want) - tol))
+
+
+@pytest.mark.parametrize("size", [(64, 48), (65, 47), (9, 7), (1, 1), (2, 1)])
+@pytest.mark.parametrize("gate", [False, True])
+def test_fusion_matches_oracle(rast, size, gate):
+    w, h = size
+    print(f"fusion {w}x{h} gate={gate}", flush=True)
+    frames = scenes.fusion_frames(2, w, h, seed_offset=w * 1000 + h)
+    fu = Fusion(rast, w, h)
+    for f in frames:
+        for tau in (0.05, -1.0, 10.0):
+            acc = torch.from_numpy(f.accum).cuda() if gate else None
+            cnt = fu.run(_dev(f.planes), w, h, f.s, f.q, f.t, tau, acc, 0.5)
+            torch.cuda.synchronize()
+            ref = fusion.voxelize_fuse(w, h, f.planes, float(np.float32(f.s)), f.q.astype(np.float64),
+                                       f.t.astype(np.float64), float(np.float32(tau)),
+                                       f.accum if gate else None, float(np.float32(0.5)))
+            n = ref["opacity"].size
+            assert int(cnt.item()) == n, (w, h, tau, gate)
+            if n:
+                _check(fu, ref, n)
+
+
+def test_fusion_capacity_and_errors(rast):
+    w, h = 33, 21
+    f = scenes.fusion_frames(1, w, h)[0]
+    planes = _dev(f.planes)
+    ref = fusion.voxelize_fuse(w, h, f.planes, float(np.float32(f.s)), f.q.astype(np.float64),
+                               f.t.astype(np.float64), -1.0)
+    cap = 100
+    out = {k: torch.full((ref[k].reshape(-1, ref["opacity"].size).shape[0], cap + 8), -7.0, device="cuda")
+           for k in PLANES}
+    ws = torch.empty(int(rast.lib.fm_fusion_workspace_size(w, h)), dtype=torch.uint8, device="cuda")
+    count = torch.zeros(1, dtype=torch.int32, device="cuda")
+    pm = native.FmPixelMap(w, h, *(planes[k].data_ptr() for k in PLANES))
+    pose = native.FmSim3(f.s, (ctypes.c_float * 4)(*f.q), (ctypes.c_float * 3)(*f.t))
+    fp = native.FmFusionParams(-1.0, 1.0)
+    # planes of capacity `cap` laid out with stride cap (the extra columns must stay untouched)
+    buf_t = {k: torch.full((out[k].shape[0] * cap + 64,), -7.0, device="cuda") for k in PLANES}
+    buf = native.FmSurfelBuffer(*(buf_t[k].data_ptr() for k in PLANES), cap)
+    rast.check(rast.lib.fm_voxelize_fuse(rast.ctx, ctypes.byref(pm), ctypes.byref(pose), ctypes.byref(fp), None,
+                                         buf, _ptr(count), _ptr(ws), ws.numel(), None))
+    torch.cuda.synchronize()
+    assert int(count.item()) == w * h
+    for k in PLANES:
+        c = out[k].shape[0]
+        got = buf_t[k][:c * cap].reshape(c, cap).cpu().numpy()
+        np.testing.assert_allclose(got, ref[k].reshape(c, -1)[:, :cap], rtol=2e-6, atol=2e-5)
+        assert torch.all(buf_t[k][c * cap:] == -7.0)
+    bad_pose = native.FmSim3(0.0, (ctypes.c_float * 4)(1, 0, 0, 0), (ctypes.c_float * 3)(0, 0, 0))
+    assert rast.lib.fm_voxelize_fuse(rast.ctx, ctypes.byref(pm), ctypes.byref(bad_pose), ctypes.byref(fp), None,
+                                     buf, _ptr(count), _ptr(ws), ws.numel(), None) == native.FM_ERR_INVALID_ARG
+    assert rast.lib.fm_voxelize_fuse(rast.ctx, ctypes.byref(pm), ctypes.byref(pose), ctypes.byref(fp), None,
+                                     buf, _ptr(count), _ptr(ws), 0, None) == native.FM_ERR_WORKSPACE
+    empty = native.FmPixelMap(0, h, *(planes[k].data_ptr() for k in PLANES))
+    assert rast.lib.fm_voxelize_fuse(rast.ctx, ctypes.byref(empty), ctypes.byref(pose), ctypes.byref(fp), None,
+                                     buf, _ptr(count), _ptr(ws), ws.numel(), None) == native.FM_ERR_INVALID_ARG
