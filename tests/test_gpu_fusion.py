@@ -22,6 +22,18 @@ def _dev(planes):
     return {k: torch.from_numpy(np.ascontiguousarray(planes[k])).cuda() for k in PLANES}
 
 
+def _tiny_frame(w, h, seed):
+    rng = np.random.default_rng(seed)
+    P = w * h
+    q = rng.normal(size=(4, P))
+    planes = dict(mean=np.stack([rng.uniform(-1, 1, P), rng.uniform(-1, 1, P), rng.uniform(2, 2.04, P)]),
+                  quat=q / np.linalg.norm(q, axis=0), scale=rng.uniform(0.01, 0.1, (2, P)),
+                  opacity=rng.uniform(0.3, 1, P), color=rng.random((3, P)))
+    planes = {k: np.ascontiguousarray(v, np.float32) for k, v in planes.items()}
+    return scenes.FusionFrame(w, h, planes, 1.05, np.array([0.9, 0.1, -0.3, 0.2], np.float32),
+                              np.array([0.1, 0.2, -0.3], np.float32), rng.random(P).astype(np.float32))
+
+
 def _check(fu, ref, n):
     for k in PLANES:
         want = ref[k].reshape(-1, n)
@@ -35,7 +47,10 @@ def _check(fu, ref, n):
 def test_fusion_matches_oracle(rast, size, gate):
     w, h = size
     print(f"fusion {w}x{h} gate={gate}", flush=True)
-    frames = scenes.fusion_frames(2, w, h, seed_offset=w * 1000 + h)
+    if w >= 3 and h >= 3:
+        frames = scenes.fusion_frames(2, w, h, seed_offset=w * 1000 + h)
+    else:  # too small for the depth-field generator: i.i.d. seeded primitives
+        frames = [_tiny_frame(w, h, seed) for seed in (1, 2)]
     fu = Fusion(rast, w, h)
     for f in frames:
         for tau in (0.05, -1.0, 10.0):
