@@ -338,6 +338,29 @@ class Adam:
                                                    _ptr(self.step_count), _stream(stream)))
 
 
+def error_mask(gs, out, tau_rgb, tau_depth=None):
+    """Pixels with high reconstruction error: mean over channels of
+    |I - I*| above tau_rgb, or (with depth targets) |D - D*| above
+    tau_depth.  Float mask over the batch's pixels."""
+    m = (out["rgb"] - gs.target_rgb).abs().mean(0) > tau_rgb
+    if tau_depth is not None and gs.target_depth is not None:
+        m = m | ((out["depth"] - gs.target_depth).abs() > tau_depth)
+    return m.float()
+
+
+def prune_scores(rast, gs, ws, out, mask):
+    """Error-attributed pruning score of every surfel (map fusion, Sec. 3.3):
+    its total compositing weight sum_px alpha T over the masked pixels of all
+    views.  With the upstream gradient dL/dI = (mask, 0, 0) the adjoint's
+    colour gradient of a surfel is exactly that sum, so the score is read from
+    one fm_backward of the last forward on ws.  Returns one tensor [n] per
+    submap."""
+    g = dict(rgb=torch.stack([mask, torch.zeros_like(mask), torch.zeros_like(mask)]))
+    grads, dvm = gs.zero_grads()
+    rast.backward(gs, ws, out, g, grads, dvm)
+    return [gr["color"][0].clone() for gr in grads]
+
+
 class Fusion:
     """Map fusion of per-pixel maps (fm_voxelize_fuse) with an owned
     workspace and output planes sized for the largest frame."""
