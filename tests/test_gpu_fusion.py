@@ -116,7 +116,8 @@ def test_prune_scores_match_oracle(rast):
     ref_out = oracle.render_scene(sc)
     # pixels the oracle flags (a threshold decision within its margin) are left out on both sides
     m = mask.cpu().numpy().astype(np.float64) * (1.0 - ref_out["flags"])
-    g = dict(rgb=np.stack([m, np.zeros_like(m), np.zeros_like(m)]))
+    z = np.zeros_like(m)
+    g = dict(rgb=np.stack([m, z, z]), depth=z, normal=np.stack([z, z, z]), alpha=z)
     mask_dev = torch.from_numpy(m.astype(np.float32)).cuda()
     scores = prune_scores(rast, gs, ws, out, mask_dev)
     torch.cuda.synchronize()
