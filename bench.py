@@ -147,6 +147,47 @@ def time_refine(rast, scene, params, iters, replays=3):
                 pair_capacity_ok=bool(st == 0))
 
 
+def time_fusion(rast, n_frames=32, w=518, h=392, tau_depth=0.05, tau_accum=0.5, replays=20):
+    """Map fusion of the incoming per-pixel maps of n_frames keyframes
+    (2x2 adaptive voxelization, similarity to world, accumulation gate):
+    all frames fused by one replay of a captured hipGraph."""
+    import torch
+    from paper_2604_03092_amd import scenes
+    from paper_2604_03092_amd.raster import PLANES, Fusion
+    frames = scenes.fusion_frames(n_frames, w, h)
+    dev = [{k: torch.from_numpy(f.planes[k]).cuda() for k in PLANES} for f in frames]
+    acc = [torch.from_numpy(f.accum).cuda() for f in frames]
+    fus = [Fusion(rast, w, h) for _ in frames]
+
+    def run():
+        for f, d, a, fu in zip(frames, dev, acc, fus):
+            fu.run(d, w, h, f.s, f.q, f.t, tau_depth, a, tau_accum)
+
+    run()
+    torch.cuda.synchronize()
+    n_out = sum(int(fu.count.item()) for fu in fus)
+    graph = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        run()
+    torch.cuda.current_stream().wait_stream(s)
+    with torch.cuda.graph(graph):
+        run()
+    graph.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(replays):
+        graph.replay()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / replays
+    npx = n_frames * w * h
+    alg = 56 * npx + 52 * n_out   # 13 floats + accumulation in per pixel, 13 floats out per primitive
+    return dict(frames=n_frames, size=f"{w}x{h}", pixels=npx, primitives_out=n_out,
+                ms_per_batch=round(dt * 1e3, 4), mpixel_s=round(npx / dt / 1e6, 1),
+                hbm=dict(bytes=alg, gbs=round(alg / dt / 1e9, 1), frac=round(alg / dt / 1e9 / HBM_PEAK_GBS, 4)))
+
+
 def time_config(rast, name, steps):
     """Fused forward + L1 + backward of one config's whole batch, eager calls,
     in Mpixel/s (setup and pair-buffer sizing untimed)."""
@@ -201,6 +242,7 @@ def main():
     ap.add_argument("--cpu-views", type=int, default=8, help="views in the CPU-baseline sample")
     ap.add_argument("--refine-iters", type=int, default=20,
                     help="iterations of the captured refine loop (render loss + Adam), 0 to skip")
+    ap.add_argument("--no-fusion", action="store_true", help="skip the map-fusion measurement")
     ap.add_argument("--all-configs", action="store_true",
                     help="also time the fused step on configs 0-4 (reported under per_config)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -368,6 +410,11 @@ def main():
         refine = time_refine(rast, scene, params, args.refine_iters)
         log(f"refine: {refine['ms_per_iteration']:.3f} ms/iteration, {refine['mpixel_s']:.1f} Mpixel/s")
 
+    fusion = None
+    if not args.no_fusion:
+        fusion = time_fusion(rast)
+        log(f"fusion: {fusion['ms_per_batch']:.3f} ms for {fusion['frames']} frames, {fusion['mpixel_s']:.0f} Mpixel/s")
+
     per_config = None
     if args.all_configs:
         per_config = {}
@@ -407,6 +454,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "refine": refine,
+        "fusion": fusion,
     }
     if per_config is not None:
         res["per_config"] = per_config
