@@ -357,6 +357,24 @@ fm_status fm_voxelize_fuse(fm_ctx *ctx, const fm_pixel_map *in, const fm_sim3 *p
                            const fm_fusion_params *params, const float *accum, fm_surfel_buffer out,
                            int32_t *count, void *workspace, size_t ws_bytes, void *stream);
 
+/* ---- loop correction of the map --------------------------------------------
+ *
+ * Primitives stay bound to the keyframe that created them (Sec. 3.3).  After
+ * loop closure moves keyframe k from T_old to T_new, every primitive bound to
+ * it is moved rigidly by Delta T_k = T_new T_old^-1, a similarity (s, q, t):
+ * mu <- s R(q) mu + t, r <- q r (Hamilton product), scales <- s scales.
+ * fm_warp_keyframes applies the moves in place to one surfel set.
+ * mean [3][n], quat [4][n], scale [2][n]: DEVICE planes, updated in place.
+ * keyframe: DEVICE int32 [n], the keyframe of each primitive; primitives
+ * with an index outside [0, n_keyframes) are left alone.  deltas: DEVICE
+ * [n_keyframes] Delta T per keyframe (the identity for keyframes that did
+ * not move; q of any non-zero norm).  Enqueued on stream; no allocation;
+ * graph-capturable.  Errors: FM_ERR_INVALID_ARG for a NULL context, NULL
+ * planes with n > 0, a negative n or n_keyframes, or NULL deltas with
+ * n_keyframes > 0; FM_ERR_HIP if the launch fails. */
+fm_status fm_warp_keyframes(fm_ctx *ctx, float *mean, float *quat, float *scale, const int32_t *keyframe,
+                            int64_t n, const fm_sim3 *deltas, int32_t n_keyframes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

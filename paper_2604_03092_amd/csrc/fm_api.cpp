@@ -736,4 +736,16 @@ fm_status fm_voxelize_fuse(fm_ctx *ctx, const fm_pixel_map *in, const fm_sim3 *p
     return FM_OK;
 }
 
+fm_status fm_warp_keyframes(fm_ctx *ctx, float *mean, float *quat, float *scale, const int32_t *keyframe,
+                            int64_t n, const fm_sim3 *deltas, int32_t n_keyframes, void *stream) {
+    if (!ctx) return FM_ERR_INVALID_ARG;
+    if (n < 0 || n_keyframes < 0 || (n > 0 && (!mean || !quat || !scale || !keyframe)) ||
+        (n_keyframes > 0 && !deltas))
+        return fail(ctx, FM_ERR_INVALID_ARG, "fm_warp_keyframes: NULL buffer or negative size");
+    fm_status s = use_device(ctx);
+    if (s != FM_OK) return s;
+    FM_TRY_HIP(fm::launch_warp(mean, quat, scale, keyframe, n, deltas, n_keyframes, (hipStream_t)stream), "warp");
+    return FM_OK;
+}
+
 }  // extern "C"

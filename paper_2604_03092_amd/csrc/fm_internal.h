@@ -205,6 +205,8 @@ size_t fusion_workspace_bytes(int32_t width, int32_t height);
 hipError_t launch_fusion(const fm_pixel_map &in, const fm_sim3 &pose, const fm_fusion_params &fp,
                          const float *accum, const fm_surfel_buffer &out, int32_t *count, void *ws,
                          hipStream_t st);
+hipError_t launch_warp(float *mean, float *quat, float *scale, const int32_t *kf, int64_t n,
+                       const fm_sim3 *deltas, int32_t K, hipStream_t st);
 hipError_t launch_adam(const fm_adam_tensor *ts, int count, const fm_adam_config &cfg, int32_t *step,
                        hipStream_t st);
 

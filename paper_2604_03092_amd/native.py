@@ -122,6 +122,8 @@ SIGNATURES = {
                               P(FmRasterParams), c_void_p]),
     "fm_adam_step": (c_int32, [c_void_p, P(FmAdamTensor), c_int32, P(FmAdamConfig), c_void_p, c_void_p]),
     "fm_fusion_workspace_size": (ctypes.c_size_t, [c_int32, c_int32]),
+    "fm_warp_keyframes": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int64, c_void_p, c_int32,
+                                    c_void_p]),
     "fm_voxelize_fuse": (c_int32, [c_void_p, P(FmPixelMap), P(FmSim3), P(FmFusionParams), c_void_p,
                                    FmSurfelBuffer, c_void_p, c_void_p, ctypes.c_size_t, c_void_p]),
 }
