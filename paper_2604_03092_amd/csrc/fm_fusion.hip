@@ -11,7 +11,7 @@
 // value is.  Survivors are mapped to world coordinates: mu_w = s R mu + t,
 // r_w = q r, scales times s.
 //
-// Three kernels: per chunk of 1024 blocks the survivor counts (reads depth
+// Three kernels: per chunk of 256 blocks the survivor counts (reads depth
 // and accumulation only), one exclusive scan of the chunk sums, and the
 // write pass (block-wide scan of the recomputed counts, then the merge and
 // the transform).  Output order: blocks in row-major order, a kept block's
