@@ -81,7 +81,11 @@ __device__ __forceinline__ void splat_alpha(const Surf &s, float amin, float ama
     h.G = __builtin_amdgcn_exp2f(h.r2 * -0.72134752044448170368f);  // exp(-r2/2)
     h.at = s.sig * h.G;
     h.hit = h.in && (h.at >= amin);
-    h.alpha = h.hit ? __builtin_fminf(h.at, amax) : 0.f;
+    // min(alpha_max, sigma G) on the bit patterns: both are >= 0, where the
+    // IEEE order is the unsigned-integer order (and no canonicalisation is
+    // needed; a NaN sigma G of a missing lane gives alpha_max, then 0)
+    const uint32_t ub = __float_as_uint(h.at), um = __float_as_uint(amax);
+    h.alpha = h.hit ? __uint_as_float(ub < um ? ub : um) : 0.f;
 }
 
 template <int TW, int TH> struct Geo {
@@ -175,7 +179,7 @@ __device__ __forceinline__ void tile_forward(const TileCtx &c, const Slots<TW, T
 #pragma clang fp contract(off)
     using Gm = Geo<TW, TH>;
     const float rho2 = kp.rho_max * kp.rho_max;
-    const float amax = __builtin_canonicalizef(kp.alpha_max);
+    const float amax = kp.alpha_max;
     const float nan = __builtin_nanf("");
     float px[Gm::NB];
     uint32_t live = 0;
@@ -205,8 +209,8 @@ __device__ __forceinline__ void tile_forward(const TileCtx &c, const Slots<TW, T
                     slast[q] = base - c.start + (uint32_t)j + 1u;
                     splat_alpha<false>(s, kp.alpha_min, amax, h);
                     const float test = T[q] * (1.f - h.alpha);
-                    const bool stop = h.hit && test < kp.t_min;
-                    const bool con = h.hit && !stop;
+                    const bool con = h.hit && test >= kp.t_min;  // test is finite
+                    const bool stop = h.hit != con;
                     const float wgt = (con ? h.alpha : 0.f) * T[q];
                     acc[q][0] = fmaf(s.r, wgt, acc[q][0]);
                     acc[q][1] = fmaf(s.g, wgt, acc[q][1]);
@@ -295,7 +299,7 @@ __device__ __forceinline__ void tile_backward(const TileCtx &c, const Slots<TW, 
                                               const uint32_t (&bound)[Geo<TW, TH>::NB], float *__restrict__ grad) {
     using Gm = Geo<TW, TH>;
     const float rho2 = kp.rho_max * kp.rho_max;
-    const float amax = __builtin_canonicalizef(kp.alpha_max);
+    const float amax = kp.alpha_max;
     float T[Gm::NB], Sk[Gm::NB];
     uint32_t smax[Gm::NB];
     uint32_t maxlast = 0;
@@ -334,7 +338,8 @@ __device__ __forceinline__ void tile_backward(const TileCtx &c, const Slots<TW, 
                 splat_geom(s, sl.px[q], sl.py[q], rho2, T[q] > Tf[q], h);
                 if (ballot64(h.in) == 0) continue;
                 splat_alpha<true>(s, kp.alpha_min, amax, h);
-                if (ballot64(h.hit) == 0) continue;
+                // no early-out when no lane is hit (rare once a lane is inside):
+                // a missing lane's terms are exact zeros
                 if (first)
                     adjoint_terms<true, HAS_N>(h, s, g[q], S[q], Sk[q], T[q], amax, gr, gn2);
                 else
