@@ -226,7 +226,7 @@ fm_status build(fm_ctx *ctx, const fm_batch *b, const fm_raster_params *prm, int
     p.o_ncount = take(4 * (size_t)NPX);
     p.o_grad = take(4 * fm::kGradStride * (size_t)E);
     p.o_ell = take(sizeof(fm::Ell) * (size_t)E);
-    p.o_pose = take(48 * (size_t)p.V * p.a7_max_blocks);
+    p.o_pose = take(4 * 48 * (size_t)p.V * p.a7_max_blocks);  // 12 floats per (view, wave)
     p.o_loss = take(4 * (size_t)T * 16);
     p.o_tot = take(4 * (size_t)fm::kRadix * fm::kMaxPasses);
     p.o_chunk = take(4 * (size_t)((max_pairs + fm::kEmitChunk - 1) / fm::kEmitChunk + 1));

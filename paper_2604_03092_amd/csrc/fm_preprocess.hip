@@ -259,7 +259,6 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
     const ViewDesc *__restrict__ views, const float *__restrict__ intr,
     const float *__restrict__ viewmat, const Rec *__restrict__ rec, const uint32_t *__restrict__ cnt,
     const float4 *__restrict__ grad, float *__restrict__ pose_part, int max_blocks) {
-    __shared__ float red[4][16];
     const int s_idx = submap_of_block(subs, S, blockIdx.x);
     const SubmapDesc &sd = subs[s_idx];
     const int lb = blockIdx.x - sd.block_base;
@@ -380,17 +379,11 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
             dsig += g[9];
             dc[0] += g[10]; dc[1] += g[11]; dc[2] += g[12];
         }
-        // block reduction of the 12 pose-gradient values of view v
+        // wave reduction of the 12 pose-gradient values of view v into this
+        // wave's partial (no block barrier: the waves run the views at their own pace)
         const float r = wave_reduce16(dV);
         const int comp = wave_reduce16_component();
-        if (comp >= 0) red[wave][comp] = r;
-        __syncthreads();
-        if (threadIdx.x < 12) {
-            const float s = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] +
-                            red[3][threadIdx.x];
-            pose_part[((int64_t)v * max_blocks + lb) * 12 + threadIdx.x] = s;
-        }
-        __syncthreads();
+        if (comp >= 0 && comp < 12) pose_part[(((int64_t)v * max_blocks + lb) * 4 + wave) * 12 + comp] = r;
     }
     if (!live) return;
     // dL/d(unit quaternion) from dL/dR_s, then project onto the raw quaternion
@@ -430,31 +423,33 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
 }
 
 // dL_dviewmat[v] += sum over the blocks of v's submap of the pose partials.
-__global__ __launch_bounds__(256) void k_pose_reduce(const ViewDesc *__restrict__ views,
-                                                      const SubmapDesc *__restrict__ subs,
-                                                      const float *__restrict__ pose_part, int max_blocks,
-                                                      float *__restrict__ dL_dviewmat) {
-    __shared__ float red[256][13];
+__global__ __launch_bounds__(1024) void k_pose_reduce(const ViewDesc *__restrict__ views,
+                                                       const SubmapDesc *__restrict__ subs,
+                                                       const float *__restrict__ pose_part, int max_blocks,
+                                                       float *__restrict__ dL_dviewmat) {
+    __shared__ float red[16][16];
     const int v = blockIdx.x;
     const SubmapDesc &sd = subs[views[v].submap];
-    const int nb = (sd.n + 255) / 256;
-    float acc[12];
+    const int nw = 4 * ((sd.n + 255) / 256);  // one partial per wave of the submap's blocks
+    float acc[16];
 #pragma unroll
-    for (int k = 0; k < 12; ++k) acc[k] = 0.f;
-    for (int b = threadIdx.x; b < nb; b += 256) {
-        const float *p = pose_part + ((int64_t)v * max_blocks + b) * 12;
-#pragma unroll
-        for (int k = 0; k < 12; ++k) acc[k] += p[k];
+    for (int k = 0; k < 16; ++k) acc[k] = 0.f;
+    const float4 *base = reinterpret_cast<const float4 *>(pose_part + (int64_t)v * max_blocks * 4 * 12);
+    for (int b = threadIdx.x; b < nw; b += 1024) {
+        const float4 x = base[3 * b], y = base[3 * b + 1], z = base[3 * b + 2];
+        acc[0] += x.x; acc[1] += x.y; acc[2] += x.z; acc[3] += x.w;
+        acc[4] += y.x; acc[5] += y.y; acc[6] += y.z; acc[7] += y.w;
+        acc[8] += z.x; acc[9] += z.y; acc[10] += z.z; acc[11] += z.w;
     }
-#pragma unroll
-    for (int k = 0; k < 12; ++k) red[threadIdx.x][k] = acc[k];
+    const float r = wave_reduce16(acc);
+    const int comp = wave_reduce16_component();
+    if (comp >= 0) red[threadIdx.x >> 6][comp] = r;
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (threadIdx.x < s)
-            for (int k = 0; k < 12; ++k) red[threadIdx.x][k] += red[threadIdx.x + s][k];
-        __syncthreads();
+    if (threadIdx.x < 12) {
+        float t = 0.f;
+        for (int w = 0; w < 16; ++w) t += red[w][threadIdx.x];
+        dL_dviewmat[12 * v + threadIdx.x] += t;
     }
-    if (threadIdx.x < 12) dL_dviewmat[12 * v + threadIdx.x] += red[0][threadIdx.x];
 }
 
 }  // namespace
@@ -514,7 +509,7 @@ hipError_t launch_preprocess_bwd(const Plan &p, void *ws, const float *intr, con
                            p.a7_max_blocks);
     }
     if (dL_dviewmat) {
-        hipLaunchKernelGGL(k_pose_reduce, dim3(p.V), dim3(256), 0, st, at<ViewDesc>(ws, p.o_views),
+        hipLaunchKernelGGL(k_pose_reduce, dim3(p.V), dim3(1024), 0, st, at<ViewDesc>(ws, p.o_views),
                            at<SubmapDesc>(ws, p.o_subs), at<float>(ws, p.o_pose), p.a7_max_blocks,
                            dL_dviewmat);
     }
