@@ -123,8 +123,10 @@ typedef struct {
     float rho_max;     /* 3: support radius in units of the tangent scales        */
     float near_plane;  /* 0.2: cull surfels with centre depth <= near_plane       */
     float bg[3];       /* background colour added with weight T_final             */
-    int32_t tile_w;    /* tile shape in pixels: 8x8, 16x8, 16x16 or 32x8; 0x0 uses  */
-    int32_t tile_h;    /* the context's autotuned choice for the batch, else 16x16 */
+    int32_t tile_w;    /* tile shape in pixels: 8x8, 16x8, 16x16, 32x8 or 32x32    */
+    int32_t tile_h;    /* (rendered as four 16x16 quadrants sharing one list);
+                          0x0 uses the context's autotuned choice for the batch,
+                          else 16x16                                            */
     int32_t reserved[2];
 } fm_raster_params;
 

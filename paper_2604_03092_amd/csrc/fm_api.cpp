@@ -86,7 +86,7 @@ fm_status resolve_tile(fm_ctx *ctx, const fm_batch *b, const fm_raster_params *p
     }
     if (!fm::tile_shape_supported(tw, th))
         return fail(ctx, FM_ERR_UNSUPPORTED, "unsupported tile shape " + std::to_string(tw) + "x" +
-                                                 std::to_string(th) + " (use 8x8, 16x8, 16x16 or 32x8)");
+                                                 std::to_string(th) + " (use 8x8, 16x8, 16x16, 32x8 or 32x32)");
     return FM_OK;
 }
 
@@ -631,7 +631,7 @@ fm_status fm_autotune(fm_ctx *ctx, const fm_batch *b, const fm_raster_params *pr
         chosen->tile_h = hit->second.second;
         return FM_OK;
     }
-    const int shapes[4][2] = {{16, 16}, {8, 8}, {16, 8}, {32, 8}};
+    const int shapes[5][2] = {{16, 16}, {8, 8}, {16, 8}, {32, 8}, {32, 32}};
     hipStream_t st = (hipStream_t)stream;
     fm_status s = use_device(ctx);
     if (s != FM_OK) return s;

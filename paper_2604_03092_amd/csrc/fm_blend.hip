@@ -88,9 +88,17 @@ __device__ __forceinline__ void splat_alpha(const Surf &s, float amin, float ama
     h.alpha = h.hit ? __uint_as_float(ub < um ? ub : um) : 0.f;
 }
 
+// One wave renders a wave tile of WTW x WTH pixels as NB slots of 8x8
+// blocks.  A 32x32 tile is split into four 16x16 quadrants, one wave each,
+// that traverse the same tile list; its pair masks mark quadrants.
 template <int TW, int TH> struct Geo {
-    static constexpr int BW = TW / 8;
-    static constexpr int BH = TH / 8;
+    static constexpr bool QUAD = TW == 32 && TH == 32;
+    static constexpr int WTW = QUAD ? 16 : TW;
+    static constexpr int WTH = QUAD ? 16 : TH;
+    static constexpr int QX = TW / WTW;
+    static constexpr int NQ = QX * (TH / WTH);  // waves per tile
+    static constexpr int BW = WTW / 8;
+    static constexpr int BH = WTH / 8;
     static constexpr int NB = BW * BH;  // pixel slots per lane
 };
 
@@ -99,6 +107,7 @@ struct TileCtx {
     int64_t pix_base;      // first pixel of the view in the output planes
     uint32_t start, end;   // the tile's range in the sorted pair list
     uint32_t n_entries;
+    int quad;  // the wave's quadrant of a 32x32 tile (0 otherwise)
 };
 
 template <int TW, int TH> struct Slots {
@@ -112,7 +121,11 @@ __device__ __forceinline__ TileCtx tile_ctx(const ViewDesc *views, int V, const 
                                             const uint32_t *te, Slots<TW, TH> &sl) {
     using Gm = Geo<TW, TH>;
     TileCtx c;
-    const int tile = (int)xcd_chunked<16>(blockIdx.x, gridDim.x);  // runs of 16 tiles share an L2
+    // runs of 16 consecutive blocks share an L2 (the quadrants of a tile
+    // are consecutive blocks)
+    const int lb = (int)xcd_chunked<16>(blockIdx.x, gridDim.x);
+    const int tile = lb / Gm::NQ;
+    c.quad = lb - tile * Gm::NQ;
     c.view = view_of_tile(views, V, tile);
     const ViewDesc &vd = views[c.view];
     const int local = tile - vd.tile_base;
@@ -126,8 +139,8 @@ __device__ __forceinline__ TileCtx tile_ctx(const ViewDesc *views, int V, const 
     const int lane = threadIdx.x;
 #pragma unroll
     for (int q = 0; q < Gm::NB; ++q) {
-        const int col = tx * TW + 8 * (q % Gm::BW) + (lane & 7);
-        const int row = ty * TH + 8 * (q / Gm::BW) + (lane >> 3);
+        const int col = tx * TW + (c.quad % Gm::QX) * Gm::WTW + 8 * (q % Gm::BW) + (lane & 7);
+        const int row = ty * TH + (c.quad / Gm::QX) * Gm::WTH + 8 * (q / Gm::BW) + (lane >> 3);
         sl.inside[q] = col < c.W && row < c.H;
         sl.pix[q] = c.pix_base + (int64_t)row * c.W + col;
         sl.px[q] = (float)col + 0.5f;
@@ -137,15 +150,18 @@ __device__ __forceinline__ TileCtx tile_ctx(const ViewDesc *views, int V, const 
 }
 
 // Stage up to 64 pairs of the tile list into LDS (one per lane).  Entries out
-// of range (impossible for emitted pairs) get an empty block mask.
+// of range (impossible for emitted pairs) get an empty block mask.  In a
+// quadrant wave (QUAD) the pair's quadrant bit becomes a mask of all slots.
+template <bool QUAD>
 __device__ __forceinline__ int stage(const TileCtx &c, uint32_t base, uint32_t end,
                                      const uint32_t *__restrict__ pval, const Rec *__restrict__ rec,
                                      Rec *srec, uint32_t *sval) {
     const int cntb = (int)min(64u, end - base);
     __syncthreads();
     if ((int)threadIdx.x < cntb) {
-        const uint32_t pv = pval[base + threadIdx.x];
+        uint32_t pv = pval[base + threadIdx.x];
         const bool ok = (pv & kEntryMask) < c.n_entries;
+        if (QUAD) pv = (pv & kEntryMask) | (((pv >> (kMaskShift + c.quad)) & 1u) ? (0xFu << kMaskShift) : 0u);
         sval[threadIdx.x] = ok ? pv : 0u;
         if (ok) srec[threadIdx.x] = rec[pv & kEntryMask];
     }
@@ -194,7 +210,7 @@ __device__ __forceinline__ void tile_forward(const TileCtx &c, const Slots<TW, T
         if (ballot64(sl.inside[q]) != 0) live |= 1u << q;
     }
     for (uint32_t base = c.start; base < c.end && live != 0; base += 64) {
-        const int cntb = stage(c, base, c.end, pval, rec, srec, sval);
+        const int cntb = stage<Gm::QUAD>(c, base, c.end, pval, rec, srec, sval);
         for (int j = 0; j < cntb; ++j) {
             const uint32_t m = (__builtin_amdgcn_readfirstlane(sval[j]) >> kMaskShift) & live;
             if (m != 0) {
@@ -314,7 +330,7 @@ __device__ __forceinline__ void tile_backward(const TileCtx &c, const Slots<TW, 
     const uint32_t end = c.start + (maxlast < len ? maxlast : len);
     const int comp = wave_reduce16_component();
     for (uint32_t base = c.start; base < end; base += 64) {
-        const int cntb = stage(c, base, end, pval, rec, srec, sval);
+        const int cntb = stage<Gm::QUAD>(c, base, end, pval, rec, srec, sval);
         const uint32_t kbase = base - c.start;
         for (int j = 0; j < cntb; ++j) {
             const uint32_t k = kbase + (uint32_t)j;
@@ -516,7 +532,7 @@ __global__ __launch_bounds__(1024) void k_loss_reduce(const float *__restrict__ 
 template <int TW, int TH>
 hipError_t fwd_t(const Plan &p, void *ws, const KParams &kp, const fm_outputs &out, hipStream_t st) {
     const uint32_t *pval = at<uint32_t>(ws, p.pairs_in_alt ? p.o_pval2 : p.o_pval);
-    hipLaunchKernelGGL((k_render_fwd<TW, TH>), dim3((unsigned)p.T), dim3(64), 0, st,
+    hipLaunchKernelGGL((k_render_fwd<TW, TH>), dim3((unsigned)(p.T * Geo<TW, TH>::NQ)), dim3(64), 0, st,
                        at<ViewDesc>(ws, p.o_views), p.V, at<uint32_t>(ws, p.o_tstart),
                        at<uint32_t>(ws, p.o_tend), pval, at<Rec>(ws, p.o_rec), kp, p.NPX, out,
                        at<float>(ws, p.o_tfinal), at<uint32_t>(ws, p.o_nlast), at<uint32_t>(ws, p.o_ncount));
@@ -528,12 +544,12 @@ hipError_t bwd_t(const Plan &p, void *ws, const KParams &kp, const fm_outputs &o
                  hipStream_t st) {
     const uint32_t *pval = at<uint32_t>(ws, p.pairs_in_alt ? p.o_pval2 : p.o_pval);
     if (g.normal)
-        hipLaunchKernelGGL((k_render_bwd<TW, TH, true>), dim3((unsigned)p.T), dim3(64), 0, st,
+        hipLaunchKernelGGL((k_render_bwd<TW, TH, true>), dim3((unsigned)(p.T * Geo<TW, TH>::NQ)), dim3(64), 0, st,
                            at<ViewDesc>(ws, p.o_views), p.V, at<uint32_t>(ws, p.o_tstart),
                            at<uint32_t>(ws, p.o_tend), pval, at<Rec>(ws, p.o_rec), kp, p.NPX, out, g,
                            at<float>(ws, p.o_tfinal), at<uint32_t>(ws, p.o_nlast), at<float>(ws, p.o_grad));
     else
-        hipLaunchKernelGGL((k_render_bwd<TW, TH, false>), dim3((unsigned)p.T), dim3(64), 0, st,
+        hipLaunchKernelGGL((k_render_bwd<TW, TH, false>), dim3((unsigned)(p.T * Geo<TW, TH>::NQ)), dim3(64), 0, st,
                            at<ViewDesc>(ws, p.o_views), p.V, at<uint32_t>(ws, p.o_tstart),
                            at<uint32_t>(ws, p.o_tend), pval, at<Rec>(ws, p.o_rec), kp, p.NPX, out, g,
                            at<float>(ws, p.o_tfinal), at<uint32_t>(ws, p.o_nlast), at<float>(ws, p.o_grad));
@@ -544,7 +560,7 @@ template <int TW, int TH>
 hipError_t fused_t(const Plan &p, void *ws, const KParams &kp, const LossArgs &la, const fm_outputs &out,
                    hipStream_t st) {
     const uint32_t *pval = at<uint32_t>(ws, p.pairs_in_alt ? p.o_pval2 : p.o_pval);
-    hipLaunchKernelGGL((k_render_fused<TW, TH>), dim3((unsigned)p.T), dim3(64), 0, st,
+    hipLaunchKernelGGL((k_render_fused<TW, TH>), dim3((unsigned)(p.T * Geo<TW, TH>::NQ)), dim3(64), 0, st,
                        at<ViewDesc>(ws, p.o_views), p.V, at<uint32_t>(ws, p.o_tstart),
                        at<uint32_t>(ws, p.o_tend), pval, at<Rec>(ws, p.o_rec), kp, p.NPX, out, la,
                        at<float>(ws, p.o_tfinal), at<uint32_t>(ws, p.o_nlast), at<uint32_t>(ws, p.o_ncount),
@@ -556,7 +572,7 @@ hipError_t fused_t(const Plan &p, void *ws, const KParams &kp, const LossArgs &l
 
 bool tile_shape_supported(int tw, int th) {
     return (tw == 8 && th == 8) || (tw == 16 && th == 8) || (tw == 16 && th == 16) ||
-           (tw == 32 && th == 8);
+           (tw == 32 && th == 8) || (tw == 32 && th == 32);
 }
 
 #define FM_DISPATCH(FN, ...)                                                     \
@@ -565,6 +581,7 @@ bool tile_shape_supported(int tw, int th) {
         if (p.tile_w == 8 && p.tile_h == 8) return FN<8, 8>(__VA_ARGS__);        \
         if (p.tile_w == 16 && p.tile_h == 8) return FN<16, 8>(__VA_ARGS__);      \
         if (p.tile_w == 32 && p.tile_h == 8) return FN<32, 8>(__VA_ARGS__);      \
+        if (p.tile_w == 32 && p.tile_h == 32) return FN<32, 32>(__VA_ARGS__);    \
         return hipErrorInvalidValue;                                             \
     } while (0)
 
@@ -587,7 +604,9 @@ hipError_t launch_render_fused(const Plan &p, void *ws, const KParams &kp, const
 
 hipError_t launch_loss_reduce(const Plan &p, void *ws, float *loss, hipStream_t st) {
     if (p.T == 0 || !loss) return hipSuccess;
-    hipLaunchKernelGGL(k_loss_reduce, dim3(1), dim3(1024), 0, st, at<float>(ws, p.o_loss), p.T, loss);
+    // one partial per block: 32x32 tiles run four blocks each
+    const int64_t nb = p.T * ((p.tile_w == 32 && p.tile_h == 32) ? 4 : 1);
+    hipLaunchKernelGGL(k_loss_reduce, dim3(1), dim3(1024), 0, st, at<float>(ws, p.o_loss), nb, loss);
     return hipGetLastError();
 }
 

@@ -93,7 +93,8 @@ struct alignas(16) Ell {
 static_assert(sizeof(Ell) == 48, "ellipse layout");
 
 // Pair values: entry id in the low 28 bits, 8x8-block mask of the tile in the
-// high 4 bits (bit b set when block b of the tile may hold a covered pixel).
+// high 4 bits (bit b set when block b of the tile may hold a covered pixel);
+// for 32x32 tiles the bits mark 16x16 quadrants.
 constexpr uint32_t kEntryMask = 0x0FFFFFFFu;
 constexpr int kMaskShift = 28;
 

@@ -289,7 +289,8 @@ __global__ __launch_bounds__(1024) void k_count_scan(const uint32_t *__restrict_
     }
 }
 
-// Which 8x8 pixel blocks of the tile with origin (x0, y0) may hold a pixel
+// Which 8x8 pixel blocks (16x16 quadrants of a 32x32 tile) of the tile with
+// origin (x0, y0) may hold a pixel
 // centre inside the entry's culling ellipse.  Per block row, the x-extent of
 // the ellipse over that row band is the hull of the slices at the clamped
 // band edges and of the leftmost/rightmost points when they fall inside the
@@ -297,11 +298,13 @@ __global__ __launch_bounds__(1024) void k_count_scan(const uint32_t *__restrict_
 // (hardware square root and reciprocal, 1 ulp).
 __device__ inline uint32_t block_mask(const Ell &el, int x0, int y0, int tw, int th) {
     const float hy2 = el.hy * el.hy;
-    const int bw = tw >> 3, bh = th >> 3;
+    const int bs = (tw == 32 && th == 32) ? 16 : 8;
+    const int bw = tw / bs, bh = th / bs;
+    const float span = (float)bs - 0.5f;
     uint32_t mask = 0;
     for (int br = 0; br < bh; ++br) {
-        float dy0 = (float)(y0 + 8 * br) + 0.5f - el.ey - 0.01f;
-        float dy1 = (float)(y0 + 8 * br) + 7.5f - el.ey + 0.01f;
+        float dy0 = (float)(y0 + bs * br) + 0.5f - el.ey - 0.01f;
+        float dy1 = (float)(y0 + bs * br) + span - el.ey + 0.01f;
         dy0 = fmaxf(dy0, -el.hy);
         dy1 = fminf(dy1, el.hy);
         if (!(dy0 <= dy1)) continue;
@@ -314,7 +317,7 @@ __device__ inline uint32_t block_mask(const Ell &el, int x0, int y0, int tw, int
         xmax += el.ex + 0.01f;
         xmin += el.ex - 0.01f;
         for (int bc = 0; bc < bw; ++bc) {
-            const float bx0 = (float)(x0 + 8 * bc) + 0.5f, bx1 = bx0 + 7.0f;
+            const float bx0 = (float)(x0 + bs * bc) + 0.5f, bx1 = (float)(x0 + bs * bc) + span;
             if (xmax >= bx0 && xmin <= bx1) mask |= 1u << (br * bw + bc);
         }
     }

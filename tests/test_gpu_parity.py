@@ -34,7 +34,7 @@ def _gpu_pairs_by_view(rast, gs, ws, sc, tile):
 
 
 # ------------------------------------------------------------------ forward
-@pytest.mark.parametrize("tile", [(16, 16), (8, 8), (16, 8), (32, 8)])
+@pytest.mark.parametrize("tile", [(16, 16), (8, 8), (16, 8), (32, 8), (32, 32)])
 def test_config0_forward_and_pairs(rast, tile):
     sc = scenes.config0()
     _say(f"config0 forward tile={tile}")
@@ -60,7 +60,7 @@ def test_tile_shape_does_not_change_images(rast):
     sc = scenes.random_scene(5, 20000, 200, 136, scale_lo=0.02, scale_hi=0.15)
     gs = GpuScene.from_scene(sc)
     ref = None
-    for tile in [(16, 16), (8, 8), (16, 8), (32, 8)]:
+    for tile in [(16, 16), (8, 8), (16, 8), (32, 8), (32, 32)]:
         _say(f"tile invariance {tile}")
         out, _ = rast.forward(gs, rast.params(tile=tile))
         got = {k: v.cpu().numpy() for k, v in out.items()}

@@ -147,7 +147,7 @@ def test_autotune_and_cache(rast, tmp_path):
     path = str(tmp_path / "tune.json")
     _say("autotune")
     chosen = rast.autotune(gs, ws, out, grads, dvm, loss, cache_path=path)
-    assert (chosen.tile_w, chosen.tile_h) in [(16, 16), (8, 8), (16, 8), (32, 8)]
+    assert (chosen.tile_w, chosen.tile_h) in [(16, 16), (8, 8), (16, 8), (32, 8), (32, 32)]
     data = json.load(open(path))
     assert list(data.values())[0] == [chosen.tile_w, chosen.tile_h]
     # a fresh context reads the cache; tile 0x0 then means "the tuned shape"

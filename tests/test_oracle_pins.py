@@ -448,7 +448,7 @@ def test_binning_order_and_ranges(orc):
     depth, index); tile ranges partition the list."""
     sc = scenes.config0()
     sm = sc.submaps[0]
-    for tw, th in ((16, 16), (8, 8), (32, 8)):
+    for tw, th in ((16, 16), (8, 8), (32, 8), (32, 32)):
         b = orc.bin_view(sm, 64, 48, sc.intr[0], sc.viewmat[0], tile_w=tw, tile_h=th)
         tx, ty = b["tiles"]
         tiles, kap, idx = [], [], []
