@@ -28,10 +28,18 @@ constexpr uint32_t kNoKey = 0xFFFFFFFFu;
 // Items of the logical block handled by this workgroup: a fixed tile of
 // kSortTile consecutive items.  Each XCD gets a contiguous run of tiles, so
 // the neighbouring output runs of one digit stay in one L2, which merges
-// their partial cache-line writes before they reach HBM.
-__device__ __forceinline__ uint32_t logical_block(int G) { return xcd_contiguous(blockIdx.x, (uint32_t)G); }
+// their partial cache-line writes before they reach HBM.  The grid is sized
+// for the capacity; only the first ga = ceil(n / kSortTile) workgroups hold
+// items, and they are the ones spread over the XCDs (workgroups go to XCDs
+// round-robin), so a pass over fewer items than the capacity still uses the
+// whole chip.  The rest map to themselves and see empty tiles.
+__device__ __forceinline__ uint32_t logical_block(uint32_t n, int G) {
+    uint32_t ga = (uint32_t)(((uint64_t)n + kSortTile - 1) / kSortTile);
+    if (ga > (uint32_t)G) ga = (uint32_t)G;
+    return blockIdx.x < ga ? xcd_contiguous(blockIdx.x, ga) : blockIdx.x;
+}
 __device__ __forceinline__ void tile_of(uint32_t n, int G, uint32_t &lo, uint32_t &hi) {
-    const uint64_t l = (uint64_t)logical_block(G) * kSortTile;
+    const uint64_t l = (uint64_t)logical_block(n, G) * kSortTile;
     lo = l < n ? (uint32_t)l : n;
     hi = l + kSortTile < n ? (uint32_t)(l + kSortTile) : n;
 }
@@ -49,8 +57,9 @@ __global__ __launch_bounds__(256) void k_radix_hist(const uint32_t *__restrict__
     const int w = threadIdx.x >> 6, lane = lane_id();
 #pragma unroll
     for (int k = 0; k < 4; ++k) h[k][threadIdx.x] = 0;
+    const uint32_t n = count_of(n_dev, n_host);
     uint32_t lo, hi;
-    tile_of(count_of(n_dev, n_host), G, lo, hi);
+    tile_of(n, G, lo, hi);
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const uint32_t wbase = lo + (uint32_t)w * (kSortTile / 4);
     uint32_t key[IPT];
@@ -76,7 +85,7 @@ __global__ __launch_bounds__(256) void k_radix_hist(const uint32_t *__restrict__
         if (ok && (m & lt) == 0) atomicAdd(&h[w][d], (uint32_t)__popcll(m));
     }
     __syncthreads();
-    hist[threadIdx.x * G + logical_block(G)] = h[0][threadIdx.x] + h[1][threadIdx.x] + h[2][threadIdx.x] +
+    hist[threadIdx.x * G + logical_block(n, G)] = h[0][threadIdx.x] + h[1][threadIdx.x] + h[2][threadIdx.x] +
                                                h[3][threadIdx.x];
 }
 
@@ -158,7 +167,7 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t *__restric
     if (lo >= hi) return;  // uniform over the block
 #pragma unroll
     for (int k = 0; k < 4; ++k) s_wcnt[k][threadIdx.x] = 0u;
-    s_glob[threadIdx.x] = hist[threadIdx.x * G + logical_block(G)];
+    s_glob[threadIdx.x] = hist[threadIdx.x * G + logical_block(n, G)];
     uint32_t key[IPT], val[IPT];
     const uint32_t wbase = lo + (uint32_t)w * PER_WAVE;
 #pragma unroll
