@@ -215,7 +215,10 @@ fm_status fm_query_status(fm_ctx *ctx, const fm_batch *batch, const fm_raster_pa
  * buffers (cap entries each): tile[k] = global tile id (views' tiles back to
  * back, row-major within a view), entry[k] = view-local surfel index, view[k]
  * = view index, and the per-tile ranges tile_start/tile_end (host arrays
- * sized to the batch's total tile count).  Synchronous. */
+ * sized to the batch's total tile count).  *n_pairs is the length of the
+ * list: the pairs of each surfel's tile rect (the count fm_query_status
+ * reports) less those of tiles that its opacity-cut support ellipse,
+ * conservatively enlarged, does not reach.  Synchronous. */
 fm_status fm_debug_pairs(fm_ctx *ctx, const fm_batch *batch, const fm_raster_params *params,
                          const void *workspace, int64_t max_pairs, uint32_t *tile,
                          uint32_t *surfel, uint32_t *view, int64_t cap, int64_t *n_pairs,

@@ -589,8 +589,8 @@ fm_status fm_debug_pairs(fm_ctx *ctx, const fm_batch *b, const fm_raster_params 
     fm::Status st;
     const char *w = static_cast<const char *>(ws);
     FM_TRY_HIP(hipMemcpy(&st, w + p.o_status, sizeof(st), hipMemcpyDeviceToHost), "hipMemcpy(status)");
-    *n_pairs = st.n_pairs;
-    const int64_t m = std::min<int64_t>(st.n_pairs, cap);
+    *n_pairs = st.n_kept;
+    const int64_t m = std::min<int64_t>(st.n_kept, cap);
     if (m > 0 && (tile || surfel || view)) {
         std::vector<uint32_t> k(m), e(m);
         FM_TRY_HIP(hipMemcpy(k.data(), w + (p.pairs_in_alt ? p.o_pkey2 : p.o_pkey), 4 * m, hipMemcpyDeviceToHost),

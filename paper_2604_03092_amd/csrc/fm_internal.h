@@ -107,7 +107,8 @@ struct Status {
     uint32_t overflow;   // 1 when required > capacity
     uint64_t required;   // pairs the batch needs
     uint32_t n_vis;      // entries that cover at least one tile
-    uint32_t pad[3];
+    uint32_t n_kept;     // pairs in the tile-sorted list (those of tiles the support reaches)
+    uint32_t pad[2];
 };
 
 struct KParams {

@@ -460,7 +460,9 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t *__restrict__ sorte
             const uint32_t rx = r - ry * ntx;
             const int tx = (int)(el.t0 & 0xFFFFu) + (int)rx, ty = (int)(el.t0 >> 16) + (int)ry;
             const uint32_t mask = block_mask(el, tx * kp.tile_w, ty * kp.tile_h, kp.tile_w, kp.tile_h);
-            pkey[p0 + q] = el.tb + ry * tiles_x + rx;
+            // a tile of the rect that no block of reaches carries no pair: its
+            // key drops it in the first tile-sort pass
+            pkey[p0 + q] = mask ? el.tb + ry * tiles_x + rx : kNoKey;
             pval[p0 + q] = ent | (mask << kMaskShift);
         }
     }
@@ -473,7 +475,7 @@ __global__ __launch_bounds__(256) void k_fill_u32(uint32_t *__restrict__ p, uint
 __global__ __launch_bounds__(256) void k_tile_ranges(const uint32_t *__restrict__ pkey, const Status *st,
                                                       uint32_t *__restrict__ ts, uint32_t *__restrict__ te,
                                                       uint32_t n_tiles) {
-    const uint32_t n = st->n_pairs;
+    const uint32_t n = st->n_kept;
     for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
         const uint32_t t = pkey[i];
         if (t >= n_tiles) continue;  // cannot happen for emitted ids; guards the stores
@@ -533,9 +535,10 @@ hipError_t launch_binning(const Plan &p, void *ws, const KParams &kp, hipStream_
                        at<Ell>(ws, p.o_ell), kp, pkey, pval);
     // 3. stable sort of the pairs by tile id
     uint32_t *ka = pkey, *va = pval, *kb = pkey2, *vb = pval2;
+    // (the first pass drops the pairs of missed tiles and counts the rest)
     for (int pass = 0; pass < p.pair_passes; ++pass) {
-        radix_pass(ka, va, kb, vb, &status->n_pairs, 0, 8 * pass, hist, p.sortG_p, tot + (4 + pass) * kRadix, 0,
-                   nullptr, st);
+        radix_pass(ka, va, kb, vb, pass == 0 ? &status->n_pairs : &status->n_kept, 0, 8 * pass, hist, p.sortG_p,
+                   tot + (4 + pass) * kRadix, pass == 0 ? 1 : 0, pass == 0 ? &status->n_kept : nullptr, st);
         uint32_t *t = ka; ka = kb; kb = t;
         t = va; va = vb; vb = t;
     }
