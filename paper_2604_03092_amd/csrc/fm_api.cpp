@@ -168,8 +168,7 @@ fm_status build(fm_ctx *ctx, const fm_batch *b, const fm_raster_params *prm, int
     p.sortG_e = grid_for(E);
     p.sortG_p = grid_for(max_pairs);
     p.scan_blocks = (int)std::max<int64_t>(1, (E + fm::kScanChunk - 1) / fm::kScanChunk);
-    p.emit_blocks = (int)std::max<int64_t>(1, std::min<int64_t>((max_pairs + fm::kEmitChunk - 1) / fm::kEmitChunk,
-                                                                 fm::kMaxEmitGrid));
+    p.emit_blocks = std::min(p.sortG_p, fm::kMaxEmitGrid);  // a block emits one sort tile at a time
 
     // submaps in index order, each with the list of its views
     out.subs.resize(p.S);

@@ -27,7 +27,7 @@ constexpr int kRadix = 1 << kRadixBits;
 constexpr int kSortBlock = 256;    // threads per radix-sort block
 constexpr int kScanChunk = 2048;   // entries per block of the count scan
 constexpr int kSortTile = 4096;     // items per block of a radix pass
-constexpr int kEmitChunk = 2048;   // pairs per iteration of the emission blocks
+constexpr int kEmitChunk = 2048;   // pairs per chunk of the emission blocks (two per sort tile)
 constexpr int kMaxEmitGrid = 4096;
 constexpr int kMaxPasses = 8;      // radix passes per binning (4 depth + up to 4 tile)
 

@@ -145,16 +145,22 @@ __global__ __launch_bounds__(256) void k_radix_rowscan(uint32_t *__restrict__ hi
 // block-local start of each digit's run.  The items are placed in LDS in
 // (digit, original order) order and written out by consecutive threads, so
 // each digit's run leaves the block as one contiguous, coalesced stream.
+// With SUBST, the output key of an item is key_subst[value] instead of its
+// key (the last pass of a sort whose keys are not needed afterwards); the
+// gathers are issued with the loads and the digits kept in LDS.
+template <bool SUBST>
 __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t *__restrict__ keys_in,
                                                         const uint32_t *__restrict__ vals_in,
                                                         uint32_t *__restrict__ keys_out,
                                                         uint32_t *__restrict__ vals_out, const uint32_t *n_dev,
                                                         uint32_t n_host, int shift,
-                                                        const uint32_t *__restrict__ hist, int G, int drop) {
+                                                        const uint32_t *__restrict__ hist, int G, int drop,
+                                                        const uint32_t *__restrict__ key_subst) {
     constexpr int IPT = kSortTile / 256;   // items per lane
     constexpr int PER_WAVE = kSortTile / 4;
     __shared__ uint32_t s_key[kSortTile];
     __shared__ uint32_t s_val[kSortTile];
+    __shared__ uint8_t s_dig[SUBST ? kSortTile : 1];
     __shared__ uint32_t s_wcnt[4][kRadix];  // per-wave digit counts, then per-wave offsets
     __shared__ uint32_t s_start[kRadix];    // block-local start of each digit's run
     __shared__ uint32_t s_glob[kRadix];     // global start of this block's run of each digit
@@ -176,6 +182,14 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t *__restric
         const bool valid = i < hi;
         key[k] = valid ? keys_in[i] : kNoKey;
         val[k] = valid ? (vals_in ? vals_in[i] : i) : 0u;
+    }
+    uint32_t sub[SUBST ? IPT : 1];
+    if (SUBST) {
+#pragma unroll
+        for (int k = 0; k < IPT; ++k) {
+            const uint32_t i = wbase + (uint32_t)k * 64u + (uint32_t)lane;
+            sub[k] = i < hi ? key_subst[val[k]] : 0u;
+        }
     }
     __syncthreads();
     uint32_t rank[IPT];
@@ -225,7 +239,12 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t *__restric
         const uint32_t d = (key[k] >> shift) & 0xFFu;
         const uint32_t lp = s_start[d] + s_wcnt[w][d] + rank[k];
         if (lp < (uint32_t)kSortTile) {  // always holds; guards the LDS store
-            s_key[lp] = key[k];
+            if (SUBST) {
+                s_key[lp] = sub[k];
+                s_dig[lp] = (uint8_t)d;
+            } else {
+                s_key[lp] = key[k];
+            }
             s_val[lp] = val[k];
         }
     }
@@ -233,7 +252,7 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t *__restric
     const uint32_t total = s_wsum[0] + s_wsum[1] + s_wsum[2] + s_wsum[3];
     for (uint32_t i = threadIdx.x; i < total; i += 256) {
         const uint32_t k = s_key[i];
-        const uint32_t d = (k >> shift) & 0xFFu;
+        const uint32_t d = SUBST ? (uint32_t)s_dig[i] : (k >> shift) & 0xFFu;
         const uint32_t g = s_glob[d] + (i - s_start[d]);
         if (g < n) {  // always holds; guards the store
             keys_out[g] = k;
@@ -244,22 +263,17 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t *__restric
 
 // ---- pair count scan and emission -----------------------------------------
 
-// Block b sums the tile counts of sorted entries [b*kScanChunk, ...) and
-// stores them in sorted order (cnt_sorted) for the offset pass.
-__global__ __launch_bounds__(256) void k_count_reduce(const uint32_t *__restrict__ sorted_entry,
-                                                       const uint32_t *__restrict__ cnt, const uint32_t *n_vis,
-                                                       uint32_t *__restrict__ blk, uint32_t *__restrict__ cnt_sorted) {
+// Block b sums the tile counts of sorted entries [b*kScanChunk, ...)
+// (cnt_sorted: the counts in depth order, written by the last depth pass).
+__global__ __launch_bounds__(256) void k_count_reduce(const uint32_t *__restrict__ cnt_sorted, const uint32_t *n_vis,
+                                                       uint32_t *__restrict__ blk) {
     __shared__ uint32_t red[4];
     const int64_t E = *n_vis;
     const int64_t lo = (int64_t)blockIdx.x * kScanChunk;
     int64_t hi = lo + kScanChunk;
     if (hi > E) hi = E;
     uint32_t s = 0;
-    for (int64_t k = lo + threadIdx.x; k < hi; k += 256) {
-        const uint32_t c = cnt[sorted_entry[k]];
-        cnt_sorted[k] = c;
-        s += c;
-    }
+    for (int64_t k = lo + threadIdx.x; k < hi; k += 256) s += cnt_sorted[k];
     for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
     if (lane_id() == 0) red[threadIdx.x >> 6] = s;
     __syncthreads();
@@ -341,10 +355,12 @@ __device__ inline uint32_t block_mask(const Ell &el, int x0, int y0, int tw, int
 // Every entry that holds the first pair of a chunk of kEmitChunk pairs writes
 // its sorted index into chunk_first.  Visible entries cover at least one
 // tile, so chunk c's pairs belong to entries chunk_first[c] .. chunk_first[c+1].
+// off32 may alias cnt_sorted: a thread reads its counts before it writes the
+// same positions.
 constexpr int kPer = kScanChunk / 256;
-__global__ __launch_bounds__(256) void k_offsets(const uint32_t *__restrict__ cnt_sorted, const uint32_t *n_vis,
+__global__ __launch_bounds__(256) void k_offsets(const uint32_t *cnt_sorted, const uint32_t *n_vis,
                                                   const uint64_t *__restrict__ blk_off, uint64_t cap,
-                                                  uint32_t *__restrict__ off32, uint32_t *__restrict__ chunk_first) {
+                                                  uint32_t *off32, uint32_t *__restrict__ chunk_first) {
     __shared__ uint32_t wsum[4];
     const int64_t E = *n_vis;
     const int64_t lo = (int64_t)blockIdx.x * kScanChunk;
@@ -398,73 +414,92 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t *__restrict__ sorte
                                                const uint32_t *__restrict__ off32, const uint32_t *n_vis,
                                                const uint32_t *__restrict__ chunk_first, const Status *st,
                                                const Ell *__restrict__ ell, KParams kp,
-                                               uint32_t *__restrict__ pkey, uint32_t *__restrict__ pval) {
+                                               uint32_t *__restrict__ pkey, uint32_t *__restrict__ pval,
+                                               uint32_t *__restrict__ hist, int G) {
+    static_assert(2 * kEmitChunk == kSortTile && kRadix == 256, "two chunks make a tile of the first tile-sort pass");
     constexpr int PER = kEmitChunk / 256;
     __shared__ uint32_t s_own[kEmitChunk];
     __shared__ uint32_t s_ent[kEmitChunk];
     __shared__ uint32_t s_off[kEmitChunk];
+    __shared__ uint32_t s_hist[kRadix];
     __shared__ uint32_t wmax[4];
     const uint32_t total = st->n_pairs;
     const uint32_t nv = *n_vis;
     const uint32_t nchunks = (total + kEmitChunk - 1) / kEmitChunk;
     const int w = threadIdx.x >> 6, lane = lane_id();
-    for (uint32_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
-        const uint32_t p0 = c * kEmitChunk;
-        const uint32_t np = total - p0 < (uint32_t)kEmitChunk ? total - p0 : (uint32_t)kEmitChunk;
-        const uint32_t first = chunk_first[c];
-        const uint32_t lastx = c + 1 < nchunks ? chunk_first[c + 1] + 1 : nv;
-        uint32_t n_ent = lastx > first ? lastx - first : 0u;
-        if (n_ent > (uint32_t)kEmitChunk) n_ent = kEmitChunk;
-        if (first >= nv || first + n_ent > nv) n_ent = 0;  // cannot happen; guards the loads
-        __syncthreads();  // the previous chunk's readers are done with the LDS arrays
+    // chunks 2t and 2t+1 make tile t of the first tile-sort pass: a block
+    // emits both and writes the digit histogram of their kept keys (low 8
+    // bits) to column t; the columns of the grid's tiles past the last chunk
+    // are cleared
+    for (uint32_t t = blockIdx.x; t < (uint32_t)G; t += gridDim.x) {
+        if (2u * t >= nchunks) {  // uniform over the block
+            hist[threadIdx.x * (uint32_t)G + t] = 0u;
+            continue;
+        }
+        __syncthreads();  // the previous tile's histogram has been read
+        s_hist[threadIdx.x] = 0u;
+        for (uint32_t c = 2u * t; c < 2u * t + 2u && c < nchunks; ++c) {
+            const uint32_t p0 = c * kEmitChunk;
+            const uint32_t np = total - p0 < (uint32_t)kEmitChunk ? total - p0 : (uint32_t)kEmitChunk;
+            const uint32_t first = chunk_first[c];
+            const uint32_t lastx = c + 1 < nchunks ? chunk_first[c + 1] + 1 : nv;
+            uint32_t n_ent = lastx > first ? lastx - first : 0u;
+            if (n_ent > (uint32_t)kEmitChunk) n_ent = kEmitChunk;
+            if (first >= nv || first + n_ent > nv) n_ent = 0;  // cannot happen; guards the loads
+            __syncthreads();  // the previous chunk's readers are done with the LDS arrays
 #pragma unroll
-        for (int i = 0; i < PER; ++i) s_own[i * 256 + threadIdx.x] = 0u;
-        __syncthreads();
-        for (uint32_t i = threadIdx.x; i < n_ent; i += 256) {
-            const uint32_t o = off32[first + i];
-            s_ent[i] = sorted_entry[first + i];
-            s_off[i] = o;
-            const uint32_t ls = o > p0 ? o - p0 : 0u;
-            if (ls < np && i > 0) s_own[ls] = i;
+            for (int i = 0; i < PER; ++i) s_own[i * 256 + threadIdx.x] = 0u;
+            __syncthreads();
+            for (uint32_t i = threadIdx.x; i < n_ent; i += 256) {
+                const uint32_t o = off32[first + i];
+                s_ent[i] = sorted_entry[first + i];
+                s_off[i] = o;
+                const uint32_t ls = o > p0 ? o - p0 : 0u;
+                if (ls < np && i > 0) s_own[ls] = i;
+            }
+            __syncthreads();
+            // inclusive max-scan of s_own: a thread owns PER consecutive positions
+            uint32_t v[PER];
+            uint32_t m = 0;
+#pragma unroll
+            for (int i = 0; i < PER; ++i) {
+                const uint32_t y = s_own[threadIdx.x * PER + i];
+                m = y > m ? y : m;
+                v[i] = m;
+            }
+            const uint32_t incl = wave_incl_max_u32(m, lane);
+            if (lane == 63) wmax[w] = incl;
+            __syncthreads();
+            uint32_t pre = __shfl_up(incl, 1);
+            if (lane == 0) pre = 0;
+            for (int j = 0; j < w; ++j) pre = wmax[j] > pre ? wmax[j] : pre;
+#pragma unroll
+            for (int i = 0; i < PER; ++i) s_own[threadIdx.x * PER + i] = v[i] > pre ? v[i] : pre;
+            __syncthreads();
+            for (uint32_t q = threadIdx.x; q < np; q += 256) {
+                uint32_t i = s_own[q];
+                if (i >= n_ent) i = 0;  // cannot happen; keeps the LDS read in range
+                const uint32_t ent = s_ent[i];
+                const uint32_t r = p0 + q - s_off[i];
+                const Ell el = ell[ent];
+                const uint32_t ntx = el.nt & 0xFFFFu, tiles_x = el.nt >> 16;
+                // r / ntx: r < 2^24, so the float estimate is off by at most one
+                uint32_t ry = (uint32_t)((float)r * __builtin_amdgcn_rcpf((float)ntx));
+                if (ry * ntx > r) --ry;
+                else if ((ry + 1u) * ntx <= r) ++ry;
+                const uint32_t rx = r - ry * ntx;
+                const int tx = (int)(el.t0 & 0xFFFFu) + (int)rx, ty = (int)(el.t0 >> 16) + (int)ry;
+                const uint32_t mask = block_mask(el, tx * kp.tile_w, ty * kp.tile_h, kp.tile_w, kp.tile_h);
+                // a tile of the rect that no block of reaches carries no pair: its
+                // key drops it in the first tile-sort pass
+                const uint32_t key = el.tb + ry * tiles_x + rx;
+                pkey[p0 + q] = mask ? key : kNoKey;
+                pval[p0 + q] = ent | (mask << kMaskShift);
+                if (mask) atomicAdd(&s_hist[key & 0xFFu], 1u);
+            }
         }
         __syncthreads();
-        // inclusive max-scan of s_own: thread t owns positions [t*PER, t*PER + PER)
-        uint32_t v[PER];
-        uint32_t m = 0;
-#pragma unroll
-        for (int i = 0; i < PER; ++i) {
-            const uint32_t y = s_own[threadIdx.x * PER + i];
-            m = y > m ? y : m;
-            v[i] = m;
-        }
-        const uint32_t incl = wave_incl_max_u32(m, lane);
-        if (lane == 63) wmax[w] = incl;
-        __syncthreads();
-        uint32_t pre = __shfl_up(incl, 1);
-        if (lane == 0) pre = 0;
-        for (int j = 0; j < w; ++j) pre = wmax[j] > pre ? wmax[j] : pre;
-#pragma unroll
-        for (int i = 0; i < PER; ++i) s_own[threadIdx.x * PER + i] = v[i] > pre ? v[i] : pre;
-        __syncthreads();
-        for (uint32_t q = threadIdx.x; q < np; q += 256) {
-            uint32_t i = s_own[q];
-            if (i >= n_ent) i = 0;  // cannot happen; keeps the LDS read in range
-            const uint32_t ent = s_ent[i];
-            const uint32_t r = p0 + q - s_off[i];
-            const Ell el = ell[ent];
-            const uint32_t ntx = el.nt & 0xFFFFu, tiles_x = el.nt >> 16;
-            // r / ntx: r < 2^24, so the float estimate is off by at most one
-            uint32_t ry = (uint32_t)((float)r * __builtin_amdgcn_rcpf((float)ntx));
-            if (ry * ntx > r) --ry;
-            else if ((ry + 1u) * ntx <= r) ++ry;
-            const uint32_t rx = r - ry * ntx;
-            const int tx = (int)(el.t0 & 0xFFFFu) + (int)rx, ty = (int)(el.t0 >> 16) + (int)ry;
-            const uint32_t mask = block_mask(el, tx * kp.tile_w, ty * kp.tile_h, kp.tile_w, kp.tile_h);
-            // a tile of the rect that no block of reaches carries no pair: its
-            // key drops it in the first tile-sort pass
-            pkey[p0 + q] = mask ? el.tb + ry * tiles_x + rx : kNoKey;
-            pval[p0 + q] = ent | (mask << kMaskShift);
-        }
+        hist[threadIdx.x * (uint32_t)G + t] = s_hist[threadIdx.x];
     }
 }
 
@@ -486,12 +521,17 @@ __global__ __launch_bounds__(256) void k_tile_ranges(const uint32_t *__restrict_
 
 void radix_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout, const uint32_t *n_dev,
                 uint32_t n_host, int shift, uint32_t *hist, int G, uint32_t *tot, int drop, uint32_t *n_kept,
-                hipStream_t s) {
-    hipLaunchKernelGGL(k_radix_hist, dim3(G), dim3(256), 0, s, kin, n_dev, n_host, shift, hist, G, drop);
+                hipStream_t s, const uint32_t *key_subst = nullptr, bool hist_ready = false) {
+    if (!hist_ready)
+        hipLaunchKernelGGL(k_radix_hist, dim3(G), dim3(256), 0, s, kin, n_dev, n_host, shift, hist, G, drop);
     hipLaunchKernelGGL(k_radix_rowsum, dim3(kRadix), dim3(256), 0, s, hist, G, tot);
     hipLaunchKernelGGL(k_radix_rowscan, dim3(kRadix), dim3(256), 0, s, hist, tot, G, n_kept);
-    hipLaunchKernelGGL(k_radix_scatter, dim3(G), dim3(256), 0, s, kin, vin, kout, vout, n_dev, n_host, shift,
-                       hist, G, drop);
+    if (key_subst)
+        hipLaunchKernelGGL(k_radix_scatter<true>, dim3(G), dim3(256), 0, s, kin, vin, kout, vout, n_dev, n_host,
+                           shift, hist, G, drop, key_subst);
+    else
+        hipLaunchKernelGGL(k_radix_scatter<false>, dim3(G), dim3(256), 0, s, kin, vin, kout, vout, n_dev, n_host,
+                           shift, hist, G, drop, key_subst);
 }
 
 }  // namespace
@@ -514,31 +554,34 @@ hipError_t launch_binning(const Plan &p, void *ws, const KParams &kp, hipStream_
     radix_pass(key, nullptr, key2, val2, nullptr, E, 0, hist, p.sortG_e, tot + 0 * kRadix, 1, n_vis, st);
     radix_pass(key2, val2, key, val, n_vis, 0, 8, hist, p.sortG_e, tot + 1 * kRadix, 0, nullptr, st);
     radix_pass(key, val, key2, val2, n_vis, 0, 16, hist, p.sortG_e, tot + 2 * kRadix, 0, nullptr, st);
-    radix_pass(key2, val2, key, val, n_vis, 0, 24, hist, p.sortG_e, tot + 3 * kRadix, 0, nullptr, st);
+    // (the last pass outputs each entry's tile count in place of its key)
+    const uint32_t *cnt = at<uint32_t>(ws, p.o_cnt);
+    radix_pass(key2, val2, key, val, n_vis, 0, 24, hist, p.sortG_e, tot + 3 * kRadix, 0, nullptr, st, cnt);
     // 2. pair offsets in depth order and emission
     uint32_t *blk = at<uint32_t>(ws, p.o_scan);
     uint64_t *blk_off = reinterpret_cast<uint64_t *>(blk + ((p.scan_blocks + 63) & ~63));
-    // the ping-pong key buffer is free after the last pass: it holds the counts in depth order
-    uint32_t *cnt_sorted = key2;
-    hipLaunchKernelGGL(k_count_reduce, dim3(p.scan_blocks), dim3(256), 0, st, val, at<uint32_t>(ws, p.o_cnt),
-                       n_vis, blk, cnt_sorted);
+    // the key buffer holds the counts in depth order
+    uint32_t *cnt_sorted = key;
+    hipLaunchKernelGGL(k_count_reduce, dim3(p.scan_blocks), dim3(256), 0, st, cnt_sorted, n_vis, blk);
     hipLaunchKernelGGL(k_count_scan, dim3(1), dim3(1024), 0, st, blk, p.scan_blocks, blk_off, status,
                        (uint64_t)p.cap);
     uint32_t *pkey = at<uint32_t>(ws, p.o_pkey), *pval = at<uint32_t>(ws, p.o_pval);
     uint32_t *pkey2 = at<uint32_t>(ws, p.o_pkey2), *pval2 = at<uint32_t>(ws, p.o_pval2);
-    // the sorted depth keys are dead after the last pass: their buffer holds the offsets
+    // the offsets replace the counts in place
     uint32_t *off32 = key;
     uint32_t *chunk_first = at<uint32_t>(ws, p.o_chunk);
     hipLaunchKernelGGL(k_offsets, dim3(p.scan_blocks), dim3(256), 0, st, cnt_sorted, n_vis, blk_off,
                        (uint64_t)p.cap, off32, chunk_first);
     hipLaunchKernelGGL(k_emit, dim3(p.emit_blocks), dim3(256), 0, st, val, off32, n_vis, chunk_first, status,
-                       at<Ell>(ws, p.o_ell), kp, pkey, pval);
+                       at<Ell>(ws, p.o_ell), kp, pkey, pval, hist, p.sortG_p);
     // 3. stable sort of the pairs by tile id
     uint32_t *ka = pkey, *va = pval, *kb = pkey2, *vb = pval2;
-    // (the first pass drops the pairs of missed tiles and counts the rest)
+    // (the first pass drops the pairs of missed tiles and counts the rest;
+    // its histogram comes from the emission)
     for (int pass = 0; pass < p.pair_passes; ++pass) {
         radix_pass(ka, va, kb, vb, pass == 0 ? &status->n_pairs : &status->n_kept, 0, 8 * pass, hist, p.sortG_p,
-                   tot + (4 + pass) * kRadix, pass == 0 ? 1 : 0, pass == 0 ? &status->n_kept : nullptr, st);
+                   tot + (4 + pass) * kRadix, pass == 0 ? 1 : 0, pass == 0 ? &status->n_kept : nullptr, st,
+                   nullptr, pass == 0);
         uint32_t *t = ka; ka = kb; kb = t;
         t = va; va = vb; vb = t;
     }
