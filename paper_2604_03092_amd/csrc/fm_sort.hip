@@ -89,53 +89,48 @@ __global__ __launch_bounds__(256) void k_radix_hist(const uint32_t *__restrict__
                                                h[3][threadIdx.x];
 }
 
-// Digit totals of the pass: block d sums row d of the histogram.
-__global__ __launch_bounds__(256) void k_radix_rowsum(const uint32_t *__restrict__ hist, int G,
-                                                       uint32_t *__restrict__ tot) {
-    __shared__ uint32_t wsum[4];
-    const int d = blockIdx.x;
-    const uint32_t *row = hist + (size_t)d * G;
-    uint32_t t = 0;
-    for (int b = threadIdx.x; b < G; b += 256) t += row[b];
-    for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off);
-    if (lane_id() == 0) wsum[threadIdx.x >> 6] = t;
-    __syncthreads();
-    if (threadIdx.x == 0) tot[d] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
-}
-
-// Global scatter offsets: block d turns row d of the histogram into
-// sum_{d' < d} tot[d'] + exclusive prefix over the blocks.  The last block
-// also stores the number of items kept by the pass when n_kept is set.
-__global__ __launch_bounds__(256) void k_radix_rowscan(uint32_t *__restrict__ hist, const uint32_t *__restrict__ tot,
-                                                        int G, uint32_t *__restrict__ n_kept) {
+// Block d turns row d of the histogram into the exclusive prefix over the
+// blocks (each block's start within the digit's run) and stores the digit's
+// total in tot[d]; the scatter adds the digit's base (the sum of the totals
+// of the smaller digits).
+__global__ __launch_bounds__(256) void k_radix_rowscan(uint32_t *__restrict__ hist, int G,
+                                                        uint32_t *__restrict__ tot) {
     __shared__ uint32_t wsum[4];
     const int d = blockIdx.x;
     const int w = threadIdx.x >> 6, lane = lane_id();
-    uint32_t t = threadIdx.x < (unsigned)d ? tot[threadIdx.x] : 0u;
-    for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off);
-    if (lane == 0) wsum[w] = t;
-    __syncthreads();
-    uint32_t carry = wsum[0] + wsum[1] + wsum[2] + wsum[3];
-    __syncthreads();
+    uint32_t carry = 0;
     uint32_t *row = hist + (size_t)d * G;
-    for (int base = 0; base < G; base += 256) {
-        const int b = base + threadIdx.x;
-        const uint32_t c = b < G ? row[b] : 0u;
-        uint32_t x = c;
+    // rounds of 256 x R columns, R consecutive ones per thread
+    constexpr int R = 16;
+    for (int base = 0; base < G; base += 256 * R) {
+        const int b0 = base + (int)threadIdx.x * R;
+        uint32_t c[R];
+        uint32_t run = 0;
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            c[i] = b0 + i < G ? row[b0 + i] : 0u;
+            run += c[i];
+        }
+        uint32_t x = run;
         for (int off = 1; off < 64; off <<= 1) {
             const uint32_t y = __shfl_up(x, off);
             if (lane >= off) x += y;
         }
         if (lane == 63) wsum[w] = x;
         __syncthreads();
-        uint32_t wb = 0;
-        for (int j = 0; j < w; ++j) wb += wsum[j];
-        if (b < G) row[b] = carry + wb + x - c;
+        uint32_t o = carry + x - run;
+        for (int j = 0; j < w; ++j) o += wsum[j];
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            if (b0 + i < G) row[b0 + i] = o;
+            o += c[i];
+        }
         carry += wsum[0] + wsum[1] + wsum[2] + wsum[3];
         __syncthreads();
     }
-    if (n_kept && d == kRadix - 1 && threadIdx.x == 0) *n_kept = carry;
+    if (threadIdx.x == 0) tot[d] = carry;
 }
+
 
 // Stable scatter by digit through a local sort.  The block's tile of
 // kSortTile items is split into one run of 1024 per wave; a wave ranks its
@@ -145,6 +140,10 @@ __global__ __launch_bounds__(256) void k_radix_rowscan(uint32_t *__restrict__ hi
 // block-local start of each digit's run.  The items are placed in LDS in
 // (digit, original order) order and written out by consecutive threads, so
 // each digit's run leaves the block as one contiguous, coalesced stream.
+// The global start of the block's run of digit d is its row-scanned
+// histogram entry plus the digit's base, the exclusive scan of the digit
+// totals, which every block forms itself; block 0 also stores the number of
+// items the pass keeps when n_kept is set.
 // With SUBST, the output key of an item is key_subst[value] instead of its
 // key (the last pass of a sort whose keys are not needed afterwards); the
 // gathers are issued with the loads and the digits kept in LDS.
@@ -155,6 +154,7 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t *__restric
                                                         uint32_t *__restrict__ vals_out, const uint32_t *n_dev,
                                                         uint32_t n_host, int shift,
                                                         const uint32_t *__restrict__ hist, int G, int drop,
+                                                        const uint32_t *__restrict__ tot, uint32_t *n_kept,
                                                         const uint32_t *__restrict__ key_subst) {
     constexpr int IPT = kSortTile / 256;   // items per lane
     constexpr int PER_WAVE = kSortTile / 4;
@@ -170,10 +170,25 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t *__restric
     const uint32_t n = count_of(n_dev, n_host);
     uint32_t lo, hi;
     tile_of(n, G, lo, hi);
-    if (lo >= hi) return;  // uniform over the block
+    if (lo >= hi) return;  // uniform over the block (block 0 returns only when the pass has no items)
+    {
+        // thread = digit: base of the digit = exclusive scan of the totals
+        const uint32_t t = tot[threadIdx.x];
+        uint32_t x = t;
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(x, off);
+            if (lane >= off) x += y;
+        }
+        if (lane == 63) s_wsum[w] = x;
+        __syncthreads();
+        uint32_t base = x - t;
+        for (int j = 0; j < w; ++j) base += s_wsum[j];
+        s_glob[threadIdx.x] = hist[threadIdx.x * G + logical_block(n, G)] + base;
+        if (n_kept && blockIdx.x == 0 && threadIdx.x == kRadix - 1) *n_kept = base + t;
+        __syncthreads();  // s_wsum is reused below
+    }
 #pragma unroll
     for (int k = 0; k < 4; ++k) s_wcnt[k][threadIdx.x] = 0u;
-    s_glob[threadIdx.x] = hist[threadIdx.x * G + logical_block(n, G)];
     uint32_t key[IPT], val[IPT];
     const uint32_t wbase = lo + (uint32_t)w * PER_WAVE;
 #pragma unroll
@@ -220,15 +235,15 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t *__restric
         s_wcnt[1][d] = c0;
         s_wcnt[2][d] = c0 + c1;
         s_wcnt[3][d] = c0 + c1 + c2;
-        const uint32_t tot = c0 + c1 + c2 + c3;
-        uint32_t x = tot;
+        const uint32_t all = c0 + c1 + c2 + c3;
+        uint32_t x = all;
         for (int off = 1; off < 64; off <<= 1) {
             const uint32_t y = __shfl_up(x, off);
             if (lane >= off) x += y;
         }
         if (lane == 63) s_wsum[w] = x;
         __syncthreads();
-        uint32_t pre = x - tot;
+        uint32_t pre = x - all;
         for (int j = 0; j < w; ++j) pre += s_wsum[j];
         s_start[d] = pre;
     }
@@ -524,14 +539,13 @@ void radix_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32
                 hipStream_t s, const uint32_t *key_subst = nullptr, bool hist_ready = false) {
     if (!hist_ready)
         hipLaunchKernelGGL(k_radix_hist, dim3(G), dim3(256), 0, s, kin, n_dev, n_host, shift, hist, G, drop);
-    hipLaunchKernelGGL(k_radix_rowsum, dim3(kRadix), dim3(256), 0, s, hist, G, tot);
-    hipLaunchKernelGGL(k_radix_rowscan, dim3(kRadix), dim3(256), 0, s, hist, tot, G, n_kept);
+    hipLaunchKernelGGL(k_radix_rowscan, dim3(kRadix), dim3(256), 0, s, hist, G, tot);
     if (key_subst)
         hipLaunchKernelGGL(k_radix_scatter<true>, dim3(G), dim3(256), 0, s, kin, vin, kout, vout, n_dev, n_host,
-                           shift, hist, G, drop, key_subst);
+                           shift, hist, G, drop, tot, n_kept, key_subst);
     else
         hipLaunchKernelGGL(k_radix_scatter<false>, dim3(G), dim3(256), 0, s, kin, vin, kout, vout, n_dev, n_host,
-                           shift, hist, G, drop, key_subst);
+                           shift, hist, G, drop, tot, n_kept, key_subst);
 }
 
 }  // namespace
@@ -542,7 +556,6 @@ hipError_t launch_binning(const Plan &p, void *ws, const KParams &kp, hipStream_
     uint32_t *val = at<uint32_t>(ws, p.o_val), *val2 = at<uint32_t>(ws, p.o_val2);
     uint32_t *hist = at<uint32_t>(ws, p.o_hist);
     uint32_t *tot = at<uint32_t>(ws, p.o_tot);
-    hipLaunchKernelGGL(k_fill_u32, dim3(8), dim3(256), 0, st, tot, 0u, (int64_t)kRadix * kMaxPasses);
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, st, reinterpret_cast<uint32_t *>(status), 0u,
                        (int64_t)(sizeof(Status) / 4));
     // 1. stable sort of the entries by their 32-bit depth key (4 passes; the
