@@ -310,6 +310,9 @@ def main():
         acc = ph if acc is None else {k: acc[k] + ph[k] for k in acc}
     rast.set_timing(False)
     phases = {k: v / n_t for k, v in acc.items()}
+    # contributor counts come from a plain forward (the fused path does not count)
+    rast.forward_into(gs, ws, out)
+    torch.cuda.synchronize()
     tf, nc = rast.pixel_state(gs, ws)
     useful = int(nc.astype(np.int64).sum())
     log(f"phases (ms): " + ", ".join(f"{k}={v:.3f}" for k, v in phases.items()))

@@ -225,8 +225,10 @@ fm_status fm_debug_pairs(fm_ctx *ctx, const fm_batch *batch, const fm_raster_par
                          uint32_t *tile_start, uint32_t *tile_end, int64_t n_tiles);
 
 /* Test hook: copies the per-pixel final transmittance and number of
- * composited surfels of the last forward into HOST buffers of npx entries
- * (npx >= total pixels of the batch).  Synchronous. */
+ * composited surfels into HOST buffers of npx entries (npx >= total pixels
+ * of the batch).  The transmittance is the last fm_forward's or
+ * fm_fwd_bwd_l1's; the counts are written by fm_forward only (the fused
+ * path does not count).  Synchronous. */
 fm_status fm_debug_pixel_state(fm_ctx *ctx, const fm_batch *batch, const fm_raster_params *params,
                                const void *workspace, int64_t max_pairs, float *t_final,
                                uint32_t *n_contrib, int64_t npx);

@@ -29,7 +29,7 @@ namespace {
 
 struct Surf {
     float c00, c01, c02, c10, c11, c12, c20, c21, c22;
-    float sig, r, g, b, n0, n1, n2, z, xs, ys;
+    float sig, r, g, b, n0, n1, n2, z, xs, ys, lsig;
 };
 
 __device__ __forceinline__ void load_surf(const Rec *rp, Surf &s) {
@@ -39,7 +39,7 @@ __device__ __forceinline__ void load_surf(const Rec *rp, Surf &s) {
     s.c11 = b.x; s.c12 = b.y; s.c20 = b.z; s.c21 = b.w;
     s.c22 = c.x; s.sig = c.y; s.r = c.z; s.g = c.w;
     s.b = d.x; s.n0 = d.y; s.n1 = d.z; s.n2 = d.w;
-    s.z = e.x; s.xs = e.y; s.ys = e.z;
+    s.z = e.x; s.xs = e.y; s.ys = e.z; s.lsig = e.w;
 }
 
 // Ray-splat intersection at the pixel centre (px, py), evaluated for every
@@ -47,15 +47,16 @@ __device__ __forceinline__ void load_surf(const Rec *rp, Surf &s) {
 // the plane at (u, v) = (w0, w1) / w2 with w = c0 + x' c2 - y' c1.
 // Stage 1 decides `in`: the lane is live and u^2 + v^2 <= rho_max^2 (a ray
 // with w2^2 below 1e-30, parallel to the plane to FP32 precision, is out).
-// Stage 2 evaluates G = exp(-r^2/2) and alpha = min(alpha_max, sigma G),
-// with `hit` = in and sigma G >= alpha_min.  Lanes that miss get alpha = 0,
+// Stage 2 evaluates sigma G = exp2(log2(sigma) - r^2 log2(e) / 2) (G =
+// exp(-r^2/2), one fused multiply-add in the exponent) and alpha =
+// min(alpha_max, sigma G), with `hit` = in and sigma G >= alpha_min.  Lanes that miss get alpha = 0,
 // so T and the weights do not move; the adjoint zeroes their gradient terms.  Forward and backward run the same
 // instructions on the same inputs and so take the same decisions.
 constexpr float kMinDen = 1e-30f;
 
 struct Hit {
     float xp, yp, w0, w1, w2, num, den, rden, r2;
-    float G, at, alpha;
+    float at, alpha;
     bool in, hit;
 };
 
@@ -78,8 +79,7 @@ __device__ __forceinline__ void splat_alpha(const Surf &s, float amin, float ama
 #pragma clang fp contract(off)
     h.rden = __builtin_amdgcn_rcpf(SAFE ? (h.in ? h.den : 1.f) : h.den);
     h.r2 = SAFE ? (h.in ? h.num * h.rden : 0.f) : h.num * h.rden;
-    h.G = __builtin_amdgcn_exp2f(h.r2 * -0.72134752044448170368f);  // exp(-r2/2)
-    h.at = s.sig * h.G;
+    h.at = __builtin_amdgcn_exp2f(fmaf(h.r2, -0.72134752044448170368f, s.lsig));  // sigma exp(-r2/2)
     h.hit = h.in && (h.at >= amin);
     // min(alpha_max, sigma G) on the bit patterns: both are >= 0, where the
     // IEEE order is the unsigned-integer order (and no canonicalisation is
@@ -184,8 +184,9 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
 // surfel's support, a bound on its last contributor for the adjoint.  A
 // pixel that is outside the image or has stopped compositing carries x =
 // NaN, which fails every support test; slots whose pixels have all stopped
-// are dropped from the live set every 8 list positions.
-template <int TW, int TH>
+// are dropped from the live set every 8 list positions.  COUNT: also count
+// each pixel's contributors (ncount; the fused path skips it).
+template <int TW, int TH, bool COUNT>
 __device__ __forceinline__ void tile_forward(const TileCtx &c, const Slots<TW, TH> &sl,
                                              const uint32_t *__restrict__ pval, const Rec *__restrict__ rec,
                                              const KParams &kp, Rec *srec, uint32_t *sval,
@@ -237,7 +238,7 @@ __device__ __forceinline__ void tile_forward(const TileCtx &c, const Slots<TW, T
                     acc[q][6] = fmaf(s.n2, wgt, acc[q][6]);
                     acc[q][7] = acc[q][7] + wgt;
                     T[q] = con ? test : T[q];
-                    ncount[q] += con ? 1u : 0u;
+                    if (COUNT) ncount[q] += con ? 1u : 0u;
                     px[q] = stop ? nan : px[q];
                 }
             }
@@ -252,7 +253,7 @@ __device__ __forceinline__ void tile_forward(const TileCtx &c, const Slots<TW, T
 }
 
 // Adjoint terms of one hit slot, added into the lane's per-surfel gradient
-// registers (gr: dL/dc0[3], dL/dc1[3], dL/dc2[3], dL/dsigma, dL/d(r, g, b),
+// registers (gr: dL/dc0[3], dL/dc1[3], dL/dc2[3], sigma dL/dsigma, dL/d(r, g, b),
 // dL/dz, dL/dn[0..1]; gn2: dL/dn[2]).  FIRST: the first slot of the surfel,
 // which assigns instead of adding.  Also steps S_k and T of the slot.
 template <bool FIRST, bool HAS_N>
@@ -280,10 +281,12 @@ __device__ __forceinline__ void adjoint_terms(const Hit &h, const Surf &s, const
         mac(gn2, gq[6], wgt);
     }
     // G = exp(-r2/2), r2 = (w0^2 + w1^2) / w2^2, w = c0 + x' c2 - y' c1:
-    // dL/dsigma = du G, dL/dr2 = -du sigma G / 2, and
+    // sigma dL/dsigma = du sigma G (divided by sigma after the tile's
+    // reduction), dL/dr2 = -du sigma G / 2, and
     // dr2/dw = (2 w0, 2 w1, -2 r2 w2) / w2^2
-    mac(gr[9], du, h.G);
-    const float kk = -(du * h.at) * h.rden;
+    const float dua = du * h.at;
+    add(gr[9], dua);
+    const float kk = -dua * h.rden;
     const float w0 = h.hit ? h.w0 : 0.f, w1 = h.hit ? h.w1 : 0.f, w2 = h.hit ? h.w2 : 0.f;
     const float gw0 = kk * w0, gw1 = kk * w1, gw2 = -(kk * h.r2) * w2;
     add(gr[0], gw0);
@@ -363,7 +366,8 @@ __device__ __forceinline__ void tile_backward(const TileCtx &c, const Slots<TW, 
                 first = false;
             }
             if (first) continue;  // no lane of the tile is hit by this surfel
-            const float r = wave_reduce16(gr);
+            float r = wave_reduce16(gr);
+            if (comp == 9) r *= __builtin_amdgcn_rcpf(s.sig);  // sigma dL/dsigma -> dL/dsigma
             float *dst = grad + (int64_t)(sval[j] & kEntryMask) * kGradStride;
             if (comp >= 0 && (HAS_N || comp < 14)) atomicAdd(dst + comp, r);  // 14, 15: normal terms
             if (HAS_N) {
@@ -389,7 +393,7 @@ __global__ __launch_bounds__(64) void k_render_fwd(const ViewDesc *__restrict__ 
     const TileCtx c = tile_ctx<TW, TH>(views, V, ts, te, sl);
     float acc[Gm::NB][8], T[Gm::NB];
     uint32_t slast[Gm::NB], nc[Gm::NB];
-    tile_forward<TW, TH>(c, sl, pval, rec, kp, srec, sval, acc, T, slast, nc);
+    tile_forward<TW, TH, true>(c, sl, pval, rec, kp, srec, sval, acc, T, slast, nc);
 #pragma unroll
     for (int q = 0; q < Gm::NB; ++q) {
         if (!sl.inside[q]) continue;
@@ -456,8 +460,7 @@ __global__ __launch_bounds__(64) void k_render_fused(const ViewDesc *__restrict_
                                                       const uint32_t *__restrict__ pval, const Rec *__restrict__ rec,
                                                       KParams kp, int64_t NPX, fm_outputs out, LossArgs la,
                                                       float *__restrict__ tfinal, uint32_t *__restrict__ nlast_out,
-                                                      uint32_t *__restrict__ ncount_out, float *__restrict__ grad,
-                                                      float *__restrict__ loss_part) {
+                                                      float *__restrict__ grad, float *__restrict__ loss_part) {
     using Gm = Geo<TW, TH>;
     __shared__ Rec srec[64];
     __shared__ uint32_t sval[64];
@@ -465,7 +468,7 @@ __global__ __launch_bounds__(64) void k_render_fused(const ViewDesc *__restrict_
     const TileCtx c = tile_ctx<TW, TH>(views, V, ts, te, sl);
     float acc[Gm::NB][8], T[Gm::NB];
     uint32_t slast[Gm::NB], nc[Gm::NB];
-    tile_forward<TW, TH>(c, sl, pval, rec, kp, srec, sval, acc, T, slast, nc);
+    tile_forward<TW, TH, false>(c, sl, pval, rec, kp, srec, sval, acc, T, slast, nc);
     float g[Gm::NB][8], S[Gm::NB], Tf[Gm::NB];
     float l = 0.f;
     const float npx = (float)c.W * (float)c.H;
@@ -491,7 +494,6 @@ __global__ __launch_bounds__(64) void k_render_fused(const ViewDesc *__restrict_
         out.alpha[p] = acc[q][7];
         tfinal[p] = T[q];
         nlast_out[p] = slast[q];
-        ncount_out[p] = nc[q];
         const bool m = la.mask ? (la.mask[p] != 0) : true;
         if (!m) continue;
         Tf[q] = T[q];
@@ -563,8 +565,8 @@ hipError_t fused_t(const Plan &p, void *ws, const KParams &kp, const LossArgs &l
     hipLaunchKernelGGL((k_render_fused<TW, TH>), dim3((unsigned)(p.T * Geo<TW, TH>::NQ)), dim3(64), 0, st,
                        at<ViewDesc>(ws, p.o_views), p.V, at<uint32_t>(ws, p.o_tstart),
                        at<uint32_t>(ws, p.o_tend), pval, at<Rec>(ws, p.o_rec), kp, p.NPX, out, la,
-                       at<float>(ws, p.o_tfinal), at<uint32_t>(ws, p.o_nlast), at<uint32_t>(ws, p.o_ncount),
-                       at<float>(ws, p.o_grad), at<float>(ws, p.o_loss));
+                       at<float>(ws, p.o_tfinal), at<uint32_t>(ws, p.o_nlast), at<float>(ws, p.o_grad),
+                       at<float>(ws, p.o_loss));
     return hipGetLastError();
 }
 

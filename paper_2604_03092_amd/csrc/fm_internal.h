@@ -69,7 +69,7 @@ struct alignas(16) Rec {
     float nrm[3];   // camera-space unit normal facing the camera
     float z;        // camera-space depth of the centre
     float xs, ys;   // pixel-frame shift (integers, exact in float)
-    float pad[1];
+    float lsig;     // log2(sigma): sigma G = exp2(log2(sigma) - r^2 / (2 ln 2))
 };
 static_assert(sizeof(Rec) == 80, "record layout");
 

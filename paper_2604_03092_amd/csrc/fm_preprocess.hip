@@ -175,7 +175,7 @@ __global__ __launch_bounds__(256) void k_preprocess(const ViewDesc *__restrict__
                         r.z = (float)depth;
                         r.xs = (float)ixc;
                         r.ys = (float)iyc;
-                        r.pad[0] = 0.f;
+                        r.lsig = (float)log2(sigma);
                         // culling ellipse: support radius with the opacity cut-off,
                         // rho_eff^2 = min(rho_max^2, 2 ln(sigma / alpha_min)), enlarged
                         // by 0.2% so that it contains every pixel the FP32 blend accepts
