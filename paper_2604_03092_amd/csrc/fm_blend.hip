@@ -286,9 +286,11 @@ __device__ __forceinline__ void adjoint_terms(const Hit &h, const Surf &s, const
     // dr2/dw = (2 w0, 2 w1, -2 r2 w2) / w2^2
     const float dua = du * h.at;
     add(gr[9], dua);
+    // (a lane that misses has du = 0 and finite rden, r2 and w -- the
+    // projection culls records with coefficients beyond 1e30 -- so its terms
+    // are signed zeros)
     const float kk = -dua * h.rden;
-    const float w0 = h.hit ? h.w0 : 0.f, w1 = h.hit ? h.w1 : 0.f, w2 = h.hit ? h.w2 : 0.f;
-    const float gw0 = kk * w0, gw1 = kk * w1, gw2 = -(kk * h.r2) * w2;
+    const float gw0 = kk * h.w0, gw1 = kk * h.w1, gw2 = -(kk * h.r2) * h.w2;
     add(gr[0], gw0);
     add(gr[1], gw1);
     add(gr[2], gw2);

@@ -157,66 +157,73 @@ __global__ __launch_bounds__(256) void k_preprocess(const ViewDesc *__restrict__
                         const double r0[3] = {H[0] - xs * H[6], H[1] - xs * H[7], H[2] - xs * H[8]};
                         const double r1[3] = {H[3] - ys * H[6], H[4] - ys * H[7], H[5] - ys * H[8]};
                         const double r2[3] = {H[6], H[7], H[8]};
-                        Rec r;
-                        r.c0[0] = (float)(r0[1] * r1[2] - r0[2] * r1[1]);
-                        r.c0[1] = (float)(r0[2] * r1[0] - r0[0] * r1[2]);
-                        r.c0[2] = (float)(r0[0] * r1[1] - r0[1] * r1[0]);
-                        r.c1[0] = (float)(r0[1] * r2[2] - r0[2] * r2[1]);
-                        r.c1[1] = (float)(r0[2] * r2[0] - r0[0] * r2[2]);
-                        r.c1[2] = (float)(r0[0] * r2[1] - r0[1] * r2[0]);
-                        r.c2[0] = (float)(r1[1] * r2[2] - r1[2] * r2[1]);
-                        r.c2[1] = (float)(r1[2] * r2[0] - r1[0] * r2[2]);
-                        r.c2[2] = (float)(r1[0] * r2[1] - r1[1] * r2[0]);
-                        r.sigma = f_sig;
-                        r.col[0] = f_c0; r.col[1] = f_c1; r.col[2] = f_c2;
-                        r.nrm[0] = (float)(sgn * n0[0]);
-                        r.nrm[1] = (float)(sgn * n0[1]);
-                        r.nrm[2] = (float)(sgn * n0[2]);
-                        r.z = (float)depth;
-                        r.xs = (float)ixc;
-                        r.ys = (float)iyc;
-                        r.lsig = (float)log2(sigma);
-                        // culling ellipse: support radius with the opacity cut-off,
-                        // rho_eff^2 = min(rho_max^2, 2 ln(sigma / alpha_min)), enlarged
-                        // by 0.2% so that it contains every pixel the FP32 blend accepts
-                        {
-                            double re2 = 2.0 * log(sigma / (double)kp.alpha_min);
-                            if (re2 > rho2) re2 = rho2;
-                            const double E00 = re2 * (H[0] * H[0] + H[1] * H[1]) - H[2] * H[2];
-                            const double E01 = re2 * (H[0] * H[3] + H[1] * H[4]) - H[2] * H[5];
-                            const double E02 = re2 * (H[0] * H[6] + H[1] * H[7]) - H[2] * H[8];
-                            const double E11 = re2 * (H[3] * H[3] + H[4] * H[4]) - H[5] * H[5];
-                            const double E12 = re2 * (H[3] * H[6] + H[4] * H[7]) - H[5] * H[8];
-                            const double E22 = re2 * (H[6] * H[6] + H[7] * H[7]) - H[8] * H[8];
-                            const double i22 = 1.0 / E22, k = 1.002 * i22 * i22;
-                            // shape in FP64, the derived slice form in FP32 (the
-                            // enlargement above dwarfs its rounding)
-                            const double s00 = (E02 * E02 - E00 * E22) * k;
-                            const double s01 = (E02 * E12 - E01 * E22) * k;
-                            const double s11 = (E12 * E12 - E11 * E22) * k;
-                            const float f00 = (float)s00, f01 = (float)s01, f11 = (float)s11;
-                            const float fdet = (float)(s00 * s11 - s01 * s01);
-                            Ell el;
-                            el.ex = (float)(E02 * i22);
-                            el.ey = (float)(E12 * i22);
-                            el.hx = f00 > 0.f ? sqrtf(f00) : 0.f;
-                            el.hy = f11 > 0.f ? sqrtf(f11) : 0.f;
-                            el.k1 = f11 > 0.f ? f01 / f11 : 0.f;
-                            el.k2 = f11 > 0.f && fdet > 0.f ? (fdet / f11) / f11 : 0.f;
-                            el.dyr = el.hx > 0.f ? f01 / el.hx : 0.f;
-                            el.pad[0] = el.pad[1] = 0u;
+                        const double cc[9] = {r0[1] * r1[2] - r0[2] * r1[1], r0[2] * r1[0] - r0[0] * r1[2],
+                                              r0[0] * r1[1] - r0[1] * r1[0], r0[1] * r2[2] - r0[2] * r2[1],
+                                              r0[2] * r2[0] - r0[0] * r2[2], r0[0] * r2[1] - r0[1] * r2[0],
+                                              r1[1] * r2[2] - r1[2] * r2[1], r1[2] * r2[0] - r1[0] * r2[2],
+                                              r1[0] * r2[1] - r1[1] * r2[0]};
+                        // a surfel whose plane coefficients exceed 1e30 (a degenerate,
+                        // astronomically large projection) is culled, so that every
+                        // record's w = c0 + x' c2 - y' c1 is finite over the image
+                        bool fin = true;
+#pragma unroll
+                        for (int k = 0; k < 9; ++k) fin = fin && fabs(cc[k]) <= 1e30;
+                        if (fin) {
+                            Rec r;
+                            r.c0[0] = (float)cc[0]; r.c0[1] = (float)cc[1]; r.c0[2] = (float)cc[2];
+                            r.c1[0] = (float)cc[3]; r.c1[1] = (float)cc[4]; r.c1[2] = (float)cc[5];
+                            r.c2[0] = (float)cc[6]; r.c2[1] = (float)cc[7]; r.c2[2] = (float)cc[8];
+                            r.sigma = f_sig;
+                            r.col[0] = f_c0; r.col[1] = f_c1; r.col[2] = f_c2;
+                            r.nrm[0] = (float)(sgn * n0[0]);
+                            r.nrm[1] = (float)(sgn * n0[1]);
+                            r.nrm[2] = (float)(sgn * n0[2]);
+                            r.z = (float)depth;
+                            r.xs = (float)ixc;
+                            r.ys = (float)iyc;
+                            r.lsig = (float)log2(sigma);
+                            // culling ellipse: support radius with the opacity cut-off,
+                            // rho_eff^2 = min(rho_max^2, 2 ln(sigma / alpha_min)), enlarged
+                            // by 0.2% so that it contains every pixel the FP32 blend accepts
+                            {
+                                double re2 = 2.0 * log(sigma / (double)kp.alpha_min);
+                                if (re2 > rho2) re2 = rho2;
+                                const double E00 = re2 * (H[0] * H[0] + H[1] * H[1]) - H[2] * H[2];
+                                const double E01 = re2 * (H[0] * H[3] + H[1] * H[4]) - H[2] * H[5];
+                                const double E02 = re2 * (H[0] * H[6] + H[1] * H[7]) - H[2] * H[8];
+                                const double E11 = re2 * (H[3] * H[3] + H[4] * H[4]) - H[5] * H[5];
+                                const double E12 = re2 * (H[3] * H[6] + H[4] * H[7]) - H[5] * H[8];
+                                const double E22 = re2 * (H[6] * H[6] + H[7] * H[7]) - H[8] * H[8];
+                                const double i22 = 1.0 / E22, k = 1.002 * i22 * i22;
+                                // shape in FP64, the derived slice form in FP32 (the
+                                // enlargement above dwarfs its rounding)
+                                const double s00 = (E02 * E02 - E00 * E22) * k;
+                                const double s01 = (E02 * E12 - E01 * E22) * k;
+                                const double s11 = (E12 * E12 - E11 * E22) * k;
+                                const float f00 = (float)s00, f01 = (float)s01, f11 = (float)s11;
+                                const float fdet = (float)(s00 * s11 - s01 * s01);
+                                Ell el;
+                                el.ex = (float)(E02 * i22);
+                                el.ey = (float)(E12 * i22);
+                                el.hx = f00 > 0.f ? sqrtf(f00) : 0.f;
+                                el.hy = f11 > 0.f ? sqrtf(f11) : 0.f;
+                                el.k1 = f11 > 0.f ? f01 / f11 : 0.f;
+                                el.k2 = f11 > 0.f && fdet > 0.f ? (fdet / f11) / f11 : 0.f;
+                                el.dyr = el.hx > 0.f ? f01 / el.hx : 0.f;
+                                el.pad[0] = el.pad[1] = 0u;
+                                const int tx0 = px0 / kp.tile_w, tx1 = px1 / kp.tile_w;
+                                const int ty0 = py0 / kp.tile_h;
+                                el.tb = (uint32_t)(vd.tile_base + ty0 * vd.tiles_x + tx0);
+                                el.t0 = (uint32_t)tx0 | ((uint32_t)ty0 << 16);
+                                el.nt = (uint32_t)(tx1 - tx0 + 1) | ((uint32_t)vd.tiles_x << 16);
+                                ell[e] = el;
+                            }
+                            rec[e] = r;
                             const int tx0 = px0 / kp.tile_w, tx1 = px1 / kp.tile_w;
-                            const int ty0 = py0 / kp.tile_h;
-                            el.tb = (uint32_t)(vd.tile_base + ty0 * vd.tiles_x + tx0);
-                            el.t0 = (uint32_t)tx0 | ((uint32_t)ty0 << 16);
-                            el.nt = (uint32_t)(tx1 - tx0 + 1) | ((uint32_t)vd.tiles_x << 16);
-                            ell[e] = el;
+                            const int ty0 = py0 / kp.tile_h, ty1 = py1 / kp.tile_h;
+                            out_cnt = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+                            out_key = __float_as_uint((float)depth);
                         }
-                        rec[e] = r;
-                        const int tx0 = px0 / kp.tile_w, tx1 = px1 / kp.tile_w;
-                        const int ty0 = py0 / kp.tile_h, ty1 = py1 / kp.tile_h;
-                        out_cnt = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
-                        out_key = __float_as_uint((float)depth);
                     }
                 }
             }
