@@ -32,6 +32,20 @@ template <int CTRL> __device__ __forceinline__ float dpp(float x) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
 }
 
+// In-place half swaps: lanes 32..63 of a with lanes 0..31 of b (swap32),
+// and the odd 16-lane rows of a with the even rows of b (swap16).  Written as
+// inline asm with both operands read-write: through the builtins the
+// compiler copied the second operand before every swap in the adjoint's
+// loop (12 moves per reduction).  The leading s_nop 1 gives the two wait
+// states a permlane swap needs after a VALU write of its operands; the
+// results may be read right away.
+__device__ __forceinline__ void swap32(float &a, float &b) {
+    asm volatile("s_nop 1\n\tv_permlane32_swap_b32 %0, %1" : "+v"(a), "+v"(b));
+}
+__device__ __forceinline__ void swap16(float &a, float &b) {
+    asm volatile("s_nop 1\n\tv_permlane16_swap_b32 %0, %1" : "+v"(a), "+v"(b));
+}
+
 // Transposing reduction of 16 values over the wave.  Every lane holds
 // v[0..15]; on return, every lane holds the wave sum of component
 // 4 * (lane >> 4) + ((lane >> 2) & 3) (the four lanes of a quad agree).
@@ -44,15 +58,13 @@ template <int CTRL> __device__ __forceinline__ float dpp(float x) {
 __device__ __forceinline__ float wave_reduce16(float v[16]) {
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-        auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[i]), __float_as_uint(v[i + 8]),
-                                                  false, false);
-        v[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+        swap32(v[i], v[i + 8]);
+        v[i] = v[i] + v[i + 8];
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v[i]), __float_as_uint(v[i + 4]),
-                                                  false, false);
-        v[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+        swap16(v[i], v[i + 4]);
+        v[i] = v[i] + v[i + 4];
     }
     // row r now holds components 4r + 0..3 in v[0..3], each partial over its 16 lanes
     const int j = lane_id();
