@@ -215,7 +215,7 @@ fm_status fm_query_status(fm_ctx *ctx, const fm_batch *batch, const fm_raster_pa
  * buffers (cap entries each): tile[k] = global tile id (views' tiles back to
  * back, row-major within a view), entry[k] = view-local surfel index, view[k]
  * = view index, and the per-tile ranges tile_start/tile_end (host arrays
- * sized to the batch's total tile count).  *n_pairs is the length of the
+ * sized to the batch's total tile count; 0, 0 for a tile without pairs).  *n_pairs is the length of the
  * list: the pairs of each surfel's tile rect (the count fm_query_status
  * reports) less those of tiles that its opacity-cut support ellipse,
  * conservatively enlarged, does not reach.  Synchronous. */

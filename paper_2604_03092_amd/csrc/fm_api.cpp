@@ -611,6 +611,8 @@ fm_status fm_debug_pairs(fm_ctx *ctx, const fm_batch *b, const fm_raster_params 
         if (n_tiles < p.T) return fail(ctx, FM_ERR_INVALID_ARG, "tile range buffers too small");
         FM_TRY_HIP(hipMemcpy(tile_start, w + p.o_tstart, 4 * p.T, hipMemcpyDeviceToHost), "hipMemcpy(ranges)");
         FM_TRY_HIP(hipMemcpy(tile_end, w + p.o_tend, 4 * p.T, hipMemcpyDeviceToHost), "hipMemcpy(ranges)");
+        for (int64_t t = 0; t < p.T; ++t)  // a tile without pairs is stored as ts > te
+            if (tile_start[t] > tile_end[t]) tile_start[t] = tile_end[t] = 0u;
     }
     return FM_OK;
 }

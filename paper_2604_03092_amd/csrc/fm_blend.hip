@@ -135,6 +135,7 @@ __device__ __forceinline__ TileCtx tile_ctx(const ViewDesc *views, int V, const 
     c.pix_base = vd.pixel_offset;
     c.start = ts[tile];
     c.end = te[tile];
+    if (c.start > c.end) c.start = c.end;  // a tile without pairs
     c.n_entries = (uint32_t)views[V - 1].entry_base + (((uint32_t)views[V - 1].n + 255u) & ~255u);
     const int lane = threadIdx.x;
 #pragma unroll

@@ -147,7 +147,15 @@ __global__ __launch_bounds__(256) void k_radix_rowscan(uint32_t *__restrict__ hi
 // With SUBST, the output key of an item is key_subst[value] instead of its
 // key (the last pass of a sort whose keys are not needed afterwards); the
 // gathers are issued with the loads and the digits kept in LDS.
-template <bool SUBST>
+// With RANGES (the last pass of the tile sort), the pass also finds the
+// tile ranges [ts, te) of the sorted output: inside one of the block's
+// digit runs the keys are sorted, so a key change there is a tile boundary
+// of the whole output and is stored directly; at the ends of a run the
+// neighbour belongs to another block, so the run's first position enters
+// ts of its tile with an atomic min and its last position + 1 enters te
+// with an atomic max (ts starts at 0xFFFFFFFF, te at 0: a tile without
+// pairs keeps ts > te).
+template <bool SUBST, bool RANGES>
 __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t *__restrict__ keys_in,
                                                         const uint32_t *__restrict__ vals_in,
                                                         uint32_t *__restrict__ keys_out,
@@ -155,7 +163,9 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t *__restric
                                                         uint32_t n_host, int shift,
                                                         const uint32_t *__restrict__ hist, int G, int drop,
                                                         const uint32_t *__restrict__ tot, uint32_t *n_kept,
-                                                        const uint32_t *__restrict__ key_subst) {
+                                                        const uint32_t *__restrict__ key_subst,
+                                                        uint32_t *__restrict__ ts, uint32_t *__restrict__ te,
+                                                        uint32_t n_tiles) {
     constexpr int IPT = kSortTile / 256;   // items per lane
     constexpr int PER_WAVE = kSortTile / 4;
     __shared__ uint32_t s_key[kSortTile];
@@ -272,6 +282,13 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t *__restric
         if (g < n) {  // always holds; guards the store
             keys_out[g] = k;
             vals_out[g] = s_val[i];
+            if (RANGES && k < n_tiles) {
+                if (i == s_start[d]) atomicMin(&ts[k], g);
+                else if (s_key[i - 1] != k) ts[k] = g;
+                const uint32_t kn = i + 1 < total ? s_key[i + 1] : kNoKey;
+                if (i + 1 >= total || ((kn >> shift) & 0xFFu) != d) atomicMax(&te[k], g + 1u);
+                else if (kn != k) te[k] = g + 1u;
+            }
         }
     }
 }
@@ -522,30 +539,31 @@ __global__ __launch_bounds__(256) void k_fill_u32(uint32_t *__restrict__ p, uint
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] = v;
 }
 
-__global__ __launch_bounds__(256) void k_tile_ranges(const uint32_t *__restrict__ pkey, const Status *st,
-                                                      uint32_t *__restrict__ ts, uint32_t *__restrict__ te,
-                                                      uint32_t n_tiles) {
-    const uint32_t n = st->n_kept;
-    for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
-        const uint32_t t = pkey[i];
-        if (t >= n_tiles) continue;  // cannot happen for emitted ids; guards the stores
-        if (i == 0 || pkey[i - 1] != t) ts[t] = i;
-        if (i == n - 1 || pkey[i + 1] != t) te[t] = i + 1;
+// Tile ranges start empty with ts > te; the last tile-sort pass fills them.
+__global__ __launch_bounds__(256) void k_init_ranges(uint32_t *__restrict__ ts, uint32_t *__restrict__ te,
+                                                      int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        ts[i] = 0xFFFFFFFFu;
+        te[i] = 0u;
     }
 }
 
 void radix_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout, const uint32_t *n_dev,
                 uint32_t n_host, int shift, uint32_t *hist, int G, uint32_t *tot, int drop, uint32_t *n_kept,
-                hipStream_t s, const uint32_t *key_subst = nullptr, bool hist_ready = false) {
+                hipStream_t s, const uint32_t *key_subst = nullptr, bool hist_ready = false,
+                uint32_t *ts = nullptr, uint32_t *te = nullptr, uint32_t n_tiles = 0) {
     if (!hist_ready)
         hipLaunchKernelGGL(k_radix_hist, dim3(G), dim3(256), 0, s, kin, n_dev, n_host, shift, hist, G, drop);
     hipLaunchKernelGGL(k_radix_rowscan, dim3(kRadix), dim3(256), 0, s, hist, G, tot);
     if (key_subst)
-        hipLaunchKernelGGL(k_radix_scatter<true>, dim3(G), dim3(256), 0, s, kin, vin, kout, vout, n_dev, n_host,
-                           shift, hist, G, drop, tot, n_kept, key_subst);
+        hipLaunchKernelGGL((k_radix_scatter<true, false>), dim3(G), dim3(256), 0, s, kin, vin, kout, vout, n_dev,
+                           n_host, shift, hist, G, drop, tot, n_kept, key_subst, ts, te, n_tiles);
+    else if (ts)
+        hipLaunchKernelGGL((k_radix_scatter<false, true>), dim3(G), dim3(256), 0, s, kin, vin, kout, vout, n_dev,
+                           n_host, shift, hist, G, drop, tot, n_kept, key_subst, ts, te, n_tiles);
     else
-        hipLaunchKernelGGL(k_radix_scatter<false>, dim3(G), dim3(256), 0, s, kin, vin, kout, vout, n_dev, n_host,
-                           shift, hist, G, drop, tot, n_kept, key_subst);
+        hipLaunchKernelGGL((k_radix_scatter<false, false>), dim3(G), dim3(256), 0, s, kin, vin, kout, vout, n_dev,
+                           n_host, shift, hist, G, drop, tot, n_kept, key_subst, ts, te, n_tiles);
 }
 
 }  // namespace
@@ -587,24 +605,22 @@ hipError_t launch_binning(const Plan &p, void *ws, const KParams &kp, hipStream_
                        (uint64_t)p.cap, off32, chunk_first);
     hipLaunchKernelGGL(k_emit, dim3(p.emit_blocks), dim3(256), 0, st, val, off32, n_vis, chunk_first, status,
                        at<Ell>(ws, p.o_ell), kp, pkey, pval, hist, p.sortG_p);
-    // 3. stable sort of the pairs by tile id
+    // 3. stable sort of the pairs by tile id; the last pass also writes the
+    //    per-tile ranges
+    uint32_t *ts = at<uint32_t>(ws, p.o_tstart), *te = at<uint32_t>(ws, p.o_tend);
+    const int fill_blocks = (int)((p.T + 255) / 256 < 4096 ? (p.T + 255) / 256 : 4096);
+    hipLaunchKernelGGL(k_init_ranges, dim3(fill_blocks), dim3(256), 0, st, ts, te, p.T);
     uint32_t *ka = pkey, *va = pval, *kb = pkey2, *vb = pval2;
     // (the first pass drops the pairs of missed tiles and counts the rest;
     // its histogram comes from the emission)
     for (int pass = 0; pass < p.pair_passes; ++pass) {
+        const bool last = pass + 1 == p.pair_passes;
         radix_pass(ka, va, kb, vb, pass == 0 ? &status->n_pairs : &status->n_kept, 0, 8 * pass, hist, p.sortG_p,
                    tot + (4 + pass) * kRadix, pass == 0 ? 1 : 0, pass == 0 ? &status->n_kept : nullptr, st,
-                   nullptr, pass == 0);
+                   nullptr, pass == 0, last ? ts : nullptr, last ? te : nullptr, (uint32_t)p.T);
         uint32_t *t = ka; ka = kb; kb = t;
         t = va; va = vb; vb = t;
     }
-    // 4. per-tile ranges
-    uint32_t *ts = at<uint32_t>(ws, p.o_tstart), *te = at<uint32_t>(ws, p.o_tend);
-    const int fill_blocks = (int)((p.T + 255) / 256 < 4096 ? (p.T + 255) / 256 : 4096);
-    hipLaunchKernelGGL(k_fill_u32, dim3(fill_blocks), dim3(256), 0, st, ts, 0u, p.T);
-    hipLaunchKernelGGL(k_fill_u32, dim3(fill_blocks), dim3(256), 0, st, te, 0u, p.T);
-    const int rblocks = (int)((p.cap + 255) / 256 < 8192 ? (p.cap + 255) / 256 : 8192);
-    hipLaunchKernelGGL(k_tile_ranges, dim3(rblocks), dim3(256), 0, st, ka, status, ts, te, (uint32_t)p.T);
     return hipGetLastError();
 }
 
