@@ -292,6 +292,43 @@ def test_autograd_matches_direct(rast):
     assert_grad_close(to_np(vm.grad), to_np(dvm), "autograd.viewmat", rel=1e-5)
 
 
+def test_overflowing_record_is_culled(rast):
+    """A surfel whose plane coefficients would overflow FP32 (scale 1e25) is
+    culled: the images equal those of the same scene with that surfel
+    culled by its opacity instead, and every gradient stays finite."""
+    import copy
+    sc = scenes.config0()
+    huge = copy.deepcopy(sc)
+    sm = huge.submaps[0]
+    sm["mean"][:, 0] = (0.0, 0.0, 3.0)
+    sm["quat"][:, 0] = (1.0, 0.0, 0.0, 0.0)
+    sm["scale"][:, 0] = (1e25, 1e25)
+    gone = copy.deepcopy(huge)
+    gone.submaps[0]["opacity"][0] = 1e-4  # below alpha_min: culled the ordinary way
+    _say("overflowing record")
+    res = []
+    for s in (huge, gone):
+        gs = GpuScene.from_scene(s)
+        out, ws = rast.forward(gs)
+        rng = np.random.default_rng(5)
+        g = random_upstream(rng, gs.npx, np.ones(gs.npx, bool))
+        gt = {k: torch.from_numpy(v.astype(np.float32)).cuda() for k, v in g.items()}
+        grads, dvm = gs.zero_grads()
+        rast.backward(gs, ws, out, gt, grads, dvm)
+        torch.cuda.synchronize()
+        res.append(({k: to_np(v) for k, v in out.items()}, {k: to_np(v) for k, v in grads[0].items()},
+                    to_np(dvm)))
+    (o1, g1, v1), (o2, g2, v2) = res
+    for k in o1:
+        assert np.array_equal(o1[k], o2[k]), k
+    for k in g1:
+        assert np.isfinite(g1[k]).all(), k
+        assert np.all(g1[k][..., 0] == 0.0), k
+        assert_grad_close(g1[k], g2[k], f"overflow.{k}")
+    assert np.isfinite(v1).all()
+    assert_grad_close(v1, v2, "overflow.viewmat")
+
+
 def test_pixel_state_matches_oracle(rast):
     """Final transmittance and number of composited surfels per pixel."""
     sc = scenes.random_scene(12, 6000, 96, 64, scale_lo=0.03, scale_hi=0.2)
