@@ -99,8 +99,9 @@ def cpu_baseline(scene, threads, n_sample):
 def time_refine(rast, scene, params, iters, replays=3):
     """The map-refinement loop over the batch's keyframes: `iters` iterations
     of (zero gradients, fused forward + L1 + backward, Adam step on every
-    surfel tensor) captured in one hipGraph and replayed; a fresh copy of the
-    scene is refined."""
+    surfel tensor) captured in one hipGraph and replayed.  Every replay
+    starts from the batch's initial surfels with fresh Adam state (restored
+    outside the timed region), as a keyframe window's refinement does."""
     import torch
     from paper_2604_03092_amd.raster import Adam, GpuScene
     gs = GpuScene.from_scene(scene)
@@ -130,16 +131,30 @@ def time_refine(rast, scene, params, iters, replays=3):
     with torch.cuda.graph(graph):
         for i in range(iters):
             iteration(i)
-    losses.zero_()
+    init = [{k: sm[k].clone() for k in sm} for sm in gs.submaps]
+
+    def restore():
+        for sm, s0, m, v in zip(gs.submaps, init, adam.m, adam.v):
+            for k in sm:
+                sm[k].copy_(s0[k])
+                m[k].zero_()
+                v[k].zero_()
+        adam.step_count.zero_()
+        losses.zero_()
+        torch.cuda.synchronize()
+
+    restore()
     graph.replay()  # warm-up replay
     torch.cuda.synchronize()
     first = float(losses[0])
-    t0 = time.perf_counter()
+    dt = 0.0
     for _ in range(replays):
-        losses.zero_()
+        restore()
+        t0 = time.perf_counter()
         graph.replay()
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / (replays * iters)
+        torch.cuda.synchronize()
+        dt += time.perf_counter() - t0
+    dt /= replays * iters
     st, _, req = rast.query(gs, ws)
     return dict(iterations=iters, views=gs.n_views, ms_per_iteration=round(dt * 1e3, 4),
                 ms_per_graph=round(dt * iters * 1e3, 3), mpixel_s=round(gs.npx / dt / 1e6, 3),
