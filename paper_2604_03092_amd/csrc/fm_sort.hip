@@ -23,7 +23,8 @@ namespace {
 __device__ __forceinline__ uint32_t count_of(const uint32_t *n_dev, uint32_t n_host) {
     return n_dev ? *n_dev : n_host;
 }
-// Entries culled or off-screen carry this key; the first depth pass drops them.
+// Entries culled or off-screen, and pairs of tiles that the support ellipse
+// misses, carry this key; the first pass of each sort drops them.
 constexpr uint32_t kNoKey = 0xFFFFFFFFu;
 // Items of the logical block handled by this workgroup: a fixed tile of
 // kSortTile consecutive items.  Each XCD gets a contiguous run of tiles, so
