@@ -238,7 +238,7 @@ __global__ __launch_bounds__(256) void k_preprocess(const ViewDesc *__restrict__
     }
 }
 
-// Zero the 16-float gradient slot of every entry that has pairs.
+// Zero the gradient slot (kGradStride floats) of every entry that has pairs.
 __global__ __launch_bounds__(256) void k_zero_grad(const uint32_t *__restrict__ cnt, float4 *__restrict__ grad,
                                                     int64_t E) {
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
