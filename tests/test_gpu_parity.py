@@ -72,13 +72,14 @@ def test_tile_shape_does_not_change_images(rast):
 
 
 # ------------------------------------------------------------------ backward
-@pytest.mark.parametrize("name,seed", [("config0", 1), ("dense", 2)])
-def test_backward_small(rast, name, seed):
+@pytest.mark.parametrize("name,seed,tile", [("config0", 1, (16, 16)), ("dense", 2, (16, 16)),
+                                           ("dense", 3, (32, 32)), ("dense", 4, (8, 8))])
+def test_backward_small(rast, name, seed, tile):
     sc = scenes.config0() if name == "config0" else scenes.random_scene(
         33, 4000, 72, 56, scale_lo=0.03, scale_hi=0.2)
-    _say(f"backward {name}")
+    _say(f"backward {name} tile={tile}")
     gs = GpuScene.from_scene(sc)
-    out, ws = rast.forward(gs)
+    out, ws = rast.forward(gs, rast.params(tile=tile))
     ref = _oracle_forward(sc)
     keep = ~ref["flags"]
     rng = np.random.default_rng(seed)
@@ -93,16 +94,17 @@ def test_backward_small(rast, name, seed):
     assert_grad_close(to_np(dvm), rdvm, f"{name}.viewmat")
 
 
-def test_fused_l1_config0(rast):
+@pytest.mark.parametrize("tile", [(16, 16), (32, 32)])
+def test_fused_l1_config0(rast, tile):
     sc = scenes.config0()
-    _say("fused l1 config0")
+    _say(f"fused l1 config0 tile={tile}")
     gs = GpuScene.from_scene(sc)
     ref = _oracle_forward(sc)
     # pixels whose L1 sign is not decided robustly are masked on both sides
     near = np.any(np.abs(ref["rgb"] - sc.target_rgb) < 5e-4, axis=0)
     keep = ~(ref["flags"] | near)
     mask = torch.from_numpy(keep.astype(np.uint8)).cuda()
-    ws = rast.workspace(gs)
+    ws = rast.workspace(gs, rast.params(tile=tile))
     out = rast.new_outputs(gs)
     grads, dvm = gs.zero_grads()
     loss = torch.zeros(1, device="cuda")
