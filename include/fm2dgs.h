@@ -364,6 +364,30 @@ fm_status fm_voxelize_fuse(fm_ctx *ctx, const fm_pixel_map *in, const fm_sim3 *p
                            const fm_fusion_params *params, const float *accum, fm_surfel_buffer out,
                            int32_t *count, void *workspace, size_t ws_bytes, void *stream);
 
+/* Workspace bytes fm_voxelize_fuse_batch needs for the n_frames maps of the
+ * HOST array maps (only their sizes are read); 0 for n_frames < 1. */
+size_t fm_fusion_batch_workspace_size(const fm_pixel_map *maps, int32_t n_frames);
+
+/* fm_voxelize_fuse over several keyframes' maps in one set of launches (a
+ * backlog of keyframes, or the frames of one fusion step).  maps, poses:
+ * HOST arrays [n_frames]; accums: HOST array [n_frames] of DEVICE gate maps
+ * (an entry may be NULL: no gate for that frame) or NULL (no gates).  The
+ * survivors of frame 0, then frame 1, ... are written to out, each frame's
+ * in fm_voxelize_fuse's order, so the result is the concatenation of
+ * per-frame calls.  offsets: DEVICE int32 [n_frames + 1]; offsets[f] is the
+ * position of frame f's first survivor and offsets[n_frames] the total,
+ * reported even when it exceeds out.capacity (primitives beyond it are not
+ * written).  Enqueued on stream; no allocation, no synchronisation;
+ * graph-capturable (the per-frame descriptors travel as kernel arguments).
+ * Errors: those of fm_voxelize_fuse for any frame, FM_ERR_INVALID_ARG for
+ * n_frames < 1, NULL arrays or offsets, or a total pixel count of 2^31 or
+ * more; FM_ERR_WORKSPACE when ws_bytes is below
+ * fm_fusion_batch_workspace_size. */
+fm_status fm_voxelize_fuse_batch(fm_ctx *ctx, const fm_pixel_map *maps, const fm_sim3 *poses, int32_t n_frames,
+                                 const fm_fusion_params *params, const float *const *accums,
+                                 fm_surfel_buffer out, int32_t *offsets, void *workspace, size_t ws_bytes,
+                                 void *stream);
+
 /* ---- loop correction of the map --------------------------------------------
  *
  * Primitives stay bound to the keyframe that created them (Sec. 3.3).  After

@@ -711,29 +711,84 @@ size_t fm_fusion_workspace_size(int32_t width, int32_t height) {
     return fm::fusion_workspace_bytes(width, height);
 }
 
-fm_status fm_voxelize_fuse(fm_ctx *ctx, const fm_pixel_map *in, const fm_sim3 *pose,
-                           const fm_fusion_params *params, const float *accum, fm_surfel_buffer out,
-                           int32_t *count, void *workspace, size_t ws_bytes, void *stream) {
-    if (!ctx) return FM_ERR_INVALID_ARG;
-    if (!in || !pose || !params || !count || !workspace)
-        return fail(ctx, FM_ERR_INVALID_ARG, "fm_voxelize_fuse: NULL map, pose, params, count or workspace");
+}  // extern "C"
+
+namespace {
+// Checks of one frame of a fusion call; the message names the entry point.
+fm_status check_frame(fm_ctx *ctx, const char *fn, const fm_pixel_map *in, const fm_sim3 *pose) {
+    const std::string f = fn;
+    if (!in || !pose) return fail(ctx, FM_ERR_INVALID_ARG, f + ": NULL map or pose");
     if (in->width < 1 || in->height < 1 || (int64_t)in->width * in->height >= ((int64_t)1 << 31))
-        return fail(ctx, FM_ERR_INVALID_ARG, "fm_voxelize_fuse: need width, height >= 1 and width*height < 2^31");
+        return fail(ctx, FM_ERR_INVALID_ARG, f + ": need width, height >= 1 and width*height < 2^31");
     if (!in->mean || !in->quat || !in->scale || !in->opacity || !in->color)
-        return fail(ctx, FM_ERR_INVALID_ARG, "fm_voxelize_fuse: NULL input plane");
+        return fail(ctx, FM_ERR_INVALID_ARG, f + ": NULL input plane");
     const double qq = (double)pose->q[0] * pose->q[0] + (double)pose->q[1] * pose->q[1] +
                       (double)pose->q[2] * pose->q[2] + (double)pose->q[3] * pose->q[3];
     if (!(pose->s > 0.f) || !std::isfinite(pose->s) || !(qq > 0.0) || !std::isfinite(qq) ||
         !std::isfinite(pose->t[0]) || !std::isfinite(pose->t[1]) || !std::isfinite(pose->t[2]))
-        return fail(ctx, FM_ERR_INVALID_ARG, "fm_voxelize_fuse: need s > 0 and a finite, non-zero pose");
+        return fail(ctx, FM_ERR_INVALID_ARG, f + ": need s > 0 and a finite, non-zero pose");
+    return FM_OK;
+}
+fm_status check_surfel_out(fm_ctx *ctx, const char *fn, const fm_surfel_buffer &out) {
     if (out.capacity < 0 ||
         (out.capacity > 0 && (!out.mean || !out.quat || !out.scale || !out.opacity || !out.color)))
-        return fail(ctx, FM_ERR_INVALID_ARG, "fm_voxelize_fuse: bad output buffer");
+        return fail(ctx, FM_ERR_INVALID_ARG, std::string(fn) + ": bad output buffer");
+    return FM_OK;
+}
+}  // namespace
+
+extern "C" {
+
+fm_status fm_voxelize_fuse(fm_ctx *ctx, const fm_pixel_map *in, const fm_sim3 *pose,
+                           const fm_fusion_params *params, const float *accum, fm_surfel_buffer out,
+                           int32_t *count, void *workspace, size_t ws_bytes, void *stream) {
+    if (!ctx) return FM_ERR_INVALID_ARG;
+    if (!params || !count || !workspace)
+        return fail(ctx, FM_ERR_INVALID_ARG, "fm_voxelize_fuse: NULL params, count or workspace");
+    fm_status s = check_frame(ctx, "fm_voxelize_fuse", in, pose);
+    if (s != FM_OK) return s;
+    s = check_surfel_out(ctx, "fm_voxelize_fuse", out);
+    if (s != FM_OK) return s;
     if (ws_bytes < fm::fusion_workspace_bytes(in->width, in->height))
         return fail(ctx, FM_ERR_WORKSPACE, "fm_voxelize_fuse: workspace too small");
-    fm_status s = use_device(ctx);
+    s = use_device(ctx);
     if (s != FM_OK) return s;
     FM_TRY_HIP(fm::launch_fusion(*in, *pose, *params, accum, out, count, workspace, (hipStream_t)stream), "fusion");
+    return FM_OK;
+}
+
+size_t fm_fusion_batch_workspace_size(const fm_pixel_map *maps, int32_t n_frames) {
+    if (!maps || n_frames < 1) return 0;
+    for (int32_t f = 0; f < n_frames; ++f)
+        if (maps[f].width < 1 || maps[f].height < 1) return 0;
+    return fm::fusion_batch_workspace_bytes(maps, n_frames);
+}
+
+fm_status fm_voxelize_fuse_batch(fm_ctx *ctx, const fm_pixel_map *maps, const fm_sim3 *poses, int32_t n_frames,
+                                 const fm_fusion_params *params, const float *const *accums,
+                                 fm_surfel_buffer out, int32_t *offsets, void *workspace, size_t ws_bytes,
+                                 void *stream) {
+    if (!ctx) return FM_ERR_INVALID_ARG;
+    if (n_frames < 1 || !maps || !poses || !params || !offsets || !workspace)
+        return fail(ctx, FM_ERR_INVALID_ARG,
+                    "fm_voxelize_fuse_batch: need n_frames >= 1 and non-NULL maps, poses, params, offsets, workspace");
+    int64_t px = 0;
+    for (int32_t f = 0; f < n_frames; ++f) {
+        fm_status s = check_frame(ctx, "fm_voxelize_fuse_batch", maps + f, poses + f);
+        if (s != FM_OK) return s;
+        px += (int64_t)maps[f].width * maps[f].height;
+    }
+    if (px >= ((int64_t)1 << 31))
+        return fail(ctx, FM_ERR_INVALID_ARG, "fm_voxelize_fuse_batch: the frames hold 2^31 pixels or more");
+    fm_status s = check_surfel_out(ctx, "fm_voxelize_fuse_batch", out);
+    if (s != FM_OK) return s;
+    if (ws_bytes < fm::fusion_batch_workspace_bytes(maps, n_frames))
+        return fail(ctx, FM_ERR_WORKSPACE, "fm_voxelize_fuse_batch: workspace too small");
+    s = use_device(ctx);
+    if (s != FM_OK) return s;
+    FM_TRY_HIP(fm::launch_fusion_batch(maps, poses, n_frames, *params, accums, out, offsets, offsets + n_frames,
+                                       workspace, (hipStream_t)stream),
+               "fusion_batch");
     return FM_OK;
 }
 

@@ -11,11 +11,14 @@
 // value is.  Survivors are mapped to world coordinates: mu_w = s R mu + t,
 // r_w = q r, scales times s.
 //
-// Three kernels: per chunk of 256 blocks the survivor counts (reads depth
-// and accumulation only), one exclusive scan of the chunk sums, and the
-// write pass (block-wide scan of the recomputed counts, then the merge and
-// the transform).  Output order: blocks in row-major order, a kept block's
-// pixels in row-major order.
+// A batch of frames runs as one set of kernels over the frames' chunks of
+// kFuseChunk blocks laid end to end: per chunk the survivor counts (reads
+// depth and accumulation only), one exclusive scan of the chunk sums (which
+// also gives each frame's first output position), and the write pass
+// (block-wide scan of the recomputed counts, then the merge and the
+// transform).  Output order: frames in order, within a frame blocks in
+// row-major order, a kept block's pixels in row-major order.  A single
+// frame is a batch of one.
 #include "fm_internal.h"
 #include "fm_wave.h"
 
@@ -87,25 +90,69 @@ __device__ __forceinline__ float block_sum(float v, float *red) {
     return s;
 }
 
-__global__ __launch_bounds__(kFuseChunk) void k_fuse_count(fm_pixel_map in, fm_fusion_params fp,
-                                                            const float *__restrict__ accum,
+struct Sim3f {
+    float s, R[9], q[4], t[3];
+};
+
+// One frame of a batch: its map, gate, similarity and first chunk.
+struct FrameDesc {
+    fm_pixel_map map;
+    const float *accum;
+    Sim3f T;
+    int32_t chunk_base;
+};
+
+constexpr int kFrameChunk = 16;  // descriptors per writer launch (kernel-argument size)
+struct FrameChunk {
+    FrameDesc d[kFrameChunk];
+    int count, first;
+};
+
+__global__ void k_write_frames(FrameChunk c, FrameDesc *out) {
+    const int i = threadIdx.x;
+    if (i < c.count) out[c.first + i] = c.d[i];
+}
+
+// The frame holding chunk c: the last frame whose chunk_base <= c.
+__device__ __forceinline__ int frame_of_chunk(const FrameDesc *fr, int nf, int c) {
+    int lo = 0, hi = nf - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (fr[mid].chunk_base <= c) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int64_t block_count_of(const fm_pixel_map &m) {
+    return (int64_t)((m.width + 1) >> 1) * ((m.height + 1) >> 1);
+}
+
+__global__ __launch_bounds__(kFuseChunk) void k_fuse_count(const FrameDesc *__restrict__ frames, int nf,
+                                                            fm_fusion_params fp,
                                                             uint32_t *__restrict__ chunk_sum) {
     __shared__ float red[kFuseChunk / 64];
-    const int64_t NB = (int64_t)((in.width + 1) >> 1) * ((in.height + 1) >> 1);
-    const int64_t b = (int64_t)blockIdx.x * kFuseChunk + threadIdx.x;
+    const FrameDesc &fr = frames[frame_of_chunk(frames, nf, (int)blockIdx.x)];
+    const fm_pixel_map &in = fr.map;
+    const int64_t NB = block_count_of(in);
+    const int64_t b = (int64_t)((int)blockIdx.x - fr.chunk_base) * kFuseChunk + threadIdx.x;
     const float *z = in.mean + 2 * (int64_t)in.width * in.height;
     int c = 0;
     if (b < NB) {
         bool merge;
         uint32_t km;
-        c = block_count(block_pixels(b, in.width, in.height), z, accum, fp.tau_depth, fp.tau_accum, merge, km);
+        c = block_count(block_pixels(b, in.width, in.height), z, fr.accum, fp.tau_depth, fp.tau_accum, merge,
+                        km);
     }
     // counts <= 4 * 1024 are exact in float
     const float s = block_sum((float)c, red);
     if (threadIdx.x == 0) chunk_sum[blockIdx.x] = (uint32_t)s;
 }
 
-__global__ __launch_bounds__(1024) void k_fuse_scan(uint32_t *__restrict__ chunk, int n, int32_t *__restrict__ count) {
+// Exclusive scan of the chunk sums in place; offsets[f] (when set) receives
+// frame f's first output position and *total the number of survivors.
+__global__ __launch_bounds__(1024) void k_fuse_scan(uint32_t *__restrict__ chunk, int n,
+                                                     const FrameDesc *__restrict__ frames, int nf,
+                                                     int32_t *__restrict__ offsets, int32_t *__restrict__ total) {
     __shared__ uint32_t part[1024];
     const int per = (n + 1023) / 1024;
     const int beg = threadIdx.x * per, end = beg + per < n ? beg + per : n;
@@ -125,7 +172,14 @@ __global__ __launch_bounds__(1024) void k_fuse_scan(uint32_t *__restrict__ chunk
         chunk[i] = run;
         run += c;
     }
-    if (threadIdx.x == 1023) *count = (int32_t)part[1023];
+    if (threadIdx.x == 1023) *total = (int32_t)part[1023];
+    if (offsets) {
+        __syncthreads();  // the scanned chunk offsets are in place
+        for (int f = threadIdx.x; f < nf; f += 1024) {
+            const int cb = frames[f].chunk_base;
+            offsets[f] = (int32_t)(cb < n ? chunk[cb] : part[1023]);
+        }
+    }
 }
 
 __device__ __forceinline__ void put(const fm_surfel_buffer &o, int64_t k, const float *mu, const float *q,
@@ -137,10 +191,6 @@ __device__ __forceinline__ void put(const fm_surfel_buffer &o, int64_t k, const 
     o.opacity[k] = op;
     o.color[k] = col[0]; o.color[C + k] = col[1]; o.color[2 * C + k] = col[2];
 }
-
-struct Sim3f {
-    float s, R[9], q[4], t[3];
-};
 
 __device__ __forceinline__ void to_world(const Sim3f &T, float *mu, float *q, float *sc) {
 #pragma clang fp contract(off)
@@ -158,16 +208,19 @@ __device__ __forceinline__ void to_world(const Sim3f &T, float *mu, float *q, fl
     sc[1] *= T.s;
 }
 
-__global__ __launch_bounds__(kFuseChunk) void k_fuse_write(fm_pixel_map in, fm_fusion_params fp, Sim3f T,
-                                                            const float *__restrict__ accum,
+__global__ __launch_bounds__(kFuseChunk) void k_fuse_write(const FrameDesc *__restrict__ frames, int nf,
+                                                            fm_fusion_params fp,
                                                             const uint32_t *__restrict__ chunk_off,
                                                             fm_surfel_buffer out) {
 #pragma clang fp contract(off)
     __shared__ uint32_t wsum[kFuseChunk / 64];
+    const FrameDesc &fr = frames[frame_of_chunk(frames, nf, (int)blockIdx.x)];
+    const fm_pixel_map &in = fr.map;
+    const float *accum = fr.accum;
     const int W = in.width, H = in.height;
     const int64_t P = (int64_t)W * H;
-    const int64_t NB = (int64_t)((W + 1) >> 1) * ((H + 1) >> 1);
-    const int64_t b = (int64_t)blockIdx.x * kFuseChunk + threadIdx.x;
+    const int64_t NB = block_count_of(in);
+    const int64_t b = (int64_t)((int)blockIdx.x - fr.chunk_base) * kFuseChunk + threadIdx.x;
     const float *z = in.mean + 2 * P;
     BlockPix bp;
     bp.n = 0;
@@ -190,6 +243,7 @@ __global__ __launch_bounds__(kFuseChunk) void k_fuse_write(fm_pixel_map in, fm_f
     uint32_t base = chunk_off[blockIdx.x] + x - (uint32_t)c;
     for (int j = 0; j < w; ++j) base += wsum[j];
     if (c == 0) return;
+    const Sim3f &T = fr.T;
     if (merge) {
         float mu[3] = {0.f, 0.f, 0.f}, sc[2] = {0.f, 0.f}, col[3] = {0.f, 0.f, 0.f}, op = 0.f;
         float q[4] = {0.f, 0.f, 0.f, 0.f};
@@ -230,20 +284,15 @@ __global__ __launch_bounds__(kFuseChunk) void k_fuse_write(fm_pixel_map in, fm_f
     }
 }
 
-}  // namespace
-
-size_t fusion_workspace_bytes(int32_t width, int32_t height) {
-    const int64_t NB = (int64_t)((width + 1) / 2) * ((height + 1) / 2);
-    return 4 * (size_t)((NB + kFuseChunk - 1) / kFuseChunk + 1);
+int64_t chunks_of(const fm_pixel_map &m) {
+    const int64_t NB = (int64_t)((m.width + 1) / 2) * ((m.height + 1) / 2);
+    return (NB + kFuseChunk - 1) / kFuseChunk;
 }
 
-hipError_t launch_fusion(const fm_pixel_map &in, const fm_sim3 &pose, const fm_fusion_params &fp,
-                         const float *accum, const fm_surfel_buffer &out, int32_t *count, void *ws,
-                         hipStream_t st) {
-    const int64_t NB = (int64_t)((in.width + 1) / 2) * ((in.height + 1) / 2);
-    const int chunks = (int)((NB + kFuseChunk - 1) / kFuseChunk);
-    uint32_t *chunk = static_cast<uint32_t *>(ws);
-    // the similarity on the host: unit quaternion and its rotation matrix
+size_t desc_bytes(int32_t n) { return ((size_t)n * sizeof(FrameDesc) + 255) & ~(size_t)255; }
+
+// the similarity on the host: unit quaternion and its rotation matrix
+Sim3f sim3_of(const fm_sim3 &pose) {
     Sim3f T;
     const double qn = std::sqrt((double)pose.q[0] * pose.q[0] + (double)pose.q[1] * pose.q[1] +
                                 (double)pose.q[2] * pose.q[2] + (double)pose.q[3] * pose.q[3]);
@@ -255,10 +304,57 @@ hipError_t launch_fusion(const fm_pixel_map &in, const fm_sim3 &pose, const fm_f
     for (int k = 0; k < 9; ++k) T.R[k] = (float)R[k];
     T.q[0] = (float)w; T.q[1] = (float)x; T.q[2] = (float)y; T.q[3] = (float)z;
     for (int k = 0; k < 3; ++k) T.t[k] = pose.t[k];
-    hipLaunchKernelGGL(k_fuse_count, dim3(chunks), dim3(kFuseChunk), 0, st, in, fp, accum, chunk);
-    hipLaunchKernelGGL(k_fuse_scan, dim3(1), dim3(1024), 0, st, chunk, chunks, count);
-    hipLaunchKernelGGL(k_fuse_write, dim3(chunks), dim3(kFuseChunk), 0, st, in, fp, T, accum, chunk, out);
+    return T;
+}
+
+}  // namespace
+
+size_t fusion_batch_workspace_bytes(const fm_pixel_map *maps, int32_t n) {
+    int64_t chunks = 0;
+    for (int32_t f = 0; f < n; ++f) chunks += chunks_of(maps[f]);
+    return desc_bytes(n) + 4 * (size_t)(chunks + 1);
+}
+
+size_t fusion_workspace_bytes(int32_t width, int32_t height) {
+    fm_pixel_map m{};
+    m.width = width;
+    m.height = height;
+    return fusion_batch_workspace_bytes(&m, 1);
+}
+
+hipError_t launch_fusion_batch(const fm_pixel_map *maps, const fm_sim3 *poses, int32_t n,
+                               const fm_fusion_params &fp, const float *const *accums, const fm_surfel_buffer &out,
+                               int32_t *offsets, int32_t *total, void *ws, hipStream_t st) {
+    FrameDesc *frames = static_cast<FrameDesc *>(ws);
+    uint32_t *chunk = reinterpret_cast<uint32_t *>(static_cast<char *>(ws) + desc_bytes(n));
+    int64_t chunks = 0;
+    FrameChunk fc;
+    fc.count = 0;
+    fc.first = 0;
+    for (int32_t f = 0; f < n; ++f) {
+        FrameDesc &d = fc.d[fc.count++];
+        d.map = maps[f];
+        d.accum = accums ? accums[f] : nullptr;
+        d.T = sim3_of(poses[f]);
+        d.chunk_base = (int32_t)chunks;
+        chunks += chunks_of(maps[f]);
+        if (fc.count == kFrameChunk || f + 1 == n) {
+            hipLaunchKernelGGL(k_write_frames, dim3(1), dim3(kFrameChunk), 0, st, fc, frames);
+            fc.first += fc.count;
+            fc.count = 0;
+        }
+    }
+    hipLaunchKernelGGL(k_fuse_count, dim3((unsigned)chunks), dim3(kFuseChunk), 0, st, frames, n, fp, chunk);
+    hipLaunchKernelGGL(k_fuse_scan, dim3(1), dim3(1024), 0, st, chunk, (int)chunks, frames, n, offsets, total);
+    hipLaunchKernelGGL(k_fuse_write, dim3((unsigned)chunks), dim3(kFuseChunk), 0, st, frames, n, fp, chunk, out);
     return hipGetLastError();
+}
+
+hipError_t launch_fusion(const fm_pixel_map &in, const fm_sim3 &pose, const fm_fusion_params &fp,
+                         const float *accum, const fm_surfel_buffer &out, int32_t *count, void *ws,
+                         hipStream_t st) {
+    const float *acc[1] = {accum};
+    return launch_fusion_batch(&in, &pose, 1, fp, acc, out, nullptr, count, ws, st);
 }
 
 }  // namespace fm

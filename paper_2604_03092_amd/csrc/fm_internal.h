@@ -204,6 +204,10 @@ hipError_t launch_preprocess_bwd(const Plan &p, void *ws, const float *intr, con
                                  float *dL_dviewmat, hipStream_t st);
 bool tile_shape_supported(int tw, int th);
 size_t fusion_workspace_bytes(int32_t width, int32_t height);
+size_t fusion_batch_workspace_bytes(const fm_pixel_map *maps, int32_t n);
+hipError_t launch_fusion_batch(const fm_pixel_map *maps, const fm_sim3 *poses, int32_t n,
+                               const fm_fusion_params &fp, const float *const *accums, const fm_surfel_buffer &out,
+                               int32_t *offsets, int32_t *total, void *ws, hipStream_t st);
 hipError_t launch_fusion(const fm_pixel_map &in, const fm_sim3 &pose, const fm_fusion_params &fp,
                          const float *accum, const fm_surfel_buffer &out, int32_t *count, void *ws,
                          hipStream_t st);

@@ -126,6 +126,9 @@ SIGNATURES = {
                                     c_void_p]),
     "fm_voxelize_fuse": (c_int32, [c_void_p, P(FmPixelMap), P(FmSim3), P(FmFusionParams), c_void_p,
                                    FmSurfelBuffer, c_void_p, c_void_p, ctypes.c_size_t, c_void_p]),
+    "fm_fusion_batch_workspace_size": (ctypes.c_size_t, [P(FmPixelMap), c_int32]),
+    "fm_voxelize_fuse_batch": (c_int32, [c_void_p, P(FmPixelMap), P(FmSim3), c_int32, P(FmFusionParams),
+                                         c_void_p, FmSurfelBuffer, c_void_p, c_void_p, ctypes.c_size_t, c_void_p]),
 }
 
 _lib = None

@@ -387,6 +387,46 @@ class Fusion:
         return self.count
 
 
+class FusionBatch:
+    """Map fusion of several per-pixel maps in one call
+    (fm_voxelize_fuse_batch): owned workspace sized for the frames' shapes
+    and output planes holding every pixel of every frame."""
+
+    def __init__(self, rast, shapes, device="cuda"):
+        self.rast = rast
+        self.shapes = [(int(w), int(h)) for (w, h) in shapes]
+        self.n = len(self.shapes)
+        self.cap = sum(w * h for (w, h) in self.shapes)
+        maps = (native.FmPixelMap * self.n)(*[native.FmPixelMap(w, h, None, None, None, None, None)
+                                              for (w, h) in self.shapes])
+        nbytes = rast.lib.fm_fusion_batch_workspace_size(maps, self.n)
+        self.ws = torch.empty(max(int(nbytes), 4), dtype=torch.uint8, device=device)
+        self.out = {k: torch.empty(CHANNELS[k], self.cap, device=device) for k in PLANES}
+        self.offsets = torch.zeros(self.n + 1, dtype=torch.int32, device=device)
+
+    def run(self, frames, tau_depth, accums=None, tau_accum=1.0, stream=None):
+        """frames: list of (planes, s, q, t) with planes a dict of device
+        [C, W*H] tensors, in the order of the shapes; accums: list of device
+        gate maps (or None entries) or None.  Returns the offsets tensor
+        (device, n + 1): frame f's survivors are out[:, offsets[f]:offsets[f+1]]."""
+        assert len(frames) == self.n
+        maps = (native.FmPixelMap * self.n)()
+        poses = (native.FmSim3 * self.n)()
+        for i, ((planes, s, q, t), (w, h)) in enumerate(zip(frames, self.shapes)):
+            maps[i] = native.FmPixelMap(w, h, *(planes[k].data_ptr() for k in PLANES))
+            poses[i] = native.FmSim3(float(s), (ctypes.c_float * 4)(*[float(x) for x in q]),
+                                     (ctypes.c_float * 3)(*[float(x) for x in t]))
+        acc = None
+        if accums is not None:
+            acc = (ctypes.c_void_p * self.n)(*[(a.data_ptr() if a is not None else None) for a in accums])
+        fp = native.FmFusionParams(float(tau_depth), float(tau_accum))
+        buf = native.FmSurfelBuffer(*(self.out[k].data_ptr() for k in PLANES), self.cap)
+        self.rast.check(self.rast.lib.fm_voxelize_fuse_batch(
+            self.rast.ctx, maps, poses, self.n, ctypes.byref(fp), acc, buf, _ptr(self.offsets), _ptr(self.ws),
+            self.ws.numel(), _stream(stream)))
+        return self.offsets
+
+
 class _RenderFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, rast, gs, params, *flat):

@@ -1,5 +1,6 @@
-"""GPU parity of map fusion (fm_voxelize_fuse through the C ABI) against the
-FP64 fusion oracle: counts and order exact, values to float32 rounding."""
+"""GPU parity of map fusion (fm_voxelize_fuse and fm_voxelize_fuse_batch through
+the C ABI) against the FP64 fusion oracle: counts and order exact, values to
+float32 rounding; a batch equals the concatenation of its frames."""
 import ctypes
 
 import numpy as np
@@ -8,7 +9,7 @@ import torch
 
 from oracle import fusion
 from paper_2604_03092_amd import native, scenes
-from paper_2604_03092_amd.raster import PLANES, Fusion, Rasterizer, _ptr
+from paper_2604_03092_amd.raster import PLANES, Fusion, FusionBatch, Rasterizer, _ptr
 
 pytestmark = pytest.mark.gpu
 
@@ -100,6 +101,70 @@ def test_fusion_capacity_and_errors(rast):
     empty = native.FmPixelMap(0, h, *(planes[k].data_ptr() for k in PLANES))
     assert rast.lib.fm_voxelize_fuse(rast.ctx, ctypes.byref(empty), ctypes.byref(pose), ctypes.byref(fp), None,
                                      buf, _ptr(count), _ptr(ws), ws.numel(), None) == native.FM_ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("tau", [0.05, -1.0])
+def test_fusion_batch_equals_frames(rast, tau):
+    """One fm_voxelize_fuse_batch over frames of mixed sizes (some gated,
+    some not) writes exactly the concatenation of the per-frame calls, and
+    its offsets delimit each frame's survivors."""
+    shapes = [(64, 48), (65, 47), (9, 7), (1, 1), (33, 21), (2, 1)]
+    frames = []
+    for i, (w, h) in enumerate(shapes):
+        if w >= 3 and h >= 3:
+            frames.append(scenes.fusion_frames(1, w, h, seed_offset=500 + i)[0])
+        else:
+            frames.append(_tiny_frame(w, h, 40 + i))
+    gates = [torch.from_numpy(f.accum).cuda() if i % 2 == 0 else None for i, f in enumerate(frames)]
+    dev = [_dev(f.planes) for f in frames]
+    print(f"fusion batch of {len(shapes)} frames tau={tau}", flush=True)
+    fb = FusionBatch(rast, shapes)
+    off = fb.run([(d, f.s, f.q, f.t) for d, f in zip(dev, frames)], tau, gates, 0.5)
+    torch.cuda.synchronize()
+    off = off.cpu().numpy()
+    assert off[0] == 0 and np.all(np.diff(off) >= 0)
+    for i, ((w, h), f, d, g) in enumerate(zip(shapes, frames, dev, gates)):
+        fu = Fusion(rast, w, h)
+        cnt = int(fu.run(d, w, h, f.s, f.q, f.t, tau, g, 0.5).item())
+        torch.cuda.synchronize()
+        assert off[i + 1] - off[i] == cnt, (i, off, cnt)
+        for k in PLANES:
+            a = fb.out[k][:, off[i]:off[i + 1]]
+            b = fu.out[k].reshape(-1, fu.cap)[:, :cnt]
+            assert torch.equal(a, b), (i, k)
+
+
+def test_fusion_batch_errors(rast):
+    w, h = 9, 7
+    f = scenes.fusion_frames(1, w, h)[0]
+    planes = _dev(f.planes)
+    maps = (native.FmPixelMap * 2)(native.FmPixelMap(w, h, *(planes[k].data_ptr() for k in PLANES)),
+                                   native.FmPixelMap(w, h, *(planes[k].data_ptr() for k in PLANES)))
+    poses = (native.FmSim3 * 2)(native.FmSim3(f.s, (ctypes.c_float * 4)(*f.q), (ctypes.c_float * 3)(*f.t)),
+                                native.FmSim3(f.s, (ctypes.c_float * 4)(*f.q), (ctypes.c_float * 3)(*f.t)))
+    fp = native.FmFusionParams(0.05, 1.0)
+    need = int(rast.lib.fm_fusion_batch_workspace_size(maps, 2))
+    assert need > 0 and int(rast.lib.fm_fusion_batch_workspace_size(maps, 0)) == 0
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    cap = 2 * w * h
+    out = {k: torch.empty(native_channels, cap, device="cuda") for k, native_channels in
+           (("mean", 3), ("quat", 4), ("scale", 2), ("opacity", 1), ("color", 3))}
+    buf = native.FmSurfelBuffer(*(out[k].data_ptr() for k in PLANES), cap)
+    offs = torch.zeros(3, dtype=torch.int32, device="cuda")
+    call = rast.lib.fm_voxelize_fuse_batch
+    assert call(rast.ctx, maps, poses, 2, ctypes.byref(fp), None, buf, _ptr(offs), _ptr(ws), need, None) == 0
+    torch.cuda.synchronize()
+    o = offs.cpu().numpy()
+    assert o[1] == o[2] - o[1] and o[2] <= cap  # the same frame twice
+    assert call(rast.ctx, maps, poses, 0, ctypes.byref(fp), None, buf, _ptr(offs), _ptr(ws), need,
+                None) == native.FM_ERR_INVALID_ARG
+    assert call(rast.ctx, maps, poses, 2, ctypes.byref(fp), None, buf, None, _ptr(ws), need,
+                None) == native.FM_ERR_INVALID_ARG
+    assert call(rast.ctx, maps, poses, 2, ctypes.byref(fp), None, buf, _ptr(offs), _ptr(ws), need - 1,
+                None) == native.FM_ERR_WORKSPACE
+    poses[1] = native.FmSim3(-1.0, (ctypes.c_float * 4)(*f.q), (ctypes.c_float * 3)(*f.t))
+    assert call(rast.ctx, maps, poses, 2, ctypes.byref(fp), None, buf, _ptr(offs), _ptr(ws), need,
+                None) == native.FM_ERR_INVALID_ARG
 
 
 def test_prune_scores_match_oracle(rast):
