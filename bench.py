@@ -111,13 +111,10 @@ def time_refine(rast, scene, params, iters, replays=3):
     ws = rast.workspace(gs, params, max_pairs=int(n_pairs * 1.5) + 4096)
     out = rast.new_outputs(gs)
     grads, dvm = gs.zero_grads()
-    adam = Adam(rast, gs, grads)
+    adam = Adam(rast, gs, grads, zero_grad=True)  # the step leaves the gradients cleared
     losses = torch.zeros(iters, device="cuda")
 
     def iteration(i):
-        for g in grads:
-            for t in g.values():
-                t.zero_()
         dvm.zero_()
         rast.fwd_bwd_l1(gs, ws, out, grads, dvm, losses[i:i + 1])
         adam.step()
@@ -134,11 +131,12 @@ def time_refine(rast, scene, params, iters, replays=3):
     init = [{k: sm[k].clone() for k in sm} for sm in gs.submaps]
 
     def restore():
-        for sm, s0, m, v in zip(gs.submaps, init, adam.m, adam.v):
+        for sm, s0, m, v, g in zip(gs.submaps, init, adam.m, adam.v, grads):
             for k in sm:
                 sm[k].copy_(s0[k])
                 m[k].zero_()
                 v[k].zero_()
+                g[k].zero_()
         adam.step_count.zero_()
         losses.zero_()
         torch.cuda.synchronize()

@@ -277,7 +277,8 @@ fm_status fm_autotune(fm_ctx *ctx, const fm_batch *batch, const fm_raster_params
 
 typedef struct {
     float *param;        /* DEVICE [n] activated values p, updated in place      */
-    const float *grad;   /* DEVICE [n] dL/dp (e.g. the fm_surfel_grads planes)    */
+    float *grad;         /* DEVICE [n] dL/dp (e.g. the fm_surfel_grads planes);   
+                            read, and cleared when the config asks for it         */
     float *m;            /* DEVICE [n] first moment of theta (zero before step 1) */
     float *v;            /* DEVICE [n] second moment of theta (zero before step 1) */
     int64_t n;           /* elements (0: the tensor is skipped)                   */
@@ -286,19 +287,22 @@ typedef struct {
 } fm_adam_tensor;
 
 typedef struct {
-    float beta1;   /* 0.9, in [0, 1)   */
-    float beta2;   /* 0.999, in [0, 1) */
-    float eps;     /* 1e-8, > 0        */
+    float beta1;         /* 0.9, in [0, 1)                                       */
+    float beta2;         /* 0.999, in [0, 1)                                     */
+    float eps;           /* 1e-8, > 0                                            */
+    int32_t zero_grad;   /* non-zero: clear each gradient element after using it,
+                            ready for the next accumulation                      */
 } fm_adam_config;
 
-/* One Adam step over count tensors (HOST array of descriptors).  step is a
+/* One Adam step over count tensors (HOST array of descriptors), all tensors
+ * in one launch (plus the counter's).  step is a
  * DEVICE int32 step counter: the call first advances it by one and every
  * update uses the advanced value t in its bias corrections, so a captured
  * graph replays consecutive steps.  The caller owns every buffer; tensors
  * must not overlap.  Enqueued on stream; no allocation, no synchronisation;
  * graph-capturable.  Errors: FM_ERR_INVALID_ARG for a NULL context, step or
- * descriptor array (count > 0), a negative count or n, NULL buffers with
- * n > 0, lr <= 0 or non-finite, an unknown kind, or betas outside [0, 1) or
+ * descriptor array (count > 0), a negative count or n, n >= 2^31, NULL
+ * buffers with n > 0, lr <= 0 or non-finite, an unknown kind, or betas outside [0, 1) or
  * eps <= 0; nothing is launched then.  FM_ERR_HIP if a launch fails. */
 fm_status fm_adam_step(fm_ctx *ctx, const fm_adam_tensor *tensors, int32_t count, const fm_adam_config *config,
                        int32_t *step, void *stream);

@@ -692,9 +692,9 @@ fm_status fm_adam_step(fm_ctx *ctx, const fm_adam_tensor *tensors, int32_t count
         return fail(ctx, FM_ERR_INVALID_ARG, "fm_adam_step: need 0 <= beta1, beta2 < 1 and eps > 0");
     for (int32_t k = 0; k < count; ++k) {
         const fm_adam_tensor &t = tensors[k];
-        if (t.n < 0 || (t.n > 0 && (!t.param || !t.grad || !t.m || !t.v)))
+        if (t.n < 0 || t.n >= ((int64_t)1 << 31) || (t.n > 0 && (!t.param || !t.grad || !t.m || !t.v)))
             return fail(ctx, FM_ERR_INVALID_ARG, "fm_adam_step: tensor " + std::to_string(k) +
-                                                     " has a negative size or a NULL buffer");
+                                                     " has a negative or too large size or a NULL buffer");
         if (!(t.lr > 0.f) || !std::isfinite(t.lr))
             return fail(ctx, FM_ERR_INVALID_ARG, "fm_adam_step: tensor " + std::to_string(k) + " needs lr > 0");
         if (t.kind != FM_PARAM_LINEAR && t.kind != FM_PARAM_LOG && t.kind != FM_PARAM_LOGIT)

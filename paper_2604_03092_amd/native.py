@@ -72,7 +72,7 @@ class FmAdamTensor(ctypes.Structure):
 
 
 class FmAdamConfig(ctypes.Structure):
-    _fields_ = [("beta1", c_float), ("beta2", c_float), ("eps", c_float)]
+    _fields_ = [("beta1", c_float), ("beta2", c_float), ("eps", c_float), ("zero_grad", c_int32)]
 
 
 class FmPixelMap(ctypes.Structure):

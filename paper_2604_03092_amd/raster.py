@@ -312,15 +312,16 @@ class Adam:
     """Fused Adam over the surfel tensors of a GpuScene (fm_adam_step): one
     moment pair per tensor and a device step counter, so a captured graph
     replays consecutive steps.  grads: the per-submap gradient dicts the
-    rasterizer accumulates into (their buffers must stay the same)."""
+    rasterizer accumulates into (their buffers must stay the same); with
+    zero_grad the step clears them for the next accumulation."""
 
-    def __init__(self, rast, gs, grads, lr=None, betas=(0.9, 0.999), eps=1e-8):
+    def __init__(self, rast, gs, grads, lr=None, betas=(0.9, 0.999), eps=1e-8, zero_grad=False):
         self.rast = rast
         self.lr = dict(ADAM_LR, **(lr or {}))
         self.m = [{k: torch.zeros_like(sm[k]) for k in PLANES} for sm in gs.submaps]
         self.v = [{k: torch.zeros_like(sm[k]) for k in PLANES} for sm in gs.submaps]
         self.step_count = torch.zeros(1, dtype=torch.int32, device=gs.intr.device)
-        self.config = native.FmAdamConfig(betas[0], betas[1], eps)
+        self.config = native.FmAdamConfig(betas[0], betas[1], eps, 1 if zero_grad else 0)
         n = len(gs.submaps) * len(PLANES)
         self.tensors = (native.FmAdamTensor * n)()
         i = 0

@@ -74,6 +74,40 @@ def test_adam_matches_oracle(rast, kind):
     assert int(step.item()) == 3
 
 
+def test_adam_many_tensors_and_zero_grad(rast):
+    """20 tensors in one call (more than one launch's table) with gradient
+    clearing: parameters and moments are bit-identical to the same step
+    without clearing, and every gradient is zero afterwards."""
+    rng = np.random.default_rng(7)
+    sizes = [int(x) for x in rng.integers(0, 3000, 20)]
+    kinds = [int(x) for x in rng.integers(0, 3, 20)]
+    runs = []
+    for zero in (0, 1):
+        dev = []
+        arr = (native.FmAdamTensor * len(sizes))()
+        r2 = np.random.default_rng(8)
+        for i, (n, k) in enumerate(zip(sizes, kinds)):
+            p = (r2.uniform(0.02, 0.98, n) if k != optim.LINEAR else r2.normal(0, 1, n)).astype(np.float32)
+            g = r2.normal(0, 1, n).astype(np.float32)
+            d = [torch.from_numpy(p).cuda() if n else torch.zeros(1, device="cuda"),
+                 torch.from_numpy(g).cuda() if n else torch.zeros(1, device="cuda"),
+                 torch.zeros(max(n, 1), device="cuda"), torch.zeros(max(n, 1), device="cuda")]
+            dev.append(d)
+            arr[i] = native.FmAdamTensor(*(t.data_ptr() for t in d), n, 0.01, k)
+        step = torch.zeros(1, dtype=torch.int32, device="cuda")
+        cfg = native.FmAdamConfig(0.9, 0.999, 1e-8, zero)
+        rast.check(rast.lib.fm_adam_step(rast.ctx, arr, len(sizes), ctypes.byref(cfg), _ptr(step), None))
+        torch.cuda.synchronize()
+        runs.append(dev)
+    for i, n in enumerate(sizes):
+        if n == 0:
+            continue
+        for j in (0, 2, 3):
+            assert torch.equal(runs[0][i][j][:n], runs[1][i][j][:n]), (i, j)
+        assert torch.count_nonzero(runs[1][i][1][:n]) == 0
+        assert torch.count_nonzero(runs[0][i][1][:n]) > 0
+
+
 def test_adam_invalid_arguments(rast):
     p = torch.zeros(4, device="cuda")
     step = torch.zeros(1, dtype=torch.int32, device="cuda")
