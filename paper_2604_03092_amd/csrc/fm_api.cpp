@@ -243,6 +243,7 @@ fm::KParams kparams(const fm_raster_params *prm, const Plan &p) {
     k.bg[0] = prm->bg[0]; k.bg[1] = prm->bg[1]; k.bg[2] = prm->bg[2];
     k.tile_w = p.tile_w;
     k.tile_h = p.tile_h;
+    k.gstride = fm::kGradSlot;
     return k;
 }
 
@@ -326,7 +327,8 @@ fm_status run_fused(fm_ctx *ctx, Built &bt, const fm_raster_params *prm, const f
     mark(ctx, st, PH_BLEND);
     FM_TRY_HIP(fm::launch_loss_reduce(bt.plan, ws, loss, st), "loss_reduce");
     mark(ctx, st, PH_LOSS);
-    FM_TRY_HIP(fm::launch_preprocess_bwd(bt.plan, ws, b->intr, b->viewmat, dL_dviewmat, st), "preprocess_bwd");
+    FM_TRY_HIP(fm::launch_preprocess_bwd(bt.plan, ws, kp.gstride, b->intr, b->viewmat, dL_dviewmat, st),
+               "preprocess_bwd");
     mark(ctx, st, PH_BWDPROJ);
     return FM_OK;
 }
@@ -525,14 +527,16 @@ fm_status fm_backward(fm_ctx *ctx, const fm_batch *b, const fm_raster_params *pr
     if (s == FM_OK) s = use_device(ctx);
     if (s != FM_OK) return s;
     hipStream_t st = (hipStream_t)stream;
-    const fm::KParams kp = kparams(prm, bt.plan);
+    fm::KParams kp = kparams(prm, bt.plan);
+    if (g.normal) kp.gstride = fm::kGradStride;  // room for the normal's gradient
     mark_begin(ctx, st);
     FM_TRY_HIP(fm::launch_setup(bt.plan, ws, bt.views.data(), bt.subs.data(), bt.vlist.data(), st), "setup");
-    FM_TRY_HIP(fm::launch_zero_grad(bt.plan, ws, st), "zero_grad");
+    FM_TRY_HIP(fm::launch_zero_grad(bt.plan, ws, kp.gstride, st), "zero_grad");
     mark(ctx, st, PH_ZERO);
     FM_TRY_HIP(fm::launch_render_bwd(bt.plan, ws, kp, out, g, st), "render_bwd");
     mark(ctx, st, PH_BLEND);
-    FM_TRY_HIP(fm::launch_preprocess_bwd(bt.plan, ws, b->intr, b->viewmat, dL_dviewmat, st), "preprocess_bwd");
+    FM_TRY_HIP(fm::launch_preprocess_bwd(bt.plan, ws, kp.gstride, b->intr, b->viewmat, dL_dviewmat, st),
+               "preprocess_bwd");
     mark(ctx, st, PH_BWDPROJ);
     return FM_OK;
 }

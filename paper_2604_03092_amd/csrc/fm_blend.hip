@@ -371,7 +371,7 @@ __device__ __forceinline__ void tile_backward(const TileCtx &c, const Slots<TW, 
             if (first) continue;  // no lane of the tile is hit by this surfel
             float r = wave_reduce16(gr);
             if (comp == 9) r *= __builtin_amdgcn_rcpf(s.sig);  // sigma dL/dsigma -> dL/dsigma
-            float *dst = grad + (int64_t)(sval[j] & kEntryMask) * kGradStride;
+            float *dst = grad + (int64_t)(sval[j] & kEntryMask) * kp.gstride;
             if (comp >= 0 && (HAS_N || comp < 14)) atomicAdd(dst + comp, r);  // 14, 15: normal terms
             if (HAS_N) {
                 const float t2 = wave_sum(gn2);

@@ -98,9 +98,13 @@ static_assert(sizeof(Ell) == 48, "ellipse layout");
 constexpr uint32_t kEntryMask = 0x0FFFFFFFu;
 constexpr int kMaskShift = 28;
 
-// Gradient slot of one entry (20 floats): dL/dc0[3], dL/dc1[3], dL/dc2[3],
-// dL/dsigma, dL/dcol[3], dL/dz, dL/dn[3], unused.
+// Gradient slot of one entry: dL/dc0[3], dL/dc1[3], dL/dc2[3], dL/dsigma,
+// dL/dcol[3], dL/dz, then dL/dn[3] when the normal map carries a gradient.
+// Slots are kGradSlot = 16 floats (64 bytes, two per 128-byte cache line:
+// zeroing and the blend's atomics touch one line per slot) when it does not
+// (the fused L1 path) and kGradStride = 20 floats when it does.
 constexpr int kGradStride = 20;
+constexpr int kGradSlot = 16;
 
 struct Status {
     uint32_t n_pairs;    // pairs actually stored (min(required, capacity))
@@ -115,6 +119,7 @@ struct KParams {
     float alpha_min, alpha_max, t_min, rho_max, near_plane;
     float bg[3];
     int32_t tile_w, tile_h;
+    int32_t gstride;  // floats per gradient slot: kGradSlot, or kGradStride with normal gradients
 };
 
 struct LossArgs {
@@ -199,8 +204,8 @@ hipError_t launch_render_bwd(const Plan &p, void *ws, const KParams &kp, const f
 hipError_t launch_render_fused(const Plan &p, void *ws, const KParams &kp, const LossArgs &la,
                                const fm_outputs &out, hipStream_t st);
 hipError_t launch_loss_reduce(const Plan &p, void *ws, float *loss, hipStream_t st);
-hipError_t launch_zero_grad(const Plan &p, void *ws, hipStream_t st);
-hipError_t launch_preprocess_bwd(const Plan &p, void *ws, const float *intr, const float *viewmat,
+hipError_t launch_zero_grad(const Plan &p, void *ws, int gstride, hipStream_t st);
+hipError_t launch_preprocess_bwd(const Plan &p, void *ws, int gstride, const float *intr, const float *viewmat,
                                  float *dL_dviewmat, hipStream_t st);
 bool tile_shape_supported(int tw, int th);
 size_t fusion_workspace_bytes(int32_t width, int32_t height);

@@ -233,19 +233,19 @@ __global__ __launch_bounds__(256) void k_preprocess(const ViewDesc *__restrict__
     cnt[e] = out_cnt;
     if (grad && out_cnt != 0) {  // the fused path clears the entry's gradient slot here
         const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll
-        for (int k = 0; k < kGradStride / 4; ++k) grad[(kGradStride / 4) * e + k] = z;
+        const int q = kp.gstride / 4;
+        for (int k = 0; k < q; ++k) grad[q * e + k] = z;
     }
 }
 
-// Zero the gradient slot (kGradStride floats) of every entry that has pairs.
+// Zero the gradient slot (gstride floats) of every entry that has pairs.
 __global__ __launch_bounds__(256) void k_zero_grad(const uint32_t *__restrict__ cnt, float4 *__restrict__ grad,
-                                                    int64_t E) {
+                                                    int64_t E, int gstride) {
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (e < E && cnt[e] != 0) {
         const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll
-        for (int k = 0; k < kGradStride / 4; ++k) grad[(kGradStride / 4) * e + k] = z;
+        const int q = gstride / 4;
+        for (int k = 0; k < q; ++k) grad[q * e + k] = z;
     }
 }
 
@@ -265,7 +265,7 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
     const SubmapDesc *__restrict__ subs, int S, const int32_t *__restrict__ vlist,
     const ViewDesc *__restrict__ views, const float *__restrict__ intr,
     const float *__restrict__ viewmat, const Rec *__restrict__ rec, const uint32_t *__restrict__ cnt,
-    const float4 *__restrict__ grad, float *__restrict__ pose_part, int max_blocks) {
+    const float4 *__restrict__ grad, int gstride, float *__restrict__ pose_part, int max_blocks) {
     const int s_idx = submap_of_block(subs, S, blockIdx.x);
     const SubmapDesc &sd = subs[s_idx];
     const int lb = blockIdx.x - sd.block_base;
@@ -308,8 +308,10 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
 #pragma unroll
         for (int j = 0; j < 16; ++j) dV[j] = 0.f;
         if (live && cnt[e] != 0) {
-            const float4 *gp = grad + (kGradStride / 4) * e;
-            const float4 g0 = gp[0], g1 = gp[1], g2 = gp[2], g3 = gp[3], g4 = gp[4];
+            const float4 *gp = grad + (gstride / 4) * e;
+            // without normal gradients the slot ends after component 15
+            const float4 g4 = gstride > kGradSlot ? gp[4] : make_float4(0.f, 0.f, 0.f, 0.f);
+            const float4 g0 = gp[0], g1 = gp[1], g2 = gp[2], g3 = gp[3];
             const float g[20] = {g0.x, g0.y, g0.z, g0.w, g1.x, g1.y, g1.z, g1.w, g2.x, g2.y,
                                  g2.z, g2.w, g3.x, g3.y, g3.z, g3.w, g4.x, g4.y, g4.z, g4.w};
             const Rec &rc = rec[e];
@@ -498,22 +500,22 @@ hipError_t launch_preprocess(const Plan &p, void *ws, const KParams &kp, const f
     return hipGetLastError();
 }
 
-hipError_t launch_zero_grad(const Plan &p, void *ws, hipStream_t st) {
+hipError_t launch_zero_grad(const Plan &p, void *ws, int gstride, hipStream_t st) {
     const int blocks = (int)((p.E + 255) / 256);
     if (blocks == 0) return hipSuccess;
     hipLaunchKernelGGL(k_zero_grad, dim3(blocks), dim3(256), 0, st, at<uint32_t>(ws, p.o_cnt),
-                       at<float4>(ws, p.o_grad), p.E);
+                       at<float4>(ws, p.o_grad), p.E, gstride);
     return hipGetLastError();
 }
 
-hipError_t launch_preprocess_bwd(const Plan &p, void *ws, const float *intr, const float *viewmat,
+hipError_t launch_preprocess_bwd(const Plan &p, void *ws, int gstride, const float *intr, const float *viewmat,
                                  float *dL_dviewmat, hipStream_t st) {
     if (p.a7_blocks > 0) {
         hipLaunchKernelGGL(k_preprocess_bwd, dim3(p.a7_blocks), dim3(256), 0, st,
                            at<SubmapDesc>(ws, p.o_subs), p.S, at<int32_t>(ws, p.o_vlist),
                            at<ViewDesc>(ws, p.o_views), intr, viewmat, at<Rec>(ws, p.o_rec),
-                           at<uint32_t>(ws, p.o_cnt), at<float4>(ws, p.o_grad), at<float>(ws, p.o_pose),
-                           p.a7_max_blocks);
+                           at<uint32_t>(ws, p.o_cnt), at<float4>(ws, p.o_grad), gstride,
+                           at<float>(ws, p.o_pose), p.a7_max_blocks);
     }
     if (dL_dviewmat) {
         hipLaunchKernelGGL(k_pose_reduce, dim3(p.V), dim3(1024), 0, st, at<ViewDesc>(ws, p.o_views),
