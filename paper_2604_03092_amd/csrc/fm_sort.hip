@@ -352,12 +352,13 @@ __global__ __launch_bounds__(1024) void k_count_scan(const uint32_t *__restrict_
 // band edges and of the leftmost/rightmost points when they fall inside the
 // band; it is widened by 0.01 px, which covers the FP32 rounding here
 // (hardware square root and reciprocal, 1 ulp).
-__device__ inline uint32_t block_mask(const Ell &el, int x0, int y0, int tw, int th) {
+template <int TW, int TH> __device__ inline uint32_t block_mask(const Ell &el, int x0, int y0) {
     const float hy2 = el.hy * el.hy;
-    const int bs = (tw == 32 && th == 32) ? 16 : 8;
-    const int bw = tw / bs, bh = th / bs;
-    const float span = (float)bs - 0.5f;
+    constexpr int bs = (TW == 32 && TH == 32) ? 16 : 8;
+    constexpr int bw = TW / bs, bh = TH / bs;
+    constexpr float span = (float)bs - 0.5f;
     uint32_t mask = 0;
+#pragma unroll
     for (int br = 0; br < bh; ++br) {
         float dy0 = (float)(y0 + bs * br) + 0.5f - el.ey - 0.01f;
         float dy1 = (float)(y0 + bs * br) + span - el.ey + 0.01f;
@@ -372,6 +373,7 @@ __device__ inline uint32_t block_mask(const Ell &el, int x0, int y0, int tw, int
         if (-el.dyr >= dy0 && -el.dyr <= dy1) xmin = -el.hx;
         xmax += el.ex + 0.01f;
         xmin += el.ex - 0.01f;
+#pragma unroll
         for (int bc = 0; bc < bw; ++bc) {
             const float bx0 = (float)(x0 + bs * bc) + 0.5f, bx1 = (float)(x0 + bs * bc) + span;
             if (xmax >= bx0 && xmin <= bx1) mask |= 1u << (br * bw + bc);
@@ -443,6 +445,7 @@ __device__ __forceinline__ uint32_t wave_incl_max_u32(uint32_t x, int lane) {
     return x;
 }
 
+template <int TW, int TH>
 __global__ __launch_bounds__(256) void k_emit(const uint32_t *__restrict__ sorted_entry,
                                                const uint32_t *__restrict__ off32, const uint32_t *n_vis,
                                                const uint32_t *__restrict__ chunk_first, const Status *st,
@@ -522,7 +525,7 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t *__restrict__ sorte
                 else if ((ry + 1u) * ntx <= r) ++ry;
                 const uint32_t rx = r - ry * ntx;
                 const int tx = (int)(el.t0 & 0xFFFFu) + (int)rx, ty = (int)(el.t0 >> 16) + (int)ry;
-                const uint32_t mask = block_mask(el, tx * kp.tile_w, ty * kp.tile_h, kp.tile_w, kp.tile_h);
+                const uint32_t mask = block_mask<TW, TH>(el, tx * TW, ty * TH);
                 // a tile of the rect that no block of reaches carries no pair: its
                 // key drops it in the first tile-sort pass
                 const uint32_t key = el.tb + ry * tiles_x + rx;
@@ -604,8 +607,16 @@ hipError_t launch_binning(const Plan &p, void *ws, const KParams &kp, hipStream_
     uint32_t *chunk_first = at<uint32_t>(ws, p.o_chunk);
     hipLaunchKernelGGL(k_offsets, dim3(p.scan_blocks), dim3(256), 0, st, cnt_sorted, n_vis, blk_off,
                        (uint64_t)p.cap, off32, chunk_first);
-    hipLaunchKernelGGL(k_emit, dim3(p.emit_blocks), dim3(256), 0, st, val, off32, n_vis, chunk_first, status,
-                       at<Ell>(ws, p.o_ell), kp, pkey, pval, hist, p.sortG_p);
+#define FM_EMIT(TW, TH)                                                                                        \
+    hipLaunchKernelGGL((k_emit<TW, TH>), dim3(p.emit_blocks), dim3(256), 0, st, val, off32, n_vis, chunk_first,   \
+                       status, at<Ell>(ws, p.o_ell), kp, pkey, pval, hist, p.sortG_p)
+    if (p.tile_w == 16 && p.tile_h == 16) FM_EMIT(16, 16);
+    else if (p.tile_w == 8 && p.tile_h == 8) FM_EMIT(8, 8);
+    else if (p.tile_w == 16 && p.tile_h == 8) FM_EMIT(16, 8);
+    else if (p.tile_w == 32 && p.tile_h == 8) FM_EMIT(32, 8);
+    else if (p.tile_w == 32 && p.tile_h == 32) FM_EMIT(32, 32);
+    else return hipErrorInvalidValue;
+#undef FM_EMIT
     // 3. stable sort of the pairs by tile id; the last pass also writes the
     //    per-tile ranges
     uint32_t *ts = at<uint32_t>(ws, p.o_tstart), *te = at<uint32_t>(ws, p.o_tend);
