@@ -202,6 +202,45 @@ def time_fusion(rast, n_frames=32, w=518, h=392, tau_depth=0.05, tau_accum=0.5, 
                 hbm=dict(bytes=alg, gbs=round(alg / dt / 1e9, 1), frac=round(alg / dt / 1e9 / HBM_PEAK_GBS, 4)))
 
 
+def time_warp(rast, n=2_000_000, n_keyframes=64, replays=50):
+    """Loop-correction warp (fm_warp_keyframes) of n keyframe-bound primitives
+    by per-keyframe similarities: one launch, timed with events over replays."""
+    import ctypes
+    import numpy as np
+    import torch
+    from paper_2604_03092_amd import native
+    from paper_2604_03092_amd.raster import _ptr
+    rng = np.random.Generator(np.random.PCG64(30920 + 77))
+    q = rng.normal(size=(4, n))
+    mean = torch.from_numpy(rng.normal(0, 3, (3, n)).astype(np.float32)).cuda()
+    quat = torch.from_numpy((q / np.linalg.norm(q, axis=0)).astype(np.float32)).cuda()
+    scale = torch.from_numpy(rng.uniform(0.01, 0.1, (2, n)).astype(np.float32)).cuda()
+    kf = torch.from_numpy(rng.integers(0, n_keyframes, n).astype(np.int32)).cuda()
+    arr = (native.FmSim3 * n_keyframes)()
+    for k in range(n_keyframes):
+        # near-identity moves keep repeated replays bounded
+        qq = np.array([1.0, *rng.normal(0, 1e-3, 3)])
+        arr[k] = native.FmSim3(1.0, (ctypes.c_float * 4)(*qq), (ctypes.c_float * 3)(*rng.normal(0, 1e-3, 3)))
+    deltas = torch.frombuffer(bytearray(bytes(arr)), dtype=torch.uint8).cuda()
+
+    def run():
+        rast.check(rast.lib.fm_warp_keyframes(rast.ctx, _ptr(mean), _ptr(quat), _ptr(scale), _ptr(kf), n,
+                                              _ptr(deltas), n_keyframes, None))
+
+    run()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(replays):
+        run()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / replays
+    alg = n * (9 * 4 * 2 + 4)  # mean, quat, scale read and written, keyframe id read
+    return dict(primitives=n, keyframes=n_keyframes, ms=round(ms, 4),
+                hbm=dict(bytes=alg, gbs=round(alg / ms / 1e6, 1), frac=round(alg / ms / 1e6 / HBM_PEAK_GBS, 4)))
+
+
 def time_config(rast, name, steps):
     """Fused forward + L1 + backward of one config's whole batch, eager calls,
     in Mpixel/s (setup and pair-buffer sizing untimed)."""
@@ -256,7 +295,7 @@ def main():
     ap.add_argument("--cpu-views", type=int, default=8, help="views in the CPU-baseline sample")
     ap.add_argument("--refine-iters", type=int, default=20,
                     help="iterations of the captured refine loop (render loss + Adam), 0 to skip")
-    ap.add_argument("--no-fusion", action="store_true", help="skip the map-fusion measurement")
+    ap.add_argument("--no-fusion", action="store_true", help="skip the map-fusion and warp measurements")
     ap.add_argument("--all-configs", action="store_true",
                     help="also time the fused step on configs 0-4 (reported under per_config)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -432,6 +471,11 @@ def main():
         fusion = time_fusion(rast)
         log(f"fusion: {fusion['ms_per_batch']:.3f} ms for {fusion['frames']} frames, {fusion['mpixel_s']:.0f} Mpixel/s")
 
+    warp = None
+    if not args.no_fusion:
+        warp = time_warp(rast)
+        log(f"warp: {warp['ms']:.3f} ms for {warp['primitives']} primitives, {warp['hbm']['gbs']:.0f} GB/s")
+
     per_config = None
     if args.all_configs:
         per_config = {}
@@ -472,6 +516,7 @@ def main():
         "cpu_baseline": cpu,
         "refine": refine,
         "fusion": fusion,
+        "warp": warp,
     }
     if per_config is not None:
         res["per_config"] = per_config
