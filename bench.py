@@ -289,6 +289,8 @@ def main():
     ap.add_argument("--workload", default="headline")
     ap.add_argument("--tile", default="16x16")
     ap.add_argument("--no-graph", action="store_true", help="time eager calls instead of a graph replay")
+    ap.add_argument("--deterministic", action="store_true",
+                    help="bitwise reproducible gradients (per-pair partials summed in a fixed order)")
     ap.add_argument("--no-plain", action="store_true", help="skip the per-view plain comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
@@ -327,7 +329,7 @@ def main():
     gs = GpuScene.from_scene(scene)
     rast = Rasterizer()
     tw, th = (int(x) for x in args.tile.split("x"))
-    params = rast.params(tile=(tw, th))
+    params = rast.params(tile=(tw, th), deterministic=args.deterministic)
 
     # size the pair buffer from one eager forward (not timed)
     out, ws = rast.forward(gs, params)
@@ -505,6 +507,7 @@ def main():
         "config": {"workload": scene.name, "views": gs.n_views, "pixels_per_step": gs.npx,
                    "surfels": int(sum(sm["opacity"].shape[0] for sm in scene.submaps)),
                    "tile": f"{tw}x{th}", "mode": "hipgraph" if graph is not None else "eager",
+                   "deterministic": bool(args.deterministic),
                    "pairs": n_pairs},
         "views_per_s": round(views_s, 3),
         "plain": plain,

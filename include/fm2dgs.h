@@ -127,7 +127,18 @@ typedef struct {
     int32_t tile_h;    /* (rendered as four 16x16 quadrants sharing one list);
                           0x0 uses the context's autotuned choice for the batch,
                           else 16x16                                            */
-    int32_t reserved[2];
+    int32_t deterministic;  /* 0: per-entry gradients are summed with float atomics in
+                               the order tiles finish (equal between runs up to
+                               rounding).  1: every (pair, wave) writes its own
+                               partial and each entry sums its partials in emission
+                               order, so gradients, the pose gradient and the loss are
+                               bitwise reproducible; the workspace grows by
+                               4 + 80 * w bytes per pair of capacity (w = 4 waves per
+                               tile for 32x32, else 1) and a step costs one clear and
+                               one reduction pass over those partials.  Forward,
+                               backward and fwd_bwd calls on one workspace must agree
+                               on it.  Other values are INVALID_ARG.               */
+    int32_t reserved;       /* must be 0 */
 } fm_raster_params;
 
 /* Output planes (device, float32): rgb[3][P], depth[P], normal[3][P],

@@ -121,6 +121,10 @@ fm_status build(fm_ctx *ctx, const fm_batch *b, const fm_raster_params *prm, int
     p.tile_w = tw;
     p.tile_h = th;
     p.cap = max_pairs;
+    if ((prm->deterministic != 0 && prm->deterministic != 1) || prm->reserved != 0)
+        return fail(ctx, FM_ERR_INVALID_ARG, "deterministic must be 0 or 1 and reserved 0");
+    p.det = prm->deterministic == 1;
+    p.nq = (tw == 32 && th == 32) ? 4 : 1;
     for (int i = 0; i < p.S; ++i) {
         const fm_surfels &sm = b->submaps[i];
         if (sm.n < 0 || sm.n > (1 << 28))
@@ -229,6 +233,10 @@ fm_status build(fm_ctx *ctx, const fm_batch *b, const fm_raster_params *prm, int
     p.o_loss = take(4 * (size_t)T * 16);
     p.o_tot = take(4 * (size_t)fm::kRadix * fm::kMaxPasses);
     p.o_chunk = take(4 * (size_t)((max_pairs + fm::kEmitChunk - 1) / fm::kEmitChunk + 1));
+    if (p.det) {  // per pair: its value, and one partial gradient slot per wave of the tile
+        p.o_meta = take(4 * (size_t)max_pairs);
+        p.o_part = take(4 * (size_t)fm::kGradStride * p.nq * (size_t)max_pairs);
+    }
     p.bytes = o;
     return FM_OK;
 }
@@ -244,6 +252,7 @@ fm::KParams kparams(const fm_raster_params *prm, const Plan &p) {
     k.tile_w = p.tile_w;
     k.tile_h = p.tile_h;
     k.gstride = fm::kGradSlot;
+    k.pair_cap = (uint32_t)p.cap;
     return k;
 }
 
@@ -322,8 +331,10 @@ fm_status run_fused(fm_ctx *ctx, Built &bt, const fm_raster_params *prm, const f
     FM_TRY_HIP(fm::launch_preprocess(bt.plan, ws, kp, b->intr, b->viewmat, true, st), "preprocess");
     mark(ctx, st, PH_PRE);
     FM_TRY_HIP(fm::launch_binning(bt.plan, ws, kp, st), "binning");
+    if (bt.plan.det) FM_TRY_HIP(fm::launch_det_clear(bt.plan, ws, kp.gstride, st), "det_clear");
     mark(ctx, st, PH_BIN);
     FM_TRY_HIP(fm::launch_render_fused(bt.plan, ws, kp, la, out, st), "render_fused");
+    if (bt.plan.det) FM_TRY_HIP(fm::launch_det_reduce(bt.plan, ws, kp.gstride, st), "det_reduce");
     mark(ctx, st, PH_BLEND);
     FM_TRY_HIP(fm::launch_loss_reduce(bt.plan, ws, loss, st), "loss_reduce");
     mark(ctx, st, PH_LOSS);
@@ -532,8 +543,10 @@ fm_status fm_backward(fm_ctx *ctx, const fm_batch *b, const fm_raster_params *pr
     mark_begin(ctx, st);
     FM_TRY_HIP(fm::launch_setup(bt.plan, ws, bt.views.data(), bt.subs.data(), bt.vlist.data(), st), "setup");
     FM_TRY_HIP(fm::launch_zero_grad(bt.plan, ws, kp.gstride, st), "zero_grad");
+    if (bt.plan.det) FM_TRY_HIP(fm::launch_det_clear(bt.plan, ws, kp.gstride, st), "det_clear");
     mark(ctx, st, PH_ZERO);
     FM_TRY_HIP(fm::launch_render_bwd(bt.plan, ws, kp, out, g, st), "render_bwd");
+    if (bt.plan.det) FM_TRY_HIP(fm::launch_det_reduce(bt.plan, ws, kp.gstride, st), "det_reduce");
     mark(ctx, st, PH_BLEND);
     FM_TRY_HIP(fm::launch_preprocess_bwd(bt.plan, ws, kp.gstride, b->intr, b->viewmat, dL_dviewmat, st),
                "preprocess_bwd");
@@ -600,6 +613,12 @@ fm_status fm_debug_pairs(fm_ctx *ctx, const fm_batch *b, const fm_raster_params 
                    "hipMemcpy(pairs)");
         FM_TRY_HIP(hipMemcpy(e.data(), w + (p.pairs_in_alt ? p.o_pval2 : p.o_pval), 4 * m, hipMemcpyDeviceToHost),
                    "hipMemcpy(pairs)");
+        if (p.det && st.n_pairs > 0) {  // the list holds emission indices
+            std::vector<uint32_t> meta(st.n_pairs);
+            FM_TRY_HIP(hipMemcpy(meta.data(), w + p.o_meta, 4 * (size_t)st.n_pairs, hipMemcpyDeviceToHost),
+                       "hipMemcpy(pairs)");
+            for (int64_t i = 0; i < m; ++i) e[i] = e[i] < st.n_pairs ? meta[e[i]] : 0u;
+        }
         for (int64_t i = 0; i < m; ++i) {
             int lo = 0, hi = p.V - 1;
             while (lo < hi) {

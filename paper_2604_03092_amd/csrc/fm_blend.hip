@@ -20,6 +20,8 @@
 // added into the entry's gradient slot with one coalesced 16-float atomic
 // group (plus one for the last normal component when normals carry a
 // gradient).
+#include <algorithm>
+
 #include "fm_internal.h"
 #include "fm_wave.h"
 
@@ -102,6 +104,15 @@ template <int TW, int TH> struct Geo {
     static constexpr int NB = BW * BH;  // pixel slots per lane
 };
 
+// Deterministic-gradient side of a pair list (meta == nullptr otherwise):
+// meta[emission index] = the pair's value, cap = pair capacity, part = the
+// partial gradient slots, one per (emission index, wave of the tile).
+struct PairMeta {
+    const uint32_t *meta;
+    uint32_t cap;
+    float *part;
+};
+
 struct TileCtx {
     int view, W, H;
     int64_t pix_base;      // first pixel of the view in the output planes
@@ -153,14 +164,20 @@ __device__ __forceinline__ TileCtx tile_ctx(const ViewDesc *views, int V, const 
 // Stage up to 64 pairs of the tile list into LDS (one per lane).  Entries out
 // of range (impossible for emitted pairs) get an empty block mask.  In a
 // quadrant wave (QUAD) the pair's quadrant bit becomes a mask of all slots.
+// Deterministic lists (meta non-null) hold emission indices: the index goes
+// to sj and meta gives the pair's value.
 template <bool QUAD>
 __device__ __forceinline__ int stage(const TileCtx &c, uint32_t base, uint32_t end,
                                      const uint32_t *__restrict__ pval, const Rec *__restrict__ rec,
-                                     Rec *srec, uint32_t *sval) {
+                                     Rec *srec, uint32_t *sval, const PairMeta &pm, uint32_t *sj) {
     const int cntb = (int)min(64u, end - base);
     __syncthreads();
     if ((int)threadIdx.x < cntb) {
         uint32_t pv = pval[base + threadIdx.x];
+        if (pm.meta) {
+            sj[threadIdx.x] = pv;
+            pv = pv < pm.cap ? pm.meta[pv] : 0u;  // (an index past the capacity cannot occur)
+        }
         const bool ok = (pv & kEntryMask) < c.n_entries;
         if (QUAD) pv = (pv & kEntryMask) | (((pv >> (kMaskShift + c.quad)) & 1u) ? (0xFu << kMaskShift) : 0u);
         sval[threadIdx.x] = ok ? pv : 0u;
@@ -191,6 +208,7 @@ template <int TW, int TH, bool COUNT>
 __device__ __forceinline__ void tile_forward(const TileCtx &c, const Slots<TW, TH> &sl,
                                              const uint32_t *__restrict__ pval, const Rec *__restrict__ rec,
                                              const KParams &kp, Rec *srec, uint32_t *sval,
+                                             const PairMeta &pm, uint32_t *sj,
                                              float (&acc)[Geo<TW, TH>::NB][8], float (&T)[Geo<TW, TH>::NB],
                                              uint32_t (&slast)[Geo<TW, TH>::NB],
                                              uint32_t (&ncount)[Geo<TW, TH>::NB]) {
@@ -212,7 +230,7 @@ __device__ __forceinline__ void tile_forward(const TileCtx &c, const Slots<TW, T
         if (ballot64(sl.inside[q]) != 0) live |= 1u << q;
     }
     for (uint32_t base = c.start; base < c.end && live != 0; base += 64) {
-        const int cntb = stage<Gm::QUAD>(c, base, c.end, pval, rec, srec, sval);
+        const int cntb = stage<Gm::QUAD>(c, base, c.end, pval, rec, srec, sval, pm, sj);
         for (int j = 0; j < cntb; ++j) {
             const uint32_t m = (__builtin_amdgcn_readfirstlane(sval[j]) >> kMaskShift) & live;
             if (m != 0) {
@@ -312,10 +330,11 @@ __device__ __forceinline__ void adjoint_terms(const Hit &h, const Surf &s, const
 // recomputed T repeats the forward's exactly, so a pixel still has
 // contributions ahead exactly while T > Tf.  HAS_N: the normal map carries a
 // gradient.
-template <int TW, int TH, bool HAS_N>
+template <int TW, int TH, bool HAS_N, bool DET>
 __device__ __forceinline__ void tile_backward(const TileCtx &c, const Slots<TW, TH> &sl,
                                               const uint32_t *__restrict__ pval, const Rec *__restrict__ rec,
                                               const KParams &kp, Rec *srec, uint32_t *sval,
+                                              const PairMeta &pm, uint32_t *sj,
                                               const float (&g)[Geo<TW, TH>::NB][8], const float (&S)[Geo<TW, TH>::NB],
                                               const float (&Tf)[Geo<TW, TH>::NB],
                                               const uint32_t (&bound)[Geo<TW, TH>::NB], float *__restrict__ grad) {
@@ -336,7 +355,7 @@ __device__ __forceinline__ void tile_backward(const TileCtx &c, const Slots<TW, 
     const uint32_t end = c.start + (maxlast < len ? maxlast : len);
     const int comp = wave_reduce16_component();
     for (uint32_t base = c.start; base < end; base += 64) {
-        const int cntb = stage<Gm::QUAD>(c, base, end, pval, rec, srec, sval);
+        const int cntb = stage<Gm::QUAD>(c, base, end, pval, rec, srec, sval, pm, sj);
         const uint32_t kbase = base - c.start;
         for (int j = 0; j < cntb; ++j) {
             const uint32_t k = kbase + (uint32_t)j;
@@ -371,11 +390,20 @@ __device__ __forceinline__ void tile_backward(const TileCtx &c, const Slots<TW, 
             if (first) continue;  // no lane of the tile is hit by this surfel
             float r = wave_reduce16(gr);
             if (comp == 9) r *= __builtin_amdgcn_rcpf(s.sig);  // sigma dL/dsigma -> dL/dsigma
-            float *dst = grad + (int64_t)(sval[j] & kEntryMask) * kp.gstride;
-            if (comp >= 0 && (HAS_N || comp < 14)) atomicAdd(dst + comp, r);  // 14, 15: normal terms
-            if (HAS_N) {
-                const float t2 = wave_sum(gn2);
-                if (lane_id() == 0) atomicAdd(dst + 16, t2);
+            if (DET) {  // this wave's own partial slot of the pair (cleared beforehand)
+                float *dst = pm.part + ((int64_t)sj[j] * Gm::NQ + c.quad) * kp.gstride;
+                if (comp >= 0 && (HAS_N || comp < 14)) dst[comp] = r;
+                if (HAS_N) {
+                    const float t2 = wave_sum(gn2);
+                    if (lane_id() == 0) dst[16] = t2;
+                }
+            } else {
+                float *dst = grad + (int64_t)(sval[j] & kEntryMask) * kp.gstride;
+                if (comp >= 0 && (HAS_N || comp < 14)) atomicAdd(dst + comp, r);  // 14, 15: normal terms
+                if (HAS_N) {
+                    const float t2 = wave_sum(gn2);
+                    if (lane_id() == 0) atomicAdd(dst + 16, t2);
+                }
             }
         }
     }
@@ -388,15 +416,15 @@ __global__ __launch_bounds__(64) void k_render_fwd(const ViewDesc *__restrict__ 
                                                     const uint32_t *__restrict__ pval, const Rec *__restrict__ rec,
                                                     KParams kp, int64_t NPX, fm_outputs out,
                                                     float *__restrict__ tfinal, uint32_t *__restrict__ nlast_out,
-                                                    uint32_t *__restrict__ ncount_out) {
+                                                    uint32_t *__restrict__ ncount_out, PairMeta pm) {
     using Gm = Geo<TW, TH>;
     __shared__ Rec srec[64];
-    __shared__ uint32_t sval[64];
+    __shared__ uint32_t sval[64], sj[64];
     Slots<TW, TH> sl;
     const TileCtx c = tile_ctx<TW, TH>(views, V, ts, te, sl);
     float acc[Gm::NB][8], T[Gm::NB];
     uint32_t slast[Gm::NB], nc[Gm::NB];
-    tile_forward<TW, TH, true>(c, sl, pval, rec, kp, srec, sval, acc, T, slast, nc);
+    tile_forward<TW, TH, true>(c, sl, pval, rec, kp, srec, sval, pm, sj, acc, T, slast, nc);
 #pragma unroll
     for (int q = 0; q < Gm::NB; ++q) {
         if (!sl.inside[q]) continue;
@@ -415,16 +443,17 @@ __global__ __launch_bounds__(64) void k_render_fwd(const ViewDesc *__restrict__ 
     }
 }
 
-template <int TW, int TH, bool HAS_N>
+template <int TW, int TH, bool HAS_N, bool DET>
 __global__ __launch_bounds__(64) void k_render_bwd(const ViewDesc *__restrict__ views, int V,
                                                     const uint32_t *__restrict__ ts, const uint32_t *__restrict__ te,
                                                     const uint32_t *__restrict__ pval, const Rec *__restrict__ rec,
                                                     KParams kp, int64_t NPX, fm_outputs out, fm_grad_outputs gout,
                                                     const float *__restrict__ tfinal,
-                                                    const uint32_t *__restrict__ nlast_in, float *__restrict__ grad) {
+                                                    const uint32_t *__restrict__ nlast_in, float *__restrict__ grad,
+                                                    PairMeta pm) {
     using Gm = Geo<TW, TH>;
     __shared__ Rec srec[64];
-    __shared__ uint32_t sval[64];
+    __shared__ uint32_t sval[64], sj[64];
     Slots<TW, TH> sl;
     const TileCtx c = tile_ctx<TW, TH>(views, V, ts, te, sl);
     float g[Gm::NB][8], S[Gm::NB], Tf[Gm::NB];
@@ -454,24 +483,25 @@ __global__ __launch_bounds__(64) void k_render_bwd(const ViewDesc *__restrict__ 
                 S[q] += g[q][4] * out.normal[p] + g[q][5] * out.normal[NPX + p] + g[q][6] * out.normal[2 * NPX + p];
         }
     }
-    tile_backward<TW, TH, HAS_N>(c, sl, pval, rec, kp, srec, sval, g, S, Tf, bound, grad);
+    tile_backward<TW, TH, HAS_N, DET>(c, sl, pval, rec, kp, srec, sval, pm, sj, g, S, Tf, bound, grad);
 }
 
-template <int TW, int TH>
+template <int TW, int TH, bool DET>
 __global__ __launch_bounds__(64) void k_render_fused(const ViewDesc *__restrict__ views, int V,
                                                       const uint32_t *__restrict__ ts, const uint32_t *__restrict__ te,
                                                       const uint32_t *__restrict__ pval, const Rec *__restrict__ rec,
                                                       KParams kp, int64_t NPX, fm_outputs out, LossArgs la,
                                                       float *__restrict__ tfinal, uint32_t *__restrict__ nlast_out,
-                                                      float *__restrict__ grad, float *__restrict__ loss_part) {
+                                                      float *__restrict__ grad, float *__restrict__ loss_part,
+                                                      PairMeta pm) {
     using Gm = Geo<TW, TH>;
     __shared__ Rec srec[64];
-    __shared__ uint32_t sval[64];
+    __shared__ uint32_t sval[64], sj[64];
     Slots<TW, TH> sl;
     const TileCtx c = tile_ctx<TW, TH>(views, V, ts, te, sl);
     float acc[Gm::NB][8], T[Gm::NB];
     uint32_t slast[Gm::NB], nc[Gm::NB];
-    tile_forward<TW, TH, false>(c, sl, pval, rec, kp, srec, sval, acc, T, slast, nc);
+    tile_forward<TW, TH, false>(c, sl, pval, rec, kp, srec, sval, pm, sj, acc, T, slast, nc);
     float g[Gm::NB][8], S[Gm::NB], Tf[Gm::NB];
     float l = 0.f;
     const float npx = (float)c.W * (float)c.H;
@@ -516,7 +546,7 @@ __global__ __launch_bounds__(64) void k_render_fused(const ViewDesc *__restrict_
     }
     const float lsum = wave_sum(l);
     if (threadIdx.x == 0) loss_part[blockIdx.x] = lsum;
-    tile_backward<TW, TH, false>(c, sl, pval, rec, kp, srec, sval, g, S, Tf, slast, grad);
+    tile_backward<TW, TH, false, DET>(c, sl, pval, rec, kp, srec, sval, pm, sj, g, S, Tf, slast, grad);
 }
 
 __global__ __launch_bounds__(1024) void k_loss_reduce(const float *__restrict__ part, int64_t n,
@@ -534,43 +564,124 @@ __global__ __launch_bounds__(1024) void k_loss_reduce(const float *__restrict__ 
     }
 }
 
+PairMeta pair_meta(const Plan &p, void *ws) {
+    PairMeta pm;
+    pm.meta = p.det ? at<uint32_t>(ws, p.o_meta) : nullptr;
+    pm.cap = (uint32_t)p.cap;
+    pm.part = p.det ? at<float>(ws, p.o_part) : nullptr;
+    return pm;
+}
+
 template <int TW, int TH>
 hipError_t fwd_t(const Plan &p, void *ws, const KParams &kp, const fm_outputs &out, hipStream_t st) {
     const uint32_t *pval = at<uint32_t>(ws, p.pairs_in_alt ? p.o_pval2 : p.o_pval);
     hipLaunchKernelGGL((k_render_fwd<TW, TH>), dim3((unsigned)(p.T * Geo<TW, TH>::NQ)), dim3(64), 0, st,
                        at<ViewDesc>(ws, p.o_views), p.V, at<uint32_t>(ws, p.o_tstart),
                        at<uint32_t>(ws, p.o_tend), pval, at<Rec>(ws, p.o_rec), kp, p.NPX, out,
-                       at<float>(ws, p.o_tfinal), at<uint32_t>(ws, p.o_nlast), at<uint32_t>(ws, p.o_ncount));
+                       at<float>(ws, p.o_tfinal), at<uint32_t>(ws, p.o_nlast), at<uint32_t>(ws, p.o_ncount),
+                       pair_meta(p, ws));
     return hipGetLastError();
+}
+
+template <int TW, int TH, bool HAS_N, bool DET>
+void bwd_launch(const Plan &p, void *ws, const KParams &kp, const fm_outputs &out, const fm_grad_outputs &g,
+                hipStream_t st) {
+    const uint32_t *pval = at<uint32_t>(ws, p.pairs_in_alt ? p.o_pval2 : p.o_pval);
+    hipLaunchKernelGGL((k_render_bwd<TW, TH, HAS_N, DET>), dim3((unsigned)(p.T * Geo<TW, TH>::NQ)), dim3(64), 0,
+                       st, at<ViewDesc>(ws, p.o_views), p.V, at<uint32_t>(ws, p.o_tstart),
+                       at<uint32_t>(ws, p.o_tend), pval, at<Rec>(ws, p.o_rec), kp, p.NPX, out, g,
+                       at<float>(ws, p.o_tfinal), at<uint32_t>(ws, p.o_nlast), at<float>(ws, p.o_grad),
+                       pair_meta(p, ws));
 }
 
 template <int TW, int TH>
 hipError_t bwd_t(const Plan &p, void *ws, const KParams &kp, const fm_outputs &out, const fm_grad_outputs &g,
                  hipStream_t st) {
-    const uint32_t *pval = at<uint32_t>(ws, p.pairs_in_alt ? p.o_pval2 : p.o_pval);
-    if (g.normal)
-        hipLaunchKernelGGL((k_render_bwd<TW, TH, true>), dim3((unsigned)(p.T * Geo<TW, TH>::NQ)), dim3(64), 0, st,
-                           at<ViewDesc>(ws, p.o_views), p.V, at<uint32_t>(ws, p.o_tstart),
-                           at<uint32_t>(ws, p.o_tend), pval, at<Rec>(ws, p.o_rec), kp, p.NPX, out, g,
-                           at<float>(ws, p.o_tfinal), at<uint32_t>(ws, p.o_nlast), at<float>(ws, p.o_grad));
-    else
-        hipLaunchKernelGGL((k_render_bwd<TW, TH, false>), dim3((unsigned)(p.T * Geo<TW, TH>::NQ)), dim3(64), 0, st,
-                           at<ViewDesc>(ws, p.o_views), p.V, at<uint32_t>(ws, p.o_tstart),
-                           at<uint32_t>(ws, p.o_tend), pval, at<Rec>(ws, p.o_rec), kp, p.NPX, out, g,
-                           at<float>(ws, p.o_tfinal), at<uint32_t>(ws, p.o_nlast), at<float>(ws, p.o_grad));
+    if (g.normal) {
+        if (p.det) bwd_launch<TW, TH, true, true>(p, ws, kp, out, g, st);
+        else bwd_launch<TW, TH, true, false>(p, ws, kp, out, g, st);
+    } else {
+        if (p.det) bwd_launch<TW, TH, false, true>(p, ws, kp, out, g, st);
+        else bwd_launch<TW, TH, false, false>(p, ws, kp, out, g, st);
+    }
     return hipGetLastError();
+}
+
+template <int TW, int TH, bool DET>
+void fused_launch(const Plan &p, void *ws, const KParams &kp, const LossArgs &la, const fm_outputs &out,
+                  hipStream_t st) {
+    const uint32_t *pval = at<uint32_t>(ws, p.pairs_in_alt ? p.o_pval2 : p.o_pval);
+    hipLaunchKernelGGL((k_render_fused<TW, TH, DET>), dim3((unsigned)(p.T * Geo<TW, TH>::NQ)), dim3(64), 0, st,
+                       at<ViewDesc>(ws, p.o_views), p.V, at<uint32_t>(ws, p.o_tstart),
+                       at<uint32_t>(ws, p.o_tend), pval, at<Rec>(ws, p.o_rec), kp, p.NPX, out, la,
+                       at<float>(ws, p.o_tfinal), at<uint32_t>(ws, p.o_nlast), at<float>(ws, p.o_grad),
+                       at<float>(ws, p.o_loss), pair_meta(p, ws));
 }
 
 template <int TW, int TH>
 hipError_t fused_t(const Plan &p, void *ws, const KParams &kp, const LossArgs &la, const fm_outputs &out,
                    hipStream_t st) {
-    const uint32_t *pval = at<uint32_t>(ws, p.pairs_in_alt ? p.o_pval2 : p.o_pval);
-    hipLaunchKernelGGL((k_render_fused<TW, TH>), dim3((unsigned)(p.T * Geo<TW, TH>::NQ)), dim3(64), 0, st,
-                       at<ViewDesc>(ws, p.o_views), p.V, at<uint32_t>(ws, p.o_tstart),
-                       at<uint32_t>(ws, p.o_tend), pval, at<Rec>(ws, p.o_rec), kp, p.NPX, out, la,
-                       at<float>(ws, p.o_tfinal), at<uint32_t>(ws, p.o_nlast), at<float>(ws, p.o_grad),
-                       at<float>(ws, p.o_loss));
+    if (p.det) fused_launch<TW, TH, true>(p, ws, kp, la, out, st);
+    else fused_launch<TW, TH, false>(p, ws, kp, la, out, st);
     return hipGetLastError();
+}
+
+// Deterministic gradients, step 1: zero the partial slots of the stored
+// pairs (n_pairs emission indices x nq waves x gs floats), since an adjoint
+// writes only the slots of pairs that hit one of its pixels.
+__global__ __launch_bounds__(256) void k_det_clear(float4 *__restrict__ part, const Status *st, int row4) {
+    const int64_t n = (int64_t)st->n_pairs * row4;
+    const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) part[i] = z;
+}
+
+__device__ __forceinline__ void add4(float4 &a, const float4 &v) {
+    a.x += v.x; a.y += v.y; a.z += v.z; a.w += v.w;
+}
+
+// Step 2: four lanes per entry in depth order, one float4 of the slot each
+// (lane 0 also takes the fifth float4 of 20-float slots): the entry's pairs
+// are the emission indices [off32[r], off32[r + 1]) (the last entry's run
+// ends at n_pairs), so its partials are one contiguous block; they are summed
+// in index order, then wave order, and stored into the entry's gradient slot.
+__global__ __launch_bounds__(256) void k_det_reduce(const uint32_t *__restrict__ sorted_entry,
+                                                     const uint32_t *__restrict__ off32, const Status *st,
+                                                     const float4 *__restrict__ part, int nq, int gs4,
+                                                     float4 *__restrict__ grad) {
+    const uint32_t nv = st->n_vis, np = st->n_pairs;
+    const int c4 = threadIdx.x & 3;
+    const bool fifth = gs4 == 5 && c4 == 0;
+    for (int64_t r = (int64_t)blockIdx.x * 64 + (threadIdx.x >> 2); r < (int64_t)nv;
+         r += (int64_t)gridDim.x * 64) {
+        const uint32_t j0 = off32[r];
+        uint32_t j1 = r + 1 < (int64_t)nv ? off32[r + 1] : np;
+        if (j1 > np) j1 = np;  // offsets are clamped to the capacity, n_pairs too
+        // rows (index, wave) in index-major order form the range [j0 nq, j1 nq);
+        // four loads are issued before they are added, in row order
+        const int64_t k1 = (int64_t)j1 * nq;
+        int64_t k = (int64_t)j0 * nq;
+        float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a;
+        for (; k + 4 <= k1; k += 4) {
+            float4 v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[u] = part[(k + u) * gs4 + c4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) add4(a, v[u]);
+            if (fifth) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) v[u] = part[(k + u) * gs4 + 4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) add4(b, v[u]);
+            }
+        }
+        for (; k < k1; ++k) {
+            add4(a, part[k * gs4 + c4]);
+            if (fifth) add4(b, part[k * gs4 + 4]);
+        }
+        float4 *dst = grad + (int64_t)sorted_entry[r] * gs4;
+        dst[c4] = a;
+        if (fifth) dst[4] = b;
+    }
 }
 
 }  // namespace
@@ -605,6 +716,27 @@ hipError_t launch_render_fused(const Plan &p, void *ws, const KParams &kp, const
                                const fm_outputs &out, hipStream_t st) {
     if (p.T == 0) return hipSuccess;
     FM_DISPATCH(fused_t, p, ws, kp, la, out, st);
+}
+
+hipError_t launch_det_clear(const Plan &p, void *ws, int gstride, hipStream_t st) {
+    if (!p.det) return hipSuccess;
+    const int row4 = p.nq * gstride / 4;
+    const int64_t n4 = p.cap * row4;
+    const int blocks = (int)std::min<int64_t>((n4 + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_det_clear, dim3(blocks), dim3(256), 0, st, at<float4>(ws, p.o_part),
+                       at<Status>(ws, p.o_status), row4);
+    return hipGetLastError();
+}
+
+hipError_t launch_det_reduce(const Plan &p, void *ws, int gstride, hipStream_t st) {
+    if (!p.det) return hipSuccess;
+    // binning leaves the depth-ordered entries in the val buffer and their
+    // pair offsets in the key buffer
+    const int blocks = (int)std::min<int64_t>((p.E + 63) / 64, 16384);
+    hipLaunchKernelGGL(k_det_reduce, dim3(blocks), dim3(256), 0, st, at<uint32_t>(ws, p.o_val),
+                       at<uint32_t>(ws, p.o_key), at<Status>(ws, p.o_status), at<float4>(ws, p.o_part), p.nq,
+                       gstride / 4, at<float4>(ws, p.o_grad));
+    return hipGetLastError();
 }
 
 hipError_t launch_loss_reduce(const Plan &p, void *ws, float *loss, hipStream_t st) {

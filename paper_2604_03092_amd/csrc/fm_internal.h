@@ -120,6 +120,7 @@ struct KParams {
     float bg[3];
     int32_t tile_w, tile_h;
     int32_t gstride;  // floats per gradient slot: kGradSlot, or kGradStride with normal gradients
+    uint32_t pair_cap;  // pair capacity (bounds the emission indices of deterministic lists)
 };
 
 struct LossArgs {
@@ -146,8 +147,13 @@ struct Plan {
     size_t o_views = 0, o_subs = 0, o_vlist = 0, o_status = 0, o_rec = 0, o_key = 0, o_cnt = 0,
            o_key2 = 0, o_val = 0, o_val2 = 0, o_scan = 0, o_pkey = 0, o_pval = 0, o_pkey2 = 0,
            o_pval2 = 0, o_hist = 0, o_tstart = 0, o_tend = 0, o_tfinal = 0, o_nlast = 0, o_ncount = 0, o_grad = 0,
-           o_pose = 0, o_loss = 0, o_tot = 0, o_ell = 0, o_chunk = 0;
+           o_pose = 0, o_loss = 0, o_tot = 0, o_ell = 0, o_chunk = 0, o_meta = 0, o_part = 0;
     size_t bytes = 0;
+    // deterministic gradients: the sorted lists hold emission indices, o_meta
+    // maps them to pair values, and the adjoint writes one partial slot per
+    // (pair, wave of the tile) at o_part, summed per entry in emission order
+    bool det = false;
+    int nq = 1;  // waves per tile (four 16x16 quadrants of a 32x32 tile)
     bool pairs_in_alt = false;  // final sorted pairs live in the *2 buffers
 };
 
@@ -205,6 +211,10 @@ hipError_t launch_render_fused(const Plan &p, void *ws, const KParams &kp, const
                                const fm_outputs &out, hipStream_t st);
 hipError_t launch_loss_reduce(const Plan &p, void *ws, float *loss, hipStream_t st);
 hipError_t launch_zero_grad(const Plan &p, void *ws, int gstride, hipStream_t st);
+// Deterministic gradients: clear the partial slots of the stored pairs before
+// an adjoint, and sum each entry's slots into its gradient slot after it.
+hipError_t launch_det_clear(const Plan &p, void *ws, int gstride, hipStream_t st);
+hipError_t launch_det_reduce(const Plan &p, void *ws, int gstride, hipStream_t st);
 hipError_t launch_preprocess_bwd(const Plan &p, void *ws, int gstride, const float *intr, const float *viewmat,
                                  float *dL_dviewmat, hipStream_t st);
 bool tile_shape_supported(int tw, int th);

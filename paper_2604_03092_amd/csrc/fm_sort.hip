@@ -436,7 +436,8 @@ __global__ __launch_bounds__(256) void k_offsets(const uint32_t *cnt_sorted, con
 // kEmitChunk, each covering >= 1 tile) are staged in LDS; every entry marks
 // the chunk position of its first pair with its local index and an inclusive
 // max-scan over the chunk gives every pair its entry.  Consecutive threads
-// write consecutive pairs.
+// write consecutive pairs.  With meta (deterministic gradients) the sorted
+// value is the pair's emission index and meta holds its entry and mask.
 __device__ __forceinline__ uint32_t wave_incl_max_u32(uint32_t x, int lane) {
     for (int off = 1; off < 64; off <<= 1) {
         const uint32_t y = __shfl_up(x, off);
@@ -451,7 +452,8 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t *__restrict__ sorte
                                                const uint32_t *__restrict__ chunk_first, const Status *st,
                                                const Ell *__restrict__ ell, KParams kp,
                                                uint32_t *__restrict__ pkey, uint32_t *__restrict__ pval,
-                                               uint32_t *__restrict__ hist, int G) {
+                                               uint32_t *__restrict__ hist, int G,
+                                               uint32_t *__restrict__ meta) {
     static_assert(2 * kEmitChunk == kSortTile && kRadix == 256, "two chunks make a tile of the first tile-sort pass");
     constexpr int PER = kEmitChunk / 256;
     __shared__ uint32_t s_own[kEmitChunk];
@@ -530,7 +532,13 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t *__restrict__ sorte
                 // key drops it in the first tile-sort pass
                 const uint32_t key = el.tb + ry * tiles_x + rx;
                 pkey[p0 + q] = mask ? key : kNoKey;
-                pval[p0 + q] = ent | (mask << kMaskShift);
+                const uint32_t v = ent | (mask << kMaskShift);
+                if (meta) {  // deterministic lists carry the emission index
+                    pval[p0 + q] = p0 + q;
+                    meta[p0 + q] = v;
+                } else {
+                    pval[p0 + q] = v;
+                }
                 if (mask) atomicAdd(&s_hist[key & 0xFFu], 1u);
             }
         }
@@ -609,7 +617,8 @@ hipError_t launch_binning(const Plan &p, void *ws, const KParams &kp, hipStream_
                        (uint64_t)p.cap, off32, chunk_first);
 #define FM_EMIT(TW, TH)                                                                                        \
     hipLaunchKernelGGL((k_emit<TW, TH>), dim3(p.emit_blocks), dim3(256), 0, st, val, off32, n_vis, chunk_first,   \
-                       status, at<Ell>(ws, p.o_ell), kp, pkey, pval, hist, p.sortG_p)
+                       status, at<Ell>(ws, p.o_ell), kp, pkey, pval, hist, p.sortG_p,                \
+                       p.det ? at<uint32_t>(ws, p.o_meta) : nullptr)
     if (p.tile_w == 16 && p.tile_h == 16) FM_EMIT(16, 16);
     else if (p.tile_w == 8 && p.tile_h == 8) FM_EMIT(8, 8);
     else if (p.tile_w == 16 && p.tile_h == 8) FM_EMIT(16, 8);

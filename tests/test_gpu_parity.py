@@ -120,6 +120,78 @@ def test_fused_l1_config0(rast, tile):
     assert_grad_close(to_np(dvm), rdvm, "fused.viewmat")
 
 
+# ------------------------------------------------------- deterministic mode
+def _fused_run(rast, gs, ws):
+    out = rast.new_outputs(gs)
+    grads, dvm = gs.zero_grads()
+    loss = torch.zeros(1, device="cuda")
+    rast.fwd_bwd_l1(gs, ws, out, grads, dvm, loss)
+    torch.cuda.synchronize()
+    assert rast.query(gs, ws)[0] == 0
+    flat = {f"{s}.{k}": to_np(v) for s, g in enumerate(grads) for k, v in g.items()}
+    flat["viewmat"] = to_np(dvm)
+    return {k: v.cpu().numpy() for k, v in out.items()}, float(loss), flat
+
+
+@pytest.mark.parametrize("tile", [(16, 16), (32, 32)])
+def test_deterministic_fused_is_reproducible(rast, tile):
+    """Three views over two submaps with heavy overlap (many tiles add into
+    one entry).  Deterministic mode: two fused steps agree bitwise in loss,
+    surfel and pose gradients; images equal the default mode's bitwise and
+    gradients agree with it to rounding."""
+    sc = scenes.random_scene(21, 12000, 96, 72, n_views=3, scale_lo=0.05, scale_hi=0.3)
+    sc.submaps.append({k: np.ascontiguousarray(v[..., ::2]) for k, v in sc.submaps[0].items()})
+    sc.views[1] = (sc.views[1][0], sc.views[1][1], 1)
+    gs = GpuScene.from_scene(sc)
+    _say(f"deterministic fused tile={tile}")
+    ws_d = rast.workspace(gs, rast.params(tile=tile, deterministic=True), max_pairs=400_000)
+    ws_n = rast.workspace(gs, rast.params(tile=tile), max_pairs=400_000)
+    img_d, loss_d, g_d = _fused_run(rast, gs, ws_d)
+    img_d2, loss_d2, g_d2 = _fused_run(rast, gs, ws_d)
+    img_n, loss_n, g_n = _fused_run(rast, gs, ws_n)
+    assert loss_d == loss_d2
+    for k in g_d:
+        assert np.array_equal(g_d[k], g_d2[k]), k
+        assert_grad_close(g_d[k], g_n[k], f"det-vs-atomic {k}", rel=1e-4)
+    for k in img_d:
+        assert np.array_equal(img_d[k], img_d2[k]), k
+        assert np.array_equal(img_d[k], img_n[k]), k
+    assert loss_d == loss_n
+
+
+@pytest.mark.parametrize("tile", [(16, 16), (32, 32)])
+def test_deterministic_backward_with_normals_matches_oracle(rast, tile):
+    """fm_backward in deterministic mode with every output plane carrying a
+    gradient (20-float slots): reproducible and equal to the oracle's
+    gradients within the usual tolerance; pairs as in the default mode."""
+    sc = scenes.random_scene(33, 4000, 72, 56, scale_lo=0.03, scale_hi=0.2)
+    gs = GpuScene.from_scene(sc)
+    _say(f"deterministic backward tile={tile}")
+    p = rast.params(tile=tile, deterministic=True)
+    out, ws = rast.forward(gs, p)
+    ref = _oracle_forward(sc)
+    keep = ~ref["flags"]
+    assert_images_close(out, ref, keep, what="deterministic")
+    out_n, ws_n = rast.forward(gs, rast.params(tile=tile))
+    pairs_d, pairs_n = rast.debug_pairs(gs, ws), rast.debug_pairs(gs, ws_n)
+    for a, b in zip(pairs_d, pairs_n):
+        assert np.array_equal(a, b)
+    g = random_upstream(np.random.default_rng(5), gs.npx, keep)
+    gt = {k: torch.from_numpy(v.astype(np.float32)).cuda() for k, v in g.items()}
+    runs = []
+    for _ in range(2):
+        grads, dvm = gs.zero_grads()
+        rast.backward(gs, ws, out, gt, grads, dvm)
+        torch.cuda.synchronize()
+        runs.append(({k: to_np(v) for k, v in grads[0].items()}, to_np(dvm)))
+    rg, rdvm = oracle.backward_scene(sc, g)
+    for k in ("mean", "quat", "scale", "opacity", "color"):
+        assert np.array_equal(runs[0][0][k], runs[1][0][k]), k
+        assert_grad_close(runs[0][0][k], rg[0][k], f"deterministic.{k}")
+    assert np.array_equal(runs[0][1], runs[1][1])
+    assert_grad_close(runs[0][1], rdvm, "deterministic.viewmat")
+
+
 # ------------------------------------------------------------------ batches
 def test_batch_equals_single_views(rast):
     sc = scenes.random_scene(9, 30000, 160, 120, n_views=4, scale_lo=0.02, scale_hi=0.12)
@@ -264,6 +336,12 @@ def test_invalid_arguments(rast):
         with pytest.raises(native.FmError) as e:
             rast.workspace(gs, rast.params(**bad_params))
         assert e.value.status == native.FM_ERR_INVALID_ARG, bad_params
+    for field, value in (("deterministic", 2), ("reserved", 1)):
+        p = rast.params()
+        setattr(p, field, value)
+        with pytest.raises(native.FmError) as e:
+            rast.workspace(gs, p)
+        assert e.value.status == native.FM_ERR_INVALID_ARG, field
     ws = rast.workspace(gs)
     ws.nbytes = 10
     with pytest.raises(native.FmError) as e:
