@@ -39,7 +39,8 @@
  *   - intr[v] = (fx, fy, cx, cy); viewmat[v] = world->camera [R|t], 12
  *     floats row-major.  A Sim(3) keyframe pose renders as its SE(3) part
  *     with depths divided by the scale; that scaling is the caller's.
- *   - Gradients are ACCUMULATED (+=) into the caller's buffers.
+ *   - Gradients are ACCUMULATED (+=) into the caller's buffers, or stored
+ *     when params->overwrite is 1.
  *   - Surfels with any non-finite value, a zero quaternion, a non-positive
  *     scale, depth <= near_plane, opacity <= alpha_min, or a support disk
  *     not entirely in front of the camera are culled: they contribute
@@ -138,7 +139,13 @@ typedef struct {
                                one reduction pass over those partials.  Forward,
                                backward and fwd_bwd calls on one workspace must agree
                                on it.  Other values are INVALID_ARG.               */
-    int32_t reserved;       /* must be 0 */
+    int32_t overwrite;      /* 0: surfel gradients, dL_dviewmat and the fused call's
+                               loss are ADDED into the caller's buffers.  1: they
+                               are STORED, so nothing needs clearing beforehand:
+                               every element of a submap that some view of the
+                               batch renders, every view's dL_dviewmat row and
+                               *loss are overwritten; submaps that no view renders
+                               are left untouched.  Other values are INVALID_ARG. */
 } fm_raster_params;
 
 /* Output planes (device, float32): rgb[3][P], depth[P], normal[3][P],
@@ -208,7 +215,8 @@ fm_status fm_backward(fm_ctx *ctx, const fm_batch *batch, const fm_raster_params
 
 /* Fused forward + L1 loss + backward of the whole batch (the refinement
  * step's render term, Sec. 3.3).  Writes the outputs, ADDS the loss into
- * *loss (device float) and accumulates the gradients as fm_backward does. */
+ * *loss (device float; stores it with params->overwrite) and accumulates
+ * (or stores) the gradients as fm_backward does. */
 fm_status fm_fwd_bwd_l1(fm_ctx *ctx, const fm_batch *batch, const fm_raster_params *params,
                         const fm_l1_loss *loss_spec, fm_outputs out, float *loss,
                         const fm_surfel_grads *grads, float *dL_dviewmat, void *workspace,

@@ -121,9 +121,10 @@ fm_status build(fm_ctx *ctx, const fm_batch *b, const fm_raster_params *prm, int
     p.tile_w = tw;
     p.tile_h = th;
     p.cap = max_pairs;
-    if ((prm->deterministic != 0 && prm->deterministic != 1) || prm->reserved != 0)
-        return fail(ctx, FM_ERR_INVALID_ARG, "deterministic must be 0 or 1 and reserved 0");
+    if ((prm->deterministic != 0 && prm->deterministic != 1) || (prm->overwrite != 0 && prm->overwrite != 1))
+        return fail(ctx, FM_ERR_INVALID_ARG, "deterministic and overwrite must be 0 or 1");
     p.det = prm->deterministic == 1;
+    p.overwrite = prm->overwrite == 1;
     p.nq = (tw == 32 && th == 32) ? 4 : 1;
     for (int i = 0; i < p.S; ++i) {
         const fm_surfels &sm = b->submaps[i];

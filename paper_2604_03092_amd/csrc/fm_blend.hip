@@ -550,7 +550,7 @@ __global__ __launch_bounds__(64) void k_render_fused(const ViewDesc *__restrict_
 }
 
 __global__ __launch_bounds__(1024) void k_loss_reduce(const float *__restrict__ part, int64_t n,
-                                                       float *__restrict__ loss) {
+                                                       float *__restrict__ loss, int overwrite) {
     __shared__ float red[16];
     float s = 0.f;
     for (int64_t i = threadIdx.x; i < n; i += 1024) s += part[i];
@@ -560,7 +560,7 @@ __global__ __launch_bounds__(1024) void k_loss_reduce(const float *__restrict__ 
     if (threadIdx.x == 0) {
         float t = 0.f;
         for (int k = 0; k < 16; ++k) t += red[k];
-        *loss += t;
+        *loss = overwrite ? t : *loss + t;
     }
 }
 
@@ -743,7 +743,8 @@ hipError_t launch_loss_reduce(const Plan &p, void *ws, float *loss, hipStream_t 
     if (p.T == 0 || !loss) return hipSuccess;
     // one partial per block: 32x32 tiles run four blocks each
     const int64_t nb = p.T * ((p.tile_w == 32 && p.tile_h == 32) ? 4 : 1);
-    hipLaunchKernelGGL(k_loss_reduce, dim3(1), dim3(1024), 0, st, at<float>(ws, p.o_loss), nb, loss);
+    hipLaunchKernelGGL(k_loss_reduce, dim3(1), dim3(1024), 0, st, at<float>(ws, p.o_loss), nb, loss,
+                       (int)p.overwrite);
     return hipGetLastError();
 }
 

@@ -265,7 +265,8 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
     const SubmapDesc *__restrict__ subs, int S, const int32_t *__restrict__ vlist,
     const ViewDesc *__restrict__ views, const float *__restrict__ intr,
     const float *__restrict__ viewmat, const Rec *__restrict__ rec, const uint32_t *__restrict__ cnt,
-    const float4 *__restrict__ grad, int gstride, float *__restrict__ pose_part, int max_blocks) {
+    const float4 *__restrict__ grad, int gstride, float *__restrict__ pose_part, int max_blocks,
+    int overwrite) {
     const int s_idx = submap_of_block(subs, S, blockIdx.x);
     const SubmapDesc &sd = subs[s_idx];
     const int lb = blockIdx.x - sd.block_base;
@@ -408,26 +409,29 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
                    x * G[6] + y * G[7]);
     const float dot = dq[0] * w + dq[1] * x + dq[2] * y + dq[3] * z;
     const float inv = 1.f / qnorm;
+    // add into the caller's gradients, or store them (overwrite)
+    const bool ow = overwrite != 0;
+    auto put = [ow](float *g, float v) { *g = ow ? v : *g + v; };
     if (sd.g_mean) {
-        sd.g_mean[i] += dmu[0];
-        sd.g_mean[n + i] += dmu[1];
-        sd.g_mean[2 * n + i] += dmu[2];
+        put(sd.g_mean + i, dmu[0]);
+        put(sd.g_mean + n + i, dmu[1]);
+        put(sd.g_mean + 2 * n + i, dmu[2]);
     }
     if (sd.g_quat) {
-        sd.g_quat[i] += (dq[0] - w * dot) * inv;
-        sd.g_quat[n + i] += (dq[1] - x * dot) * inv;
-        sd.g_quat[2 * n + i] += (dq[2] - y * dot) * inv;
-        sd.g_quat[3 * n + i] += (dq[3] - z * dot) * inv;
+        put(sd.g_quat + i, (dq[0] - w * dot) * inv);
+        put(sd.g_quat + n + i, (dq[1] - x * dot) * inv);
+        put(sd.g_quat + 2 * n + i, (dq[2] - y * dot) * inv);
+        put(sd.g_quat + 3 * n + i, (dq[3] - z * dot) * inv);
     }
     if (sd.g_scale) {
-        sd.g_scale[i] += dsu;
-        sd.g_scale[n + i] += dsv;
+        put(sd.g_scale + i, dsu);
+        put(sd.g_scale + n + i, dsv);
     }
-    if (sd.g_opacity) sd.g_opacity[i] += dsig;
+    if (sd.g_opacity) put(sd.g_opacity + i, dsig);
     if (sd.g_color) {
-        sd.g_color[i] += dc[0];
-        sd.g_color[n + i] += dc[1];
-        sd.g_color[2 * n + i] += dc[2];
+        put(sd.g_color + i, dc[0]);
+        put(sd.g_color + n + i, dc[1]);
+        put(sd.g_color + 2 * n + i, dc[2]);
     }
 }
 
@@ -435,7 +439,7 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
 __global__ __launch_bounds__(1024) void k_pose_reduce(const ViewDesc *__restrict__ views,
                                                        const SubmapDesc *__restrict__ subs,
                                                        const float *__restrict__ pose_part, int max_blocks,
-                                                       float *__restrict__ dL_dviewmat) {
+                                                       float *__restrict__ dL_dviewmat, int overwrite) {
     __shared__ float red[16][16];
     const int v = blockIdx.x;
     const SubmapDesc &sd = subs[views[v].submap];
@@ -457,7 +461,8 @@ __global__ __launch_bounds__(1024) void k_pose_reduce(const ViewDesc *__restrict
     if (threadIdx.x < 12) {
         float t = 0.f;
         for (int w = 0; w < 16; ++w) t += red[w][threadIdx.x];
-        dL_dviewmat[12 * v + threadIdx.x] += t;
+        float *d = dL_dviewmat + 12 * v + threadIdx.x;
+        *d = overwrite ? t : *d + t;
     }
 }
 
@@ -515,12 +520,12 @@ hipError_t launch_preprocess_bwd(const Plan &p, void *ws, int gstride, const flo
                            at<SubmapDesc>(ws, p.o_subs), p.S, at<int32_t>(ws, p.o_vlist),
                            at<ViewDesc>(ws, p.o_views), intr, viewmat, at<Rec>(ws, p.o_rec),
                            at<uint32_t>(ws, p.o_cnt), at<float4>(ws, p.o_grad), gstride,
-                           at<float>(ws, p.o_pose), p.a7_max_blocks);
+                           at<float>(ws, p.o_pose), p.a7_max_blocks, (int)p.overwrite);
     }
     if (dL_dviewmat) {
         hipLaunchKernelGGL(k_pose_reduce, dim3(p.V), dim3(1024), 0, st, at<ViewDesc>(ws, p.o_views),
                            at<SubmapDesc>(ws, p.o_subs), at<float>(ws, p.o_pose), p.a7_max_blocks,
-                           dL_dviewmat);
+                           dL_dviewmat, (int)p.overwrite);
     }
     return hipGetLastError();
 }

@@ -52,7 +52,7 @@ def test_host_only_calls(lib):
     lib.fm_default_params(ctypes.byref(p))
     assert p.tile_w == 16 and p.tile_h == 16 and abs(p.alpha_max - 0.99) < 1e-7
     assert abs(p.alpha_min - 1 / 255) < 1e-9 and abs(p.t_min - 1e-4) < 1e-10 and p.rho_max == 3.0
-    assert p.deterministic == 0 and p.reserved == 0
+    assert p.deterministic == 0 and p.overwrite == 0
     assert lib.fm_version() >= 10000
     assert lib.fm_status_string(2) == b"pair capacity exceeded"
     # tile count is host arithmetic

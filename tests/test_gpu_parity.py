@@ -192,6 +192,50 @@ def test_deterministic_backward_with_normals_matches_oracle(rast, tile):
     assert_grad_close(runs[0][1], rdvm, "deterministic.viewmat")
 
 
+def test_overwrite_stores_gradients(rast):
+    """overwrite = 1: the fused call and fm_backward store surfel gradients,
+    pose gradients and the loss over whatever the buffers held, equal bitwise
+    to accumulating into zeroed buffers; a submap no view renders keeps its
+    contents."""
+    sc = scenes.random_scene(23, 6000, 80, 60, n_views=2, scale_lo=0.03, scale_hi=0.2)
+    sc.submaps.append({k: np.ascontiguousarray(v[..., :500]) for k, v in sc.submaps[0].items()})
+    gs = GpuScene.from_scene(sc)
+    _say("overwrite mode")
+    res = {}
+    for ow in (False, True):
+        # (deterministic sums, so that the two modes can be compared bitwise)
+        ws = rast.workspace(gs, rast.params(overwrite=ow, deterministic=True), max_pairs=200_000)
+        out = rast.new_outputs(gs)
+        grads, dvm = gs.zero_grads()
+        loss = torch.zeros(1, device="cuda")
+        if ow:
+            for g in grads:
+                for t in g.values():
+                    t.fill_(7.0)
+            dvm.fill_(7.0)
+            loss.fill_(7.0)
+        rast.fwd_bwd_l1(gs, ws, out, grads, dvm, loss)
+        torch.cuda.synchronize()
+        assert rast.query(gs, ws)[0] == 0
+        res[ow] = ({k: to_np(v) for k, v in grads[0].items()}, to_np(dvm), float(loss),
+                   {k: to_np(v) for k, v in grads[1].items()})
+        up = {k: torch.ones_like(v) for k, v in out.items()}
+        for g in grads:
+            for t in g.values():
+                t.fill_(3.0 if ow else 0.0)
+        dvm.fill_(3.0 if ow else 0.0)
+        rast.backward(gs, ws, out, up, grads, dvm)
+        torch.cuda.synchronize()
+        res[ow] += ({k: to_np(v) for k, v in grads[0].items()}, to_np(dvm))
+    for k in res[False][0]:
+        assert np.array_equal(res[True][0][k], res[False][0][k]), k
+        assert np.array_equal(res[True][4][k], res[False][4][k]), k
+        assert np.all(res[True][3][k] == 7.0), k  # submap 1 has no view
+    assert np.array_equal(res[True][1], res[False][1])
+    assert np.array_equal(res[True][5], res[False][5])
+    assert res[True][2] == res[False][2]
+
+
 # ------------------------------------------------------------------ batches
 def test_batch_equals_single_views(rast):
     sc = scenes.random_scene(9, 30000, 160, 120, n_views=4, scale_lo=0.02, scale_hi=0.12)
@@ -336,7 +380,7 @@ def test_invalid_arguments(rast):
         with pytest.raises(native.FmError) as e:
             rast.workspace(gs, rast.params(**bad_params))
         assert e.value.status == native.FM_ERR_INVALID_ARG, bad_params
-    for field, value in (("deterministic", 2), ("reserved", 1)):
+    for field, value in (("deterministic", 2), ("overwrite", -1)):
         p = rast.params()
         setattr(p, field, value)
         with pytest.raises(native.FmError) as e:
