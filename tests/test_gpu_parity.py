@@ -511,3 +511,45 @@ def test_graph_replay_matches_eager(rast):
             assert torch.allclose(grads[0][k], ref_g[k], rtol=1e-4, atol=1e-6 * float(ref_g[k].abs().max())), (rep, k)
         assert torch.allclose(dvm, ref_dvm, rtol=1e-4, atol=1e-6 * float(ref_dvm.abs().max()))
         _ = torch.randn(1000, device="cuda").sum()   # eager work between replays
+
+
+def test_graph_replay_deterministic_overwrite(rast):
+    """Deterministic sums and stored gradients under graph capture: with no
+    clearing in the graph and the buffers scribbled over between replays,
+    every replay reproduces the eager result bitwise."""
+    sc = scenes.random_scene(14, 20000, 128, 96, n_views=3, scale_lo=0.02, scale_hi=0.12)
+    gs = GpuScene.from_scene(sc)
+    _say("graph replay, deterministic + overwrite")
+    p = rast.params(deterministic=True, overwrite=True)
+    out0, ws = rast.forward(gs, p)
+    ws = rast.workspace(gs, p, max_pairs=ws.n_pairs + 1024)
+    out = rast.new_outputs(gs)
+    grads, dvm = gs.zero_grads()
+    loss = torch.zeros(1, device="cuda")
+    rast.fwd_bwd_l1(gs, ws, out, grads, dvm, loss)
+    torch.cuda.synchronize()
+    ref = {k: v.clone() for k, v in out.items()}
+    ref_g = {k: v.clone() for k, v in grads[0].items()}
+    ref_dvm, ref_loss = dvm.clone(), loss.clone()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        rast.fwd_bwd_l1(gs, ws, out, grads, dvm, loss)
+    torch.cuda.current_stream().wait_stream(s)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        rast.fwd_bwd_l1(gs, ws, out, grads, dvm, loss)
+    for rep in range(4):
+        out["rgb"].fill_(-1.0)
+        for t in grads[0].values():
+            t.fill_(123.0)
+        dvm.fill_(5.0)
+        loss.fill_(9.0)
+        graph.replay()
+        torch.cuda.synchronize()
+        for k in ref:
+            assert torch.equal(out[k], ref[k]), (rep, k)
+        for k in ref_g:
+            assert torch.equal(grads[0][k], ref_g[k]), (rep, k)
+        assert torch.equal(dvm, ref_dvm) and torch.equal(loss, ref_loss), rep
+        _ = torch.randn(1000, device="cuda").sum()   # eager work between replays
