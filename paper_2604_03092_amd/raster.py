@@ -430,6 +430,28 @@ class FusionBatch:
         return self.offsets
 
 
+def sim3_table(deltas, device="cuda"):
+    """Device table of fm_sim3 records from host (s, q(w,x,y,z), t) triples,
+    one per keyframe, for warp_keyframes."""
+    arr = (native.FmSim3 * max(1, len(deltas)))()
+    for k, (s, q, t) in enumerate(deltas):
+        arr[k] = native.FmSim3(float(s), (ctypes.c_float * 4)(*[float(x) for x in q]),
+                               (ctypes.c_float * 3)(*[float(x) for x in t]))
+    return torch.frombuffer(bytearray(bytes(arr)), dtype=torch.uint8).to(device), len(deltas)
+
+
+def warp_keyframes(rast, surfels, keyframe, table, stream=None):
+    """Loop-correction warp in place (fm_warp_keyframes): surfels holds the
+    device planes mean [3, n], quat [4, n], scale [2, n]; keyframe is a
+    device int32 [n] binding; table = sim3_table(...) (device records and
+    their count).  Primitives bound outside the table are left alone."""
+    rec, n_kf = table
+    n = int(keyframe.numel())
+    rast.check(rast.lib.fm_warp_keyframes(rast.ctx, _ptr(surfels["mean"]), _ptr(surfels["quat"]),
+                                          _ptr(surfels["scale"]), _ptr(keyframe), n, _ptr(rec), n_kf,
+                                          _stream(stream)))
+
+
 class _RenderFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, rast, gs, params, *flat):

@@ -8,7 +8,7 @@ import torch
 
 from oracle import warp
 from paper_2604_03092_amd import native
-from paper_2604_03092_amd.raster import Rasterizer, _ptr
+from paper_2604_03092_amd.raster import Rasterizer, _ptr, sim3_table, warp_keyframes
 
 pytestmark = pytest.mark.gpu
 
@@ -61,3 +61,25 @@ def test_warp_invalid_arguments(rast):
         native.FM_ERR_INVALID_ARG
     assert rast.lib.fm_warp_keyframes(rast.ctx, _ptr(x), _ptr(x), _ptr(x), _ptr(x), -1, _ptr(x), 1, None) == \
         native.FM_ERR_INVALID_ARG
+
+
+def test_warp_wrapper_matches_oracle(rast):
+    """The Python wrapper (sim3_table + warp_keyframes) on a small set."""
+    rng = np.random.default_rng(91)
+    n, K = 5000, 7
+    q = rng.normal(size=(4, n))
+    planes = dict(mean=rng.normal(0, 3, (3, n)).astype(np.float32),
+                  quat=(q / np.linalg.norm(q, axis=0)).astype(np.float32),
+                  scale=rng.uniform(0.01, 0.1, (2, n)).astype(np.float32))
+    kf = rng.integers(-2, K + 2, n).astype(np.int32)
+    host = [(float(rng.uniform(0.8, 1.2)), rng.normal(size=4), rng.normal(0, 1, 3)) for _ in range(K)]
+    dev = {k: torch.from_numpy(v.copy()).cuda() for k, v in planes.items()}
+    warp_keyframes(rast, dev, torch.from_numpy(kf).cuda(), sim3_table(host))
+    torch.cuda.synchronize()
+    deltas = [(float(np.float32(s)), np.asarray(qq, np.float32).astype(np.float64),
+               np.asarray(t, np.float32).astype(np.float64)) for (s, qq, t) in host]
+    ref = warp.warp(planes, kf, deltas)
+    got = {k: v.cpu().numpy().astype(np.float64) for k, v in dev.items()}
+    np.testing.assert_allclose(got["mean"], ref["mean"], rtol=2e-6, atol=2e-5)
+    np.testing.assert_allclose(got["quat"], ref["quat"], rtol=2e-6, atol=2e-6)
+    np.testing.assert_allclose(got["scale"], ref["scale"], rtol=2e-6)
