@@ -269,9 +269,11 @@ fm_status fm_tile_count(const fm_batch *batch, const fm_raster_params *params, i
  * batch (outputs, gradients and the loss are overwritten/accumulated while
  * it runs) and writes the fastest shape into *chosen (a copy of *params
  * with tile_w/tile_h set).  The choice is cached in the context under the
- * batch's shape signature and, if cache_path is not NULL, in a JSON file
- * read back by later contexts.  The workspace must be sized for the largest
- * candidate (fm_workspace_size with tile 8x8).  Synchronous. */
+ * batch's shape signature and the deterministic flag (the two modes tune
+ * separately) and, if cache_path is not NULL, in a JSON file read back by
+ * later contexts.  Shapes whose workspace (fm_workspace_size) exceeds
+ * ws_bytes or whose pairs exceed max_pairs are skipped; without
+ * deterministic sums the 8x8 workspace is the largest.  Synchronous. */
 fm_status fm_autotune(fm_ctx *ctx, const fm_batch *batch, const fm_raster_params *params,
                       const fm_l1_loss *loss_spec, fm_outputs out, float *loss,
                       const fm_surfel_grads *grads, float *dL_dviewmat, void *workspace,

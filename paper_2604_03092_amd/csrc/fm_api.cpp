@@ -64,6 +64,12 @@ std::string signature(const fm_batch *b) {
     return os.str();
 }
 
+// Autotune cache key: the batch signature; deterministic sums change the
+// cost of each shape, so they tune separately.
+std::string tune_key(const fm_batch *b, const fm_raster_params *prm) {
+    return signature(b) + (prm->deterministic == 1 ? "/det" : "");
+}
+
 struct Built {
     Plan plan;
     std::vector<ViewDesc> views;
@@ -75,7 +81,7 @@ fm_status resolve_tile(fm_ctx *ctx, const fm_batch *b, const fm_raster_params *p
     tw = prm->tile_w;
     th = prm->tile_h;
     if (tw == 0 && th == 0) {
-        auto it = ctx->tuned.find(signature(b));
+        auto it = ctx->tuned.find(tune_key(b, prm));
         if (it != ctx->tuned.end()) {
             tw = it->second.first;
             th = it->second.second;
@@ -648,7 +654,7 @@ fm_status fm_autotune(fm_ctx *ctx, const fm_batch *b, const fm_raster_params *pr
     if (!ctx) return FM_ERR_INVALID_ARG;
     if (!chosen || !prm) return fail(ctx, FM_ERR_INVALID_ARG, "params and chosen must not be NULL");
     if (cache_path) load_cache(ctx, cache_path);
-    const std::string sig = signature(b);
+    const std::string sig = tune_key(b, prm);
     *chosen = *prm;
     auto hit = ctx->tuned.find(sig);
     if (hit != ctx->tuned.end()) {
@@ -660,9 +666,16 @@ fm_status fm_autotune(fm_ctx *ctx, const fm_batch *b, const fm_raster_params *pr
     hipStream_t st = (hipStream_t)stream;
     fm_status s = use_device(ctx);
     if (s != FM_OK) return s;
-    hipEvent_t e0, e1;
-    FM_TRY_HIP(hipEventCreate(&e0), "hipEventCreate");
-    FM_TRY_HIP(hipEventCreate(&e1), "hipEventCreate");
+    struct Events {  // destroyed on every return path
+        hipEvent_t e[2] = {nullptr, nullptr};
+        ~Events() {
+            for (hipEvent_t x : e)
+                if (x) (void)hipEventDestroy(x);
+        }
+    } ev;
+    FM_TRY_HIP(hipEventCreate(&ev.e[0]), "hipEventCreate");
+    FM_TRY_HIP(hipEventCreate(&ev.e[1]), "hipEventCreate");
+    hipEvent_t e0 = ev.e[0], e1 = ev.e[1];
     float best = 1e30f;
     int bw = 16, bh = 16;
     bool any = false;
@@ -696,8 +709,6 @@ fm_status fm_autotune(fm_ctx *ctx, const fm_batch *b, const fm_raster_params *pr
             bh = sh[1];
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     if (!any) return s != FM_OK ? s : fail(ctx, FM_ERR_WORKSPACE, "no tile shape fits the workspace and capacity");
     ctx->tuned[sig] = {bw, bh};
     if (cache_path) save_cache(ctx, cache_path);
