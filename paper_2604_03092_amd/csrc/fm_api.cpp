@@ -335,7 +335,9 @@ fm_status run_fused(fm_ctx *ctx, Built &bt, const fm_raster_params *prm, const f
     la.w_depth = ls->w_depth;
     mark_begin(ctx, st);
     FM_TRY_HIP(fm::launch_setup(bt.plan, ws, bt.views.data(), bt.subs.data(), bt.vlist.data(), st), "setup");
-    FM_TRY_HIP(fm::launch_preprocess(bt.plan, ws, kp, b->intr, b->viewmat, true, st), "preprocess");
+    // the slots are cleared for the blend's atomics; deterministic sums store
+    // every slot the backward projection reads (those of visible entries)
+    FM_TRY_HIP(fm::launch_preprocess(bt.plan, ws, kp, b->intr, b->viewmat, !bt.plan.det, st), "preprocess");
     mark(ctx, st, PH_PRE);
     FM_TRY_HIP(fm::launch_binning(bt.plan, ws, kp, st), "binning");
     if (bt.plan.det) FM_TRY_HIP(fm::launch_det_clear(bt.plan, ws, kp.gstride, st), "det_clear");
@@ -549,8 +551,8 @@ fm_status fm_backward(fm_ctx *ctx, const fm_batch *b, const fm_raster_params *pr
     if (g.normal) kp.gstride = fm::kGradStride;  // room for the normal's gradient
     mark_begin(ctx, st);
     FM_TRY_HIP(fm::launch_setup(bt.plan, ws, bt.views.data(), bt.subs.data(), bt.vlist.data(), st), "setup");
-    FM_TRY_HIP(fm::launch_zero_grad(bt.plan, ws, kp.gstride, st), "zero_grad");
     if (bt.plan.det) FM_TRY_HIP(fm::launch_det_clear(bt.plan, ws, kp.gstride, st), "det_clear");
+    else FM_TRY_HIP(fm::launch_zero_grad(bt.plan, ws, kp.gstride, st), "zero_grad");
     mark(ctx, st, PH_ZERO);
     FM_TRY_HIP(fm::launch_render_bwd(bt.plan, ws, kp, out, g, st), "render_bwd");
     if (bt.plan.det) FM_TRY_HIP(fm::launch_det_reduce(bt.plan, ws, kp.gstride, st), "det_reduce");
