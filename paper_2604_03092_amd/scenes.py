@@ -384,6 +384,32 @@ def random_scene(seed, n, w, h, n_views=1, fx=None, lo=(-1, -1, 2), hi=(1, 1, 6)
                     *((1.0, 8.0) if depth_target else (None, None)))
 
 
+def largest_view_clusters(seed=SEED_BASE + 41, size=16384, f=8000.0, n_per=600, crop=512, spread=100.0):
+    """One view at the largest supported size with surfels in two small
+    clusters, near the top-left and the bottom-right corner.  Each cluster's
+    centres lie on rays within `spread` pixels of its centre pixel at depths
+    in [3, 5], with tangent scales log-uniform in [0.002, 0.006] (supports
+    under 50 pixels), so every support stays inside the crop x crop window
+    whose corner (x0, y0) is listed in meta["crops"]; the rest of the image
+    is empty.  No targets."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    c = size / 2.0
+    parts, crops = [], []
+    for (px, py) in [(300.0, 260.0), (size - 300.0, size - 260.0)]:
+        sm = _surfels(rng, n_per, (0, 0, 3), (1, 1, 5), 0.002, 0.006)
+        z = sm["mean"][2].astype(np.float64)
+        u = px + rng.uniform(-spread, spread, n_per)
+        v = py + rng.uniform(-spread, spread, n_per)
+        sm["mean"] = np.ascontiguousarray(np.stack([(u - c) * z / f, (v - c) * z / f, z]).astype(np.float32))
+        parts.append(sm)
+        crops.append((int(px) - crop // 2, int(py) - crop // 2))
+    sm = {k: np.ascontiguousarray(np.concatenate([p[k] for p in parts], axis=-1)) for k in parts[0]}
+    intr = np.array([[f, f, c, c]], np.float32)
+    vm = np.array([[1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0]], np.float32)
+    return Scene(f"largest_view_{size}x{size}", [sm], [(size, size, 0)], intr, vm,
+                 meta=dict(crops=crops, crop=crop))
+
+
 def make(name):
     """Scene by name: config0..config4, config4_stress, headline."""
     table = {"config0": config0, "config1": config1, "config2": config2,

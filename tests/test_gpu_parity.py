@@ -369,6 +369,36 @@ def test_empty_and_culled(rast):
     assert float(out0["alpha"].abs().max()) == 0.0
 
 
+def test_largest_view_crops_match_oracle(rast):
+    """A 16384 x 16384 view (the largest accepted; 2^28 pixels, ~1M tiles, a
+    three-pass tile sort) with two small surfel clusters in opposite corners:
+    each cluster's crop equals the oracle's rendering of the same crop (a view
+    with the principal point shifted by the crop corner) and every pixel
+    outside the crops is exactly background."""
+    sc = scenes.largest_view_clusters()
+    gs = GpuScene.from_scene(sc)
+    size, crop = sc.views[0][0], sc.meta["crop"]
+    _say(f"largest view {size}x{size}")
+    out, ws = rast.forward(gs)
+    torch.cuda.synchronize()
+    img = {k: v.view(-1, size, size) for k, v in out.items()}
+    rest = {"alpha": img["alpha"].clone(), "rgb": img["rgb"][0].clone()}
+    for (x0, y0) in sc.meta["crops"]:
+        fx, fy, cx, cy = (float(x) for x in sc.intr[0])
+        csc = scenes.Scene("crop", sc.submaps, [(crop, crop, 0)],
+                           np.array([[fx, fy, cx - x0, cy - y0]], np.float32), sc.viewmat)
+        ref = _oracle_forward(csc)
+        keep = ~ref["flags"]
+        assert keep.mean() > 0.99
+        got = {k: v[:, y0:y0 + crop, x0:x0 + crop].reshape(v.shape[0], -1).squeeze(0) for k, v in img.items()}
+        assert float(got["alpha"].max()) > 0.5  # the cluster is there
+        assert_images_close(got, ref, keep, what=f"crop {x0},{y0}")
+        for v in rest.values():
+            v[..., y0:y0 + crop, x0:x0 + crop] = 0.0
+    for k, v in rest.items():
+        assert float(v.abs().max()) == 0.0, k
+
+
 def test_invalid_arguments(rast):
     from paper_2604_03092_amd import native
     sc = scenes.config0()
