@@ -13,6 +13,8 @@
 // dL/dH, dL/dsigma, dL/dc, dL/dn back to mean, quaternion, scales, opacity,
 // colour and the view matrix.  No atomics: each surfel is owned by one
 // thread; pose partials are reduced per block and summed by a second kernel.
+#include <cstring>
+
 #include "fm_internal.h"
 #include "fm_wave.h"
 
@@ -36,6 +38,27 @@ struct ListChunk {
     int32_t d[kListChunk];
     int count, first;
 };
+
+// Batches of up to 16 views over up to 8 submaps (the common case) travel in
+// one launch.
+constexpr int kSmallViews = 16;
+constexpr int kSmallSubs = 8;
+struct SmallSetup {
+    ViewDesc v[kSmallViews];
+    SubmapDesc s[kSmallSubs];
+    int32_t l[kSmallViews];
+    int nv, ns;
+};
+static_assert(sizeof(SmallSetup) <= 4096, "kernel arguments are limited to 4 KB");
+
+__global__ void k_write_small(SmallSetup c, ViewDesc *ov, SubmapDesc *os, int32_t *ol) {
+    const int i = threadIdx.x;
+    if (i < c.nv) {
+        ov[i] = c.v[i];
+        ol[i] = c.l[i];
+    }
+    if (i < c.ns) os[i] = c.s[i];
+}
 
 __global__ void k_write_views(ViewChunk c, ViewDesc *out) {
     int i = threadIdx.x;
@@ -470,6 +493,20 @@ __global__ __launch_bounds__(1024) void k_pose_reduce(const ViewDesc *__restrict
 
 hipError_t launch_setup(const Plan &p, void *ws, const ViewDesc *views, const SubmapDesc *subs,
                         const int32_t *vlist, hipStream_t st) {
+    if (p.V <= kSmallViews && p.S <= kSmallSubs) {
+        SmallSetup c;
+        memset(&c, 0, sizeof(c));
+        c.nv = p.V;
+        c.ns = p.S;
+        for (int i = 0; i < p.V; ++i) {
+            c.v[i] = views[i];
+            c.l[i] = vlist[i];
+        }
+        for (int i = 0; i < p.S; ++i) c.s[i] = subs[i];
+        hipLaunchKernelGGL(k_write_small, dim3(1), dim3(64), 0, st, c, at<ViewDesc>(ws, p.o_views),
+                           at<SubmapDesc>(ws, p.o_subs), at<int32_t>(ws, p.o_vlist));
+        return hipGetLastError();
+    }
     for (int f = 0; f < p.V; f += kViewChunk) {
         ViewChunk c;
         c.first = f;

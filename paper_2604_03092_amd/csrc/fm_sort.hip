@@ -547,13 +547,12 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t *__restrict__ sorte
     }
 }
 
-__global__ __launch_bounds__(256) void k_fill_u32(uint32_t *__restrict__ p, uint32_t v, int64_t n) {
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] = v;
-}
-
-// Tile ranges start empty with ts > te; the last tile-sort pass fills them.
-__global__ __launch_bounds__(256) void k_init_ranges(uint32_t *__restrict__ ts, uint32_t *__restrict__ te,
+// Start of binning: clear the status words (block 0) and start every tile
+// range empty with ts > te; the last tile-sort pass fills the ranges.
+__global__ __launch_bounds__(256) void k_init_ranges(uint32_t *__restrict__ status, int n_status,
+                                                      uint32_t *__restrict__ ts, uint32_t *__restrict__ te,
                                                       int64_t n) {
+    if (blockIdx.x == 0 && (int)threadIdx.x < n_status) status[threadIdx.x] = 0u;
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
         ts[i] = 0xFFFFFFFFu;
         te[i] = 0u;
@@ -586,8 +585,11 @@ hipError_t launch_binning(const Plan &p, void *ws, const KParams &kp, hipStream_
     uint32_t *val = at<uint32_t>(ws, p.o_val), *val2 = at<uint32_t>(ws, p.o_val2);
     uint32_t *hist = at<uint32_t>(ws, p.o_hist);
     uint32_t *tot = at<uint32_t>(ws, p.o_tot);
-    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, st, reinterpret_cast<uint32_t *>(status), 0u,
-                       (int64_t)(sizeof(Status) / 4));
+    uint32_t *ts = at<uint32_t>(ws, p.o_tstart), *te = at<uint32_t>(ws, p.o_tend);
+    const int fill_blocks = (int)((p.T + 255) / 256 < 4096 ? (p.T + 255) / 256 : 4096);
+    static_assert(sizeof(Status) / 4 <= 256, "status words are cleared by one block");
+    hipLaunchKernelGGL(k_init_ranges, dim3(fill_blocks), dim3(256), 0, st, reinterpret_cast<uint32_t *>(status),
+                       (int)(sizeof(Status) / 4), ts, te, p.T);
     // 1. stable sort of the entries by their 32-bit depth key (4 passes; the
     //    first pass starts from the identity permutation and drops the
     //    entries that cover no tile, so the later passes see only the
@@ -628,9 +630,6 @@ hipError_t launch_binning(const Plan &p, void *ws, const KParams &kp, hipStream_
 #undef FM_EMIT
     // 3. stable sort of the pairs by tile id; the last pass also writes the
     //    per-tile ranges
-    uint32_t *ts = at<uint32_t>(ws, p.o_tstart), *te = at<uint32_t>(ws, p.o_tend);
-    const int fill_blocks = (int)((p.T + 255) / 256 < 4096 ? (p.T + 255) / 256 : 4096);
-    hipLaunchKernelGGL(k_init_ranges, dim3(fill_blocks), dim3(256), 0, st, ts, te, p.T);
     uint32_t *ka = pkey, *va = pval, *kb = pkey2, *vb = pval2;
     // (the first pass drops the pairs of missed tiles and counts the rest;
     // its histogram comes from the emission)
