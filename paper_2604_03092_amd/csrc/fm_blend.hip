@@ -19,7 +19,11 @@
 // screen-space gradients of the tile are reduced with permlane swaps + DPP and
 // added into the entry's gradient slot with one coalesced 16-float atomic
 // group (plus one for the last normal component when normals carry a
-// gradient).
+// gradient).  With deterministic sums they are stored instead into a slot of
+// the pair's own (per wave of the tile), and k_det_reduce sums each entry's
+// slots in a fixed order.
+//
+// A 32x32 tile runs as four 16x16 quadrant waves over one shared list.
 #include <algorithm>
 
 #include "fm_internal.h"
