@@ -242,19 +242,41 @@ def time_warp(rast, n=2_000_000, n_keyframes=64, replays=50):
 
 def time_config(rast, name, steps):
     """Fused forward + L1 + backward of one config's whole batch, eager calls,
-    in Mpixel/s (setup and pair-buffer sizing untimed)."""
+    in Mpixel/s, at 16x16 tiles and at the tile shape the autotuner picks
+    (setup, tuning and pair-buffer sizing untimed)."""
     import torch
     from paper_2604_03092_amd.raster import GpuScene
     scene = make_workload(name)
     gs = GpuScene.from_scene(scene)
-    params = rast.params(overwrite=True)
-    out, ws = rast.forward(gs, params)
+    # the autotuner needs a workspace and capacity for its largest candidate (8x8)
+    p8 = rast.params(tile=(8, 8), overwrite=True)
+    _, ws8 = rast.forward(gs, p8)
     torch.cuda.synchronize()
-    _, n_pairs, _ = rast.query(gs, ws)
-    ws = rast.workspace(gs, params, max_pairs=int(n_pairs * 1.1) + 4096)
+    ws8 = rast.workspace(gs, p8, max_pairs=int(ws8.n_pairs * 1.1) + 4096)
     out = rast.new_outputs(gs)
     grads, dvm = gs.zero_grads()
     loss = torch.zeros(1, device="cuda")
+    chosen = rast.autotune(gs, ws8, out, grads, dvm, loss)
+    tuned = (int(chosen.tile_w), int(chosen.tile_h))
+    del ws8
+    res = dict(views=gs.n_views, pixels=gs.npx)
+    for tile in [(16, 16)] + ([tuned] if tuned != (16, 16) else []):
+        r = _time_config_tile(rast, gs, tile, steps, out, grads, dvm, loss)
+        key = "tile_16x16" if tile == (16, 16) else "tuned"
+        res[key] = dict(tile=f"{tile[0]}x{tile[1]}", **r)
+    res["autotuned_tile"] = f"{tuned[0]}x{tuned[1]}"
+    del out, grads, dvm
+    torch.cuda.empty_cache()
+    return res
+
+
+def _time_config_tile(rast, gs, tile, steps, out, grads, dvm, loss):
+    import torch
+    params = rast.params(tile=tile, overwrite=True)
+    _, ws = rast.forward(gs, params)
+    torch.cuda.synchronize()
+    _, n_pairs, _ = rast.query(gs, ws)
+    ws = rast.workspace(gs, params, max_pairs=int(n_pairs * 1.1) + 4096)
 
     def step():  # stores gradients, pose gradients and the loss (overwrite mode)
         rast.fwd_bwd_l1(gs, ws, out, grads, dvm, loss)
@@ -268,9 +290,9 @@ def time_config(rast, name, steps):
         step()
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
-    res = dict(views=gs.n_views, pixels=gs.npx, pairs=n_pairs, ms_per_step=round(dt * 1e3, 4),
-               mpixel_s=round(gs.npx / dt / 1e6, 3), views_s=round(gs.n_views / dt, 3))
-    del ws, out, grads, dvm
+    res = dict(pairs=n_pairs, ms_per_step=round(dt * 1e3, 4), mpixel_s=round(gs.npx / dt / 1e6, 3),
+               views_s=round(gs.n_views / dt, 3))
+    del ws
     torch.cuda.empty_cache()
     return res
 
