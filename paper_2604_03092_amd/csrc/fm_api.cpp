@@ -178,6 +178,7 @@ fm_status build(fm_ctx *ctx, const fm_batch *b, const fm_raster_params *prm, int
     auto grid_for = [](int64_t n) { return (int)std::max<int64_t>(1, (n + fm::kSortTile - 1) / fm::kSortTile); };
     p.sortG_e = grid_for(E);
     p.sortG_p = grid_for(max_pairs);
+    p.sortG_t = grid_for(T);
     p.scan_blocks = (int)std::max<int64_t>(1, (E + fm::kScanChunk - 1) / fm::kScanChunk);
     p.emit_blocks = std::min(p.sortG_p, fm::kMaxEmitGrid);  // a block emits one sort tile at a time
 
@@ -228,9 +229,12 @@ fm_status build(fm_ctx *ctx, const fm_batch *b, const fm_raster_params *prm, int
     p.o_pval = take(4 * (size_t)max_pairs);
     p.o_pkey2 = take(4 * (size_t)max_pairs);
     p.o_pval2 = take(4 * (size_t)max_pairs);
-    p.o_hist = take(4 * (size_t)fm::kRadix * std::max(p.sortG_e, p.sortG_p));
+    p.o_hist = take(4 * (size_t)fm::kRadix * std::max({p.sortG_e, p.sortG_p, p.sortG_t}));
     p.o_tstart = take(4 * (size_t)T);
     p.o_tend = take(4 * (size_t)T);
+    p.o_tkey = take(4 * (size_t)T);  // blend order: cost keys, sorted keys, tile ids
+    p.o_tkey2 = take(4 * (size_t)T);
+    p.o_torder = take(4 * (size_t)T);
     p.o_tfinal = take(4 * (size_t)NPX);
     p.o_nlast = take(4 * (size_t)NPX);
     p.o_ncount = take(4 * (size_t)NPX);

@@ -133,14 +133,15 @@ template <int TW, int TH> struct Slots {
 
 template <int TW, int TH>
 __device__ __forceinline__ TileCtx tile_ctx(const ViewDesc *views, int V, const uint32_t *ts,
-                                            const uint32_t *te, Slots<TW, TH> &sl) {
+                                            const uint32_t *te, const uint32_t *order, Slots<TW, TH> &sl) {
     using Gm = Geo<TW, TH>;
     TileCtx c;
     // runs of 16 consecutive blocks share an L2 (the quadrants of a tile
     // are consecutive blocks)
     const int lb = (int)xcd_chunked<16>(blockIdx.x, gridDim.x);
-    const int tile = lb / Gm::NQ;
-    c.quad = lb - tile * Gm::NQ;
+    const int rank = lb / Gm::NQ;
+    c.quad = lb - rank * Gm::NQ;
+    const int tile = (int)order[rank];  // tiles longest list first
     c.view = view_of_tile(views, V, tile);
     const ViewDesc &vd = views[c.view];
     const int local = tile - vd.tile_base;
@@ -417,6 +418,7 @@ __device__ __forceinline__ void tile_backward(const TileCtx &c, const Slots<TW, 
 template <int TW, int TH>
 __global__ __launch_bounds__(64) void k_render_fwd(const ViewDesc *__restrict__ views, int V,
                                                     const uint32_t *__restrict__ ts, const uint32_t *__restrict__ te,
+                                                    const uint32_t *__restrict__ order,
                                                     const uint32_t *__restrict__ pval, const Rec *__restrict__ rec,
                                                     KParams kp, int64_t NPX, fm_outputs out,
                                                     float *__restrict__ tfinal, uint32_t *__restrict__ nlast_out,
@@ -425,7 +427,7 @@ __global__ __launch_bounds__(64) void k_render_fwd(const ViewDesc *__restrict__ 
     __shared__ Rec srec[64];
     __shared__ uint32_t sval[64], sj[64];
     Slots<TW, TH> sl;
-    const TileCtx c = tile_ctx<TW, TH>(views, V, ts, te, sl);
+    const TileCtx c = tile_ctx<TW, TH>(views, V, ts, te, order, sl);
     float acc[Gm::NB][8], T[Gm::NB];
     uint32_t slast[Gm::NB], nc[Gm::NB];
     tile_forward<TW, TH, true>(c, sl, pval, rec, kp, srec, sval, pm, sj, acc, T, slast, nc);
@@ -450,6 +452,7 @@ __global__ __launch_bounds__(64) void k_render_fwd(const ViewDesc *__restrict__ 
 template <int TW, int TH, bool HAS_N, bool DET>
 __global__ __launch_bounds__(64) void k_render_bwd(const ViewDesc *__restrict__ views, int V,
                                                     const uint32_t *__restrict__ ts, const uint32_t *__restrict__ te,
+                                                    const uint32_t *__restrict__ order,
                                                     const uint32_t *__restrict__ pval, const Rec *__restrict__ rec,
                                                     KParams kp, int64_t NPX, fm_outputs out, fm_grad_outputs gout,
                                                     const float *__restrict__ tfinal,
@@ -459,7 +462,7 @@ __global__ __launch_bounds__(64) void k_render_bwd(const ViewDesc *__restrict__ 
     __shared__ Rec srec[64];
     __shared__ uint32_t sval[64], sj[64];
     Slots<TW, TH> sl;
-    const TileCtx c = tile_ctx<TW, TH>(views, V, ts, te, sl);
+    const TileCtx c = tile_ctx<TW, TH>(views, V, ts, te, order, sl);
     float g[Gm::NB][8], S[Gm::NB], Tf[Gm::NB];
     uint32_t bound[Gm::NB];
 #pragma unroll
@@ -493,6 +496,7 @@ __global__ __launch_bounds__(64) void k_render_bwd(const ViewDesc *__restrict__ 
 template <int TW, int TH, bool DET>
 __global__ __launch_bounds__(64) void k_render_fused(const ViewDesc *__restrict__ views, int V,
                                                       const uint32_t *__restrict__ ts, const uint32_t *__restrict__ te,
+                                                    const uint32_t *__restrict__ order,
                                                       const uint32_t *__restrict__ pval, const Rec *__restrict__ rec,
                                                       KParams kp, int64_t NPX, fm_outputs out, LossArgs la,
                                                       float *__restrict__ tfinal, uint32_t *__restrict__ nlast_out,
@@ -502,7 +506,7 @@ __global__ __launch_bounds__(64) void k_render_fused(const ViewDesc *__restrict_
     __shared__ Rec srec[64];
     __shared__ uint32_t sval[64], sj[64];
     Slots<TW, TH> sl;
-    const TileCtx c = tile_ctx<TW, TH>(views, V, ts, te, sl);
+    const TileCtx c = tile_ctx<TW, TH>(views, V, ts, te, order, sl);
     float acc[Gm::NB][8], T[Gm::NB];
     uint32_t slast[Gm::NB], nc[Gm::NB];
     tile_forward<TW, TH, false>(c, sl, pval, rec, kp, srec, sval, pm, sj, acc, T, slast, nc);
@@ -581,7 +585,7 @@ hipError_t fwd_t(const Plan &p, void *ws, const KParams &kp, const fm_outputs &o
     const uint32_t *pval = at<uint32_t>(ws, p.pairs_in_alt ? p.o_pval2 : p.o_pval);
     hipLaunchKernelGGL((k_render_fwd<TW, TH>), dim3((unsigned)(p.T * Geo<TW, TH>::NQ)), dim3(64), 0, st,
                        at<ViewDesc>(ws, p.o_views), p.V, at<uint32_t>(ws, p.o_tstart),
-                       at<uint32_t>(ws, p.o_tend), pval, at<Rec>(ws, p.o_rec), kp, p.NPX, out,
+                       at<uint32_t>(ws, p.o_tend), at<uint32_t>(ws, p.o_torder), pval, at<Rec>(ws, p.o_rec), kp, p.NPX, out,
                        at<float>(ws, p.o_tfinal), at<uint32_t>(ws, p.o_nlast), at<uint32_t>(ws, p.o_ncount),
                        pair_meta(p, ws));
     return hipGetLastError();
@@ -593,7 +597,7 @@ void bwd_launch(const Plan &p, void *ws, const KParams &kp, const fm_outputs &ou
     const uint32_t *pval = at<uint32_t>(ws, p.pairs_in_alt ? p.o_pval2 : p.o_pval);
     hipLaunchKernelGGL((k_render_bwd<TW, TH, HAS_N, DET>), dim3((unsigned)(p.T * Geo<TW, TH>::NQ)), dim3(64), 0,
                        st, at<ViewDesc>(ws, p.o_views), p.V, at<uint32_t>(ws, p.o_tstart),
-                       at<uint32_t>(ws, p.o_tend), pval, at<Rec>(ws, p.o_rec), kp, p.NPX, out, g,
+                       at<uint32_t>(ws, p.o_tend), at<uint32_t>(ws, p.o_torder), pval, at<Rec>(ws, p.o_rec), kp, p.NPX, out, g,
                        at<float>(ws, p.o_tfinal), at<uint32_t>(ws, p.o_nlast), at<float>(ws, p.o_grad),
                        pair_meta(p, ws));
 }
@@ -617,7 +621,7 @@ void fused_launch(const Plan &p, void *ws, const KParams &kp, const LossArgs &la
     const uint32_t *pval = at<uint32_t>(ws, p.pairs_in_alt ? p.o_pval2 : p.o_pval);
     hipLaunchKernelGGL((k_render_fused<TW, TH, DET>), dim3((unsigned)(p.T * Geo<TW, TH>::NQ)), dim3(64), 0, st,
                        at<ViewDesc>(ws, p.o_views), p.V, at<uint32_t>(ws, p.o_tstart),
-                       at<uint32_t>(ws, p.o_tend), pval, at<Rec>(ws, p.o_rec), kp, p.NPX, out, la,
+                       at<uint32_t>(ws, p.o_tend), at<uint32_t>(ws, p.o_torder), pval, at<Rec>(ws, p.o_rec), kp, p.NPX, out, la,
                        at<float>(ws, p.o_tfinal), at<uint32_t>(ws, p.o_nlast), at<float>(ws, p.o_grad),
                        at<float>(ws, p.o_loss), pair_meta(p, ws));
 }

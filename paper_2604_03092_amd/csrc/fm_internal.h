@@ -29,7 +29,7 @@ constexpr int kScanChunk = 2048;   // entries per block of the count scan
 constexpr int kSortTile = 4096;     // items per block of a radix pass
 constexpr int kEmitChunk = 2048;   // pairs per chunk of the emission blocks (two per sort tile)
 constexpr int kMaxEmitGrid = 4096;
-constexpr int kMaxPasses = 8;      // radix passes per binning (4 depth + up to 4 tile)
+constexpr int kMaxPasses = 9;      // radix passes per binning (4 depth + up to 4 tile + 1 blend order)
 
 // Per-view descriptor, written into the workspace at the start of each call.
 struct ViewDesc {
@@ -139,7 +139,7 @@ struct Plan {
     int tile_w = 16, tile_h = 16;
     int tile_bits = 1;
     int pair_passes = 1;
-    int sortG_e = 1, sortG_p = 1;
+    int sortG_e = 1, sortG_p = 1, sortG_t = 1;
     int scan_blocks = 1;
     int emit_blocks = 1;
     int a7_blocks = 0;      // total blocks of the backward projection
@@ -147,7 +147,8 @@ struct Plan {
     size_t o_views = 0, o_subs = 0, o_vlist = 0, o_status = 0, o_rec = 0, o_key = 0, o_cnt = 0,
            o_key2 = 0, o_val = 0, o_val2 = 0, o_scan = 0, o_pkey = 0, o_pval = 0, o_pkey2 = 0,
            o_pval2 = 0, o_hist = 0, o_tstart = 0, o_tend = 0, o_tfinal = 0, o_nlast = 0, o_ncount = 0, o_grad = 0,
-           o_pose = 0, o_loss = 0, o_tot = 0, o_ell = 0, o_chunk = 0, o_meta = 0, o_part = 0;
+           o_pose = 0, o_loss = 0, o_tot = 0, o_ell = 0, o_chunk = 0, o_meta = 0, o_part = 0, o_tkey = 0,
+           o_tkey2 = 0, o_torder = 0;
     size_t bytes = 0;
     // deterministic gradients: the sorted lists hold emission indices, o_meta
     // maps them to pair values, and the adjoint writes one partial slot per

@@ -559,6 +559,19 @@ __global__ __launch_bounds__(256) void k_init_ranges(uint32_t *__restrict__ stat
     }
 }
 
+// Blend order: a tile's cost key is 255 minus 16 log2(1 + list length)
+// (capped), so one stable 8-bit pass lists the tiles longest first; the
+// blend's workgroups take tiles in that order, so long tiles start early and
+// short ones fill the end of the launch.
+__global__ __launch_bounds__(256) void k_tile_cost(const uint32_t *__restrict__ ts, const uint32_t *__restrict__ te,
+                                                    int64_t n, uint32_t *__restrict__ key) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const uint32_t len = te[i] > ts[i] ? te[i] - ts[i] : 0u;  // an empty tile has ts > te
+        const float lv = 16.f * __log2f((float)len + 1.f);
+        key[i] = 255u - (lv < 255.f ? (uint32_t)lv : 255u);
+    }
+}
+
 void radix_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout, const uint32_t *n_dev,
                 uint32_t n_host, int shift, uint32_t *hist, int G, uint32_t *tot, int drop, uint32_t *n_kept,
                 hipStream_t s, const uint32_t *key_subst = nullptr, bool hist_ready = false,
@@ -641,6 +654,11 @@ hipError_t launch_binning(const Plan &p, void *ws, const KParams &kp, hipStream_
         uint32_t *t = ka; ka = kb; kb = t;
         t = va; va = vb; vb = t;
     }
+    // 4. the blend's tile order, longest list first
+    uint32_t *tkey = at<uint32_t>(ws, p.o_tkey), *tkey2 = at<uint32_t>(ws, p.o_tkey2);
+    hipLaunchKernelGGL(k_tile_cost, dim3(fill_blocks), dim3(256), 0, st, ts, te, p.T, tkey);
+    radix_pass(tkey, nullptr, tkey2, at<uint32_t>(ws, p.o_torder), nullptr, (uint32_t)p.T, 0, hist, p.sortG_t,
+               tot + 8 * kRadix, 0, nullptr, st);
     return hipGetLastError();
 }
 
