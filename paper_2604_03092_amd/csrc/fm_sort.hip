@@ -562,13 +562,30 @@ __global__ __launch_bounds__(256) void k_init_ranges(uint32_t *__restrict__ stat
 // Blend order: a tile's cost key is 255 minus 16 log2(1 + list length)
 // (capped), so one stable 8-bit pass lists the tiles longest first; the
 // blend's workgroups take tiles in that order, so long tiles start early and
-// short ones fill the end of the launch.
+// short ones fill the end of the launch.  A block keys the tiles of one
+// 4096-item sort tile and writes that sort tile's digit histogram for the
+// pass.
 __global__ __launch_bounds__(256) void k_tile_cost(const uint32_t *__restrict__ ts, const uint32_t *__restrict__ te,
-                                                    int64_t n, uint32_t *__restrict__ key) {
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-        const uint32_t len = te[i] > ts[i] ? te[i] - ts[i] : 0u;  // an empty tile has ts > te
-        const float lv = 16.f * __log2f((float)len + 1.f);
-        key[i] = 255u - (lv < 255.f ? (uint32_t)lv : 255u);
+                                                    int64_t n, uint32_t *__restrict__ key,
+                                                    uint32_t *__restrict__ hist, int G) {
+    __shared__ uint32_t s_hist[kRadix];
+    static_assert(kRadix == 256, "one digit per thread");
+    for (uint32_t t = blockIdx.x; t < (uint32_t)G; t += gridDim.x) {
+        __syncthreads();  // the previous sort tile's histogram has been read
+        s_hist[threadIdx.x] = 0u;
+        __syncthreads();
+        for (int k = 0; k < kSortTile / 256; ++k) {
+            const int64_t i = (int64_t)t * kSortTile + k * 256 + threadIdx.x;
+            if (i < n) {
+                const uint32_t len = te[i] > ts[i] ? te[i] - ts[i] : 0u;  // an empty tile has ts > te
+                const float lv = 16.f * __log2f((float)len + 1.f);
+                const uint32_t kk = 255u - (lv < 255.f ? (uint32_t)lv : 255u);
+                key[i] = kk;
+                atomicAdd(&s_hist[kk], 1u);
+            }
+        }
+        __syncthreads();
+        hist[threadIdx.x * (uint32_t)G + t] = s_hist[threadIdx.x];
     }
 }
 
@@ -656,9 +673,10 @@ hipError_t launch_binning(const Plan &p, void *ws, const KParams &kp, hipStream_
     }
     // 4. the blend's tile order, longest list first
     uint32_t *tkey = at<uint32_t>(ws, p.o_tkey), *tkey2 = at<uint32_t>(ws, p.o_tkey2);
-    hipLaunchKernelGGL(k_tile_cost, dim3(fill_blocks), dim3(256), 0, st, ts, te, p.T, tkey);
+    hipLaunchKernelGGL(k_tile_cost, dim3((unsigned)std::min(p.sortG_t, kMaxEmitGrid)), dim3(256), 0, st, ts, te,
+                       p.T, tkey, hist, p.sortG_t);
     radix_pass(tkey, nullptr, tkey2, at<uint32_t>(ws, p.o_torder), nullptr, (uint32_t)p.T, 0, hist, p.sortG_t,
-               tot + 8 * kRadix, 0, nullptr, st);
+               tot + 8 * kRadix, 0, nullptr, st, nullptr, true);
     return hipGetLastError();
 }
 
