@@ -265,6 +265,7 @@ def time_config(rast, name, steps):
         key = "tile_16x16" if tile == (16, 16) else "tuned"
         res[key] = dict(tile=f"{tile[0]}x{tile[1]}", **r)
     res["autotuned_tile"] = f"{tuned[0]}x{tuned[1]}"
+    res["autotuned_order"] = "longest list first" if chosen.tile_order == 1 else "image order"
     del out, grads, dvm
     torch.cuda.empty_cache()
     return res

@@ -146,6 +146,13 @@ typedef struct {
                                batch renders, every view's dL_dviewmat row and
                                *loss are overwritten; submaps that no view renders
                                are left untouched.  Other values are INVALID_ARG. */
+    int32_t tile_order;     /* order in which the blend takes the tiles: 1 = longest
+                               list first (long tiles start early and short ones
+                               fill the end of the launch); 2 = image order
+                               (neighbouring tiles run together and share surfel
+                               records in cache); 0 = the order fm_autotune chose
+                               for this batch and tile shape, else 1.  Other values
+                               are INVALID_ARG.                                    */
 } fm_raster_params;
 
 /* Output planes (device, float32): rgb[3][P], depth[P], normal[3][P],

@@ -27,7 +27,10 @@ struct fm_ctx {
     std::string name;
     int n_cu = 0;
     std::string last_error;
-    std::map<std::string, std::pair<int, int>> tuned;  // batch signature -> tile shape
+    struct Tuned {
+        int tw, th, order;
+    };
+    std::map<std::string, Tuned> tuned;  // batch signature -> tile shape and tile order
     // optional phase timing (benchmarks): events recorded between phases
     bool timing = false;
     hipEvent_t ev[8] = {};
@@ -77,22 +80,23 @@ struct Built {
     std::vector<int32_t> vlist;
 };
 
-fm_status resolve_tile(fm_ctx *ctx, const fm_batch *b, const fm_raster_params *prm, int &tw, int &th) {
+fm_status resolve_tile(fm_ctx *ctx, const fm_batch *b, const fm_raster_params *prm, int &tw, int &th,
+                       int &order) {
     tw = prm->tile_w;
     th = prm->tile_h;
+    auto it = ctx->tuned.find(tune_key(b, prm));
+    const bool hit = it != ctx->tuned.end();
     if (tw == 0 && th == 0) {
-        auto it = ctx->tuned.find(tune_key(b, prm));
-        if (it != ctx->tuned.end()) {
-            tw = it->second.first;
-            th = it->second.second;
-        } else {
-            tw = 16;
-            th = 16;
-        }
+        tw = hit ? it->second.tw : 16;
+        th = hit ? it->second.th : 16;
     }
     if (!fm::tile_shape_supported(tw, th))
         return fail(ctx, FM_ERR_UNSUPPORTED, "unsupported tile shape " + std::to_string(tw) + "x" +
                                                  std::to_string(th) + " (use 8x8, 16x8, 16x16, 32x8 or 32x32)");
+    if (prm->tile_order < 0 || prm->tile_order > 2)
+        return fail(ctx, FM_ERR_INVALID_ARG, "tile_order must be 0, 1 or 2");
+    order = prm->tile_order;
+    if (order == 0) order = (hit && it->second.tw == tw && it->second.th == th) ? it->second.order : 1;
     return FM_OK;
 }
 
@@ -116,12 +120,13 @@ fm_status build(fm_ctx *ctx, const fm_batch *b, const fm_raster_params *prm, int
         if (!std::isfinite(prm->bg[k])) return fail(ctx, FM_ERR_INVALID_ARG, "background must be finite");
     if (max_pairs < 1 || max_pairs > (int64_t)0x7FFFFFFF)
         return fail(ctx, FM_ERR_INVALID_ARG, "max_pairs must be in [1, 2^31-1]");
-    int tw, th;
-    fm_status s = resolve_tile(ctx, b, prm, tw, th);
+    int tw, th, order;
+    fm_status s = resolve_tile(ctx, b, prm, tw, th, order);
     if (s != FM_OK) return s;
 
     Plan &p = out.plan;
     p = Plan();
+    p.lpt = order == 1;
     p.V = b->n_views;
     p.S = b->n_submaps;
     p.tile_w = tw;
@@ -367,7 +372,7 @@ fm_status check_loss(fm_ctx *ctx, const fm_l1_loss *ls) {
     return FM_OK;
 }
 
-// --- tiny JSON cache: {"signature": [tw, th], ...} ---------------------------
+// --- tiny JSON cache: {"signature": [tw, th, tile order], ...} ----------------
 void load_cache(fm_ctx *ctx, const char *path) {
     std::ifstream f(path);
     if (!f) return;
@@ -389,9 +394,10 @@ void load_cache(fm_ctx *ctx, const char *path) {
             pos = q1 + 1;
             continue;
         }
-        int tw = 0, th = 0;
-        if (sscanf(s.c_str() + lb, "[%d, %d]", &tw, &th) == 2 && fm::tile_shape_supported(tw, th))
-            ctx->tuned[key] = {tw, th};
+        int tw = 0, th = 0, order = 1;
+        const int got = sscanf(s.c_str() + lb, "[%d, %d, %d]", &tw, &th, &order);
+        if (got >= 2 && fm::tile_shape_supported(tw, th))
+            ctx->tuned[key] = {tw, th, (got == 3 && (order == 1 || order == 2)) ? order : 1};
         pos = rb + 1;
     }
 }
@@ -402,7 +408,7 @@ void save_cache(fm_ctx *ctx, const char *path) {
     f << "{\n";
     size_t k = 0;
     for (auto &kv : ctx->tuned) {
-        f << "  \"" << kv.first << "\": [" << kv.second.first << ", " << kv.second.second << "]";
+        f << "  \"" << kv.first << "\": [" << kv.second.tw << ", " << kv.second.th << ", " << kv.second.order << "]";
         f << (++k < ctx->tuned.size() ? ",\n" : "\n");
     }
     f << "}\n";
@@ -664,8 +670,9 @@ fm_status fm_autotune(fm_ctx *ctx, const fm_batch *b, const fm_raster_params *pr
     *chosen = *prm;
     auto hit = ctx->tuned.find(sig);
     if (hit != ctx->tuned.end()) {
-        chosen->tile_w = hit->second.first;
-        chosen->tile_h = hit->second.second;
+        chosen->tile_w = hit->second.tw;
+        chosen->tile_h = hit->second.th;
+        chosen->tile_order = hit->second.order;
         return FM_OK;
     }
     const int shapes[5][2] = {{16, 16}, {8, 8}, {16, 8}, {32, 8}, {32, 32}};
@@ -683,12 +690,14 @@ fm_status fm_autotune(fm_ctx *ctx, const fm_batch *b, const fm_raster_params *pr
     FM_TRY_HIP(hipEventCreate(&ev.e[1]), "hipEventCreate");
     hipEvent_t e0 = ev.e[0], e1 = ev.e[1];
     float best = 1e30f;
-    int bw = 16, bh = 16;
+    int bw = 16, bh = 16, bo = 1;
     bool any = false;
-    for (auto &sh : shapes) {
+    for (int cand = 0; cand < 10; ++cand) {  // every shape with both tile orders
+        const int *sh = shapes[cand / 2];
         fm_raster_params q = *prm;
         q.tile_w = sh[0];
         q.tile_h = sh[1];
+        q.tile_order = 1 + cand % 2;
         Built bt;
         s = build(ctx, b, &q, max_pairs, grads, true, bt);
         if (s != FM_OK || bt.plan.bytes > ws_bytes) continue;
@@ -713,13 +722,15 @@ fm_status fm_autotune(fm_ctx *ctx, const fm_batch *b, const fm_raster_params *pr
             best = ms;
             bw = sh[0];
             bh = sh[1];
+            bo = q.tile_order;
         }
     }
     if (!any) return s != FM_OK ? s : fail(ctx, FM_ERR_WORKSPACE, "no tile shape fits the workspace and capacity");
-    ctx->tuned[sig] = {bw, bh};
+    ctx->tuned[sig] = {bw, bh, bo};
     if (cache_path) save_cache(ctx, cache_path);
     chosen->tile_w = bw;
     chosen->tile_h = bh;
+    chosen->tile_order = bo;
     return FM_OK;
 }
 

@@ -141,7 +141,7 @@ __device__ __forceinline__ TileCtx tile_ctx(const ViewDesc *views, int V, const 
     const int lb = (int)xcd_chunked<16>(blockIdx.x, gridDim.x);
     const int rank = lb / Gm::NQ;
     c.quad = lb - rank * Gm::NQ;
-    const int tile = (int)order[rank];  // tiles longest list first
+    const int tile = order ? (int)order[rank] : rank;  // longest list first, or image order
     c.view = view_of_tile(views, V, tile);
     const ViewDesc &vd = views[c.view];
     const int local = tile - vd.tile_base;
@@ -572,6 +572,10 @@ __global__ __launch_bounds__(1024) void k_loss_reduce(const float *__restrict__ 
     }
 }
 
+// The blend's tile order: a permutation written by the binning, or none
+// (image order).
+const uint32_t *tile_order(const Plan &p, void *ws) { return p.lpt ? at<uint32_t>(ws, p.o_torder) : nullptr; }
+
 PairMeta pair_meta(const Plan &p, void *ws) {
     PairMeta pm;
     pm.meta = p.det ? at<uint32_t>(ws, p.o_meta) : nullptr;
@@ -585,7 +589,7 @@ hipError_t fwd_t(const Plan &p, void *ws, const KParams &kp, const fm_outputs &o
     const uint32_t *pval = at<uint32_t>(ws, p.pairs_in_alt ? p.o_pval2 : p.o_pval);
     hipLaunchKernelGGL((k_render_fwd<TW, TH>), dim3((unsigned)(p.T * Geo<TW, TH>::NQ)), dim3(64), 0, st,
                        at<ViewDesc>(ws, p.o_views), p.V, at<uint32_t>(ws, p.o_tstart),
-                       at<uint32_t>(ws, p.o_tend), at<uint32_t>(ws, p.o_torder), pval, at<Rec>(ws, p.o_rec), kp, p.NPX, out,
+                       at<uint32_t>(ws, p.o_tend), tile_order(p, ws), pval, at<Rec>(ws, p.o_rec), kp, p.NPX, out,
                        at<float>(ws, p.o_tfinal), at<uint32_t>(ws, p.o_nlast), at<uint32_t>(ws, p.o_ncount),
                        pair_meta(p, ws));
     return hipGetLastError();
@@ -597,7 +601,7 @@ void bwd_launch(const Plan &p, void *ws, const KParams &kp, const fm_outputs &ou
     const uint32_t *pval = at<uint32_t>(ws, p.pairs_in_alt ? p.o_pval2 : p.o_pval);
     hipLaunchKernelGGL((k_render_bwd<TW, TH, HAS_N, DET>), dim3((unsigned)(p.T * Geo<TW, TH>::NQ)), dim3(64), 0,
                        st, at<ViewDesc>(ws, p.o_views), p.V, at<uint32_t>(ws, p.o_tstart),
-                       at<uint32_t>(ws, p.o_tend), at<uint32_t>(ws, p.o_torder), pval, at<Rec>(ws, p.o_rec), kp, p.NPX, out, g,
+                       at<uint32_t>(ws, p.o_tend), tile_order(p, ws), pval, at<Rec>(ws, p.o_rec), kp, p.NPX, out, g,
                        at<float>(ws, p.o_tfinal), at<uint32_t>(ws, p.o_nlast), at<float>(ws, p.o_grad),
                        pair_meta(p, ws));
 }
@@ -621,7 +625,7 @@ void fused_launch(const Plan &p, void *ws, const KParams &kp, const LossArgs &la
     const uint32_t *pval = at<uint32_t>(ws, p.pairs_in_alt ? p.o_pval2 : p.o_pval);
     hipLaunchKernelGGL((k_render_fused<TW, TH, DET>), dim3((unsigned)(p.T * Geo<TW, TH>::NQ)), dim3(64), 0, st,
                        at<ViewDesc>(ws, p.o_views), p.V, at<uint32_t>(ws, p.o_tstart),
-                       at<uint32_t>(ws, p.o_tend), at<uint32_t>(ws, p.o_torder), pval, at<Rec>(ws, p.o_rec), kp, p.NPX, out, la,
+                       at<uint32_t>(ws, p.o_tend), tile_order(p, ws), pval, at<Rec>(ws, p.o_rec), kp, p.NPX, out, la,
                        at<float>(ws, p.o_tfinal), at<uint32_t>(ws, p.o_nlast), at<float>(ws, p.o_grad),
                        at<float>(ws, p.o_loss), pair_meta(p, ws));
 }

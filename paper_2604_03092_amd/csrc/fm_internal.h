@@ -155,6 +155,7 @@ struct Plan {
     // (pair, wave of the tile) at o_part, summed per entry in emission order
     bool det = false;
     bool overwrite = false;  // store (not add) surfel gradients, pose gradients and the loss
+    bool lpt = true;         // blend takes tiles longest list first (else image order)
     int nq = 1;  // waves per tile (four 16x16 quadrants of a 32x32 tile)
     bool pairs_in_alt = false;  // final sorted pairs live in the *2 buffers
 };

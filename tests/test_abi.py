@@ -52,7 +52,7 @@ def test_host_only_calls(lib):
     lib.fm_default_params(ctypes.byref(p))
     assert p.tile_w == 16 and p.tile_h == 16 and abs(p.alpha_max - 0.99) < 1e-7
     assert abs(p.alpha_min - 1 / 255) < 1e-9 and abs(p.t_min - 1e-4) < 1e-10 and p.rho_max == 3.0
-    assert p.deterministic == 0 and p.overwrite == 0
+    assert p.deterministic == 0 and p.overwrite == 0 and p.tile_order == 0
     assert lib.fm_version() >= 10000
     assert lib.fm_status_string(2) == b"pair capacity exceeded"
     # tile count is host arithmetic
@@ -76,7 +76,8 @@ int main(void) {
   S(fm_grad_outputs) S(fm_l1_loss) S(fm_adam_tensor) S(fm_adam_config) S(fm_pixel_map) S(fm_sim3)
   S(fm_fusion_params) S(fm_surfel_buffer) O(fm_surfel_buffer, capacity) O(fm_sim3, t)
   O(fm_batch, views) O(fm_batch, intr) O(fm_batch, viewmat) O(fm_raster_params, bg)
-  O(fm_raster_params, tile_w) O(fm_raster_params, deterministic) O(fm_l1_loss, w_rgb) O(fm_surfels, color) O(fm_adam_tensor, n)
+  O(fm_raster_params, tile_w) O(fm_raster_params, deterministic) O(fm_raster_params, tile_order)
+  O(fm_l1_loss, w_rgb) O(fm_surfels, color) O(fm_adam_tensor, n)
   O(fm_adam_tensor, lr) O(fm_adam_tensor, kind)
   return 0;
 }
@@ -105,6 +106,7 @@ def test_ctypes_layout_matches_header():
     assert int(vals["fm_raster_params.bg"]) == native.FmRasterParams.bg.offset
     assert int(vals["fm_raster_params.tile_w"]) == native.FmRasterParams.tile_w.offset
     assert int(vals["fm_raster_params.deterministic"]) == native.FmRasterParams.deterministic.offset
+    assert int(vals["fm_raster_params.tile_order"]) == native.FmRasterParams.tile_order.offset
     assert int(vals["fm_l1_loss.w_rgb"]) == native.FmL1Loss.w_rgb.offset
     assert int(vals["fm_surfels.color"]) == native.FmSurfels.color.offset
     assert int(vals["fm_surfel_buffer.capacity"]) == native.FmSurfelBuffer.capacity.offset

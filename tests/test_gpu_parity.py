@@ -57,12 +57,14 @@ def test_config0_forward_and_pairs(rast, tile):
 
 
 def test_tile_shape_does_not_change_images(rast):
+    """Images are bitwise the same for every tile shape and both tile orders."""
     sc = scenes.random_scene(5, 20000, 200, 136, scale_lo=0.02, scale_hi=0.15)
     gs = GpuScene.from_scene(sc)
     ref = None
-    for tile in [(16, 16), (8, 8), (16, 8), (32, 8), (32, 32)]:
-        _say(f"tile invariance {tile}")
-        out, _ = rast.forward(gs, rast.params(tile=tile))
+    for tile, order in [((16, 16), 1), ((16, 16), 2), ((8, 8), 1), ((16, 8), 2), ((32, 8), 1), ((32, 32), 1),
+                        ((32, 32), 2)]:
+        _say(f"tile invariance {tile} order {order}")
+        out, _ = rast.forward(gs, rast.params(tile=tile, tile_order=order))
         got = {k: v.cpu().numpy() for k, v in out.items()}
         if ref is None:
             ref = got
@@ -410,7 +412,7 @@ def test_invalid_arguments(rast):
         with pytest.raises(native.FmError) as e:
             rast.workspace(gs, rast.params(**bad_params))
         assert e.value.status == native.FM_ERR_INVALID_ARG, bad_params
-    for field, value in (("deterministic", 2), ("overwrite", -1)):
+    for field, value in (("deterministic", 2), ("overwrite", -1), ("tile_order", 3)):
         p = rast.params()
         setattr(p, field, value)
         with pytest.raises(native.FmError) as e:

@@ -148,12 +148,13 @@ def test_autotune_and_cache(rast, tmp_path):
     _say("autotune")
     chosen = rast.autotune(gs, ws, out, grads, dvm, loss, cache_path=path)
     assert (chosen.tile_w, chosen.tile_h) in [(16, 16), (8, 8), (16, 8), (32, 8), (32, 32)]
+    assert chosen.tile_order in (1, 2)
     data = json.load(open(path))
-    assert list(data.values())[0] == [chosen.tile_w, chosen.tile_h]
+    assert list(data.values())[0] == [chosen.tile_w, chosen.tile_h, chosen.tile_order]
     # a fresh context reads the cache; tile 0x0 then means "the tuned shape"
     r2 = Rasterizer()
     chosen2 = r2.autotune(gs, ws, out, grads, dvm, loss, cache_path=path)
-    assert (chosen2.tile_w, chosen2.tile_h) == (chosen.tile_w, chosen.tile_h)
+    assert (chosen2.tile_w, chosen2.tile_h, chosen2.tile_order) == (chosen.tile_w, chosen.tile_h, chosen.tile_order)
     auto = r2.params(tile=(0, 0))
     o2, _ = r2.forward(gs, auto)
     ref, _ = r2.forward(gs, r2.params(tile=(chosen.tile_w, chosen.tile_h)))
