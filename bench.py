@@ -305,6 +305,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="headline")
     ap.add_argument("--tile", default="16x16")
+    ap.add_argument("--tile-order", type=int, default=1, choices=(1, 2),
+                    help="blend tile order: 1 longest list first, 2 image order")
     ap.add_argument("--no-graph", action="store_true", help="time eager calls instead of a graph replay")
     ap.add_argument("--deterministic", action="store_true",
                     help="bitwise reproducible gradients (per-pair partials summed in a fixed order)")
@@ -348,7 +350,8 @@ def main():
     tw, th = (int(x) for x in args.tile.split("x"))
     # the step stores its gradients, pose gradients and loss (overwrite mode),
     # so no clearing kernels run between steps
-    params = rast.params(tile=(tw, th), deterministic=args.deterministic, overwrite=True)
+    params = rast.params(tile=(tw, th), deterministic=args.deterministic, overwrite=True,
+                         tile_order=args.tile_order)
 
     # size the pair buffer from one eager forward (not timed)
     out, ws = rast.forward(gs, params)
@@ -524,6 +527,7 @@ def main():
                    "surfels": int(sum(sm["opacity"].shape[0] for sm in scene.submaps)),
                    "tile": f"{tw}x{th}", "mode": "hipgraph" if graph is not None else "eager",
                    "deterministic": bool(args.deterministic),
+                   "tile_order": "longest list first" if args.tile_order == 1 else "image order",
                    "pairs": n_pairs},
         "views_per_s": round(views_s, 3),
         "plain": plain,
