@@ -148,16 +148,22 @@ def test_deterministic_fused_is_reproducible(rast, tile):
     _say(f"deterministic fused tile={tile}")
     ws_d = rast.workspace(gs, rast.params(tile=tile, deterministic=True), max_pairs=400_000)
     ws_n = rast.workspace(gs, rast.params(tile=tile), max_pairs=400_000)
+    # the same sums in image tile order: the deterministic result does not
+    # depend on the order in which tiles run
+    ws_i = rast.workspace(gs, rast.params(tile=tile, deterministic=True, tile_order=2), max_pairs=400_000)
     img_d, loss_d, g_d = _fused_run(rast, gs, ws_d)
     img_d2, loss_d2, g_d2 = _fused_run(rast, gs, ws_d)
+    img_i, loss_i, g_i = _fused_run(rast, gs, ws_i)
     img_n, loss_n, g_n = _fused_run(rast, gs, ws_n)
     assert loss_d == loss_d2
     for k in g_d:
         assert np.array_equal(g_d[k], g_d2[k]), k
+        assert np.array_equal(g_d[k], g_i[k]), k
         assert_grad_close(g_d[k], g_n[k], f"det-vs-atomic {k}", rel=1e-4)
     for k in img_d:
         assert np.array_equal(img_d[k], img_d2[k]), k
         assert np.array_equal(img_d[k], img_n[k]), k
+        assert np.array_equal(img_d[k], img_i[k]), k
     assert loss_d == loss_n
 
 
