@@ -272,10 +272,10 @@ fm_status fm_phase_times(fm_ctx *ctx, float *ms, int n);
 /* Total tile count of a batch for the given tile shape. */
 fm_status fm_tile_count(const fm_batch *batch, const fm_raster_params *params, int64_t *n_tiles);
 
-/* Autotuner: times fm_fwd_bwd_l1 over the supported tile shapes on this
- * batch (outputs, gradients and the loss are overwritten/accumulated while
- * it runs) and writes the fastest shape into *chosen (a copy of *params
- * with tile_w/tile_h set).  The choice is cached in the context under the
+/* Autotuner: times fm_fwd_bwd_l1 over the supported tile shapes, each with
+ * both tile orders, on this batch (outputs, gradients and the loss are
+ * overwritten/accumulated while it runs) and writes the fastest into
+ * *chosen (a copy of *params with tile_w, tile_h and tile_order set).  The choice is cached in the context under the
  * batch's shape signature and the deterministic flag (the two modes tune
  * separately) and, if cache_path is not NULL, in a JSON file read back by
  * later contexts.  Shapes whose workspace (fm_workspace_size) exceeds
