@@ -275,10 +275,10 @@ fm_status fm_tile_count(const fm_batch *batch, const fm_raster_params *params, i
 /* Autotuner: times fm_fwd_bwd_l1 over the supported tile shapes, each with
  * both tile orders, on this batch (outputs, gradients and the loss are
  * overwritten/accumulated while it runs) and writes the fastest into
- * *chosen (a copy of *params with tile_w, tile_h and tile_order set).  The choice is cached in the context under the
- * batch's shape signature and the deterministic flag (the two modes tune
- * separately) and, if cache_path is not NULL, in a JSON file read back by
- * later contexts.  Shapes whose workspace (fm_workspace_size) exceeds
+ * *chosen (a copy of *params with tile_w, tile_h and tile_order set).  The
+ * choice is cached in the context under the batch's shape signature and the
+ * deterministic flag (the two modes tune separately) and, if cache_path is
+ * not NULL, in a JSON file read back by later contexts.  Shapes whose workspace (fm_workspace_size) exceeds
  * ws_bytes or whose pairs exceed max_pairs are skipped; without
  * deterministic sums the 8x8 workspace is the largest.  Synchronous. */
 fm_status fm_autotune(fm_ctx *ctx, const fm_batch *batch, const fm_raster_params *params,
