@@ -151,8 +151,10 @@ typedef struct {
                                fill the end of the launch); 2 = image order
                                (neighbouring tiles run together and share surfel
                                records in cache); 0 = the order fm_autotune chose
-                               for this batch and tile shape, else 1.  Other values
-                               are INVALID_ARG.                                    */
+                               for this batch and tile shape, else 1.  It changes
+                               only the schedule: forward and backward calls on one
+                               workspace may differ in it.  Other values are
+                               INVALID_ARG.                                        */
 } fm_raster_params;
 
 /* Output planes (device, float32): rgb[3][P], depth[P], normal[3][P],

@@ -671,9 +671,8 @@ hipError_t launch_binning(const Plan &p, void *ws, const KParams &kp, hipStream_
         uint32_t *t = ka; ka = kb; kb = t;
         t = va; va = vb; vb = t;
     }
-    // 4. the blend's tile order, longest list first (else the blend takes the
-    //    tiles in image order)
-    if (!p.lpt) return hipGetLastError();
+    // 4. the longest-first tile order, written whichever order the blend
+    //    uses, so that a later call on this workspace may choose either
     uint32_t *tkey = at<uint32_t>(ws, p.o_tkey), *tkey2 = at<uint32_t>(ws, p.o_tkey2);
     hipLaunchKernelGGL(k_tile_cost, dim3((unsigned)std::min(p.sortG_t, kMaxEmitGrid)), dim3(256), 0, st, ts, te,
                        p.T, tkey, hist, p.sortG_t);
