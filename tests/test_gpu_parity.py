@@ -200,6 +200,30 @@ def test_deterministic_backward_with_normals_matches_oracle(rast, tile):
     assert_grad_close(runs[0][1], rdvm, "deterministic.viewmat")
 
 
+def test_backward_in_the_other_tile_order(rast):
+    """A forward in image order followed by backwards in either order on the
+    same workspace: the tile order only schedules, so the deterministic
+    gradients are the same bits."""
+    from paper_2604_03092_amd.raster import Workspace
+    sc = scenes.random_scene(34, 4000, 72, 56, scale_lo=0.03, scale_hi=0.2)
+    gs = GpuScene.from_scene(sc)
+    _say("backward in the other tile order")
+    out, ws = rast.forward(gs, rast.params(tile_order=2, deterministic=True))
+    keep = ~_oracle_forward(sc)["flags"]
+    g = random_upstream(np.random.default_rng(6), gs.npx, keep)
+    gt = {k: torch.from_numpy(v.astype(np.float32)).cuda() for k, v in g.items()}
+    res = []
+    for order in (2, 1):
+        w = Workspace(ws.buf, ws.nbytes, ws.max_pairs, rast.params(tile_order=order, deterministic=True))
+        grads, dvm = gs.zero_grads()
+        rast.backward(gs, w, out, gt, grads, dvm)
+        torch.cuda.synchronize()
+        res.append(({k: to_np(v) for k, v in grads[0].items()}, to_np(dvm)))
+    for k in res[0][0]:
+        assert np.array_equal(res[0][0][k], res[1][0][k]), k
+    assert np.array_equal(res[0][1], res[1][1])
+
+
 def test_overwrite_stores_gradients(rast):
     """overwrite = 1: the fused call and fm_backward store surfel gradients,
     pose gradients and the loss over whatever the buffers held, equal bitwise
