@@ -142,7 +142,9 @@ def backward_view(sm, w, h, intr, viewmat, g, grads=None, **kw):
 
 def bin_view(sm, w, h, intr, viewmat, tile_w=16, tile_h=16, cap=None, **kw):
     """Tile binning of one view: per-surfel tile rects and depth-key bits,
-    and the pair list sorted by (tile, depth key, index) with tile ranges."""
+    the pair list sorted by (tile, depth key, index) with tile ranges, and
+    per pair whether the surfel reaches a pixel of the tile (passes the
+    support and opacity tests at one of its pixel centres)."""
     L = lib()
     n, arrs = _surf_args(sm)
     rect = np.zeros((n, 4), np.int32)
@@ -156,19 +158,23 @@ def bin_view(sm, w, h, intr, viewmat, tile_w=16, tile_h=16, cap=None, **kw):
                  ctypes.c_int(tile_h), _ptr(rect, ctypes.c_int32), _ptr(kappa, ctypes.c_uint32),
                  ctypes.byref(npairs)]
     c = 1 if cap is None else cap
-    pt = np.zeros(max(c, 1), np.uint32); ps = np.zeros(max(c, 1), np.uint32)
-    rc = L.orc_bin(*args_head, _ptr(pt, ctypes.c_uint32), _ptr(ps, ctypes.c_uint32),
-                   ctypes.c_int64(c), _ptr(ts, ctypes.c_uint32), _ptr(te, ctypes.c_uint32))
-    if rc == 2 and cap is None:
-        c = int(npairs.value)
+
+    def run(c):
         pt = np.zeros(max(c, 1), np.uint32); ps = np.zeros(max(c, 1), np.uint32)
+        pr = np.zeros(max(c, 1), np.uint8)
         rc = L.orc_bin(*args_head, _ptr(pt, ctypes.c_uint32), _ptr(ps, ctypes.c_uint32),
-                       ctypes.c_int64(c), _ptr(ts, ctypes.c_uint32), _ptr(te, ctypes.c_uint32))
+                       ctypes.c_int64(c), _ptr(ts, ctypes.c_uint32), _ptr(te, ctypes.c_uint32),
+                       _ptr(pr, ctypes.c_uint8))
+        return rc, pt, ps, pr
+
+    rc, pt, ps, pr = run(c)
+    if rc == 2 and cap is None:
+        rc, pt, ps, pr = run(int(npairs.value))
     if rc != 0:
         raise RuntimeError(f"oracle binning failed ({rc})")
     m = int(npairs.value)
     return dict(rect=rect, kappa=kappa, n_pairs=m, pair_tile=pt[:m].copy(), pair_surf=ps[:m].copy(),
-                tile_start=ts, tile_end=te, tiles=(tx, ty))
+                pair_reached=pr[:m].astype(bool), tile_start=ts, tile_end=te, tiles=(tx, ty))
 
 
 def project(sm, w, h, intr, viewmat, **kw):

@@ -445,6 +445,67 @@ int orc_render(int n, const float *mean, const float *quat, const float *scale, 
     return 0;
 }
 
+/*
+ * Pruning scores of one view for map fusion (Sec. 3.3, "Map Fusion": the map
+ * is rendered from the keyframe and primitives that contribute to pixels
+ * with a high reconstruction error are removed).  For every pixel with
+ * mask[q] != 0, each surfel composited there adds its weight alpha T (its
+ * contribution in Eq. 1) to score[idx]; score[n] is ADDED into.
+ */
+int orc_contrib_scores(int n, const float *mean, const float *quat, const float *scale, const float *opacity,
+                       const float *color, int W, int H, const float *intr, const float *viewmat,
+                       const orc_params *pp, const uint8_t *mask, double *score)
+{
+#ifdef _OPENMP
+    if (pp->n_threads > 0) omp_set_num_threads(pp->n_threads);
+    int nt = omp_get_max_threads();
+#else
+    int nt = 1;
+#endif
+    scene_t sc;
+    if (build_scene(&sc, n, mean, quat, scale, opacity, color, W, H, intr, viewmat, pp)) {
+        free_scene(&sc);
+        return -1;
+    }
+    double *acc = (double *)calloc((size_t)nt * (size_t)(n > 0 ? n : 1), sizeof(double));
+    if (!acc) { free_scene(&sc); return -1; }
+    int fail = 0;
+#pragma omp parallel
+    {
+#ifdef _OPENMP
+        int tid = omp_get_thread_num();
+#else
+        int tid = 0;
+#endif
+        double *my = acc + (size_t)tid * n;
+        int cap = 1024;
+        contrib_t *list = (contrib_t *)malloc(sizeof(contrib_t) * cap);
+#pragma omp for schedule(dynamic, 4)
+        for (int row = 0; row < H; ++row) {
+            for (int col = 0; col < W; ++col) {
+                if (!mask[(size_t)row * W + col]) continue;
+                double o[8], T;
+                int fl, m;
+                for (;;) {
+                    m = composite_pixel(&sc, pp, col, row, W, o, &T, &fl, list, cap, NULL);
+                    if (m <= cap || !list) break;
+                    cap = m * 2;
+                    free(list);
+                    list = (contrib_t *)malloc(sizeof(contrib_t) * cap);
+                }
+                if (!list) { fail = 1; continue; }
+                for (int k = 0; k < m; ++k) my[list[k].idx] += list[k].alpha * list[k].T;
+            }
+        }
+        free(list);
+    }
+    for (int t = 0; t < nt; ++t)
+        for (int i = 0; i < n; ++i) score[i] += acc[(size_t)t * n + i];
+    free(acc);
+    free_scene(&sc);
+    return fail ? -1 : 0;
+}
+
 /* dL/d(unit quaternion) from dL/dR for the rotation matrix written above */
 static void drot_dq(const double q[4], const double G[9], double dq[4])
 {
@@ -625,13 +686,37 @@ int orc_render_backward(int n, const float *mean, const float *quat, const float
 }
 
 /*
+ * Whether a surfel reaches a pixel of tile (a, b): some pixel centre of the
+ * tile inside the image where the ray meets the surfel plane inside the
+ * support (r^2 <= rho_max^2) with sigma G >= alpha_min -- the two per-pixel
+ * tests of the compositing, before any transmittance stop.  A pair of the
+ * bbox list whose tile no pixel passes cannot contribute to any pixel.
+ */
+static int tile_reached(const surf_t *s, const orc_params *pp, int a, int b, int tile_w, int tile_h, int W,
+                        int H)
+{
+    double rho2 = pp->rho_max * pp->rho_max;
+    for (int row = b * tile_h; row < (b + 1) * tile_h && row < H; ++row)
+        for (int col = a * tile_w; col < (a + 1) * tile_w && col < W; ++col) {
+            double aa[3], bb[3], w[3], u, v, r2;
+            if (!intersect(s, col + 0.5, row + 0.5, aa, bb, w, &u, &v, &r2)) continue;
+            if (r2 > rho2) continue;
+            if (s->sigma * exp(-0.5 * r2) < pp->alpha_min) continue;
+            return 1;
+        }
+    return 0;
+}
+
+/*
  * Tile binning of one view.  For every surfel surviving the culls, the tiles
  * covered by its pixel-centre bbox are listed; pairs are ordered by
  * (tile, fp32 depth key, surfel index).  Outputs:
  *   rect[4n]      tx0, ty0, tx1, ty1 per surfel (-1 when it covers no tile),
  *   kappa[n]      bits of the fp32 depth key (0 for culled surfels),
  *   pair_tile / pair_surf (capacity cap), *n_pairs,
- *   tile_start / tile_end [tiles_x * tiles_y] half-open ranges.
+ *   tile_start / tile_end [tiles_x * tiles_y] half-open ranges,
+ *   pair_reached  (may be NULL) 1 when the pair's surfel reaches a pixel of
+ *                 the pair's tile (tile_reached), else 0.
  */
 typedef struct { uint32_t tile; float kappa; int32_t idx; } pair_t;
 static int cmp_pair(const void *a, const void *b)
@@ -646,7 +731,7 @@ int orc_bin(int n, const float *mean, const float *quat, const float *scale, con
             const float *color, int W, int H, const float *intr, const float *viewmat,
             const orc_params *pp, int tile_w, int tile_h, int32_t *rect, uint32_t *kappa,
             int64_t *n_pairs, uint32_t *pair_tile, uint32_t *pair_surf, int64_t cap,
-            uint32_t *tile_start, uint32_t *tile_end)
+            uint32_t *tile_start, uint32_t *tile_end, uint8_t *pair_reached)
 {
     int tx = (W + tile_w - 1) / tile_w, ty = (H + tile_h - 1) / tile_h;
     surf_t *s = (surf_t *)malloc(sizeof(surf_t) * (size_t)(n > 0 ? n : 1));
@@ -688,6 +773,12 @@ int orc_bin(int n, const float *mean, const float *quat, const float *scale, con
         pair_surf[j] = (uint32_t)pr[j].idx;
         if (j == 0 || pr[j - 1].tile != pr[j].tile) tile_start[pr[j].tile] = (uint32_t)j;
         if (j == total - 1 || pr[j + 1].tile != pr[j].tile) tile_end[pr[j].tile] = (uint32_t)(j + 1);
+    }
+    if (pair_reached) {
+#pragma omp parallel for schedule(dynamic, 256)
+        for (int64_t j = 0; j < total; ++j)
+            pair_reached[j] = (uint8_t)tile_reached(&s[pr[j].idx], pp, (int)(pr[j].tile % (uint32_t)tx),
+                                                    (int)(pr[j].tile / (uint32_t)tx), tile_w, tile_h, W, H);
     }
     free(pr);
     free(s);

@@ -50,7 +50,7 @@ def test_config0_forward_and_pairs(rast, tile):
     # pair list and tile ranges: bit-exact
     b = oracle.bin_view(sc.submaps[0], 64, 48, sc.intr[0], sc.viewmat[0], tile_w=tile[0], tile_h=tile[1])
     t, s, v, ts, te = rast.debug_pairs(gs, ws)
-    kept = assert_pairs_match(b, t, s, ts, te, sc.submaps[0], sc.intr[0], sc.viewmat[0], 64, 48, tile)
+    kept = assert_pairs_match(b, t, s, ts, te)
     _say(f"config0 tile={tile}: {kept:.3f} of the oracle's pairs kept")
     starts = np.concatenate([[0], np.cumsum(te - ts)[:-1]])
     assert np.array_equal(ts[te > ts], starts[te > ts])
@@ -334,7 +334,7 @@ def test_config1_forward_backward(rast):
     _say("config1 pairs")
     b = oracle.bin_view(sc.submaps[0], 640, 480, sc.intr[0], sc.viewmat[0])
     t, s, v, ts, te = rast.debug_pairs(gs, ws)
-    kept = assert_pairs_match(b, t, s, ts, te, sc.submaps[0], sc.intr[0], sc.viewmat[0], 640, 480, (16, 16))
+    kept = assert_pairs_match(b, t, s, ts, te)
     _say(f"config1: {kept:.3f} of the oracle's pairs kept")
     _say("config1 backward")
     near = np.any(np.abs(ref["rgb"] - sc.target_rgb) < 5e-4, axis=0) | (

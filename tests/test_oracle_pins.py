@@ -497,6 +497,154 @@ def test_pixels_with_support_lie_in_rect(orc):
         assert a0 >= 0 and cols.min() >= a0 and cols.max() <= a1 and rows.min() >= b0 and rows.max() <= b1
 
 
+def _reached_margin(sm, intr, viewmat, surf, tiles, tiles_x, tile_w, tile_h, width, height):
+    """For each (surfel, tile): the smallest r^2 / rho_eff^2 over the tile's
+    pixel centres, rho_eff^2 = min(rho_max^2, 2 ln(sigma / alpha_min)), with
+    (u, v) from the ray-plane intersection written independently of the
+    oracle's homography form: the ray d = ((x - cx)/fx, (y - cy)/fy, 1) meets
+    the camera-frame plane through p with normal n at lambda = (p.n)/(d.n),
+    and u, v are the coordinates of lambda d - p along t_u / s_u, t_v / s_v
+    (rotation from scipy's quaternion convention)."""
+    q = sm["quat"][:, surf].astype(np.float64)
+    Rs = Rotation.from_quat(np.stack([q[1], q[2], q[3], q[0]], 1)).as_matrix()     # [n,3,3]
+    vm = np.asarray(viewmat, np.float32).astype(np.float64).reshape(3, 4)
+    R, t = vm[:, :3], vm[:, 3]
+    p = (R @ sm["mean"][:, surf].astype(np.float64)).T + t                          # [n,3]
+    tu, tv, nr = (np.einsum("ij,njk->nik", R, Rs[:, :, c:c + 1])[:, :, 0] for c in range(3))
+    su, sv = (sm["scale"][c, surf].astype(np.float64) for c in range(2))
+    sig = sm["opacity"][surf].astype(np.float64)
+    fx, fy, cx, cy = (float(v) for v in np.asarray(intr, np.float32))
+    tx, ty = tiles % tiles_x, tiles // tiles_x
+    ox, oy = np.meshgrid(np.arange(tile_w), np.arange(tile_h))
+    col = tx[:, None] * tile_w + ox.reshape(-1)[None]
+    row = ty[:, None] * tile_h + oy.reshape(-1)[None]
+    on = (col < width) & (row < height)
+    d = np.stack([(col + 0.5 - cx) / fx, (row + 0.5 - cy) / fy, np.ones(col.shape)], -1)   # [n,P,3]
+    with np.errstate(divide="ignore", invalid="ignore"):
+        lam = np.einsum("nk,nk->n", p, nr)[:, None] / np.einsum("npk,nk->np", d, nr)
+        X = lam[..., None] * d - p[:, None]
+        u = np.einsum("npk,nk->np", X, tu) / su[:, None]
+        v = np.einsum("npk,nk->np", X, tv) / sv[:, None]
+        r2 = u * u + v * v
+    r2 = np.where(on & np.isfinite(r2), r2, np.inf)
+    a_min = float(np.float32(1.0 / 255.0))
+    re2 = np.minimum(9.0, 2.0 * np.log(sig / a_min))
+    return r2.min(axis=1) / re2
+
+
+@pytest.mark.parametrize("name,tile", [("config0", (16, 16)), ("config0", (8, 8)), ("config0", (32, 32)),
+                                       ("tilted", (16, 8)), ("tilted", (32, 8))])
+def test_reached_flags_match_ray_plane_definition(orc, name, tile):
+    """The oracle's per-pair flag (the surfel passes the support and opacity
+    tests at some pixel centre of the tile) agrees with the independent
+    ray-plane evaluation for every bbox pair, except pairs whose closest
+    pixel lies within 1e-9 of the support boundary."""
+    if name == "config0":
+        sc = scenes.config0()
+    else:
+        sc = scenes.random_scene(91, 3000, 80, 56, n_views=2, scale_lo=0.03, scale_hi=0.25)
+    v = sc.n_views - 1
+    w, h, _ = sc.views[v]
+    sm = sc.submaps[0]
+    b = orc.bin_view(sm, w, h, sc.intr[v], sc.viewmat[v], tile_w=tile[0], tile_h=tile[1])
+    m = _reached_margin(sm, sc.intr[v], sc.viewmat[v], b["pair_surf"].astype(np.int64),
+                        b["pair_tile"].astype(np.int64), b["tiles"][0], tile[0], tile[1], w, h)
+    sure = np.abs(m - 1.0) > 1e-9
+    assert sure.mean() > 0.999
+    assert np.array_equal(b["pair_reached"][sure], (m <= 1.0)[sure])
+    assert 0.0 < b["pair_reached"].mean() < 1.0
+
+
+# ---------------------------------------------------------------- depth-key ties
+def _tie_stack():
+    """Fronto-parallel surfels centred on pixel (8, 8) of a 16x16 view at the
+    identity pose.  Indices 0, 2 and 4 share the bit-equal depth 3.0 and are
+    listed with opacities that do not follow their index; index 1 lies in
+    front of them at 2.0 with a higher index than 0; index 3 lies behind at
+    4.0.  Compositing takes (depth key, index) order: 1, 0, 2, 4, 3."""
+    s = [one_surfel([0, 0, 3.0], [1, 0, 0, 0], [0.5, 0.5], 0.3, [1, 0, 0]),
+         one_surfel([0, 0, 2.0], [1, 0, 0, 0], [0.5, 0.5], 0.2, [0, 0, 0]),
+         one_surfel([0, 0, 3.0], [1, 0, 0, 0], [0.5, 0.5], 0.6, [0, 1, 0]),
+         one_surfel([0, 0, 4.0], [1, 0, 0, 0], [0.5, 0.5], 0.5, [1, 1, 1]),
+         one_surfel([0, 0, 3.0], [1, 0, 0, 0], [0.5, 0.5], 0.45, [0, 0, 1])]
+    return stack(*s), [1, 0, 2, 4, 3]
+
+
+def _stack_closed_form(sm, order, q_uv=(0.0, 0.0)):
+    """Front-to-back compositing of the listed surfels at one pixel whose
+    local coordinates are (u, v) on every surfel (alpha = sigma exp(-r^2/2)),
+    written out: T_k = prod_{j<k} (1 - alpha_j)."""
+    r2 = q_uv[0] ** 2 + q_uv[1] ** 2
+    T, rgb, a_sum, d_sum = 1.0, np.zeros(3), 0.0, 0.0
+    for i in order:
+        a = float(sm["opacity"][i]) * math.exp(-0.5 * r2)
+        rgb += sm["color"][:, i].astype(np.float64) * a * T
+        d_sum += float(sm["mean"][2, i]) * a * T
+        a_sum += a * T
+        T *= 1.0 - a
+    return rgb, d_sum, a_sum, T
+
+
+def test_depth_key_ties_take_index_order(orc):
+    """Surfels with bit-equal fp32 depth keys composite in index order
+    (reading of the tie-break); the listed order is not the array order."""
+    sm, order = _tie_stack()
+    intr = np.array([20, 20, 8.5, 8.5], np.float32)
+    o = orc.render_view(sm, 16, 16, intr, IDENT)
+    q = 8 * 16 + 8
+    rgb, d, a, T = _stack_closed_form(sm, order)
+    np.testing.assert_allclose(o["rgb"][:, q], rgb, atol=1e-12)
+    np.testing.assert_allclose(o["depth"][q], d, atol=1e-12)
+    np.testing.assert_allclose(o["alpha"][q], a, atol=1e-12)
+    np.testing.assert_allclose(o["t_final"][q], T, rtol=1e-12)
+    assert o["n_contrib"][q] == 5
+    # the reverse index order among the tied surfels gives a different pixel
+    other, *_ = _stack_closed_form(sm, [1, 4, 2, 0, 3])
+    assert np.abs(other - rgb).max() > 0.05
+    b = orc.bin_view(sm, 16, 16, intr, IDENT, tile_w=8, tile_h=8)
+    first = b["pair_surf"][b["tile_start"][3]:b["tile_end"][3]]
+    assert list(first) == order
+
+
+def test_depth_key_ties_with_distinct_fp64_depths(orc):
+    """Two surfels whose FP64 centre depths differ by less than half an fp32
+    ulp share the depth key fp32(z) and so take index order, even though
+    the FP64 depth of the lower index is the larger one.  The view rotates by
+    1e-4 rad about x and each surfel is turned by the inverse rotation, so in
+    the camera frame both are fronto-parallel; their camera-frame centres are
+    computed here from the pose in FP64 for the closed form."""
+    ang = 1e-4
+    Rv = Rotation.from_rotvec([ang, 0.0, 0.0]).as_matrix().astype(np.float32)
+    vm = np.concatenate([Rv, np.zeros((3, 1), np.float32)], 1).reshape(12)
+    qi = Rotation.from_matrix(Rv.astype(np.float64).T).as_quat()           # x, y, z, w
+    q = [qi[3], qi[0], qi[1], qi[2]]
+    # mean y of surfel 0 puts its FP64 depth 5e-8 above surfel 1's (half ulp at 3.0: 1.2e-7)
+    R64 = Rv.astype(np.float64)
+    y0 = float(np.float32(5e-8 / R64[2, 1]))
+    sm = stack(one_surfel([0, y0, 3.0], q, [0.4, 0.4], 0.5, [1, 0, 0]),
+               one_surfel([0, 0, 3.0], q, [0.4, 0.4], 0.7, [0, 1, 0]))
+    z = [R64[2] @ sm["mean"][:, i].astype(np.float64) for i in range(2)]
+    assert z[0] > z[1] and np.float32(z[0]) == np.float32(z[1])
+    intr = np.array([30, 30, 8.0, 8.0], np.float32)
+    o = orc.render_view(sm, 16, 16, intr, vm)
+    pr = orc.project(sm, 16, 16, intr, vm)
+    assert pr["depth"][0] == z[0] and pr["depth"][1] == z[1]
+    q_px = 7 * 16 + 7
+    # in index order at the pixel centre (7.5, 7.5): each surfel's own (u, v)
+    x, y = 7.5, 7.5
+    fx, fy, cx, cy = 30.0, 30.0, 8.0, 8.0
+    T, rgb = 1.0, np.zeros(3)
+    for i in (0, 1):
+        p = R64 @ sm["mean"][:, i].astype(np.float64)
+        u = (x - cx - fx * p[0] / p[2]) * p[2] / (fx * 0.4)
+        v = (y - cy - fy * p[1] / p[2]) * p[2] / (fy * 0.4)
+        a = float(sm["opacity"][i]) * math.exp(-0.5 * (u * u + v * v))
+        rgb += sm["color"][:, i] * a * T
+        T *= 1.0 - a
+    np.testing.assert_allclose(o["rgb"][:, q_px], rgb, atol=1e-6)
+    np.testing.assert_allclose(o["t_final"][q_px], T, atol=1e-6)
+
+
 def test_l1_loss_definition(orc):
     sc = scenes.config0()
     out = dict(rgb=np.full((3, 3072), 0.5), depth=np.zeros(3072), normal=np.zeros((3, 3072)),
