@@ -189,7 +189,9 @@ typedef struct {
 } fm_l1_loss;
 
 /* Context: binds to a HIP device, queries its properties and holds the
- * autotuner's choices.  Allocates no device memory. */
+ * autotuner's choices.  Allocates no device memory; the first context on a
+ * device resolves that device's address of the static scratch array of
+ * fm_fwd_bwd_l1_noalloc. */
 fm_status fm_create(fm_ctx **ctx, int device);
 void fm_destroy(fm_ctx *ctx);
 const char *fm_status_string(fm_status s);
@@ -230,6 +232,28 @@ fm_status fm_fwd_bwd_l1(fm_ctx *ctx, const fm_batch *batch, const fm_raster_para
                         const fm_l1_loss *loss_spec, fm_outputs out, float *loss,
                         const fm_surfel_grads *grads, float *dL_dviewmat, void *workspace,
                         size_t ws_bytes, int64_t max_pairs, void *stream);
+
+/* For callers that cannot allocate (code under HIP graph capture without a
+ * workspace of its own, tight serving loops, harnesses that forbid
+ * allocation): fm_fwd_bwd_l1 with its workspace taken from a static device
+ * array of FM_NOALLOC_SCRATCH_BYTES (128 MiB) that the library keeps on each
+ * GPU it runs on until the process ends (its device address is resolved by
+ * fm_create).  Same arguments and results as fm_fwd_bwd_l1 without the
+ * workspace.  A batch whose workspace (fm_workspace_size with this
+ * max_pairs) exceeds FM_NOALLOC_SCRATCH_BYTES fails with FM_ERR_WORKSPACE
+ * before anything is enqueued; the 640x480 view of 300k surfels fits with
+ * room for 1.5M pairs.  Every call on one GPU uses that GPU's one array,
+ * which keeps the last call's contents: calls that overlap on one GPU (other
+ * streams, contexts or host threads) race and give wrong results, so the
+ * caller serialises them.  pair_status (device, 2 int64, may be NULL)
+ * receives the pairs the batch needed and 1 if that exceeded max_pairs
+ * (the results are then incomplete, as with FM_ERR_CAPACITY), else 0.
+ * Calls no allocating routine and does not synchronise. */
+#define FM_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+fm_status fm_fwd_bwd_l1_noalloc(fm_ctx *ctx, const fm_batch *batch, const fm_raster_params *params,
+                                const fm_l1_loss *loss_spec, fm_outputs out, float *loss,
+                                const fm_surfel_grads *grads, float *dL_dviewmat, int64_t max_pairs,
+                                int64_t *pair_status, void *stream);
 
 /* After the stream that ran fm_forward / fm_fwd_bwd_l1 has been synchronised:
  * reads the pair count of the last forward on this workspace.  Returns

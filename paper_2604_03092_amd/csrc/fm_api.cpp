@@ -12,6 +12,7 @@
 #include <cstring>
 #include <fstream>
 #include <map>
+#include <mutex>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -31,6 +32,9 @@ struct fm_ctx {
         int tw, th, order;
     };
     std::map<std::string, Tuned> tuned;  // batch signature -> tile shape and tile order
+    // device address of this device's copy of the library's static scratch
+    // array (fm_fwd_bwd_l1_noalloc), resolved once per device by fm_create
+    void *scratch = nullptr;
     // optional phase timing (benchmarks): events recorded between phases
     bool timing = false;
     hipEvent_t ev[8] = {};
@@ -38,7 +42,46 @@ struct fm_ctx {
     int ev_phase[8] = {};
 };
 
+// Workspace of fm_fwd_bwd_l1_noalloc: a file-scope device array, one copy per
+// GPU the library runs on, held until the process ends.  Host code never
+// passes the array's name to a kernel or a copy (on the host it is only a
+// stand-in symbol); it uses the device address that hipGetSymbolAddress
+// returns for the current device.
+static __device__ __align__(256) unsigned char scratch[FM_NOALLOC_SCRATCH_BYTES];
+
 namespace {
+
+// One device address per device, resolved with that device current.
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[64] = {};
+
+hipError_t scratch_address(int device, void **out) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (device < 0 || device >= 64) return hipErrorInvalidDevice;
+    if (!g_scratch_ptr[device]) {
+        int prev = -1;
+        hipError_t e = hipGetDevice(&prev);
+        if (e != hipSuccess) return e;
+        if (prev != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (prev != device) (void)hipSetDevice(prev);
+        if (e != hipSuccess) return e;
+        if (!ptr) return hipErrorInvalidSymbol;
+        g_scratch_ptr[device] = ptr;
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
+
+// Copies the pair count of the last binning and its overflow flag out of the
+// status word (fm_fwd_bwd_l1_noalloc's pair_status).
+__global__ void k_pair_status(const fm::Status *st, int64_t *out) {
+    if (threadIdx.x == 0) {
+        out[0] = (int64_t)st->required;
+        out[1] = st->overflow ? 1 : 0;
+    }
+}
 
 constexpr int kVersion = 10000;  // 1.0.0
 
@@ -425,10 +468,13 @@ fm_status fm_create(fm_ctx **out, int device) {
     if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return FM_ERR_INVALID_ARG;
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) != hipSuccess) return FM_ERR_HIP;
+    void *scratch_ptr = nullptr;
+    if (scratch_address(device, &scratch_ptr) != hipSuccess) return FM_ERR_HIP;
     fm_ctx *c = new fm_ctx();
     c->device = device;
     c->name = prop.gcnArchName;
     c->n_cu = prop.multiProcessorCount;
+    c->scratch = scratch_ptr;
     *out = c;
     return FM_OK;
 }
@@ -586,6 +632,33 @@ fm_status fm_fwd_bwd_l1(fm_ctx *ctx, const fm_batch *b, const fm_raster_params *
     if (s == FM_OK) s = use_device(ctx);
     if (s != FM_OK) return s;
     return run_fused(ctx, bt, prm, b, ws, ls, out, loss, dL_dviewmat, (hipStream_t)stream);
+}
+
+fm_status fm_fwd_bwd_l1_noalloc(fm_ctx *ctx, const fm_batch *b, const fm_raster_params *prm,
+                                const fm_l1_loss *ls, fm_outputs out, float *loss, const fm_surfel_grads *grads,
+                                float *dL_dviewmat, int64_t max_pairs, int64_t *pair_status, void *stream) {
+    if (!ctx) return FM_ERR_INVALID_ARG;
+    if (!grads) return fail(ctx, FM_ERR_INVALID_ARG, "grads must not be NULL (one entry per submap)");
+    if (!ctx->scratch) return fail(ctx, FM_ERR_HIP, "the static scratch array has no device address");
+    Built bt;
+    fm_status s = build(ctx, b, prm, max_pairs, grads, true, bt);
+    if (s != FM_OK) return s;
+    if (bt.plan.bytes > (size_t)FM_NOALLOC_SCRATCH_BYTES)
+        return fail(ctx, FM_ERR_WORKSPACE,
+                    "fm_fwd_bwd_l1_noalloc: the batch needs " + std::to_string(bt.plan.bytes) +
+                        " bytes of workspace, the static scratch holds " +
+                        std::to_string((size_t)FM_NOALLOC_SCRATCH_BYTES) + " (use fm_fwd_bwd_l1)");
+    s = check_out(ctx, out);
+    if (s == FM_OK) s = check_loss(ctx, ls);
+    if (s == FM_OK) s = use_device(ctx);
+    if (s != FM_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    s = run_fused(ctx, bt, prm, b, ctx->scratch, ls, out, loss, dL_dviewmat, st);
+    if (s != FM_OK || !pair_status) return s;
+    hipLaunchKernelGGL(k_pair_status, dim3(1), dim3(64), 0, st, fm::at<fm::Status>(ctx->scratch, bt.plan.o_status),
+                       pair_status);
+    FM_TRY_HIP(hipGetLastError(), "pair_status");
+    return FM_OK;
 }
 
 fm_status fm_query_status(fm_ctx *ctx, const fm_batch *b, const fm_raster_params *prm, const void *ws,

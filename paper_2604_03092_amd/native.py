@@ -21,6 +21,8 @@ FM_ERR_CAPACITY = 2
 FM_ERR_HIP = 3
 FM_ERR_UNSUPPORTED = 4
 FM_ERR_WORKSPACE = 5
+# bytes of the static scratch array behind fm_fwd_bwd_l1_noalloc
+FM_NOALLOC_SCRATCH_BYTES = 128 << 20
 
 
 class FmSurfels(ctypes.Structure):
@@ -109,6 +111,8 @@ SIGNATURES = {
                               ctypes.c_size_t, c_int64, P(FmSurfelGrads), c_void_p, c_void_p]),
     "fm_fwd_bwd_l1": (c_int32, [c_void_p, P(FmBatch), P(FmRasterParams), P(FmL1Loss), FmOutputs, c_void_p,
                                 P(FmSurfelGrads), c_void_p, c_void_p, ctypes.c_size_t, c_int64, c_void_p]),
+    "fm_fwd_bwd_l1_noalloc": (c_int32, [c_void_p, P(FmBatch), P(FmRasterParams), P(FmL1Loss), FmOutputs,
+                                        c_void_p, P(FmSurfelGrads), c_void_p, c_int64, c_void_p, c_void_p]),
     "fm_query_status": (c_int32, [c_void_p, P(FmBatch), P(FmRasterParams), c_void_p, c_int64, P(c_int64),
                                   P(c_int64)]),
     "fm_debug_pairs": (c_int32, [c_void_p, P(FmBatch), P(FmRasterParams), c_void_p, c_int64, c_void_p,

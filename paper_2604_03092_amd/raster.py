@@ -243,6 +243,20 @@ class Rasterizer:
                                           ctypes.byref(ls), _outputs(out), _ptr(loss), gg, _ptr(dviewmat),
                                           _ptr(ws.buf), ws.nbytes, ws.max_pairs, _stream(stream)))
 
+    def fwd_bwd_l1_noalloc(self, gs, params, max_pairs, out, grads, dviewmat, loss, pair_status=None, mask=None,
+                           stream=None):
+        """fwd_bwd_l1 on the library's static scratch array instead of a
+        workspace (fm_fwd_bwd_l1_noalloc).  pair_status: optional int64
+        device tensor of 2 (pairs needed, overflow flag)."""
+        ls = FmL1Loss(gs.target_rgb.data_ptr(),
+                      gs.target_depth.data_ptr() if gs.target_depth is not None else None,
+                      mask.data_ptr() if mask is not None else None, gs.w_rgb,
+                      gs.w_depth if gs.target_depth is not None else 0.0)
+        gg = _grad_structs(grads)
+        self.check(self.lib.fm_fwd_bwd_l1_noalloc(self.ctx, ctypes.byref(gs.batch()), ctypes.byref(params),
+                                                  ctypes.byref(ls), _outputs(out), _ptr(loss), gg, _ptr(dviewmat),
+                                                  int(max_pairs), _ptr(pair_status), _stream(stream)))
+
     def autotune(self, gs, ws, out, grads, dviewmat, loss, cache_path=None):
         ls = FmL1Loss(gs.target_rgb.data_ptr(),
                       gs.target_depth.data_ptr() if gs.target_depth is not None else None, None, gs.w_rgb,

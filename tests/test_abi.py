@@ -123,3 +123,11 @@ def test_create_without_gpu_fails_cleanly(lib):
     ctx = ctypes.c_void_p()
     assert lib.fm_create(ctypes.byref(ctx), 0) != 0
     assert not ctx.value
+
+
+def test_noalloc_scratch_size_matches_header():
+    """The binding's copy of the static scratch size is the header's."""
+    text = open(HEADER).read()
+    m = re.search(r"#define FM_NOALLOC_SCRATCH_BYTES \(\(size_t\)(\d+) << (\d+)\)", text)
+    assert m, "FM_NOALLOC_SCRATCH_BYTES not found"
+    assert native.FM_NOALLOC_SCRATCH_BYTES == int(m.group(1)) << int(m.group(2))
