@@ -72,15 +72,31 @@ def make_workload(name):
     return scenes.make(name)
 
 
-def cpu_baseline(scene, threads, n_sample):
-    """FP64 oracle (as it stands) on a bounded sample: the first n_sample views
-    of the batch, forward + L1 loss + backward."""
+def host_info():
+    """CPU model, logical CPUs of the host, and CPUs this process may run on."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        allowed = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        allowed = os.cpu_count() or 1
+    return dict(cpu_model=model, nproc=os.cpu_count(), cpus_allowed=allowed)
+
+
+def _oracle_fwd_bwd(scene, n_views, threads):
+    """Seconds of one FP64 oracle forward + L1 loss + backward of the first
+    n_views views of the batch, and their pixel count."""
     import oracle
     from paper_2604_03092_amd import scenes as S
-    n_sample = min(n_sample, scene.n_views)
-    npx = sum(w * h for (w, h, _) in scene.views[:n_sample])
-    sub = S.Scene("sample", scene.submaps, list(scene.views[:n_sample]), scene.intr[:n_sample],
-                  scene.viewmat[:n_sample], scene.target_rgb[:, :npx],
+    npx = sum(w * h for (w, h, _) in scene.views[:n_views])
+    sub = S.Scene("sample", scene.submaps, list(scene.views[:n_views]), scene.intr[:n_views],
+                  scene.viewmat[:n_views], scene.target_rgb[:, :npx],
                   scene.target_depth[:npx] if scene.target_depth is not None else None, scene.w_rgb,
                   scene.w_depth)
     oracle.lib()
@@ -88,12 +104,23 @@ def cpu_baseline(scene, threads, n_sample):
     out = oracle.render_scene(sub, n_threads=threads)
     _, g = oracle.l1_loss(sub, out)
     oracle.backward_scene(sub, g, n_threads=threads)
-    dt = time.perf_counter() - t0
+    return time.perf_counter() - t0, npx
+
+
+def cpu_baseline(scene, threads, n_sample):
+    """FP64 oracle (as it stands) on bounded samples of the batch: the first
+    n_sample views on `threads` threads, and the first view on one thread."""
+    n_sample = min(n_sample, scene.n_views)
+    dt, npx = _oracle_fwd_bwd(scene, n_sample, threads)
+    dt1, npx1 = _oracle_fwd_bwd(scene, 1, 1)
     w, h, s = scene.views[0]
     return dict(value=round(npx / dt / 1e6, 6), unit="Mpixel/s", cores=threads, kind="oracle",
                 sample=f"views 0-{n_sample - 1} of {scene.n_views} ({w}x{h}, "
                        f"{scene.submaps[s]['opacity'].shape[0]} surfels): FP64 oracle forward + L1 loss + "
-                       f"backward, {dt:.2f} s")
+                       f"backward on {threads} threads, {dt:.2f} s",
+                single_thread=dict(value=round(npx1 / dt1 / 1e6, 6), unit="Mpixel/s", cores=1,
+                                   sample=f"view 0 on one thread, {dt1:.2f} s"),
+                **host_info())
 
 
 def time_refine(rast, scene, params, iters, replays=3):
@@ -101,10 +128,13 @@ def time_refine(rast, scene, params, iters, replays=3):
     of (fused forward + L1 + backward storing the gradients, Adam step on
     every surfel tensor) captured in one hipGraph and replayed.  Every replay
     starts from the batch's initial surfels with fresh Adam state (restored
-    outside the timed region), as a keyframe window's refinement does."""
+    outside the timed region), as a keyframe window's refinement does.  The
+    pair buffer is sized from the largest pair count of an eager pass over
+    all iterations (the map moves under Adam), checked after every one."""
     import torch
     from paper_2604_03092_amd.raster import Adam, GpuScene
     gs = GpuScene.from_scene(scene)
+    init = [{k: sm[k].clone() for k in sm} for sm in gs.submaps]
     out, ws = rast.forward(gs, params)
     torch.cuda.synchronize()
     _, n_pairs, _ = rast.query(gs, ws)
@@ -118,17 +148,6 @@ def time_refine(rast, scene, params, iters, replays=3):
         rast.fwd_bwd_l1(gs, ws, out, grads, dvm, losses[i:i + 1])
         adam.step()
 
-    s = torch.cuda.Stream()
-    s.wait_stream(torch.cuda.current_stream())
-    with torch.cuda.stream(s):
-        iteration(0)
-    torch.cuda.current_stream().wait_stream(s)
-    graph = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(graph):
-        for i in range(iters):
-            iteration(i)
-    init = [{k: sm[k].clone() for k in sm} for sm in gs.submaps]
-
     def restore():
         for sm, s0, m, v, g in zip(gs.submaps, init, adam.m, adam.v, grads):
             for k in sm:
@@ -139,6 +158,27 @@ def time_refine(rast, scene, params, iters, replays=3):
         adam.step_count.zero_()
         losses.zero_()
         torch.cuda.synchronize()
+
+    # eager pass: the largest pair count along the refinement trajectory
+    max_req = 0
+    for i in range(iters):
+        iteration(i)
+        torch.cuda.synchronize()
+        st, _, req = rast.query(gs, ws)
+        max_req = max(max_req, req)
+    if max_req * 1.1 > ws.max_pairs:
+        ws = rast.workspace(gs, params, max_pairs=int(max_req * 1.25) + 4096)
+    restore()
+
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        iteration(0)
+    torch.cuda.current_stream().wait_stream(s)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        for i in range(iters):
+            iteration(i)
 
     restore()
     graph.replay()  # warm-up replay
@@ -156,7 +196,8 @@ def time_refine(rast, scene, params, iters, replays=3):
     return dict(iterations=iters, views=gs.n_views, ms_per_iteration=round(dt * 1e3, 4),
                 ms_per_graph=round(dt * iters * 1e3, 3), mpixel_s=round(gs.npx / dt / 1e6, 3),
                 loss_first=round(first, 6), loss_last=round(float(losses[-1]), 6),
-                pair_capacity_ok=bool(st == 0))
+                max_pairs_seen=int(max_req), pair_capacity=int(ws.max_pairs),
+                pair_capacity_ok=bool(st == 0 and max_req <= ws.max_pairs))
 
 
 def time_fusion(rast, n_frames=32, w=518, h=392, tau_depth=0.05, tau_accum=0.5, replays=20):
@@ -201,9 +242,11 @@ def time_fusion(rast, n_frames=32, w=518, h=392, tau_depth=0.05, tau_accum=0.5, 
                 hbm=dict(bytes=alg, gbs=round(alg / dt / 1e9, 1), frac=round(alg / dt / 1e9 / HBM_PEAK_GBS, 4)))
 
 
-def time_warp(rast, n=2_000_000, n_keyframes=64, replays=50):
+def time_warp(rast, n=16_000_000, n_keyframes=64, replays=20):
     """Loop-correction warp (fm_warp_keyframes) of n keyframe-bound primitives
-    by per-keyframe similarities: one launch, timed with events over replays."""
+    by per-keyframe similarities: one launch, timed with events over replays.
+    16M primitives are 1.2 GB of data, several times the 256 MB last-level
+    cache, so every replay streams them from HBM."""
     import ctypes
     import numpy as np
     import torch
@@ -240,10 +283,61 @@ def time_warp(rast, n=2_000_000, n_keyframes=64, replays=50):
                 hbm=dict(bytes=alg, gbs=round(alg / ms / 1e6, 1), frac=round(alg / ms / 1e6 / HBM_PEAK_GBS, 4)))
 
 
+def step_alg_bytes(n_surf, n_vis, n_pairs, npx):
+    """Algorithmic HBM bytes of one fused step: 52 B of parameters read and
+    52 B of gradients written per surfel; per visible (view, surfel) a 68 B
+    record and a 68 B screen-space gradient, each written and read once; per
+    pair 12 B emitted, 24 B for one sort pass, 4 B read by the forward and
+    4 B by the backward traversal; per pixel 32 B of outputs, 8 B of state
+    written and read, 32 B of upstream gradient (targets)."""
+    return 104 * n_surf + 272 * n_vis + 44 * n_pairs + 80 * npx
+
+
+def step_rooflines(n_surf, n_vis, n_pairs, npx, useful, ms):
+    """The step's HBM fraction by the byte model and its VALU fraction by the
+    useful evaluations, both over the whole step time."""
+    b = step_alg_bytes(n_surf, n_vis, n_pairs, npx)
+    t = ms * 1e-3
+    ops = useful * OPS_PER_USEFUL
+    return dict(hbm=dict(bytes=b, gbs=round(b / t / 1e9, 1), frac=round(b / t / 1e9 / HBM_PEAK_GBS, 4)),
+                valu=dict(lane_ops=ops, tops=round(ops / t / 1e12, 3),
+                          frac=round(ops / t / 1e12 / ALU_PEAK_TOPS, 4)))
+
+
+def lds_peak(rast, blocks=256 * 8 * 4, iters=4096):
+    """LDS read bandwidth measured with the library's probe (per-lane 16-byte
+    words without bank conflicts, and wave broadcasts of one 16-byte word)."""
+    import ctypes
+    import torch
+    sink = torch.empty(blocks * 256, device="cuda")
+    res = {}
+    for mode, name in ((0, "per_lane"), (1, "broadcast")):
+        nbytes = ctypes.c_double(0)
+        st = torch.cuda.current_stream()
+        call = lambda: rast.check(rast.lib.fm_bench_lds(rast.ctx, mode, blocks, iters, ctypes.c_void_p(sink.data_ptr()),
+                                                        ctypes.byref(nbytes), ctypes.c_void_p(st.cuda_stream)))
+        call()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 5
+        e0.record()
+        for _ in range(reps):
+            call()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        insts = blocks * 4 * iters * 8   # wave-level ds_read_b128 instructions
+        res[name] = dict(lane_tbs=round(nbytes.value / ms / 1e9, 2), ms=round(ms, 4),
+                         wave_insts_per_s=float(f"{insts / ms * 1e3:.4g}"))
+    res["nominal_tbs"] = round(256 * 128 * 2.4e9 / 1e12, 1)  # 128 B per clock per CU
+    return res
+
+
 def time_config(rast, name, steps):
-    """Fused forward + L1 + backward of one config's whole batch, eager calls,
-    in Mpixel/s, at 16x16 tiles and at the tile shape the autotuner picks
-    (setup, tuning and pair-buffer sizing untimed)."""
+    """Fused forward + L1 + backward of one config's whole batch, one hipGraph
+    replay per step, at 16x16 tiles (longest list first) and at the tile shape
+    and order the autotuner picks (setup, tuning and pair-buffer sizing
+    untimed), each with the step's HBM and VALU rooflines."""
     import torch
     from paper_2604_03092_amd.raster import GpuScene
     scene = make_workload(name)
@@ -257,12 +351,12 @@ def time_config(rast, name, steps):
     grads, dvm = gs.zero_grads()
     loss = torch.zeros(1, device="cuda")
     chosen = rast.autotune(gs, ws8, out, grads, dvm, loss)
-    tuned = (int(chosen.tile_w), int(chosen.tile_h))
+    tuned = (int(chosen.tile_w), int(chosen.tile_h), int(chosen.tile_order))
     del ws8
     res = dict(views=gs.n_views, pixels=gs.npx)
-    for tile in [(16, 16)] + ([tuned] if tuned != (16, 16) else []):
-        r = _time_config_tile(rast, gs, tile, steps, out, grads, dvm, loss)
-        key = "tile_16x16" if tile == (16, 16) else "tuned"
+    for tile in [(16, 16, 1)] + ([tuned] if tuned != (16, 16, 1) else []):
+        r = _time_config_tile(rast, gs, tile[:2], tile[2], steps, out, grads, dvm, loss)
+        key = "tile_16x16" if tile == (16, 16, 1) else "tuned"
         res[key] = dict(tile=f"{tile[0]}x{tile[1]}", **r)
     res["autotuned_tile"] = f"{tuned[0]}x{tuned[1]}"
     res["autotuned_order"] = "longest list first" if chosen.tile_order == 1 else "image order"
@@ -271,9 +365,12 @@ def time_config(rast, name, steps):
     return res
 
 
-def _time_config_tile(rast, gs, tile, steps, out, grads, dvm, loss):
+def _time_config_tile(rast, gs, tile, order, steps, out, grads, dvm, loss):
+    """One hipGraph replay of the fused step per timed step (gradients,
+    pose gradients and loss stored), timed with events; the rooflines use the
+    step's median time."""
     import torch
-    params = rast.params(tile=tile, overwrite=True)
+    params = rast.params(tile=tile, overwrite=True, tile_order=order)
     _, ws = rast.forward(gs, params)
     torch.cuda.synchronize()
     _, n_pairs, _ = rast.query(gs, ws)
@@ -286,16 +383,49 @@ def _time_config_tile(rast, gs, tile, steps, out, grads, dvm, loss):
         step()
     torch.cuda.synchronize()
     assert rast.query(gs, ws)[0] == 0
-    t0 = time.perf_counter()
-    for _ in range(steps):
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
         step()
+    torch.cuda.current_stream().wait_stream(s)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        step()
+    graph.replay()
     torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / steps
-    res = dict(pairs=n_pairs, ms_per_step=round(dt * 1e3, 4), mpixel_s=round(gs.npx / dt / 1e6, 3),
-               views_s=round(gs.n_views / dt, 3))
-    del ws
+    per, total = _timed_replays(graph.replay, steps)
+    assert rast.query(gs, ws)[0] == 0
+    med = float(np.median(per))
+    # useful evaluations (contributor counts of a plain forward), visible entries
+    rast.forward_into(gs, ws, out)
+    torch.cuda.synchronize()
+    _, nc = rast.pixel_state(gs, ws)
+    useful = int(nc.astype(np.int64).sum())
+    n_vis, _ = rast.counts(gs, ws)
+    n_surf = sum(int(gs.submaps[k]["opacity"].shape[-1]) for k in {v[2] for v in gs.views})
+    res = dict(pairs=n_pairs, visible_entries=n_vis, useful_evals=useful,
+               ms_per_step=round(total / steps, 4), ms_per_step_median=round(med, 4),
+               mpixel_s=round(gs.npx / med / 1e3, 3), views_s=round(gs.n_views / med * 1e3, 3),
+               **step_rooflines(n_surf, n_vis, n_pairs, gs.npx, useful, med))
+    del ws, graph
     torch.cuda.empty_cache()
     return res
+
+
+def _timed_replays(run, steps):
+    """Per-step milliseconds (events between consecutive runs on the current
+    stream) and the total wall milliseconds of `steps` runs."""
+    import torch
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev[0].record()
+    for i in range(steps):
+        run()
+        ev[i + 1].record()
+    torch.cuda.synchronize()
+    total = (time.perf_counter() - t0) * 1e3
+    return [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)], total
 
 
 def main():
@@ -317,8 +447,10 @@ def main():
     ap.add_argument("--refine-iters", type=int, default=20,
                     help="iterations of the captured refine loop (render loss + Adam), 0 to skip")
     ap.add_argument("--no-fusion", action="store_true", help="skip the map-fusion and warp measurements")
-    ap.add_argument("--all-configs", action="store_true",
-                    help="also time the fused step on configs 0-4 (reported under per_config)")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the per-config block (configs 0-4, graph-replayed fused steps with rooflines)")
+    ap.add_argument("--config-steps", type=int, default=20, help="timed steps per config and tile shape")
+    ap.add_argument("--no-lds", action="store_true", help="skip the LDS bandwidth probe")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 1 GiB device buffer 5 times (reference for HBM counter scaling)")
     args = ap.parse_args()
@@ -407,12 +539,10 @@ def main():
         run()
     torch.cuda.synchronize()
     log(f"timing {args.steps} fused steps ({'graph' if graph else 'eager'})")
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        run()
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+    per_step, total_ms = _timed_replays(run, args.steps)
+    dt = total_ms * 1e-3
     ms_step = dt / args.steps * 1e3
+    ms_median = float(np.median(per_step))
     mpx = gs.npx * args.steps / dt / 1e6
     views_s = gs.n_views * args.steps / dt
     log(f"fused: {ms_step:.3f} ms/step, {mpx:.1f} Mpixel/s, {views_s:.1f} views/s")
@@ -473,9 +603,9 @@ def main():
     # binning 12 B emitted + 24 B of one sort pass per pair; backward
     # projection a 68 B screen-space gradient per visible entry + 52 B of
     # parameters read and 52 B of gradients written per surfel
-    _, surf_ids, view_ids, _, _ = rast.debug_pairs(gs, ws)
-    n_vis = int(np.unique(view_ids.astype(np.int64) << 32 | surf_ids.astype(np.int64)).size)
+    n_vis, _ = rast.counts(gs, ws)
     n_surf = int(sum(sm["opacity"].shape[0] for sm in scene.submaps))
+    step_roof = step_rooflines(n_surf, n_vis, n_pairs, gs.npx, useful, ms_median)
     alg = {"projection": 52 * n_surf + 68 * n_vis, "binning": 36 * n_pairs,
            "backward_projection": 68 * n_vis + 104 * n_surf}
     phase_hbm = {k: dict(bytes=b, gbs=round(b / (phases[k] * 1e-3) / 1e9, 1),
@@ -498,15 +628,21 @@ def main():
         log(f"warp: {warp['ms']:.3f} ms for {warp['primitives']} primitives, {warp['hbm']['gbs']:.0f} GB/s")
 
     per_config = None
-    if args.all_configs:
+    if not args.no_configs:
         per_config = {}
         for name in ("config0", "config1", "config2", "config3", "config4"):
             log(f"config {name}")
-            per_config[name] = time_config(rast, name, max(3, args.steps // 10))
+            per_config[name] = time_config(rast, name, args.config_steps)
+
+    lds = None
+    if not args.no_lds:
+        lds = lds_peak(rast)
+        log(f"lds: per-lane {lds['per_lane']['lane_tbs']} TB/s, broadcast {lds['broadcast']['lane_tbs']} TB/s")
 
     cpu = None
     if not args.no_cpu_baseline:
-        threads = args.cpu_threads or min(16, os.cpu_count() or 1)
+        # every CPU this process may run on (the OpenMP thread budget when one is set)
+        threads = args.cpu_threads or int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or host_info()["cpus_allowed"]
         log(f"cpu baseline on {threads} threads")
         cpu = cpu_baseline(scene, threads, args.cpu_views)
 
@@ -518,6 +654,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms_step, 4),
+        "ms_per_step_median": round(ms_median, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -535,7 +672,9 @@ def main():
         "phases_ms": {k: round(v, 4) for k, v in phases.items()},
         "visible_entries": n_vis,
         "phase_hbm": phase_hbm,
+        "step_roofline": step_roof,
         "roofline": roofline,
+        "lds": lds,
         "cpu_baseline": cpu,
         "refine": refine,
         "fusion": fusion,

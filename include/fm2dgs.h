@@ -285,6 +285,25 @@ fm_status fm_debug_pixel_state(fm_ctx *ctx, const fm_batch *batch, const fm_rast
                                const void *workspace, int64_t max_pairs, float *t_final,
                                uint32_t *n_contrib, int64_t npx);
 
+/* Test and benchmark hook: counts of the last forward on this workspace,
+ * read after the stream has been synchronised: *n_visible = (view, surfel)
+ * entries whose tile rect is not empty, *n_kept = pairs in the tile-sorted
+ * list (either pointer may be NULL).  Synchronous. */
+fm_status fm_debug_counts(fm_ctx *ctx, const fm_batch *batch, const fm_raster_params *params,
+                          const void *workspace, int64_t max_pairs, int64_t *n_visible,
+                          int64_t *n_kept);
+
+/* Benchmark hook, not part of rendering: LDS read bandwidth of the device.
+ * Enqueues `blocks` workgroups of 256 threads; every thread reads 16-byte
+ * words from LDS 8 * iters times and stores one float into sink (device,
+ * blocks * 256 floats).  mode 0: each lane its own word, consecutive lanes
+ * consecutive words (no bank conflicts); mode 1: all lanes of a wave the same
+ * word (a broadcast, the blend kernels' access to staged records).
+ * *lane_bytes (host, may be NULL) receives the bytes delivered to lanes,
+ * blocks * 256 * 8 * iters * 16.  The caller times the stream. */
+fm_status fm_bench_lds(fm_ctx *ctx, int32_t mode, int32_t blocks, int32_t iters, float *sink,
+                       double *lane_bytes, void *stream);
+
 /* Benchmark hook.  With timing enabled, fm_forward / fm_backward /
  * fm_fwd_bwd_l1 record HIP events between their phases on the call's stream
  * (skipped while the stream is being captured).  fm_phase_times waits for the
@@ -445,6 +464,53 @@ fm_status fm_voxelize_fuse_batch(fm_ctx *ctx, const fm_pixel_map *maps, const fm
                                  const fm_fusion_params *params, const float *const *accums,
                                  fm_surfel_buffer out, int32_t *offsets, void *workspace, size_t ws_bytes,
                                  void *stream);
+
+/* ---- map fusion: pruning the global map ---------------------------------
+ *
+ * Before new primitives join, the backend renders the global map from the
+ * new keyframe's pose and removes the primitives that contribute to pixels
+ * with a high RGB or depth reconstruction error (Sec. 3.3, "Map Fusion").
+ * fm_prune_scores renders the batch (outputs as fm_forward writes them),
+ * flags the high-error pixels -- (|I_r - I*_r| + |I_g - I*_g|) + |I_b - I*_b|,
+ * divided by 3, above tau_rgb, or with a depth target |D - D*| above
+ * tau_depth, each step in float32 -- and gives every surfel its score: the
+ * sum over the flagged pixels of all views of its compositing weight
+ * alpha_i T_i (its share in Eq. 1), summed in float32 in no fixed order.
+ * fm_prune_compact then removes the surfels whose score exceeds a cut. */
+typedef struct {
+    const float *target_rgb;    /* DEVICE [3][P] observed image (unused with mask_in)         */
+    const float *target_depth;  /* DEVICE [P] observed depth, or NULL: no depth criterion     */
+    const uint8_t *mask_in;     /* DEVICE [P] or NULL: flag these pixels (non-zero) instead   */
+    uint8_t *mask_out;          /* DEVICE [P] or NULL: receives the flags used (0/1)          */
+    float tau_rgb;              /* mean absolute RGB error above which a pixel is flagged     */
+    float tau_depth;            /* absolute depth error above which a pixel is flagged        */
+} fm_prune_spec;
+
+/* Scores of every surfel of every submap a view renders.  scores: HOST array
+ * [n_submaps] of DEVICE float arrays [n of that submap], overwritten (an
+ * entry may be NULL for a submap no view renders; such arrays are not
+ * written).  Workspace, capacity and errors as fm_forward (query the pair
+ * count with fm_query_status); the tile shape and order are the params'.
+ * Enqueued on stream; no allocation, no synchronisation. */
+fm_status fm_prune_scores(fm_ctx *ctx, const fm_batch *batch, const fm_raster_params *params,
+                          const fm_prune_spec *spec, fm_outputs out, float *const *scores,
+                          void *workspace, size_t ws_bytes, int64_t max_pairs, void *stream);
+
+/* Workspace bytes fm_prune_compact needs for n surfels. */
+size_t fm_prune_compact_workspace_size(int64_t n);
+
+/* Removal: the surfels of `in` whose score (DEVICE [in->n]) is not above
+ * tau_prune stay and are written, in their original order, to out; their
+ * number goes to *count (DEVICE int32).  tau_prune = 0 removes every surfel
+ * that contributes to a flagged pixel; a NaN score keeps its surfel.
+ * Surfels beyond out.capacity are not written (*count still counts them).
+ * Errors: FM_ERR_INVALID_ARG for NULL pointers, a negative size or
+ * capacity, NULL output planes with capacity > 0, or a NaN tau_prune;
+ * FM_ERR_WORKSPACE below fm_prune_compact_workspace_size.  Enqueued on
+ * stream; no allocation, no synchronisation. */
+fm_status fm_prune_compact(fm_ctx *ctx, const fm_surfels *in, const float *score, float tau_prune,
+                           fm_surfel_buffer out, int32_t *count, void *workspace, size_t ws_bytes,
+                           void *stream);
 
 /* ---- loop correction of the map --------------------------------------------
  *

@@ -18,7 +18,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libfm2dgs.so")
-SOURCES = ["fm_api.cpp", "fm_preprocess.hip", "fm_sort.hip", "fm_blend.hip", "fm_optim.hip", "fm_fusion.hip", "fm_warp.hip"]
+SOURCES = ["fm_api.cpp", "fm_preprocess.hip", "fm_sort.hip", "fm_blend.hip", "fm_optim.hip", "fm_fusion.hip", "fm_warp.hip", "fm_bench.hip", "fm_prune.hip"]
 BUILD_DIR = os.path.join(HERE, "_build")
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-I", INCLUDE, "-I", CSRC,

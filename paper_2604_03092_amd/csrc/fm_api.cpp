@@ -511,6 +511,35 @@ fm_status fm_phase_times(fm_ctx *ctx, float *ms, int n) {
     return FM_OK;
 }
 
+fm_status fm_debug_counts(fm_ctx *ctx, const fm_batch *b, const fm_raster_params *prm, const void *ws,
+                          int64_t max_pairs, int64_t *n_visible, int64_t *n_kept) {
+    if (!ctx) return FM_ERR_INVALID_ARG;
+    Built bt;
+    fm_status s = build(ctx, b, prm, max_pairs, nullptr, false, bt);
+    if (s != FM_OK) return s;
+    if (!ws) return fail(ctx, FM_ERR_INVALID_ARG, "workspace must not be NULL");
+    s = use_device(ctx);
+    if (s != FM_OK) return s;
+    fm::Status st;
+    FM_TRY_HIP(hipMemcpy(&st, static_cast<const char *>(ws) + bt.plan.o_status, sizeof(st), hipMemcpyDeviceToHost),
+               "hipMemcpy(status)");
+    if (n_visible) *n_visible = st.n_vis;
+    if (n_kept) *n_kept = st.n_kept;
+    return FM_OK;
+}
+
+fm_status fm_bench_lds(fm_ctx *ctx, int32_t mode, int32_t blocks, int32_t iters, float *sink, double *lane_bytes,
+                       void *stream) {
+    if (!ctx) return FM_ERR_INVALID_ARG;
+    if ((mode != 0 && mode != 1) || blocks < 1 || iters < 1 || !sink)
+        return fail(ctx, FM_ERR_INVALID_ARG, "fm_bench_lds: mode 0 or 1, blocks >= 1, iters >= 1, sink not NULL");
+    fm_status s = use_device(ctx);
+    if (s != FM_OK) return s;
+    FM_TRY_HIP(fm::launch_lds_probe(mode, blocks, iters, sink, (hipStream_t)stream), "lds_probe");
+    if (lane_bytes) *lane_bytes = (double)fm::lds_probe_bytes(blocks, iters);
+    return FM_OK;
+}
+
 fm_status fm_debug_pixel_state(fm_ctx *ctx, const fm_batch *b, const fm_raster_params *prm, const void *ws,
                                int64_t max_pairs, float *t_final, uint32_t *n_contrib, int64_t npx) {
     if (!ctx) return FM_ERR_INVALID_ARG;
@@ -658,6 +687,78 @@ fm_status fm_fwd_bwd_l1_noalloc(fm_ctx *ctx, const fm_batch *b, const fm_raster_
     hipLaunchKernelGGL(k_pair_status, dim3(1), dim3(64), 0, st, fm::at<fm::Status>(ctx->scratch, bt.plan.o_status),
                        pair_status);
     FM_TRY_HIP(hipGetLastError(), "pair_status");
+    return FM_OK;
+}
+
+fm_status fm_prune_scores(fm_ctx *ctx, const fm_batch *b, const fm_raster_params *prm, const fm_prune_spec *spec,
+                          fm_outputs out, float *const *scores, void *ws, size_t ws_bytes, int64_t max_pairs,
+                          void *stream) {
+    if (!ctx) return FM_ERR_INVALID_ARG;
+    if (!spec || !scores) return fail(ctx, FM_ERR_INVALID_ARG, "fm_prune_scores: spec and scores must not be NULL");
+    if (!spec->mask_in) {
+        if (!spec->target_rgb)
+            return fail(ctx, FM_ERR_INVALID_ARG, "fm_prune_scores: target_rgb is needed without mask_in");
+        if (!std::isfinite(spec->tau_rgb) || (spec->target_depth && !std::isfinite(spec->tau_depth)))
+            return fail(ctx, FM_ERR_INVALID_ARG, "fm_prune_scores: thresholds must be finite");
+    }
+    if (!b || b->n_submaps < 1) return fail(ctx, FM_ERR_INVALID_ARG, "batch must not be NULL");
+    // the per-surfel reduction stores each submap's scores through the g_opacity slot
+    std::vector<fm_surfel_grads> dst((size_t)b->n_submaps);
+    for (int i = 0; i < b->n_submaps; ++i) {
+        memset(&dst[i], 0, sizeof(dst[i]));
+        dst[i].opacity = scores[i];
+    }
+    Built bt;
+    fm_status s = build(ctx, b, prm, max_pairs, dst.data(), false, bt);
+    if (s == FM_OK) s = check_ws(ctx, bt.plan, ws, ws_bytes);
+    if (s == FM_OK) s = check_out(ctx, out);
+    if (s == FM_OK) s = use_device(ctx);
+    if (s != FM_OK) return s;
+    for (int i = 0; i < b->n_submaps; ++i)
+        if (!scores[i] && bt.subs[i].view_count > 0 && b->submaps[i].n > 0)
+            return fail(ctx, FM_ERR_INVALID_ARG,
+                        "fm_prune_scores: scores[" + std::to_string(i) + "] is NULL but a view renders submap");
+    hipStream_t st = (hipStream_t)stream;
+    fm::KParams kp = kparams(prm, bt.plan);
+    fm::PruneArgs pa;
+    pa.target_rgb = spec->target_rgb;
+    pa.target_depth = spec->target_depth;
+    pa.mask_in = spec->mask_in;
+    pa.mask_out = spec->mask_out;
+    pa.tau_rgb = spec->tau_rgb;
+    pa.tau_depth = spec->tau_depth;
+    mark_begin(ctx, st);
+    FM_TRY_HIP(fm::launch_setup(bt.plan, ws, bt.views.data(), bt.subs.data(), bt.vlist.data(), st), "setup");
+    // the projection clears the slots whose first float collects each entry's score
+    FM_TRY_HIP(fm::launch_preprocess(bt.plan, ws, kp, b->intr, b->viewmat, true, st), "preprocess");
+    mark(ctx, st, PH_PRE);
+    FM_TRY_HIP(fm::launch_binning(bt.plan, ws, kp, st), "binning");
+    mark(ctx, st, PH_BIN);
+    FM_TRY_HIP(fm::launch_render_prune(bt.plan, ws, kp, pa, out, st), "render_prune");
+    mark(ctx, st, PH_BLEND);
+    FM_TRY_HIP(fm::launch_score_reduce(bt.plan, ws, kp.gstride, st), "score_reduce");
+    mark(ctx, st, PH_BWDPROJ);
+    return FM_OK;
+}
+
+size_t fm_prune_compact_workspace_size(int64_t n) { return n < 0 ? 0 : fm::prune_compact_workspace_bytes(n); }
+
+fm_status fm_prune_compact(fm_ctx *ctx, const fm_surfels *in, const float *score, float tau_prune,
+                           fm_surfel_buffer out, int32_t *count, void *ws, size_t ws_bytes, void *stream) {
+    if (!ctx) return FM_ERR_INVALID_ARG;
+    if (!in || !count || !ws) return fail(ctx, FM_ERR_INVALID_ARG, "fm_prune_compact: NULL in, count or workspace");
+    if (in->n < 0) return fail(ctx, FM_ERR_INVALID_ARG, "fm_prune_compact: negative n");
+    if (in->n > 0 && (!score || !in->mean || !in->quat || !in->scale || !in->opacity || !in->color))
+        return fail(ctx, FM_ERR_INVALID_ARG, "fm_prune_compact: NULL surfel plane or score");
+    if (out.capacity < 0 ||
+        (out.capacity > 0 && (!out.mean || !out.quat || !out.scale || !out.opacity || !out.color)))
+        return fail(ctx, FM_ERR_INVALID_ARG, "fm_prune_compact: negative capacity or NULL output plane");
+    if (std::isnan(tau_prune)) return fail(ctx, FM_ERR_INVALID_ARG, "fm_prune_compact: tau_prune is NaN");
+    if (ws_bytes < fm::prune_compact_workspace_bytes(in->n))
+        return fail(ctx, FM_ERR_WORKSPACE, "fm_prune_compact: workspace smaller than fm_prune_compact_workspace_size");
+    fm_status s = use_device(ctx);
+    if (s != FM_OK) return s;
+    FM_TRY_HIP(fm::launch_prune_compact(*in, score, tau_prune, out, count, ws, (hipStream_t)stream), "prune_compact");
     return FM_OK;
 }
 

@@ -129,6 +129,14 @@ struct LossArgs {
     float w_rgb, w_depth;
 };
 
+// Map-fusion pruning: the error criterion's inputs, or a caller mask.
+struct PruneArgs {
+    const float *target_rgb, *target_depth;
+    const uint8_t *mask_in;
+    uint8_t *mask_out;
+    float tau_rgb, tau_depth;
+};
+
 struct Plan {
     int V = 0, S = 0;
     int64_t E = 0;      // entries (padded)
@@ -213,6 +221,16 @@ hipError_t launch_render_bwd(const Plan &p, void *ws, const KParams &kp, const f
 hipError_t launch_render_fused(const Plan &p, void *ws, const KParams &kp, const LossArgs &la,
                                const fm_outputs &out, hipStream_t st);
 hipError_t launch_loss_reduce(const Plan &p, void *ws, float *loss, hipStream_t st);
+// Pruning products: forward render, error flags and per-entry scores (the
+// first float of each entry's gradient slot, cleared by the projection), then
+// the per-surfel sum over the views (into each submap's g_opacity pointer).
+hipError_t launch_render_prune(const Plan &p, void *ws, const KParams &kp, const PruneArgs &pa,
+                               const fm_outputs &out, hipStream_t st);
+hipError_t launch_score_reduce(const Plan &p, void *ws, int gstride, hipStream_t st);
+// Removal of the surfels whose score exceeds tau (order kept).
+size_t prune_compact_workspace_bytes(int64_t n);
+hipError_t launch_prune_compact(const fm_surfels &in, const float *score, float tau, const fm_surfel_buffer &out,
+                                int32_t *count, void *ws, hipStream_t st);
 hipError_t launch_zero_grad(const Plan &p, void *ws, int gstride, hipStream_t st);
 // Deterministic gradients: clear the partial slots of the stored pairs before
 // an adjoint, and sum each entry's slots into its gradient slot after it.
@@ -221,6 +239,9 @@ hipError_t launch_det_reduce(const Plan &p, void *ws, int gstride, hipStream_t s
 hipError_t launch_preprocess_bwd(const Plan &p, void *ws, int gstride, const float *intr, const float *viewmat,
                                  float *dL_dviewmat, hipStream_t st);
 bool tile_shape_supported(int tw, int th);
+// LDS read probe of the benchmark (mode 0: per-lane words, 1: wave broadcast)
+hipError_t launch_lds_probe(int mode, int blocks, int iters, float *sink, hipStream_t st);
+int64_t lds_probe_bytes(int blocks, int iters);
 size_t fusion_workspace_bytes(int32_t width, int32_t height);
 size_t fusion_batch_workspace_bytes(const fm_pixel_map *maps, int32_t n);
 hipError_t launch_fusion_batch(const fm_pixel_map *maps, const fm_sim3 *poses, int32_t n,

@@ -96,6 +96,11 @@ class FmSurfelBuffer(ctypes.Structure):
                 ("color", c_void_p), ("capacity", c_int64)]
 
 
+class FmPruneSpec(ctypes.Structure):
+    _fields_ = [("target_rgb", c_void_p), ("target_depth", c_void_p), ("mask_in", c_void_p),
+                ("mask_out", c_void_p), ("tau_rgb", c_float), ("tau_depth", c_float)]
+
+
 P = ctypes.POINTER
 SIGNATURES = {
     "fm_create": (c_int32, [P(c_void_p), c_int32]),
@@ -113,6 +118,11 @@ SIGNATURES = {
                                 P(FmSurfelGrads), c_void_p, c_void_p, ctypes.c_size_t, c_int64, c_void_p]),
     "fm_fwd_bwd_l1_noalloc": (c_int32, [c_void_p, P(FmBatch), P(FmRasterParams), P(FmL1Loss), FmOutputs,
                                         c_void_p, P(FmSurfelGrads), c_void_p, c_int64, c_void_p, c_void_p]),
+    "fm_prune_scores": (c_int32, [c_void_p, P(FmBatch), P(FmRasterParams), P(FmPruneSpec), FmOutputs,
+                                  P(c_void_p), c_void_p, ctypes.c_size_t, c_int64, c_void_p]),
+    "fm_prune_compact_workspace_size": (ctypes.c_size_t, [c_int64]),
+    "fm_prune_compact": (c_int32, [c_void_p, P(FmSurfels), c_void_p, c_float, FmSurfelBuffer, c_void_p, c_void_p,
+                                   ctypes.c_size_t, c_void_p]),
     "fm_query_status": (c_int32, [c_void_p, P(FmBatch), P(FmRasterParams), c_void_p, c_int64, P(c_int64),
                                   P(c_int64)]),
     "fm_debug_pairs": (c_int32, [c_void_p, P(FmBatch), P(FmRasterParams), c_void_p, c_int64, c_void_p,
@@ -120,6 +130,9 @@ SIGNATURES = {
     "fm_tile_count": (c_int32, [P(FmBatch), P(FmRasterParams), P(c_int64)]),
     "fm_debug_pixel_state": (c_int32, [c_void_p, P(FmBatch), P(FmRasterParams), c_void_p, c_int64, c_void_p,
                                        c_void_p, c_int64]),
+    "fm_debug_counts": (c_int32, [c_void_p, P(FmBatch), P(FmRasterParams), c_void_p, c_int64, P(c_int64),
+                                  P(c_int64)]),
+    "fm_bench_lds": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_void_p, P(ctypes.c_double), c_void_p]),
     "fm_set_timing": (c_int32, [c_void_p, c_int32]),
     "fm_phase_times": (c_int32, [c_void_p, P(c_float), c_int32]),
     "fm_autotune": (c_int32, [c_void_p, P(FmBatch), P(FmRasterParams), P(FmL1Loss), FmOutputs, c_void_p,

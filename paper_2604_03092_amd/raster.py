@@ -281,6 +281,13 @@ class Rasterizer:
                                                  gs.npx))
         return tf, nc
 
+    def counts(self, gs, ws):
+        """(visible entries, kept pairs) of the last forward on ws (synchronous)."""
+        nv, nk = ctypes.c_int64(0), ctypes.c_int64(0)
+        self.check(self.lib.fm_debug_counts(self.ctx, ctypes.byref(gs.batch()), ctypes.byref(ws.params),
+                                            _ptr(ws.buf), ws.max_pairs, ctypes.byref(nv), ctypes.byref(nk)))
+        return int(nv.value), int(nk.value)
+
     def set_timing(self, on=True):
         self.check(self.lib.fm_set_timing(self.ctx, 1 if on else 0))
 
@@ -356,27 +363,53 @@ class Adam:
                                                    _ptr(self.step_count), _stream(stream)))
 
 
-def error_mask(gs, out, tau_rgb, tau_depth=None):
-    """Pixels with high reconstruction error: mean over channels of
-    |I - I*| above tau_rgb, or (with depth targets) |D - D*| above
-    tau_depth.  Float mask over the batch's pixels."""
-    m = (out["rgb"] - gs.target_rgb).abs().mean(0) > tau_rgb
-    if tau_depth is not None and gs.target_depth is not None:
-        m = m | ((out["depth"] - gs.target_depth).abs() > tau_depth)
-    return m.float()
+def prune_scores(rast, gs, params=None, tau_rgb=0.1, tau_depth=None, mask=None, ws=None, out=None,
+                 stream=None):
+    """Error-attributed pruning scores of map fusion (Sec. 3.3) through
+    fm_prune_scores: renders the batch, flags the high-error pixels (mean
+    absolute RGB error above tau_rgb, or with tau_depth and depth targets
+    |D - D*| above tau_depth; or the pixels of the uint8 `mask`) and sums
+    every surfel's compositing weight alpha T over them.  Grows the pair
+    capacity (synchronising) when it overflows.  Returns (scores: one tensor
+    [n] per submap, flags: uint8 [P], outputs, workspace)."""
+    params = params or rast.params()
+    ws = ws or rast.workspace(gs, params)
+    out = out or rast.new_outputs(gs)
+    dev = gs.intr.device
+    scores = [torch.zeros(int(sm["opacity"].shape[-1]), device=dev) for sm in gs.submaps]
+    flags = torch.empty(gs.npx, dtype=torch.uint8, device=dev)
+    use_depth = tau_depth is not None and gs.target_depth is not None and mask is None
+    spec = native.FmPruneSpec(gs.target_rgb.data_ptr() if gs.target_rgb is not None else None,
+                              gs.target_depth.data_ptr() if use_depth else None,
+                              mask.data_ptr() if mask is not None else None, flags.data_ptr(),
+                              float(tau_rgb), float(tau_depth) if use_depth else 0.0)
+    arr = (ctypes.c_void_p * len(scores))(*[t.data_ptr() for t in scores])
+    while True:
+        rast.check(rast.lib.fm_prune_scores(rast.ctx, ctypes.byref(gs.batch()), ctypes.byref(params),
+                                            ctypes.byref(spec), _outputs(out), arr, _ptr(ws.buf), ws.nbytes,
+                                            ws.max_pairs, _stream(stream)))
+        st, n, req = rast.query(gs, ws)
+        ws.n_pairs = n
+        if st == 0:
+            return scores, flags, out, ws
+        ws = rast.workspace(gs, params, max_pairs=int(req * 1.25) + 1024)
 
 
-def prune_scores(rast, gs, ws, out, mask):
-    """Error-attributed pruning score of every surfel (map fusion, Sec. 3.3):
-    its total compositing weight sum_px alpha T over the masked pixels of all
-    views.  With the upstream gradient dL/dI = (mask, 0, 0) the adjoint's
-    colour gradient of a surfel is exactly that sum, so the score is read from
-    one fm_backward of the last forward on ws.  Returns one tensor [n] per
-    submap."""
-    g = dict(rgb=torch.stack([mask, torch.zeros_like(mask), torch.zeros_like(mask)]))
-    grads, dvm = gs.zero_grads()
-    rast.backward(gs, ws, out, g, grads, dvm)
-    return [gr["color"][0].clone() for gr in grads]
+def prune_compact(rast, sm, score, tau_prune=0.0, stream=None):
+    """The surfels of one submap (dict of planes [C, n]) whose score is not
+    above tau_prune, in their original order (fm_prune_compact).  Reads the
+    count back (synchronising) and returns dict of planes [C, count]."""
+    n = int(sm["opacity"].shape[-1])
+    dev = sm["opacity"].device
+    outp = {k: torch.empty(CHANNELS[k], max(n, 1), device=dev) for k in PLANES}
+    count = torch.zeros(1, dtype=torch.int32, device=dev)
+    wsb = torch.empty(max(int(rast.lib.fm_prune_compact_workspace_size(n)), 4), dtype=torch.uint8, device=dev)
+    src = FmSurfels(n, *(sm[k].data_ptr() for k in PLANES))
+    buf = native.FmSurfelBuffer(*(outp[k].data_ptr() for k in PLANES), n)
+    rast.check(rast.lib.fm_prune_compact(rast.ctx, ctypes.byref(src), _ptr(score), float(tau_prune), buf,
+                                         _ptr(count), _ptr(wsb), wsb.numel(), _stream(stream)))
+    c = int(count.item())
+    return {k: (outp[k][:, :c] if CHANNELS[k] > 1 else outp[k][0, :c]).contiguous() for k in PLANES}
 
 
 class Fusion:

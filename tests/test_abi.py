@@ -78,7 +78,8 @@ int main(void) {
   O(fm_batch, views) O(fm_batch, intr) O(fm_batch, viewmat) O(fm_raster_params, bg)
   O(fm_raster_params, tile_w) O(fm_raster_params, deterministic) O(fm_raster_params, tile_order)
   O(fm_l1_loss, w_rgb) O(fm_surfels, color) O(fm_adam_tensor, n)
-  O(fm_adam_tensor, lr) O(fm_adam_tensor, kind)
+  O(fm_adam_tensor, lr) O(fm_adam_tensor, kind) S(fm_prune_spec) O(fm_prune_spec, tau_rgb)
+  O(fm_prune_spec, tau_depth)
   return 0;
 }
 """
@@ -97,7 +98,7 @@ def test_ctypes_layout_matches_header():
          "fm_grad_outputs": native.FmGradOutputs, "fm_l1_loss": native.FmL1Loss,
          "fm_adam_tensor": native.FmAdamTensor, "fm_adam_config": native.FmAdamConfig,
          "fm_pixel_map": native.FmPixelMap, "fm_sim3": native.FmSim3, "fm_fusion_params": native.FmFusionParams,
-         "fm_surfel_buffer": native.FmSurfelBuffer}
+         "fm_surfel_buffer": native.FmSurfelBuffer, "fm_prune_spec": native.FmPruneSpec}
     for k, cls in m.items():
         assert int(vals[k]) == ctypes.sizeof(cls), k
     assert int(vals["fm_batch.views"]) == native.FmBatch.views.offset
@@ -113,6 +114,8 @@ def test_ctypes_layout_matches_header():
     assert int(vals["fm_sim3.t"]) == native.FmSim3.t.offset
     for f in ("n", "lr", "kind"):
         assert int(vals["fm_adam_tensor." + f]) == getattr(native.FmAdamTensor, f).offset
+    for f in ("tau_rgb", "tau_depth"):
+        assert int(vals["fm_prune_spec." + f]) == getattr(native.FmPruneSpec, f).offset
 
 
 def test_create_without_gpu_fails_cleanly(lib):

@@ -57,8 +57,8 @@ def _compare(tag, a, b, bitwise):
     assert abs(la - lb) <= 1e-6 * max(abs(la), 1e-6), (tag, la, lb)
     for s in range(len(ga)):
         for k in PLANES:
-            assert_grad_close(to_np(gb[s][k]), to_np(ga[s][k]), f"{tag}.{k}", rel=1e-5)
-    assert_grad_close(to_np(db), to_np(da), f"{tag}.viewmat", rel=1e-5)
+            assert_grad_close(to_np(gb[s][k]), to_np(ga[s][k]), f"{tag}.{k}")
+    assert_grad_close(to_np(db), to_np(da), f"{tag}.viewmat")
 
 
 def test_noalloc_matches_workspace_call_twice(rast):
