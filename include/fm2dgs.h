@@ -134,8 +134,9 @@ typedef struct {
                                partial and each entry sums its partials in emission
                                order, so gradients, the pose gradient and the loss are
                                bitwise reproducible; the workspace grows by
-                               4 + 80 * w bytes per pair of capacity (w = 4 waves per
-                               tile for 32x32, else 1) and a step costs one clear and
+                               4 + 80 * w bytes per pair of capacity (w = waves per
+                               tile: 4 for 32x32, the 8x8 blocks of the tile with
+                               tile_waves 2, else 1) and a step costs one clear and
                                one reduction pass over those partials.  Forward,
                                backward and fwd_bwd calls on one workspace must agree
                                on it.  Other values are INVALID_ARG.               */
@@ -155,6 +156,23 @@ typedef struct {
                                only the schedule: forward and backward calls on one
                                workspace may differ in it.  Other values are
                                INVALID_ARG.                                        */
+    int32_t tile_waves;     /* work split of the blend: 1 = one wave per tile (four
+                               16x16 quadrant waves for 32x32 tiles); 2 = one wave
+                               per 8x8 block of a 16x8, 16x16 or 32x8 tile, which
+                               traverse the tile's one list side by side (more,
+                               shorter waves for batches that do not fill the
+                               chip; 8x8 and 32x32 tiles are the same either
+                               way); 0 = fm_autotune's choice for this batch and
+                               tile shape, else 1.  It changes only the schedule:
+                               images are bitwise the same.  With deterministic
+                               sums, forward, backward and fwd_bwd calls on one
+                               workspace must agree on it (the partial gradient
+                               slots are per wave).  Other values are INVALID_ARG. */
+    int32_t lds_depth;      /* surfel records the fused call's blend stages in LDS
+                               per batch: 32, 64 or 128; 0 = fm_autotune's choice
+                               for this batch and tile shape, else 64.  The other
+                               calls stage 64.  Deterministic sums need 64 (or 0).
+                               Other values are INVALID_ARG.                      */
 } fm_raster_params;
 
 /* Output planes (device, float32): rgb[3][P], depth[P], normal[3][P],
@@ -317,13 +335,17 @@ fm_status fm_phase_times(fm_ctx *ctx, float *ms, int n);
 /* Total tile count of a batch for the given tile shape. */
 fm_status fm_tile_count(const fm_batch *batch, const fm_raster_params *params, int64_t *n_tiles);
 
-/* Autotuner: times fm_fwd_bwd_l1 over the supported tile shapes, each with
- * both tile orders, on this batch (outputs, gradients and the loss are
- * overwritten/accumulated while it runs) and writes the fastest into
- * *chosen (a copy of *params with tile_w, tile_h and tile_order set).  The
- * choice is cached in the context under the batch's shape signature and the
- * deterministic flag (the two modes tune separately) and, if cache_path is
- * not NULL, in a JSON file read back by later contexts.  Shapes whose workspace (fm_workspace_size) exceeds
+/* Autotuner: times fm_fwd_bwd_l1 (5 calls after a warm-up, every status
+ * checked) over the supported tile shapes, each with both tile orders and,
+ * for tiles of several 8x8 blocks, both work splits (tile_waves 1 and 2),
+ * then the LDS batch depths 32 and 128 of the fastest (not with
+ * deterministic sums), on this batch (outputs, gradients and the loss are
+ * overwritten/accumulated while it runs), and writes the fastest into
+ * *chosen (a copy of *params with tile_w, tile_h, tile_order, tile_waves and
+ * lds_depth set).  The choice is cached in the context under the device's
+ * architecture, the batch's shape signature and the deterministic flag (the
+ * two modes tune separately) and, if cache_path is not NULL, in a JSON file
+ * read back by later contexts.  Shapes whose workspace (fm_workspace_size) exceeds
  * ws_bytes or whose pairs exceed max_pairs are skipped; without
  * deterministic sums the 8x8 workspace is the largest.  Synchronous. */
 fm_status fm_autotune(fm_ctx *ctx, const fm_batch *batch, const fm_raster_params *params,

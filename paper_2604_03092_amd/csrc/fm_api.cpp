@@ -29,9 +29,9 @@ struct fm_ctx {
     int n_cu = 0;
     std::string last_error;
     struct Tuned {
-        int tw, th, order;
+        int tw, th, order, waves, depth;
     };
-    std::map<std::string, Tuned> tuned;  // batch signature -> tile shape and tile order
+    std::map<std::string, Tuned> tuned;  // device arch + batch signature -> launch choice
     // device address of this device's copy of the library's static scratch
     // array (fm_fwd_bwd_l1_noalloc), resolved once per device by fm_create
     void *scratch = nullptr;
@@ -110,10 +110,10 @@ std::string signature(const fm_batch *b) {
     return os.str();
 }
 
-// Autotune cache key: the batch signature; deterministic sums change the
-// cost of each shape, so they tune separately.
-std::string tune_key(const fm_batch *b, const fm_raster_params *prm) {
-    return signature(b) + (prm->deterministic == 1 ? "/det" : "");
+// Autotune cache key: the device's architecture and the batch signature;
+// deterministic sums change the cost of each shape, so they tune separately.
+std::string tune_key(const fm_ctx *ctx, const fm_batch *b, const fm_raster_params *prm) {
+    return ctx->name + "/" + signature(b) + (prm->deterministic == 1 ? "/det" : "");
 }
 
 struct Built {
@@ -123,23 +123,43 @@ struct Built {
     std::vector<int32_t> vlist;
 };
 
-fm_status resolve_tile(fm_ctx *ctx, const fm_batch *b, const fm_raster_params *prm, int &tw, int &th,
-                       int &order) {
-    tw = prm->tile_w;
-    th = prm->tile_h;
-    auto it = ctx->tuned.find(tune_key(b, prm));
+// The launch a call uses: the params' explicit choices, else the autotuned
+// ones for this batch (when they were tuned for the same tile shape), else
+// the defaults (16x16, longest list first, one wave per tile, depth 64).
+struct Launch {
+    int tw, th, order, waves, depth;
+};
+
+bool split_possible(int tw, int th) { return (tw == 16 && th == 16) || (tw == 16 && th == 8) || (tw == 32 && th == 8); }
+
+fm_status resolve_launch(fm_ctx *ctx, const fm_batch *b, const fm_raster_params *prm, Launch &L) {
+    L.tw = prm->tile_w;
+    L.th = prm->tile_h;
+    auto it = ctx->tuned.find(tune_key(ctx, b, prm));
     const bool hit = it != ctx->tuned.end();
-    if (tw == 0 && th == 0) {
-        tw = hit ? it->second.tw : 16;
-        th = hit ? it->second.th : 16;
+    if (L.tw == 0 && L.th == 0) {
+        L.tw = hit ? it->second.tw : 16;
+        L.th = hit ? it->second.th : 16;
     }
-    if (!fm::tile_shape_supported(tw, th))
-        return fail(ctx, FM_ERR_UNSUPPORTED, "unsupported tile shape " + std::to_string(tw) + "x" +
-                                                 std::to_string(th) + " (use 8x8, 16x8, 16x16, 32x8 or 32x32)");
+    if (!fm::tile_shape_supported(L.tw, L.th))
+        return fail(ctx, FM_ERR_UNSUPPORTED, "unsupported tile shape " + std::to_string(L.tw) + "x" +
+                                                 std::to_string(L.th) + " (use 8x8, 16x8, 16x16, 32x8 or 32x32)");
     if (prm->tile_order < 0 || prm->tile_order > 2)
         return fail(ctx, FM_ERR_INVALID_ARG, "tile_order must be 0, 1 or 2");
-    order = prm->tile_order;
-    if (order == 0) order = (hit && it->second.tw == tw && it->second.th == th) ? it->second.order : 1;
+    if (prm->tile_waves < 0 || prm->tile_waves > 2)
+        return fail(ctx, FM_ERR_INVALID_ARG, "tile_waves must be 0, 1 or 2");
+    if (prm->lds_depth != 0 && prm->lds_depth != 32 && prm->lds_depth != 64 && prm->lds_depth != 128)
+        return fail(ctx, FM_ERR_INVALID_ARG, "lds_depth must be 0, 32, 64 or 128");
+    const bool same = hit && it->second.tw == L.tw && it->second.th == L.th;
+    L.order = prm->tile_order != 0 ? prm->tile_order : (same ? it->second.order : 1);
+    L.waves = prm->tile_waves != 0 ? prm->tile_waves : (same ? it->second.waves : 1);
+    L.depth = prm->lds_depth != 0 ? prm->lds_depth : (same ? it->second.depth : 64);
+    if (prm->deterministic == 1) {
+        if (prm->lds_depth != 0 && prm->lds_depth != 64)
+            return fail(ctx, FM_ERR_INVALID_ARG, "deterministic sums run with lds_depth 64 (or 0)");
+        L.depth = 64;
+    }
+    if (!split_possible(L.tw, L.th)) L.waves = 1;  // 8x8: one block; 32x32: always four quadrant waves
     return FM_OK;
 }
 
@@ -163,13 +183,16 @@ fm_status build(fm_ctx *ctx, const fm_batch *b, const fm_raster_params *prm, int
         if (!std::isfinite(prm->bg[k])) return fail(ctx, FM_ERR_INVALID_ARG, "background must be finite");
     if (max_pairs < 1 || max_pairs > (int64_t)0x7FFFFFFF)
         return fail(ctx, FM_ERR_INVALID_ARG, "max_pairs must be in [1, 2^31-1]");
-    int tw, th, order;
-    fm_status s = resolve_tile(ctx, b, prm, tw, th, order);
+    Launch L;
+    fm_status s = resolve_launch(ctx, b, prm, L);
     if (s != FM_OK) return s;
+    const int tw = L.tw, th = L.th;
 
     Plan &p = out.plan;
     p = Plan();
-    p.lpt = order == 1;
+    p.lpt = L.order == 1;
+    p.split = L.waves == 2;
+    p.depth = L.depth;
     p.V = b->n_views;
     p.S = b->n_submaps;
     p.tile_w = tw;
@@ -179,7 +202,7 @@ fm_status build(fm_ctx *ctx, const fm_batch *b, const fm_raster_params *prm, int
         return fail(ctx, FM_ERR_INVALID_ARG, "deterministic and overwrite must be 0 or 1");
     p.det = prm->deterministic == 1;
     p.overwrite = prm->overwrite == 1;
-    p.nq = (tw == 32 && th == 32) ? 4 : 1;
+    p.nq = (tw == 32 && th == 32) ? 4 : (p.split ? (tw / 8) * (th / 8) : 1);
     for (int i = 0; i < p.S; ++i) {
         const fm_surfels &sm = b->submaps[i];
         if (sm.n < 0 || sm.n > (1 << 28))
@@ -288,6 +311,7 @@ fm_status build(fm_ctx *ctx, const fm_batch *b, const fm_raster_params *prm, int
     p.o_ncount = take(4 * (size_t)NPX);
     p.o_grad = take(4 * fm::kGradStride * (size_t)E);
     p.o_ell = take(sizeof(fm::Ell) * (size_t)E);
+    p.o_emeta = take(4 * (size_t)E);  // per entry: pixel-frame shift and normal flip (backward projection)
     p.o_pose = take(4 * 48 * (size_t)p.V * p.a7_max_blocks);  // 12 floats per (view, wave)
     p.o_loss = take(4 * (size_t)T * 16);
     p.o_tot = take(4 * (size_t)fm::kRadix * fm::kMaxPasses);
@@ -415,7 +439,7 @@ fm_status check_loss(fm_ctx *ctx, const fm_l1_loss *ls) {
     return FM_OK;
 }
 
-// --- tiny JSON cache: {"signature": [tw, th, tile order], ...} ----------------
+// --- tiny JSON cache: {"arch/signature": [tw, th, tile order, waves, lds depth], ...} --
 void load_cache(fm_ctx *ctx, const char *path) {
     std::ifstream f(path);
     if (!f) return;
@@ -437,10 +461,12 @@ void load_cache(fm_ctx *ctx, const char *path) {
             pos = q1 + 1;
             continue;
         }
-        int tw = 0, th = 0, order = 1;
-        const int got = sscanf(s.c_str() + lb, "[%d, %d, %d]", &tw, &th, &order);
+        int tw = 0, th = 0, order = 1, waves = 1, depth = 64;
+        const int got = sscanf(s.c_str() + lb, "[%d, %d, %d, %d, %d]", &tw, &th, &order, &waves, &depth);
         if (got >= 2 && fm::tile_shape_supported(tw, th))
-            ctx->tuned[key] = {tw, th, (got == 3 && (order == 1 || order == 2)) ? order : 1};
+            ctx->tuned[key] = {tw, th, (got >= 3 && (order == 1 || order == 2)) ? order : 1,
+                               (got >= 4 && waves == 2) ? 2 : 1,
+                               (got >= 5 && (depth == 32 || depth == 128)) ? depth : 64};
         pos = rb + 1;
     }
 }
@@ -451,7 +477,8 @@ void save_cache(fm_ctx *ctx, const char *path) {
     f << "{\n";
     size_t k = 0;
     for (auto &kv : ctx->tuned) {
-        f << "  \"" << kv.first << "\": [" << kv.second.tw << ", " << kv.second.th << ", " << kv.second.order << "]";
+        f << "  \"" << kv.first << "\": [" << kv.second.tw << ", " << kv.second.th << ", " << kv.second.order << ", "
+          << kv.second.waves << ", " << kv.second.depth << "]";
         f << (++k < ctx->tuned.size() ? ",\n" : "\n");
     }
     f << "}\n";
@@ -838,21 +865,27 @@ fm_status fm_autotune(fm_ctx *ctx, const fm_batch *b, const fm_raster_params *pr
                       size_t ws_bytes, int64_t max_pairs, const char *cache_path, fm_raster_params *chosen,
                       void *stream) {
     if (!ctx) return FM_ERR_INVALID_ARG;
-    if (!chosen || !prm) return fail(ctx, FM_ERR_INVALID_ARG, "params and chosen must not be NULL");
+    if (!chosen || !prm || !b) return fail(ctx, FM_ERR_INVALID_ARG, "batch, params and chosen must not be NULL");
     if (cache_path) load_cache(ctx, cache_path);
-    const std::string sig = tune_key(b, prm);
+    const std::string sig = tune_key(ctx, b, prm);
     *chosen = *prm;
+    auto put = [&](const fm_ctx::Tuned &t) {
+        chosen->tile_w = t.tw;
+        chosen->tile_h = t.th;
+        chosen->tile_order = t.order;
+        chosen->tile_waves = t.waves;
+        chosen->lds_depth = t.depth;
+    };
     auto hit = ctx->tuned.find(sig);
     if (hit != ctx->tuned.end()) {
-        chosen->tile_w = hit->second.tw;
-        chosen->tile_h = hit->second.th;
-        chosen->tile_order = hit->second.order;
+        put(hit->second);
         return FM_OK;
     }
-    const int shapes[5][2] = {{16, 16}, {8, 8}, {16, 8}, {32, 8}, {32, 32}};
-    hipStream_t st = (hipStream_t)stream;
-    fm_status s = use_device(ctx);
+    fm_status s = check_loss(ctx, ls);
+    if (s == FM_OK) s = check_out(ctx, out);
+    if (s == FM_OK) s = use_device(ctx);
     if (s != FM_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
     struct Events {  // destroyed on every return path
         hipEvent_t e[2] = {nullptr, nullptr};
         ~Events() {
@@ -862,49 +895,80 @@ fm_status fm_autotune(fm_ctx *ctx, const fm_batch *b, const fm_raster_params *pr
     } ev;
     FM_TRY_HIP(hipEventCreate(&ev.e[0]), "hipEventCreate");
     FM_TRY_HIP(hipEventCreate(&ev.e[1]), "hipEventCreate");
-    hipEvent_t e0 = ev.e[0], e1 = ev.e[1];
-    float best = 1e30f;
-    int bw = 16, bh = 16, bo = 1;
-    bool any = false;
-    for (int cand = 0; cand < 10; ++cand) {  // every shape with both tile orders
-        const int *sh = shapes[cand / 2];
+    // Times one candidate: a warm-up call, its pair status, then `reps` calls
+    // (each call's status checked) between two events.  Returns false when
+    // the candidate does not fit the workspace or the capacity.
+    auto time_one = [&](const fm_ctx::Tuned &t, float &ms) -> fm_status {
         fm_raster_params q = *prm;
-        q.tile_w = sh[0];
-        q.tile_h = sh[1];
-        q.tile_order = 1 + cand % 2;
+        q.tile_w = t.tw;
+        q.tile_h = t.th;
+        q.tile_order = t.order;
+        q.tile_waves = t.waves;
+        q.lds_depth = t.depth;
         Built bt;
-        s = build(ctx, b, &q, max_pairs, grads, true, bt);
-        if (s != FM_OK || bt.plan.bytes > ws_bytes) continue;
-        if (check_loss(ctx, ls) != FM_OK || check_out(ctx, out) != FM_OK) break;
-        // warm-up, then time a few repetitions
-        s = run_fused(ctx, bt, &q, b, ws, ls, out, loss, dL_dviewmat, st);
-        if (s != FM_OK) break;
+        fm_status r = build(ctx, b, &q, max_pairs, grads, true, bt);
+        ms = -1.f;
+        if (r != FM_OK || bt.plan.bytes > ws_bytes) return FM_OK;  // does not fit: skipped
+        r = run_fused(ctx, bt, &q, b, ws, ls, out, loss, dL_dviewmat, st);
+        if (r != FM_OK) return r;
         FM_TRY_HIP(hipStreamSynchronize(st), "hipStreamSynchronize");
         fm::Status stt;
         FM_TRY_HIP(hipMemcpy(&stt, static_cast<char *>(ws) + bt.plan.o_status, sizeof(stt), hipMemcpyDeviceToHost),
                    "hipMemcpy(status)");
-        if (stt.overflow) continue;
-        const int reps = 3;
-        FM_TRY_HIP(hipEventRecord(e0, st), "hipEventRecord");
-        for (int r = 0; r < reps; ++r) run_fused(ctx, bt, &q, b, ws, ls, out, loss, dL_dviewmat, st);
-        FM_TRY_HIP(hipEventRecord(e1, st), "hipEventRecord");
-        FM_TRY_HIP(hipEventSynchronize(e1), "hipEventSynchronize");
-        float ms = 0.f;
-        FM_TRY_HIP(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
-        any = true;
-        if (ms < best) {
-            best = ms;
-            bw = sh[0];
-            bh = sh[1];
-            bo = q.tile_order;
+        if (stt.overflow) return FM_OK;  // capacity too small for this shape: skipped
+        const int reps = 5;
+        FM_TRY_HIP(hipEventRecord(ev.e[0], st), "hipEventRecord");
+        for (int k = 0; k < reps; ++k) {
+            r = run_fused(ctx, bt, &q, b, ws, ls, out, loss, dL_dviewmat, st);
+            if (r != FM_OK) return r;
+        }
+        FM_TRY_HIP(hipEventRecord(ev.e[1], st), "hipEventRecord");
+        FM_TRY_HIP(hipEventSynchronize(ev.e[1]), "hipEventSynchronize");
+        float t_ms = 0.f;
+        FM_TRY_HIP(hipEventElapsedTime(&t_ms, ev.e[0], ev.e[1]), "hipEventElapsedTime");
+        ms = t_ms / reps;
+        return FM_OK;
+    };
+    // every tile shape with both tile orders and, where a tile holds several
+    // 8x8 blocks, one wave per tile or per block; then the LDS batch depths
+    // of the fastest (deterministic sums keep depth 64)
+    const int shapes[5][2] = {{16, 16}, {8, 8}, {16, 8}, {32, 8}, {32, 32}};
+    float best = 1e30f;
+    fm_ctx::Tuned bt_best = {16, 16, 1, 1, 64};
+    bool any = false;
+    for (const auto &sh : shapes) {
+        for (int waves = 1; waves <= (split_possible(sh[0], sh[1]) ? 2 : 1); ++waves) {
+            for (int order = 1; order <= 2; ++order) {
+                const fm_ctx::Tuned t = {sh[0], sh[1], order, waves, 64};
+                float ms;
+                s = time_one(t, ms);
+                if (s != FM_OK) return s;
+                if (ms < 0.f) continue;
+                any = true;
+                if (ms < best) {
+                    best = ms;
+                    bt_best = t;
+                }
+            }
         }
     }
-    if (!any) return s != FM_OK ? s : fail(ctx, FM_ERR_WORKSPACE, "no tile shape fits the workspace and capacity");
-    ctx->tuned[sig] = {bw, bh, bo};
+    if (!any) return fail(ctx, FM_ERR_WORKSPACE, "no tile shape fits the workspace and capacity");
+    if (prm->deterministic != 1) {
+        for (int depth : {32, 128}) {
+            fm_ctx::Tuned t = bt_best;
+            t.depth = depth;
+            float ms;
+            s = time_one(t, ms);
+            if (s != FM_OK) return s;
+            if (ms >= 0.f && ms < best) {
+                best = ms;
+                bt_best = t;
+            }
+        }
+    }
+    ctx->tuned[sig] = bt_best;
     if (cache_path) save_cache(ctx, cache_path);
-    chosen->tile_w = bw;
-    chosen->tile_h = bh;
-    chosen->tile_order = bo;
+    put(bt_best);
     return FM_OK;
 }
 

@@ -94,18 +94,28 @@ __device__ __forceinline__ void splat_alpha(const Surf &s, float amin, float ama
     h.alpha = h.hit ? __uint_as_float(ub < um ? ub : um) : 0.f;
 }
 
-// One wave renders a wave tile of WTW x WTH pixels as NB slots of 8x8
-// blocks.  A 32x32 tile is split into four 16x16 quadrants, one wave each,
-// that traverse the same tile list; its pair masks mark quadrants.
-template <int TW, int TH> struct Geo {
-    static constexpr bool QUAD = TW == 32 && TH == 32;
-    static constexpr int WTW = QUAD ? 16 : TW;
-    static constexpr int WTH = QUAD ? 16 : TH;
+// Launch geometry of the blend kernels.  A tile of TW x TH pixels is a grid
+// of 8x8 blocks, which its pair masks mark.  Without SPLIT one wave renders
+// the whole tile as NB slots of 8x8 blocks per lane, except 32x32 tiles,
+// which four 16x16 quadrant waves traverse (their pair masks mark quadrants).
+// With SPLIT (16x8, 16x16 and 32x8 tiles) every 8x8 block of the tile gets a
+// wave of its own, NB = 1: more, shorter waves over the same list, for
+// batches too small to fill the chip.  A wave of a tile with several waves
+// takes the mask bit of its block or quadrant.  DEPTH: records staged in LDS
+// per batch (32, 64 or 128; 64 is one per lane).
+template <int TW_, int TH_, bool SPLIT_ = false, int DEPTH_ = 64> struct Geo {
+    static constexpr int TW = TW_, TH = TH_, DEPTH = DEPTH_;
+    static constexpr bool BIG = TW == 32 && TH == 32;
+    static constexpr bool SPLIT = SPLIT_ && !BIG && (TW > 8 || TH > 8);
+    static constexpr bool QUAD = BIG || SPLIT;  // several waves per tile, one per mask bit
+    static constexpr int WTW = BIG ? 16 : (SPLIT ? 8 : TW);
+    static constexpr int WTH = BIG ? 16 : (SPLIT ? 8 : TH);
     static constexpr int QX = TW / WTW;
     static constexpr int NQ = QX * (TH / WTH);  // waves per tile
     static constexpr int BW = WTW / 8;
     static constexpr int BH = WTH / 8;
     static constexpr int NB = BW * BH;  // pixel slots per lane
+    static_assert(DEPTH == 32 || DEPTH == 64 || DEPTH == 128, "LDS batch depth");
 };
 
 // Deterministic-gradient side of a pair list (meta == nullptr otherwise):
@@ -125,16 +135,17 @@ struct TileCtx {
     int quad;  // the wave's quadrant of a 32x32 tile (0 otherwise)
 };
 
-template <int TW, int TH> struct Slots {
-    float px[Geo<TW, TH>::NB], py[Geo<TW, TH>::NB];
-    int64_t pix[Geo<TW, TH>::NB];
-    bool inside[Geo<TW, TH>::NB];
+template <class G> struct Slots {
+    float px[G::NB], py[G::NB];
+    int64_t pix[G::NB];
+    bool inside[G::NB];
 };
 
-template <int TW, int TH>
+template <class G>
 __device__ __forceinline__ TileCtx tile_ctx(const ViewDesc *views, int V, const uint32_t *ts,
-                                            const uint32_t *te, const uint32_t *order, Slots<TW, TH> &sl) {
-    using Gm = Geo<TW, TH>;
+                                            const uint32_t *te, const uint32_t *order, Slots<G> &sl) {
+    using Gm = G;
+    constexpr int TW = G::TW, TH = G::TH;
     TileCtx c;
     // runs of 16 consecutive blocks share an L2 (the quadrants of a tile
     // are consecutive blocks)
@@ -166,27 +177,33 @@ __device__ __forceinline__ TileCtx tile_ctx(const ViewDesc *views, int V, const 
     return c;
 }
 
-// Stage up to 64 pairs of the tile list into LDS (one per lane).  Entries out
-// of range (impossible for emitted pairs) get an empty block mask.  In a
-// quadrant wave (QUAD) the pair's quadrant bit becomes a mask of all slots.
+// Stage up to G::DEPTH pairs of the tile list into LDS (one per lane and
+// 64-pair half).  Entries out of range (impossible for emitted pairs) get an
+// empty block mask.  In a wave of a tile with several waves (QUAD) the
+// pair's bit of the wave's block or quadrant becomes a mask of all slots.
 // Deterministic lists (meta non-null) hold emission indices: the index goes
 // to sj and meta gives the pair's value.
-template <bool QUAD>
+template <class G>
 __device__ __forceinline__ int stage(const TileCtx &c, uint32_t base, uint32_t end,
                                      const uint32_t *__restrict__ pval, const Rec *__restrict__ rec,
                                      Rec *srec, uint32_t *sval, const PairMeta &pm, uint32_t *sj) {
-    const int cntb = (int)min(64u, end - base);
+    const int cntb = (int)min((uint32_t)G::DEPTH, end - base);
     __syncthreads();
-    if ((int)threadIdx.x < cntb) {
-        uint32_t pv = pval[base + threadIdx.x];
-        if (pm.meta) {
-            sj[threadIdx.x] = pv;
-            pv = pv < pm.cap ? pm.meta[pv] : 0u;  // (an index past the capacity cannot occur)
+#pragma unroll
+    for (int h = 0; h < (G::DEPTH + 63) / 64; ++h) {
+        const int i = h * 64 + (int)threadIdx.x;
+        if (i < cntb) {
+            uint32_t pv = pval[base + i];
+            if (pm.meta) {
+                sj[i] = pv;
+                pv = pv < pm.cap ? pm.meta[pv] : 0u;  // (an index past the capacity cannot occur)
+            }
+            const bool ok = (pv & kEntryMask) < c.n_entries;
+            if (G::QUAD)
+                pv = (pv & kEntryMask) | (((pv >> (kMaskShift + c.quad)) & 1u) ? (0xFu << kMaskShift) : 0u);
+            sval[i] = ok ? pv : 0u;
+            if (ok) srec[i] = rec[pv & kEntryMask];
         }
-        const bool ok = (pv & kEntryMask) < c.n_entries;
-        if (QUAD) pv = (pv & kEntryMask) | (((pv >> (kMaskShift + c.quad)) & 1u) ? (0xFu << kMaskShift) : 0u);
-        sval[threadIdx.x] = ok ? pv : 0u;
-        if (ok) srec[threadIdx.x] = rec[pv & kEntryMask];
     }
     __syncthreads();
     return cntb;
@@ -209,16 +226,16 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
 // NaN, which fails every support test; slots whose pixels have all stopped
 // are dropped from the live set every 8 list positions.  COUNT: also count
 // each pixel's contributors (ncount; the fused path skips it).
-template <int TW, int TH, bool COUNT>
-__device__ __forceinline__ void tile_forward(const TileCtx &c, const Slots<TW, TH> &sl,
+template <class G, bool COUNT>
+__device__ __forceinline__ void tile_forward(const TileCtx &c, const Slots<G> &sl,
                                              const uint32_t *__restrict__ pval, const Rec *__restrict__ rec,
                                              const KParams &kp, Rec *srec, uint32_t *sval,
                                              const PairMeta &pm, uint32_t *sj,
-                                             float (&acc)[Geo<TW, TH>::NB][8], float (&T)[Geo<TW, TH>::NB],
-                                             uint32_t (&slast)[Geo<TW, TH>::NB],
-                                             uint32_t (&ncount)[Geo<TW, TH>::NB]) {
+                                             float (&acc)[G::NB][8], float (&T)[G::NB],
+                                             uint32_t (&slast)[G::NB],
+                                             uint32_t (&ncount)[G::NB]) {
 #pragma clang fp contract(off)
-    using Gm = Geo<TW, TH>;
+    using Gm = G;
     const float rho2 = kp.rho_max * kp.rho_max;
     const float amax = kp.alpha_max;
     const float nan = __builtin_nanf("");
@@ -234,8 +251,8 @@ __device__ __forceinline__ void tile_forward(const TileCtx &c, const Slots<TW, T
         for (int k = 0; k < 8; ++k) acc[q][k] = 0.f;
         if (ballot64(sl.inside[q]) != 0) live |= 1u << q;
     }
-    for (uint32_t base = c.start; base < c.end && live != 0; base += 64) {
-        const int cntb = stage<Gm::QUAD>(c, base, c.end, pval, rec, srec, sval, pm, sj);
+    for (uint32_t base = c.start; base < c.end && live != 0; base += G::DEPTH) {
+        const int cntb = stage<Gm>(c, base, c.end, pval, rec, srec, sval, pm, sj);
         for (int j = 0; j < cntb; ++j) {
             const uint32_t m = (__builtin_amdgcn_readfirstlane(sval[j]) >> kMaskShift) & live;
             if (m != 0) {
@@ -335,15 +352,15 @@ __device__ __forceinline__ void adjoint_terms(const Hit &h, const Surf &s, const
 // recomputed T repeats the forward's exactly, so a pixel still has
 // contributions ahead exactly while T > Tf.  HAS_N: the normal map carries a
 // gradient.
-template <int TW, int TH, bool HAS_N, bool DET>
-__device__ __forceinline__ void tile_backward(const TileCtx &c, const Slots<TW, TH> &sl,
+template <class G, bool HAS_N, bool DET>
+__device__ __forceinline__ void tile_backward(const TileCtx &c, const Slots<G> &sl,
                                               const uint32_t *__restrict__ pval, const Rec *__restrict__ rec,
                                               const KParams &kp, Rec *srec, uint32_t *sval,
                                               const PairMeta &pm, uint32_t *sj,
-                                              const float (&g)[Geo<TW, TH>::NB][8], const float (&S)[Geo<TW, TH>::NB],
-                                              const float (&Tf)[Geo<TW, TH>::NB],
-                                              const uint32_t (&bound)[Geo<TW, TH>::NB], float *__restrict__ grad) {
-    using Gm = Geo<TW, TH>;
+                                              const float (&g)[G::NB][8], const float (&S)[G::NB],
+                                              const float (&Tf)[G::NB],
+                                              const uint32_t (&bound)[G::NB], float *__restrict__ grad) {
+    using Gm = G;
     const float rho2 = kp.rho_max * kp.rho_max;
     const float amax = kp.alpha_max;
     float T[Gm::NB], Sk[Gm::NB];
@@ -359,8 +376,8 @@ __device__ __forceinline__ void tile_backward(const TileCtx &c, const Slots<TW, 
     const uint32_t len = c.end - c.start;
     const uint32_t end = c.start + (maxlast < len ? maxlast : len);
     const int comp = wave_reduce16_component();
-    for (uint32_t base = c.start; base < end; base += 64) {
-        const int cntb = stage<Gm::QUAD>(c, base, end, pval, rec, srec, sval, pm, sj);
+    for (uint32_t base = c.start; base < end; base += G::DEPTH) {
+        const int cntb = stage<Gm>(c, base, end, pval, rec, srec, sval, pm, sj);
         const uint32_t kbase = base - c.start;
         for (int j = 0; j < cntb; ++j) {
             const uint32_t k = kbase + (uint32_t)j;
@@ -414,8 +431,70 @@ __device__ __forceinline__ void tile_backward(const TileCtx &c, const Slots<TW, 
     }
 }
 
+// Map-fusion pruning score traversal (forward side, no adjoint): walks the
+// tile list again like the forward, recomputing T exactly, for the slots
+// whose pixel is flagged (flag[q], with final transmittance Tf[q]); every
+// surfel's weights alpha T on the flagged pixels of the wave are summed and
+// added into the first float of its entry's gradient slot (one atomic per
+// (tile, surfel) that touches a flagged pixel).
+template <class G>
+__device__ __forceinline__ void tile_score(const TileCtx &c, const Slots<G> &sl,
+                                           const uint32_t *__restrict__ pval, const Rec *__restrict__ rec,
+                                           const KParams &kp, Rec *srec, uint32_t *sval, const PairMeta &pm,
+                                           uint32_t *sj, const bool (&flag)[G::NB],
+                                           const float (&Tf)[G::NB],
+                                           const uint32_t (&bound)[G::NB], float *__restrict__ grad) {
+#pragma clang fp contract(off)
+    using Gm = G;
+    const float rho2 = kp.rho_max * kp.rho_max;
+    float T[Gm::NB];
+    uint32_t smax[Gm::NB];
+    uint32_t maxlast = 0;
+#pragma unroll
+    for (int q = 0; q < Gm::NB; ++q) {
+        T[q] = 1.f;
+        // a slot without flagged pixels is not traversed
+        smax[q] = ballot64(flag[q]) != 0 ? bound[q] : 0u;
+        maxlast = smax[q] > maxlast ? smax[q] : maxlast;
+    }
+    const uint32_t len = c.end - c.start;
+    const uint32_t end = c.start + (maxlast < len ? maxlast : len);
+    for (uint32_t base = c.start; base < end; base += G::DEPTH) {
+        const int cntb = stage<Gm>(c, base, end, pval, rec, srec, sval, pm, sj);
+        const uint32_t kbase = base - c.start;
+        for (int j = 0; j < cntb; ++j) {
+            const uint32_t k = kbase + (uint32_t)j;
+            uint32_t m = __builtin_amdgcn_readfirstlane(sval[j]) >> kMaskShift;
+#pragma unroll
+            for (int q = 0; q < Gm::NB; ++q)
+                if (k >= smax[q]) m &= ~(1u << q);
+            if (m == 0) continue;
+            Surf s;
+            load_surf(&srec[j], s);
+            float w = 0.f;
+            bool any = false;
+#pragma unroll
+            for (int q = 0; q < Gm::NB; ++q) {
+                if (((m >> q) & 1u) == 0) continue;
+                Hit h;
+                splat_geom(s, sl.px[q], sl.py[q], rho2, flag[q] && T[q] > Tf[q], h);
+                if (ballot64(h.in) == 0) continue;
+                splat_alpha<false>(s, kp.alpha_min, kp.alpha_max, h);
+                // alpha = 0 where the surfel misses: T and the sum do not move
+                w = fmaf(h.alpha, T[q], w);
+                T[q] = T[q] * (1.f - h.alpha);
+                any = true;
+            }
+            if (!any) continue;
+            const float tot = wave_sum(w);
+            // (staging has mapped a deterministic list's emission index to the pair value)
+            if (lane_id() == 0 && tot != 0.f) atomicAdd(grad + (int64_t)(sval[j] & kEntryMask) * kp.gstride, tot);
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
-template <int TW, int TH>
+template <class G>
 __global__ __launch_bounds__(64) void k_render_fwd(const ViewDesc *__restrict__ views, int V,
                                                     const uint32_t *__restrict__ ts, const uint32_t *__restrict__ te,
                                                     const uint32_t *__restrict__ order,
@@ -423,14 +502,14 @@ __global__ __launch_bounds__(64) void k_render_fwd(const ViewDesc *__restrict__ 
                                                     KParams kp, int64_t NPX, fm_outputs out,
                                                     float *__restrict__ tfinal, uint32_t *__restrict__ nlast_out,
                                                     uint32_t *__restrict__ ncount_out, PairMeta pm) {
-    using Gm = Geo<TW, TH>;
-    __shared__ Rec srec[64];
-    __shared__ uint32_t sval[64], sj[64];
-    Slots<TW, TH> sl;
-    const TileCtx c = tile_ctx<TW, TH>(views, V, ts, te, order, sl);
+    using Gm = G;
+    __shared__ Rec srec[G::DEPTH];
+    __shared__ uint32_t sval[G::DEPTH], sj[G::DEPTH];
+    Slots<G> sl;
+    const TileCtx c = tile_ctx<G>(views, V, ts, te, order, sl);
     float acc[Gm::NB][8], T[Gm::NB];
     uint32_t slast[Gm::NB], nc[Gm::NB];
-    tile_forward<TW, TH, true>(c, sl, pval, rec, kp, srec, sval, pm, sj, acc, T, slast, nc);
+    tile_forward<G, true>(c, sl, pval, rec, kp, srec, sval, pm, sj, acc, T, slast, nc);
 #pragma unroll
     for (int q = 0; q < Gm::NB; ++q) {
         if (!sl.inside[q]) continue;
@@ -449,7 +528,7 @@ __global__ __launch_bounds__(64) void k_render_fwd(const ViewDesc *__restrict__ 
     }
 }
 
-template <int TW, int TH, bool HAS_N, bool DET>
+template <class G, bool HAS_N, bool DET>
 __global__ __launch_bounds__(64) void k_render_bwd(const ViewDesc *__restrict__ views, int V,
                                                     const uint32_t *__restrict__ ts, const uint32_t *__restrict__ te,
                                                     const uint32_t *__restrict__ order,
@@ -458,11 +537,11 @@ __global__ __launch_bounds__(64) void k_render_bwd(const ViewDesc *__restrict__ 
                                                     const float *__restrict__ tfinal,
                                                     const uint32_t *__restrict__ nlast_in, float *__restrict__ grad,
                                                     PairMeta pm) {
-    using Gm = Geo<TW, TH>;
-    __shared__ Rec srec[64];
-    __shared__ uint32_t sval[64], sj[64];
-    Slots<TW, TH> sl;
-    const TileCtx c = tile_ctx<TW, TH>(views, V, ts, te, order, sl);
+    using Gm = G;
+    __shared__ Rec srec[G::DEPTH];
+    __shared__ uint32_t sval[G::DEPTH], sj[G::DEPTH];
+    Slots<G> sl;
+    const TileCtx c = tile_ctx<G>(views, V, ts, te, order, sl);
     float g[Gm::NB][8], S[Gm::NB], Tf[Gm::NB];
     uint32_t bound[Gm::NB];
 #pragma unroll
@@ -490,10 +569,10 @@ __global__ __launch_bounds__(64) void k_render_bwd(const ViewDesc *__restrict__ 
                 S[q] += g[q][4] * out.normal[p] + g[q][5] * out.normal[NPX + p] + g[q][6] * out.normal[2 * NPX + p];
         }
     }
-    tile_backward<TW, TH, HAS_N, DET>(c, sl, pval, rec, kp, srec, sval, pm, sj, g, S, Tf, bound, grad);
+    tile_backward<G, HAS_N, DET>(c, sl, pval, rec, kp, srec, sval, pm, sj, g, S, Tf, bound, grad);
 }
 
-template <int TW, int TH, bool DET>
+template <class G, bool DET>
 __global__ __launch_bounds__(64) void k_render_fused(const ViewDesc *__restrict__ views, int V,
                                                       const uint32_t *__restrict__ ts, const uint32_t *__restrict__ te,
                                                     const uint32_t *__restrict__ order,
@@ -502,14 +581,14 @@ __global__ __launch_bounds__(64) void k_render_fused(const ViewDesc *__restrict_
                                                       float *__restrict__ tfinal, uint32_t *__restrict__ nlast_out,
                                                       float *__restrict__ grad, float *__restrict__ loss_part,
                                                       PairMeta pm) {
-    using Gm = Geo<TW, TH>;
-    __shared__ Rec srec[64];
-    __shared__ uint32_t sval[64], sj[64];
-    Slots<TW, TH> sl;
-    const TileCtx c = tile_ctx<TW, TH>(views, V, ts, te, order, sl);
+    using Gm = G;
+    __shared__ Rec srec[G::DEPTH];
+    __shared__ uint32_t sval[G::DEPTH], sj[G::DEPTH];
+    Slots<G> sl;
+    const TileCtx c = tile_ctx<G>(views, V, ts, te, order, sl);
     float acc[Gm::NB][8], T[Gm::NB];
     uint32_t slast[Gm::NB], nc[Gm::NB];
-    tile_forward<TW, TH, false>(c, sl, pval, rec, kp, srec, sval, pm, sj, acc, T, slast, nc);
+    tile_forward<G, false>(c, sl, pval, rec, kp, srec, sval, pm, sj, acc, T, slast, nc);
     float g[Gm::NB][8], S[Gm::NB], Tf[Gm::NB];
     float l = 0.f;
     const float npx = (float)c.W * (float)c.H;
@@ -554,7 +633,60 @@ __global__ __launch_bounds__(64) void k_render_fused(const ViewDesc *__restrict_
     }
     const float lsum = wave_sum(l);
     if (threadIdx.x == 0) loss_part[blockIdx.x] = lsum;
-    tile_backward<TW, TH, false, DET>(c, sl, pval, rec, kp, srec, sval, pm, sj, g, S, Tf, slast, grad);
+    tile_backward<G, false, DET>(c, sl, pval, rec, kp, srec, sval, pm, sj, g, S, Tf, slast, grad);
+}
+
+// Pruning products of map fusion: forward render (outputs written as by the
+// plain forward), the per-pixel error flag (a caller mask, or mean over the
+// channels of |I - I*| above tau_rgb, or |D - D*| above tau_depth with a
+// depth target), then the score traversal of the same list.
+template <class G>
+__global__ __launch_bounds__(64) void k_render_prune(const ViewDesc *__restrict__ views, int V,
+                                                      const uint32_t *__restrict__ ts, const uint32_t *__restrict__ te,
+                                                      const uint32_t *__restrict__ order,
+                                                      const uint32_t *__restrict__ pval, const Rec *__restrict__ rec,
+                                                      KParams kp, int64_t NPX, fm_outputs out, PruneArgs pa,
+                                                      float *__restrict__ tfinal, float *__restrict__ grad,
+                                                      PairMeta pm) {
+#pragma clang fp contract(off)
+    using Gm = G;
+    __shared__ Rec srec[G::DEPTH];
+    __shared__ uint32_t sval[G::DEPTH], sj[G::DEPTH];
+    Slots<G> sl;
+    const TileCtx c = tile_ctx<G>(views, V, ts, te, order, sl);
+    float acc[Gm::NB][8], T[Gm::NB];
+    uint32_t slast[Gm::NB], nc[Gm::NB];
+    tile_forward<G, false>(c, sl, pval, rec, kp, srec, sval, pm, sj, acc, T, slast, nc);
+    bool flag[Gm::NB];
+#pragma unroll
+    for (int q = 0; q < Gm::NB; ++q) {
+        flag[q] = false;
+        if (!sl.inside[q]) continue;
+        const int64_t p = sl.pix[q];
+        const float o0 = acc[q][0] + T[q] * kp.bg[0], o1 = acc[q][1] + T[q] * kp.bg[1],
+                    o2 = acc[q][2] + T[q] * kp.bg[2];
+        out.rgb[p] = o0;
+        out.rgb[NPX + p] = o1;
+        out.rgb[2 * NPX + p] = o2;
+        out.depth[p] = acc[q][3];
+        out.normal[p] = acc[q][4];
+        out.normal[NPX + p] = acc[q][5];
+        out.normal[2 * NPX + p] = acc[q][6];
+        out.alpha[p] = acc[q][7];
+        tfinal[p] = T[q];
+        bool f;
+        if (pa.mask_in) {
+            f = pa.mask_in[p] != 0;
+        } else {
+            const float e = (fabsf(o0 - pa.target_rgb[p]) + fabsf(o1 - pa.target_rgb[NPX + p])) +
+                            fabsf(o2 - pa.target_rgb[2 * NPX + p]);
+            f = e / 3.f > pa.tau_rgb;
+            if (pa.target_depth) f = f || fabsf(acc[q][3] - pa.target_depth[p]) > pa.tau_depth;
+        }
+        if (pa.mask_out) pa.mask_out[p] = f ? 1 : 0;
+        flag[q] = f;
+    }
+    tile_score<G>(c, sl, pval, rec, kp, srec, sval, pm, sj, flag, T, slast, grad);
 }
 
 __global__ __launch_bounds__(1024) void k_loss_reduce(const float *__restrict__ part, int64_t n,
@@ -584,10 +716,10 @@ PairMeta pair_meta(const Plan &p, void *ws) {
     return pm;
 }
 
-template <int TW, int TH>
+template <class G>
 hipError_t fwd_t(const Plan &p, void *ws, const KParams &kp, const fm_outputs &out, hipStream_t st) {
     const uint32_t *pval = at<uint32_t>(ws, p.pairs_in_alt ? p.o_pval2 : p.o_pval);
-    hipLaunchKernelGGL((k_render_fwd<TW, TH>), dim3((unsigned)(p.T * Geo<TW, TH>::NQ)), dim3(64), 0, st,
+    hipLaunchKernelGGL((k_render_fwd<G>), dim3((unsigned)(p.T * G::NQ)), dim3(64), 0, st,
                        at<ViewDesc>(ws, p.o_views), p.V, at<uint32_t>(ws, p.o_tstart),
                        at<uint32_t>(ws, p.o_tend), tile_order(p, ws), pval, at<Rec>(ws, p.o_rec), kp, p.NPX, out,
                        at<float>(ws, p.o_tfinal), at<uint32_t>(ws, p.o_nlast), at<uint32_t>(ws, p.o_ncount),
@@ -595,46 +727,64 @@ hipError_t fwd_t(const Plan &p, void *ws, const KParams &kp, const fm_outputs &o
     return hipGetLastError();
 }
 
-template <int TW, int TH, bool HAS_N, bool DET>
+template <class G, bool HAS_N, bool DET>
 void bwd_launch(const Plan &p, void *ws, const KParams &kp, const fm_outputs &out, const fm_grad_outputs &g,
                 hipStream_t st) {
     const uint32_t *pval = at<uint32_t>(ws, p.pairs_in_alt ? p.o_pval2 : p.o_pval);
-    hipLaunchKernelGGL((k_render_bwd<TW, TH, HAS_N, DET>), dim3((unsigned)(p.T * Geo<TW, TH>::NQ)), dim3(64), 0,
+    hipLaunchKernelGGL((k_render_bwd<G, HAS_N, DET>), dim3((unsigned)(p.T * G::NQ)), dim3(64), 0,
                        st, at<ViewDesc>(ws, p.o_views), p.V, at<uint32_t>(ws, p.o_tstart),
                        at<uint32_t>(ws, p.o_tend), tile_order(p, ws), pval, at<Rec>(ws, p.o_rec), kp, p.NPX, out, g,
                        at<float>(ws, p.o_tfinal), at<uint32_t>(ws, p.o_nlast), at<float>(ws, p.o_grad),
                        pair_meta(p, ws));
 }
 
-template <int TW, int TH>
+template <class G>
 hipError_t bwd_t(const Plan &p, void *ws, const KParams &kp, const fm_outputs &out, const fm_grad_outputs &g,
                  hipStream_t st) {
     if (g.normal) {
-        if (p.det) bwd_launch<TW, TH, true, true>(p, ws, kp, out, g, st);
-        else bwd_launch<TW, TH, true, false>(p, ws, kp, out, g, st);
+        if (p.det) bwd_launch<G, true, true>(p, ws, kp, out, g, st);
+        else bwd_launch<G, true, false>(p, ws, kp, out, g, st);
     } else {
-        if (p.det) bwd_launch<TW, TH, false, true>(p, ws, kp, out, g, st);
-        else bwd_launch<TW, TH, false, false>(p, ws, kp, out, g, st);
+        if (p.det) bwd_launch<G, false, true>(p, ws, kp, out, g, st);
+        else bwd_launch<G, false, false>(p, ws, kp, out, g, st);
     }
     return hipGetLastError();
 }
 
-template <int TW, int TH, bool DET>
+template <class G, bool DET>
 void fused_launch(const Plan &p, void *ws, const KParams &kp, const LossArgs &la, const fm_outputs &out,
                   hipStream_t st) {
     const uint32_t *pval = at<uint32_t>(ws, p.pairs_in_alt ? p.o_pval2 : p.o_pval);
-    hipLaunchKernelGGL((k_render_fused<TW, TH, DET>), dim3((unsigned)(p.T * Geo<TW, TH>::NQ)), dim3(64), 0, st,
+    hipLaunchKernelGGL((k_render_fused<G, DET>), dim3((unsigned)(p.T * G::NQ)), dim3(64), 0, st,
                        at<ViewDesc>(ws, p.o_views), p.V, at<uint32_t>(ws, p.o_tstart),
                        at<uint32_t>(ws, p.o_tend), tile_order(p, ws), pval, at<Rec>(ws, p.o_rec), kp, p.NPX, out, la,
                        at<float>(ws, p.o_tfinal), at<uint32_t>(ws, p.o_nlast), at<float>(ws, p.o_grad),
                        at<float>(ws, p.o_loss), pair_meta(p, ws));
 }
 
-template <int TW, int TH>
+// Deterministic sums run with the default LDS depth only (the plan forces it).
+template <class G>
 hipError_t fused_t(const Plan &p, void *ws, const KParams &kp, const LossArgs &la, const fm_outputs &out,
                    hipStream_t st) {
-    if (p.det) fused_launch<TW, TH, true>(p, ws, kp, la, out, st);
-    else fused_launch<TW, TH, false>(p, ws, kp, la, out, st);
+    if constexpr (G::DEPTH == 64) {
+        if (p.det) {
+            fused_launch<G, true>(p, ws, kp, la, out, st);
+            return hipGetLastError();
+        }
+    }
+    if (p.det) return hipErrorInvalidValue;
+    fused_launch<G, false>(p, ws, kp, la, out, st);
+    return hipGetLastError();
+}
+
+template <class G>
+hipError_t prune_t(const Plan &p, void *ws, const KParams &kp, const PruneArgs &pa, const fm_outputs &out,
+                   hipStream_t st) {
+    const uint32_t *pval = at<uint32_t>(ws, p.pairs_in_alt ? p.o_pval2 : p.o_pval);
+    hipLaunchKernelGGL((k_render_prune<G>), dim3((unsigned)(p.T * G::NQ)), dim3(64), 0, st,
+                       at<ViewDesc>(ws, p.o_views), p.V, at<uint32_t>(ws, p.o_tstart), at<uint32_t>(ws, p.o_tend),
+                       tile_order(p, ws), pval, at<Rec>(ws, p.o_rec), kp, p.NPX, out, pa,
+                       at<float>(ws, p.o_tfinal), at<float>(ws, p.o_grad), pair_meta(p, ws));
     return hipGetLastError();
 }
 
@@ -703,31 +853,44 @@ bool tile_shape_supported(int tw, int th) {
            (tw == 32 && th == 8) || (tw == 32 && th == 32);
 }
 
-#define FM_DISPATCH(FN, ...)                                                     \
-    do {                                                                         \
-        if (p.tile_w == 16 && p.tile_h == 16) return FN<16, 16>(__VA_ARGS__);    \
-        if (p.tile_w == 8 && p.tile_h == 8) return FN<8, 8>(__VA_ARGS__);        \
-        if (p.tile_w == 16 && p.tile_h == 8) return FN<16, 8>(__VA_ARGS__);      \
-        if (p.tile_w == 32 && p.tile_h == 8) return FN<32, 8>(__VA_ARGS__);      \
-        if (p.tile_w == 32 && p.tile_h == 32) return FN<32, 32>(__VA_ARGS__);    \
-        return hipErrorInvalidValue;                                             \
+// Dispatch on the tile shape, the wave split (16x8, 16x16, 32x8) and the LDS
+// batch depth D.
+#define FM_DISPATCH(FN, D, ...)                                                                   \
+    do {                                                                                          \
+        if (p.tile_w == 16 && p.tile_h == 16)                                                     \
+            return p.split ? FN<Geo<16, 16, true, D>>(__VA_ARGS__) : FN<Geo<16, 16, false, D>>(__VA_ARGS__); \
+        if (p.tile_w == 8 && p.tile_h == 8) return FN<Geo<8, 8, false, D>>(__VA_ARGS__);           \
+        if (p.tile_w == 16 && p.tile_h == 8)                                                      \
+            return p.split ? FN<Geo<16, 8, true, D>>(__VA_ARGS__) : FN<Geo<16, 8, false, D>>(__VA_ARGS__); \
+        if (p.tile_w == 32 && p.tile_h == 8)                                                      \
+            return p.split ? FN<Geo<32, 8, true, D>>(__VA_ARGS__) : FN<Geo<32, 8, false, D>>(__VA_ARGS__); \
+        if (p.tile_w == 32 && p.tile_h == 32) return FN<Geo<32, 32, false, D>>(__VA_ARGS__);       \
+        return hipErrorInvalidValue;                                                              \
     } while (0)
 
 hipError_t launch_render_fwd(const Plan &p, void *ws, const KParams &kp, const fm_outputs &out, hipStream_t st) {
     if (p.T == 0) return hipSuccess;
-    FM_DISPATCH(fwd_t, p, ws, kp, out, st);
+    FM_DISPATCH(fwd_t, 64, p, ws, kp, out, st);
 }
 
 hipError_t launch_render_bwd(const Plan &p, void *ws, const KParams &kp, const fm_outputs &out,
                              const fm_grad_outputs &g, hipStream_t st) {
     if (p.T == 0) return hipSuccess;
-    FM_DISPATCH(bwd_t, p, ws, kp, out, g, st);
+    FM_DISPATCH(bwd_t, 64, p, ws, kp, out, g, st);
 }
 
 hipError_t launch_render_fused(const Plan &p, void *ws, const KParams &kp, const LossArgs &la,
                                const fm_outputs &out, hipStream_t st) {
     if (p.T == 0) return hipSuccess;
-    FM_DISPATCH(fused_t, p, ws, kp, la, out, st);
+    if (p.depth == 32) FM_DISPATCH(fused_t, 32, p, ws, kp, la, out, st);
+    if (p.depth == 128) FM_DISPATCH(fused_t, 128, p, ws, kp, la, out, st);
+    FM_DISPATCH(fused_t, 64, p, ws, kp, la, out, st);
+}
+
+hipError_t launch_render_prune(const Plan &p, void *ws, const KParams &kp, const PruneArgs &pa,
+                               const fm_outputs &out, hipStream_t st) {
+    if (p.T == 0) return hipSuccess;
+    FM_DISPATCH(prune_t, 64, p, ws, kp, pa, out, st);
 }
 
 hipError_t launch_det_clear(const Plan &p, void *ws, int gstride, hipStream_t st) {
@@ -753,8 +916,8 @@ hipError_t launch_det_reduce(const Plan &p, void *ws, int gstride, hipStream_t s
 
 hipError_t launch_loss_reduce(const Plan &p, void *ws, float *loss, hipStream_t st) {
     if (p.T == 0 || !loss) return hipSuccess;
-    // one partial per block: 32x32 tiles run four blocks each
-    const int64_t nb = p.T * ((p.tile_w == 32 && p.tile_h == 32) ? 4 : 1);
+    // one partial per block: a tile runs nq blocks
+    const int64_t nb = p.T * p.nq;
     hipLaunchKernelGGL(k_loss_reduce, dim3(1), dim3(1024), 0, st, at<float>(ws, p.o_loss), nb, loss,
                        (int)p.overwrite);
     return hipGetLastError();

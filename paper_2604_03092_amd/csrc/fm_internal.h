@@ -156,7 +156,7 @@ struct Plan {
            o_key2 = 0, o_val = 0, o_val2 = 0, o_scan = 0, o_pkey = 0, o_pval = 0, o_pkey2 = 0,
            o_pval2 = 0, o_hist = 0, o_tstart = 0, o_tend = 0, o_tfinal = 0, o_nlast = 0, o_ncount = 0, o_grad = 0,
            o_pose = 0, o_loss = 0, o_tot = 0, o_ell = 0, o_chunk = 0, o_meta = 0, o_part = 0, o_tkey = 0,
-           o_tkey2 = 0, o_torder = 0;
+           o_tkey2 = 0, o_torder = 0, o_emeta = 0;
     size_t bytes = 0;
     // deterministic gradients: the sorted lists hold emission indices, o_meta
     // maps them to pair values, and the adjoint writes one partial slot per
@@ -164,7 +164,9 @@ struct Plan {
     bool det = false;
     bool overwrite = false;  // store (not add) surfel gradients, pose gradients and the loss
     bool lpt = true;         // blend takes tiles longest list first (else image order)
-    int nq = 1;  // waves per tile (four 16x16 quadrants of a 32x32 tile)
+    int nq = 1;  // waves (blocks of the blend) per tile: four 16x16 quadrants of a 32x32 tile, one per 8x8 block with split
+    bool split = false;  // 16x8, 16x16, 32x8 tiles: one blend wave per 8x8 block instead of one per tile
+    int depth = 64;      // records the fused blend stages in LDS per batch (32, 64 or 128)
     bool pairs_in_alt = false;  // final sorted pairs live in the *2 buffers
 };
 

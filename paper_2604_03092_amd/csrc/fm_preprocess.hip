@@ -80,7 +80,7 @@ __global__ __launch_bounds__(256) void k_preprocess(const ViewDesc *__restrict__
                                                      const float *__restrict__ viewmat, KParams kp,
                                                      Rec *__restrict__ rec, uint32_t *__restrict__ key,
                                                      uint32_t *__restrict__ cnt, float4 *__restrict__ grad,
-                                                     Ell *__restrict__ ell) {
+                                                     Ell *__restrict__ ell, uint32_t *__restrict__ emeta) {
 #pragma clang fp contract(off)
     const int64_t e0 = (int64_t)blockIdx.x * 256;
     const int v = view_of_entry(views, V, e0);
@@ -204,12 +204,16 @@ __global__ __launch_bounds__(256) void k_preprocess(const ViewDesc *__restrict__
                             r.z = (float)depth;
                             r.xs = (float)ixc;
                             r.ys = (float)iyc;
-                            r.lsig = (float)log2(sigma);
+                            // log2(sigma) in FP32: the blend's exponent (one ulp moves sigma G by
+                            // < 1e-6 relative; no integer decision depends on it)
+                            r.lsig = __log2f(f_sig);
                             // culling ellipse: support radius with the opacity cut-off,
                             // rho_eff^2 = min(rho_max^2, 2 ln(sigma / alpha_min)), enlarged
                             // by 0.2% so that it contains every pixel the FP32 blend accepts
                             {
-                                double re2 = 2.0 * log(sigma / (double)kp.alpha_min);
+                                // 2 ln(sigma / alpha_min) in FP32 (its rounding is far inside the
+                                // 0.2% enlargement)
+                                double re2 = (double)(2.f * (__logf(f_sig) - __logf(kp.alpha_min)));
                                 if (re2 > rho2) re2 = rho2;
                                 const double E00 = re2 * (H[0] * H[0] + H[1] * H[1]) - H[2] * H[2];
                                 const double E01 = re2 * (H[0] * H[3] + H[1] * H[4]) - H[2] * H[5];
@@ -242,6 +246,9 @@ __global__ __launch_bounds__(256) void k_preprocess(const ViewDesc *__restrict__
                                 ell[e] = el;
                             }
                             rec[e] = r;
+                            // what the backward projection needs of the record: the
+                            // pixel-frame shift and whether the normal was flipped
+                            emeta[e] = (uint32_t)ixc | ((uint32_t)iyc << 14) | (sgn < 0.0 ? 0x80000000u : 0u);
                             const int tx0 = px0 / kp.tile_w, tx1 = px1 / kp.tile_w;
                             const int ty0 = py0 / kp.tile_h, ty1 = py1 / kp.tile_h;
                             out_cnt = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
@@ -284,10 +291,31 @@ __device__ inline int submap_of_block(const SubmapDesc *s, int S, int b) {
     return lo;
 }
 
+// Pruning scores: one thread per surfel of a rendered submap sums its
+// entries' scores (the first float of each gradient slot of an entry with
+// pairs) over the submap's views in view order and stores the sum into the
+// submap's g_opacity plane, which the pruning call points at the caller's
+// score array.
+__global__ __launch_bounds__(256) void k_score_reduce(const SubmapDesc *__restrict__ subs, int S,
+                                                       const int32_t *__restrict__ vlist,
+                                                       const ViewDesc *__restrict__ views,
+                                                       const uint32_t *__restrict__ cnt,
+                                                       const float *__restrict__ grad, int gstride) {
+    const SubmapDesc &sd = subs[submap_of_block(subs, S, blockIdx.x)];
+    const int i = ((int)blockIdx.x - sd.block_base) * 256 + (int)threadIdx.x;
+    if (i >= sd.n || !sd.g_opacity) return;
+    float sc = 0.f;
+    for (int k = 0; k < sd.view_count; ++k) {
+        const int64_t e = (int64_t)views[vlist[sd.view_begin + k]].entry_base + i;
+        if (cnt[e] != 0) sc += grad[e * gstride];
+    }
+    sd.g_opacity[i] = sc;
+}
+
 __global__ __launch_bounds__(256) void k_preprocess_bwd(
     const SubmapDesc *__restrict__ subs, int S, const int32_t *__restrict__ vlist,
     const ViewDesc *__restrict__ views, const float *__restrict__ intr,
-    const float *__restrict__ viewmat, const Rec *__restrict__ rec, const uint32_t *__restrict__ cnt,
+    const float *__restrict__ viewmat, const uint32_t *__restrict__ emeta, const uint32_t *__restrict__ cnt,
     const float4 *__restrict__ grad, int gstride, float *__restrict__ pose_part, int max_blocks,
     int overwrite) {
     const int s_idx = submap_of_block(subs, S, blockIdx.x);
@@ -338,9 +366,8 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
             const float4 g0 = gp[0], g1 = gp[1], g2 = gp[2], g3 = gp[3];
             const float g[20] = {g0.x, g0.y, g0.z, g0.w, g1.x, g1.y, g1.z, g1.w, g2.x, g2.y,
                                  g2.z, g2.w, g3.x, g3.y, g3.z, g3.w, g4.x, g4.y, g4.z, g4.w};
-            const Rec &rc = rec[e];
-            const float xs = rc.xs, ys = rc.ys;
-            const float nr0 = rc.nrm[0], nr1 = rc.nrm[1], nr2 = rc.nrm[2];
+            const uint32_t em = emeta[e];
+            const float xs = (float)(em & 0x3FFFu), ys = (float)((em >> 14) & 0x3FFFu);
             const float *vm = viewmat + 12 * v;
             const float R[9] = {vm[0], vm[1], vm[2], vm[4], vm[5], vm[6], vm[8], vm[9], vm[10]};
             const float t[3] = {vm[3], vm[7], vm[11]};
@@ -387,7 +414,7 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
                 dM[3 + c] = fy * dr1[c];
                 dM[6 + c] = ox * dr0[c] + oy * dr1[c] + dr2[c];
             }
-            const float sgn = (n0[0] * nr0 + n0[1] * nr1 + n0[2] * nr2) >= 0.f ? 1.f : -1.f;
+            const float sgn = (em & 0x80000000u) ? -1.f : 1.f;  // the projection's camera-facing flip
             const float dp[3] = {dM[2], dM[5], dM[8] + g[13]};
             const float dtu[3] = {su * dM[0], su * dM[3], su * dM[6]};
             const float dtv[3] = {sv * dM[1], sv * dM[4], sv * dM[7]};
@@ -538,7 +565,7 @@ hipError_t launch_preprocess(const Plan &p, void *ws, const KParams &kp, const f
     hipLaunchKernelGGL(k_preprocess, dim3(blocks), dim3(256), 0, st, at<ViewDesc>(ws, p.o_views), p.V,
                        intr, viewmat, kp, at<Rec>(ws, p.o_rec), at<uint32_t>(ws, p.o_key),
                        at<uint32_t>(ws, p.o_cnt), zero_grad ? at<float4>(ws, p.o_grad) : nullptr,
-                       at<Ell>(ws, p.o_ell));
+                       at<Ell>(ws, p.o_ell), at<uint32_t>(ws, p.o_emeta));
     return hipGetLastError();
 }
 
@@ -550,12 +577,20 @@ hipError_t launch_zero_grad(const Plan &p, void *ws, int gstride, hipStream_t st
     return hipGetLastError();
 }
 
+hipError_t launch_score_reduce(const Plan &p, void *ws, int gstride, hipStream_t st) {
+    if (p.a7_blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_score_reduce, dim3(p.a7_blocks), dim3(256), 0, st, at<SubmapDesc>(ws, p.o_subs), p.S,
+                       at<int32_t>(ws, p.o_vlist), at<ViewDesc>(ws, p.o_views), at<uint32_t>(ws, p.o_cnt),
+                       at<float>(ws, p.o_grad), gstride);
+    return hipGetLastError();
+}
+
 hipError_t launch_preprocess_bwd(const Plan &p, void *ws, int gstride, const float *intr, const float *viewmat,
                                  float *dL_dviewmat, hipStream_t st) {
     if (p.a7_blocks > 0) {
         hipLaunchKernelGGL(k_preprocess_bwd, dim3(p.a7_blocks), dim3(256), 0, st,
                            at<SubmapDesc>(ws, p.o_subs), p.S, at<int32_t>(ws, p.o_vlist),
-                           at<ViewDesc>(ws, p.o_views), intr, viewmat, at<Rec>(ws, p.o_rec),
+                           at<ViewDesc>(ws, p.o_views), intr, viewmat, at<uint32_t>(ws, p.o_emeta),
                            at<uint32_t>(ws, p.o_cnt), at<float4>(ws, p.o_grad), gstride,
                            at<float>(ws, p.o_pose), p.a7_max_blocks, (int)p.overwrite);
     }

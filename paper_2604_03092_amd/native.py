@@ -48,7 +48,7 @@ class FmRasterParams(ctypes.Structure):
     _fields_ = [("alpha_min", c_float), ("alpha_max", c_float), ("t_min", c_float), ("rho_max", c_float),
                 ("near_plane", c_float), ("bg", c_float * 3), ("tile_w", c_int32), ("tile_h", c_int32),
                 ("deterministic", c_int32), ("overwrite", c_int32),
-                ("tile_order", c_int32)]
+                ("tile_order", c_int32), ("tile_waves", c_int32), ("lds_depth", c_int32)]
 
 
 class FmOutputs(ctypes.Structure):

@@ -154,7 +154,8 @@ class Rasterizer:
             raise native.FmError(st, self.lib.fm_last_error(self.ctx).decode())
 
     def params(self, alpha_min=1.0 / 255.0, alpha_max=0.99, t_min=1e-4, rho_max=3.0, near=0.2,
-               bg=(0.0, 0.0, 0.0), tile=(16, 16), deterministic=False, overwrite=False, tile_order=0):
+               bg=(0.0, 0.0, 0.0), tile=(16, 16), deterministic=False, overwrite=False, tile_order=0,
+               tile_waves=0, lds_depth=0):
         p = FmRasterParams()
         self.lib.fm_default_params(ctypes.byref(p))
         p.alpha_min, p.alpha_max, p.t_min, p.rho_max, p.near_plane = alpha_min, alpha_max, t_min, rho_max, near
@@ -164,6 +165,8 @@ class Rasterizer:
         p.deterministic = 1 if deterministic else 0
         p.overwrite = 1 if overwrite else 0
         p.tile_order = int(tile_order)
+        p.tile_waves = int(tile_waves)
+        p.lds_depth = int(lds_depth)
         return p
 
     def workspace_size(self, gs, params, max_pairs):

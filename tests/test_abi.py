@@ -53,6 +53,7 @@ def test_host_only_calls(lib):
     assert p.tile_w == 16 and p.tile_h == 16 and abs(p.alpha_max - 0.99) < 1e-7
     assert abs(p.alpha_min - 1 / 255) < 1e-9 and abs(p.t_min - 1e-4) < 1e-10 and p.rho_max == 3.0
     assert p.deterministic == 0 and p.overwrite == 0 and p.tile_order == 0
+    assert p.tile_waves == 0 and p.lds_depth == 0
     assert lib.fm_version() >= 10000
     assert lib.fm_status_string(2) == b"pair capacity exceeded"
     # tile count is host arithmetic
@@ -77,6 +78,7 @@ int main(void) {
   S(fm_fusion_params) S(fm_surfel_buffer) O(fm_surfel_buffer, capacity) O(fm_sim3, t)
   O(fm_batch, views) O(fm_batch, intr) O(fm_batch, viewmat) O(fm_raster_params, bg)
   O(fm_raster_params, tile_w) O(fm_raster_params, deterministic) O(fm_raster_params, tile_order)
+  O(fm_raster_params, tile_waves) O(fm_raster_params, lds_depth)
   O(fm_l1_loss, w_rgb) O(fm_surfels, color) O(fm_adam_tensor, n)
   O(fm_adam_tensor, lr) O(fm_adam_tensor, kind) S(fm_prune_spec) O(fm_prune_spec, tau_rgb)
   O(fm_prune_spec, tau_depth)
@@ -108,6 +110,8 @@ def test_ctypes_layout_matches_header():
     assert int(vals["fm_raster_params.tile_w"]) == native.FmRasterParams.tile_w.offset
     assert int(vals["fm_raster_params.deterministic"]) == native.FmRasterParams.deterministic.offset
     assert int(vals["fm_raster_params.tile_order"]) == native.FmRasterParams.tile_order.offset
+    assert int(vals["fm_raster_params.tile_waves"]) == native.FmRasterParams.tile_waves.offset
+    assert int(vals["fm_raster_params.lds_depth"]) == native.FmRasterParams.lds_depth.offset
     assert int(vals["fm_l1_loss.w_rgb"]) == native.FmL1Loss.w_rgb.offset
     assert int(vals["fm_surfels.color"]) == native.FmSurfels.color.offset
     assert int(vals["fm_surfel_buffer.capacity"]) == native.FmSurfelBuffer.capacity.offset

@@ -165,27 +165,3 @@ def test_fusion_batch_errors(rast):
     poses[1] = native.FmSim3(-1.0, (ctypes.c_float * 4)(*f.q), (ctypes.c_float * 3)(*f.t))
     assert call(rast.ctx, maps, poses, 2, ctypes.byref(fp), None, buf, _ptr(offs), _ptr(ws), need,
                 None) == native.FM_ERR_INVALID_ARG
-
-
-def test_prune_scores_match_oracle(rast):
-    """Per-surfel weight on high-error pixels from one backward with the
-    upstream (mask, 0, 0), against the oracle's adjoint with the same upstream."""
-    import oracle
-    from paper_2604_03092_amd.raster import GpuScene, error_mask, prune_scores
-    from tests.gpu_util import assert_grad_close
-    sc = scenes.config0()
-    gs = GpuScene.from_scene(sc)
-    out, ws = rast.forward(gs)
-    mask = error_mask(gs, out, 0.3)
-    torch.cuda.synchronize()
-    ref_out = oracle.render_scene(sc)
-    # pixels the oracle flags (a threshold decision within its margin) are left out on both sides
-    m = mask.cpu().numpy().astype(np.float64) * (1.0 - ref_out["flags"])
-    z = np.zeros_like(m)
-    g = dict(rgb=np.stack([m, z, z]), depth=z, normal=np.stack([z, z, z]), alpha=z)
-    mask_dev = torch.from_numpy(m.astype(np.float32)).cuda()
-    scores = prune_scores(rast, gs, ws, out, mask_dev)
-    torch.cuda.synchronize()
-    ref, _ = oracle.backward_scene(sc, g)
-    assert_grad_close(scores[0].cpu().numpy(), ref[0]["color"][0], "prune score")
-    assert float(scores[0].sum()) > 0

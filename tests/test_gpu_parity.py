@@ -61,10 +61,11 @@ def test_tile_shape_does_not_change_images(rast):
     sc = scenes.random_scene(5, 20000, 200, 136, scale_lo=0.02, scale_hi=0.15)
     gs = GpuScene.from_scene(sc)
     ref = None
-    for tile, order in [((16, 16), 1), ((16, 16), 2), ((8, 8), 1), ((16, 8), 2), ((32, 8), 1), ((32, 32), 1),
-                        ((32, 32), 2)]:
-        _say(f"tile invariance {tile} order {order}")
-        out, _ = rast.forward(gs, rast.params(tile=tile, tile_order=order))
+    for tile, order, waves in [((16, 16), 1, 1), ((16, 16), 2, 1), ((8, 8), 1, 1), ((16, 8), 2, 1),
+                               ((32, 8), 1, 1), ((32, 32), 1, 1), ((32, 32), 2, 1), ((16, 16), 1, 2),
+                               ((16, 8), 2, 2), ((32, 8), 1, 2)]:
+        _say(f"tile invariance {tile} order {order} waves {waves}")
+        out, _ = rast.forward(gs, rast.params(tile=tile, tile_order=order, tile_waves=waves))
         got = {k: v.cpu().numpy() for k, v in out.items()}
         if ref is None:
             ref = got
@@ -120,6 +121,58 @@ def test_fused_l1_config0(rast, tile):
     for k in ("mean", "quat", "scale", "opacity", "color"):
         assert_grad_close(to_np(grads[0][k]), rg[0][k], f"fused.{k}")
     assert_grad_close(to_np(dvm), rdvm, "fused.viewmat")
+
+
+@pytest.mark.parametrize("tile,waves,depth,det", [((16, 16), 2, 32, False), ((32, 8), 2, 128, False),
+                                                  ((16, 8), 2, 64, True), ((16, 16), 1, 128, False),
+                                                  ((32, 32), 1, 32, False)])
+def test_work_split_and_lds_depth_match_oracle(rast, tile, waves, depth, det):
+    """The fused call with one wave per 8x8 block and other LDS batch depths
+    against the oracle (three views over two submaps, depth loss)."""
+    sc = scenes.random_scene(43, 6000, 96, 72, n_views=3, scale_lo=0.03, scale_hi=0.2)
+    _say(f"work split tile={tile} waves={waves} depth={depth} det={det}")
+    gs = GpuScene.from_scene(sc)
+    ref = _oracle_forward(sc)
+    near = np.any(np.abs(ref["rgb"] - sc.target_rgb) < 5e-4, axis=0) | (np.abs(ref["depth"] - sc.target_depth) < 5e-4)
+    keep = ~(ref["flags"] | near)
+    mask = torch.from_numpy(keep.astype(np.uint8)).cuda()
+    p = rast.params(tile=tile, tile_waves=waves, lds_depth=depth, deterministic=det)
+    _, ws = rast.forward(gs, p)
+    ws = rast.workspace(gs, p, max_pairs=ws.n_pairs + 4096)
+    out = rast.new_outputs(gs)
+    grads, dvm = gs.zero_grads()
+    loss = torch.zeros(1, device="cuda")
+    rast.fwd_bwd_l1(gs, ws, out, grads, dvm, loss, mask=mask)
+    torch.cuda.synchronize()
+    assert rast.query(gs, ws)[0] == 0
+    L, g = oracle.l1_loss(sc, ref, mask=keep)
+    assert abs(float(loss) - L) <= 1e-5 * max(1.0, abs(L))
+    assert_images_close(out, ref, ~ref["flags"], what="split")
+    rg, rdvm = oracle.backward_scene(sc, g)
+    for k in ("mean", "quat", "scale", "opacity", "color"):
+        assert_grad_close(to_np(grads[0][k]), rg[0][k], f"split.{k}")
+    assert_grad_close(to_np(dvm), rdvm, "split.viewmat")
+    # the backward through fm_backward with the same split
+    gu = random_upstream(np.random.default_rng(44), gs.npx, ~ref["flags"])
+    gt = {k: torch.from_numpy(v.astype(np.float32)).cuda() for k, v in gu.items()}
+    out2, ws2 = rast.forward(gs, rast.params(tile=tile, tile_waves=waves, deterministic=det))
+    grads2, dvm2 = gs.zero_grads()
+    rast.backward(gs, ws2, out2, gt, grads2, dvm2)
+    torch.cuda.synchronize()
+    rg2, rdvm2 = oracle.backward_scene(sc, gu)
+    for k in ("mean", "quat", "scale", "opacity", "color"):
+        assert_grad_close(to_np(grads2[0][k]), rg2[0][k], f"split bwd.{k}")
+    assert_grad_close(to_np(dvm2), rdvm2, "split bwd.viewmat")
+
+
+def test_invalid_work_split(rast):
+    sc = scenes.config0()
+    gs = GpuScene.from_scene(sc)
+    from paper_2604_03092_amd import native
+    for kw in (dict(tile_waves=3), dict(lds_depth=48), dict(deterministic=True, lds_depth=32)):
+        with pytest.raises(native.FmError) as e:
+            rast.forward(gs, rast.params(**kw))
+        assert e.value.status == native.FM_ERR_INVALID_ARG, kw
 
 
 # ------------------------------------------------------- deterministic mode

@@ -1,0 +1,196 @@
+"""GPU parity of map-fusion pruning (Sec. 3.3, "Map Fusion") against the
+oracle (oracle/prune.py): the error flags of fm_prune_scores, the
+per-surfel scores (sum of alpha T over the flagged pixels) and the removal
+of fm_prune_compact.
+
+The flags depend on the rendered image, which the GPU computes in float32:
+they are compared with the oracle's flags from its FP64 image except at
+pixels the oracle flags for a threshold decision (R18 margin) and pixels
+whose error lies within 2e-4 of a cut (the images agree to 1e-4).  The
+scores are compared with the oracle given the same flags (the oracle's,
+passed to the GPU as its mask), at the gradient tolerances.  The removal
+takes the oracle's scores rounded to float32 and must keep exactly the
+surfels prune_keep keeps, bit for bit and in order."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import prune as oprune
+from paper_2604_03092_amd import native, scenes
+from paper_2604_03092_amd.raster import GpuScene, Rasterizer, prune_compact, prune_scores
+from tests.gpu_util import assert_grad_close, to_np
+
+pytestmark = pytest.mark.gpu
+
+PLANES = ("mean", "quat", "scale", "opacity", "color")
+CH = {"mean": 3, "quat": 4, "scale": 2, "opacity": 1, "color": 3}
+
+
+@pytest.fixture(scope="module")
+def rast():
+    return Rasterizer()
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _two_submap_scene():
+    """Three 80x60 views over two submaps of config-0 laws (views 0 and 2
+    see submap 0, view 1 submap 1), with depth targets."""
+    a = scenes.random_scene(81, 3000, 80, 60, n_views=2, scale_lo=0.03, scale_hi=0.15)
+    b = scenes.random_scene(82, 2000, 80, 60, n_views=1, scale_lo=0.03, scale_hi=0.15)
+    views = [(80, 60, 0), (80, 60, 1), (80, 60, 0)]
+    intr = np.concatenate([a.intr[:1], b.intr[:1], a.intr[1:2]])
+    vm = np.concatenate([a.viewmat[:1], b.viewmat[:1], a.viewmat[1:2]])
+    sc = scenes.Scene("prune_two_submaps", [a.submaps[0], b.submaps[0]], views, intr, vm, w_rgb=1.0,
+                      w_depth=0.1)
+    rng = np.random.default_rng(83)
+    sc.target_rgb = rng.random((3, sc.total_pixels)).astype(np.float32)
+    sc.target_depth = rng.uniform(1.0, 8.0, sc.total_pixels).astype(np.float32)
+    return sc
+
+
+def _scene(name):
+    return scenes.config0() if name == "config0" else _two_submap_scene()
+
+
+@pytest.mark.parametrize("name,tau_depth", [("config0", None), ("two_submaps", 2.0)])
+def test_error_flags_match_oracle(rast, name, tau_depth):
+    sc = _scene(name)
+    gs = GpuScene.from_scene(sc)
+    tau = 0.3
+    scores, flags, out, _ = prune_scores(rast, gs, tau_rgb=tau, tau_depth=tau_depth)
+    torch.cuda.synchronize()
+    ref = oracle.render_scene(sc)
+    want = oprune.error_mask(ref["rgb"], ref["depth"], sc.target_rgb,
+                             sc.target_depth if tau_depth is not None else None, tau, tau_depth)
+    e = np.mean(np.abs(ref["rgb"] - sc.target_rgb.astype(np.float64)), axis=0)
+    unsure = ref["flags"] | (np.abs(e - tau) <= 2e-4)
+    if tau_depth is not None:
+        unsure |= np.abs(np.abs(ref["depth"] - sc.target_depth) - tau_depth) <= 2e-4
+    got = flags.cpu().numpy().astype(bool)
+    assert unsure.mean() < 0.01
+    assert np.array_equal(got[~unsure], want[~unsure])
+    assert 0.05 < want.mean() < 0.95
+    # the outputs are the plain forward's
+    for k in ("rgb", "depth", "normal", "alpha"):
+        d = np.abs(to_np(out[k]) - ref[k])[..., ~ref["flags"]]
+        assert d.max() <= 1e-4, k
+
+
+@pytest.mark.parametrize("name,tile,det", [("config0", (16, 16), False), ("two_submaps", (16, 16), False),
+                                           ("two_submaps", (8, 8), True), ("two_submaps", (32, 32), False)])
+def test_scores_match_oracle(rast, name, tile, det):
+    """The oracle's flags (zeroed where it flags a threshold decision) go to
+    both sides; the GPU's scores must match the oracle's sum of alpha T."""
+    sc = _scene(name)
+    gs = GpuScene.from_scene(sc)
+    ref = oracle.render_scene(sc)
+    want = oprune.error_mask(ref["rgb"], ref["depth"], sc.target_rgb, None, 0.3) & ~ref["flags"]
+    mask = torch.from_numpy(want.astype(np.uint8)).cuda()
+    params = rast.params(tile=tile, deterministic=det)
+    scores, flags, _, _ = prune_scores(rast, gs, params, mask=mask)
+    torch.cuda.synchronize()
+    assert np.array_equal(flags.cpu().numpy().astype(bool), want)
+    ref_scores = oprune.contribution_scores(sc, want)
+    for s in range(len(sc.submaps)):
+        got = to_np(scores[s])
+        assert_grad_close(got, ref_scores[s], f"{name} score[{s}]")
+        assert got.max() > 0.0
+    _say(f"scores {name} {tile} det={det}: {[int((to_np(x) > 0).sum()) for x in scores]} surfels scored")
+
+
+def _compact_case(rast, sm, score32, tau):
+    dev = {k: torch.from_numpy(np.ascontiguousarray(sm[k])).cuda() for k in PLANES}
+    got = prune_compact(rast, dev, torch.from_numpy(score32).cuda(), tau)
+    want = oprune.prune_surfels(sm, score32, tau)
+    for k in PLANES:
+        assert np.array_equal(got[k].cpu().numpy().reshape(-1), want[k].reshape(-1)), k
+    return got["opacity"].shape[-1]
+
+
+def test_compaction_matches_oracle(rast):
+    sc = _two_submap_scene()
+    ref = oracle.render_scene(sc)
+    want = oprune.error_mask(ref["rgb"], ref["depth"], sc.target_rgb, None, 0.3)
+    ref_scores = oprune.contribution_scores(sc, want)
+    for s, sm in enumerate(sc.submaps):
+        score32 = ref_scores[s].astype(np.float32)
+        n = score32.size
+        for tau in (0.0, float(np.median(score32[score32 > 0])), 1e30, -1.0):
+            kept = _compact_case(rast, sm, score32, tau)
+            _say(f"compact submap {s} tau={tau:.3g}: kept {kept} of {n}")
+            if tau == 1e30:
+                assert kept == n
+            if tau == -1.0:
+                assert kept == 0
+    # a NaN score keeps its surfel; the count covers surfels beyond the capacity
+    sm = sc.submaps[1]
+    score32 = ref_scores[1].astype(np.float32)
+    score32[:7] = np.nan
+    _compact_case(rast, sm, score32, 0.0)
+    dev = {k: torch.from_numpy(np.ascontiguousarray(sm[k])).cuda() for k in PLANES}
+    n = score32.size
+    cap = 100
+    outp = {k: torch.full((CH[k], cap), -5.0, device="cuda") for k in PLANES}
+    count = torch.zeros(1, dtype=torch.int32, device="cuda")
+    wsb = torch.empty(int(rast.lib.fm_prune_compact_workspace_size(n)), dtype=torch.uint8, device="cuda")
+    import ctypes
+    src = native.FmSurfels(n, *(dev[k].data_ptr() for k in PLANES))
+    buf = native.FmSurfelBuffer(*(outp[k].data_ptr() for k in PLANES), cap)
+    sdev = torch.from_numpy(score32).cuda()
+    rast.check(rast.lib.fm_prune_compact(rast.ctx, ctypes.byref(src), ctypes.c_void_p(sdev.data_ptr()), 0.0, buf,
+                                         ctypes.c_void_p(count.data_ptr()), ctypes.c_void_p(wsb.data_ptr()),
+                                         wsb.numel(), None))
+    torch.cuda.synchronize()
+    keep = oprune.prune_keep(score32, 0.0)
+    assert int(count.item()) == keep.size > cap
+    for k in PLANES:
+        assert np.array_equal(outp[k].cpu().numpy().reshape(-1), sm[k][..., keep[:cap]].reshape(-1)), k
+
+
+def test_compaction_empty_and_errors(rast):
+    import ctypes
+    count = torch.full((1,), 9, dtype=torch.int32, device="cuda")
+    wsb = torch.empty(16, dtype=torch.uint8, device="cuda")
+    src = native.FmSurfels(0, None, None, None, None, None)
+    buf = native.FmSurfelBuffer(None, None, None, None, None, 0)
+    rast.check(rast.lib.fm_prune_compact(rast.ctx, ctypes.byref(src), None, 0.0, buf,
+                                         ctypes.c_void_p(count.data_ptr()), ctypes.c_void_p(wsb.data_ptr()),
+                                         wsb.numel(), None))
+    torch.cuda.synchronize()
+    assert int(count.item()) == 0
+    # NaN cut, NULL count, workspace too small
+    src = native.FmSurfels(5000, *([ctypes.c_void_p(wsb.data_ptr())] * 5))
+    st = rast.lib.fm_prune_compact(rast.ctx, ctypes.byref(src), ctypes.c_void_p(wsb.data_ptr()), float("nan"), buf,
+                                   ctypes.c_void_p(count.data_ptr()), ctypes.c_void_p(wsb.data_ptr()), 1 << 20, None)
+    assert st == native.FM_ERR_INVALID_ARG
+    st = rast.lib.fm_prune_compact(rast.ctx, ctypes.byref(src), ctypes.c_void_p(wsb.data_ptr()), 0.0, buf, None,
+                                   ctypes.c_void_p(wsb.data_ptr()), 1 << 20, None)
+    assert st == native.FM_ERR_INVALID_ARG
+    st = rast.lib.fm_prune_compact(rast.ctx, ctypes.byref(src), ctypes.c_void_p(wsb.data_ptr()), 0.0, buf,
+                                   ctypes.c_void_p(count.data_ptr()), ctypes.c_void_p(wsb.data_ptr()), 4, None)
+    assert st == native.FM_ERR_WORKSPACE
+
+
+def test_prune_scores_argument_errors(rast):
+    import ctypes
+    sc = scenes.config0()
+    gs = GpuScene.from_scene(sc)
+    p = rast.params()
+    ws = rast.workspace(gs, p)
+    out = rast.new_outputs(gs)
+    spec = native.FmPruneSpec(None, None, None, None, 0.3, 0.0)   # no target and no mask
+    arr = (ctypes.c_void_p * 1)(ctypes.c_void_p(out["alpha"].data_ptr()))
+    st = rast.lib.fm_prune_scores(rast.ctx, ctypes.byref(gs.batch()), ctypes.byref(p), ctypes.byref(spec),
+                                  native.FmOutputs(*(out[k].data_ptr() for k in ("rgb", "depth", "normal", "alpha"))),
+                                  arr, ctypes.c_void_p(ws.buf.data_ptr()), ws.nbytes, ws.max_pairs, None)
+    assert st == native.FM_ERR_INVALID_ARG
+    spec = native.FmPruneSpec(gs.target_rgb.data_ptr(), None, None, None, 0.3, 0.0)
+    arr = (ctypes.c_void_p * 1)(None)   # a rendered submap without a score array
+    st = rast.lib.fm_prune_scores(rast.ctx, ctypes.byref(gs.batch()), ctypes.byref(p), ctypes.byref(spec),
+                                  native.FmOutputs(*(out[k].data_ptr() for k in ("rgb", "depth", "normal", "alpha"))),
+                                  arr, ctypes.c_void_p(ws.buf.data_ptr()), ws.nbytes, ws.max_pairs, None)
+    assert st == native.FM_ERR_INVALID_ARG

@@ -149,12 +149,16 @@ def test_autotune_and_cache(rast, tmp_path):
     chosen = rast.autotune(gs, ws, out, grads, dvm, loss, cache_path=path)
     assert (chosen.tile_w, chosen.tile_h) in [(16, 16), (8, 8), (16, 8), (32, 8), (32, 32)]
     assert chosen.tile_order in (1, 2)
+    assert chosen.tile_waves in (1, 2) and chosen.lds_depth in (32, 64, 128)
     data = json.load(open(path))
-    assert list(data.values())[0] == [chosen.tile_w, chosen.tile_h, chosen.tile_order]
+    key, val = list(data.items())[0]
+    assert key.startswith("gfx950")   # the cache is keyed by the device's architecture
+    assert val == [chosen.tile_w, chosen.tile_h, chosen.tile_order, chosen.tile_waves, chosen.lds_depth]
     # a fresh context reads the cache; tile 0x0 then means "the tuned shape"
     r2 = Rasterizer()
     chosen2 = r2.autotune(gs, ws, out, grads, dvm, loss, cache_path=path)
-    assert (chosen2.tile_w, chosen2.tile_h, chosen2.tile_order) == (chosen.tile_w, chosen.tile_h, chosen.tile_order)
+    assert (chosen2.tile_w, chosen2.tile_h, chosen2.tile_order, chosen2.tile_waves, chosen2.lds_depth) == (
+        chosen.tile_w, chosen.tile_h, chosen.tile_order, chosen.tile_waves, chosen.lds_depth)
     auto = r2.params(tile=(0, 0))
     o2, _ = r2.forward(gs, auto)
     ref, _ = r2.forward(gs, r2.params(tile=(chosen.tile_w, chosen.tile_h)))
