@@ -351,26 +351,32 @@ def time_config(rast, name, steps):
     grads, dvm = gs.zero_grads()
     loss = torch.zeros(1, device="cuda")
     chosen = rast.autotune(gs, ws8, out, grads, dvm, loss)
-    tuned = (int(chosen.tile_w), int(chosen.tile_h), int(chosen.tile_order))
+    tuned = (int(chosen.tile_w), int(chosen.tile_h), int(chosen.tile_order), int(chosen.tile_waves),
+             int(chosen.lds_depth))
     del ws8
     res = dict(views=gs.n_views, pixels=gs.npx)
-    for tile in [(16, 16, 1)] + ([tuned] if tuned != (16, 16, 1) else []):
-        r = _time_config_tile(rast, gs, tile[:2], tile[2], steps, out, grads, dvm, loss)
-        key = "tile_16x16" if tile == (16, 16, 1) else "tuned"
-        res[key] = dict(tile=f"{tile[0]}x{tile[1]}", **r)
+    default = (16, 16, 1, 1, 64)
+    for launch in [default] + ([tuned] if tuned != default else []):
+        r = _time_config_tile(rast, gs, launch, steps, out, grads, dvm, loss)
+        key = "tile_16x16" if launch == default else "tuned"
+        res[key] = dict(tile=f"{launch[0]}x{launch[1]}", **r)
     res["autotuned_tile"] = f"{tuned[0]}x{tuned[1]}"
     res["autotuned_order"] = "longest list first" if chosen.tile_order == 1 else "image order"
+    res["autotuned_waves_per_tile"] = "one per 8x8 block" if chosen.tile_waves == 2 else "one per tile"
+    res["autotuned_lds_depth"] = int(chosen.lds_depth)
     del out, grads, dvm
     torch.cuda.empty_cache()
     return res
 
 
-def _time_config_tile(rast, gs, tile, order, steps, out, grads, dvm, loss):
+def _time_config_tile(rast, gs, launch, steps, out, grads, dvm, loss):
     """One hipGraph replay of the fused step per timed step (gradients,
     pose gradients and loss stored), timed with events; the rooflines use the
-    step's median time."""
+    step's median time.  launch: (tile w, tile h, tile order, waves per
+    tile, LDS batch depth)."""
     import torch
-    params = rast.params(tile=tile, overwrite=True, tile_order=order)
+    tw, th, order, waves, depth = launch
+    params = rast.params(tile=(tw, th), overwrite=True, tile_order=order, tile_waves=waves, lds_depth=depth)
     _, ws = rast.forward(gs, params)
     torch.cuda.synchronize()
     _, n_pairs, _ = rast.query(gs, ws)
@@ -437,6 +443,10 @@ def main():
     ap.add_argument("--tile", default="16x16")
     ap.add_argument("--tile-order", type=int, default=1, choices=(1, 2),
                     help="blend tile order: 1 longest list first, 2 image order")
+    ap.add_argument("--tile-waves", type=int, default=1, choices=(1, 2),
+                    help="blend waves per tile: 1 one per tile, 2 one per 8x8 block")
+    ap.add_argument("--lds-depth", type=int, default=64, choices=(32, 64, 128),
+                    help="records the fused blend stages in LDS per batch")
     ap.add_argument("--no-graph", action="store_true", help="time eager calls instead of a graph replay")
     ap.add_argument("--deterministic", action="store_true",
                     help="bitwise reproducible gradients (per-pair partials summed in a fixed order)")
@@ -483,7 +493,7 @@ def main():
     # the step stores its gradients, pose gradients and loss (overwrite mode),
     # so no clearing kernels run between steps
     params = rast.params(tile=(tw, th), deterministic=args.deterministic, overwrite=True,
-                         tile_order=args.tile_order)
+                         tile_order=args.tile_order, tile_waves=args.tile_waves, lds_depth=args.lds_depth)
 
     # size the pair buffer from one eager forward (not timed)
     out, ws = rast.forward(gs, params)
@@ -665,6 +675,8 @@ def main():
                    "tile": f"{tw}x{th}", "mode": "hipgraph" if graph is not None else "eager",
                    "deterministic": bool(args.deterministic),
                    "tile_order": "longest list first" if args.tile_order == 1 else "image order",
+                   "waves_per_tile": "one per 8x8 block" if args.tile_waves == 2 else "one per tile",
+                   "lds_depth": args.lds_depth,
                    "pairs": n_pairs},
         "views_per_s": round(views_s, 3),
         "plain": plain,

@@ -17,6 +17,8 @@
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "fm_internal.h"
 
 using fm::Plan;
@@ -249,14 +251,13 @@ fm_status build(fm_ctx *ctx, const fm_batch *b, const fm_raster_params *prm, int
     auto grid_for = [](int64_t n) { return (int)std::max<int64_t>(1, (n + fm::kSortTile - 1) / fm::kSortTile); };
     p.sortG_e = grid_for(E);
     p.sortG_p = grid_for(max_pairs);
-    p.sortG_t = grid_for(T);
     p.scan_blocks = (int)std::max<int64_t>(1, (E + fm::kScanChunk - 1) / fm::kScanChunk);
     p.emit_blocks = std::min(p.sortG_p, fm::kMaxEmitGrid);  // a block emits one sort tile at a time
 
     // submaps in index order, each with the list of its views
     out.subs.resize(p.S);
     out.vlist.clear();
-    int blocks = 0, max_blocks = 1;
+    int blocks = 0, max_blocks = 1, proj_blocks = 0;
     for (int sidx = 0; sidx < p.S; ++sidx) {
         const fm_surfels &sm = b->submaps[sidx];
         SubmapDesc &d = out.subs[sidx];
@@ -274,9 +275,12 @@ fm_status build(fm_ctx *ctx, const fm_batch *b, const fm_raster_params *prm, int
         d.block_base = blocks;
         const int nb = d.view_count > 0 ? (sm.n + 255) / 256 : 0;
         blocks += nb;
+        d.proj_block_base = proj_blocks;
+        proj_blocks += nb * ((d.view_count + fm::kProjViewsPerThread - 1) / fm::kProjViewsPerThread);
         max_blocks = std::max(max_blocks, (sm.n + 255) / 256);
     }
     p.a7_blocks = blocks;
+    p.proj_blocks = proj_blocks;
     p.a7_max_blocks = max_blocks;
 
     size_t o = 0;
@@ -300,12 +304,11 @@ fm_status build(fm_ctx *ctx, const fm_batch *b, const fm_raster_params *prm, int
     p.o_pval = take(4 * (size_t)max_pairs);
     p.o_pkey2 = take(4 * (size_t)max_pairs);
     p.o_pval2 = take(4 * (size_t)max_pairs);
-    p.o_hist = take(4 * (size_t)fm::kRadix * std::max({p.sortG_e, p.sortG_p, p.sortG_t}));
+    p.o_hist = take(4 * (size_t)fm::kRadix * std::max(p.sortG_e, p.sortG_p));
     p.o_tstart = take(4 * (size_t)T);
     p.o_tend = take(4 * (size_t)T);
-    p.o_tkey = take(4 * (size_t)T);  // blend order: cost keys, sorted keys, tile ids
-    p.o_tkey2 = take(4 * (size_t)T);
-    p.o_torder = take(4 * (size_t)T);
+    p.o_torder = take(4 * (size_t)T);  // blend order: tile ids, longest list first
+    p.o_tbucket = take(4 * 2 * (size_t)fm::kRadix);  // its cost-bucket counts and cursors
     p.o_tfinal = take(4 * (size_t)NPX);
     p.o_nlast = take(4 * (size_t)NPX);
     p.o_ncount = take(4 * (size_t)NPX);
@@ -385,15 +388,37 @@ void mark(fm_ctx *ctx, hipStream_t st, int phase) {
         if (_e != hipSuccess) return hip_fail(ctx, _e, where); \
     } while (0)
 
+// roctx ranges over a call and its phases (host-side spans of the enqueueing,
+// shown by rocprofv3 --marker-trace next to the kernels they launch).
+struct Ranges {
+    int depth = 0;
+    explicit Ranges(const char *call) {
+        roctxRangePushA(call);
+        depth = 1;
+    }
+    void phase(const char *name) {
+        if (depth == 2) roctxRangePop();
+        roctxRangePushA(name);
+        depth = 2;
+    }
+    ~Ranges() {
+        while (depth-- > 0) roctxRangePop();
+    }
+};
+
 fm_status run_forward(fm_ctx *ctx, Built &bt, const fm_raster_params *prm, const fm_batch *b, void *ws,
                       const fm_outputs &out, hipStream_t st) {
     const fm::KParams kp = kparams(prm, bt.plan);
+    Ranges rg("fm2dgs/forward");
     mark_begin(ctx, st);
+    rg.phase("fm2dgs/projection");
     FM_TRY_HIP(fm::launch_setup(bt.plan, ws, bt.views.data(), bt.subs.data(), bt.vlist.data(), st), "setup");
     FM_TRY_HIP(fm::launch_preprocess(bt.plan, ws, kp, b->intr, b->viewmat, false, st), "preprocess");
     mark(ctx, st, PH_PRE);
+    rg.phase("fm2dgs/binning");
     FM_TRY_HIP(fm::launch_binning(bt.plan, ws, kp, st), "binning");
     mark(ctx, st, PH_BIN);
+    rg.phase("fm2dgs/blend");
     FM_TRY_HIP(fm::launch_render_fwd(bt.plan, ws, kp, out, st), "render_fwd");
     mark(ctx, st, PH_BLEND);
     return FM_OK;
@@ -409,20 +434,26 @@ fm_status run_fused(fm_ctx *ctx, Built &bt, const fm_raster_params *prm, const f
     la.mask = ls->mask;
     la.w_rgb = ls->w_rgb;
     la.w_depth = ls->w_depth;
+    Ranges rg("fm2dgs/fwd_bwd_l1");
     mark_begin(ctx, st);
+    rg.phase("fm2dgs/projection");
     FM_TRY_HIP(fm::launch_setup(bt.plan, ws, bt.views.data(), bt.subs.data(), bt.vlist.data(), st), "setup");
     // the slots are cleared for the blend's atomics; deterministic sums store
     // every slot the backward projection reads (those of visible entries)
     FM_TRY_HIP(fm::launch_preprocess(bt.plan, ws, kp, b->intr, b->viewmat, !bt.plan.det, st), "preprocess");
     mark(ctx, st, PH_PRE);
+    rg.phase("fm2dgs/binning");
     FM_TRY_HIP(fm::launch_binning(bt.plan, ws, kp, st), "binning");
     if (bt.plan.det) FM_TRY_HIP(fm::launch_det_clear(bt.plan, ws, kp.gstride, st), "det_clear");
     mark(ctx, st, PH_BIN);
+    rg.phase("fm2dgs/blend");
     FM_TRY_HIP(fm::launch_render_fused(bt.plan, ws, kp, la, out, st), "render_fused");
     if (bt.plan.det) FM_TRY_HIP(fm::launch_det_reduce(bt.plan, ws, kp.gstride, st), "det_reduce");
     mark(ctx, st, PH_BLEND);
+    rg.phase("fm2dgs/loss_reduce");
     FM_TRY_HIP(fm::launch_loss_reduce(bt.plan, ws, loss, st), "loss_reduce");
     mark(ctx, st, PH_LOSS);
+    rg.phase("fm2dgs/backward_projection");
     FM_TRY_HIP(fm::launch_preprocess_bwd(bt.plan, ws, kp.gstride, b->intr, b->viewmat, dL_dviewmat, st),
                "preprocess_bwd");
     mark(ctx, st, PH_BWDPROJ);
@@ -661,14 +692,18 @@ fm_status fm_backward(fm_ctx *ctx, const fm_batch *b, const fm_raster_params *pr
     hipStream_t st = (hipStream_t)stream;
     fm::KParams kp = kparams(prm, bt.plan);
     if (g.normal) kp.gstride = fm::kGradStride;  // room for the normal's gradient
+    Ranges rg("fm2dgs/backward");
     mark_begin(ctx, st);
+    rg.phase("fm2dgs/zero_grad");
     FM_TRY_HIP(fm::launch_setup(bt.plan, ws, bt.views.data(), bt.subs.data(), bt.vlist.data(), st), "setup");
     if (bt.plan.det) FM_TRY_HIP(fm::launch_det_clear(bt.plan, ws, kp.gstride, st), "det_clear");
     else FM_TRY_HIP(fm::launch_zero_grad(bt.plan, ws, kp.gstride, st), "zero_grad");
     mark(ctx, st, PH_ZERO);
+    rg.phase("fm2dgs/blend");
     FM_TRY_HIP(fm::launch_render_bwd(bt.plan, ws, kp, out, g, st), "render_bwd");
     if (bt.plan.det) FM_TRY_HIP(fm::launch_det_reduce(bt.plan, ws, kp.gstride, st), "det_reduce");
     mark(ctx, st, PH_BLEND);
+    rg.phase("fm2dgs/backward_projection");
     FM_TRY_HIP(fm::launch_preprocess_bwd(bt.plan, ws, kp.gstride, b->intr, b->viewmat, dL_dviewmat, st),
                "preprocess_bwd");
     mark(ctx, st, PH_BWDPROJ);
@@ -754,15 +789,20 @@ fm_status fm_prune_scores(fm_ctx *ctx, const fm_batch *b, const fm_raster_params
     pa.mask_out = spec->mask_out;
     pa.tau_rgb = spec->tau_rgb;
     pa.tau_depth = spec->tau_depth;
+    Ranges rg("fm2dgs/prune_scores");
     mark_begin(ctx, st);
+    rg.phase("fm2dgs/projection");
     FM_TRY_HIP(fm::launch_setup(bt.plan, ws, bt.views.data(), bt.subs.data(), bt.vlist.data(), st), "setup");
     // the projection clears the slots whose first float collects each entry's score
     FM_TRY_HIP(fm::launch_preprocess(bt.plan, ws, kp, b->intr, b->viewmat, true, st), "preprocess");
     mark(ctx, st, PH_PRE);
+    rg.phase("fm2dgs/binning");
     FM_TRY_HIP(fm::launch_binning(bt.plan, ws, kp, st), "binning");
     mark(ctx, st, PH_BIN);
+    rg.phase("fm2dgs/blend");
     FM_TRY_HIP(fm::launch_render_prune(bt.plan, ws, kp, pa, out, st), "render_prune");
     mark(ctx, st, PH_BLEND);
+    rg.phase("fm2dgs/score_reduce");
     FM_TRY_HIP(fm::launch_score_reduce(bt.plan, ws, kp.gstride, st), "score_reduce");
     mark(ctx, st, PH_BWDPROJ);
     return FM_OK;

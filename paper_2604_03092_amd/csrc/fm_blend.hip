@@ -132,7 +132,8 @@ struct TileCtx {
     int64_t pix_base;      // first pixel of the view in the output planes
     uint32_t start, end;   // the tile's range in the sorted pair list
     uint32_t n_entries;
-    int quad;  // the wave's quadrant of a 32x32 tile (0 otherwise)
+    int tile;  // batch-global tile id
+    int quad;  // the wave's block or quadrant of a tile with several waves (0 otherwise)
 };
 
 template <class G> struct Slots {
@@ -153,6 +154,7 @@ __device__ __forceinline__ TileCtx tile_ctx(const ViewDesc *views, int V, const 
     const int rank = lb / Gm::NQ;
     c.quad = lb - rank * Gm::NQ;
     const int tile = order ? (int)order[rank] : rank;  // longest list first, or image order
+    c.tile = tile;
     c.view = view_of_tile(views, V, tile);
     const ViewDesc &vd = views[c.view];
     const int local = tile - vd.tile_base;
@@ -632,7 +634,8 @@ __global__ __launch_bounds__(64) void k_render_fused(const ViewDesc *__restrict_
         S[q] = g[q][0] * o0 + g[q][1] * o1 + g[q][2] * o2 + g[q][3] * acc[q][3];
     }
     const float lsum = wave_sum(l);
-    if (threadIdx.x == 0) loss_part[blockIdx.x] = lsum;
+    // partials by (tile, wave), so the reduction's order does not depend on the schedule
+    if (threadIdx.x == 0) loss_part[(int64_t)c.tile * G::NQ + c.quad] = lsum;
     tile_backward<G, false, DET>(c, sl, pval, rec, kp, srec, sval, pm, sj, g, S, Tf, slast, grad);
 }
 

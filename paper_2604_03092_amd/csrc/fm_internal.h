@@ -29,7 +29,7 @@ constexpr int kScanChunk = 2048;   // entries per block of the count scan
 constexpr int kSortTile = 4096;     // items per block of a radix pass
 constexpr int kEmitChunk = 2048;   // pairs per chunk of the emission blocks (two per sort tile)
 constexpr int kMaxEmitGrid = 4096;
-constexpr int kMaxPasses = 9;      // radix passes per binning (4 depth + up to 4 tile + 1 blend order)
+constexpr int kMaxPasses = 8;      // radix passes per binning (4 depth + up to 4 tile)
 
 // Per-view descriptor, written into the workspace at the start of each call.
 struct ViewDesc {
@@ -51,6 +51,7 @@ struct SubmapDesc {
     int32_t n;
     int32_t view_begin, view_count;  // slice of the submap-ordered view list
     int32_t block_base;              // first block of the backward projection
+    int32_t proj_block_base;         // first block of the projection
 };
 
 // Projected surfel as the blend kernels consume it (80 bytes).
@@ -147,16 +148,17 @@ struct Plan {
     int tile_w = 16, tile_h = 16;
     int tile_bits = 1;
     int pair_passes = 1;
-    int sortG_e = 1, sortG_p = 1, sortG_t = 1;
+    int sortG_e = 1, sortG_p = 1;
     int scan_blocks = 1;
     int emit_blocks = 1;
+    int proj_blocks = 0;    // total blocks of the projection (surfel blocks x view groups per submap)
     int a7_blocks = 0;      // total blocks of the backward projection
     int a7_max_blocks = 0;  // max blocks of one submap
     size_t o_views = 0, o_subs = 0, o_vlist = 0, o_status = 0, o_rec = 0, o_key = 0, o_cnt = 0,
            o_key2 = 0, o_val = 0, o_val2 = 0, o_scan = 0, o_pkey = 0, o_pval = 0, o_pkey2 = 0,
            o_pval2 = 0, o_hist = 0, o_tstart = 0, o_tend = 0, o_tfinal = 0, o_nlast = 0, o_ncount = 0, o_grad = 0,
-           o_pose = 0, o_loss = 0, o_tot = 0, o_ell = 0, o_chunk = 0, o_meta = 0, o_part = 0, o_tkey = 0,
-           o_tkey2 = 0, o_torder = 0, o_emeta = 0;
+           o_pose = 0, o_loss = 0, o_tot = 0, o_ell = 0, o_chunk = 0, o_meta = 0, o_part = 0,
+           o_torder = 0, o_emeta = 0, o_tbucket = 0;
     size_t bytes = 0;
     // deterministic gradients: the sorted lists hold emission indices, o_meta
     // maps them to pair values, and the adjoint writes one partial slot per
@@ -213,6 +215,8 @@ template <uint32_t C> __device__ __forceinline__ uint32_t xcd_chunked(uint32_t b
 // ---- launchers (host) ------------------------------------------------------
 hipError_t launch_setup(const Plan &p, void *ws, const ViewDesc *views, const SubmapDesc *subs,
                         const int32_t *vlist, hipStream_t st);
+// views one projection thread handles
+constexpr int kProjViewsPerThread = 4;
 hipError_t launch_preprocess(const Plan &p, void *ws, const KParams &kp, const float *intr,
                              const float *viewmat, bool zero_grad, hipStream_t st);
 hipError_t launch_binning(const Plan &p, void *ws, const KParams &kp, hipStream_t st);

@@ -75,41 +75,62 @@ __global__ void k_write_list(ListChunk c, int32_t *out) {
 // ---------------------------------------------------------------------------
 // forward projection
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_preprocess(const ViewDesc *__restrict__ views, int V,
+// Threads take one surfel and up to kProjViews views of its submap: the
+// per-surfel part (inputs, finiteness, the normalised quaternion's matrix in
+// FP64) is evaluated once for those views.  Block b of the grid belongs to
+// the submap whose proj_block_base is the last <= b; within it, blocks run
+// over the surfel blocks of 256 for each group of kProjViews views.
+constexpr int kProjViews = kProjViewsPerThread;
+
+__device__ inline int submap_of_proj_block(const SubmapDesc *s, int S, int b) {
+    int lo = 0, hi = S - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (s[mid].proj_block_base <= b) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(256) void k_preprocess(const SubmapDesc *__restrict__ subs, int S,
+                                                     const int32_t *__restrict__ vlist,
+                                                     const ViewDesc *__restrict__ views,
                                                      const float *__restrict__ intr,
                                                      const float *__restrict__ viewmat, KParams kp,
                                                      Rec *__restrict__ rec, uint32_t *__restrict__ key,
                                                      uint32_t *__restrict__ cnt, float4 *__restrict__ grad,
                                                      Ell *__restrict__ ell, uint32_t *__restrict__ emeta) {
 #pragma clang fp contract(off)
-    const int64_t e0 = (int64_t)blockIdx.x * 256;
-    const int v = view_of_entry(views, V, e0);
-    const ViewDesc &vd = views[v];
-    const int64_t e = e0 + threadIdx.x;
-    const int i = (int)(e - vd.entry_base);
-    const int n = vd.n;
-    uint32_t out_key = 0xFFFFFFFFu, out_cnt = 0;
+    const SubmapDesc &sd = subs[submap_of_proj_block(subs, S, blockIdx.x)];
+    const int n = sd.n;
+    const int nsb = (n + 255) >> 8;
+    const int lb = (int)blockIdx.x - sd.proj_block_base;
+    const int grp = lb / nsb;
+    const int i = (lb - grp * nsb) * 256 + (int)threadIdx.x;
+    // per surfel
+    float f_sig = 0.f, f_c0 = 0.f, f_c1 = 0.f, f_c2 = 0.f;
+    double mx = 0.0, my = 0.0, mz = 0.0, su = 0.0, sv = 0.0, sigma = 0.0;
+    double Rs[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    bool sok = false;
     if (i < n) {
-        const float f_mx = vd.mean[i], f_my = vd.mean[n + i], f_mz = vd.mean[2 * n + i];
-        const float f_qw = vd.quat[i], f_qx = vd.quat[n + i], f_qy = vd.quat[2 * n + i],
-                    f_qz = vd.quat[3 * n + i];
-        const float f_su = vd.scale[i], f_sv = vd.scale[n + i];
-        const float f_sig = vd.opacity[i];
-        const float f_c0 = vd.color[i], f_c1 = vd.color[n + i], f_c2 = vd.color[2 * n + i];
+        const float f_mx = sd.mean[i], f_my = sd.mean[n + i], f_mz = sd.mean[2 * n + i];
+        const float f_qw = sd.quat[i], f_qx = sd.quat[n + i], f_qy = sd.quat[2 * n + i],
+                    f_qz = sd.quat[3 * n + i];
+        const float f_su = sd.scale[i], f_sv = sd.scale[n + i];
+        f_sig = sd.opacity[i];
+        f_c0 = sd.color[i]; f_c1 = sd.color[n + i]; f_c2 = sd.color[2 * n + i];
         bool ok = isfinite(f_mx) && isfinite(f_my) && isfinite(f_mz) && isfinite(f_qw) &&
                   isfinite(f_qx) && isfinite(f_qy) && isfinite(f_qz) && isfinite(f_su) &&
                   isfinite(f_sv) && isfinite(f_sig) && isfinite(f_c0) && isfinite(f_c1) &&
                   isfinite(f_c2);
-        const double mx = f_mx, my = f_my, mz = f_mz;
+        mx = f_mx; my = f_my; mz = f_mz;
         const double qw = f_qw, qx = f_qx, qy = f_qy, qz = f_qz;
-        const double su = f_su, sv = f_sv, sigma = f_sig;
+        su = f_su; sv = f_sv; sigma = f_sig;
         ok = ok && (su > 0.0) && (sv > 0.0);
         const double qn = qw * qw + qx * qx + qy * qy + qz * qz;
         ok = ok && (qn > 0.0);
         if (ok) {
             const double qnorm = sqrt(qn);
             const double w = qw / qnorm, x = qx / qnorm, y = qy / qnorm, z = qz / qnorm;
-            double Rs[9];
             Rs[0] = 1.0 - 2.0 * (y * y + z * z);
             Rs[1] = 2.0 * (x * y - w * z);
             Rs[2] = 2.0 * (x * z + w * y);
@@ -119,6 +140,18 @@ __global__ __launch_bounds__(256) void k_preprocess(const ViewDesc *__restrict__
             Rs[6] = 2.0 * (x * z - w * y);
             Rs[7] = 2.0 * (y * z + w * x);
             Rs[8] = 1.0 - 2.0 * (x * x + y * y);
+        }
+        sok = ok;
+    }
+    // per view of the group
+    const int k_end = min(sd.view_count, (grp + 1) * kProjViews);
+    for (int k = grp * kProjViews; k < k_end; ++k) {
+        const int v = vlist[sd.view_begin + k];
+        const ViewDesc &vd = views[v];
+        const int64_t e = (int64_t)vd.entry_base + i;
+        uint32_t out_key = 0xFFFFFFFFu, out_cnt = 0;
+        bool ok = sok;
+        if (ok) {
             const float *vm = viewmat + 12 * v;
             const double R[9] = {vm[0], vm[1], vm[2], vm[4], vm[5], vm[6], vm[8], vm[9], vm[10]};
             const double t[3] = {vm[3], vm[7], vm[11]};
@@ -258,13 +291,13 @@ __global__ __launch_bounds__(256) void k_preprocess(const ViewDesc *__restrict__
                 }
             }
         }
-    }
-    key[e] = out_key;
-    cnt[e] = out_cnt;
-    if (grad && out_cnt != 0) {  // the fused path clears the entry's gradient slot here
-        const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
-        const int q = kp.gstride / 4;
-        for (int k = 0; k < q; ++k) grad[q * e + k] = z;
+        key[e] = out_key;
+        cnt[e] = out_cnt;
+        if (grad && out_cnt != 0) {  // the fused path clears the entry's gradient slot here
+            const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+            const int q = kp.gstride / 4;
+            for (int kk = 0; kk < q; ++kk) grad[q * e + kk] = z;
+        }
     }
 }
 
@@ -560,9 +593,9 @@ hipError_t launch_setup(const Plan &p, void *ws, const ViewDesc *views, const Su
 
 hipError_t launch_preprocess(const Plan &p, void *ws, const KParams &kp, const float *intr,
                              const float *viewmat, bool zero_grad, hipStream_t st) {
-    const int blocks = (int)(p.E / 256);
-    if (blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_preprocess, dim3(blocks), dim3(256), 0, st, at<ViewDesc>(ws, p.o_views), p.V,
+    if (p.proj_blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_preprocess, dim3(p.proj_blocks), dim3(256), 0, st, at<SubmapDesc>(ws, p.o_subs), p.S,
+                       at<int32_t>(ws, p.o_vlist), at<ViewDesc>(ws, p.o_views),
                        intr, viewmat, kp, at<Rec>(ws, p.o_rec), at<uint32_t>(ws, p.o_key),
                        at<uint32_t>(ws, p.o_cnt), zero_grad ? at<float4>(ws, p.o_grad) : nullptr,
                        at<Ell>(ws, p.o_ell), at<uint32_t>(ws, p.o_emeta));

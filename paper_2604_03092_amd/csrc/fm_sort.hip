@@ -550,42 +550,78 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t *__restrict__ sorte
 // Start of binning: clear the status words (block 0) and start every tile
 // range empty with ts > te; the last tile-sort pass fills the ranges.
 __global__ __launch_bounds__(256) void k_init_ranges(uint32_t *__restrict__ status, int n_status,
+                                                      uint32_t *__restrict__ tbucket,
                                                       uint32_t *__restrict__ ts, uint32_t *__restrict__ te,
                                                       int64_t n) {
     if (blockIdx.x == 0 && (int)threadIdx.x < n_status) status[threadIdx.x] = 0u;
+    if (blockIdx.x == 0) {  // the blend order's bucket counts and cursors
+        tbucket[threadIdx.x] = 0u;
+        tbucket[kRadix + threadIdx.x] = 0u;
+    }
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
         ts[i] = 0xFFFFFFFFu;
         te[i] = 0u;
     }
 }
 
-// Blend order: a tile's cost key is 255 minus 16 log2(1 + list length)
-// (capped), so one stable 8-bit pass lists the tiles longest first; the
-// blend's workgroups take tiles in that order, so long tiles start early and
-// short ones fill the end of the launch.  A block keys the tiles of one
-// 4096-item sort tile and writes that sort tile's digit histogram for the
-// pass.
+// Blend order: a tile's cost bucket is 255 minus 16 log2(1 + list length)
+// (capped); listing the tiles by increasing bucket puts the longest lists
+// first, so the blend's workgroups (which take tiles in that order) start the
+// long tiles early and the short ones fill the end of the launch.  Two
+// kernels: a histogram of the buckets (LDS per block, one global atomic per
+// bucket and block), then each block takes ranges of its buckets' slots with
+// one atomic per bucket and places its tiles.  The order within a bucket
+// depends on the schedule; nothing computed depends on the order.
+__device__ __forceinline__ uint32_t tile_bucket(const uint32_t *ts, const uint32_t *te, int64_t i) {
+    const uint32_t len = te[i] > ts[i] ? te[i] - ts[i] : 0u;  // an empty tile has ts > te
+    const float lv = 16.f * __log2f((float)len + 1.f);
+    return 255u - (lv < 255.f ? (uint32_t)lv : 255u);
+}
+
 __global__ __launch_bounds__(256) void k_tile_cost(const uint32_t *__restrict__ ts, const uint32_t *__restrict__ te,
-                                                    int64_t n, uint32_t *__restrict__ key,
-                                                    uint32_t *__restrict__ hist, int G) {
+                                                    int64_t n, uint32_t *__restrict__ bucket_count) {
     __shared__ uint32_t s_hist[kRadix];
-    static_assert(kRadix == 256, "one digit per thread");
-    for (uint32_t t = blockIdx.x; t < (uint32_t)G; t += gridDim.x) {
-        __syncthreads();  // the previous sort tile's histogram has been read
-        s_hist[threadIdx.x] = 0u;
+    s_hist[threadIdx.x] = 0u;
+    __syncthreads();
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        atomicAdd(&s_hist[tile_bucket(ts, te, i)], 1u);
+    __syncthreads();
+    if (s_hist[threadIdx.x]) atomicAdd(&bucket_count[threadIdx.x], s_hist[threadIdx.x]);
+}
+
+__global__ __launch_bounds__(256) void k_tile_place(const uint32_t *__restrict__ ts, const uint32_t *__restrict__ te,
+                                                     int64_t n, const uint32_t *__restrict__ bucket_count,
+                                                     uint32_t *__restrict__ bucket_cursor,
+                                                     uint32_t *__restrict__ order) {
+    __shared__ uint32_t s_base[kRadix], s_cnt[kRadix], s_take[kRadix];
+    // exclusive scan of the bucket counts (each block redundantly)
+    const int lane = lane_id(), w = threadIdx.x >> 6;
+    __shared__ uint32_t wsum[4];
+    const uint32_t c = bucket_count[threadIdx.x];
+    uint32_t x = c;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) wsum[w] = x;
+    __syncthreads();
+    uint32_t base = x - c;
+    for (int j = 0; j < w; ++j) base += wsum[j];
+    s_base[threadIdx.x] = base;
+    for (int64_t i0 = (int64_t)blockIdx.x * 256; i0 < n; i0 += (int64_t)gridDim.x * 256) {
+        const int64_t i = i0 + threadIdx.x;
         __syncthreads();
-        for (int k = 0; k < kSortTile / 256; ++k) {
-            const int64_t i = (int64_t)t * kSortTile + k * 256 + threadIdx.x;
-            if (i < n) {
-                const uint32_t len = te[i] > ts[i] ? te[i] - ts[i] : 0u;  // an empty tile has ts > te
-                const float lv = 16.f * __log2f((float)len + 1.f);
-                const uint32_t kk = 255u - (lv < 255.f ? (uint32_t)lv : 255u);
-                key[i] = kk;
-                atomicAdd(&s_hist[kk], 1u);
-            }
+        s_cnt[threadIdx.x] = 0u;
+        __syncthreads();
+        uint32_t b = 0, rank = 0;
+        if (i < n) {
+            b = tile_bucket(ts, te, i);
+            rank = atomicAdd(&s_cnt[b], 1u);
         }
         __syncthreads();
-        hist[threadIdx.x * (uint32_t)G + t] = s_hist[threadIdx.x];
+        if (s_cnt[threadIdx.x]) s_take[threadIdx.x] = atomicAdd(&bucket_cursor[threadIdx.x], s_cnt[threadIdx.x]);
+        __syncthreads();
+        if (i < n) order[s_base[b] + s_take[b] + rank] = (uint32_t)i;
     }
 }
 
@@ -619,7 +655,7 @@ hipError_t launch_binning(const Plan &p, void *ws, const KParams &kp, hipStream_
     const int fill_blocks = (int)((p.T + 255) / 256 < 4096 ? (p.T + 255) / 256 : 4096);
     static_assert(sizeof(Status) / 4 <= 256, "status words are cleared by one block");
     hipLaunchKernelGGL(k_init_ranges, dim3(fill_blocks), dim3(256), 0, st, reinterpret_cast<uint32_t *>(status),
-                       (int)(sizeof(Status) / 4), ts, te, p.T);
+                       (int)(sizeof(Status) / 4), at<uint32_t>(ws, p.o_tbucket), ts, te, p.T);
     // 1. stable sort of the entries by their 32-bit depth key (4 passes; the
     //    first pass starts from the identity permutation and drops the
     //    entries that cover no tile, so the later passes see only the
@@ -673,11 +709,11 @@ hipError_t launch_binning(const Plan &p, void *ws, const KParams &kp, hipStream_
     }
     // 4. the longest-first tile order, written whichever order the blend
     //    uses, so that a later call on this workspace may choose either
-    uint32_t *tkey = at<uint32_t>(ws, p.o_tkey), *tkey2 = at<uint32_t>(ws, p.o_tkey2);
-    hipLaunchKernelGGL(k_tile_cost, dim3((unsigned)std::min(p.sortG_t, kMaxEmitGrid)), dim3(256), 0, st, ts, te,
-                       p.T, tkey, hist, p.sortG_t);
-    radix_pass(tkey, nullptr, tkey2, at<uint32_t>(ws, p.o_torder), nullptr, (uint32_t)p.T, 0, hist, p.sortG_t,
-               tot + 8 * kRadix, 0, nullptr, st, nullptr, true);
+    uint32_t *tb = at<uint32_t>(ws, p.o_tbucket);
+    const int tblocks = (int)std::min<int64_t>((p.T + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_tile_cost, dim3(tblocks), dim3(256), 0, st, ts, te, p.T, tb);
+    hipLaunchKernelGGL(k_tile_place, dim3(tblocks), dim3(256), 0, st, ts, te, p.T, tb, tb + kRadix,
+                       at<uint32_t>(ws, p.o_torder));
     return hipGetLastError();
 }
 
