@@ -296,6 +296,8 @@ fm_status build(fm_ctx *ctx, const fm_batch *b, const fm_raster_params *prm, int
     p.o_rec = take(sizeof(fm::Rec) * (size_t)E);
     p.o_key = take(4 * (size_t)E);
     p.o_cnt = take(4 * (size_t)E);
+    p.o_cnt2 = take(4 * (size_t)E);  // tile counts riding along the depth sort
+    p.o_cnt3 = take(4 * (size_t)E);
     p.o_key2 = take(4 * (size_t)E);
     p.o_val = take(4 * (size_t)E);
     p.o_val2 = take(4 * (size_t)E);

@@ -145,9 +145,12 @@ __global__ __launch_bounds__(256) void k_radix_rowscan(uint32_t *__restrict__ hi
 // histogram entry plus the digit's base, the exclusive scan of the digit
 // totals, which every block forms itself; block 0 also stores the number of
 // items the pass keeps when n_kept is set.
-// With SUBST, the output key of an item is key_subst[value] instead of its
-// key (the last pass of a sort whose keys are not needed afterwards); the
-// gathers are issued with the loads and the digits kept in LDS.
+// CARRY moves a second word per item along with the key and value, read at
+// the item's input position from v2_in (so the first pass of a sort, whose
+// input is in entry order, reads it coalesced): CARRY 1 writes it to v2_out
+// at the output position, CARRY 2 writes it in place of the key (the last
+// pass of a sort whose keys are not needed afterwards; the digits are kept
+// in LDS).
 // With RANGES (the last pass of the tile sort), the pass also finds the
 // tile ranges [ts, te) of the sorted output: inside one of the block's
 // digit runs the keys are sorted, so a key change there is a tile boundary
@@ -156,7 +159,7 @@ __global__ __launch_bounds__(256) void k_radix_rowscan(uint32_t *__restrict__ hi
 // ts of its tile with an atomic min and its last position + 1 enters te
 // with an atomic max (ts starts at 0xFFFFFFFF, te at 0: a tile without
 // pairs keeps ts > te).
-template <bool SUBST, bool RANGES>
+template <int CARRY, bool RANGES>
 __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t *__restrict__ keys_in,
                                                         const uint32_t *__restrict__ vals_in,
                                                         uint32_t *__restrict__ keys_out,
@@ -164,14 +167,16 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t *__restric
                                                         uint32_t n_host, int shift,
                                                         const uint32_t *__restrict__ hist, int G, int drop,
                                                         const uint32_t *__restrict__ tot, uint32_t *n_kept,
-                                                        const uint32_t *__restrict__ key_subst,
+                                                        const uint32_t *__restrict__ v2_in,
+                                                        uint32_t *__restrict__ v2_out,
                                                         uint32_t *__restrict__ ts, uint32_t *__restrict__ te,
                                                         uint32_t n_tiles) {
     constexpr int IPT = kSortTile / 256;   // items per lane
     constexpr int PER_WAVE = kSortTile / 4;
     __shared__ uint32_t s_key[kSortTile];
     __shared__ uint32_t s_val[kSortTile];
-    __shared__ uint8_t s_dig[SUBST ? kSortTile : 1];
+    __shared__ uint8_t s_dig[CARRY == 2 ? kSortTile : 1];
+    __shared__ uint32_t s_v2[CARRY == 1 ? kSortTile : 1];
     __shared__ uint32_t s_wcnt[4][kRadix];  // per-wave digit counts, then per-wave offsets
     __shared__ uint32_t s_start[kRadix];    // block-local start of each digit's run
     __shared__ uint32_t s_glob[kRadix];     // global start of this block's run of each digit
@@ -209,12 +214,12 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t *__restric
         key[k] = valid ? keys_in[i] : kNoKey;
         val[k] = valid ? (vals_in ? vals_in[i] : i) : 0u;
     }
-    uint32_t sub[SUBST ? IPT : 1];
-    if (SUBST) {
+    uint32_t v2[CARRY ? IPT : 1];
+    if (CARRY) {
 #pragma unroll
         for (int k = 0; k < IPT; ++k) {
             const uint32_t i = wbase + (uint32_t)k * 64u + (uint32_t)lane;
-            sub[k] = i < hi ? key_subst[val[k]] : 0u;
+            v2[k] = i < hi ? v2_in[i] : 0u;
         }
     }
     __syncthreads();
@@ -265,12 +270,13 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t *__restric
         const uint32_t d = (key[k] >> shift) & 0xFFu;
         const uint32_t lp = s_start[d] + s_wcnt[w][d] + rank[k];
         if (lp < (uint32_t)kSortTile) {  // always holds; guards the LDS store
-            if (SUBST) {
-                s_key[lp] = sub[k];
+            if (CARRY == 2) {
+                s_key[lp] = v2[k];
                 s_dig[lp] = (uint8_t)d;
             } else {
                 s_key[lp] = key[k];
             }
+            if (CARRY == 1) s_v2[lp] = v2[k];
             s_val[lp] = val[k];
         }
     }
@@ -278,11 +284,12 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t *__restric
     const uint32_t total = s_wsum[0] + s_wsum[1] + s_wsum[2] + s_wsum[3];
     for (uint32_t i = threadIdx.x; i < total; i += 256) {
         const uint32_t k = s_key[i];
-        const uint32_t d = SUBST ? (uint32_t)s_dig[i] : (k >> shift) & 0xFFu;
+        const uint32_t d = CARRY == 2 ? (uint32_t)s_dig[i] : (k >> shift) & 0xFFu;
         const uint32_t g = s_glob[d] + (i - s_start[d]);
         if (g < n) {  // always holds; guards the store
             keys_out[g] = k;
             vals_out[g] = s_val[i];
+            if (CARRY == 1) v2_out[g] = s_v2[i];
             if (RANGES && k < n_tiles) {
                 if (i == s_start[d]) atomicMin(&ts[k], g);
                 else if (s_key[i - 1] != k) ts[k] = g;
@@ -627,20 +634,19 @@ __global__ __launch_bounds__(256) void k_tile_place(const uint32_t *__restrict__
 
 void radix_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout, const uint32_t *n_dev,
                 uint32_t n_host, int shift, uint32_t *hist, int G, uint32_t *tot, int drop, uint32_t *n_kept,
-                hipStream_t s, const uint32_t *key_subst = nullptr, bool hist_ready = false,
-                uint32_t *ts = nullptr, uint32_t *te = nullptr, uint32_t n_tiles = 0) {
+                hipStream_t s, int carry = 0, const uint32_t *v2_in = nullptr, uint32_t *v2_out = nullptr,
+                bool hist_ready = false, uint32_t *ts = nullptr, uint32_t *te = nullptr, uint32_t n_tiles = 0) {
     if (!hist_ready)
         hipLaunchKernelGGL(k_radix_hist, dim3(G), dim3(256), 0, s, kin, n_dev, n_host, shift, hist, G, drop);
     hipLaunchKernelGGL(k_radix_rowscan, dim3(kRadix), dim3(256), 0, s, hist, G, tot);
-    if (key_subst)
-        hipLaunchKernelGGL((k_radix_scatter<true, false>), dim3(G), dim3(256), 0, s, kin, vin, kout, vout, n_dev,
-                           n_host, shift, hist, G, drop, tot, n_kept, key_subst, ts, te, n_tiles);
-    else if (ts)
-        hipLaunchKernelGGL((k_radix_scatter<false, true>), dim3(G), dim3(256), 0, s, kin, vin, kout, vout, n_dev,
-                           n_host, shift, hist, G, drop, tot, n_kept, key_subst, ts, te, n_tiles);
-    else
-        hipLaunchKernelGGL((k_radix_scatter<false, false>), dim3(G), dim3(256), 0, s, kin, vin, kout, vout, n_dev,
-                           n_host, shift, hist, G, drop, tot, n_kept, key_subst, ts, te, n_tiles);
+#define FM_SCATTER(C, R)                                                                                     \
+    hipLaunchKernelGGL((k_radix_scatter<C, R>), dim3(G), dim3(256), 0, s, kin, vin, kout, vout, n_dev, n_host, \
+                       shift, hist, G, drop, tot, n_kept, v2_in, v2_out, ts, te, n_tiles)
+    if (carry == 1) FM_SCATTER(1, false);
+    else if (carry == 2) FM_SCATTER(2, false);
+    else if (ts) FM_SCATTER(0, true);
+    else FM_SCATTER(0, false);
+#undef FM_SCATTER
 }
 
 }  // namespace
@@ -662,12 +668,14 @@ hipError_t launch_binning(const Plan &p, void *ws, const KParams &kp, hipStream_
     //    visible ones)
     const uint32_t E = (uint32_t)p.E;
     uint32_t *n_vis = &status->n_vis;
-    radix_pass(key, nullptr, key2, val2, nullptr, E, 0, hist, p.sortG_e, tot + 0 * kRadix, 1, n_vis, st);
-    radix_pass(key2, val2, key, val, n_vis, 0, 8, hist, p.sortG_e, tot + 1 * kRadix, 0, nullptr, st);
-    radix_pass(key, val, key2, val2, n_vis, 0, 16, hist, p.sortG_e, tot + 2 * kRadix, 0, nullptr, st);
-    // (the last pass outputs each entry's tile count in place of its key)
+    // each entry's tile count rides along (read coalesced by the first pass
+    // in entry order) and the last pass outputs it in place of the key
     const uint32_t *cnt = at<uint32_t>(ws, p.o_cnt);
-    radix_pass(key2, val2, key, val, n_vis, 0, 24, hist, p.sortG_e, tot + 3 * kRadix, 0, nullptr, st, cnt);
+    uint32_t *ca = at<uint32_t>(ws, p.o_cnt2), *cb = at<uint32_t>(ws, p.o_cnt3);
+    radix_pass(key, nullptr, key2, val2, nullptr, E, 0, hist, p.sortG_e, tot + 0 * kRadix, 1, n_vis, st, 1, cnt, ca);
+    radix_pass(key2, val2, key, val, n_vis, 0, 8, hist, p.sortG_e, tot + 1 * kRadix, 0, nullptr, st, 1, ca, cb);
+    radix_pass(key, val, key2, val2, n_vis, 0, 16, hist, p.sortG_e, tot + 2 * kRadix, 0, nullptr, st, 1, cb, ca);
+    radix_pass(key2, val2, key, val, n_vis, 0, 24, hist, p.sortG_e, tot + 3 * kRadix, 0, nullptr, st, 2, ca);
     // 2. pair offsets in depth order and emission
     uint32_t *blk = at<uint32_t>(ws, p.o_scan);
     uint64_t *blk_off = reinterpret_cast<uint64_t *>(blk + ((p.scan_blocks + 63) & ~63));
@@ -702,8 +710,8 @@ hipError_t launch_binning(const Plan &p, void *ws, const KParams &kp, hipStream_
     for (int pass = 0; pass < p.pair_passes; ++pass) {
         const bool last = pass + 1 == p.pair_passes;
         radix_pass(ka, va, kb, vb, pass == 0 ? &status->n_pairs : &status->n_kept, 0, 8 * pass, hist, p.sortG_p,
-                   tot + (4 + pass) * kRadix, pass == 0 ? 1 : 0, pass == 0 ? &status->n_kept : nullptr, st,
-                   nullptr, pass == 0, last ? ts : nullptr, last ? te : nullptr, (uint32_t)p.T);
+                   tot + (4 + pass) * kRadix, pass == 0 ? 1 : 0, pass == 0 ? &status->n_kept : nullptr, st, 0,
+                   nullptr, nullptr, pass == 0, last ? ts : nullptr, last ? te : nullptr, (uint32_t)p.T);
         uint32_t *t = ka; ka = kb; kb = t;
         t = va; va = vb; vb = t;
     }
