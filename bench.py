@@ -51,14 +51,24 @@ def git_blob_sha1(path):
     return hashlib.sha1(b"blob %d\0" % len(data) + data).hexdigest()
 
 
-def measured_traffic():
+def blend_kernel_name(tw, th, waves, depth, deterministic):
+    """The blend kernel's name as the profiler prints it for a launch."""
+    split = "true" if waves == 2 else "false"
+    det = "true" if deterministic else "false"
+    return f"k_render_fused<Geo<{tw}, {th}, {split}, {depth}>, {det}>"
+
+
+def measured_traffic(kernel, order):
     """Per-launch HBM bytes of the blend kernel, or None when the measurement
-    is missing or was taken on a different kernel source."""
+    is missing, was taken on a different kernel source, or on another launch
+    (kernel instance or tile order) than the one timed."""
     try:
         t = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
         return None
     if t.get("blend_source_sha1") != git_blob_sha1(BLEND_SOURCE):
+        return None
+    if t.get("kernel") != kernel or t.get("tile_order") != order:
         return None
     return t.get("bytes_per_launch")
 
@@ -333,6 +343,24 @@ def lds_peak(rast, blocks=256 * 8 * 4, iters=4096):
     return res
 
 
+def tune_launch(rast, gs, deterministic=False):
+    """The autotuner's launch for a batch (untimed): (tile w, tile h, tile
+    order, waves per tile, LDS depth).  Its workspace and pair capacity are
+    sized for the largest candidate (8x8 tiles)."""
+    import torch
+    p8 = rast.params(tile=(8, 8), overwrite=True, deterministic=deterministic)
+    _, ws8 = rast.forward(gs, p8)
+    torch.cuda.synchronize()
+    ws8 = rast.workspace(gs, p8, max_pairs=int(ws8.n_pairs * 1.1) + 4096)
+    out = rast.new_outputs(gs)
+    grads, dvm = gs.zero_grads()
+    loss = torch.zeros(1, device="cuda")
+    c = rast.autotune(gs, ws8, out, grads, dvm, loss)
+    del ws8, out, grads, dvm
+    torch.cuda.empty_cache()
+    return (int(c.tile_w), int(c.tile_h), int(c.tile_order), int(c.tile_waves), int(c.lds_depth))
+
+
 def time_config(rast, name, steps):
     """Fused forward + L1 + backward of one config's whole batch, one hipGraph
     replay per step, at 16x16 tiles (longest list first) and at the tile shape
@@ -440,7 +468,9 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="headline")
-    ap.add_argument("--tile", default="16x16")
+    ap.add_argument("--tile", default="auto",
+                    help="tile shape WxH, or auto: the autotuner picks the shape, tile order, waves per tile and "
+                         "LDS depth for the batch (untimed) and the step runs with its choice")
     ap.add_argument("--tile-order", type=int, default=1, choices=(1, 2),
                     help="blend tile order: 1 longest list first, 2 image order")
     ap.add_argument("--tile-waves", type=int, default=1, choices=(1, 2),
@@ -489,11 +519,18 @@ def main():
     scene = make_workload(args.workload)
     gs = GpuScene.from_scene(scene)
     rast = Rasterizer()
-    tw, th = (int(x) for x in args.tile.split("x"))
     # the step stores its gradients, pose gradients and loss (overwrite mode),
     # so no clearing kernels run between steps
-    params = rast.params(tile=(tw, th), deterministic=args.deterministic, overwrite=True,
-                         tile_order=args.tile_order, tile_waves=args.tile_waves, lds_depth=args.lds_depth)
+    tuned = None
+    if args.tile == "auto":
+        tuned = tune_launch(rast, gs, args.deterministic)
+        tw, th, order, waves, depth = tuned
+        log(f"autotuned: {tw}x{th}, order {order}, waves {waves}, lds depth {depth}")
+    else:
+        tw, th = (int(x) for x in args.tile.split("x"))
+        order, waves, depth = args.tile_order, args.tile_waves, args.lds_depth
+    params = rast.params(tile=(tw, th), deterministic=args.deterministic, overwrite=True, tile_order=order,
+                         tile_waves=waves, lds_depth=depth)
 
     # size the pair buffer from one eager forward (not timed)
     out, ws = rast.forward(gs, params)
@@ -559,7 +596,7 @@ def main():
 
     plain = None
     if not args.no_plain:
-        plain_params = rast.params(tile=(tw, th), deterministic=args.deterministic)
+        plain_params = rast.params(tile=(16, 16), deterministic=args.deterministic)
         singles = []
         for v in range(gs.n_views):
             gv = GpuScene(gs.submaps, [gs.views[v]], gs.intr[v:v + 1].contiguous(), gs.viewmat[v:v + 1].contiguous())
@@ -602,10 +639,11 @@ def main():
         log(f"plain: {plain['ms_per_step']:.3f} ms/step, {plain['mpixel_s']:.1f} Mpixel/s")
 
     blend_s = phases["blend"] * 1e-3
+    blend_kernel = blend_kernel_name(tw, th, waves, 64 if args.deterministic else depth, args.deterministic)
     achieved = useful * OPS_PER_USEFUL / blend_s / 1e12 if blend_s > 0 else 0.0
     roofline = dict(bound="alu", achieved=round(achieved, 3), peak=round(ALU_PEAK_TOPS, 3), unit="TOP/s",
-                    frac=round(achieved / ALU_PEAK_TOPS, 4), traffic=measured_traffic(),
-                    kernel="k_render_fused", kernel_ms=round(phases["blend"], 4),
+                    frac=round(achieved / ALU_PEAK_TOPS, 4), traffic=measured_traffic(blend_kernel, order),
+                    kernel=blend_kernel, kernel_ms=round(phases["blend"], 4),
                     useful_evals=useful, ops_per_useful=OPS_PER_USEFUL)
 
     # HBM-bound phases against their algorithmic bytes: projection 52 B of
@@ -674,9 +712,9 @@ def main():
                    "surfels": int(sum(sm["opacity"].shape[0] for sm in scene.submaps)),
                    "tile": f"{tw}x{th}", "mode": "hipgraph" if graph is not None else "eager",
                    "deterministic": bool(args.deterministic),
-                   "tile_order": "longest list first" if args.tile_order == 1 else "image order",
-                   "waves_per_tile": "one per 8x8 block" if args.tile_waves == 2 else "one per tile",
-                   "lds_depth": args.lds_depth,
+                   "tile_order": "longest list first" if order == 1 else "image order",
+                   "waves_per_tile": "one per 8x8 block" if waves == 2 else "one per tile",
+                   "lds_depth": depth, "launch": "autotuned" if tuned else "given",
                    "pairs": n_pairs},
         "views_per_s": round(views_s, 3),
         "plain": plain,

@@ -335,13 +335,19 @@ fm_status fm_phase_times(fm_ctx *ctx, float *ms, int n);
 /* Total tile count of a batch for the given tile shape. */
 fm_status fm_tile_count(const fm_batch *batch, const fm_raster_params *params, int64_t *n_tiles);
 
-/* Autotuner: times fm_fwd_bwd_l1 (5 calls after a warm-up, every status
- * checked) over the supported tile shapes, each with both tile orders and,
- * for tiles of several 8x8 blocks, both work splits (tile_waves 1 and 2),
- * then the LDS batch depths 32 and 128 of the fastest (not with
- * deterministic sums), on this batch (outputs, gradients and the loss are
- * overwritten/accumulated while it runs), and writes the fastest into
- * *chosen (a copy of *params with tile_w, tile_h, tile_order, tile_waves and
+/* Autotuner: times fm_fwd_bwd_l1 in two stages, every call's status
+ * checked and every call timed on its own (a candidate's score is its
+ * median call after a warm-up call).  Stage 1, 5 calls each: the supported
+ * tile shapes, each with both tile orders and, for tiles of several 8x8
+ * blocks, both work splits (tile_waves 1 and 2), at LDS depth 64.  Stage 2,
+ * 15 calls each: the default launch (16x16, tile_order 1, tile_waves 1,
+ * depth 64) and the three fastest of stage 1, each at LDS depths 64, 32 and
+ * 128 (depth 64 only with deterministic sums), in that order; a candidate
+ * replaces the best so far only when its median is more than 1% lower.
+ * Runs on this batch (outputs, gradients and the loss are
+ * overwritten/accumulated while it runs), and
+ * writes the stage-2 winner into *chosen (a copy of *params with
+ * tile_w, tile_h, tile_order, tile_waves and
  * lds_depth set).  The choice is cached in the context under the device's
  * architecture, the batch's shape signature and the deterministic flag (the
  * two modes tune separately) and, if cache_path is not NULL, in a JSON file

@@ -928,19 +928,23 @@ fm_status fm_autotune(fm_ctx *ctx, const fm_batch *b, const fm_raster_params *pr
     if (s == FM_OK) s = use_device(ctx);
     if (s != FM_OK) return s;
     hipStream_t st = (hipStream_t)stream;
+    // one event per call boundary: each call is timed on its own and a
+    // candidate is scored by the median, so that one slow call (a clock
+    // change, another process on the device) does not decide the choice
+    constexpr int kMaxReps = 15;
     struct Events {  // destroyed on every return path
-        hipEvent_t e[2] = {nullptr, nullptr};
+        hipEvent_t e[kMaxReps + 1] = {};
         ~Events() {
             for (hipEvent_t x : e)
                 if (x) (void)hipEventDestroy(x);
         }
     } ev;
-    FM_TRY_HIP(hipEventCreate(&ev.e[0]), "hipEventCreate");
-    FM_TRY_HIP(hipEventCreate(&ev.e[1]), "hipEventCreate");
-    // Times one candidate: a warm-up call, its pair status, then `reps` calls
-    // (each call's status checked) between two events.  Returns false when
-    // the candidate does not fit the workspace or the capacity.
-    auto time_one = [&](const fm_ctx::Tuned &t, float &ms) -> fm_status {
+    for (hipEvent_t &x : ev.e) FM_TRY_HIP(hipEventCreate(&x), "hipEventCreate");
+    // Times one candidate: a warm-up call and its pair status, then `reps`
+    // calls (each call's status checked), each between two events; `ms` is
+    // the median call.  A candidate that does not fit the workspace or the
+    // pair capacity gets ms < 0 (skipped).
+    auto time_one = [&](const fm_ctx::Tuned &t, int reps, float &ms) -> fm_status {
         fm_raster_params q = *prm;
         q.tile_w = t.tw;
         q.tile_h = t.th;
@@ -958,51 +962,65 @@ fm_status fm_autotune(fm_ctx *ctx, const fm_batch *b, const fm_raster_params *pr
         FM_TRY_HIP(hipMemcpy(&stt, static_cast<char *>(ws) + bt.plan.o_status, sizeof(stt), hipMemcpyDeviceToHost),
                    "hipMemcpy(status)");
         if (stt.overflow) return FM_OK;  // capacity too small for this shape: skipped
-        const int reps = 5;
+        reps = std::max(1, std::min(reps, kMaxReps));
         FM_TRY_HIP(hipEventRecord(ev.e[0], st), "hipEventRecord");
         for (int k = 0; k < reps; ++k) {
             r = run_fused(ctx, bt, &q, b, ws, ls, out, loss, dL_dviewmat, st);
             if (r != FM_OK) return r;
+            FM_TRY_HIP(hipEventRecord(ev.e[k + 1], st), "hipEventRecord");
         }
-        FM_TRY_HIP(hipEventRecord(ev.e[1], st), "hipEventRecord");
-        FM_TRY_HIP(hipEventSynchronize(ev.e[1]), "hipEventSynchronize");
-        float t_ms = 0.f;
-        FM_TRY_HIP(hipEventElapsedTime(&t_ms, ev.e[0], ev.e[1]), "hipEventElapsedTime");
-        ms = t_ms / reps;
+        FM_TRY_HIP(hipEventSynchronize(ev.e[reps]), "hipEventSynchronize");
+        float dt[kMaxReps];
+        for (int k = 0; k < reps; ++k)
+            FM_TRY_HIP(hipEventElapsedTime(&dt[k], ev.e[k], ev.e[k + 1]), "hipEventElapsedTime");
+        std::sort(dt, dt + reps);
+        ms = dt[reps / 2];
         return FM_OK;
     };
-    // every tile shape with both tile orders and, where a tile holds several
-    // 8x8 blocks, one wave per tile or per block; then the LDS batch depths
-    // of the fastest (deterministic sums keep depth 64)
+    // Stage 1: every tile shape with both tile orders and, where a tile holds
+    // several 8x8 blocks, one wave per tile or per block, at LDS depth 64 and
+    // a few calls each.  Stage 2: the default launch (16x16, longest list
+    // first, one wave per tile, depth 64) and the three fastest of stage 1,
+    // each at LDS depths 64, 32 and 128 (deterministic sums keep depth 64),
+    // with more calls.  A candidate replaces the best so far only when its
+    // median is more than 1% lower, so that timing noise does not move the
+    // choice away from the default.
     const int shapes[5][2] = {{16, 16}, {8, 8}, {16, 8}, {32, 8}, {32, 32}};
-    float best = 1e30f;
-    fm_ctx::Tuned bt_best = {16, 16, 1, 1, 64};
-    bool any = false;
+    const fm_ctx::Tuned dflt = {16, 16, 1, 1, 64};
+    std::vector<std::pair<float, fm_ctx::Tuned>> stage1;
     for (const auto &sh : shapes) {
         for (int waves = 1; waves <= (split_possible(sh[0], sh[1]) ? 2 : 1); ++waves) {
             for (int order = 1; order <= 2; ++order) {
                 const fm_ctx::Tuned t = {sh[0], sh[1], order, waves, 64};
                 float ms;
-                s = time_one(t, ms);
+                s = time_one(t, 5, ms);
                 if (s != FM_OK) return s;
-                if (ms < 0.f) continue;
-                any = true;
-                if (ms < best) {
-                    best = ms;
-                    bt_best = t;
-                }
+                if (ms >= 0.f) stage1.push_back({ms, t});
             }
         }
     }
-    if (!any) return fail(ctx, FM_ERR_WORKSPACE, "no tile shape fits the workspace and capacity");
-    if (prm->deterministic != 1) {
-        for (int depth : {32, 128}) {
-            fm_ctx::Tuned t = bt_best;
+    if (stage1.empty()) return fail(ctx, FM_ERR_WORKSPACE, "no tile shape fits the workspace and capacity");
+    std::stable_sort(stage1.begin(), stage1.end(),
+                     [](const auto &x, const auto &y) { return x.first < y.first; });
+    auto same = [](const fm_ctx::Tuned &x, const fm_ctx::Tuned &y) {
+        return x.tw == y.tw && x.th == y.th && x.order == y.order && x.waves == y.waves && x.depth == y.depth;
+    };
+    std::vector<fm_ctx::Tuned> stage2;
+    for (const auto &c : stage1)
+        if (same(c.second, dflt)) stage2.push_back(dflt);  // only when it fits
+    for (size_t i = 0; i < stage1.size() && i < 3; ++i)
+        if (!same(stage1[i].second, dflt)) stage2.push_back(stage1[i].second);
+    float best = 1e30f;
+    fm_ctx::Tuned bt_best = stage1[0].second;
+    for (const fm_ctx::Tuned &c : stage2) {
+        for (int depth : {64, 32, 128}) {
+            if (depth != 64 && prm->deterministic == 1) continue;
+            fm_ctx::Tuned t = c;
             t.depth = depth;
             float ms;
-            s = time_one(t, ms);
+            s = time_one(t, kMaxReps, ms);
             if (s != FM_OK) return s;
-            if (ms >= 0.f && ms < best) {
+            if (ms >= 0.f && ms < 0.99f * best) {
                 best = ms;
                 bt_best = t;
             }
