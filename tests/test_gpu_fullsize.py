@@ -81,6 +81,8 @@ def _compare_grads(tag, grads, dvm, rg, rdvm, submaps, views):
 
 
 def _fused_vs_oracle(rast, sc, views, tag, params=None, okw=None):
+    """params: one raster-parameter set or a list of them (launches), each
+    run on the GPU against the same oracle forward and backward."""
     okw = okw or {}
     gs = GpuScene.from_scene(sc)
     _say(f"{tag}: oracle forward of views {views}")
@@ -89,22 +91,25 @@ def _fused_vs_oracle(rast, sc, views, tag, params=None, okw=None):
     assert keep.mean() > 0.98, keep.mean()
     mask = np.zeros(sc.total_pixels, np.uint8)
     mask[sel] = keep
-    _say(f"{tag}: fused batch of {gs.n_views} views")
-    out, grads, dvm, loss, ws = _fused_masked(rast, gs, params or _bench_params(rast),
-                                               torch.from_numpy(mask).cuda())
-    got = {k: x[..., torch.from_numpy(sel).cuda()] for k, x in out.items()}
-    assert_images_close(got, ref, ~ref["flags"], what=tag)
     L, g = oracle.l1_loss(sc, ref, views=views, mask=keep)
-    assert abs(loss - L) <= 2e-5 * max(L, 1e-6), (loss, L)
     _say(f"{tag}: oracle backward")
     rg, rdvm = oracle.backward_scene(sc, g, views=views, **okw)
     used = sorted({sc.views[v][2] for v in views})
-    res = _compare_grads(tag, grads, dvm, rg, rdvm, used, views)
-    # views without loss pixels store a zero pose gradient
-    others = [v for v in range(sc.n_views) if v not in views]
-    if others:
-        assert float(dvm[others].abs().max()) == 0.0
-    return res
+    plist = params if isinstance(params, list) else [params or _bench_params(rast)]
+    res = []
+    for p in plist:
+        t = f"{tag} {p.tile_w}x{p.tile_h}/order {p.tile_order}/waves {p.tile_waves}/depth {p.lds_depth}"
+        _say(f"{t}: fused batch of {gs.n_views} views")
+        out, grads, dvm, loss, ws = _fused_masked(rast, gs, p, torch.from_numpy(mask).cuda())
+        got = {k: x[..., torch.from_numpy(sel).cuda()] for k, x in out.items()}
+        assert_images_close(got, ref, ~ref["flags"], what=t)
+        assert abs(loss - L) <= 2e-5 * max(L, 1e-6), (loss, L)
+        res.append(_compare_grads(t, grads, dvm, rg, rdvm, used, views))
+        # views without loss pixels store a zero pose gradient
+        others = [v for v in range(sc.n_views) if v not in views]
+        if others:
+            assert float(dvm[others].abs().max()) == 0.0
+    return res if isinstance(params, list) else res[0]
 
 
 def test_fused_headline_views_match_oracle(rast):
@@ -120,12 +125,24 @@ def test_fused_config2_view_matches_oracle(rast):
 
 def test_fused_config3_views_match_oracle(rast):
     """Config 3 (64 uneven views over 8 submaps): its largest 1280x720 view and
-    a 320x240 view of another submap, with pose gradients."""
+    a 320x240 view of another submap, with pose gradients; at the benchmark's
+    16x16 launch and at the 32x32 launch the autotuner picks for this batch
+    (the per-config block of the benchmark times both)."""
     sc = scenes.config3()
     big = max(range(sc.n_views), key=lambda v: sc.views[v][0] * sc.views[v][1])
     small = next(v for v in range(sc.n_views)
                  if sc.views[v][:2] == (320, 240) and sc.views[v][2] != sc.views[big][2])
-    _fused_vs_oracle(rast, sc, [small, big], f"config3 v{small},v{big}")
+    _fused_vs_oracle(rast, sc, [small, big], f"config3 v{small},v{big}",
+                     params=[_bench_params(rast), rast.params(tile=(32, 32), tile_order=1, overwrite=True)])
+
+
+def test_fused_config4_views_match_oracle(rast):
+    """Config 4 (32 per-pixel maps of 518x392, each view rendering its own
+    frame): views 5 and 20 carry the loss; at 16x16 and at the autotuner's
+    16x8 launch with LDS depth 32."""
+    _fused_vs_oracle(rast, scenes.config4(), [5, 20], "config4 v5,v20",
+                     params=[_bench_params(rast),
+                             rast.params(tile=(16, 8), tile_order=1, lds_depth=32, overwrite=True)])
 
 
 # ------------------------------------------------------------ edge parameters
