@@ -382,11 +382,8 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
         Rs[7] = 2.f * (y * z + w * x);
         Rs[8] = 1.f - 2.f * (x * x + y * y);
     }
-    // the chain through the homography runs in FP64: for surfels seen at
-    // grazing angles its FP32 rounding reached 1e-3 of the gradients' rms
-    double dmu[3] = {0.0, 0.0, 0.0}, dRs[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    double dsu = 0.0, dsv = 0.0;
-    float dsig = 0.f, dc[3] = {0.f, 0.f, 0.f};
+    float dmu[3] = {0.f, 0.f, 0.f}, dRs[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    float dsu = 0.f, dsv = 0.f, dsig = 0.f, dc[3] = {0.f, 0.f, 0.f};
 
     for (int k = 0; k < sd.view_count; ++k) {
         const int v = vlist[sd.view_begin + k];
@@ -405,34 +402,41 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
             const uint32_t em = emeta[e];
             const float xs = (float)(em & 0x3FFFu), ys = (float)((em >> 14) & 0x3FFFu);
             const float *vm = viewmat + 12 * v;
-            const double R[9] = {vm[0], vm[1], vm[2], vm[4], vm[5], vm[6], vm[8], vm[9], vm[10]};
-            const double t[3] = {vm[3], vm[7], vm[11]};
+            const float R[9] = {vm[0], vm[1], vm[2], vm[4], vm[5], vm[6], vm[8], vm[9], vm[10]};
             const float *K = intr + 4 * v;
-            const double fx = K[0], fy = K[1], cx = K[2], cy = K[3];
-            double tu[3], tv[3], n0[3], p[3];
-#pragma unroll
-            for (int r = 0; r < 3; ++r) {
-                tu[r] = R[3 * r] * Rs[0] + R[3 * r + 1] * Rs[3] + R[3 * r + 2] * Rs[6];
-                tv[r] = R[3 * r] * Rs[1] + R[3 * r + 1] * Rs[4] + R[3 * r + 2] * Rs[7];
-                n0[r] = R[3 * r] * Rs[2] + R[3 * r + 1] * Rs[5] + R[3 * r + 2] * Rs[8];
-                p[r] = R[3 * r] * mu[0] + R[3 * r + 1] * mu[1] + R[3 * r + 2] * mu[2] + t[r];
-            }
-            // M = [s_u t_u | s_v t_v | p]; shifted rows r0 = fx M0 + (cx - xs) M2,
-            // r1 = fy M1 + (cy - ys) M2, r2 = M2
-            const double M0[3] = {su * tu[0], sv * tv[0], p[0]};
-            const double M1[3] = {su * tu[1], sv * tv[1], p[1]};
-            const double M2[3] = {su * tu[2], sv * tv[2], p[2]};
-            const double ox = cx - xs, oy = cy - ys;
-            double r0[3], r1[3];
+            const float fx = K[0], fy = K[1], cx = K[2], cy = K[3];
+            const float ox = cx - xs, oy = cy - ys;
+            // The camera-frame tangents and centre and the shifted rows
+            // r0 = fx M0 + (cx - xs) M2, r1 = fy M1 + (cy - ys) M2, r2 = M2 of
+            // M = [s_u t_u | s_v t_v | p] are formed in FP64: the shift cancels
+            // most of fx p0 and fy p1, and for surfels seen at grazing angles
+            // the FP32 rounding of p, amplified by that cancellation, reached
+            // 1e-3 of the gradients' rms.  The rest of the chain is FP32.
+            float tu[3], tv[3], n0[3], r0[3], r1[3], r2[3];
+            // column c of M: s_u t_u, s_v t_v, p (one column's three doubles at a time)
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                r0[c] = fx * M0[c] + ox * M2[c];
-                r1[c] = fy * M1[c] + oy * M2[c];
+                double m[3];
+#pragma unroll
+                for (int r = 0; r < 3; ++r) {
+                    const double a = R[3 * r], b = R[3 * r + 1], e = R[3 * r + 2];
+                    if (c < 2) {
+                        const double x = a * Rs[c] + b * Rs[3 + c] + e * Rs[6 + c];
+                        if (c == 0) tu[r] = (float)x; else tv[r] = (float)x;
+                        m[r] = (c == 0 ? (double)su : (double)sv) * x;
+                    } else {
+                        m[r] = a * mu[0] + b * mu[1] + e * mu[2] + (double)vm[4 * r + 3];
+                    }
+                }
+                r0[c] = (float)((double)fx * m[0] + (double)ox * m[2]);
+                r1[c] = (float)((double)fy * m[1] + (double)oy * m[2]);
+                r2[c] = (float)m[2];
             }
-            const double *r2 = M2;
+#pragma unroll
+            for (int r = 0; r < 3; ++r) n0[r] = R[3 * r] * Rs[2] + R[3 * r + 1] * Rs[5] + R[3 * r + 2] * Rs[8];
             // c0 = r0 x r1, c1 = r0 x r2, c2 = r1 x r2  ->  d(r0, r1, r2)
-            const double dc0[3] = {g[0], g[1], g[2]}, dc1[3] = {g[3], g[4], g[5]}, dc2[3] = {g[6], g[7], g[8]};
-            double dr0[3], dr1[3], dr2[3];
+            const float dc0[3] = {g[0], g[1], g[2]}, dc1[3] = {g[3], g[4], g[5]}, dc2[3] = {g[6], g[7], g[8]};
+            float dr0[3], dr1[3], dr2[3];
             dr0[0] = (r1[1] * dc0[2] - r1[2] * dc0[1]) + (r2[1] * dc1[2] - r2[2] * dc1[1]);
             dr0[1] = (r1[2] * dc0[0] - r1[0] * dc0[2]) + (r2[2] * dc1[0] - r2[0] * dc1[2]);
             dr0[2] = (r1[0] * dc0[1] - r1[1] * dc0[0]) + (r2[0] * dc1[1] - r2[1] * dc1[0]);
@@ -443,20 +447,20 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
             dr2[1] = (dc1[2] * r0[0] - dc1[0] * r0[2]) + (dc2[2] * r1[0] - dc2[0] * r1[2]);
             dr2[2] = (dc1[0] * r0[1] - dc1[1] * r0[0]) + (dc2[0] * r1[1] - dc2[1] * r1[0]);
             // r0 = fx M0 + (cx - xs) M2, r1 = fy M1 + (cy - ys) M2, r2 = M2  ->  dM
-            double dM[9];
+            float dM[9];
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 dM[c] = fx * dr0[c];
                 dM[3 + c] = fy * dr1[c];
                 dM[6 + c] = ox * dr0[c] + oy * dr1[c] + dr2[c];
             }
-            const double sgn = (em & 0x80000000u) ? -1.0 : 1.0;  // the projection's camera-facing flip
-            const double dp[3] = {dM[2], dM[5], dM[8] + g[13]};
-            const double dtu[3] = {su * dM[0], su * dM[3], su * dM[6]};
-            const double dtv[3] = {sv * dM[1], sv * dM[4], sv * dM[7]};
+            const float sgn = (em & 0x80000000u) ? -1.f : 1.f;  // the projection's camera-facing flip
+            const float dp[3] = {dM[2], dM[5], dM[8] + g[13]};
+            const float dtu[3] = {su * dM[0], su * dM[3], su * dM[6]};
+            const float dtv[3] = {sv * dM[1], sv * dM[4], sv * dM[7]};
             dsu += tu[0] * dM[0] + tu[1] * dM[3] + tu[2] * dM[6];
             dsv += tv[0] * dM[1] + tv[1] * dM[4] + tv[2] * dM[7];
-            const double dn0[3] = {sgn * g[14], sgn * g[15], sgn * g[16]};
+            const float dn0[3] = {sgn * g[14], sgn * g[15], sgn * g[16]};
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 dmu[c] += R[c] * dp[0] + R[3 + c] * dp[1] + R[6 + c] * dp[2];
@@ -468,9 +472,9 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
             for (int r = 0; r < 3; ++r) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c)
-                    dV[4 * r + c] = (float)(dp[r] * mu[c] + dtu[r] * Rs[3 * c] + dtv[r] * Rs[3 * c + 1] +
-                                            dn0[r] * Rs[3 * c + 2]);
-                dV[4 * r + 3] = (float)dp[r];
+                    dV[4 * r + c] = dp[r] * mu[c] + dtu[r] * Rs[3 * c] + dtv[r] * Rs[3 * c + 1] +
+                                    dn0[r] * Rs[3 * c + 2];
+                dV[4 * r + 3] = dp[r];
             }
             dsig += g[9];
             dc[0] += g[10]; dc[1] += g[11]; dc[2] += g[12];
@@ -484,8 +488,7 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
     if (!live) return;
     // dL/d(unit quaternion) from dL/dR_s, then project onto the raw quaternion
     const float w = qh[0], x = qh[1], y = qh[2], z = qh[3];
-    float G[9];
-    for (int k = 0; k < 9; ++k) G[k] = (float)dRs[k];
+    const float *G = dRs;
     float dq[4];
     dq[0] = 2.f * (-z * G[1] + y * G[2] + z * G[3] - x * G[5] - y * G[6] + x * G[7]);
     dq[1] = 2.f * (y * G[1] + z * G[2] + y * G[3] - 2.f * x * G[4] - w * G[5] + z * G[6] + w * G[7] -
@@ -500,9 +503,9 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
     const bool ow = overwrite != 0;
     auto put = [ow](float *g, float v) { *g = ow ? v : *g + v; };
     if (sd.g_mean) {
-        put(sd.g_mean + i, (float)dmu[0]);
-        put(sd.g_mean + n + i, (float)dmu[1]);
-        put(sd.g_mean + 2 * n + i, (float)dmu[2]);
+        put(sd.g_mean + i, dmu[0]);
+        put(sd.g_mean + n + i, dmu[1]);
+        put(sd.g_mean + 2 * n + i, dmu[2]);
     }
     if (sd.g_quat) {
         put(sd.g_quat + i, (dq[0] - w * dot) * inv);
@@ -511,8 +514,8 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
         put(sd.g_quat + 3 * n + i, (dq[3] - z * dot) * inv);
     }
     if (sd.g_scale) {
-        put(sd.g_scale + i, (float)dsu);
-        put(sd.g_scale + n + i, (float)dsv);
+        put(sd.g_scale + i, dsu);
+        put(sd.g_scale + n + i, dsv);
     }
     if (sd.g_opacity) put(sd.g_opacity + i, dsig);
     if (sd.g_color) {
