@@ -118,6 +118,16 @@ def test_fused_headline_views_match_oracle(rast):
     _fused_vs_oracle(rast, scenes.headline(), [0, 9], "headline v0,v9")
 
 
+def test_fused_config1_matches_oracle(rast):
+    """Config 1 (one 640x480 view, 300k surfels) at 16x16 and at the launches
+    the autotuner picks for it: 16x8 tiles with one wave per 8x8 block, and
+    8x8 tiles."""
+    _fused_vs_oracle(rast, scenes.config1(), [0], "config1",
+                     params=[_bench_params(rast),
+                             rast.params(tile=(16, 8), tile_order=1, tile_waves=2, overwrite=True),
+                             rast.params(tile=(8, 8), tile_order=1, overwrite=True)])
+
+
 def test_fused_config2_view_matches_oracle(rast):
     """Config 2 (16 x 512x384 over 1M shared surfels): view 3."""
     _fused_vs_oracle(rast, scenes.config2(), [3], "config2 v3")
