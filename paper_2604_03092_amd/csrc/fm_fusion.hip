@@ -48,35 +48,52 @@ __device__ __forceinline__ BlockPix block_pixels(int64_t b, int W, int H) {
     return bp;
 }
 
+// Depth and accumulation value of a block's pixel slots, all loaded at once
+// (slots past bp.n are not read).
+struct BlockVals {
+    float z[4], a[4];
+};
+
+__device__ __forceinline__ BlockVals block_vals(const BlockPix &bp, const float *__restrict__ z,
+                                                const float *__restrict__ accum) {
+    BlockVals v;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const bool ok = i < bp.n;
+        v.z[i] = ok ? z[bp.p[i]] : 0.f;
+        v.a[i] = ok && accum ? accum[bp.p[i]] : 0.f;
+    }
+    return v;
+}
+
 // merge decision and survivor count of a block; keep_mask bit i: pixel i is
-// kept on its own (unmerged blocks)
-__device__ __forceinline__ int block_count(const BlockPix &bp, const float *__restrict__ z,
-                                           const float *__restrict__ accum, float tau_d, float tau_a,
+// kept on its own (unmerged blocks); has_accum: an accumulation map gates
+__device__ __forceinline__ int block_count(int n, const BlockVals &v, bool has_accum, float tau_d, float tau_a,
                                            bool &merge, uint32_t &keep_mask) {
 #pragma clang fp contract(off)
-    float zmin = z[bp.p[0]], zmax = zmin;
-    for (int i = 1; i < bp.n; ++i) {
-        const float v = z[bp.p[i]];
-        zmin = fminf(zmin, v);
-        zmax = fmaxf(zmax, v);
+    float zmin = v.z[0], zmax = zmin;
+#pragma unroll
+    for (int i = 1; i < 4; ++i) {
+        if (i >= n) break;
+        zmin = fminf(zmin, v.z[i]);
+        zmax = fmaxf(zmax, v.z[i]);
     }
-    merge = bp.n > 1 && (zmax - zmin) <= tau_d;
+    merge = n > 1 && (zmax - zmin) <= tau_d;
     keep_mask = 0;
     if (merge) {
-        if (!accum) return 1;
-        float tot;
-        if (bp.n == 4)
-            tot = (accum[bp.p[0]] + accum[bp.p[1]]) + (accum[bp.p[2]] + accum[bp.p[3]]);
-        else
-            tot = accum[bp.p[0]] + accum[bp.p[1]];
-        return tot < tau_a * (float)bp.n ? 1 : 0;
+        if (!has_accum) return 1;
+        const float tot = n == 4 ? (v.a[0] + v.a[1]) + (v.a[2] + v.a[3]) : v.a[0] + v.a[1];
+        return tot < tau_a * (float)n ? 1 : 0;
     }
     int c = 0;
-    for (int i = 0; i < bp.n; ++i)
-        if (!accum || accum[bp.p[i]] < tau_a) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        if (i >= n) break;
+        if (!has_accum || v.a[i] < tau_a) {
             keep_mask |= 1u << i;
             ++c;
         }
+    }
     return c;
 }
 
@@ -140,7 +157,8 @@ __global__ __launch_bounds__(kFuseChunk) void k_fuse_count(const FrameDesc *__re
     if (b < NB) {
         bool merge;
         uint32_t km;
-        c = block_count(block_pixels(b, in.width, in.height), z, fr.accum, fp.tau_depth, fp.tau_accum, merge,
+        const BlockPix bp = block_pixels(b, in.width, in.height);
+        c = block_count(bp.n, block_vals(bp, z, fr.accum), fr.accum != nullptr, fp.tau_depth, fp.tau_accum, merge,
                         km);
     }
     // counts <= 4 * 1024 are exact in float
@@ -227,9 +245,23 @@ __global__ __launch_bounds__(kFuseChunk) void k_fuse_write(const FrameDesc *__re
     bool merge = false;
     uint32_t km = 0;
     int c = 0;
+    // every slot's surfel (13 floats) is loaded with the block's depths and
+    // gate values, before the scan, so that the loads overlap
+    float pv[4][13];
     if (b < NB) {
         bp = block_pixels(b, W, H);
-        c = block_count(bp, z, accum, fp.tau_depth, fp.tau_accum, merge, km);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            if (i >= bp.n) break;
+            const int64_t p = bp.p[i];
+            pv[i][0] = in.mean[p]; pv[i][1] = in.mean[P + p]; pv[i][2] = in.mean[2 * P + p];
+            pv[i][3] = in.quat[p]; pv[i][4] = in.quat[P + p]; pv[i][5] = in.quat[2 * P + p];
+            pv[i][6] = in.quat[3 * P + p];
+            pv[i][7] = in.scale[p]; pv[i][8] = in.scale[P + p];
+            pv[i][9] = in.opacity[p];
+            pv[i][10] = in.color[p]; pv[i][11] = in.color[P + p]; pv[i][12] = in.color[2 * P + p];
+        }
+        c = block_count(bp.n, block_vals(bp, z, accum), accum != nullptr, fp.tau_depth, fp.tau_accum, merge, km);
     }
     // block-wide exclusive scan of the counts
     const int lane = lane_id(), w = threadIdx.x >> 6;
@@ -247,15 +279,15 @@ __global__ __launch_bounds__(kFuseChunk) void k_fuse_write(const FrameDesc *__re
     if (merge) {
         float mu[3] = {0.f, 0.f, 0.f}, sc[2] = {0.f, 0.f}, col[3] = {0.f, 0.f, 0.f}, op = 0.f;
         float q[4] = {0.f, 0.f, 0.f, 0.f};
-        const float q0w = in.quat[bp.p[0]], q0x = in.quat[P + bp.p[0]], q0y = in.quat[2 * P + bp.p[0]],
-                    q0z = in.quat[3 * P + bp.p[0]];
-        for (int i = 0; i < bp.n; ++i) {
-            const int64_t p = bp.p[i];
-            for (int k = 0; k < 3; ++k) mu[k] += in.mean[k * P + p];
-            for (int k = 0; k < 2; ++k) sc[k] += in.scale[k * P + p];
-            for (int k = 0; k < 3; ++k) col[k] += in.color[k * P + p];
-            op += in.opacity[p];
-            const float qw = in.quat[p], qx = in.quat[P + p], qy = in.quat[2 * P + p], qz = in.quat[3 * P + p];
+        const float q0w = pv[0][3], q0x = pv[0][4], q0y = pv[0][5], q0z = pv[0][6];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            if (i >= bp.n) break;
+            for (int k = 0; k < 3; ++k) mu[k] += pv[i][k];
+            for (int k = 0; k < 2; ++k) sc[k] += pv[i][7 + k];
+            for (int k = 0; k < 3; ++k) col[k] += pv[i][10 + k];
+            op += pv[i][9];
+            const float qw = pv[i][3], qx = pv[i][4], qy = pv[i][5], qz = pv[i][6];
             const float d = (qw * q0w + qx * q0x) + (qy * q0y + qz * q0z);
             const float sg = d < 0.f ? -1.f : 1.f;
             q[0] += sg * qw; q[1] += sg * qx; q[2] += sg * qy; q[3] += sg * qz;
@@ -271,15 +303,16 @@ __global__ __launch_bounds__(kFuseChunk) void k_fuse_write(const FrameDesc *__re
         return;
     }
     uint32_t o = base;
-    for (int i = 0; i < bp.n; ++i) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        if (i >= bp.n) break;
         if (!((km >> i) & 1u)) continue;
-        const int64_t p = bp.p[i];
-        float mu[3] = {in.mean[p], in.mean[P + p], in.mean[2 * P + p]};
-        float q[4] = {in.quat[p], in.quat[P + p], in.quat[2 * P + p], in.quat[3 * P + p]};
-        float sc[2] = {in.scale[p], in.scale[P + p]};
-        const float col[3] = {in.color[p], in.color[P + p], in.color[2 * P + p]};
+        float mu[3] = {pv[i][0], pv[i][1], pv[i][2]};
+        float q[4] = {pv[i][3], pv[i][4], pv[i][5], pv[i][6]};
+        float sc[2] = {pv[i][7], pv[i][8]};
+        const float col[3] = {pv[i][10], pv[i][11], pv[i][12]};
         to_world(T, mu, q, sc);
-        if ((int64_t)o < out.capacity) put(out, o, mu, q, sc, in.opacity[p], col);
+        if ((int64_t)o < out.capacity) put(out, o, mu, q, sc, pv[i][9], col);
         ++o;
     }
 }
