@@ -98,7 +98,8 @@ def _fused_vs_oracle(rast, sc, views, tag, params=None, okw=None):
     plist = params if isinstance(params, list) else [params or _bench_params(rast)]
     res = []
     for p in plist:
-        t = f"{tag} {p.tile_w}x{p.tile_h}/order {p.tile_order}/waves {p.tile_waves}/depth {p.lds_depth}"
+        t = (f"{tag} {p.tile_w}x{p.tile_h}/order {p.tile_order}/waves {p.tile_waves}/depth {p.lds_depth}"
+             + ("/deterministic" if p.deterministic else ""))
         _say(f"{t}: fused batch of {gs.n_views} views")
         out, grads, dvm, loss, ws = _fused_masked(rast, gs, p, torch.from_numpy(mask).cuda())
         got = {k: x[..., torch.from_numpy(sel).cuda()] for k, x in out.items()}
@@ -114,8 +115,10 @@ def _fused_vs_oracle(rast, sc, views, tag, params=None, okw=None):
 
 def test_fused_headline_views_match_oracle(rast):
     """Headline batch (16 x 640x480, 300k surfels): views 0 and 9 carry the
-    loss; surfel and pose gradients of the timed kernel against the oracle."""
-    _fused_vs_oracle(rast, scenes.headline(), [0, 9], "headline v0,v9")
+    loss; surfel and pose gradients of the timed kernel against the oracle,
+    and of the same launch with deterministic sums."""
+    _fused_vs_oracle(rast, scenes.headline(), [0, 9], "headline v0,v9",
+                     params=[_bench_params(rast), _bench_params(rast, deterministic=True)])
 
 
 def test_fused_config1_matches_oracle(rast):
