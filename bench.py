@@ -523,9 +523,16 @@ def main():
     # so no clearing kernels run between steps
     tuned = None
     if args.tile == "auto":
-        tuned = tune_launch(rast, gs, args.deterministic)
+        from paper_2604_03092_amd import native
+        try:
+            tuned = tune_launch(rast, gs, args.deterministic)
+        except native.FmError as e:  # e.g. no candidate fits the device memory: keep the default launch
+            log(f"autotune failed ({e}); using 16x16, longest list first, one wave per tile, depth 64")
+    if tuned is not None:
         tw, th, order, waves, depth = tuned
         log(f"autotuned: {tw}x{th}, order {order}, waves {waves}, lds depth {depth}")
+    elif args.tile == "auto":
+        tw, th, order, waves, depth = 16, 16, 1, 1, 64
     else:
         tw, th = (int(x) for x in args.tile.split("x"))
         order, waves, depth = args.tile_order, args.tile_waves, args.lds_depth
@@ -714,7 +721,8 @@ def main():
                    "deterministic": bool(args.deterministic),
                    "tile_order": "longest list first" if order == 1 else "image order",
                    "waves_per_tile": "one per 8x8 block" if waves == 2 else "one per tile",
-                   "lds_depth": depth, "launch": "autotuned" if tuned else "given",
+                   "lds_depth": depth,
+                   "launch": "autotuned" if tuned else ("default (autotune failed)" if args.tile == "auto" else "given"),
                    "pairs": n_pairs},
         "views_per_s": round(views_s, 3),
         "plain": plain,
