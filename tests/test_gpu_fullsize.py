@@ -124,16 +124,20 @@ def test_fused_headline_views_match_oracle(rast):
 def test_fused_config1_matches_oracle(rast):
     """Config 1 (one 640x480 view, 300k surfels) at 16x16 and at the launches
     the autotuner picks for it: 16x8 tiles with one wave per 8x8 block, and
-    8x8 tiles."""
+    8x8 tiles at LDS depth 64 and 32."""
     _fused_vs_oracle(rast, scenes.config1(), [0], "config1",
                      params=[_bench_params(rast),
                              rast.params(tile=(16, 8), tile_order=1, tile_waves=2, overwrite=True),
-                             rast.params(tile=(8, 8), tile_order=1, overwrite=True)])
+                             rast.params(tile=(8, 8), tile_order=1, overwrite=True),
+                             rast.params(tile=(8, 8), tile_order=1, lds_depth=32, overwrite=True)])
 
 
 def test_fused_config2_view_matches_oracle(rast):
-    """Config 2 (16 x 512x384 over 1M shared surfels): view 3."""
-    _fused_vs_oracle(rast, scenes.config2(), [3], "config2 v3")
+    """Config 2 (16 x 512x384 over 1M shared surfels): view 3, at 16x16 and at
+    the autotuner's picks for this batch (16x16 and 32x32 in image order)."""
+    _fused_vs_oracle(rast, scenes.config2(), [3], "config2 v3",
+                     params=[_bench_params(rast), rast.params(tile=(16, 16), tile_order=2, overwrite=True),
+                             rast.params(tile=(32, 32), tile_order=2, overwrite=True)])
 
 
 def test_fused_config3_views_match_oracle(rast):
