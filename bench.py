@@ -38,6 +38,14 @@ OPS_PER_USEFUL = 32 + 2 * 4 + 90 + 3 * 4
 # gfx950: 256 CUs x 64 FP32 lanes x 2.4 GHz, one non-packed VALU op per lane per clock
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
+# The paper's own speed figures for the backend (appendix "Detailed Runtime
+# Breakdown", runtime table; one RTX 4090 with a Xeon 6133, the experimental
+# setup of Sec. 4).  Other hardware, and the keyframe count, resolution and
+# map size of its refine step are not stated: context only, never a target.
+PAPER_CONTEXT = dict(hardware="one RTX 4090 + Xeon 6133 (the paper's setup)",
+                     refine_ms_per_frame=77.0, refine_iterations_per_frame=20,
+                     refine_ms_per_iteration=77.0 / 20, merge_voxelization_ms_per_frame=0.5,
+                     loop_correction_ms=2.0)
 # HBM traffic of the blend kernel measured with rocprofv3 FETCH_SIZE / WRITE_SIZE
 # (scaled by a 1 GiB copy), valid while the kernel source is the one measured
 TRAFFIC_FILE = os.path.join(HERE, "profiles", "blend_traffic_headline.json")
@@ -742,6 +750,11 @@ def main():
         "refine": refine,
         "fusion": fusion,
         "warp": warp,
+        "paper_context": dict(PAPER_CONTEXT,
+                              this_refine_ms_per_iteration=refine["ms_per_iteration"] if refine else None,
+                              this_fusion_ms_per_frame=(round(fusion["ms_per_batch"] / fusion["frames"], 5)
+                                                        if fusion else None),
+                              this_warp_ms=warp["ms"] if warp else None),
     }
     if per_config is not None:
         res["per_config"] = per_config
