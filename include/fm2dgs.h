@@ -134,10 +134,12 @@ typedef struct {
                                partial and each entry sums its partials in emission
                                order, so gradients, the pose gradient and the loss are
                                bitwise reproducible; the workspace grows by
-                               4 + 80 * w bytes per pair of capacity (w = waves per
+                               4 + 81 * w bytes per pair of capacity (w = waves per
                                tile: 4 for 32x32, the 8x8 blocks of the tile with
-                               tile_waves 2, else 1) and a step costs one clear and
-                               one reduction pass over those partials.  Forward,
+                               tile_waves 2, else 1: a partial slot and a written
+                               flag per wave) and a step costs one clear of the
+                               flags and one reduction pass over the written
+                               partials.  Forward,
                                backward and fwd_bwd calls on one workspace must agree
                                on it.  Other values are INVALID_ARG.               */
     int32_t overwrite;      /* 0: surfel gradients, dL_dviewmat and the fused call's

@@ -324,6 +324,7 @@ fm_status build(fm_ctx *ctx, const fm_batch *b, const fm_raster_params *prm, int
     if (p.det) {  // per pair: its value, and one partial gradient slot per wave of the tile
         p.o_meta = take(4 * (size_t)max_pairs);
         p.o_part = take(4 * (size_t)fm::kGradStride * p.nq * (size_t)max_pairs);
+        p.o_pflag = take(align_up((size_t)p.nq * (size_t)max_pairs, 16));  // one byte per (pair, wave)
     }
     p.bytes = o;
     return FM_OK;

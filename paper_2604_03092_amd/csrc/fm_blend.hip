@@ -120,11 +120,14 @@ template <int TW_, int TH_, bool SPLIT_ = false, int DEPTH_ = 64> struct Geo {
 
 // Deterministic-gradient side of a pair list (meta == nullptr otherwise):
 // meta[emission index] = the pair's value, cap = pair capacity, part = the
-// partial gradient slots, one per (emission index, wave of the tile).
+// partial gradient slots, one per (emission index, wave of the tile), and
+// flag = one byte per slot, set when the wave has written the slot (slots
+// whose flag is clear are read as zero).
 struct PairMeta {
     const uint32_t *meta;
     uint32_t cap;
     float *part;
+    uint8_t *flag;
 };
 
 struct TileCtx {
@@ -414,13 +417,18 @@ __device__ __forceinline__ void tile_backward(const TileCtx &c, const Slots<G> &
             if (first) continue;  // no lane of the tile is hit by this surfel
             float r = wave_reduce16(gr);
             if (comp == 9) r *= __builtin_amdgcn_rcpf(s.sig);  // sigma dL/dsigma -> dL/dsigma
-            if (DET) {  // this wave's own partial slot of the pair (cleared beforehand)
-                float *dst = pm.part + ((int64_t)sj[j] * Gm::NQ + c.quad) * kp.gstride;
-                if (comp >= 0 && (HAS_N || comp < 14)) dst[comp] = r;
+            if (DET) {  // this wave's own partial slot of the pair, every float of it, then its flag
+                const int64_t slot = (int64_t)sj[j] * Gm::NQ + c.quad;
+                float *dst = pm.part + slot * kp.gstride;
+                if (comp >= 0) dst[comp] = r;  // without normal gradients 14 and 15 hold zeros
                 if (HAS_N) {
                     const float t2 = wave_sum(gn2);
-                    if (lane_id() == 0) dst[16] = t2;
+                    if (lane_id() == 0) {
+                        dst[16] = t2;
+                        dst[17] = dst[18] = dst[19] = 0.f;
+                    }
                 }
+                if (lane_id() == 0) pm.flag[slot] = 1;
             } else {
                 float *dst = grad + (int64_t)(sval[j] & kEntryMask) * kp.gstride;
                 if (comp >= 0 && (HAS_N || comp < 14)) atomicAdd(dst + comp, r);  // 14, 15: normal terms
@@ -716,6 +724,7 @@ PairMeta pair_meta(const Plan &p, void *ws) {
     pm.meta = p.det ? at<uint32_t>(ws, p.o_meta) : nullptr;
     pm.cap = (uint32_t)p.cap;
     pm.part = p.det ? at<float>(ws, p.o_part) : nullptr;
+    pm.flag = p.det ? at<uint8_t>(ws, p.o_pflag) : nullptr;
     return pm;
 }
 
@@ -791,13 +800,12 @@ hipError_t prune_t(const Plan &p, void *ws, const KParams &kp, const PruneArgs &
     return hipGetLastError();
 }
 
-// Deterministic gradients, step 1: zero the partial slots of the stored
-// pairs (n_pairs emission indices x nq waves x gs floats), since an adjoint
-// writes only the slots of pairs that hit one of its pixels.
-__global__ __launch_bounds__(256) void k_det_clear(float4 *__restrict__ part, const Status *st, int row4) {
-    const int64_t n = (int64_t)st->n_pairs * row4;
-    const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) part[i] = z;
+// Deterministic gradients, step 1: clear the slot flags of the stored pairs
+// (n_pairs emission indices x nq waves, one byte each, four per word), since
+// an adjoint writes only the slots of pairs that hit one of its pixels.
+__global__ __launch_bounds__(256) void k_det_clear(uint32_t *__restrict__ flag4, const Status *st, int nq) {
+    const int64_t n = ((int64_t)st->n_pairs * nq + 3) / 4;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) flag4[i] = 0u;
 }
 
 __device__ __forceinline__ void add4(float4 &a, const float4 &v) {
@@ -807,11 +815,13 @@ __device__ __forceinline__ void add4(float4 &a, const float4 &v) {
 // Step 2: four lanes per entry in depth order, one float4 of the slot each
 // (lane 0 also takes the fifth float4 of 20-float slots): the entry's pairs
 // are the emission indices [off32[r], off32[r + 1]) (the last entry's run
-// ends at n_pairs), so its partials are one contiguous block; they are summed
-// in index order, then wave order, and stored into the entry's gradient slot.
+// ends at n_pairs), so its partials are one contiguous block; the flagged
+// ones are summed in index order, then wave order, and stored into the
+// entry's gradient slot.
 __global__ __launch_bounds__(256) void k_det_reduce(const uint32_t *__restrict__ sorted_entry,
                                                      const uint32_t *__restrict__ off32, const Status *st,
-                                                     const float4 *__restrict__ part, int nq, int gs4,
+                                                     const float4 *__restrict__ part,
+                                                     const uint8_t *__restrict__ flag, int nq, int gs4,
                                                      float4 *__restrict__ grad) {
     const uint32_t nv = st->n_vis, np = st->n_pairs;
     const int c4 = threadIdx.x & 3;
@@ -827,19 +837,27 @@ __global__ __launch_bounds__(256) void k_det_reduce(const uint32_t *__restrict__
         int64_t k = (int64_t)j0 * nq;
         float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a;
         for (; k + 4 <= k1; k += 4) {
+            bool f[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) f[u] = flag[k + u] != 0;
             float4 v[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) v[u] = part[(k + u) * gs4 + c4];
+            for (int u = 0; u < 4; ++u)
+                if (f[u]) v[u] = part[(k + u) * gs4 + c4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) add4(a, v[u]);
+            for (int u = 0; u < 4; ++u)
+                if (f[u]) add4(a, v[u]);
             if (fifth) {
 #pragma unroll
-                for (int u = 0; u < 4; ++u) v[u] = part[(k + u) * gs4 + 4];
+                for (int u = 0; u < 4; ++u)
+                    if (f[u]) v[u] = part[(k + u) * gs4 + 4];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) add4(b, v[u]);
+                for (int u = 0; u < 4; ++u)
+                    if (f[u]) add4(b, v[u]);
             }
         }
         for (; k < k1; ++k) {
+            if (flag[k] == 0) continue;
             add4(a, part[k * gs4 + c4]);
             if (fifth) add4(b, part[k * gs4 + 4]);
         }
@@ -897,12 +915,12 @@ hipError_t launch_render_prune(const Plan &p, void *ws, const KParams &kp, const
 }
 
 hipError_t launch_det_clear(const Plan &p, void *ws, int gstride, hipStream_t st) {
+    (void)gstride;
     if (!p.det) return hipSuccess;
-    const int row4 = p.nq * gstride / 4;
-    const int64_t n4 = p.cap * row4;
-    const int blocks = (int)std::min<int64_t>((n4 + 255) / 256, 8192);
-    hipLaunchKernelGGL(k_det_clear, dim3(blocks), dim3(256), 0, st, at<float4>(ws, p.o_part),
-                       at<Status>(ws, p.o_status), row4);
+    const int64_t n4 = (p.cap * p.nq + 3) / 4;
+    const int blocks = (int)std::min<int64_t>((n4 + 255) / 256, 2048);
+    hipLaunchKernelGGL(k_det_clear, dim3(blocks), dim3(256), 0, st, at<uint32_t>(ws, p.o_pflag),
+                       at<Status>(ws, p.o_status), p.nq);
     return hipGetLastError();
 }
 
@@ -912,7 +930,8 @@ hipError_t launch_det_reduce(const Plan &p, void *ws, int gstride, hipStream_t s
     // pair offsets in the key buffer
     const int blocks = (int)std::min<int64_t>((p.E + 63) / 64, 16384);
     hipLaunchKernelGGL(k_det_reduce, dim3(blocks), dim3(256), 0, st, at<uint32_t>(ws, p.o_val),
-                       at<uint32_t>(ws, p.o_key), at<Status>(ws, p.o_status), at<float4>(ws, p.o_part), p.nq,
+                       at<uint32_t>(ws, p.o_key), at<Status>(ws, p.o_status), at<float4>(ws, p.o_part),
+                       at<uint8_t>(ws, p.o_pflag), p.nq,
                        gstride / 4, at<float4>(ws, p.o_grad));
     return hipGetLastError();
 }

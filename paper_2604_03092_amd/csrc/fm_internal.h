@@ -158,11 +158,12 @@ struct Plan {
            o_key2 = 0, o_val = 0, o_val2 = 0, o_scan = 0, o_pkey = 0, o_pval = 0, o_pkey2 = 0,
            o_pval2 = 0, o_hist = 0, o_tstart = 0, o_tend = 0, o_tfinal = 0, o_nlast = 0, o_ncount = 0, o_grad = 0,
            o_pose = 0, o_loss = 0, o_tot = 0, o_ell = 0, o_chunk = 0, o_meta = 0, o_part = 0,
-           o_torder = 0, o_emeta = 0, o_tbucket = 0, o_cnt2 = 0, o_cnt3 = 0;
+           o_torder = 0, o_emeta = 0, o_tbucket = 0, o_cnt2 = 0, o_cnt3 = 0, o_pflag = 0;
     size_t bytes = 0;
     // deterministic gradients: the sorted lists hold emission indices, o_meta
     // maps them to pair values, and the adjoint writes one partial slot per
-    // (pair, wave of the tile) at o_part, summed per entry in emission order
+    // (pair, wave of the tile) at o_part and sets its byte at o_pflag; the
+    // flagged slots are summed per entry in emission order
     bool det = false;
     bool overwrite = false;  // store (not add) surfel gradients, pose gradients and the loss
     bool lpt = true;         // blend takes tiles longest list first (else image order)
