@@ -419,7 +419,7 @@ fm_status run_forward(fm_ctx *ctx, Built &bt, const fm_raster_params *prm, const
     FM_TRY_HIP(fm::launch_preprocess(bt.plan, ws, kp, b->intr, b->viewmat, false, st), "preprocess");
     mark(ctx, st, PH_PRE);
     rg.phase("fm2dgs/binning");
-    FM_TRY_HIP(fm::launch_binning(bt.plan, ws, kp, st), "binning");
+    FM_TRY_HIP(fm::launch_binning(bt.plan, ws, st), "binning");
     mark(ctx, st, PH_BIN);
     rg.phase("fm2dgs/blend");
     FM_TRY_HIP(fm::launch_render_fwd(bt.plan, ws, kp, out, st), "render_fwd");
@@ -446,7 +446,7 @@ fm_status run_fused(fm_ctx *ctx, Built &bt, const fm_raster_params *prm, const f
     FM_TRY_HIP(fm::launch_preprocess(bt.plan, ws, kp, b->intr, b->viewmat, !bt.plan.det, st), "preprocess");
     mark(ctx, st, PH_PRE);
     rg.phase("fm2dgs/binning");
-    FM_TRY_HIP(fm::launch_binning(bt.plan, ws, kp, st), "binning");
+    FM_TRY_HIP(fm::launch_binning(bt.plan, ws, st), "binning");
     if (bt.plan.det) FM_TRY_HIP(fm::launch_det_clear(bt.plan, ws, kp.gstride, st), "det_clear");
     mark(ctx, st, PH_BIN);
     rg.phase("fm2dgs/blend");
@@ -800,7 +800,7 @@ fm_status fm_prune_scores(fm_ctx *ctx, const fm_batch *b, const fm_raster_params
     FM_TRY_HIP(fm::launch_preprocess(bt.plan, ws, kp, b->intr, b->viewmat, true, st), "preprocess");
     mark(ctx, st, PH_PRE);
     rg.phase("fm2dgs/binning");
-    FM_TRY_HIP(fm::launch_binning(bt.plan, ws, kp, st), "binning");
+    FM_TRY_HIP(fm::launch_binning(bt.plan, ws, st), "binning");
     mark(ctx, st, PH_BIN);
     rg.phase("fm2dgs/blend");
     FM_TRY_HIP(fm::launch_render_prune(bt.plan, ws, kp, pa, out, st), "render_prune");

@@ -220,7 +220,7 @@ hipError_t launch_setup(const Plan &p, void *ws, const ViewDesc *views, const Su
 constexpr int kProjViewsPerThread = 4;
 hipError_t launch_preprocess(const Plan &p, void *ws, const KParams &kp, const float *intr,
                              const float *viewmat, bool zero_grad, hipStream_t st);
-hipError_t launch_binning(const Plan &p, void *ws, const KParams &kp, hipStream_t st);
+hipError_t launch_binning(const Plan &p, void *ws, hipStream_t st);
 hipError_t launch_render_fwd(const Plan &p, void *ws, const KParams &kp, const fm_outputs &out,
                              hipStream_t st);
 hipError_t launch_render_bwd(const Plan &p, void *ws, const KParams &kp, const fm_outputs &out,

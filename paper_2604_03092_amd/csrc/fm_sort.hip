@@ -457,7 +457,7 @@ template <int TW, int TH>
 __global__ __launch_bounds__(256) void k_emit(const uint32_t *__restrict__ sorted_entry,
                                                const uint32_t *__restrict__ off32, const uint32_t *n_vis,
                                                const uint32_t *__restrict__ chunk_first, const Status *st,
-                                               const Ell *__restrict__ ell, KParams kp,
+                                               const Ell *__restrict__ ell,
                                                uint32_t *__restrict__ pkey, uint32_t *__restrict__ pval,
                                                uint32_t *__restrict__ hist, int G,
                                                uint32_t *__restrict__ meta) {
@@ -651,7 +651,7 @@ void radix_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32
 
 }  // namespace
 
-hipError_t launch_binning(const Plan &p, void *ws, const KParams &kp, hipStream_t st) {
+hipError_t launch_binning(const Plan &p, void *ws, hipStream_t st) {
     Status *status = at<Status>(ws, p.o_status);
     uint32_t *key = at<uint32_t>(ws, p.o_key), *key2 = at<uint32_t>(ws, p.o_key2);
     uint32_t *val = at<uint32_t>(ws, p.o_val), *val2 = at<uint32_t>(ws, p.o_val2);
@@ -693,7 +693,7 @@ hipError_t launch_binning(const Plan &p, void *ws, const KParams &kp, hipStream_
                        (uint64_t)p.cap, off32, chunk_first);
 #define FM_EMIT(TW, TH)                                                                                        \
     hipLaunchKernelGGL((k_emit<TW, TH>), dim3(p.emit_blocks), dim3(256), 0, st, val, off32, n_vis, chunk_first,   \
-                       status, at<Ell>(ws, p.o_ell), kp, pkey, pval, hist, p.sortG_p,                \
+                       status, at<Ell>(ws, p.o_ell), pkey, pval, hist, p.sortG_p,                    \
                        p.det ? at<uint32_t>(ws, p.o_meta) : nullptr)
     if (p.tile_w == 16 && p.tile_h == 16) FM_EMIT(16, 16);
     else if (p.tile_w == 8 && p.tile_h == 8) FM_EMIT(8, 8);
