@@ -165,3 +165,33 @@ def test_fusion_batch_errors(rast):
     poses[1] = native.FmSim3(-1.0, (ctypes.c_float * 4)(*f.q), (ctypes.c_float * 3)(*f.t))
     assert call(rast.ctx, maps, poses, 2, ctypes.byref(fp), None, buf, _ptr(offs), _ptr(ws), need,
                 None) == native.FM_ERR_INVALID_ARG
+
+
+def test_fusion_full_size_batch_matches_oracle(rast):
+    """The benchmark's workload: one fm_voxelize_fuse_batch over 32 per-pixel
+    maps of 518x392 with accumulation gates (tau_depth 0.05, gate 0.5);
+    frames 0, 17 and 31 of the batch against the oracle (counts and order
+    exact, values to float32 rounding), the offsets against the counts."""
+    w, h, n_frames = 518, 392, 32
+    print("fusion batch 32 x 518x392", flush=True)
+    frames = scenes.fusion_frames(n_frames, w, h)
+    dev = [_dev(f.planes) for f in frames]
+    gates = [torch.from_numpy(f.accum).cuda() for f in frames]
+    fb = FusionBatch(rast, [(w, h)] * n_frames)
+    off = fb.run([(d, f.s, f.q, f.t) for d, f in zip(dev, frames)], 0.05, gates, 0.5)
+    torch.cuda.synchronize()
+    off = off.cpu().numpy()
+    assert off[0] == 0 and np.all(np.diff(off) >= 0)
+    for i in (0, 17, 31):
+        f = frames[i]
+        print(f"fusion oracle frame {i}", flush=True)
+        ref = fusion.voxelize_fuse(w, h, f.planes, float(np.float32(f.s)), f.q.astype(np.float64),
+                                   f.t.astype(np.float64), float(np.float32(0.05)), f.accum,
+                                   float(np.float32(0.5)))
+        n = ref["opacity"].size
+        assert off[i + 1] - off[i] == n, (i, off[i + 1] - off[i], n)
+        for k in PLANES:
+            want = ref[k].reshape(-1, n)
+            got = fb.out[k][:, off[i]:off[i + 1]].reshape(-1, n).cpu().numpy().astype(np.float64)
+            tol = 2e-6 * (np.abs(want) + (1.0 if k == "mean" else 0.0) * 6.0) + 1e-7
+            assert np.all(np.abs(got - want) <= tol), (i, k, np.max(np.abs(got - want) - tol))

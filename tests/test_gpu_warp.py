@@ -83,3 +83,42 @@ def test_warp_wrapper_matches_oracle(rast):
     np.testing.assert_allclose(got["mean"], ref["mean"], rtol=2e-6, atol=2e-5)
     np.testing.assert_allclose(got["quat"], ref["quat"], rtol=2e-6, atol=2e-6)
     np.testing.assert_allclose(got["scale"], ref["scale"], rtol=2e-6)
+
+
+def test_warp_full_size_sampled(rast):
+    """The benchmark's size: 16M primitives bound to 64 keyframes (and a
+    share unbound), warped in one launch; 200k sampled primitives against the
+    oracle, computed on the sample alone (the warp is elementwise)."""
+    n, K = 16_000_000, 64
+    print(f"warp n={n} K={K}", flush=True)
+    rng = np.random.default_rng(16064)
+    q = rng.normal(size=(4, n)).astype(np.float32)
+    q /= np.maximum(np.linalg.norm(q, axis=0), 1e-12)
+    planes = dict(mean=rng.normal(0, 3, (3, n)).astype(np.float32), quat=q,
+                  scale=rng.uniform(0.01, 0.1, (2, n)).astype(np.float32))
+    kf = rng.integers(-1, K + 1, n).astype(np.int32)
+    arr = (native.FmSim3 * K)()
+    deltas = []
+    for k in range(K):
+        qq = rng.normal(size=4)
+        s, t = float(rng.uniform(0.8, 1.2)), rng.normal(0, 1, 3)
+        arr[k] = native.FmSim3(s, (ctypes.c_float * 4)(*qq), (ctypes.c_float * 3)(*t))
+        deltas.append((float(np.float32(s)), qq.astype(np.float32).astype(np.float64),
+                       t.astype(np.float32).astype(np.float64)))
+    dev = {k: torch.from_numpy(v).cuda() for k, v in planes.items()}
+    kf_d = torch.from_numpy(kf).cuda()
+    d_d = torch.frombuffer(bytearray(bytes(arr)), dtype=torch.uint8).cuda()
+    rast.check(rast.lib.fm_warp_keyframes(rast.ctx, _ptr(dev["mean"]), _ptr(dev["quat"]), _ptr(dev["scale"]),
+                                          _ptr(kf_d), n, _ptr(d_d), K, None))
+    torch.cuda.synchronize()
+    idx = np.sort(rng.choice(n, 200_000, replace=False))
+    sub = {k: np.ascontiguousarray(v[:, idx]) for k, v in planes.items()}
+    ref = warp.warp(sub, kf[idx], deltas)
+    idx_d = torch.from_numpy(idx).cuda()
+    got = {k: v[:, idx_d].cpu().numpy().astype(np.float64) for k, v in dev.items()}
+    np.testing.assert_allclose(got["mean"], ref["mean"], rtol=2e-6, atol=2e-5)
+    np.testing.assert_allclose(got["quat"], ref["quat"], rtol=2e-6, atol=2e-6)
+    np.testing.assert_allclose(got["scale"], ref["scale"], rtol=2e-6)
+    unbound = (kf[idx] < 0) | (kf[idx] >= K)
+    for k in planes:
+        np.testing.assert_array_equal(got[k][:, unbound], sub[k][:, unbound].astype(np.float64))
