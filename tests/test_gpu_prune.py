@@ -194,3 +194,28 @@ def test_prune_scores_argument_errors(rast):
                                   native.FmOutputs(*(out[k].data_ptr() for k in ("rgb", "depth", "normal", "alpha"))),
                                   arr, ctypes.c_void_p(ws.buf.data_ptr()), ws.nbytes, ws.max_pairs, None)
     assert st == native.FM_ERR_INVALID_ARG
+
+
+def test_scores_match_oracle_headline(rast):
+    """Scores over the whole headline batch (16 x 640x480, 300k surfels) with
+    the oracle's error flags of views 0 and 9 as the mask (the other views'
+    pixels unflagged): the GPU's per-surfel sums of alpha T against the
+    oracle's over those two views."""
+    sc = scenes.headline()
+    gs = GpuScene.from_scene(sc)
+    views = [0, 9]
+    _say("prune headline: oracle forward of views 0 and 9")
+    ref = oracle.render_scene(sc, views=views)
+    sel = np.concatenate([np.arange(sc.pixel_offsets[v], sc.pixel_offsets[v] + sc.view_pixels(v)) for v in views])
+    want = oprune.error_mask(ref["rgb"], ref["depth"], sc.target_rgb[:, sel], None, 0.3) & ~ref["flags"]
+    assert 0.05 < want.mean() < 0.95
+    full = np.zeros(sc.total_pixels, np.uint8)
+    full[sel] = want
+    scores, flags, _, _ = prune_scores(rast, gs, rast.params(), mask=torch.from_numpy(full).cuda())
+    torch.cuda.synchronize()
+    assert np.array_equal(flags.cpu().numpy().astype(np.uint8), full)
+    _say("prune headline: oracle scores")
+    ref_scores = oprune.contribution_scores(sc, want, views=views)
+    got = to_np(scores[0])
+    assert_grad_close(got, ref_scores[0], "headline score")
+    _say(f"scores headline: {int((got > 0).sum())} surfels scored")
