@@ -9,7 +9,7 @@ import torch
 
 from oracle import optim
 from paper_2604_03092_amd import native, scenes
-from paper_2604_03092_amd.raster import Adam, GpuScene, Rasterizer, _ptr
+from paper_2604_03092_amd.raster import ADAM_KINDS, Adam, GpuScene, Rasterizer, _ptr
 
 pytestmark = pytest.mark.gpu
 
@@ -178,3 +178,46 @@ def test_refine_loop_in_one_graph(rast):
     for sm in gs.submaps:
         assert torch.isfinite(sm["mean"]).all() and torch.isfinite(sm["color"]).all()
         assert (sm["opacity"] > 0).all() and (sm["opacity"] < 1).all() and (sm["scale"] > 0).all()
+
+
+def test_adam_full_size_chain(rast):
+    """The refine loop's optimizer at full size: Adam over every tensor of
+    the 300k-surfel scene (3.9M parameters in five tensors, the three
+    parameter kinds) through the same binding the refine loop uses, three
+    consecutive steps with seeded gradients (a third of the surfels get
+    none, as unseen surfels do), each compared element by element with the
+    oracle's chain of three steps from the same initial state.  The bounds
+    grow with the step number: every step adds one step's FP32 rounding."""
+    sc = scenes.config1()
+    gs = GpuScene.from_scene(sc)
+    grads, _ = gs.zero_grads()
+    adam = Adam(rast, gs, grads)
+    rng = np.random.default_rng(2024)
+    f32 = lambda x: float(np.float32(x))
+    state = {k: (sc.submaps[0][k].astype(np.float64), 0.0, 0.0, 0.0, 0.0) for k in gs.submaps[0]}
+    n = gs.submaps[0]["opacity"].numel()
+    for t in range(1, 4):
+        _say(f"adam full size step {t}")
+        seen = rng.random(n) < 2.0 / 3.0
+        gnp = {}
+        for k, gt in grads[0].items():
+            g = rng.normal(0, 1, gt.shape) * 10.0 ** rng.uniform(-6, -1, gt.shape)
+            g = (g * seen).astype(np.float32)
+            gt.copy_(torch.from_numpy(g))
+            gnp[k] = g
+        adam.step()
+        torch.cuda.synchronize()
+        for k, (p0, m0, v0, sm0, sv0) in state.items():
+            kind = int(ADAM_KINDS[k])
+            p1, m1, v1 = optim.adam_step(p0, gnp[k].astype(np.float64), m0, v0, t, f32(adam.lr[k]), kind,
+                                         beta1=f32(0.9), beta2=f32(0.999), eps=f32(1e-8))
+            _, gth = optim.to_theta(p0, gnp[k], kind)
+            sm1 = 0.9 * sm0 + 0.1 * np.abs(gth)
+            sv1 = 0.999 * sv0 + 0.001 * gth * gth
+            gp, gm, gv = (x[0][k].cpu().numpy() for x in (gs.submaps, adam.m, adam.v))
+            dp = np.abs(gp - p1) - t * (2e-6 * np.abs(p1) + 1e-5 * adam.lr[k])
+            assert dp.max() <= 0, (k, t, float(dp.max()))
+            assert np.all(np.abs(gm - m1) <= 4e-6 * t * sm1 + 1e-30), (k, t)
+            assert np.all(np.abs(gv - v1) <= 4e-6 * t * sv1 + 1e-30), (k, t)
+            state[k] = (p1, m1, v1, sm1, sv1)
+    assert int(adam.step_count.item()) == 3
