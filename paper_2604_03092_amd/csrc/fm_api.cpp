@@ -301,7 +301,7 @@ fm_status build(fm_ctx *ctx, const fm_batch *b, const fm_raster_params *prm, int
     p.o_key2 = take(4 * (size_t)E);
     p.o_val = take(4 * (size_t)E);
     p.o_val2 = take(4 * (size_t)E);
-    p.o_scan = take(4 * align_up(p.scan_blocks, 64) + 8 * (size_t)p.scan_blocks);
+    p.o_scan = take(4 * align_up(p.scan_blocks, 64));
     p.o_pkey = take(4 * (size_t)max_pairs);
     p.o_pval = take(4 * (size_t)max_pairs);
     p.o_pkey2 = take(4 * (size_t)max_pairs);

@@ -703,8 +703,18 @@ __global__ __launch_bounds__(64) void k_render_prune(const ViewDesc *__restrict_
 __global__ __launch_bounds__(1024) void k_loss_reduce(const float *__restrict__ part, int64_t n,
                                                        float *__restrict__ loss, int overwrite) {
     __shared__ float red[16];
+    // a thread sums its partials in index order; eight loads are issued
+    // before they are added
     float s = 0.f;
-    for (int64_t i = threadIdx.x; i < n; i += 1024) s += part[i];
+    int64_t i = threadIdx.x;
+    for (; i + 7 * 1024 < n; i += 8 * 1024) {
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = part[i + u * 1024];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; i < n; i += 1024) s += part[i];
     s = wave_sum(s);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
     __syncthreads();

@@ -312,44 +312,20 @@ __global__ __launch_bounds__(256) void k_count_reduce(const uint32_t *__restrict
     const int64_t lo = (int64_t)blockIdx.x * kScanChunk;
     int64_t hi = lo + kScanChunk;
     if (hi > E) hi = E;
+    // all of a thread's loads are issued before they are added
+    uint32_t c[kScanChunk / 256];
+#pragma unroll
+    for (int u = 0; u < kScanChunk / 256; ++u) {
+        const int64_t k = lo + threadIdx.x + u * 256;
+        c[u] = k < hi ? cnt_sorted[k] : 0u;
+    }
     uint32_t s = 0;
-    for (int64_t k = lo + threadIdx.x; k < hi; k += 256) s += cnt_sorted[k];
+#pragma unroll
+    for (int u = 0; u < kScanChunk / 256; ++u) s += c[u];
     for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
     if (lane_id() == 0) red[threadIdx.x >> 6] = s;
     __syncthreads();
     if (threadIdx.x == 0) blk[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
-}
-
-// Exclusive scan of the block sums into 64-bit block offsets; the total is
-// the number of pairs the batch needs.
-__global__ __launch_bounds__(1024) void k_count_scan(const uint32_t *__restrict__ blk, int nb,
-                                                      uint64_t *__restrict__ blk_off, Status *st,
-                                                      uint64_t cap) {
-    __shared__ uint64_t part[1024];
-    const int per = (nb + 1023) / 1024;
-    const int beg = threadIdx.x * per;
-    const int end = beg + per < nb ? beg + per : nb;
-    uint64_t s = 0;
-    for (int i = beg; i < end; ++i) s += blk[i];
-    part[threadIdx.x] = s;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        uint64_t v = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0ull;
-        __syncthreads();
-        part[threadIdx.x] += v;
-        __syncthreads();
-    }
-    uint64_t run = threadIdx.x ? part[threadIdx.x - 1] : 0ull;
-    for (int i = beg; i < end; ++i) {
-        blk_off[i] = run;
-        run += blk[i];
-    }
-    if (threadIdx.x == 1023) {
-        const uint64_t total = part[1023];
-        st->required = total;
-        st->overflow = total > cap ? 1u : 0u;
-        st->n_pairs = (uint32_t)(total > cap ? cap : total);
-    }
 }
 
 // Which 8x8 pixel blocks (16x16 quadrants of a 32x32 tile) of the tile with
@@ -393,6 +369,11 @@ template <int TW, int TH> __device__ inline uint32_t block_mask(const Ell &el, i
 // emission chunk.  Block b owns sorted entries [b*kScanChunk, ...), thread t
 // the kPer consecutive ones from b*kScanChunk + t*kPer; the exclusive scan of
 // their tile counts, plus the block's offset, gives each entry's first pair.
+// The block's offset is the sum of the block sums of blocks 0 .. b-1, which
+// every block forms itself (64-bit); the block holding the last visible
+// entry also records the batch's pair count, whether it exceeds the
+// capacity, and the pairs stored (a batch without visible entries keeps the
+// cleared status: no pairs).
 // Offsets are clamped to the capacity (pairs beyond it are never emitted).
 // Every entry that holds the first pair of a chunk of kEmitChunk pairs writes
 // its sorted index into chunk_first.  Visible entries cover at least one
@@ -401,13 +382,21 @@ template <int TW, int TH> __device__ inline uint32_t block_mask(const Ell &el, i
 // same positions.
 constexpr int kPer = kScanChunk / 256;
 __global__ __launch_bounds__(256) void k_offsets(const uint32_t *cnt_sorted, const uint32_t *n_vis,
-                                                  const uint64_t *__restrict__ blk_off, uint64_t cap,
+                                                  const uint32_t *__restrict__ blk, Status *st, uint64_t cap,
                                                   uint32_t *off32, uint32_t *__restrict__ chunk_first) {
     __shared__ uint32_t wsum[4];
+    __shared__ uint64_t wpre[4];
     const int64_t E = *n_vis;
     const int64_t lo = (int64_t)blockIdx.x * kScanChunk;
     if (lo >= E) return;
     const int w = threadIdx.x >> 6, lane = lane_id();
+    uint64_t pre = 0;
+    for (int i = (int)threadIdx.x; i < (int)blockIdx.x; i += 256) pre += blk[i];
+    for (int off = 32; off > 0; off >>= 1) {
+        const uint32_t l32 = __shfl_xor((uint32_t)pre, off), h32 = __shfl_xor((uint32_t)(pre >> 32), off);
+        pre += ((uint64_t)h32 << 32) | l32;
+    }
+    if (lane == 0) wpre[w] = pre;
     const int64_t k0 = lo + (int64_t)threadIdx.x * kPer;
     uint32_t c[kPer];
 #pragma unroll
@@ -422,7 +411,14 @@ __global__ __launch_bounds__(256) void k_offsets(const uint32_t *cnt_sorted, con
     }
     if (lane == 63) wsum[w] = x;
     __syncthreads();
-    uint64_t o = blk_off[blockIdx.x] + (x - run);
+    const uint64_t base = wpre[0] + wpre[1] + wpre[2] + wpre[3];
+    if (threadIdx.x == 0 && E - lo <= kScanChunk) {
+        const uint64_t total = base + (uint64_t)wsum[0] + wsum[1] + wsum[2] + wsum[3];
+        st->required = total;
+        st->overflow = total > cap ? 1u : 0u;
+        st->n_pairs = (uint32_t)(total > cap ? cap : total);
+    }
+    uint64_t o = base + (x - run);
     for (int j = 0; j < w; ++j) o += wsum[j];
 #pragma unroll
     for (int i = 0; i < kPer; ++i) {
@@ -678,18 +674,15 @@ hipError_t launch_binning(const Plan &p, void *ws, hipStream_t st) {
     radix_pass(key2, val2, key, val, n_vis, 0, 24, hist, p.sortG_e, tot + 3 * kRadix, 0, nullptr, st, 2, ca);
     // 2. pair offsets in depth order and emission
     uint32_t *blk = at<uint32_t>(ws, p.o_scan);
-    uint64_t *blk_off = reinterpret_cast<uint64_t *>(blk + ((p.scan_blocks + 63) & ~63));
     // the key buffer holds the counts in depth order
     uint32_t *cnt_sorted = key;
     hipLaunchKernelGGL(k_count_reduce, dim3(p.scan_blocks), dim3(256), 0, st, cnt_sorted, n_vis, blk);
-    hipLaunchKernelGGL(k_count_scan, dim3(1), dim3(1024), 0, st, blk, p.scan_blocks, blk_off, status,
-                       (uint64_t)p.cap);
     uint32_t *pkey = at<uint32_t>(ws, p.o_pkey), *pval = at<uint32_t>(ws, p.o_pval);
     uint32_t *pkey2 = at<uint32_t>(ws, p.o_pkey2), *pval2 = at<uint32_t>(ws, p.o_pval2);
     // the offsets replace the counts in place
     uint32_t *off32 = key;
     uint32_t *chunk_first = at<uint32_t>(ws, p.o_chunk);
-    hipLaunchKernelGGL(k_offsets, dim3(p.scan_blocks), dim3(256), 0, st, cnt_sorted, n_vis, blk_off,
+    hipLaunchKernelGGL(k_offsets, dim3(p.scan_blocks), dim3(256), 0, st, cnt_sorted, n_vis, blk, status,
                        (uint64_t)p.cap, off32, chunk_first);
 #define FM_EMIT(TW, TH)                                                                                        \
     hipLaunchKernelGGL((k_emit<TW, TH>), dim3(p.emit_blocks), dim3(256), 0, st, val, off32, n_vis, chunk_first,   \
