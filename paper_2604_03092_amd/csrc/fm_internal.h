@@ -84,14 +84,16 @@ static_assert(sizeof(Rec) == 80, "record layout");
 // derived values in FP32).  The entry's tile rect (from the canonical inclusive
 // pixel-centre bbox) rides along: tb is the batch-global id of its top-left
 // tile, t0 = tx0 | ty0 << 16 that tile's position in the view,
-// nt = (tiles per rect row) | (tiles_x of the view) << 16.
-struct alignas(16) Ell {
+// nt = (tiles per rect row) | (tiles_x of the view) << 16.  Padded to 64
+// bytes: the emission gathers the structs in depth order, and a 64-byte
+// aligned struct never straddles two 128-byte cache lines.
+struct alignas(64) Ell {
     float ex, ey, hx, hy;
     float k1, k2, dyr;
     uint32_t tb;
-    uint32_t t0, nt, pad[2];
+    uint32_t t0, nt, pad[6];
 };
-static_assert(sizeof(Ell) == 48, "ellipse layout");
+static_assert(sizeof(Ell) == 64, "ellipse layout");
 
 // Pair values: entry id in the low 28 bits, 8x8-block mask of the tile in the
 // high 4 bits (bit b set when block b of the tile may hold a covered pixel);

@@ -270,7 +270,7 @@ __global__ __launch_bounds__(256) void k_preprocess(const SubmapDesc *__restrict
                                 el.k1 = f11 > 0.f ? f01 / f11 : 0.f;
                                 el.k2 = f11 > 0.f && fdet > 0.f ? (fdet / f11) / f11 : 0.f;
                                 el.dyr = el.hx > 0.f ? f01 / el.hx : 0.f;
-                                el.pad[0] = el.pad[1] = 0u;
+                                for (int k = 0; k < 6; ++k) el.pad[k] = 0u;
                                 const int tx0 = px0 / kp.tile_w, tx1 = px1 / kp.tile_w;
                                 const int ty0 = py0 / kp.tile_h;
                                 el.tb = (uint32_t)(vd.tile_base + ty0 * vd.tiles_x + tx0);

@@ -522,7 +522,14 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t *__restrict__ sorte
                 if (i >= n_ent) i = 0;  // cannot happen; keeps the LDS read in range
                 const uint32_t ent = s_ent[i];
                 const uint32_t r = p0 + q - s_off[i];
-                const Ell el = ell[ent];
+                Ell el;  // the first 48 bytes (the padding is not read)
+                {
+                    const float4 *q = reinterpret_cast<const float4 *>(ell + ent);
+                    const float4 a = q[0], b = q[1], c4 = q[2];
+                    el.ex = a.x; el.ey = a.y; el.hx = a.z; el.hy = a.w;
+                    el.k1 = b.x; el.k2 = b.y; el.dyr = b.z; el.tb = __float_as_uint(b.w);
+                    el.t0 = __float_as_uint(c4.x); el.nt = __float_as_uint(c4.y);
+                }
                 const uint32_t ntx = el.nt & 0xFFFFu, tiles_x = el.nt >> 16;
                 // r / ntx: r < 2^24, so the float estimate is off by at most one
                 uint32_t ry = (uint32_t)((float)r * __builtin_amdgcn_rcpf((float)ntx));
