@@ -538,22 +538,12 @@ __global__ __launch_bounds__(1024) void k_pose_reduce(const ViewDesc *__restrict
 #pragma unroll
     for (int k = 0; k < 16; ++k) acc[k] = 0.f;
     const float4 *base = reinterpret_cast<const float4 *>(pose_part + (int64_t)v * max_blocks * 4 * 12);
-    // a thread adds its partials in index order; the loads of two are
-    // issued before they are added
-    auto add = [&](const float4 &x, const float4 &y, const float4 &z) {
+    for (int b = threadIdx.x; b < nw; b += 1024) {
+        const float4 x = base[3 * b], y = base[3 * b + 1], z = base[3 * b + 2];
         acc[0] += x.x; acc[1] += x.y; acc[2] += x.z; acc[3] += x.w;
         acc[4] += y.x; acc[5] += y.y; acc[6] += y.z; acc[7] += y.w;
         acc[8] += z.x; acc[9] += z.y; acc[10] += z.z; acc[11] += z.w;
-    };
-    int b = threadIdx.x;
-    for (; b + 1024 < nw; b += 2048) {
-        const float4 x0 = base[3 * b], y0 = base[3 * b + 1], z0 = base[3 * b + 2];
-        const int c = b + 1024;
-        const float4 x1 = base[3 * c], y1 = base[3 * c + 1], z1 = base[3 * c + 2];
-        add(x0, y0, z0);
-        add(x1, y1, z1);
     }
-    if (b < nw) add(base[3 * b], base[3 * b + 1], base[3 * b + 2]);
     const float r = wave_reduce16(acc);
     const int comp = wave_reduce16_component();
     if (comp >= 0) red[threadIdx.x >> 6][comp] = r;
