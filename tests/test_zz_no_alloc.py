@@ -68,6 +68,8 @@ def test_noalloc_matches_workspace_call_twice(rast):
     _, ws = rast.forward(big, p)
     max_pairs = ws.n_pairs + 4096
     assert rast.workspace_size(big, p, max_pairs) <= native.FM_NOALLOC_SCRATCH_BYTES
+    # the documented limit: this view fits with room for 1.5M pairs
+    assert rast.workspace_size(big, p, 1_500_000) <= native.FM_NOALLOC_SCRATCH_BYTES
     del ws
     print("no-alloc: 640x480 / 300k", flush=True)
     a, b = _run_both(rast, big, p, max_pairs)
