@@ -415,7 +415,7 @@ fm_status run_forward(fm_ctx *ctx, Built &bt, const fm_raster_params *prm, const
     Ranges rg("fm2dgs/forward");
     mark_begin(ctx, st);
     rg.phase("fm2dgs/projection");
-    FM_TRY_HIP(fm::launch_setup(bt.plan, ws, bt.views.data(), bt.subs.data(), bt.vlist.data(), st), "setup");
+    FM_TRY_HIP(fm::launch_setup(bt.plan, ws, bt.views.data(), bt.subs.data(), bt.vlist.data(), true, st), "setup");
     FM_TRY_HIP(fm::launch_preprocess(bt.plan, ws, kp, b->intr, b->viewmat, false, st), "preprocess");
     mark(ctx, st, PH_PRE);
     rg.phase("fm2dgs/binning");
@@ -440,7 +440,7 @@ fm_status run_fused(fm_ctx *ctx, Built &bt, const fm_raster_params *prm, const f
     Ranges rg("fm2dgs/fwd_bwd_l1");
     mark_begin(ctx, st);
     rg.phase("fm2dgs/projection");
-    FM_TRY_HIP(fm::launch_setup(bt.plan, ws, bt.views.data(), bt.subs.data(), bt.vlist.data(), st), "setup");
+    FM_TRY_HIP(fm::launch_setup(bt.plan, ws, bt.views.data(), bt.subs.data(), bt.vlist.data(), true, st), "setup");
     // the slots are cleared for the blend's atomics; deterministic sums store
     // every slot the backward projection reads (those of visible entries)
     FM_TRY_HIP(fm::launch_preprocess(bt.plan, ws, kp, b->intr, b->viewmat, !bt.plan.det, st), "preprocess");
@@ -698,7 +698,7 @@ fm_status fm_backward(fm_ctx *ctx, const fm_batch *b, const fm_raster_params *pr
     Ranges rg("fm2dgs/backward");
     mark_begin(ctx, st);
     rg.phase("fm2dgs/zero_grad");
-    FM_TRY_HIP(fm::launch_setup(bt.plan, ws, bt.views.data(), bt.subs.data(), bt.vlist.data(), st), "setup");
+    FM_TRY_HIP(fm::launch_setup(bt.plan, ws, bt.views.data(), bt.subs.data(), bt.vlist.data(), false, st), "setup");
     if (bt.plan.det) FM_TRY_HIP(fm::launch_det_clear(bt.plan, ws, kp.gstride, st), "det_clear");
     else FM_TRY_HIP(fm::launch_zero_grad(bt.plan, ws, kp.gstride, st), "zero_grad");
     mark(ctx, st, PH_ZERO);
@@ -795,7 +795,7 @@ fm_status fm_prune_scores(fm_ctx *ctx, const fm_batch *b, const fm_raster_params
     Ranges rg("fm2dgs/prune_scores");
     mark_begin(ctx, st);
     rg.phase("fm2dgs/projection");
-    FM_TRY_HIP(fm::launch_setup(bt.plan, ws, bt.views.data(), bt.subs.data(), bt.vlist.data(), st), "setup");
+    FM_TRY_HIP(fm::launch_setup(bt.plan, ws, bt.views.data(), bt.subs.data(), bt.vlist.data(), true, st), "setup");
     // the projection clears the slots whose first float collects each entry's score
     FM_TRY_HIP(fm::launch_preprocess(bt.plan, ws, kp, b->intr, b->viewmat, true, st), "preprocess");
     mark(ctx, st, PH_PRE);

@@ -215,14 +215,37 @@ template <uint32_t C> __device__ __forceinline__ uint32_t xcd_chunked(uint32_t b
     return b < (n / grp) * grp ? (b / grp) * grp + (b & 7u) * C + (b >> 3) % C : b;
 }
 
+// Start of a call's binning state, run by every block of a 256-thread grid:
+// block 0 clears the status words and the blend order's bucket counts and
+// cursors, and the grid starts every tile range empty with ts > te (the last
+// tile-sort pass fills the ranges).  The setup kernels run it, before the
+// projection (which touches none of it).
+__device__ __forceinline__ void init_ranges_block(uint32_t *status, int n_status, uint32_t *tbucket,
+                                                  uint32_t *ts, uint32_t *te, int64_t n) {
+    if (blockIdx.x == 0 && (int)threadIdx.x < n_status) status[threadIdx.x] = 0u;
+    if (blockIdx.x == 0) {
+        tbucket[threadIdx.x] = 0u;
+        tbucket[kRadix + threadIdx.x] = 0u;
+    }
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        ts[i] = 0xFFFFFFFFu;
+        te[i] = 0u;
+    }
+}
+
 // ---- launchers (host) ------------------------------------------------------
+// start_binning: also start the binning state of a call that bins (forward,
+// fused, pruning), not of a backward that reads a previous forward's lists
 hipError_t launch_setup(const Plan &p, void *ws, const ViewDesc *views, const SubmapDesc *subs,
-                        const int32_t *vlist, hipStream_t st);
+                        const int32_t *vlist, bool start_binning, hipStream_t st);
 // views one projection thread handles
 constexpr int kProjViewsPerThread = 4;
 hipError_t launch_preprocess(const Plan &p, void *ws, const KParams &kp, const float *intr,
                              const float *viewmat, bool zero_grad, hipStream_t st);
 hipError_t launch_binning(const Plan &p, void *ws, hipStream_t st);
+// the binning state's start (init_ranges_block) as a kernel of its own
+hipError_t launch_init_ranges(const Plan &p, void *ws, hipStream_t st);
+int init_ranges_blocks(const Plan &p);
 hipError_t launch_render_fwd(const Plan &p, void *ws, const KParams &kp, const fm_outputs &out,
                              hipStream_t st);
 hipError_t launch_render_bwd(const Plan &p, void *ws, const KParams &kp, const fm_outputs &out,

@@ -51,13 +51,20 @@ struct SmallSetup {
 };
 static_assert(sizeof(SmallSetup) <= 4096, "kernel arguments are limited to 4 KB");
 
-__global__ void k_write_small(SmallSetup c, ViewDesc *ov, SubmapDesc *os, int32_t *ol) {
+// Block 0 writes the descriptors; with `init` the whole grid also starts the
+// call's binning state (init_ranges_block).
+__global__ __launch_bounds__(256) void k_write_small(SmallSetup c, ViewDesc *ov, SubmapDesc *os, int32_t *ol,
+                                                      int init, uint32_t *status, int n_status, uint32_t *tbucket,
+                                                      uint32_t *ts, uint32_t *te, int64_t n_tiles) {
     const int i = threadIdx.x;
-    if (i < c.nv) {
-        ov[i] = c.v[i];
-        ol[i] = c.l[i];
+    if (blockIdx.x == 0) {
+        if (i < c.nv) {
+            ov[i] = c.v[i];
+            ol[i] = c.l[i];
+        }
+        if (i < c.ns) os[i] = c.s[i];
     }
-    if (i < c.ns) os[i] = c.s[i];
+    if (init) init_ranges_block(status, n_status, tbucket, ts, te, n_tiles);
 }
 
 __global__ void k_write_views(ViewChunk c, ViewDesc *out) {
@@ -559,7 +566,7 @@ __global__ __launch_bounds__(1024) void k_pose_reduce(const ViewDesc *__restrict
 }  // namespace
 
 hipError_t launch_setup(const Plan &p, void *ws, const ViewDesc *views, const SubmapDesc *subs,
-                        const int32_t *vlist, hipStream_t st) {
+                        const int32_t *vlist, bool start_binning, hipStream_t st) {
     if (p.V <= kSmallViews && p.S <= kSmallSubs) {
         SmallSetup c;
         memset(&c, 0, sizeof(c));
@@ -570,9 +577,18 @@ hipError_t launch_setup(const Plan &p, void *ws, const ViewDesc *views, const Su
             c.l[i] = vlist[i];
         }
         for (int i = 0; i < p.S; ++i) c.s[i] = subs[i];
-        hipLaunchKernelGGL(k_write_small, dim3(1), dim3(64), 0, st, c, at<ViewDesc>(ws, p.o_views),
-                           at<SubmapDesc>(ws, p.o_subs), at<int32_t>(ws, p.o_vlist));
+        static_assert(kSmallViews <= 256 && kSmallSubs <= 256, "one thread per descriptor");
+        hipLaunchKernelGGL(k_write_small, dim3(start_binning ? init_ranges_blocks(p) : 1), dim3(256), 0, st, c,
+                           at<ViewDesc>(ws, p.o_views), at<SubmapDesc>(ws, p.o_subs), at<int32_t>(ws, p.o_vlist),
+                           start_binning ? 1 : 0,
+                           reinterpret_cast<uint32_t *>(at<Status>(ws, p.o_status)), (int)(sizeof(Status) / 4),
+                           at<uint32_t>(ws, p.o_tbucket), at<uint32_t>(ws, p.o_tstart), at<uint32_t>(ws, p.o_tend),
+                           p.T);
         return hipGetLastError();
+    }
+    if (start_binning) {
+        const hipError_t e = launch_init_ranges(p, ws, st);
+        if (e != hipSuccess) return e;
     }
     for (int f = 0; f < p.V; f += kViewChunk) {
         ViewChunk c;

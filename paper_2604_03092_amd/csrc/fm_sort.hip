@@ -557,21 +557,11 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t *__restrict__ sorte
     }
 }
 
-// Start of binning: clear the status words (block 0) and start every tile
-// range empty with ts > te; the last tile-sort pass fills the ranges.
 __global__ __launch_bounds__(256) void k_init_ranges(uint32_t *__restrict__ status, int n_status,
                                                       uint32_t *__restrict__ tbucket,
                                                       uint32_t *__restrict__ ts, uint32_t *__restrict__ te,
                                                       int64_t n) {
-    if (blockIdx.x == 0 && (int)threadIdx.x < n_status) status[threadIdx.x] = 0u;
-    if (blockIdx.x == 0) {  // the blend order's bucket counts and cursors
-        tbucket[threadIdx.x] = 0u;
-        tbucket[kRadix + threadIdx.x] = 0u;
-    }
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-        ts[i] = 0xFFFFFFFFu;
-        te[i] = 0u;
-    }
+    init_ranges_block(status, n_status, tbucket, ts, te, n);
 }
 
 // Blend order: a tile's cost bucket is 255 minus 16 log2(1 + list length)
@@ -654,6 +644,19 @@ void radix_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32
 
 }  // namespace
 
+int init_ranges_blocks(const Plan &p) {
+    const int64_t b = (p.T + 255) / 256;
+    return (int)(b < 1 ? 1 : (b < 4096 ? b : 4096));
+}
+
+hipError_t launch_init_ranges(const Plan &p, void *ws, hipStream_t st) {
+    static_assert(sizeof(Status) / 4 <= 256, "status words are cleared by one block");
+    hipLaunchKernelGGL(k_init_ranges, dim3(init_ranges_blocks(p)), dim3(256), 0, st,
+                       reinterpret_cast<uint32_t *>(at<Status>(ws, p.o_status)), (int)(sizeof(Status) / 4),
+                       at<uint32_t>(ws, p.o_tbucket), at<uint32_t>(ws, p.o_tstart), at<uint32_t>(ws, p.o_tend), p.T);
+    return hipGetLastError();
+}
+
 hipError_t launch_binning(const Plan &p, void *ws, hipStream_t st) {
     Status *status = at<Status>(ws, p.o_status);
     uint32_t *key = at<uint32_t>(ws, p.o_key), *key2 = at<uint32_t>(ws, p.o_key2);
@@ -661,10 +664,8 @@ hipError_t launch_binning(const Plan &p, void *ws, hipStream_t st) {
     uint32_t *hist = at<uint32_t>(ws, p.o_hist);
     uint32_t *tot = at<uint32_t>(ws, p.o_tot);
     uint32_t *ts = at<uint32_t>(ws, p.o_tstart), *te = at<uint32_t>(ws, p.o_tend);
-    const int fill_blocks = (int)((p.T + 255) / 256 < 4096 ? (p.T + 255) / 256 : 4096);
-    static_assert(sizeof(Status) / 4 <= 256, "status words are cleared by one block");
-    hipLaunchKernelGGL(k_init_ranges, dim3(fill_blocks), dim3(256), 0, st, reinterpret_cast<uint32_t *>(status),
-                       (int)(sizeof(Status) / 4), at<uint32_t>(ws, p.o_tbucket), ts, te, p.T);
+    // (the status words, the tile ranges and the order's buckets were
+    // initialised by the setup of the call)
     // 1. stable sort of the entries by their 32-bit depth key (4 passes; the
     //    first pass starts from the identity permutation and drops the
     //    entries that cover no tile, so the later passes see only the
