@@ -420,6 +420,25 @@ def test_capacity_overflow_then_retry(rast):
     assert_images_close(out2, ref, ~ref["flags"], what="after grow")
 
 
+def test_capacity_overflow_counts_every_pair(rast):
+    """A 640x480 view of 300k surfels (about 90 blocks of the pair count
+    scan) with room for half its pairs: the call reports the overflow, stores
+    exactly the capacity, and the required count equals the pair count of a
+    call with room for all of them."""
+    gs = GpuScene.from_scene(scenes.config1())
+    _say("capacity overflow, 640x480 / 300k")
+    out, ws = rast.forward(gs)
+    torch.cuda.synchronize()
+    st, n_full, req_full = rast.query(gs, ws)
+    assert st == 0 and n_full == req_full > 100_000
+    cap = req_full // 2
+    ws2 = rast.workspace(gs, max_pairs=cap)
+    rast.forward_into(gs, ws2, rast.new_outputs(gs))
+    torch.cuda.synchronize()
+    st2, n2, req2 = rast.query(gs, ws2)
+    assert st2 == 2 and n2 == cap and req2 == req_full
+
+
 def test_empty_and_culled(rast):
     # every surfel culled: NaN, zero quaternion, behind the camera, transparent
     n = 8
